@@ -1,0 +1,165 @@
+/*
+ * srhd.h -- C ABI of libsrhd, an MI355X (gfx950) library for one finite-volume step of special
+ * relativistic hydrodynamics with the Taub-Mathews equation of state over a batch of 8^3-cell
+ * patches, after Tseng, Schive & Chiueh, arXiv:2012.11130 ("GAMER-SR").
+ *
+ * Conventions shared by every call
+ *   - Units c = k_B = m = 1; Theta = k_B T / (m c^2).
+ *   - Primitive variables (rho, Ux, Uy, Uz, p): proper density, four-velocity, pressure.
+ *     Conserved variables (D, Mx, My, Mz, Et): lab density, momentum, reduced energy Et = E - D
+ *     (Sec. 2.1, Eqs. 5a-5c and 6).
+ *   - Every data pointer is a DEVICE pointer owned by the caller, unless the comment says host.
+ *     The library never keeps a pointer after the call returns.
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL = the default stream).  Results
+ *     are valid once the stream is synchronised.  No call synchronises the device.
+ *   - Return value: SRHD_OK (0) or a negative srhd_err.  Argument errors are detected before any
+ *     launch and leave outputs untouched; srhd_last_error() then describes the problem.
+ *   - Physical failures are data, not errors: they are reported per state (status codes) or in
+ *     srhd_step_stats, and the affected outputs are NaN.
+ *   - Arrays of states are structure-of-arrays, field-major: [5][n].  Patch arrays are
+ *     [patch][field][z][y][x], x fastest; a padded patch has N = 8 + 2 ghost cells per side.
+ *   - The library allocates no user-visible memory.  Work buffers are passed in by the caller.
+ */
+#ifndef SRHD_H
+#define SRHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SRHD_ABI_VERSION 1
+
+typedef enum { SRHD_F64 = 0, SRHD_F32 = 1 } srhd_dtype;
+
+typedef enum {
+  SRHD_OK = 0,
+  SRHD_EINVAL = -1,       /* bad argument (NULL pointer, negative size, misaligned pointer...) */
+  SRHD_EHIP = -2,         /* the HIP runtime reported an error at launch */
+  SRHD_EUNSUPPORTED = -3  /* valid request that this build does not implement */
+} srhd_err;
+
+/* Per-state status of an inversion (int8). */
+enum {
+  SRHD_ST_OK = 0,
+  SRHD_ST_UNPHYSICAL = 1, /* D <= 0, Et <= 0, non-finite input, or L <= eps (Eq. 30) */
+  SRHD_ST_FALLBACK = 2,   /* the supplied initial guess failed; the analytic guess converged */
+  SRHD_ST_NOCONV = 3      /* Newton did not converge within max_iter from either guess */
+};
+
+typedef enum { SRHD_GUESS_ANALYTIC = 0, SRHD_GUESS_MLP = 1 } srhd_guess_kind;
+typedef enum { SRHD_HLLC = 0, SRHD_HLLE = 1 } srhd_riemann;
+/* FP64: every stage in FP64.  MIXED: reconstruction, fluxes and the update increment in FP32;
+ * the left-hand side L of Eq. 15 and the Newton inversion in FP64 (state storage stays FP64). */
+typedef enum { SRHD_PREC_FP64 = 0, SRHD_PREC_MIXED = 1 } srhd_prec;
+
+/* Learned initial guess (device parameters of a 3-64-64-1 SiLU perceptron; see srhd_mlp_*). */
+typedef struct {
+  const uint16_t *w_bf16;  /* BF16 weights, layer-major: W1[64][3], W2[64][64], W3[1][64] */
+  const float *bias;       /* FP32 biases: b1[64], b2[64], b3[1] */
+  const float *norm;       /* FP32 [8]: input mean[3], input std[3], output mean, output std */
+} srhd_mlp;
+
+typedef struct {
+  int kind;                /* srhd_guess_kind */
+  const srhd_mlp *mlp;     /* host pointer to device parameters; required when kind == MLP */
+  int max_iter;            /* Newton iterations per guess; <= 0 selects 30 */
+} srhd_guess;
+
+/* ---------------------------------------------------------------------------------------- */
+/* Conversions (Sec. 2.3)                                                                   */
+/* ---------------------------------------------------------------------------------------- */
+
+/* prim[5][n] -> cons[5][n] by Eqs. 8, 5a, 22, 5b, 15 and 23 (no root finding).  dtype selects
+ * FP64 or FP32 storage and arithmetic.  prim and cons must not overlap. */
+int srhd_prim2cons(int dtype, int64_t n, const void *prim, void *cons, void *stream);
+
+/* cons[5][n] -> prim[5][n]: L = x^2 + 2x - m^2 (x = Et/D, m = |M|/D) from error-free products
+ * and a compensated sum, the physical check L > eps (Eq. 30), the root ht of f(ht) = L
+ * (Eq. 15) by Newton's method (Eqs. A1-A2) from the guess selected by `guess` (NULL: the
+ * analytic guess of App. A, Eqs. A3-A7), then Eqs. 17, 8, 5a, 16 and 18.
+ * status[n] (int8, SRHD_ST_*) and iters[n] (uint8, Newton iterations) may be NULL.
+ * FP32: L, Newton and recovery in FP32.  FP64: all in FP64. */
+int srhd_cons2prim(int dtype, int64_t n, const void *cons, void *prim, int8_t *status,
+                   uint8_t *iters, const srhd_guess *guess, void *stream);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Patches (Sec. 3.1: 8^3-cell patches with ghost zones)                                    */
+/* ---------------------------------------------------------------------------------------- */
+
+#define SRHD_MAX_LEVEL 8
+
+typedef struct {
+  int64_t n_patch;
+  int ghost;               /* ghost cells per side, >= 2 (3 in the GAMER layout) */
+  int dtype;               /* storage type of `padded` (SRHD_F64 only for the step) */
+  const void *padded;      /* [n_patch][5][N][N][N] conserved variables, N = 8 + 2 ghost */
+  const int8_t *level;     /* [n_patch] refinement level, or NULL (all level 0) */
+  int n_level;             /* 1 .. SRHD_MAX_LEVEL */
+  double dh[SRHD_MAX_LEVEL];  /* host: cell size per level */
+} srhd_patches;
+
+/* Neighbour table neighbor[n_patch][27] (int32, device): slot (oz+1)*9 + (oy+1)*3 + (ox+1)
+ * holds the index in `interior` of the same-level patch at offset (ox, oy, oz); slot 13 is the
+ * patch's own index (so a table listing a subset of patches fills only those).  -1 in a face slot
+ * marks a domain boundary: ghost cells beyond it copy the nearest interior cell (outflow,
+ * zero gradient).  Periodic domains list wrapped neighbours.
+ * Fills every ghost cell of padded[n_patch][5][N][N][N] (faces, edges and corners) from
+ * interior[n_src][5][8][8][8]; also copies the interior.  A cell whose source index is outside
+ * [0, n_src) -- e.g. -1 in an edge slot while no face slot marks a boundary -- is set to NaN. */
+int srhd_fill_ghosts(int dtype, int64_t n_patch, int ghost, int64_t n_src, const void *interior,
+                     const int32_t *neighbor, void *padded, void *stream);
+
+/* CFL time step (Sec. 3.3, Eqs. 26-28, the sum taken over |Ux| + |Uy| + |Uz|): one global
+ * maximum signal speed S_max over the interior cells of interior[n_patch][5][8^3] (inverted
+ * with the analytic guess), then dt_lev[l] = c_cfl * dh[l] / S_max for l < n_level (so
+ * dt_l = dt_0 / 2^l when dh_l = dh_0 / 2^l).  dt_lev: device double[n_level].
+ * work: device buffer of srhd_cfl_work_bytes() bytes (reused across calls, contents scratch).
+ * The maximum is exact (order independent), so the result is deterministic. */
+size_t srhd_cfl_work_bytes(void);
+int srhd_cfl_dt(int dtype, int64_t n_patch, const void *interior, int n_level,
+                const double *dh /* host [n_level] */, double c_cfl, double *dt_lev,
+                void *work, void *stream);
+
+typedef struct {
+  double theta;            /* limiter coefficient of the generalized minmod (default 1.5) */
+  int riemann;             /* srhd_riemann */
+  int prec;                /* srhd_prec */
+  int max_retry;           /* reductions theta *= 0.75 before the final theta = 0 attempt */
+  srhd_guess guess;        /* initial guess for every inversion in the step */
+} srhd_step_params;
+
+/* Device counters, accumulated (never reset by the step; see srhd_stats_reset). */
+typedef struct {
+  uint64_t n_unphysical;   /* failed inversions + failed output cells of the final attempts */
+  uint64_t n_fallback;     /* inversions whose supplied guess failed (analytic rescue) */
+  uint64_t n_noconv;       /* inversions that did not converge */
+  uint64_t newton_iters;   /* Newton iterations over all inversions of all attempts */
+  uint64_t n_inversions;   /* inversions performed (all attempts) */
+  uint64_t n_retry;        /* extra attempts with a reduced limiter coefficient */
+  uint64_t reserved[2];
+} srhd_step_stats;
+
+int srhd_stats_reset(srhd_step_stats *stats, void *stream);
+
+/* One unsplit MUSCL-Hancock step (Sec. 3.2) of every patch: cell-centre inversion, PLM in
+ * (rho, Ux, Uy, Uz, p) with the hybrid van Leer / generalized minmod limiter, the half-step
+ * face states, face inversions, HLLC or HLLE fluxes with the TM sound speed (Eq. 14) and the
+ * reduced energy, and the conservative full update of the 8^3 interior:
+ *   out[p] = U^n - dt_l/dh_l sum_d (F_{d,+1/2} - F_{d,-1/2}).
+ * A patch meeting an unphysical state is redone with theta *= 0.75 (max_retry times) and then
+ * theta = 0 (Sec. 3.4).  dt_lev: device double[n_level] (e.g. from srhd_cfl_dt).
+ * out: [n_patch][5][8][8][8] FP64; must not overlap in->padded.  stats may be NULL. */
+int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
+                    const srhd_step_params *prm, srhd_step_stats *stats, void *stream);
+
+/* Thread-local description of the last non-zero return. */
+const char *srhd_last_error(void);
+int srhd_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -75,7 +75,7 @@ def lib():
     L.or_is_physical.argtypes = [_p]
     L.or_is_physical.restype = ctypes.c_int
     L.or_fluid_step.restype = ctypes.c_int
-    L.or_fill_ghosts.argtypes = [_i64, ctypes.c_int, _p, _p, _p]
+    L.or_fill_ghosts.argtypes = [_i64, ctypes.c_int, _i64, _p, _p, _p]
     L.or_fill_ghosts.restype = ctypes.c_int
     L.or_extract_interior.argtypes = [_i64, ctypes.c_int, _p, _p]
     L.or_extract_interior.restype = None
@@ -231,12 +231,14 @@ def cfl_dt(interior, level, dh_lev, c_cfl=0.5):
 
 
 def fill_ghosts(interior, neighbor, ghost=3):
+    """Padded patches for the rows of ``neighbor`` (slot 13 = own index into ``interior``)."""
     interior = _f64(interior)
     neighbor = np.ascontiguousarray(neighbor, dtype=np.int32)
-    P = interior.shape[0]
+    P = neighbor.shape[0]
     N = 8 + 2 * ghost
     padded = np.empty((P, 5, N, N, N))
-    rc = lib().or_fill_ghosts(P, ghost, _ptr(interior), _ptr(neighbor), _ptr(padded))
+    rc = lib().or_fill_ghosts(P, ghost, interior.shape[0], _ptr(interior), _ptr(neighbor),
+                              _ptr(padded))
     if rc != 0:
         raise ValueError("neighbour table leaves a ghost cell without a source")
     return padded

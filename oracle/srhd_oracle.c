@@ -729,11 +729,12 @@ int or_fluid_step(int64_t n_patch, int ghost, const double *padded, const int8_t
 /* ===================================================================================== */
 
 /* Neighbour table: neighbor[p][n] with n = (oz+1)*9 + (oy+1)*3 + (ox+1) for the offset
- * (ox, oy, oz) in {-1,0,1}^3 (entry 13, the patch itself, is ignored).  -1 in a face entry
+ * (ox, oy, oz) in {-1,0,1}^3; entry 13 (offset 0) is the patch's own index in `interior`, so a
+ * table of a subset of patches fills just those patches.  -1 in a face entry
  * marks a domain boundary in that direction: there the ghost cells copy the nearest cell
  * inside the domain (outflow, zero gradient).  Periodic domains list wrapped neighbours. */
-int or_fill_ghosts(int64_t n_patch, int ghost, const double *interior, const int32_t *neighbor,
-                   double *padded)
+int or_fill_ghosts(int64_t n_patch, int ghost, int64_t n_src, const double *interior,
+                   const int32_t *neighbor, double *padded)
 {
   int N = PS + 2 * ghost;
   int64_t per = (int64_t)NF * N * N * N;
@@ -755,8 +756,8 @@ int or_fill_ghosts(int64_t n_patch, int ghost, const double *interior, const int
           int o[3];
           for (int d = 0; d < 3; d++) o[d] = (c[d] < 0) ? -1 : (c[d] >= PS ? 1 : 0);
           int slot = (o[2] + 1) * 9 + (o[1] + 1) * 3 + (o[0] + 1);
-          int64_t src = (slot == 13) ? p : nb[slot];
-          if (src < 0) { bad = 1; continue; }
+          int64_t src = nb[slot];
+          if (src < 0 || src >= n_src) { bad = 1; continue; }
           int si = c[0] - PS * o[0], sj = c[1] - PS * o[1], sk = c[2] - PS * o[2];
           for (int f = 0; f < NF; f++)
             padded[p * per + (((int64_t)f * N + z) * N + y) * N + x] =

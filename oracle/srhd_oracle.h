@@ -43,8 +43,8 @@ int or_is_physical(const double u[5]);
 int or_fluid_step(int64_t n_patch, int ghost, const double *padded, const int8_t *level,
                   const double *dh_lev, const double *dt_lev, double theta, int riemann,
                   int max_retry, double *out, int64_t *counts);
-int or_fill_ghosts(int64_t n_patch, int ghost, const double *interior, const int32_t *neighbor,
-                   double *padded);
+int or_fill_ghosts(int64_t n_patch, int ghost, int64_t n_src, const double *interior,
+                   const int32_t *neighbor, double *padded);
 void or_extract_interior(int64_t n_patch, int ghost, const double *padded, double *interior);
 int or_num_threads(void);
 void or_set_num_threads(int n);

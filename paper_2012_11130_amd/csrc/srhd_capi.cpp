@@ -1,0 +1,184 @@
+// srhd_capi.cpp -- the extern "C" entry points of libsrhd (declared in include/srhd.h):
+// argument validation, error reporting and kernel launches on the caller's stream.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "srhd_internal.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...)
+{
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_status(hipError_t e, const char *what)
+{
+  if (e == hipSuccess) return SRHD_OK;
+  return fail(SRHD_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+size_t dsize(int dtype) { return dtype == SRHD_F64 ? 8 : 4; }
+
+bool valid_dtype(int dtype) { return dtype == SRHD_F64 || dtype == SRHD_F32; }
+
+int check_guess(const srhd_guess *g, srhd::GuessArgs &out)
+{
+  out = srhd::GuessArgs{SRHD_GUESS_ANALYTIC, 30, nullptr, nullptr, nullptr};
+  if (!g) return SRHD_OK;
+  if (g->max_iter > 255) return fail(SRHD_EINVAL, "guess.max_iter %d exceeds 255", g->max_iter);
+  out.max_iter = g->max_iter > 0 ? g->max_iter : 30;
+  if (g->kind == SRHD_GUESS_ANALYTIC) return SRHD_OK;
+  if (g->kind == SRHD_GUESS_MLP)
+    return fail(SRHD_EUNSUPPORTED, "the learned guess is not available in this entry point");
+  return fail(SRHD_EINVAL, "unknown guess kind %d", g->kind);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *srhd_last_error(void) { return g_err; }
+
+int srhd_abi_version(void) { return SRHD_ABI_VERSION; }
+
+int srhd_prim2cons(int dtype, int64_t n, const void *prim, void *cons, void *stream)
+{
+  if (!valid_dtype(dtype)) return fail(SRHD_EINVAL, "srhd_prim2cons: bad dtype %d", dtype);
+  if (n < 0) return fail(SRHD_EINVAL, "srhd_prim2cons: n = %lld < 0", (long long)n);
+  if (n == 0) return SRHD_OK;
+  if (!prim || !cons) return fail(SRHD_EINVAL, "srhd_prim2cons: NULL array");
+  if (!aligned(prim, dsize(dtype)) || !aligned(cons, dsize(dtype)))
+    return fail(SRHD_EINVAL, "srhd_prim2cons: misaligned array");
+  const char *a = (const char *)prim, *b = (const char *)cons;
+  size_t bytes = (size_t)n * 5 * dsize(dtype);
+  if (a < b + bytes && b < a + bytes) return fail(SRHD_EINVAL, "srhd_prim2cons: prim and cons overlap");
+  return hip_status(srhd::launch_prim2cons(dtype, n, prim, cons, (hipStream_t)stream),
+                    "srhd_prim2cons");
+}
+
+int srhd_cons2prim(int dtype, int64_t n, const void *cons, void *prim, int8_t *status,
+                   uint8_t *iters, const srhd_guess *guess, void *stream)
+{
+  if (!valid_dtype(dtype)) return fail(SRHD_EINVAL, "srhd_cons2prim: bad dtype %d", dtype);
+  if (n < 0) return fail(SRHD_EINVAL, "srhd_cons2prim: n = %lld < 0", (long long)n);
+  srhd::GuessArgs g;
+  int rc = check_guess(guess, g);
+  if (rc) return rc;
+  if (n == 0) return SRHD_OK;
+  if (!prim || !cons) return fail(SRHD_EINVAL, "srhd_cons2prim: NULL array");
+  if (!aligned(prim, dsize(dtype)) || !aligned(cons, dsize(dtype)))
+    return fail(SRHD_EINVAL, "srhd_cons2prim: misaligned array");
+  const char *a = (const char *)prim, *b = (const char *)cons;
+  size_t bytes = (size_t)n * 5 * dsize(dtype);
+  if (a < b + bytes && b < a + bytes) return fail(SRHD_EINVAL, "srhd_cons2prim: prim and cons overlap");
+  return hip_status(srhd::launch_cons2prim(dtype, n, cons, prim, status, iters, g,
+                                           (hipStream_t)stream),
+                    "srhd_cons2prim");
+}
+
+int srhd_fill_ghosts(int dtype, int64_t n_patch, int ghost, int64_t n_src, const void *interior,
+                     const int32_t *neighbor, void *padded, void *stream)
+{
+  if (n_src < 0) return fail(SRHD_EINVAL, "srhd_fill_ghosts: n_src < 0");
+  if (!valid_dtype(dtype)) return fail(SRHD_EINVAL, "srhd_fill_ghosts: bad dtype %d", dtype);
+  if (n_patch < 0) return fail(SRHD_EINVAL, "srhd_fill_ghosts: n_patch < 0");
+  if (ghost < 0 || ghost > 8) return fail(SRHD_EINVAL, "srhd_fill_ghosts: ghost %d not in [0, 8]", ghost);
+  if (n_patch == 0) return SRHD_OK;
+  if (!interior || !neighbor || !padded) return fail(SRHD_EINVAL, "srhd_fill_ghosts: NULL array");
+  if (!aligned(interior, dsize(dtype)) || !aligned(padded, dsize(dtype)) || !aligned(neighbor, 4))
+    return fail(SRHD_EINVAL, "srhd_fill_ghosts: misaligned array");
+  return hip_status(srhd::launch_fill_ghosts(dtype, n_patch, ghost, n_src, interior, neighbor, padded,
+                                             (hipStream_t)stream),
+                    "srhd_fill_ghosts");
+}
+
+size_t srhd_cfl_work_bytes(void) { return 256; }
+
+int srhd_cfl_dt(int dtype, int64_t n_patch, const void *interior, int n_level, const double *dh,
+                double c_cfl, double *dt_lev, void *work, void *stream)
+{
+  if (!valid_dtype(dtype)) return fail(SRHD_EINVAL, "srhd_cfl_dt: bad dtype %d", dtype);
+  if (n_patch < 0) return fail(SRHD_EINVAL, "srhd_cfl_dt: n_patch < 0");
+  if (n_level < 1 || n_level > SRHD_MAX_LEVEL)
+    return fail(SRHD_EINVAL, "srhd_cfl_dt: n_level %d not in [1, %d]", n_level, SRHD_MAX_LEVEL);
+  if (!dh || !dt_lev || !work || (n_patch > 0 && !interior))
+    return fail(SRHD_EINVAL, "srhd_cfl_dt: NULL argument");
+  if (!(c_cfl > 0.0)) return fail(SRHD_EINVAL, "srhd_cfl_dt: c_cfl must be positive");
+  if (!aligned(work, 8) || !aligned(dt_lev, 8)) return fail(SRHD_EINVAL, "srhd_cfl_dt: misaligned buffer");
+  srhd::LevelArgs lv;
+  lv.n_level = n_level;
+  for (int l = 0; l < SRHD_MAX_LEVEL; ++l) lv.dh[l] = l < n_level ? dh[l] : 0.0;
+  for (int l = 0; l < n_level; ++l)
+    if (!(dh[l] > 0.0)) return fail(SRHD_EINVAL, "srhd_cfl_dt: dh[%d] must be positive", l);
+  return hip_status(srhd::launch_cfl(dtype, n_patch, interior, lv, c_cfl, dt_lev, work,
+                                     (hipStream_t)stream),
+                    "srhd_cfl_dt");
+}
+
+int srhd_stats_reset(srhd_step_stats *stats, void *stream)
+{
+  if (!stats) return fail(SRHD_EINVAL, "srhd_stats_reset: NULL stats");
+  return hip_status(srhd::launch_stats_reset(stats, (hipStream_t)stream), "srhd_stats_reset");
+}
+
+int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
+                    const srhd_step_params *prm, srhd_step_stats *stats, void *stream)
+{
+  if (!in || !prm) return fail(SRHD_EINVAL, "srhd_fluid_step: NULL descriptor");
+  if (in->n_patch < 0) return fail(SRHD_EINVAL, "srhd_fluid_step: n_patch < 0");
+  if (in->dtype != SRHD_F64)
+    return fail(SRHD_EUNSUPPORTED, "srhd_fluid_step: patch storage must be FP64");
+  if (in->ghost < 2 || in->ghost > 8)
+    return fail(SRHD_EINVAL, "srhd_fluid_step: ghost %d not in [2, 8]", in->ghost);
+  if (in->n_level < 1 || in->n_level > SRHD_MAX_LEVEL)
+    return fail(SRHD_EINVAL, "srhd_fluid_step: n_level %d not in [1, %d]", in->n_level, SRHD_MAX_LEVEL);
+  if (in->n_patch > 0x7fffffffLL) return fail(SRHD_EINVAL, "srhd_fluid_step: too many patches");
+  if (prm->prec != SRHD_PREC_FP64 && prm->prec != SRHD_PREC_MIXED)
+    return fail(SRHD_EINVAL, "srhd_fluid_step: bad precision %d", prm->prec);
+  if (prm->riemann != SRHD_HLLC && prm->riemann != SRHD_HLLE)
+    return fail(SRHD_EINVAL, "srhd_fluid_step: bad Riemann solver %d", prm->riemann);
+  if (!(prm->theta >= 0.0 && prm->theta <= 2.0))
+    return fail(SRHD_EINVAL, "srhd_fluid_step: theta %g not in [0, 2]", prm->theta);
+  if (prm->max_retry < 0 || prm->max_retry > 64)
+    return fail(SRHD_EINVAL, "srhd_fluid_step: max_retry %d not in [0, 64]", prm->max_retry);
+  srhd::GuessArgs g;
+  int rc = check_guess(&prm->guess, g);
+  if (rc) return rc;
+  if (in->n_patch == 0) return SRHD_OK;
+  if (!in->padded || !out || !dt_lev) return fail(SRHD_EINVAL, "srhd_fluid_step: NULL array");
+  if (!aligned(in->padded, 8) || !aligned(out, 8) || !aligned(dt_lev, 8))
+    return fail(SRHD_EINVAL, "srhd_fluid_step: misaligned array");
+  for (int l = 0; l < in->n_level; ++l)
+    if (!(in->dh[l] > 0.0)) return fail(SRHD_EINVAL, "srhd_fluid_step: dh[%d] must be positive", l);
+  int N = 8 + 2 * in->ghost;
+  const char *a = (const char *)in->padded, *b = (const char *)out;
+  size_t abytes = (size_t)in->n_patch * 5 * N * N * N * 8, bbytes = (size_t)in->n_patch * 5 * 512 * 8;
+  if (a < b + bbytes && b < a + abytes) return fail(SRHD_EINVAL, "srhd_fluid_step: out overlaps the input");
+  srhd::StepArgs s;
+  s.n_patch = in->n_patch;
+  s.ghost = in->ghost;
+  s.padded = (const double *)in->padded;
+  s.level = in->level;
+  s.n_level = in->n_level;
+  s.dt_lev = dt_lev;
+  for (int l = 0; l < SRHD_MAX_LEVEL; ++l) s.dh[l] = l < in->n_level ? in->dh[l] : 1.0;
+  s.theta = prm->theta;
+  s.riemann = prm->riemann;
+  s.max_retry = prm->max_retry;
+  s.guess = g;
+  s.out = (double *)out;
+  s.stats = stats;
+  return hip_status(srhd::launch_step(prm->prec, s, (hipStream_t)stream), "srhd_fluid_step");
+}
+
+}  // extern "C"

@@ -1,0 +1,423 @@
+// srhd_device.hpp -- device math of the SRHD step for gfx950 (arXiv:2012.11130).
+//
+// Everything here is __device__ code shared by the conversion and step kernels:
+//   * error-free transformations and a K = 3 compensated sum for the left-hand side
+//     L = x^2 + 2x - m^2 of Eq. 15 (its cancellation is the (1 + Mach^2) eps of Eq. 20);
+//   * the TM EoS: Eq. 22 (ht of Theta), Eq. 16 (Theta of ht), Eq. 14 (sound speed);
+//   * the Newton iteration for f(ht) = L (Eqs. 15, A1, A2) and the analytic guess (Eqs. A3-A7,
+//     with A4 taken as the positive root of A3);
+//   * prim -> cons (Eqs. 8, 5a, 5b, 22, 15, 23) and the recovery after the root (Eqs. 17, 8,
+//     5a, 16, 18);
+//   * fluxes (Eqs. 4a, 4b, 7), signal speeds and the HLLE / HLLC Riemann solvers adapted to
+//     the TM sound speed and to the reduced energy (Sec. 3.2).
+// Templates take the bulk arithmetic type T (double, or float on the mixed-precision path).
+// The inversion always runs in double.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace srhd {
+
+// ------------------------------------------------------------------------------ arithmetic
+// Division and square root: IEEE in double; hardware reciprocal / square root (about 1 ulp)
+// in float, where the bulk of the mixed-precision path tolerates FP32 rounding anyway.
+__device__ __forceinline__ double dv(double a, double b) { return a / b; }
+__device__ __forceinline__ float dv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double sq(double a) { return __builtin_sqrt(a); }
+__device__ __forceinline__ float sq(float a) { return __builtin_amdgcn_sqrtf(a); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <class T> __device__ __forceinline__ T absT(T a) { return a < T(0) ? -a : a; }
+template <class T> __device__ __forceinline__ T minT(T a, T b) { return b < a ? b : a; }
+template <class T> __device__ __forceinline__ T maxT(T a, T b) { return b > a ? b : a; }
+template <class T> __device__ __forceinline__ bool finiteT(T a) { return a - a == T(0); }
+
+// The error-free transformations below must see every product rounded exactly once, so FMA
+// contraction (on by default in HIP) is switched off inside them: fusing a rounded product
+// into the following sum would silently break the exactness.
+
+// Knuth's branch-free two-sum: s + e == a + b exactly.
+template <class T>
+__device__ __forceinline__ void two_sum(T a, T b, T &s, T &e)
+{
+#pragma clang fp contract(off)
+  s = a + b;
+  T bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Ogita-Rump-Oishi SumK with K = 3: two error-free cascades, then the plain sum.  The result
+// is as accurate as if summed in triple precision and rounded once.
+template <class T, int N>
+__device__ __forceinline__ T sum_k3(T (&t)[N])
+{
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+    for (int i = 1; i < N; ++i) {
+      T s, e;
+      two_sum(t[i], t[i - 1], s, e);
+      t[i] = s;
+      t[i - 1] = e;
+    }
+  }
+  T r = t[0];
+#pragma unroll
+  for (int i = 1; i < N - 1; ++i) r += t[i];
+  return r + t[N - 1];
+}
+
+// L = (Et^2 + 2 Et D - |M|^2) / D^2 with the numerator summed from error-free products
+// (a*b = p + fma(a, b, -p)).
+template <class T>
+__device__ __forceinline__ T lhs_L(T D, T Mx, T My, T Mz, T Et)
+{
+#pragma clang fp contract(off)
+  T t[10];
+  t[0] = Et * Et;       t[1] = fmaT(Et, Et, -t[0]);
+  T e2 = T(2) * Et;
+  t[2] = e2 * D;        t[3] = fmaT(e2, D, -t[2]);
+  t[4] = -(Mx * Mx);    t[5] = -fmaT(Mx, Mx, t[4]);
+  t[6] = -(My * My);    t[7] = -fmaT(My, My, t[6]);
+  t[8] = -(Mz * Mz);    t[9] = -fmaT(Mz, Mz, t[8]);
+  T N = sum_k3(t);
+  return dv(dv(N, D), D);
+}
+
+// The same in double from FP32 conserved variables: products of floats are exact in double.
+__device__ __forceinline__ double lhs_L_from_f32(float D, float Mx, float My, float Mz, float Et)
+{
+#pragma clang fp contract(off)
+  double d = D, e = Et, x = Mx, y = My, z = Mz;
+  double t[5];
+  t[0] = e * e;
+  t[1] = 2.0 * e * d;
+  t[2] = -(x * x);
+  t[3] = -(y * y);
+  t[4] = -(z * z);
+  double N = sum_k3(t);
+  return (N / d) / d;
+}
+
+// ------------------------------------------------------------------------------ EoS
+// Eq. 22: reduced enthalpy from Theta, free of the subtraction h - 1.
+template <class T>
+__device__ __forceinline__ T htilde_of_theta(T th)
+{
+  T a = T(2.25) * th * th;
+  return T(2.5) * th + dv(a, T(1) + sq(a + T(1)));
+}
+
+// Eq. 16: Theta from the reduced enthalpy, with 9 ht^2 + 18 ht + 25 = 9 h^2 + 16.
+template <class T>
+__device__ __forceinline__ T theta_of_htilde(T ht)
+{
+  T h = ht + T(1);
+  return dv(T(2) * ht * (ht + T(2)), T(5) * h + sq(T(9) * h * h + T(16)));
+}
+
+// Eq. 14: squared sound speed.
+template <class T>
+__device__ __forceinline__ T sound_speed2(T th)
+{
+  T h = T(2.5) * th + sq(T(2.25) * th * th + T(1));
+  return dv(th * (T(5) * h - T(8) * th), T(3) * h * (h - th));
+}
+
+// ------------------------------------------------------------------------------ inversion
+// App. A: analytic guess -- hot (Eq. A6) above the threshold of Eq. A7, else the positive root
+// of the quadratic Eq. A3 (the corrected Eq. A4).
+template <class T>
+__device__ __forceinline__ T guess_analytic(T L, T m2)
+{
+  T a = T(1) + m2;
+  T thr = dv(T(1800) * a, T(437) * m2 + T(117));
+  thr *= thr;
+  if (L > thr) return T(4.0 / 3.0) * sq(L);
+  T b = T(43) * m2 + T(63);
+  return dv(T(125) * a * L, T(75) * a + sq(T(125) * a * b * L + T(5625) * a * a));
+}
+
+// Newton iteration for f(ht) = L from x.  With h = ht + 1, s = sqrt(9 h^2 + 16),
+// den = 5 h + s, q = h^2 + m^2 and r = h^2 / q:
+//   Theta  = 2 ht (ht + 2) / den                            (Eq. 16)
+//   Theta' = (4 h - Theta (5 + 9 h / s)) / den              (Eq. A2)
+//   f      = ht (ht + 2) - 2 Theta h + Theta^2 r            (Eq. 15)
+//   f'     = 2 h - 2 Theta - 2 h Theta' + 2 Theta Theta' r + 2 Theta^2 r (m^2/q) / h   (Eq. A1)
+// f is increasing and convex, so from any positive start the iterates stay positive and
+// converge quadratically; the loop stops once the applied step is below tol * ht, which
+// leaves an error of order tol^2.  Returns false on a non-finite iterate or after max_iter.
+template <class T>
+__device__ __forceinline__ bool newton_htilde(T L, T m2, T x, T tol, int max_iter, T &ht,
+                                              int &iters)
+{
+  for (int it = 1; it <= max_iter; ++it) {
+    T h = x + T(1);
+    T s = sq(T(9) * h * h + T(16));
+    T iden = dv(T(1), T(5) * h + s);
+    T th = T(2) * x * (x + T(2)) * iden;
+    T dth = (T(4) * h - th * (T(5) + dv(T(9) * h, s))) * iden;
+    T h2 = h * h;
+    T iq = dv(T(1), h2 + m2);
+    T r = h2 * iq;
+    T omr = m2 * iq;
+    T f = x * (x + T(2)) - T(2) * th * h + th * th * r;
+    T fp = T(2) * (h - th - h * dth + th * dth * r + dv(th * th * r * omr, h));
+    T dx = dv(f - L, fp);
+    x -= dx;
+    if (!(x > T(0)) || !finiteT(x)) { iters = it; ht = x; return false; }
+    if (absT(dx) <= tol * x) { iters = it; ht = x; return true; }
+  }
+  iters = max_iter;
+  ht = x;
+  return false;
+}
+
+enum { ST_OK = 0, ST_UNPHYSICAL = 1, ST_FALLBACK = 2, ST_NOCONV = 3 };
+
+template <class T>
+struct InvOut {
+  T rho, ux, uy, uz, p;        // primitive variables
+  T ht;                        // reduced enthalpy (the root)
+  int status;                  // SRHD_ST_*
+  int iters;                   // Newton iterations (both guesses)
+};
+
+// Recovery after the root: Eqs. 17, 8, 5a, 16, 18.
+template <class T>
+__device__ __forceinline__ void recover(T D, T Mx, T My, T Mz, T ht, InvOut<T> &o)
+{
+  T iDh = dv(T(1), D * (T(1) + ht));
+  o.ux = Mx * iDh;
+  o.uy = My * iDh;
+  o.uz = Mz * iDh;
+  T gam = sq(T(1) + o.ux * o.ux + o.uy * o.uy + o.uz * o.uz);
+  o.rho = dv(D, gam);
+  o.p = o.rho * theta_of_htilde(ht);
+  o.ht = ht;
+}
+
+template <class T>
+__device__ __forceinline__ void set_unphysical(InvOut<T> &o)
+{
+  const T nan = T(__builtin_nan(""));
+  o.rho = o.ux = o.uy = o.uz = o.p = o.ht = nan;
+  o.status = ST_UNPHYSICAL;
+  o.iters = 0;
+}
+
+// The physical check shared by the inversion and the step's output test (Eq. 30, strict).
+template <class T>
+__device__ __forceinline__ bool admissible(T D, T Mx, T My, T Mz, T Et, T eps, T &L)
+{
+  if (!(finiteT(D) && finiteT(Mx) && finiteT(My) && finiteT(Mz) && finiteT(Et)) ||
+      !(D > T(0)) || !(Et > T(0))) {
+    L = T(0);
+    return false;
+  }
+  L = lhs_L(D, Mx, My, Mz, Et);
+  return L > eps;
+}
+
+// Inversion from a known, admissible L.  `guess` <= 0 selects the analytic guess; otherwise
+// the supplied guess is tried first and the analytic guess is the fallback (status FALLBACK
+// when it rescues the inversion).
+template <class T>
+__device__ __forceinline__ void invert_with_L(T D, T Mx, T My, T Mz, T L, T guess, T tol,
+                                              int max_iter, InvOut<T> &o)
+{
+  T iD = dv(T(1), D);
+  T mx = Mx * iD, my = My * iD, mz = Mz * iD;
+  T m2 = mx * mx + my * my + mz * mz;
+  T ht;
+  int it1 = 0, it2 = 0;
+  o.status = ST_OK;
+  bool ok;
+  if (guess > T(0)) {
+    ok = newton_htilde(L, m2, guess, tol, max_iter, ht, it1);
+    if (!ok) {
+      ok = newton_htilde(L, m2, guess_analytic(L, m2), tol, max_iter, ht, it2);
+      o.status = ok ? ST_FALLBACK : ST_NOCONV;
+    }
+  } else {
+    ok = newton_htilde(L, m2, guess_analytic(L, m2), tol, max_iter, ht, it1);
+    if (!ok) o.status = ST_NOCONV;
+  }
+  o.iters = it1 + it2;
+  recover(D, Mx, My, Mz, ht, o);
+}
+
+// ------------------------------------------------------------------------------ prim -> cons
+template <class T>
+struct Prim { T rho, u[3], p; };
+template <class T>
+struct Cons { T D, m[3], E; };   // E is the reduced energy Et
+
+// Eqs. 8, 5a, 22, 5b, 15 (with Theta = p / rho known), 23.
+template <class T>
+__device__ __forceinline__ Cons<T> prim2cons(const Prim<T> &w)
+{
+  T U2 = w.u[0] * w.u[0] + w.u[1] * w.u[1] + w.u[2] * w.u[2];
+  T gam = sq(T(1) + U2);
+  T D = w.rho * gam;
+  T th = dv(w.p, w.rho);
+  T ht = htilde_of_theta(th);
+  T h = T(1) + ht;
+  T Dh = D * h;
+  T h2 = h * h;
+  T m2 = h2 * U2;
+  T f = ht * (ht + T(2)) - T(2) * th * h + dv(th * th * h2, h2 + m2);
+  T a = m2 + f;
+  Cons<T> u;
+  u.D = D;
+  u.m[0] = Dh * w.u[0];
+  u.m[1] = Dh * w.u[1];
+  u.m[2] = Dh * w.u[2];
+  u.E = dv(D * a, T(1) + sq(T(1) + a));
+  return u;
+}
+
+// ------------------------------------------------------------------------------ fluxes
+// The direction d is a template parameter so that every component index is a constant.
+
+// Physical flux along d (Eqs. 4a, 4b, 7) with v_d = U_d / gamma.
+template <int d, class T>
+__device__ __forceinline__ Cons<T> phys_flux(const Prim<T> &w, const Cons<T> &u)
+{
+  T gam = sq(T(1) + w.u[0] * w.u[0] + w.u[1] * w.u[1] + w.u[2] * w.u[2]);
+  T v = dv(w.u[d], gam);
+  Cons<T> F;
+  F.D = u.D * v;
+  F.m[0] = u.m[0] * v;
+  F.m[1] = u.m[1] * v;
+  F.m[2] = u.m[2] * v;
+  F.m[d] += w.p;
+  F.E = (u.E + w.p) * v;
+  return F;
+}
+
+// Signal speeds along d in four-velocity form:
+// lambda_pm = [gamma U_d (1 - cs^2) +- cs sqrt(1 + U_perp^2 (1 - cs^2))] / (1 + U^2 (1 - cs^2)).
+template <int d, class T>
+__device__ __forceinline__ void signal_speeds(const Prim<T> &w, T &lm, T &lp)
+{
+  constexpr int a1 = d == 0 ? 1 : 0, a2 = d == 2 ? 1 : 2;
+  T cs2 = sound_speed2(dv(w.p, w.rho));
+  T cs = sq(cs2);
+  T Ud = w.u[d];
+  T Up2 = w.u[a1] * w.u[a1] + w.u[a2] * w.u[a2];
+  T U2 = Ud * Ud + Up2;
+  T gam = sq(T(1) + U2);
+  T a = T(1) - cs2;
+  T iden = dv(T(1), T(1) + U2 * a);
+  T s = cs * sq(T(1) + Up2 * a);
+  T c = gam * Ud * a;
+  lm = (c - s) * iden;
+  lp = (c + s) * iden;
+}
+
+// HLLE: HLL flux with S_L^- = min(S_L, 0), S_R^+ = max(S_R, 0).
+template <int d, class T>
+__device__ __forceinline__ Cons<T> hlle(const Prim<T> &wl, const Prim<T> &wr)
+{
+  Cons<T> ul = prim2cons(wl), ur = prim2cons(wr);
+  Cons<T> fl = phys_flux<d>(wl, ul), fr = phys_flux<d>(wr, ur);
+  T lmL, lpL, lmR, lpR;
+  signal_speeds<d>(wl, lmL, lpL);
+  signal_speeds<d>(wr, lmR, lpR);
+  T sl = minT(minT(lmL, lmR), T(0));
+  T sr = maxT(maxT(lpL, lpR), T(0));
+  T inv = dv(T(1), sr - sl);
+  T srl = sr * sl;
+  Cons<T> F;
+  F.D = (sr * fl.D - sl * fr.D + srl * (ur.D - ul.D)) * inv;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) F.m[k] = (sr * fl.m[k] - sl * fr.m[k] + srl * (ur.m[k] - ul.m[k])) * inv;
+  F.E = (sr * fl.E - sl * fr.E + srl * (ur.E - ul.E)) * inv;
+  return F;
+}
+
+template <class T>
+__device__ __forceinline__ Cons<T> sel(bool c, const Cons<T> &a, const Cons<T> &b)
+{
+  Cons<T> r;
+  r.D = c ? a.D : b.D;
+  r.m[0] = c ? a.m[0] : b.m[0];
+  r.m[1] = c ? a.m[1] : b.m[1];
+  r.m[2] = c ? a.m[2] : b.m[2];
+  r.E = c ? a.E : b.E;
+  return r;
+}
+
+// HLLC (Mignone & Bodo 2005) with the total energy E = Et + D in the contact-speed quadratic
+// F^E l^2 - (E + F^m) l + m = 0 (root 2 m / (B + sqrt(B^2 - 4 F^E m)), B = E + F^m), the star
+// pressure p* = F^m - l* F^E, and the reduced-energy star state
+// Et* = [Et (S - v) + p* l* - p v] / (S - l*), which carries no rest-mass cancellation.
+template <int d, class T>
+__device__ __forceinline__ Cons<T> hllc(const Prim<T> &wl, const Prim<T> &wr)
+{
+  Cons<T> ul = prim2cons(wl), ur = prim2cons(wr);
+  Cons<T> fl = phys_flux<d>(wl, ul), fr = phys_flux<d>(wr, ur);
+  T lmL, lpL, lmR, lpR;
+  signal_speeds<d>(wl, lmL, lpL);
+  signal_speeds<d>(wr, lmR, lpR);
+  T sl = minT(lmL, lmR);
+  T sr = maxT(lpL, lpR);
+  T inv = dv(T(1), sr - sl);
+  T srl = sl * sr;
+  // HLL averages of the quantities the contact speed needs
+  T Dh = (sr * ur.D - sl * ul.D + fl.D - fr.D) * inv;
+  T Eh = (sr * ur.E - sl * ul.E + fl.E - fr.E) * inv + Dh;
+  T mh = (sr * ur.m[d] - sl * ul.m[d] + fl.m[d] - fr.m[d]) * inv;
+  T FDh = (srl * (ur.D - ul.D) + sr * fl.D - sl * fr.D) * inv;
+  T FEh = (srl * (ur.E - ul.E) + sr * fl.E - sl * fr.E) * inv + FDh;
+  T Fmh = (srl * (ur.m[d] - ul.m[d]) + sr * fl.m[d] - sl * fr.m[d]) * inv;
+  T B = Eh + Fmh;
+  T disc = maxT(B * B - T(4) * FEh * mh, T(0));
+  T ls = dv(T(2) * mh, B + sq(disc));
+  T ps = Fmh - ls * FEh;
+  bool left = ls >= T(0);
+  Cons<T> u = sel(left, ul, ur);
+  Cons<T> f = sel(left, fl, fr);
+  T S = left ? sl : sr;
+  T wu0 = left ? wl.u[0] : wr.u[0];
+  T wu1 = left ? wl.u[1] : wr.u[1];
+  T wu2 = left ? wl.u[2] : wr.u[2];
+  T wp = left ? wl.p : wr.p;
+  T wud = d == 0 ? wu0 : (d == 1 ? wu1 : wu2);
+  T gam = sq(T(1) + wu0 * wu0 + wu1 * wu1 + wu2 * wu2);
+  T v = dv(wud, gam);
+  T a = S - v;
+  T iS = dv(T(1), S - ls);
+  Cons<T> us;
+  us.D = u.D * a * iS;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) us.m[k] = u.m[k] * a * iS;
+  us.m[d] = (u.m[d] * a + ps - wp) * iS;
+  us.E = (u.E * a + ps * ls - wp * v) * iS;
+  Cons<T> F;
+  F.D = f.D + S * (us.D - u.D);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) F.m[k] = f.m[k] + S * (us.m[k] - u.m[k]);
+  F.E = f.E + S * (us.E - u.E);
+  // supersonic cases: the upwind physical flux
+  F = sel(sl >= T(0), fl, F);
+  F = sel(sr <= T(0), fr, F);
+  return F;
+}
+
+// ------------------------------------------------------------------------------ PLM
+// Hybrid van Leer / generalized minmod slope (zero at extrema).
+template <class T>
+__device__ __forceinline__ T limited_slope(T wl, T wc, T wr, T theta)
+{
+  T dl = wc - wl, dr = wr - wc;
+  bool mono = (dl > T(0) && dr > T(0)) || (dl < T(0) && dr < T(0));
+  T vl = absT(dv(T(2) * dl * dr, dl + dr));
+  T s = minT(vl, minT(theta * absT(dl), theta * absT(dr)));
+  s = dl > T(0) ? s : -s;
+  return mono ? s : T(0);
+}
+
+}  // namespace srhd

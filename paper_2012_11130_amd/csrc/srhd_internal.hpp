@@ -1,0 +1,50 @@
+// srhd_internal.hpp -- launch interface between the C ABI (srhd_capi.cpp) and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/srhd.h"
+
+namespace srhd {
+
+struct GuessArgs {
+  int kind;                // srhd_guess_kind
+  int max_iter;
+  const uint16_t *w;       // MLP weights (BF16), NULL for the analytic guess
+  const float *bias;
+  const float *norm;
+};
+
+struct LevelArgs {
+  int n_level;
+  double dh[SRHD_MAX_LEVEL];
+};
+
+hipError_t launch_prim2cons(int dtype, int64_t n, const void *prim, void *cons, hipStream_t s);
+hipError_t launch_cons2prim(int dtype, int64_t n, const void *cons, void *prim, int8_t *status,
+                            uint8_t *iters, const GuessArgs &g, hipStream_t s);
+hipError_t launch_fill_ghosts(int dtype, int64_t n_patch, int ghost, int64_t n_src, const void *interior,
+                              const int32_t *neighbor, void *padded, hipStream_t s);
+hipError_t launch_cfl(int dtype, int64_t n_patch, const void *interior, const LevelArgs &lv,
+                      double c_cfl, double *dt_lev, void *work, hipStream_t s);
+hipError_t launch_stats_reset(srhd_step_stats *st, hipStream_t s);
+
+struct StepArgs {
+  int64_t n_patch;
+  int ghost;
+  const double *padded;
+  const int8_t *level;
+  int n_level;
+  const double *dt_lev;
+  double dh[SRHD_MAX_LEVEL];
+  double theta;
+  int riemann;
+  int max_retry;
+  GuessArgs guess;
+  double *out;
+  srhd_step_stats *stats;
+};
+
+hipError_t launch_step(int prec, const StepArgs &a, hipStream_t s);
+
+}  // namespace srhd

@@ -1,0 +1,392 @@
+// srhd_step.hip -- one unsplit MUSCL-Hancock step (Sec. 3.2) of a batch of padded 8^3 patches
+// on gfx950: one workgroup of 512 threads (8 wavefronts) per patch, with the patch's
+// primitive tile, half-step corrections and interface fluxes staged in LDS.
+//
+// Work per patch (interior coordinates i in [0, 8); ghosts at -1, -2, 8, 9 are used):
+//   A. cell-centre inversions of the 1376 cells the stencil touches       -> LDS W (12^3 box)
+//   B. for the 896 cells whose face states the full step needs (the interior and the first
+//      ghost layer across each face): PLM slopes in x, y, z, the six face states, their
+//      conserved variables and physical fluxes, and the half-step correction
+//      C = -(dt / 2dh) sum_d [F_d(W_{d,+}) - F_d(W_{d,-})]                  -> LDS C (10^3 box)
+//   C. for the 3 x 576 interfaces: the two half-step face states U(W_face) + C, their
+//      inversions, and the HLLC / HLLE flux                                  -> LDS F (ring)
+//   D. the full update U^{n+1} = U^n - (dt/dh) sum_d (F_{+1/2} - F_{-1/2}) with the Eq. 30
+//      check of every output cell.
+// Phase C runs over the flat list of 1728 interfaces in rounds of 512; a two-direction ring
+// buffer of fluxes lets each thread fold a direction's flux differences into its own cell as
+// soon as that direction is complete (x after round 1, y after round 2, z after round 3).
+// If any half-step face state or output cell is unphysical, the whole patch repeats B-D with
+// theta *= 0.75 (max_retry times), then theta = 0 (Sec. 3.4); A is not repeated.
+#include <float.h>
+
+#include "srhd_device.hpp"
+#include "srhd_internal.hpp"
+
+namespace srhd {
+namespace {
+
+constexpr int NT = 512;          // threads per workgroup (one per interior cell)
+constexpr int BX = 12;           // primitive box [-2, 10)^3
+constexpr int NB = BX * BX * BX;
+constexpr int HX = 10;           // half-step box [-1, 9)^3
+constexpr int NHB = HX * HX * HX;
+constexpr int NPC = 1376;        // centre inversions per patch
+constexpr int NHC = 896;         // half-step cells per patch
+constexpr int NIF = 576;         // interfaces per direction (9 x 8 x 8)
+
+constexpr bool in_half(int i, int j, int k)
+{
+  int c[3] = {i, j, k};
+  int out = 0;
+  for (int d = 0; d < 3; ++d) {
+    if (c[d] >= 0 && c[d] < 8) continue;
+    if (c[d] == -1 || c[d] == 8) ++out;
+    else return false;
+  }
+  return out <= 1;
+}
+
+constexpr bool in_prim(int i, int j, int k)
+{
+  return in_half(i, j, k) || in_half(i - 1, j, k) || in_half(i + 1, j, k) ||
+         in_half(i, j - 1, k) || in_half(i, j + 1, k) || in_half(i, j, k - 1) ||
+         in_half(i, j, k + 1);
+}
+
+struct Tables {
+  uint16_t pcell[NPC];   // 12-box index of each centre cell, increasing (x fastest)
+  uint16_t hcell[NHC];   // 10-box index of each half-step cell, increasing
+};
+
+constexpr Tables make_tables()
+{
+  Tables t{};
+  int np = 0, nh = 0;
+  for (int k = -2; k < 10; ++k)
+    for (int j = -2; j < 10; ++j)
+      for (int i = -2; i < 10; ++i) {
+        if (in_prim(i, j, k)) t.pcell[np++] = (uint16_t)(((k + 2) * BX + (j + 2)) * BX + (i + 2));
+        if (in_half(i, j, k)) t.hcell[nh++] = (uint16_t)(((k + 1) * HX + (j + 1)) * HX + (i + 1));
+      }
+  return t;
+}
+
+constexpr Tables kTabInit = make_tables();
+static_assert(kTabInit.pcell[NPC - 1] != 0 && kTabInit.hcell[NHC - 1] != 0, "cell tables");
+__constant__ Tables kTab = kTabInit;
+
+template <class T> struct StepTol;
+template <> struct StepTol<double> { static constexpr double v = 0x1p-27; };
+template <> struct StepTol<float> { static constexpr double v = 0x1p-14; };
+
+// LDS tile.  Field-major so that neighbouring lanes touch neighbouring words.
+template <class T>
+struct Tile {
+  T W[5][NB];            // centre primitives (rho, Ux, Uy, Uz, p), 12^3 box
+  T C[5][NHB];           // half-step corrections, 10^3 box
+  T F[2][5][NIF];        // interface fluxes of two directions (ring)
+  unsigned int cnt[8];   // workgroup counters
+};
+
+__device__ __forceinline__ int bidx(int i, int j, int k) { return ((k + 2) * BX + (j + 2)) * BX + (i + 2); }
+__device__ __forceinline__ int hidx(int i, int j, int k) { return ((k + 1) * HX + (j + 1)) * HX + (i + 1); }
+
+template <class T>
+__device__ __forceinline__ Prim<T> load_prim(const Tile<T> &s, int b)
+{
+  Prim<T> w;
+  w.rho = s.W[0][b];
+  w.u[0] = s.W[1][b];
+  w.u[1] = s.W[2][b];
+  w.u[2] = s.W[3][b];
+  w.p = s.W[4][b];
+  return w;
+}
+
+// Double inversion of bulk-type conserved variables (FP64 path: lhs_L in double; mixed path:
+// the float values' products are exact in double).
+__device__ __forceinline__ double L_of(const Cons<double> &u) { return lhs_L(u.D, u.m[0], u.m[1], u.m[2], u.E); }
+__device__ __forceinline__ double L_of(const Cons<float> &u) { return lhs_L_from_f32(u.D, u.m[0], u.m[1], u.m[2], u.E); }
+
+template <class T>
+__device__ __forceinline__ bool invert_face(const Cons<T> &u, Prim<T> &w, int &iters, int &status)
+{
+  double D = u.D, Mx = u.m[0], My = u.m[1], Mz = u.m[2], Et = u.E;
+  bool ok = finiteT(D) && finiteT(Mx) && finiteT(My) && finiteT(Mz) && finiteT(Et) &&
+            D > 0.0 && Et > 0.0;
+  double L = ok ? L_of(u) : 0.0;
+  ok = ok && L > DBL_EPSILON;
+  InvOut<double> o;
+  if (ok) invert_with_L(D, Mx, My, Mz, L, -1.0, StepTol<T>::v, 30, o);
+  else set_unphysical(o);
+  w.rho = (T)o.rho;
+  w.u[0] = (T)o.ux;
+  w.u[1] = (T)o.uy;
+  w.u[2] = (T)o.uz;
+  w.p = (T)o.p;
+  iters = o.iters;
+  status = o.status;
+  return ok;
+}
+
+// Face state of cell (i, j, k) on side `side` (0: minus, 1: plus) of direction d: PLM along d,
+// prim -> cons, plus the cell's half-step correction, then the inversion.
+template <int d, class T>
+__device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, int j, int k,
+                                           T theta, Prim<T> &w, int &iters, int &status)
+{
+  constexpr int sd = d == 0 ? 1 : (d == 1 ? BX : BX * BX);
+  int b = bidx(i, j, k);
+  int hb = hidx(i, j, k);
+  T half = side ? T(0.5) : T(-0.5);
+  Prim<T> wf;
+  T v[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    T wc = s.W[f][b];
+    v[f] = wc + half * limited_slope(s.W[f][b - sd], wc, s.W[f][b + sd], theta);
+  }
+  wf.rho = v[0];
+  wf.u[0] = v[1];
+  wf.u[1] = v[2];
+  wf.u[2] = v[3];
+  wf.p = v[4];
+  Cons<T> u = prim2cons(wf);
+  u.D += s.C[0][hb];
+  u.m[0] += s.C[1][hb];
+  u.m[1] += s.C[2][hb];
+  u.m[2] += s.C[3][hb];
+  u.E += s.C[4][hb];
+  return invert_face(u, w, iters, status);
+}
+
+struct IfaceCount {
+  unsigned int iters, inv, fb, nc, unphys;
+};
+
+// Flux through interface r of direction d (between cells c-1 and c along d; transverse
+// coordinates (bb, aa) in increasing axis order), written to the ring slot of d.
+template <int d, class T>
+__device__ __forceinline__ bool interface_flux(Tile<T> &s, int r, T theta, int solver,
+                                               IfaceCount &cnt)
+{
+  constexpr int a1 = d == 0 ? 1 : 0, a2 = d == 2 ? 1 : 2;
+  int c = r % 9, ab = r / 9, bb = ab & 7, aa = ab >> 3;
+  int cr[3];
+  cr[d] = c;
+  cr[a1] = bb;
+  cr[a2] = aa;
+  int cl[3] = {cr[0], cr[1], cr[2]};
+  cl[d] -= 1;
+  Prim<T> wl, wr;
+  int itl, itr, stl, str;
+  bool okl = face_state<d>(s, 1, cl[0], cl[1], cl[2], theta, wl, itl, stl);
+  bool okr = face_state<d>(s, 0, cr[0], cr[1], cr[2], theta, wr, itr, str);
+  cnt.iters += itl + itr;
+  cnt.inv += 2;
+  cnt.fb += (stl == ST_FALLBACK) + (str == ST_FALLBACK);
+  cnt.nc += (stl == ST_NOCONV) + (str == ST_NOCONV);
+  cnt.unphys += !okl + !okr;
+  Cons<T> F = solver == SRHD_HLLE ? hlle<d>(wl, wr) : hllc<d>(wl, wr);
+  constexpr int slot = d & 1;
+  s.F[slot][0][r] = F.D;
+  s.F[slot][1][r] = F.m[0];
+  s.F[slot][2][r] = F.m[1];
+  s.F[slot][3][r] = F.m[2];
+  s.F[slot][4][r] = F.E;
+  return okl && okr;
+}
+
+template <class T>
+__global__ void __launch_bounds__(NT) k_step(StepArgs a)
+{
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Tile<T> &s = *reinterpret_cast<Tile<T> *>(smem_raw);
+  const int tid = threadIdx.x;
+  const int64_t p = blockIdx.x;
+  const int g = a.ghost;
+  const int N = 8 + 2 * g;
+  const int N3 = N * N * N;
+  const double *__restrict__ q = a.padded + p * 5 * N3;
+  int lv = a.level ? (int)a.level[p] : 0;
+  lv = lv < 0 ? 0 : (lv >= a.n_level ? a.n_level - 1 : lv);     // never index past dt_lev
+  const double dt = a.dt_lev[lv];
+  const double dh = a.dh[lv];
+
+  if (tid < 8) s.cnt[tid] = 0u;
+  unsigned int my_iters = 0, my_inv = 0, my_fb = 0, my_nc = 0;
+  __syncthreads();
+
+  // ---------------------------------------------------------------- A: centre inversions
+  bool centre_bad = false;
+  unsigned int centre_unphys = 0;
+  for (int r = tid; r < NPC; r += NT) {
+    int b = kTab.pcell[r];
+    int bi = b % BX, bj = (b / BX) % BX, bk = b / (BX * BX);
+    int off = ((bk + g - 2) * N + (bj + g - 2)) * N + (bi + g - 2);
+    double D = q[off], Mx = q[N3 + off], My = q[2 * N3 + off], Mz = q[3 * N3 + off],
+           Et = q[4 * N3 + off];
+    double L;
+    InvOut<double> o;
+    if (admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L)) invert_with_L(D, Mx, My, Mz, L, -1.0, StepTol<T>::v, 30, o);
+    else set_unphysical(o);
+    centre_bad |= o.status == ST_UNPHYSICAL;
+    centre_unphys += o.status == ST_UNPHYSICAL;
+    my_iters += o.iters;
+    my_inv += 1;
+    my_nc += o.status == ST_NOCONV;
+    s.W[0][b] = (T)o.rho;
+    s.W[1][b] = (T)o.ux;
+    s.W[2][b] = (T)o.uy;
+    s.W[3][b] = (T)o.uz;
+    s.W[4][b] = (T)o.p;
+  }
+  centre_bad = __syncthreads_or(centre_bad);
+
+  // this thread's interior cell for phase D
+  const int ci = tid & 7, cj = (tid >> 3) & 7, ck = tid >> 6;
+  const int cq = ((ck + g) * N + (cj + g)) * N + (ci + g);
+
+  T theta = (T)a.theta;
+  unsigned int retries = 0, unphys = 0;
+  for (int attempt = 0;; ++attempt) {
+    // -------------------------------------------------------------- B: half-step corrections
+    const T half = T(0.5 * dt / dh);
+    for (int r = tid; r < NHC; r += NT) {
+      int hb = kTab.hcell[r];
+      int i = hb % HX - 1, j = (hb / HX) % HX - 1, k = hb / (HX * HX) - 1;
+      int b = bidx(i, j, k);
+      Prim<T> wc = load_prim(s, b);
+      T acc[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int sd = d == 0 ? 1 : (d == 1 ? BX : BX * BX);
+        Prim<T> wm = load_prim(s, b - sd), wp = load_prim(s, b + sd);
+        T sl[5];
+        sl[0] = limited_slope(wm.rho, wc.rho, wp.rho, theta);
+        sl[1] = limited_slope(wm.u[0], wc.u[0], wp.u[0], theta);
+        sl[2] = limited_slope(wm.u[1], wc.u[1], wp.u[1], theta);
+        sl[3] = limited_slope(wm.u[2], wc.u[2], wp.u[2], theta);
+        sl[4] = limited_slope(wm.p, wc.p, wp.p, theta);
+        Prim<T> fm, fp;
+        fm.rho = wc.rho - T(0.5) * sl[0];  fp.rho = wc.rho + T(0.5) * sl[0];
+        fm.u[0] = wc.u[0] - T(0.5) * sl[1]; fp.u[0] = wc.u[0] + T(0.5) * sl[1];
+        fm.u[1] = wc.u[1] - T(0.5) * sl[2]; fp.u[1] = wc.u[1] + T(0.5) * sl[2];
+        fm.u[2] = wc.u[2] - T(0.5) * sl[3]; fp.u[2] = wc.u[2] + T(0.5) * sl[3];
+        fm.p = wc.p - T(0.5) * sl[4];      fp.p = wc.p + T(0.5) * sl[4];
+        Cons<T> Fm, Fp;
+        if (d == 0) { Fm = phys_flux<0>(fm, prim2cons(fm)); Fp = phys_flux<0>(fp, prim2cons(fp)); }
+        else if (d == 1) { Fm = phys_flux<1>(fm, prim2cons(fm)); Fp = phys_flux<1>(fp, prim2cons(fp)); }
+        else { Fm = phys_flux<2>(fm, prim2cons(fm)); Fp = phys_flux<2>(fp, prim2cons(fp)); }
+        acc[0] += Fp.D - Fm.D;
+        acc[1] += Fp.m[0] - Fm.m[0];
+        acc[2] += Fp.m[1] - Fm.m[1];
+        acc[3] += Fp.m[2] - Fm.m[2];
+        acc[4] += Fp.E - Fm.E;
+      }
+#pragma unroll
+      for (int f = 0; f < 5; ++f) s.C[f][hb] = -half * acc[f];
+    }
+    __syncthreads();
+
+    // -------------------------------------------------------------- C + D: fluxes, update
+    bool fail = false;
+    T dU[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll 1
+    for (int round = 0; round < 4; ++round) {
+      int qi = round * NT + tid;
+      if (qi < 3 * NIF) {
+        // 576 = 9 x 64: the direction is uniform across each wavefront
+        int d = qi / NIF;
+        int r = qi - d * NIF;
+        IfaceCount ic = {0, 0, 0, 0, 0};
+        bool ok;
+        if (d == 0) ok = interface_flux<0>(s, r, theta, a.riemann, ic);
+        else if (d == 1) ok = interface_flux<1>(s, r, theta, a.riemann, ic);
+        else ok = interface_flux<2>(s, r, theta, a.riemann, ic);
+        fail |= !ok;
+        my_iters += ic.iters;
+        my_inv += ic.inv;
+        my_fb += ic.fb;
+        my_nc += ic.nc;
+        unphys += ic.unphys;
+      }
+      __syncthreads();
+      if (round >= 1) {
+        // direction round-1 is complete: fold F_{+1/2} - F_{-1/2} into this thread's cell
+        int d = round - 1;
+        int slot = d & 1;
+        int cc = d == 0 ? ci : (d == 1 ? cj : ck);
+        int t0 = d == 0 ? cj : ci;
+        int t1 = d == 2 ? cj : ck;
+        int r = (t1 * 8 + t0) * 9 + cc;
+#pragma unroll
+        for (int f = 0; f < 5; ++f) dU[f] += s.F[slot][f][r + 1] - s.F[slot][f][r];
+        __syncthreads();
+      }
+    }
+    const double full = dt / dh;
+    double un[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) un[f] = q[f * N3 + cq] - full * (double)dU[f];
+    double Lo;
+    bool ok_out = admissible(un[0], un[1], un[2], un[3], un[4], DBL_EPSILON, Lo);
+    fail |= !ok_out;
+    fail = __syncthreads_or(fail);
+    bool last = !fail || centre_bad || theta == T(0);
+    if (last) {
+      double *o = a.out + p * 5 * 512 + tid;
+#pragma unroll
+      for (int f = 0; f < 5; ++f) o[f * 512] = un[f];
+      unphys += !ok_out;
+      break;
+    }
+    ++retries;
+    unphys = 0;
+    theta = attempt < a.max_retry ? theta * T(0.75) : T(0);
+  }
+
+  // ---------------------------------------------------------------- counters
+  if (a.stats) {
+    atomicAdd(&s.cnt[0], unphys + centre_unphys);
+    atomicAdd(&s.cnt[1], my_fb);
+    atomicAdd(&s.cnt[2], my_nc);
+    atomicAdd(&s.cnt[3], my_iters);
+    atomicAdd(&s.cnt[4], my_inv);
+    __syncthreads();
+    if (tid == 0) {
+      unsigned long long *st = (unsigned long long *)a.stats;
+      if (s.cnt[0]) atomicAdd(&st[0], (unsigned long long)s.cnt[0]);
+      if (s.cnt[1]) atomicAdd(&st[1], (unsigned long long)s.cnt[1]);
+      if (s.cnt[2]) atomicAdd(&st[2], (unsigned long long)s.cnt[2]);
+      atomicAdd(&st[3], (unsigned long long)s.cnt[3]);
+      atomicAdd(&st[4], (unsigned long long)s.cnt[4]);
+      if (retries) atomicAdd(&st[5], (unsigned long long)retries);
+    }
+  }
+}
+
+template <class T>
+hipError_t launch_step_t(const StepArgs &a, hipStream_t st)
+{
+  const size_t bytes = sizeof(Tile<T>);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_step<T>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_step<T>, dim3((unsigned)a.n_patch), dim3(NT), bytes, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_step(int prec, const StepArgs &a, hipStream_t st)
+{
+  if (a.n_patch == 0) return hipSuccess;
+  return prec == SRHD_PREC_MIXED ? launch_step_t<float>(a, st) : launch_step_t<double>(a, st);
+}
+
+}  // namespace srhd

@@ -1,0 +1,236 @@
+"""Thin ctypes binding of libsrhd (include/srhd.h) for PyTorch device tensors.
+
+Argument marshalling only: every computation runs in the HIP kernels of libsrhd.so.  Tensors
+must live on the GPU; the current torch stream is passed to the library.  Importing this module
+fails loudly if the library has not been built (``python -m paper_2012_11130_amd.build``).
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsrhd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libsrhd.so is missing: build it with `python -m paper_2012_11130_amd.build` "
+                      "(there is no fallback implementation)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+F64, F32 = 0, 1
+OK, EINVAL, EHIP, EUNSUPPORTED = 0, -1, -2, -3
+ST_OK, ST_UNPHYSICAL, ST_FALLBACK, ST_NOCONV = 0, 1, 2, 3
+GUESS_ANALYTIC, GUESS_MLP = 0, 1
+HLLC, HLLE = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+MAX_LEVEL = 8
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_int = ctypes.c_int
+
+
+class srhd_mlp(ctypes.Structure):
+    _fields_ = [("w_bf16", _vp), ("bias", _vp), ("norm", _vp)]
+
+
+class srhd_guess(ctypes.Structure):
+    _fields_ = [("kind", _int), ("mlp", ctypes.POINTER(srhd_mlp)), ("max_iter", _int)]
+
+
+class srhd_patches(ctypes.Structure):
+    _fields_ = [("n_patch", _i64), ("ghost", _int), ("dtype", _int), ("padded", _vp),
+                ("level", _vp), ("n_level", _int), ("dh", ctypes.c_double * MAX_LEVEL)]
+
+
+class srhd_step_params(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_double), ("riemann", _int), ("prec", _int),
+                ("max_retry", _int), ("guess", srhd_guess)]
+
+
+class srhd_step_stats(ctypes.Structure):
+    _fields_ = [("n_unphysical", ctypes.c_uint64), ("n_fallback", ctypes.c_uint64),
+                ("n_noconv", ctypes.c_uint64), ("newton_iters", ctypes.c_uint64),
+                ("n_inversions", ctypes.c_uint64), ("n_retry", ctypes.c_uint64),
+                ("reserved", ctypes.c_uint64 * 2)]
+
+
+STATS_FIELDS = ("n_unphysical", "n_fallback", "n_noconv", "newton_iters", "n_inversions",
+                "n_retry")
+
+_sig = {
+    "srhd_prim2cons": [_int, _i64, _vp, _vp, _vp],
+    "srhd_cons2prim": [_int, _i64, _vp, _vp, _vp, _vp, ctypes.POINTER(srhd_guess), _vp],
+    "srhd_fill_ghosts": [_int, _i64, _int, _i64, _vp, _vp, _vp, _vp],
+    "srhd_cfl_dt": [_int, _i64, _vp, _int, ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                    _vp, _vp, _vp],
+    "srhd_stats_reset": [_vp, _vp],
+    "srhd_fluid_step": [ctypes.POINTER(srhd_patches), _vp, _vp,
+                        ctypes.POINTER(srhd_step_params), _vp, _vp],
+}
+for _name, _args in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _int
+_lib.srhd_last_error.argtypes = []
+_lib.srhd_last_error.restype = ctypes.c_char_p
+_lib.srhd_cfl_work_bytes.argtypes = []
+_lib.srhd_cfl_work_bytes.restype = ctypes.c_size_t
+_lib.srhd_abi_version.argtypes = []
+_lib.srhd_abi_version.restype = _int
+
+EXPORTS = tuple(_sig) + ("srhd_last_error", "srhd_cfl_work_bytes", "srhd_abi_version")
+
+
+class SrhdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("libsrhd error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _check(rc):
+    if rc != OK:
+        raise SrhdError(rc, _lib.srhd_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dtype_code(t):
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError("expected float64 or float32 tensor, got %s" % t.dtype)
+
+
+def _need_cuda(*ts):
+    for t in ts:
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("tensors must be contiguous GPU tensors")
+
+
+# ------------------------------------------------------------------------------- conversions
+def srhd_prim2cons(prim, cons=None):
+    """prim [5][n] -> cons [5][n] (same dtype)."""
+    _need_cuda(prim)
+    if cons is None:
+        cons = torch.empty_like(prim)
+    _need_cuda(cons)
+    n = prim.shape[-1]
+    _check(_lib.srhd_prim2cons(_dtype_code(prim), n, _ptr(prim), _ptr(cons), _stream()))
+    return cons
+
+
+def srhd_cons2prim(cons, prim=None, status=None, iters=None, guess=None, max_iter=0):
+    """cons [5][n] -> prim [5][n]; status int8 [n] and iters uint8 [n] if given (or True)."""
+    _need_cuda(cons)
+    n = cons.shape[-1]
+    if prim is None:
+        prim = torch.empty_like(cons)
+    if status is True:
+        status = torch.empty(n, dtype=torch.int8, device=cons.device)
+    if iters is True:
+        iters = torch.empty(n, dtype=torch.uint8, device=cons.device)
+    _need_cuda(prim, status, iters)
+    g = guess if guess is not None else srhd_guess(GUESS_ANALYTIC, None, max_iter)
+    _check(_lib.srhd_cons2prim(_dtype_code(cons), n, _ptr(cons), _ptr(prim), _ptr(status),
+                               _ptr(iters), ctypes.byref(g), _stream()))
+    return prim, status, iters
+
+
+# ------------------------------------------------------------------------------- patches
+def srhd_fill_ghosts(interior, neighbor, ghost=3, padded=None):
+    """interior [Q][5][8][8][8] + neighbour table [P][27] int32 -> padded [P][5][N][N][N]."""
+    _need_cuda(interior, neighbor)
+    if neighbor.dtype != torch.int32:
+        raise TypeError("neighbour table must be int32")
+    P = neighbor.shape[0]
+    N = 8 + 2 * ghost
+    if padded is None:
+        padded = torch.empty((P, 5, N, N, N), dtype=interior.dtype, device=interior.device)
+    _need_cuda(padded)
+    _check(_lib.srhd_fill_ghosts(_dtype_code(interior), P, ghost, interior.shape[0],
+                                 _ptr(interior), _ptr(neighbor),
+                                 _ptr(padded), _stream()))
+    return padded
+
+
+_cfl_work = {}
+
+
+def _work(device):
+    key = (device.type, device.index)
+    if key not in _cfl_work:
+        n = int(_lib.srhd_cfl_work_bytes())
+        _cfl_work[key] = torch.empty(n, dtype=torch.uint8, device=device)
+    return _cfl_work[key]
+
+
+def srhd_cfl_dt(interior, dh, c_cfl=0.5, dt_lev=None, work=None):
+    """Per-level time step (device float64 [n_level]) from interior cons [P][5][8][8][8]."""
+    _need_cuda(interior)
+    dh = [float(x) for x in dh]
+    nl = len(dh)
+    if dt_lev is None:
+        dt_lev = torch.empty(nl, dtype=torch.float64, device=interior.device)
+    if work is None:
+        work = _work(interior.device)
+    arr = (ctypes.c_double * nl)(*dh)
+    _check(_lib.srhd_cfl_dt(_dtype_code(interior), interior.shape[0], _ptr(interior), nl, arr,
+                            float(c_cfl), _ptr(dt_lev), _ptr(work), _stream()))
+    return dt_lev
+
+
+def new_stats(device):
+    return torch.zeros(8, dtype=torch.int64, device=device)
+
+
+def stats_dict(stats):
+    v = stats.cpu().tolist()
+    return dict(zip(STATS_FIELDS, v[:len(STATS_FIELDS)]))
+
+
+def srhd_stats_reset(stats):
+    _check(_lib.srhd_stats_reset(_ptr(stats), _stream()))
+
+
+def srhd_fluid_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann=HLLC,
+                    prec=PREC_FP64, max_retry=4, stats=None, ghost=None, guess=None):
+    """One MUSCL-Hancock step: padded cons [P][5][N][N][N] -> interior [P][5][8][8][8]."""
+    _need_cuda(padded, dt_lev, level, stats)
+    P = padded.shape[0]
+    N = padded.shape[-1]
+    g = (N - 8) // 2 if ghost is None else ghost
+    if out is None:
+        out = torch.empty((P, 5, 8, 8, 8), dtype=torch.float64, device=padded.device)
+    _need_cuda(out)
+    dh = [float(x) for x in dh]
+    d = srhd_patches()
+    d.n_patch = P
+    d.ghost = g
+    d.dtype = _dtype_code(padded)
+    d.padded = padded.data_ptr()
+    d.level = None if level is None else level.data_ptr()
+    d.n_level = len(dh)
+    for i, h in enumerate(dh):
+        d.dh[i] = h
+    prm = srhd_step_params()
+    prm.theta = float(theta)
+    prm.riemann = int(riemann)
+    prm.prec = int(prec)
+    prm.max_retry = int(max_retry)
+    prm.guess = guess if guess is not None else srhd_guess(GUESS_ANALYTIC, None, 0)
+    _check(_lib.srhd_fluid_step(ctypes.byref(d), _ptr(out), _ptr(dt_lev), ctypes.byref(prm),
+                                _ptr(stats), _stream()))
+    return out
+
+
+def abi_version():
+    return _lib.srhd_abi_version()

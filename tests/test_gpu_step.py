@@ -1,0 +1,145 @@
+"""GPU parity of the patch step against the CPU oracle (Sec. 3), through the C ABI.
+
+FP64 path: ghost fill bit-exact, the CFL time step within 1e-13, and one step within 1e-10 on
+the same inputs (D and Et pointwise relative, each momentum component normwise over the grid).
+Multi-step runs are compared with each side advancing from its own state.  The mixed path
+(FP32 bulk, FP64 inversion) states its per-field error against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from tests.parity import oracle_cons, step_errors
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2012_11130_amd import srhd
+    return srhd
+
+
+def _gpu(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    return t if dtype is None else t.to(dtype)
+
+
+def _one_step_pair(S, grid, cons, prec=0, riemann=0, theta=1.5):
+    """Oracle and GPU one step from the same cons; the same dt (the oracle's) on both sides."""
+    dt_o, _, _ = O.cfl_dt(cons, None, grid.dh_lev, 0.5)
+    pad_o = O.fill_ghosts(cons, grid.neighbor, 3)
+    ref, cnt = O.fluid_step(pad_o, dt_o, grid.dh_lev, None, theta, riemann)
+    c = _gpu(cons)
+    nb = _gpu(grid.neighbor)
+    dt_g = S.srhd_cfl_dt(c, grid.dh_lev, 0.5)
+    pad = S.srhd_fill_ghosts(c, nb, 3)
+    st = S.new_stats(DEV)
+    out = S.srhd_fluid_step(pad, _gpu(dt_o), grid.dh_lev, theta=theta, riemann=riemann,
+                            prec=prec, stats=st)
+    torch.cuda.synchronize()
+    return dict(ref=ref, cnt=cnt, dt_o=dt_o, pad_o=pad_o, out=out.cpu().numpy(),
+                dt_g=dt_g.cpu().numpy(), pad=pad.cpu().numpy(), stats=S.stats_dict(st))
+
+
+@pytest.mark.parametrize("riemann", [0, 1])
+def test_shock_tube_one_step_fp64(S, riemann):
+    g = W.shock_tube_32()
+    r = _one_step_pair(S, g, oracle_cons(g), riemann=riemann)
+    assert np.array_equal(r["pad"], r["pad_o"])
+    assert abs(r["dt_g"][0] / r["dt_o"][0] - 1) < 1e-13
+    e = step_errors(r["out"], r["ref"])
+    assert max(e.values()) <= 1e-10, e
+    assert r["stats"]["n_unphysical"] == 0 and r["cnt"][0] == 0
+    assert r["stats"]["n_retry"] == r["cnt"][3]
+    assert r["stats"]["n_inversions"] == 64 * (1376 + 3456)
+
+
+def test_ragged_patch_count_and_determinism(S):
+    # 5 patches of a shock tube row (not a multiple of anything), run twice: bitwise equal.
+    g = W.riemann_1d(40, (1.0, 0.3, 0.0, 0.0, 10.0), (0.2, -0.1, 0.05, 0.0, 1e-3), x0=0.43)
+    cons = oracle_cons(g)
+    r1 = _one_step_pair(S, g, cons)
+    e = step_errors(r1["out"], r1["ref"])
+    assert max(e.values()) <= 1e-10, e
+    r2 = _one_step_pair(S, g, cons)
+    assert np.array_equal(r1["out"], r2["out"])
+
+
+def test_blast_multistep_fp64_with_retries(S):
+    # 64^3 blast, 4 steps, each side from its own state with its own dt: the hot ellipsoid
+    # triggers limiter retries (Sec. 3.4); both sides must retry the same patches.
+    g = W.blast(64, seed=3)
+    co = oracle_cons(g)
+    cg = _gpu(co)
+    nb = _gpu(g.neighbor)
+    for step in range(4):
+        dt_o, _, _ = O.cfl_dt(co, None, g.dh_lev, 0.5)
+        pad_o = O.fill_ghosts(co, g.neighbor, 3)
+        co, cnt = O.fluid_step(pad_o, dt_o, g.dh_lev)
+        dt_g = S.srhd_cfl_dt(cg, g.dh_lev, 0.5)
+        pad = S.srhd_fill_ghosts(cg, nb, 3)
+        st = S.new_stats(DEV)
+        cg = S.srhd_fluid_step(pad, dt_g, g.dh_lev, stats=st)
+        torch.cuda.synchronize()
+        assert abs(dt_g.cpu().item() / dt_o[0] - 1) < 1e-12
+        sd = S.stats_dict(st)
+        assert sd["n_unphysical"] == 0 and sd["n_retry"] == cnt[3], (step, sd, cnt)
+        e = step_errors(cg.cpu().numpy(), co)
+        assert max(e.values()) <= 1e-10 * (step + 1), (step, e)
+
+
+def test_conservation_on_gpu(S):
+    # periodic box: sum of D, M, Et conserved to round-off while no patch retries
+    g = W.blast(32, seed=5)
+    g.prim[:, 4] = np.where(g.extra["labels"] == 1, 1.0, 0.1)
+    _, _, z = W.patch_cell_centres(4, 4, 4, 1 / 32)
+    g.prim[:, 1] = 0.3 * np.sin(2 * np.pi * z)
+    c0 = _gpu(oracle_cons(g))
+    nb = _gpu(g.neighbor)
+    c = c0
+    st = S.new_stats(DEV)
+    for _ in range(3):
+        dt = S.srhd_cfl_dt(c, g.dh_lev)
+        c = S.srhd_fluid_step(S.srhd_fill_ghosts(c, nb), dt, g.dh_lev, stats=st)
+    torch.cuda.synchronize()
+    assert S.stats_dict(st)["n_retry"] == 0
+    a, b = c0.cpu().numpy(), c.cpu().numpy()
+    for f in range(5):
+        tot = np.abs(a[:, f]).sum() + np.abs(b[:, f]).sum()
+        assert abs(b[:, f].sum() - a[:, f].sum()) <= 1e-13 * tot, f
+
+
+def test_mixed_precision_error_is_stated(S):
+    # FP32 reconstruction / fluxes / increment with FP64 inversion: per-field error against the
+    # FP64 oracle after one step of the shock tube and of the 64^3 blast.
+    for g in (W.shock_tube_32(), W.blast(64, seed=3)):
+        r = _one_step_pair(S, g, oracle_cons(g), prec=1)
+        e = step_errors(r["out"], r["ref"])
+        assert e["D"] < 1e-5 and e["Et"] < 1e-4 and max(e["Mx"], e["My"], e["Mz"]) < 1e-4, (g.name, e)
+
+
+def test_full_size_blast_sampled_patches(S):
+    # 256^3 (32768 patches) in the benchmark's launch configuration; the step is patch-local
+    # given its padded input, so sampled patches are checked against the oracle one by one.
+    g = W.blast(256, seed=1003)
+    cons = oracle_cons(g)
+    c = _gpu(cons)
+    nb = _gpu(g.neighbor)
+    dt_g = S.srhd_cfl_dt(c, g.dh_lev)
+    pad = S.srhd_fill_ghosts(c, nb)
+    out = S.srhd_fluid_step(pad, dt_g, g.dh_lev)
+    torch.cuda.synchronize()
+    dt = dt_g.cpu().numpy()
+    dt_o, _, _ = O.cfl_dt(cons, None, g.dh_lev, 0.5)
+    assert abs(dt[0] / dt_o[0] - 1) < 1e-13
+    lab = g.extra["labels"].reshape(g.n_patch, -1).any(axis=1)
+    rng = np.random.default_rng(0)
+    sample = np.unique(np.concatenate([np.nonzero(lab)[0], rng.choice(g.n_patch, 200, replace=False)]))
+    pad_o = O.fill_ghosts(cons, g.neighbor[sample], 3)
+    ref, cnt = O.fluid_step(pad_o, dt, g.dh_lev)
+    e = step_errors(out.cpu().numpy()[sample], ref)
+    assert max(e.values()) <= 1e-10, e

@@ -31,7 +31,7 @@ def neighbor_table(nx, ny, nz, periodic):
     """Neighbour table [P][27] of an nx*ny*nz block of same-level patches.
 
     Slot (oz+1)*9 + (oy+1)*3 + (ox+1) holds the patch at offset (ox, oy, oz); slot 13 is the
-    patch itself.  Outside a non-periodic box the entry is -1.  Patch id = (pz*ny + py)*nx + px.
+    patch's own index.  Outside a non-periodic box the entry is -1.  Patch id = (pz*ny + py)*nx + px.
     """
     P = nx * ny * nz
     nb = np.full((P, 27), -1, dtype=np.int32)
