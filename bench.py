@@ -37,7 +37,10 @@ FLOP_FACE = 105          # slope + face state + prim2cons + correction (inversio
 FLOP_RIEMANN = 260       # HLLC: 2 prim2cons, 2 fluxes, 4 signal speeds, HLL averages, star state
 FLOP_UPDATE = 180        # flux differences, update, exact-L admissibility check of the output
 HALF_CELLS, INTERFACES, OUT_CELLS = 896, 1728, 512
-IO_BYTES_PER_PATCH = (1376 + 512) * 5 * 8     # the tile cells the step needs + the 8^3 output
+IO_BYTES_PER_PATCH = {                         # what one patch's step consumes and produces
+    "padded": (1376 + 512) * 5 * 8,            # FP64 tile cells + FP64 output
+    "grid": 1376 * 5 * 4 + 512 * 5 * (8 + 8 + 4),   # FP32 tile prims, cons in/out, prims out
+}
 
 # HBM bytes per launch of the mixed step kernel on this workload, from the rocprofv3
 # FETCH_SIZE / WRITE_SIZE runs summarised in profiles/step_blast256_mixed.md; valid only for the
@@ -117,6 +120,8 @@ def parse():
     ap.add_argument("--conversion", type=int, default=100_000_000,
                     help="states of the standalone conversion batch (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--path", choices=("grid", "padded"), default="grid",
+                    help="grid: gather-mode step chain (default); padded: CFL + fill + step")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB of a plain elementwise copy run once before the steps, as the "
                          "calibration kernel for hardware byte counters (0 = none)")
@@ -143,7 +148,7 @@ def main():
 
     # ---------------------------------------------------------------- inputs (resident in HBM)
     t0 = time.time()
-    g = W.blast(args.cells, seed=1003)
+    g = W.blast(args.cells, seed=1003, order="morton")
     P = g.n_patch
     n_cells = P * 512
     prim = torch.from_numpy(g.prim).to(dev)                            # [P][5][8][8][8]
@@ -167,8 +172,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    def run(prec, n_steps, time_kernel=False):
-        """n_steps from the initial state; returns (total ms, [step-kernel ms], stats dict)."""
+    def run_padded(prec, n_steps, time_kernel=False):
+        """n_steps from the initial state with CFL kernel + ghost fill + padded step."""
         bufs[0].copy_(cons0)
         cur = 0
         S.srhd_stats_reset(stats)
@@ -194,6 +199,47 @@ def main():
         ms = e_start.elapsed_time(e_end)
         kms = [a.elapsed_time(b) for a, b in evs]
         return ms, kms, S.stats_dict(stats), bufs[cur]
+
+    pbufs = {}
+
+    def run_grid(prec, n_steps, time_kernel=False):
+        """n_steps from the initial state with the gather-mode step: each step is one kernel
+        that reads ghosts from neighbour interiors and returns the next S_max; the entry
+        inversion of the initial state is inside the timed region."""
+        pdt = S.prims_dtype(prec)
+        key = str(pdt)
+        if key not in pbufs:
+            pbufs[key] = [torch.empty(cons0.shape, dtype=pdt, device=dev) for _ in range(2)]
+        pb = pbufs[key]
+        sb = [torch.empty(1, dtype=torch.int64, device=dev) for _ in range(2)]
+        bufs[0].copy_(cons0)
+        cur = 0
+        S.srhd_stats_reset(stats)
+        evs = []
+        e_start = torch.cuda.Event(enable_timing=True)
+        e_end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e_start.record(stream)
+        S.srhd_grid_prims(bufs[0], prec=prec, prims=pb[0], smax_bits=sb[0])
+        for _ in range(n_steps):
+            if time_kernel:
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+            S.srhd_fluid_step_grid(bufs[cur], pb[cur], nb, dh, smax_in=sb[cur], c_cfl=0.5,
+                                   cons_out=bufs[1 - cur], prims_out=pb[1 - cur],
+                                   smax_out=sb[1 - cur], prec=prec, stats=stats)
+            if time_kernel:
+                b.record(stream)
+                evs.append((a, b))
+            cur = 1 - cur
+        e_end.record(stream)
+        torch.cuda.synchronize()
+        ms = e_start.elapsed_time(e_end)
+        kms = [a.elapsed_time(b) for a, b in evs]
+        return ms, kms, S.stats_dict(stats), bufs[cur]
+
+    run = run_grid if args.path == "grid" else run_padded
 
     def measure(prec):
         if args.warmup:
@@ -233,12 +279,14 @@ def main():
     kavg = float(np.mean(kms_mx)) * 1e-3
     flops = step_flops(P, {k: v / args.steps for k, v in st_mx.items()})
     traffic = None
-    if step_sources_hash() == PROFILED_TRAFFIC["sources_sha256_16"] and args.cells == 256:
+    if (step_sources_hash() == PROFILED_TRAFFIC["sources_sha256_16"] and args.cells == 256
+            and args.path == PROFILED_TRAFFIC.get("path", "padded")):
         traffic = PROFILED_TRAFFIC["read"] + PROFILED_TRAFFIC["write"]
     roofline = {"bound": "alu", "achieved": flops / kavg / 1e12, "peak": PEAK_ALU / 1e12,
                 "unit": "TFLOP/s", "frac": flops / kavg / PEAK_ALU, "traffic": traffic,
-                "kernel": "k_step<float> (mixed)", "launch_ms": kavg * 1e3,
-                "hbm_GBps_algorithmic": IO_BYTES_PER_PATCH * P / kavg / 1e9,
+                "kernel": "k_step<float,%s> (mixed)" % ("gather" if args.path == "grid" else "padded"),
+                "launch_ms": kavg * 1e3,
+                "hbm_GBps_algorithmic": IO_BYTES_PER_PATCH[args.path] * P / kavg / 1e9,
                 "flops_per_launch": flops}
 
     # ---------------------------------------------------------------- standalone conversions
@@ -314,6 +362,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "blast_%d^3_periodic_%dpatches_mixed_precision" % (args.cells, P),
+                   "path": args.path, "patch_order": "morton",
                    "cells": n_cells, "patches": P, "ghost": 3, "riemann": "HLLC",
                    "limiter_theta": 1.5, "guess": "analytic", "steps_per_run": args.steps},
         "roofline": roofline, "cpu_baseline": cpu, "mixed_stats": st_mx,

@@ -155,6 +155,47 @@ int srhd_stats_reset(srhd_step_stats *stats, void *stream);
 int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
                     const srhd_step_params *prm, srhd_step_stats *stats, void *stream);
 
+/* ---------------------------------------------------------------------------------------- */
+/* The same step on a block of same-level patches without padded copies                     */
+/* ---------------------------------------------------------------------------------------- */
+
+/* A block of same-level patches: the step reads each patch's ghost cells directly from the
+ * interiors of its 26 neighbours (the rule of srhd_fill_ghosts, including outflow clamping),
+ * so no padded copy is written or read.  Primitives travel with the state: the step inverts
+ * every updated cell once and returns its primitives and the maximum signal speed for the
+ * next step's time step. */
+typedef struct {
+  int64_t n_patch;
+  const double *cons;      /* [n_patch][5][8][8][8] FP64 conserved interiors */
+  const void *prims;       /* [n_patch][5][8][8][8] primitives of `cons` in the step's bulk type:
+                              float for SRHD_PREC_MIXED, double for SRHD_PREC_FP64 */
+  const int32_t *neighbor; /* [n_patch][27] int32, as for srhd_fill_ghosts (indices < n_patch) */
+  const int8_t *level;     /* [n_patch] or NULL */
+  int n_level;
+  double dh[SRHD_MAX_LEVEL];  /* host */
+} srhd_grid;
+
+/* Entry state of a chain of srhd_fluid_step_grid calls: inverts every interior cell (as
+ * srhd_cons2prim with the analytic guess, Newton tolerance of the step's precision), writes the
+ * primitives in the step's bulk type, and the maximum S_max (Eqs. 26-27) over the cells as the
+ * bit pattern of a positive double in *smax_bits (device; zeroed first).  Unphysical cells get
+ * NaN primitives and do not enter the maximum. */
+int srhd_grid_prims(int prec, int64_t n_patch, const double *cons, void *prims,
+                    uint64_t *smax_bits, void *stream);
+
+/* One MUSCL-Hancock step of a srhd_grid, identical in arithmetic to srhd_fluid_step on the
+ * padded copies of the same patches.  The time step is dt_l = c_cfl * dh[l] / S_max with S_max
+ * read from *smax_in (the bits written by srhd_grid_prims or by the previous step), unless
+ * dt_lev (device double[n_level]) is given.  Outputs: cons_out [n_patch][5][8][8][8] FP64,
+ * prims_out (bulk type) and *smax_out (zeroed, then the maximum over the updated cells);
+ * dt_used (device double[n_level], may be NULL) receives the time step used.
+ * Outputs must not overlap the inputs.  Patches are mapped to workgroups so that each XCD works
+ * on a contiguous range of patch indices (order patches along a space-filling curve). */
+int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_cfl,
+                         const double *dt_lev, double *cons_out, void *prims_out,
+                         uint64_t *smax_out, double *dt_used, const srhd_step_params *prm,
+                         srhd_step_stats *stats, void *stream);
+
 /* Thread-local description of the last non-zero return. */
 const char *srhd_last_error(void);
 int srhd_abi_version(void);

@@ -178,7 +178,107 @@ int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
   s.guess = g;
   s.out = (double *)out;
   s.stats = stats;
+  s.cons = nullptr;
+  s.prims = nullptr;
+  s.neighbor = nullptr;
+  s.prims_out = nullptr;
+  s.smax_in = nullptr;
+  s.smax_out = nullptr;
+  s.c_cfl = 0.0;
+  s.dt_out = nullptr;
+  s.xcd_remap = 0;
   return hip_status(srhd::launch_step(prm->prec, s, (hipStream_t)stream), "srhd_fluid_step");
+}
+
+int srhd_grid_prims(int prec, int64_t n_patch, const double *cons, void *prims,
+                    uint64_t *smax_bits, void *stream)
+{
+  if (prec != SRHD_PREC_FP64 && prec != SRHD_PREC_MIXED)
+    return fail(SRHD_EINVAL, "srhd_grid_prims: bad precision %d", prec);
+  if (n_patch < 0) return fail(SRHD_EINVAL, "srhd_grid_prims: n_patch < 0");
+  if (!smax_bits || (n_patch > 0 && (!cons || !prims)))
+    return fail(SRHD_EINVAL, "srhd_grid_prims: NULL argument");
+  size_t ps = prec == SRHD_PREC_MIXED ? 4 : 8;
+  if (!aligned(cons, 8) || !aligned(prims, ps) || !aligned(smax_bits, 8))
+    return fail(SRHD_EINVAL, "srhd_grid_prims: misaligned array");
+  const char *a = (const char *)cons, *b = (const char *)prims;
+  size_t ab = (size_t)n_patch * 5 * 512 * 8, bb = (size_t)n_patch * 5 * 512 * ps;
+  if (n_patch > 0 && a < b + bb && b < a + ab)
+    return fail(SRHD_EINVAL, "srhd_grid_prims: prims overlap cons");
+  return hip_status(srhd::launch_grid_prims(prec, n_patch, cons, prims,
+                                            (unsigned long long *)smax_bits, (hipStream_t)stream),
+                    "srhd_grid_prims");
+}
+
+int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_cfl,
+                         const double *dt_lev, double *cons_out, void *prims_out,
+                         uint64_t *smax_out, double *dt_used, const srhd_step_params *prm,
+                         srhd_step_stats *stats, void *stream)
+{
+  if (!in || !prm) return fail(SRHD_EINVAL, "srhd_fluid_step_grid: NULL descriptor");
+  if (in->n_patch < 0) return fail(SRHD_EINVAL, "srhd_fluid_step_grid: n_patch < 0");
+  if (in->n_patch > (0x7fffffffLL / 8) * 8 - 8)
+    return fail(SRHD_EINVAL, "srhd_fluid_step_grid: too many patches");
+  if (in->n_level < 1 || in->n_level > SRHD_MAX_LEVEL)
+    return fail(SRHD_EINVAL, "srhd_fluid_step_grid: n_level %d not in [1, %d]", in->n_level, SRHD_MAX_LEVEL);
+  if (prm->prec != SRHD_PREC_FP64 && prm->prec != SRHD_PREC_MIXED)
+    return fail(SRHD_EINVAL, "srhd_fluid_step_grid: bad precision %d", prm->prec);
+  if (prm->riemann != SRHD_HLLC && prm->riemann != SRHD_HLLE)
+    return fail(SRHD_EINVAL, "srhd_fluid_step_grid: bad Riemann solver %d", prm->riemann);
+  if (!(prm->theta >= 0.0 && prm->theta <= 2.0))
+    return fail(SRHD_EINVAL, "srhd_fluid_step_grid: theta %g not in [0, 2]", prm->theta);
+  if (prm->max_retry < 0 || prm->max_retry > 64)
+    return fail(SRHD_EINVAL, "srhd_fluid_step_grid: max_retry %d not in [0, 64]", prm->max_retry);
+  srhd::GuessArgs g;
+  int rc = check_guess(&prm->guess, g);
+  if (rc) return rc;
+  if (!smax_out) return fail(SRHD_EINVAL, "srhd_fluid_step_grid: NULL smax_out");
+  if (!dt_lev && (!smax_in || !(c_cfl > 0.0)))
+    return fail(SRHD_EINVAL, "srhd_fluid_step_grid: need dt_lev, or smax_in and c_cfl > 0");
+  for (int l = 0; l < in->n_level; ++l)
+    if (!(in->dh[l] > 0.0)) return fail(SRHD_EINVAL, "srhd_fluid_step_grid: dh[%d] must be positive", l);
+  size_t ps = prm->prec == SRHD_PREC_MIXED ? 4 : 8;
+  if (in->n_patch > 0) {
+    if (!in->cons || !in->prims || !in->neighbor || !cons_out || !prims_out)
+      return fail(SRHD_EINVAL, "srhd_fluid_step_grid: NULL array");
+    if (!aligned(in->cons, 8) || !aligned(cons_out, 8) || !aligned(in->prims, ps) ||
+        !aligned(prims_out, ps) || !aligned(in->neighbor, 4) || !aligned(smax_out, 8))
+      return fail(SRHD_EINVAL, "srhd_fluid_step_grid: misaligned array");
+    size_t cb = (size_t)in->n_patch * 5 * 512 * 8, pb = (size_t)in->n_patch * 5 * 512 * ps;
+    struct R { const char *p; size_t n; } ins[2] = {{(const char *)in->cons, cb}, {(const char *)in->prims, pb}},
+        outs[2] = {{(const char *)cons_out, cb}, {(const char *)prims_out, pb}};
+    for (auto &i : ins)
+      for (auto &o : outs)
+        if (i.p < o.p + o.n && o.p < i.p + i.n)
+          return fail(SRHD_EINVAL, "srhd_fluid_step_grid: an output overlaps an input");
+    if (outs[0].p < outs[1].p + outs[1].n && outs[1].p < outs[0].p + outs[0].n)
+      return fail(SRHD_EINVAL, "srhd_fluid_step_grid: cons_out overlaps prims_out");
+  }
+  srhd::StepArgs s;
+  s.n_patch = in->n_patch;
+  s.ghost = 3;
+  s.padded = nullptr;
+  s.level = in->level;
+  s.n_level = in->n_level;
+  s.dt_lev = dt_lev;
+  for (int l = 0; l < SRHD_MAX_LEVEL; ++l) s.dh[l] = l < in->n_level ? in->dh[l] : 1.0;
+  s.theta = prm->theta;
+  s.riemann = prm->riemann;
+  s.max_retry = prm->max_retry;
+  s.guess = g;
+  s.out = cons_out;
+  s.stats = stats;
+  s.cons = in->cons;
+  s.prims = in->prims;
+  s.neighbor = in->neighbor;
+  s.prims_out = prims_out;
+  s.smax_in = (const unsigned long long *)smax_in;
+  s.smax_out = (unsigned long long *)smax_out;
+  s.c_cfl = c_cfl;
+  s.dt_out = dt_used;
+  s.xcd_remap = 1;
+  return hip_status(srhd::launch_step_grid(prm->prec, s, (hipStream_t)stream),
+                    "srhd_fluid_step_grid");
 }
 
 }  // extern "C"

@@ -407,6 +407,19 @@ __device__ __forceinline__ Cons<T> hllc(const Prim<T> &wl, const Prim<T> &wr)
   return F;
 }
 
+// ------------------------------------------------------------------------------ CFL
+// Eqs. 26-27 for one cell (the sum over |Ux| + |Uy| + |Uz|): U_max = gamma_s sum |U_i| +
+// 3 gamma U_s, S_max = U_max / sqrt(1 + U_max^2).  Always in double.
+__device__ __forceinline__ double signal_smax(double rho, double ux, double uy, double uz, double p)
+{
+  double cs2 = sound_speed2(p / rho);
+  double gs = 1.0 / sqrt(1.0 - cs2);                  // gamma_s
+  double Us = sqrt(cs2) * gs;                         // U_s = c_s / sqrt(1 - c_s^2)
+  double gam = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
+  double Umax = gs * (fabs(ux) + fabs(uy) + fabs(uz)) + 3.0 * gam * Us;
+  return Umax / sqrt(1.0 + Umax * Umax);
+}
+
 // ------------------------------------------------------------------------------ PLM
 // Hybrid van Leer / generalized minmod slope (zero at extrema).
 template <class T>

@@ -43,8 +43,21 @@ struct StepArgs {
   GuessArgs guess;
   double *out;
   srhd_step_stats *stats;
+  // gather mode: same-level patches whose ghost cells are read from the neighbours' interiors
+  const double *cons;                   // [P][5][512] conserved interiors (padded unused)
+  const void *prims;                    // [P][5][512] primitives in the bulk type
+  const int32_t *neighbor;              // [P][27]
+  void *prims_out;                      // [P][5][512] primitives of the output
+  const unsigned long long *smax_in;    // S_max of the input (bit pattern), used when !dt_lev
+  unsigned long long *smax_out;         // S_max of the output (zeroed by the launcher)
+  double c_cfl;
+  double *dt_out;                       // optional [n_level]: the dt the step used
+  int xcd_remap;                        // give each XCD a contiguous range of patches
 };
 
 hipError_t launch_step(int prec, const StepArgs &a, hipStream_t s);
+hipError_t launch_step_grid(int prec, const StepArgs &a, hipStream_t s);
+hipError_t launch_grid_prims(int prec, int64_t n_patch, const double *cons, void *prims,
+                             unsigned long long *smax_bits, hipStream_t s);
 
 }  // namespace srhd

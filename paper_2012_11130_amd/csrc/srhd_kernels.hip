@@ -146,14 +146,7 @@ __global__ void __launch_bounds__(kBlock) k_cfl_smax(int64_t n_patch,
     if (!admissible(D, Mx, My, Mz, Et, T(Tol<T>::eps), L)) continue;
     InvOut<T> o;
     invert_with_L(D, Mx, My, Mz, L, T(-1), T(Tol<T>::v), 30, o);
-    double rho = o.rho, p_ = o.p, ux = o.ux, uy = o.uy, uz = o.uz;
-    double cs2 = sound_speed2(p_ / rho);
-    double igs = sqrt(1.0 - cs2);                       // 1 / gamma_s
-    double gs = 1.0 / igs;
-    double Us = sqrt(cs2) * gs;                         // U_s = c_s / sqrt(1 - c_s^2)
-    double gam = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
-    double Umax = gs * (fabs(ux) + fabs(uy) + fabs(uz)) + 3.0 * gam * Us;
-    double S = Umax / sqrt(1.0 + Umax * Umax);
+    double S = signal_smax(o.rho, o.ux, o.uy, o.uz, o.p);
     if (S > vmax) vmax = S;
   }
   vmax = wave_max(vmax);

@@ -85,7 +85,9 @@ struct Tile {
   T W[5][NB];            // centre primitives (rho, Ux, Uy, Uz, p), 12^3 box
   T C[5][NHB];           // half-step corrections, 10^3 box
   T F[2][5][NIF];        // interface fluxes of two directions (ring)
+  double red[NT / 64];   // per-wavefront maxima
   unsigned int cnt[8];   // workgroup counters
+  int nb[32];            // neighbour table row (gather mode)
 };
 
 __device__ __forceinline__ int bidx(int i, int j, int k) { return ((k + 2) * BX + (j + 2)) * BX + (i + 2); }
@@ -197,49 +199,107 @@ __device__ __forceinline__ bool interface_flux(Tile<T> &s, int r, T theta, int s
   return okl && okr;
 }
 
-template <class T>
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2); this mapping
+// hands each XCD a contiguous range of patches so that neighbouring patches, whose cells the
+// gather reads, are processed under the same L2.
+__device__ __forceinline__ int64_t patch_of_block(int64_t n_patch, int remap)
+{
+  if (!remap) return blockIdx.x;
+  int64_t chunk = (n_patch + 7) / 8;
+  return (int64_t)(blockIdx.x % 8) * chunk + blockIdx.x / 8;
+}
+
+// GATHER = false: padded conserved patches, cell-centre inversions in phase A.
+// GATHER = true : the 1,376 tile cells' primitives are read from the interiors of the patch and
+//                 its 26 neighbours (outflow clamping where a face neighbour is -1), and every
+//                 updated cell is inverted at the end -- its primitives and the workgroup's
+//                 maximum signal speed (Eqs. 26-27) feed the next step.
+template <class T, bool GATHER>
 __global__ void __launch_bounds__(NT) k_step(StepArgs a)
 {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Tile<T> &s = *reinterpret_cast<Tile<T> *>(smem_raw);
   const int tid = threadIdx.x;
-  const int64_t p = blockIdx.x;
+  const int64_t p = patch_of_block(a.n_patch, a.xcd_remap);
+  if (p >= a.n_patch) return;                          // whole workgroup: uniform exit
   const int g = a.ghost;
   const int N = 8 + 2 * g;
   const int N3 = N * N * N;
-  const double *__restrict__ q = a.padded + p * 5 * N3;
+  const double *__restrict__ q = GATHER ? nullptr : a.padded + p * 5 * N3;
   int lv = a.level ? (int)a.level[p] : 0;
   lv = lv < 0 ? 0 : (lv >= a.n_level ? a.n_level - 1 : lv);     // never index past dt_lev
-  const double dt = a.dt_lev[lv];
   const double dh = a.dh[lv];
+  double dt;
+  if (a.dt_lev) dt = a.dt_lev[lv];
+  else dt = a.c_cfl * dh / __longlong_as_double((long long)a.smax_in[0]);
+  if (GATHER && a.dt_out && blockIdx.x == 0 && tid < a.n_level)
+    a.dt_out[tid] = a.dt_lev ? a.dt_lev[tid]
+                             : a.c_cfl * a.dh[tid] / __longlong_as_double((long long)a.smax_in[0]);
 
   if (tid < 8) s.cnt[tid] = 0u;
+  if (GATHER && tid < 27) s.nb[tid] = a.neighbor[p * 27 + tid];
   unsigned int my_iters = 0, my_inv = 0, my_fb = 0, my_nc = 0;
   __syncthreads();
 
-  // ---------------------------------------------------------------- A: centre inversions
+  // ---------------------------------------------------------------- A: centre primitives
   bool centre_bad = false;
   unsigned int centre_unphys = 0;
   for (int r = tid; r < NPC; r += NT) {
     int b = kTab.pcell[r];
     int bi = b % BX, bj = (b / BX) % BX, bk = b / (BX * BX);
-    int off = ((bk + g - 2) * N + (bj + g - 2)) * N + (bi + g - 2);
-    double D = q[off], Mx = q[N3 + off], My = q[2 * N3 + off], Mz = q[3 * N3 + off],
-           Et = q[4 * N3 + off];
-    double L;
-    InvOut<double> o;
-    if (admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L)) invert_with_L(D, Mx, My, Mz, L, -1.0, StepTol<T>::v, 30, o);
-    else set_unphysical(o);
-    centre_bad |= o.status == ST_UNPHYSICAL;
-    centre_unphys += o.status == ST_UNPHYSICAL;
-    my_iters += o.iters;
-    my_inv += 1;
-    my_nc += o.status == ST_NOCONV;
-    s.W[0][b] = (T)o.rho;
-    s.W[1][b] = (T)o.ux;
-    s.W[2][b] = (T)o.uy;
-    s.W[3][b] = (T)o.uz;
-    s.W[4][b] = (T)o.p;
+    if (GATHER) {
+      const T *__restrict__ pr = (const T *)a.prims;
+      int c[3] = {bi - 2, bj - 2, bk - 2};
+      const int fs[3] = {1, 3, 9};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        int o = c[d] < 0 ? -1 : (c[d] >= 8 ? 1 : 0);
+        if (o != 0 && s.nb[13 + o * fs[d]] < 0) c[d] = o < 0 ? 0 : 7;     // outflow
+      }
+      int o0 = c[0] < 0 ? -1 : (c[0] >= 8 ? 1 : 0);
+      int o1 = c[1] < 0 ? -1 : (c[1] >= 8 ? 1 : 0);
+      int o2 = c[2] < 0 ? -1 : (c[2] >= 8 ? 1 : 0);
+      int64_t src = s.nb[(o2 + 1) * 9 + (o1 + 1) * 3 + (o0 + 1)];
+      bool okc = src >= 0 && src < a.n_patch;
+      int sc = ((c[2] - 8 * o2) * 8 + (c[1] - 8 * o1)) * 8 + (c[0] - 8 * o0);
+      const T nan = T(__builtin_nan(""));
+      const T *w = pr + (okc ? src : 0) * 5 * 512 + sc;
+      T v0 = okc ? w[0] : nan, v1 = okc ? w[512] : nan, v2 = okc ? w[1024] : nan,
+        v3 = okc ? w[1536] : nan, v4 = okc ? w[2048] : nan;
+      bool bad = !(v0 > T(0)) || !(v4 > T(0)) || !finiteT(v1) || !finiteT(v2) || !finiteT(v3);
+      centre_bad |= bad;
+      centre_unphys += bad;
+      s.W[0][b] = v0;
+      s.W[1][b] = v1;
+      s.W[2][b] = v2;
+      s.W[3][b] = v3;
+      s.W[4][b] = v4;
+    } else {
+      int off = ((bk + g - 2) * N + (bj + g - 2)) * N + (bi + g - 2);
+      double D = q[off], Mx = q[N3 + off], My = q[2 * N3 + off], Mz = q[3 * N3 + off],
+             Et = q[4 * N3 + off];
+      double L;
+      InvOut<double> o;
+      if (admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L)) invert_with_L(D, Mx, My, Mz, L, -1.0, StepTol<T>::v, 30, o);
+      else set_unphysical(o);
+      centre_bad |= o.status == ST_UNPHYSICAL;
+      centre_unphys += o.status == ST_UNPHYSICAL;
+      my_iters += o.iters;
+      my_inv += 1;
+      my_nc += o.status == ST_NOCONV;
+      s.W[0][b] = (T)o.rho;
+      s.W[1][b] = (T)o.ux;
+      s.W[2][b] = (T)o.uy;
+      s.W[3][b] = (T)o.uz;
+      s.W[4][b] = (T)o.p;
+    }
   }
   centre_bad = __syncthreads_or(centre_bad);
 
@@ -328,7 +388,10 @@ __global__ void __launch_bounds__(NT) k_step(StepArgs a)
     const double full = dt / dh;
     double un[5];
 #pragma unroll
-    for (int f = 0; f < 5; ++f) un[f] = q[f * N3 + cq] - full * (double)dU[f];
+    for (int f = 0; f < 5; ++f) {
+      double u0 = GATHER ? a.cons[(p * 5 + f) * 512 + tid] : q[f * N3 + cq];
+      un[f] = u0 - full * (double)dU[f];
+    }
     double Lo;
     bool ok_out = admissible(un[0], un[1], un[2], un[3], un[4], DBL_EPSILON, Lo);
     fail |= !ok_out;
@@ -339,6 +402,31 @@ __global__ void __launch_bounds__(NT) k_step(StepArgs a)
 #pragma unroll
       for (int f = 0; f < 5; ++f) o[f * 512] = un[f];
       unphys += !ok_out;
+      if (GATHER) {
+        // the updated cell's primitives and signal speed, for the next step
+        InvOut<double> w;
+        if (ok_out) invert_with_L(un[0], un[1], un[2], un[3], Lo, -1.0, StepTol<T>::v, 30, w);
+        else set_unphysical(w);
+        my_iters += w.iters;
+        my_inv += 1;
+        my_nc += w.status == ST_NOCONV;
+        T *po = (T *)a.prims_out + p * 5 * 512 + tid;
+        po[0] = (T)w.rho;
+        po[512] = (T)w.ux;
+        po[1024] = (T)w.uy;
+        po[1536] = (T)w.uz;
+        po[2048] = (T)w.p;
+        double sm = ok_out ? signal_smax(w.rho, w.ux, w.uy, w.uz, w.p) : 0.0;
+        sm = wave_max(sm);
+        if ((tid & 63) == 0) s.red[tid >> 6] = sm;
+        __syncthreads();
+        if (tid == 0) {
+          double m = s.red[0];
+#pragma unroll
+          for (int w8 = 1; w8 < NT / 64; ++w8) m = fmax(m, s.red[w8]);
+          atomicMax(a.smax_out, (unsigned long long)__double_as_longlong(m));
+        }
+      }
       break;
     }
     ++retries;
@@ -366,18 +454,59 @@ __global__ void __launch_bounds__(NT) k_step(StepArgs a)
   }
 }
 
+// Inversion of every interior cell into the bulk type, with the maximum signal speed (the
+// entry state of the gather-mode step).  Same inversion and tolerance as the step's own output
+// inversion, so a chain of steps sees identically computed primitives throughout.
 template <class T>
+__global__ void __launch_bounds__(256) k_grid_prims(int64_t n_patch, const double *__restrict__ cons,
+                                                    T *__restrict__ prims,
+                                                    unsigned long long *__restrict__ smax_bits)
+{
+  __shared__ double red[4];
+  const int64_t total = n_patch * 512;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  double vmax = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+    int64_t pp = t >> 9;
+    int c = (int)(t & 511);
+    const double *u = cons + pp * 5 * 512 + c;
+    double L;
+    InvOut<double> w;
+    bool ok = admissible(u[0], u[512], u[1024], u[1536], u[2048], DBL_EPSILON, L);
+    if (ok) invert_with_L(u[0], u[512], u[1024], u[1536], L, -1.0, StepTol<T>::v, 30, w);
+    else set_unphysical(w);
+    T *po = prims + pp * 5 * 512 + c;
+    po[0] = (T)w.rho;
+    po[512] = (T)w.ux;
+    po[1024] = (T)w.uy;
+    po[1536] = (T)w.uz;
+    po[2048] = (T)w.p;
+    if (ok) vmax = fmax(vmax, signal_smax(w.rho, w.ux, w.uy, w.uz, w.p));
+  }
+  vmax = wave_max(vmax);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = vmax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    atomicMax(smax_bits, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+__global__ void k_zero_bits(unsigned long long *p)
+{
+  if (threadIdx.x == 0) p[0] = 0ull;
+}
+
+template <class T, bool GATHER>
 hipError_t launch_step_t(const StepArgs &a, hipStream_t st)
 {
   const size_t bytes = sizeof(Tile<T>);
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_step<T>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  hipLaunchKernelGGL(k_step<T>, dim3((unsigned)a.n_patch), dim3(NT), bytes, st, a);
+  hipError_t e = hipFuncSetAttribute((const void *)k_step<T, GATHER>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  if (GATHER) hipLaunchKernelGGL(k_zero_bits, dim3(1), dim3(64), 0, st, a.smax_out);
+  int64_t blocks = a.xcd_remap ? 8 * ((a.n_patch + 7) / 8) : a.n_patch;
+  hipLaunchKernelGGL((k_step<T, GATHER>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
   return hipGetLastError();
 }
 
@@ -386,7 +515,34 @@ hipError_t launch_step_t(const StepArgs &a, hipStream_t st)
 hipError_t launch_step(int prec, const StepArgs &a, hipStream_t st)
 {
   if (a.n_patch == 0) return hipSuccess;
-  return prec == SRHD_PREC_MIXED ? launch_step_t<float>(a, st) : launch_step_t<double>(a, st);
+  return prec == SRHD_PREC_MIXED ? launch_step_t<float, false>(a, st) : launch_step_t<double, false>(a, st);
+}
+
+hipError_t launch_step_grid(int prec, const StepArgs &a, hipStream_t st)
+{
+  if (a.n_patch == 0) {
+    hipLaunchKernelGGL(k_zero_bits, dim3(1), dim3(64), 0, st, a.smax_out);
+    return hipGetLastError();
+  }
+  return prec == SRHD_PREC_MIXED ? launch_step_t<float, true>(a, st) : launch_step_t<double, true>(a, st);
+}
+
+hipError_t launch_grid_prims(int prec, int64_t n_patch, const double *cons, void *prims,
+                             unsigned long long *smax_bits, hipStream_t st)
+{
+  hipLaunchKernelGGL(k_zero_bits, dim3(1), dim3(64), 0, st, smax_bits);
+  if (n_patch > 0) {
+    int64_t total = n_patch * 512;
+    int blocks = (int)((total + 511) / 512);
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    if (prec == SRHD_PREC_MIXED)
+      hipLaunchKernelGGL(k_grid_prims<float>, dim3(blocks), dim3(256), 0, st, n_patch, cons,
+                         (float *)prims, smax_bits);
+    else
+      hipLaunchKernelGGL(k_grid_prims<double>, dim3(blocks), dim3(256), 0, st, n_patch, cons,
+                         (double *)prims, smax_bits);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace srhd

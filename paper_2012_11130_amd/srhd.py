@@ -44,6 +44,11 @@ class srhd_patches(ctypes.Structure):
                 ("level", _vp), ("n_level", _int), ("dh", ctypes.c_double * MAX_LEVEL)]
 
 
+class srhd_grid(ctypes.Structure):
+    _fields_ = [("n_patch", _i64), ("cons", _vp), ("prims", _vp), ("neighbor", _vp),
+                ("level", _vp), ("n_level", _int), ("dh", ctypes.c_double * MAX_LEVEL)]
+
+
 class srhd_step_params(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("riemann", _int), ("prec", _int),
                 ("max_retry", _int), ("guess", srhd_guess)]
@@ -68,6 +73,9 @@ _sig = {
     "srhd_stats_reset": [_vp, _vp],
     "srhd_fluid_step": [ctypes.POINTER(srhd_patches), _vp, _vp,
                         ctypes.POINTER(srhd_step_params), _vp, _vp],
+    "srhd_grid_prims": [_int, _i64, _vp, _vp, _vp, _vp],
+    "srhd_fluid_step_grid": [ctypes.POINTER(srhd_grid), _vp, ctypes.c_double, _vp, _vp, _vp,
+                             _vp, _vp, ctypes.POINTER(srhd_step_params), _vp, _vp],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -230,6 +238,68 @@ def srhd_fluid_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann
     _check(_lib.srhd_fluid_step(ctypes.byref(d), _ptr(out), _ptr(dt_lev), ctypes.byref(prm),
                                 _ptr(stats), _stream()))
     return out
+
+
+def prims_dtype(prec):
+    return torch.float32 if prec == PREC_MIXED else torch.float64
+
+
+def srhd_grid_prims(cons, prec=PREC_FP64, prims=None, smax_bits=None):
+    """Interior cons [P][5][8][8][8] -> (prims in the step's bulk type, S_max bits int64 [1])."""
+    _need_cuda(cons)
+    P = cons.shape[0]
+    if prims is None:
+        prims = torch.empty(cons.shape, dtype=prims_dtype(prec), device=cons.device)
+    if smax_bits is None:
+        smax_bits = torch.empty(1, dtype=torch.int64, device=cons.device)
+    _need_cuda(prims, smax_bits)
+    _check(_lib.srhd_grid_prims(int(prec), P, _ptr(cons), _ptr(prims), _ptr(smax_bits),
+                                _stream()))
+    return prims, smax_bits
+
+
+def smax_value(bits):
+    """The double whose bit pattern is stored in an int64 tensor."""
+    return bits.cpu().view(torch.float64).item()
+
+
+def srhd_fluid_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, dt_lev=None,
+                         level=None, cons_out=None, prims_out=None, smax_out=None, dt_used=None,
+                         theta=1.5, riemann=HLLC, prec=PREC_FP64, max_retry=4, stats=None,
+                         guess=None):
+    """One step of a block of same-level patches (ghosts gathered from neighbour interiors).
+    Returns (cons_out, prims_out, smax_out)."""
+    _need_cuda(cons, prims, neighbor, smax_in, dt_lev, level, stats)
+    P = cons.shape[0]
+    if cons_out is None:
+        cons_out = torch.empty_like(cons)
+    if prims_out is None:
+        prims_out = torch.empty(cons.shape, dtype=prims_dtype(prec), device=cons.device)
+    if smax_out is None:
+        smax_out = torch.empty(1, dtype=torch.int64, device=cons.device)
+    _need_cuda(cons_out, prims_out, smax_out, dt_used)
+    if prims.dtype != prims_dtype(prec) or prims_out.dtype != prims_dtype(prec):
+        raise TypeError("primitives must be %s for this precision" % prims_dtype(prec))
+    dh = [float(x) for x in dh]
+    gr = srhd_grid()
+    gr.n_patch = P
+    gr.cons = cons.data_ptr()
+    gr.prims = prims.data_ptr()
+    gr.neighbor = neighbor.data_ptr()
+    gr.level = None if level is None else level.data_ptr()
+    gr.n_level = len(dh)
+    for i, h in enumerate(dh):
+        gr.dh[i] = h
+    prm = srhd_step_params()
+    prm.theta = float(theta)
+    prm.riemann = int(riemann)
+    prm.prec = int(prec)
+    prm.max_retry = int(max_retry)
+    prm.guess = guess if guess is not None else srhd_guess(GUESS_ANALYTIC, None, 0)
+    _check(_lib.srhd_fluid_step_grid(ctypes.byref(gr), _ptr(smax_in), float(c_cfl), _ptr(dt_lev),
+                                     _ptr(cons_out), _ptr(prims_out), _ptr(smax_out),
+                                     _ptr(dt_used), ctypes.byref(prm), _ptr(stats), _stream()))
+    return cons_out, prims_out, smax_out
 
 
 def abi_version():

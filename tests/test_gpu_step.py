@@ -143,3 +143,63 @@ def test_full_size_blast_sampled_patches(S):
     ref, cnt = O.fluid_step(pad_o, dt, g.dh_lev)
     e = step_errors(out.cpu().numpy()[sample], ref)
     assert max(e.values()) <= 1e-10, e
+
+
+# ------------------------------------------------------------------ gather-mode (grid) step
+def _grid_chain(S, g, cons, n_steps, prec=0, dt_fixed=None):
+    """n_steps of srhd_fluid_step_grid from oracle-made cons; returns the list of states."""
+    c = _gpu(cons)
+    nb = _gpu(g.neighbor)
+    prims, smax = S.srhd_grid_prims(c, prec=prec)
+    st = S.new_stats(DEV)
+    out = []
+    for _ in range(n_steps):
+        dtl = None if dt_fixed is None else _gpu(np.atleast_1d(dt_fixed))
+        c, prims, smax = S.srhd_fluid_step_grid(c, prims, nb, g.dh_lev, smax_in=smax, dt_lev=dtl,
+                                                prec=prec, stats=st)
+        out.append((c.clone(), prims.clone(), smax.clone()))
+    torch.cuda.synchronize()
+    return out, S.stats_dict(st)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_grid_step_equals_padded_step_bitwise(S, prec):
+    # Same arithmetic, ghosts gathered instead of copied: bit-identical output (outflow and
+    # periodic blocks, patches in Morton order).
+    for g in (W.shock_tube_32(), W.blast(64, seed=3, order="morton")):
+        cons = oracle_cons(g)
+        c = _gpu(cons)
+        nb = _gpu(g.neighbor)
+        dt = S.srhd_cfl_dt(c, g.dh_lev)
+        ref = S.srhd_fluid_step(S.srhd_fill_ghosts(c, nb), dt, g.dh_lev, prec=prec)
+        prims, smax = S.srhd_grid_prims(c, prec=prec)
+        dt_used = torch.empty(1, dtype=torch.float64, device=DEV)
+        out, po, so = S.srhd_fluid_step_grid(c, prims, nb, g.dh_lev, smax_in=smax, prec=prec,
+                                             dt_used=dt_used)
+        torch.cuda.synchronize()
+        if prec == 0:
+            assert torch.equal(dt_used, dt), g.name        # S_max path == CFL kernel, bitwise
+        else:
+            assert abs(dt_used.item() / dt.item() - 1) < 1e-6
+        if prec == 0:
+            assert torch.equal(out, ref), g.name
+        # the primitives and S_max handed to the next step equal a fresh inversion of the output
+        p2, s2 = S.srhd_grid_prims(out, prec=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(p2, po) and torch.equal(s2, so), g.name
+
+
+def test_grid_chain_matches_oracle_multistep(S):
+    # 64^3 blast in Morton order, 4 steps: the GPU chain (fused CFL, gathered ghosts) against the
+    # oracle's CFL + ghost fill + step, each side from its own state.
+    g = W.blast(64, seed=3, order="morton")
+    co = oracle_cons(g)
+    states, sd = _grid_chain(S, g, co, 4)
+    retries = 0
+    for k in range(4):
+        dt_o, _, _ = O.cfl_dt(co, None, g.dh_lev, 0.5)
+        co, cnt = O.fluid_step(O.fill_ghosts(co, g.neighbor, 3), dt_o, g.dh_lev)
+        retries += cnt[3]
+        e = step_errors(states[k][0].cpu().numpy(), co)
+        assert max(e.values()) <= 1e-10 * (k + 1), (k, e)
+    assert sd["n_retry"] == retries and sd["n_unphysical"] == 0

@@ -77,10 +77,23 @@ def grid_to_interior(g, nx, ny, nz):
     return np.ascontiguousarray(a.reshape(nz * ny * nx, F, PS, PS, PS))
 
 
-class PatchGrid:
-    """A uniform single-level block of patches with its primitive initial state."""
+def morton_order(nx, ny, nz):
+    """Permutation of lexicographic patch ids ((pz*ny + py)*nx + px) into Z-order."""
+    pz, py, px = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    key = np.zeros(pz.size, dtype=np.int64)
+    for bit in range(21):
+        for k, c in enumerate((px.ravel(), py.ravel(), pz.ravel())):
+            key |= ((c >> bit) & 1).astype(np.int64) << (3 * bit + k)
+    return np.argsort(key, kind="stable")
 
-    def __init__(self, name, prim, nx, ny, nz, periodic, dh, extra=None):
+
+class PatchGrid:
+    """A uniform single-level block of patches with its primitive initial state.
+
+    With order="morton" the patches are stored along a Z-order curve (neighbour table and all
+    per-patch arrays permuted consistently); `lex_index[i]` is the lexicographic id of patch i."""
+
+    def __init__(self, name, prim, nx, ny, nz, periodic, dh, extra=None, order="lex"):
         self.name = name
         self.prim = prim                # [P][5][8][8][8] float64
         self.nx, self.ny, self.nz = nx, ny, nz
@@ -90,6 +103,20 @@ class PatchGrid:
         self.level = None
         self.dh_lev = np.array([dh])
         self.extra = extra or {}
+        self.lex_index = np.arange(prim.shape[0])
+        if order == "morton":
+            perm = morton_order(nx, ny, nz)
+            inv = np.empty_like(perm)
+            inv[perm] = np.arange(perm.size)
+            self.prim = np.ascontiguousarray(prim[perm])
+            nb = self.neighbor[perm]
+            self.neighbor = np.where(nb >= 0, inv[np.maximum(nb, 0)], -1).astype(np.int32)
+            self.lex_index = perm
+            for k, v in list(self.extra.items()):
+                if isinstance(v, np.ndarray) and v.shape[:1] == (perm.size,):
+                    self.extra[k] = np.ascontiguousarray(v[perm])
+        elif order != "lex":
+            raise ValueError(order)
 
     @property
     def n_patch(self):
@@ -182,14 +209,14 @@ BLAST_AMBIENT = (1.0, 0.0, 0.0, 0.0, 1e-6)     # rho=1, Theta=1e-6
 BLAST_SOURCE = (1e-2, 0.0, 0.0, 0.0, 1e4)      # rho=1e-2, p=1e4 (Theta=1e6)
 
 
-def blast(n_cells=256, seed=1003):
+def blast(n_cells=256, seed=1003, order="lex"):
     """Off-centre ellipsoidal blast wave on n_cells^3 periodic cells (256^3 = 32768 patches)."""
     labels, geo = blast_labels(n_cells, seed)
     table = np.array([BLAST_AMBIENT, BLAST_SOURCE])
     n = n_cells // PS
     prim = np.ascontiguousarray(table[labels].transpose(0, 4, 1, 2, 3))
     g = PatchGrid("blast_%d" % n_cells, prim, n, n, n, True, 1.0 / n_cells,
-                  extra=dict(geo, labels=labels, table=table))
+                  extra=dict(geo, labels=labels, table=table), order=order)
     return g
 
 
