@@ -55,10 +55,14 @@ typedef enum { SRHD_HLLC = 0, SRHD_HLLE = 1 } srhd_riemann;
  * the left-hand side L of Eq. 15 and the Newton inversion in FP64 (state storage stays FP64). */
 typedef enum { SRHD_PREC_FP64 = 0, SRHD_PREC_MIXED = 1 } srhd_prec;
 
-/* Learned initial guess (device parameters of a 3-64-64-1 SiLU perceptron; see srhd_mlp_*). */
+/* Learned initial guess: device parameters of a 3-64-64-1 SiLU perceptron that maps the
+ * standardised features (log D, log max(|M|/D, 1e-300), log(Et/D)) to the standardised log of the
+ * Newton unknown ht (see srhd_mlp_*).  Not in the paper: an addition whose Newton refinement
+ * and analytic fallback keep the inversion's result unchanged. */
 typedef struct {
-  const uint16_t *w_bf16;  /* BF16 weights, layer-major: W1[64][3], W2[64][64], W3[1][64] */
-  const float *bias;       /* FP32 biases: b1[64], b2[64], b3[1] */
+  const uint16_t *w_bf16;  /* BF16 weights, 16-byte aligned: W1[64][3], W2[64][64] (row = output
+                              unit), W3[64] -- 4352 values */
+  const float *bias;       /* FP32 biases: b1[64], b2[64], b3 -- 129 values */
   const float *norm;       /* FP32 [8]: input mean[3], input std[3], output mean, output std */
 } srhd_mlp;
 
@@ -181,7 +185,7 @@ typedef struct {
  * bit pattern of a positive double in *smax_bits (device; zeroed first).  Unphysical cells get
  * NaN primitives and do not enter the maximum. */
 int srhd_grid_prims(int prec, int64_t n_patch, const double *cons, void *prims,
-                    uint64_t *smax_bits, void *stream);
+                    uint64_t *smax_bits, const srhd_guess *guess, void *stream);
 
 /* One MUSCL-Hancock step of a srhd_grid, identical in arithmetic to srhd_fluid_step on the
  * padded copies of the same patches.  The time step is dt_l = c_cfl * dh[l] / S_max with S_max
@@ -195,6 +199,37 @@ int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_
                          const double *dt_lev, double *cons_out, void *prims_out,
                          uint64_t *smax_out, double *dt_used, const srhd_step_params *prm,
                          srhd_step_stats *stats, void *stream);
+
+/* ---------------------------------------------------------------------------------------- */
+/* The learned guess: inference and training                                                */
+/* ---------------------------------------------------------------------------------------- */
+
+#define SRHD_MLP_NPARAM 4481   /* W1[64][3], b1[64], W2[64][64], b2[64], W3[64], b3 */
+
+/* Features (log D, log max(|M|/D, 1e-300), log(Et/D)) of cons[5][n] into feat[3][n] (FP32).
+ * With prim[5][n] (the states' primitives, same dtype) also the training target
+ * target[n] = log ht, ht from Eq. 22 at Theta = p/rho; prim and target are both NULL or both set. */
+int srhd_mlp_features(int dtype, int64_t n, const void *cons, const void *prim, float *feat,
+                      float *target, void *stream);
+
+/* y[n] = de-standardised network output (the guess of log ht) for raw features feat[3][n]; the
+ * hidden layer runs on the matrix cores (BF16 operands, FP32 accumulation). */
+int srhd_mlp_forward(const srhd_mlp *m, int64_t n, const float *feat, float *y, void *stream);
+
+/* Bytes of the workspace srhd_mlp_grad needs for a minibatch of `batch` samples. */
+size_t srhd_mlp_workspace_bytes(int64_t batch);
+
+/* Mean-squared-error gradient over a minibatch: targets target[batch] are log ht; the loss is
+ * taken on the standardised output.  grad[SRHD_MLP_NPARAM] and loss[1] are FP32 device
+ * outputs; the sum over samples is in sample order (bit-reproducible). */
+int srhd_mlp_grad(const srhd_mlp *m, int64_t batch, const float *feat, const float *target,
+                  float *grad, float *loss, void *ws, void *stream);
+
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8; `step` counts from 1) on the FP32 master
+ * parameters master[SRHD_MLP_NPARAM] with moments m1, m2; rewrites the BF16 weights w_bf16[4352]
+ * and the FP32 biases bias[129] that inference reads. */
+int srhd_mlp_adam(float *master, float *m1, float *m2, const float *grad, int step, float lr,
+                  uint16_t *w_bf16, float *bias, void *stream);
 
 /* Thread-local description of the last non-zero return. */
 const char *srhd_last_error(void);

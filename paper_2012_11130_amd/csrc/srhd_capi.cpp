@@ -38,8 +38,17 @@ int check_guess(const srhd_guess *g, srhd::GuessArgs &out)
   if (g->max_iter > 255) return fail(SRHD_EINVAL, "guess.max_iter %d exceeds 255", g->max_iter);
   out.max_iter = g->max_iter > 0 ? g->max_iter : 30;
   if (g->kind == SRHD_GUESS_ANALYTIC) return SRHD_OK;
-  if (g->kind == SRHD_GUESS_MLP)
-    return fail(SRHD_EUNSUPPORTED, "the learned guess is not available in this entry point");
+  if (g->kind == SRHD_GUESS_MLP) {
+    if (!g->mlp || !g->mlp->w_bf16 || !g->mlp->bias || !g->mlp->norm)
+      return fail(SRHD_EINVAL, "learned guess: missing network parameters");
+    if (!aligned(g->mlp->w_bf16, 16) || !aligned(g->mlp->bias, 4) || !aligned(g->mlp->norm, 4))
+      return fail(SRHD_EINVAL, "learned guess: misaligned parameters (weights need 16 bytes)");
+    out.kind = SRHD_GUESS_MLP;
+    out.w = g->mlp->w_bf16;
+    out.bias = g->mlp->bias;
+    out.norm = g->mlp->norm;
+    return SRHD_OK;
+  }
   return fail(SRHD_EINVAL, "unknown guess kind %d", g->kind);
 }
 
@@ -191,8 +200,11 @@ int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
 }
 
 int srhd_grid_prims(int prec, int64_t n_patch, const double *cons, void *prims,
-                    uint64_t *smax_bits, void *stream)
+                    uint64_t *smax_bits, const srhd_guess *guess, void *stream)
 {
+  srhd::GuessArgs g;
+  int rc = check_guess(guess, g);
+  if (rc) return rc;
   if (prec != SRHD_PREC_FP64 && prec != SRHD_PREC_MIXED)
     return fail(SRHD_EINVAL, "srhd_grid_prims: bad precision %d", prec);
   if (n_patch < 0) return fail(SRHD_EINVAL, "srhd_grid_prims: n_patch < 0");
@@ -206,8 +218,69 @@ int srhd_grid_prims(int prec, int64_t n_patch, const double *cons, void *prims,
   if (n_patch > 0 && a < b + bb && b < a + ab)
     return fail(SRHD_EINVAL, "srhd_grid_prims: prims overlap cons");
   return hip_status(srhd::launch_grid_prims(prec, n_patch, cons, prims,
-                                            (unsigned long long *)smax_bits, (hipStream_t)stream),
+                                            (unsigned long long *)smax_bits, g, (hipStream_t)stream),
                     "srhd_grid_prims");
+}
+
+static int check_mlp(const srhd_mlp *m, const char *who)
+{
+  if (!m || !m->w_bf16 || !m->bias || !m->norm) return fail(SRHD_EINVAL, "%s: missing network parameters", who);
+  if (!aligned(m->w_bf16, 16) || !aligned(m->bias, 4) || !aligned(m->norm, 4))
+    return fail(SRHD_EINVAL, "%s: misaligned parameters (weights need 16 bytes)", who);
+  return SRHD_OK;
+}
+
+int srhd_mlp_features(int dtype, int64_t n, const void *cons, const void *prim, float *feat,
+                      float *target, void *stream)
+{
+  if (!valid_dtype(dtype)) return fail(SRHD_EINVAL, "srhd_mlp_features: bad dtype %d", dtype);
+  if (n < 0) return fail(SRHD_EINVAL, "srhd_mlp_features: n < 0");
+  if (n == 0) return SRHD_OK;
+  if (!cons || !feat) return fail(SRHD_EINVAL, "srhd_mlp_features: NULL array");
+  if (!aligned(cons, dsize(dtype)) || !aligned(feat, 4) || !aligned(prim, dsize(dtype)) || !aligned(target, 4))
+    return fail(SRHD_EINVAL, "srhd_mlp_features: misaligned array");
+  if ((prim == nullptr) != (target == nullptr))
+    return fail(SRHD_EINVAL, "srhd_mlp_features: prim and target go together");
+  return hip_status(srhd::launch_mlp_features(dtype, n, cons, prim, feat, target, (hipStream_t)stream),
+                    "srhd_mlp_features");
+}
+
+int srhd_mlp_forward(const srhd_mlp *m, int64_t n, const float *feat, float *y, void *stream)
+{
+  int rc = check_mlp(m, "srhd_mlp_forward");
+  if (rc) return rc;
+  if (n < 0) return fail(SRHD_EINVAL, "srhd_mlp_forward: n < 0");
+  if (n == 0) return SRHD_OK;
+  if (!feat || !y) return fail(SRHD_EINVAL, "srhd_mlp_forward: NULL array");
+  if (!aligned(feat, 4) || !aligned(y, 4)) return fail(SRHD_EINVAL, "srhd_mlp_forward: misaligned array");
+  srhd::MlpDev d = {m->w_bf16, m->bias, m->norm};
+  return hip_status(srhd::launch_mlp_forward(d, n, feat, y, (hipStream_t)stream), "srhd_mlp_forward");
+}
+
+size_t srhd_mlp_workspace_bytes(int64_t batch) { return batch > 0 ? srhd::mlp_workspace_bytes(batch) : 0; }
+
+int srhd_mlp_grad(const srhd_mlp *m, int64_t batch, const float *feat, const float *target,
+                  float *grad, float *loss, void *ws, void *stream)
+{
+  int rc = check_mlp(m, "srhd_mlp_grad");
+  if (rc) return rc;
+  if (batch <= 0 || batch > (1LL << 31)) return fail(SRHD_EINVAL, "srhd_mlp_grad: batch must be in [1, 2^31]");
+  if (!feat || !target || !grad || !loss || !ws) return fail(SRHD_EINVAL, "srhd_mlp_grad: NULL array");
+  if (!aligned(feat, 4) || !aligned(target, 4) || !aligned(grad, 4) || !aligned(loss, 4) || !aligned(ws, 4))
+    return fail(SRHD_EINVAL, "srhd_mlp_grad: misaligned array");
+  srhd::MlpDev d = {m->w_bf16, m->bias, m->norm};
+  return hip_status(srhd::launch_mlp_grad(d, batch, feat, target, grad, loss, ws, (hipStream_t)stream),
+                    "srhd_mlp_grad");
+}
+
+int srhd_mlp_adam(float *master, float *m1, float *m2, const float *grad, int step, float lr,
+                  uint16_t *w_bf16, float *bias, void *stream)
+{
+  if (!master || !m1 || !m2 || !grad || !w_bf16 || !bias) return fail(SRHD_EINVAL, "srhd_mlp_adam: NULL array");
+  if (step < 1) return fail(SRHD_EINVAL, "srhd_mlp_adam: step counts from 1");
+  if (!(lr > 0.0f)) return fail(SRHD_EINVAL, "srhd_mlp_adam: lr must be positive");
+  return hip_status(srhd::launch_mlp_adam(master, m1, m2, grad, step, lr, w_bf16, bias, (hipStream_t)stream),
+                    "srhd_mlp_adam");
 }
 
 int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_cfl,

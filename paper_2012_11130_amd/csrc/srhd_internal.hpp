@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include "../../include/srhd.h"
+#include "srhd_mlp.hpp"
 
 namespace srhd {
 
@@ -56,8 +57,17 @@ struct StepArgs {
 };
 
 hipError_t launch_step(int prec, const StepArgs &a, hipStream_t s);
+
+size_t mlp_workspace_bytes(int64_t batch);
+hipError_t launch_mlp_features(int dtype, int64_t n, const void *cons, const void *prim,
+                               float *feat, float *target, hipStream_t s);
+hipError_t launch_mlp_forward(const MlpDev &m, int64_t n, const float *feat, float *y, hipStream_t s);
+hipError_t launch_mlp_grad(const MlpDev &m, int64_t n, const float *feat, const float *target,
+                           float *grad, float *loss, void *ws, hipStream_t s);
+hipError_t launch_mlp_adam(float *master, float *m1, float *m2, const float *grad, int step,
+                           float lr, uint16_t *w, float *bias, hipStream_t s);
 hipError_t launch_step_grid(int prec, const StepArgs &a, hipStream_t s);
 hipError_t launch_grid_prims(int prec, int64_t n_patch, const double *cons, void *prims,
-                             unsigned long long *smax_bits, hipStream_t s);
+                             unsigned long long *smax_bits, const GuessArgs &g, hipStream_t s);
 
 }  // namespace srhd

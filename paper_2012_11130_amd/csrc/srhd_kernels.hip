@@ -48,20 +48,30 @@ __global__ void __launch_bounds__(kBlock) k_prim2cons(int64_t n, const T *__rest
   }
 }
 
-template <class T>
+// With MLP, the learned guess is tried first and the analytic guess is the fallback.  The loop
+// runs the same number of times in every lane of a wavefront (the network's matrix instructions
+// need all lanes); lanes past the end work on a dummy state and store nothing.
+template <class T, bool MLP>
 __global__ void __launch_bounds__(kBlock) k_cons2prim(int64_t n, const T *__restrict__ cons,
                                                       T *__restrict__ prim,
                                                       int8_t *__restrict__ status,
-                                                      uint8_t *__restrict__ iters, int max_iter)
+                                                      uint8_t *__restrict__ iters, int max_iter,
+                                                      MlpDev mlp)
 {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    T D = cons[i], Mx = cons[n + i], My = cons[2 * n + i], Mz = cons[3 * n + i],
-      Et = cons[4 * n + i];
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+    const int64_t i = base + threadIdx.x;
+    const bool in = i < n;
+    const int64_t j = in ? i : 0;
+    T D = cons[j], Mx = cons[n + j], My = cons[2 * n + j], Mz = cons[3 * n + j],
+      Et = cons[4 * n + j];
+    T guess = T(-1);
+    if (MLP) guess = (T)mlp_guess(mlp, D, Mx, My, Mz, Et);
+    if (!in) continue;
     InvOut<T> o;
     T L;
     if (admissible(D, Mx, My, Mz, Et, T(Tol<T>::eps), L))
-      invert_with_L(D, Mx, My, Mz, L, T(-1), T(Tol<T>::v), max_iter, o);
+      invert_with_L(D, Mx, My, Mz, L, guess, T(Tol<T>::v), max_iter, o);
     else
       set_unphysical(o);
     prim[i] = o.rho;
@@ -195,12 +205,23 @@ hipError_t launch_cons2prim(int dtype, int64_t n, const void *cons, void *prim, 
 {
   if (n == 0) return hipSuccess;
   int mi = g.max_iter > 0 ? g.max_iter : 30;
-  if (dtype == SRHD_F64)
-    hipLaunchKernelGGL(k_cons2prim<double>, dim3(grid_for(n)), dim3(kBlock), 0, s, n,
-                       (const double *)cons, (double *)prim, status, iters, mi);
-  else
-    hipLaunchKernelGGL(k_cons2prim<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, n,
-                       (const float *)cons, (float *)prim, status, iters, mi);
+  MlpDev m = {g.w, g.bias, g.norm};
+  const bool mlp = g.kind == SRHD_GUESS_MLP;
+  if (dtype == SRHD_F64) {
+    if (mlp)
+      hipLaunchKernelGGL((k_cons2prim<double, true>), dim3(grid_for(n)), dim3(kBlock), 0, s, n,
+                         (const double *)cons, (double *)prim, status, iters, mi, m);
+    else
+      hipLaunchKernelGGL((k_cons2prim<double, false>), dim3(grid_for(n)), dim3(kBlock), 0, s, n,
+                         (const double *)cons, (double *)prim, status, iters, mi, m);
+  } else {
+    if (mlp)
+      hipLaunchKernelGGL((k_cons2prim<float, true>), dim3(grid_for(n)), dim3(kBlock), 0, s, n,
+                         (const float *)cons, (float *)prim, status, iters, mi, m);
+    else
+      hipLaunchKernelGGL((k_cons2prim<float, false>), dim3(grid_for(n)), dim3(kBlock), 0, s, n,
+                         (const float *)cons, (float *)prim, status, iters, mi, m);
+  }
   return hipGetLastError();
 }
 

@@ -1,0 +1,161 @@
+// srhd_mlp.hpp -- learned initial guess for the Newton inversion: inference of a 3-64-64-1
+// perceptron with SiLU activations on the matrix cores of gfx950.
+//
+// Inputs are three log-scaled invariants of the conserved state, f = (log D, log max(|M|/D,
+// 1e-300), log(Et/D)), standardised with the training set's mean and deviation; the output is the
+// standardised log of the reduced enthalpy ht, the unknown of Eq. 15.
+//
+// One call evaluates the network for the 64 states held by the 64 lanes of a wavefront (every
+// lane must be active).  Layer 1 (3 -> 64) is lane-local FP32.  Layer 2 (64 -> 64) runs on
+// v_mfma_f32_32x32x16_bf16 with the states as the N dimension: D[h][s] = sum_k W2[h][k] H1[k][s]
+// with BF16 operands and FP32 accumulation.  For that instruction lane l supplies B[k][n] for
+// n = l % 32 and k = 8 (l / 32) + 0..7; every lane holds all 64 hidden values of its own state,
+// so one v_permlane32_swap per register builds the operands of both 32-state tiles at once.
+// Layer 3 (64 -> 1) sums each lane's 32 rows of D and adds the partner lane's half.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace srhd {
+
+constexpr int MLP_H = 64;
+constexpr int MLP_W1 = 0, MLP_W2 = 192, MLP_W3 = 192 + 4096, MLP_NW = 192 + 4096 + 64;
+constexpr int MLP_B1 = 0, MLP_B2 = 64, MLP_B3 = 128, MLP_NB = 129;
+constexpr int MLP_NPARAM = 4481;   // W1 b1 W2 b2 W3 b3
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
+
+struct MlpDev {
+  const uint16_t *w;    // BF16 weights: W1[64][3], W2[64][64] (row = output unit), W3[64]
+  const float *bias;    // b1[64], b2[64], b3
+  const float *norm;    // mean_in[3], std_in[3], mean_out, std_out
+};
+
+// SiLU(a) = a sigmoid(a) with the hardware exponential and reciprocal.
+__device__ __forceinline__ float silu_f(float a)
+{
+  return a * __builtin_amdgcn_rcpf(1.0f + __expf(-a));
+}
+
+__device__ __forceinline__ float bf16_to_f(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
+
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi)
+{
+  __bf16 a = (__bf16)lo, b = (__bf16)hi;     // round to nearest even
+  return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+}
+
+union Frag8 {
+  bf16x8_t v;
+  uint32_t u[4];
+};
+
+// Standardised network output z for this lane's features (f0, f1, f2).
+// The 64 hidden units of layer 1 are produced in four slabs of 16 (the K extent of one matrix
+// instruction); each slab is packed to BF16, lane-swapped into the two state tiles' B operands
+// and accumulated at once into the four 32x32 output tiles [hidden tile][state tile], so only
+// one slab of activations is live at a time.
+__device__ __forceinline__ float mlp_eval(const MlpDev &m, float f0, float f1, float f2)
+{
+  const int lane = threadIdx.x & 63;
+  const float x0 = (f0 - m.norm[0]) / m.norm[3];
+  const float x1 = (f1 - m.norm[1]) / m.norm[4];
+  const float x2 = (f2 - m.norm[2]) / m.norm[5];
+
+  f32x16_t acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};   // [hidden tile][state tile]
+#pragma unroll 1
+  for (int ks = 0; ks < 4; ++ks) {
+    Frag8 lo, hi;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      // hidden units k0 and k0 + 1 of this slab; j < 4 fills the low half, j >= 4 the high half
+      const int k0 = 16 * ks + 2 * j;
+      float h[2];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int k = k0 + e;
+        float a = m.bias[MLP_B1 + k];
+        a = __builtin_fmaf(bf16_to_f(m.w[MLP_W1 + 3 * k + 0]), x0, a);
+        a = __builtin_fmaf(bf16_to_f(m.w[MLP_W1 + 3 * k + 1]), x1, a);
+        a = __builtin_fmaf(bf16_to_f(m.w[MLP_W1 + 3 * k + 2]), x2, a);
+        h[e] = silu_f(a);
+      }
+      if (j < 4) lo.u[j] = pack_bf16(h[0], h[1]);
+      else hi.u[j - 4] = pack_bf16(h[0], h[1]);
+    }
+    // lanes < 32 keep their own low half and receive the low half of lane + 32 (second tile);
+    // lanes >= 32 receive the high half of lane - 32 (first tile) and keep their own high half
+    Frag8 t0, t1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      auto r = __builtin_amdgcn_permlane32_swap(lo.u[j], hi.u[j], false, false);
+      t0.u[j] = r[0];
+      t1.u[j] = r[1];
+    }
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      // A[h][k] = W2[32 mt + lane % 32][16 ks + 8 (lane / 32) + 0..7]: 16 contiguous bytes
+      const uint4 wv = *reinterpret_cast<const uint4 *>(
+          m.w + MLP_W2 + (32 * mt + (lane & 31)) * 64 + 16 * ks + 8 * (lane >> 5));
+      Frag8 a;
+      a.u[0] = wv.x;
+      a.u[1] = wv.y;
+      a.u[2] = wv.z;
+      a.u[3] = wv.w;
+      if (mt == 0) {
+        acc00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, t0.v, acc00, 0, 0, 0);
+        acc01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, t1.v, acc01, 0, 0, 0);
+      } else {
+        acc10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, t0.v, acc10, 0, 0, 0);
+        acc11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, t1.v, acc11, 0, 0, 0);
+      }
+    }
+  }
+  // layer 3: acc_mt_nt[v] = D[32 mt + 8 (v / 4) + 4 (lane / 32) + v % 4][32 nt + lane % 32]
+  float part0 = 0.0f, part1 = 0.0f;
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int hrow = 32 * mt + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      const float w3 = bf16_to_f(m.w[MLP_W3 + hrow]);
+      const float b2 = m.bias[MLP_B2 + hrow];
+      part0 = __builtin_fmaf(w3, silu_f((mt ? acc10[v] : acc00[v]) + b2), part0);
+      part1 = __builtin_fmaf(w3, silu_f((mt ? acc11[v] : acc01[v]) + b2), part1);
+    }
+  // the other half of the 64 rows of a state's column sits in lane ^ 32; the state of this lane
+  // is column lane % 32 of tile lane / 32
+  const float part = lane < 32 ? part0 : part1;
+  const float give = lane < 32 ? part1 : part0;     // what the partner lane needs
+  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(give), __float_as_uint(give), false, false);
+  const float other = __uint_as_float(lane < 32 ? r[1] : r[0]);
+  return part + other + m.bias[MLP_B3];
+}
+
+// Features of a conserved state, the network's input before standardisation.  The ratios are
+// formed in double (|M| can exceed the FP32 range when squared); the logarithms in FP32.
+// log max(|M|/D, 1e-300) is taken as max(log(|M|/D), log 1e-300).
+__device__ __forceinline__ void mlp_features(double D, double Mx, double My, double Mz, double Et,
+                                             float &f0, float &f1, float &f2)
+{
+  double iD = 1.0 / D;
+  double m = sqrt(Mx * Mx + My * My + Mz * Mz) * iD;
+  f0 = __logf((float)D);
+  if (m >= 1e-37) f1 = __logf((float)m);
+  else if (m > 1e-300) f1 = (float)log(m);               // below the FP32 normal range
+  else f1 = -690.77552789821368f;                        // log(1e-300): states at rest
+  f2 = __logf((float)(Et * iD));
+}
+
+// Guess of ht for this lane's state from the network (exp of the de-standardised output).
+__device__ __forceinline__ double mlp_guess(const MlpDev &m, double D, double Mx, double My,
+                                            double Mz, double Et)
+{
+  float f0, f1, f2;
+  mlp_features(D, Mx, My, Mz, Et, f0, f1, f2);
+  float z = mlp_eval(m, f0, f1, f2);
+  return (double)__expf(m.norm[6] + m.norm[7] * z);
+}
+
+}  // namespace srhd

@@ -111,7 +111,8 @@ __device__ __forceinline__ double L_of(const Cons<double> &u) { return lhs_L(u.D
 __device__ __forceinline__ double L_of(const Cons<float> &u) { return lhs_L_from_f32(u.D, u.m[0], u.m[1], u.m[2], u.E); }
 
 template <class T>
-__device__ __forceinline__ bool invert_face(const Cons<T> &u, Prim<T> &w, int &iters, int &status)
+__device__ __forceinline__ bool invert_face(const Cons<T> &u, Prim<T> &w, int &iters, int &status,
+                                            double guess)
 {
   double D = u.D, Mx = u.m[0], My = u.m[1], Mz = u.m[2], Et = u.E;
   bool ok = finiteT(D) && finiteT(Mx) && finiteT(My) && finiteT(Mz) && finiteT(Et) &&
@@ -119,7 +120,7 @@ __device__ __forceinline__ bool invert_face(const Cons<T> &u, Prim<T> &w, int &i
   double L = ok ? L_of(u) : 0.0;
   ok = ok && L > DBL_EPSILON;
   InvOut<double> o;
-  if (ok) invert_with_L(D, Mx, My, Mz, L, -1.0, StepTol<T>::v, 30, o);
+  if (ok) invert_with_L(D, Mx, My, Mz, L, guess, StepTol<T>::v, 30, o);
   else set_unphysical(o);
   w.rho = (T)o.rho;
   w.u[0] = (T)o.ux;
@@ -133,9 +134,10 @@ __device__ __forceinline__ bool invert_face(const Cons<T> &u, Prim<T> &w, int &i
 
 // Face state of cell (i, j, k) on side `side` (0: minus, 1: plus) of direction d: PLM along d,
 // prim -> cons, plus the cell's half-step correction, then the inversion.
-template <int d, class T>
+template <int d, bool MLP, class T>
 __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, int j, int k,
-                                           T theta, Prim<T> &w, int &iters, int &status)
+                                           T theta, const MlpDev &mlp, Prim<T> &w, int &iters,
+                                           int &status)
 {
   constexpr int sd = d == 0 ? 1 : (d == 1 ? BX : BX * BX);
   int b = bidx(i, j, k);
@@ -159,7 +161,10 @@ __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, in
   u.m[1] += s.C[2][hb];
   u.m[2] += s.C[3][hb];
   u.E += s.C[4][hb];
-  return invert_face(u, w, iters, status);
+  // the learned guess is evaluated by every lane of the wavefront (a wavefront handles one
+  // direction and all its lanes are active here)
+  double guess = MLP ? mlp_guess(mlp, u.D, u.m[0], u.m[1], u.m[2], u.E) : -1.0;
+  return invert_face(u, w, iters, status, guess);
 }
 
 struct IfaceCount {
@@ -168,9 +173,9 @@ struct IfaceCount {
 
 // Flux through interface r of direction d (between cells c-1 and c along d; transverse
 // coordinates (bb, aa) in increasing axis order), written to the ring slot of d.
-template <int d, class T>
+template <int d, bool MLP, class T>
 __device__ __forceinline__ bool interface_flux(Tile<T> &s, int r, T theta, int solver,
-                                               IfaceCount &cnt)
+                                               const MlpDev &mlp, IfaceCount &cnt)
 {
   constexpr int a1 = d == 0 ? 1 : 0, a2 = d == 2 ? 1 : 2;
   int c = r % 9, ab = r / 9, bb = ab & 7, aa = ab >> 3;
@@ -182,8 +187,8 @@ __device__ __forceinline__ bool interface_flux(Tile<T> &s, int r, T theta, int s
   cl[d] -= 1;
   Prim<T> wl, wr;
   int itl, itr, stl, str;
-  bool okl = face_state<d>(s, 1, cl[0], cl[1], cl[2], theta, wl, itl, stl);
-  bool okr = face_state<d>(s, 0, cr[0], cr[1], cr[2], theta, wr, itr, str);
+  bool okl = face_state<d, MLP>(s, 1, cl[0], cl[1], cl[2], theta, mlp, wl, itl, stl);
+  bool okr = face_state<d, MLP>(s, 0, cr[0], cr[1], cr[2], theta, mlp, wr, itr, str);
   cnt.iters += itl + itr;
   cnt.inv += 2;
   cnt.fb += (stl == ST_FALLBACK) + (str == ST_FALLBACK);
@@ -221,9 +226,10 @@ __device__ __forceinline__ int64_t patch_of_block(int64_t n_patch, int remap)
 //                 its 26 neighbours (outflow clamping where a face neighbour is -1), and every
 //                 updated cell is inverted at the end -- its primitives and the workgroup's
 //                 maximum signal speed (Eqs. 26-27) feed the next step.
-template <class T, bool GATHER>
+template <class T, bool GATHER, bool MLP>
 __global__ void __launch_bounds__(NT) k_step(StepArgs a)
 {
+  const MlpDev mlp = {a.guess.w, a.guess.bias, a.guess.norm};
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Tile<T> &s = *reinterpret_cast<Tile<T> *>(smem_raw);
   const int tid = threadIdx.x;
@@ -251,10 +257,15 @@ __global__ void __launch_bounds__(NT) k_step(StepArgs a)
   // ---------------------------------------------------------------- A: centre primitives
   bool centre_bad = false;
   unsigned int centre_unphys = 0;
-  for (int r = tid; r < NPC; r += NT) {
-    int b = kTab.pcell[r];
+  for (int r0 = 0; r0 < NPC; r0 += NT) {
+    // every lane runs every round (the learned guess needs whole wavefronts); lanes past the
+    // end of the list work on the first cell again and store nothing
+    const int r = r0 + tid;
+    const bool valid = r < NPC;
+    int b = kTab.pcell[valid ? r : 0];
     int bi = b % BX, bj = (b / BX) % BX, bk = b / (BX * BX);
     if (GATHER) {
+      if (!valid) continue;
       const T *__restrict__ pr = (const T *)a.prims;
       int c[3] = {bi - 2, bj - 2, bk - 2};
       const int fs[3] = {1, 3, 9};
@@ -287,7 +298,9 @@ __global__ void __launch_bounds__(NT) k_step(StepArgs a)
              Et = q[4 * N3 + off];
       double L;
       InvOut<double> o;
-      if (admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L)) invert_with_L(D, Mx, My, Mz, L, -1.0, StepTol<T>::v, 30, o);
+      double guess = MLP ? mlp_guess(mlp, D, Mx, My, Mz, Et) : -1.0;
+      if (!valid) continue;
+      if (admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L)) invert_with_L(D, Mx, My, Mz, L, guess, StepTol<T>::v, 30, o);
       else set_unphysical(o);
       centre_bad |= o.status == ST_UNPHYSICAL;
       centre_unphys += o.status == ST_UNPHYSICAL;
@@ -361,9 +374,9 @@ __global__ void __launch_bounds__(NT) k_step(StepArgs a)
         int r = qi - d * NIF;
         IfaceCount ic = {0, 0, 0, 0, 0};
         bool ok;
-        if (d == 0) ok = interface_flux<0>(s, r, theta, a.riemann, ic);
-        else if (d == 1) ok = interface_flux<1>(s, r, theta, a.riemann, ic);
-        else ok = interface_flux<2>(s, r, theta, a.riemann, ic);
+        if (d == 0) ok = interface_flux<0, MLP>(s, r, theta, a.riemann, mlp, ic);
+        else if (d == 1) ok = interface_flux<1, MLP>(s, r, theta, a.riemann, mlp, ic);
+        else ok = interface_flux<2, MLP>(s, r, theta, a.riemann, mlp, ic);
         fail |= !ok;
         my_iters += ic.iters;
         my_inv += ic.inv;
@@ -405,7 +418,8 @@ __global__ void __launch_bounds__(NT) k_step(StepArgs a)
       if (GATHER) {
         // the updated cell's primitives and signal speed, for the next step
         InvOut<double> w;
-        if (ok_out) invert_with_L(un[0], un[1], un[2], un[3], Lo, -1.0, StepTol<T>::v, 30, w);
+        double guess = MLP ? mlp_guess(mlp, un[0], un[1], un[2], un[3], un[4]) : -1.0;
+        if (ok_out) invert_with_L(un[0], un[1], un[2], un[3], Lo, guess, StepTol<T>::v, 30, w);
         else set_unphysical(w);
         my_iters += w.iters;
         my_inv += 1;
@@ -457,23 +471,26 @@ __global__ void __launch_bounds__(NT) k_step(StepArgs a)
 // Inversion of every interior cell into the bulk type, with the maximum signal speed (the
 // entry state of the gather-mode step).  Same inversion and tolerance as the step's own output
 // inversion, so a chain of steps sees identically computed primitives throughout.
-template <class T>
+template <class T, bool MLP>
 __global__ void __launch_bounds__(256) k_grid_prims(int64_t n_patch, const double *__restrict__ cons,
                                                     T *__restrict__ prims,
-                                                    unsigned long long *__restrict__ smax_bits)
+                                                    unsigned long long *__restrict__ smax_bits,
+                                                    MlpDev mlp)
 {
   __shared__ double red[4];
   const int64_t total = n_patch * 512;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   double vmax = 0.0;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += stride) {
+    const int64_t t = base + threadIdx.x;       // total is a multiple of 512: always in range
     int64_t pp = t >> 9;
     int c = (int)(t & 511);
     const double *u = cons + pp * 5 * 512 + c;
     double L;
     InvOut<double> w;
+    double guess = MLP ? mlp_guess(mlp, u[0], u[512], u[1024], u[1536], u[2048]) : -1.0;
     bool ok = admissible(u[0], u[512], u[1024], u[1536], u[2048], DBL_EPSILON, L);
-    if (ok) invert_with_L(u[0], u[512], u[1024], u[1536], L, -1.0, StepTol<T>::v, 30, w);
+    if (ok) invert_with_L(u[0], u[512], u[1024], u[1536], L, guess, StepTol<T>::v, 30, w);
     else set_unphysical(w);
     T *po = prims + pp * 5 * 512 + c;
     po[0] = (T)w.rho;
@@ -497,17 +514,24 @@ __global__ void k_zero_bits(unsigned long long *p)
   if (threadIdx.x == 0) p[0] = 0ull;
 }
 
-template <class T, bool GATHER>
-hipError_t launch_step_t(const StepArgs &a, hipStream_t st)
+template <class T, bool GATHER, bool MLP>
+hipError_t launch_step_k(const StepArgs &a, hipStream_t st)
 {
   const size_t bytes = sizeof(Tile<T>);
-  hipError_t e = hipFuncSetAttribute((const void *)k_step<T, GATHER>,
+  hipError_t e = hipFuncSetAttribute((const void *)k_step<T, GATHER, MLP>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
   if (GATHER) hipLaunchKernelGGL(k_zero_bits, dim3(1), dim3(64), 0, st, a.smax_out);
   int64_t blocks = a.xcd_remap ? 8 * ((a.n_patch + 7) / 8) : a.n_patch;
-  hipLaunchKernelGGL((k_step<T, GATHER>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
+  hipLaunchKernelGGL((k_step<T, GATHER, MLP>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
   return hipGetLastError();
+}
+
+template <class T, bool GATHER>
+hipError_t launch_step_t(const StepArgs &a, hipStream_t st)
+{
+  return a.guess.kind == SRHD_GUESS_MLP ? launch_step_k<T, GATHER, true>(a, st)
+                                        : launch_step_k<T, GATHER, false>(a, st);
 }
 
 }  // namespace
@@ -528,19 +552,22 @@ hipError_t launch_step_grid(int prec, const StepArgs &a, hipStream_t st)
 }
 
 hipError_t launch_grid_prims(int prec, int64_t n_patch, const double *cons, void *prims,
-                             unsigned long long *smax_bits, hipStream_t st)
+                             unsigned long long *smax_bits, const GuessArgs &g, hipStream_t st)
 {
   hipLaunchKernelGGL(k_zero_bits, dim3(1), dim3(64), 0, st, smax_bits);
   if (n_patch > 0) {
     int64_t total = n_patch * 512;
     int blocks = (int)((total + 511) / 512);
     if (blocks > 256 * 64) blocks = 256 * 64;
-    if (prec == SRHD_PREC_MIXED)
-      hipLaunchKernelGGL(k_grid_prims<float>, dim3(blocks), dim3(256), 0, st, n_patch, cons,
-                         (float *)prims, smax_bits);
-    else
-      hipLaunchKernelGGL(k_grid_prims<double>, dim3(blocks), dim3(256), 0, st, n_patch, cons,
-                         (double *)prims, smax_bits);
+    MlpDev m = {g.w, g.bias, g.norm};
+    const bool mlp = g.kind == SRHD_GUESS_MLP;
+    if (prec == SRHD_PREC_MIXED) {
+      if (mlp) hipLaunchKernelGGL((k_grid_prims<float, true>), dim3(blocks), dim3(256), 0, st, n_patch, cons, (float *)prims, smax_bits, m);
+      else hipLaunchKernelGGL((k_grid_prims<float, false>), dim3(blocks), dim3(256), 0, st, n_patch, cons, (float *)prims, smax_bits, m);
+    } else {
+      if (mlp) hipLaunchKernelGGL((k_grid_prims<double, true>), dim3(blocks), dim3(256), 0, st, n_patch, cons, (double *)prims, smax_bits, m);
+      else hipLaunchKernelGGL((k_grid_prims<double, false>), dim3(blocks), dim3(256), 0, st, n_patch, cons, (double *)prims, smax_bits, m);
+    }
   }
   return hipGetLastError();
 }

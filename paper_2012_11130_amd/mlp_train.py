@@ -1,0 +1,181 @@
+"""Training of the learned Newton guess on the GPU with libsrhd's own kernels.
+
+Training states follow the conversion-batch distribution (rho log-uniform in [1e-6, 1e6], Theta
+in [1e-8, 1e4], gamma in [1, 1e6], isotropic four-velocity), drawn on the device from a seeded
+generator.  Their conserved variables come from srhd_prim2cons; the label of each state is
+log ht of srhd_cons2prim applied to those stored conserved variables (not of the generating
+primitives, which differ from it by the conversion's round-off); unphysical states are dropped.
+Features and labels are standardised with the training set's mean and deviation.  The loss is
+the mean squared error of the standardised output (srhd_mlp_grad); the optimiser is Adam
+(srhd_mlp_adam) with a cosine-decayed learning rate.
+
+    python -m paper_2012_11130_amd.mlp_train --out paper_2012_11130_amd/mlp_guess.npz
+"""
+import argparse
+import math
+import os
+import time
+
+import numpy as np
+import torch
+
+from . import srhd as S
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_WEIGHTS = os.path.join(HERE, "mlp_guess.npz")
+
+
+def draw_states(n, seed, device):
+    """Primitive states [5][n] (float64) of the conversion-batch distribution."""
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    t = torch.empty(n, dtype=torch.float64, device=device)
+
+    def logu(lo, hi):
+        return torch.exp(t.uniform_(math.log(lo), math.log(hi), generator=g)).clone()
+    prim = torch.empty((5, n), dtype=torch.float64, device=device)
+    prim[0] = logu(1e-6, 1e6)
+    th = logu(1e-8, 1e4)
+    gam = logu(1.0, 1e6)
+    d = torch.randn((3, n), dtype=torch.float64, device=device, generator=g)
+    d /= torch.sqrt((d * d).sum(dim=0))
+    prim[1:4] = torch.sqrt((gam - 1) * (gam + 1)) * d
+    prim[4] = prim[0] * th
+    return prim
+
+
+def labelled_set(n, seed, device, chunk=1 << 22):
+    """Features float32 [3][m] and labels log ht float32 [m] of the physical states among n."""
+    feats, targets = [], []
+    done = 0
+    k = 0
+    while done < n:
+        c = min(chunk, n - done)
+        prim = draw_states(c, seed * 1000 + k, device)
+        cons = S.srhd_prim2cons(prim)
+        w, st, _ = S.srhd_cons2prim(cons, status=True)
+        ok = st == S.ST_OK
+        f, t = S.srhd_mlp_features(cons, prim=w)
+        feats.append(f[:, ok])
+        targets.append(t[ok])
+        done += c
+        k += 1
+    return torch.cat(feats, dim=1).contiguous(), torch.cat(targets).contiguous()
+
+
+def glorot(seed):
+    """Glorot-uniform weights and zero biases, flat in the order W1 b1 W2 b2 W3 b3."""
+    rng = np.random.default_rng(seed)
+
+    def u(fan_in, fan_out, n):
+        lim = math.sqrt(6.0 / (fan_in + fan_out))
+        return rng.uniform(-lim, lim, n)
+    return np.concatenate([u(3, 64, 192), np.zeros(64), u(64, 64, 4096), np.zeros(64),
+                           u(64, 1, 64), np.zeros(1)]).astype(np.float32)
+
+
+def split_params(master):
+    """Flat parameters [4481] (W1 b1 W2 b2 W3 b3) -> (BF16 weights [4352] as int16, biases [129])."""
+    W1, b1 = master[0:192], master[192:256]
+    W2, b2 = master[256:4352], master[4352:4416]
+    W3, b3 = master[4416:4480], master[4480:4481]
+    w = torch.cat([W1, W2, W3]).to(torch.bfloat16).view(torch.int16)
+    bias = torch.cat([b1, b2, b3]).float()
+    return w, bias
+
+
+def make_mlp(master, norm):
+    w, bias = split_params(master)
+    return S.Mlp(w.contiguous(), bias.contiguous(), norm.contiguous())
+
+
+def test_loss(mlp, feat, target, std_out):
+    y = S.srhd_mlp_forward(mlp, feat)
+    return float((((y - target) / std_out) ** 2).mean().item())
+
+
+def train(n_train=10_000_000, n_test=1_000_000, epochs=20, batch=8192, lr=1e-3, seed=2000,
+          device="cuda:0", log=print):
+    t0 = time.time()
+    dev = torch.device(device)
+    feat, target = labelled_set(n_train, seed, dev)
+    tfeat, ttarget = labelled_set(n_test, seed + 1, dev)
+    mu, sd = feat.mean(dim=1), feat.std(dim=1)
+    norm = torch.cat([mu, sd, target.mean().reshape(1), target.std().reshape(1)]).float()
+    master = torch.from_numpy(glorot(seed)).to(dev)
+    m1 = torch.zeros_like(master)
+    m2 = torch.zeros_like(master)
+    mlp = make_mlp(master, norm)
+    m = feat.shape[1]
+    steps_per_epoch = m // batch
+    total = steps_per_epoch * epochs
+    ws = torch.empty(S.srhd_mlp_workspace_bytes(batch), dtype=torch.uint8, device=dev)
+    grad = torch.empty(S.MLP_NPARAM, dtype=torch.float32, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed + 7)
+    history = {"epoch": [], "train_loss": [], "test_loss": []}
+    l0 = test_loss(mlp, tfeat, ttarget, norm[7])
+    log("# learned guess: %d training / %d test states, initial test loss %.4f (%.1f s)"
+        % (m, tfeat.shape[1], l0, time.time() - t0))
+    step = 0
+    for ep in range(epochs):
+        perm = torch.randperm(m, generator=gen, device=dev)
+        acc = torch.zeros(1, dtype=torch.float32, device=dev)
+        for b in range(steps_per_epoch):
+            idx = perm[b * batch:(b + 1) * batch]
+            fb = feat[:, idx].contiguous()
+            tb = target[idx].contiguous()
+            S.srhd_mlp_grad(mlp, fb, tb, grad=grad, loss=loss, ws=ws)
+            acc += loss
+            step += 1
+            lr_t = lr * 0.5 * (1 + math.cos(math.pi * step / total))
+            S.srhd_mlp_adam(master, m1, m2, grad, step, max(lr_t, 1e-7), mlp)
+        tl = test_loss(mlp, tfeat, ttarget, norm[7])
+        history["epoch"].append(ep + 1)
+        history["train_loss"].append(float(acc.item()) / steps_per_epoch)
+        history["test_loss"].append(tl)
+        log("# epoch %d: train loss %.4f, test loss %.4f (%.1f s)"
+            % (ep + 1, history["train_loss"][-1], tl, time.time() - t0))
+    return {"w": mlp.w.cpu().numpy().view(np.uint16), "bias": mlp.bias.cpu().numpy(),
+            "norm": norm.cpu().numpy(), "master": master.cpu().numpy(),
+            "initial_test_loss": l0, "history": history, "n_train": m,
+            "seconds": time.time() - t0}
+
+
+def save(res, path):
+    np.savez(path, w=res["w"], bias=res["bias"], norm=res["norm"], master=res["master"],
+             test_loss=np.array(res["history"]["test_loss"]),
+             train_loss=np.array(res["history"]["train_loss"]),
+             initial_test_loss=np.array([res["initial_test_loss"]]),
+             n_train=np.array([res["n_train"]]), seconds=np.array([res["seconds"]]))
+
+
+def load(path=DEFAULT_WEIGHTS, device="cuda:0"):
+    """The trained guess as an srhd.Mlp on `device`, or None if no weights file exists."""
+    if not os.path.exists(path):
+        return None
+    z = np.load(path, allow_pickle=False)
+    dev = torch.device(device)
+    w = torch.from_numpy(z["w"].view(np.int16).copy()).to(dev)
+    bias = torch.from_numpy(z["bias"].astype(np.float32)).to(dev)
+    norm = torch.from_numpy(z["norm"].astype(np.float32)).to(dev)
+    return S.Mlp(w, bias, norm)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--n-train", type=int, default=10_000_000)
+    ap.add_argument("--n-test", type=int, default=1_000_000)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=8192)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    a = ap.parse_args()
+    res = train(a.n_train, a.n_test, a.epochs, a.batch, a.lr)
+    save(res, a.out)
+    print("# saved", a.out, flush=True)
+
+
+if __name__ == "__main__":
+    main()

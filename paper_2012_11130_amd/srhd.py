@@ -73,7 +73,11 @@ _sig = {
     "srhd_stats_reset": [_vp, _vp],
     "srhd_fluid_step": [ctypes.POINTER(srhd_patches), _vp, _vp,
                         ctypes.POINTER(srhd_step_params), _vp, _vp],
-    "srhd_grid_prims": [_int, _i64, _vp, _vp, _vp, _vp],
+    "srhd_grid_prims": [_int, _i64, _vp, _vp, _vp, ctypes.POINTER(srhd_guess), _vp],
+    "srhd_mlp_features": [_int, _i64, _vp, _vp, _vp, _vp, _vp],
+    "srhd_mlp_forward": [ctypes.POINTER(srhd_mlp), _i64, _vp, _vp, _vp],
+    "srhd_mlp_grad": [ctypes.POINTER(srhd_mlp), _i64, _vp, _vp, _vp, _vp, _vp, _vp],
+    "srhd_mlp_adam": [_vp, _vp, _vp, _vp, _int, ctypes.c_float, _vp, _vp, _vp],
     "srhd_fluid_step_grid": [ctypes.POINTER(srhd_grid), _vp, ctypes.c_double, _vp, _vp, _vp,
                              _vp, _vp, ctypes.POINTER(srhd_step_params), _vp, _vp],
 }
@@ -87,8 +91,12 @@ _lib.srhd_cfl_work_bytes.argtypes = []
 _lib.srhd_cfl_work_bytes.restype = ctypes.c_size_t
 _lib.srhd_abi_version.argtypes = []
 _lib.srhd_abi_version.restype = _int
+_lib.srhd_mlp_workspace_bytes.argtypes = [_i64]
+_lib.srhd_mlp_workspace_bytes.restype = ctypes.c_size_t
 
-EXPORTS = tuple(_sig) + ("srhd_last_error", "srhd_cfl_work_bytes", "srhd_abi_version")
+EXPORTS = tuple(_sig) + ("srhd_last_error", "srhd_cfl_work_bytes", "srhd_abi_version",
+                         "srhd_mlp_workspace_bytes")
+MLP_NPARAM = 4481
 
 
 class SrhdError(RuntimeError):
@@ -244,7 +252,7 @@ def prims_dtype(prec):
     return torch.float32 if prec == PREC_MIXED else torch.float64
 
 
-def srhd_grid_prims(cons, prec=PREC_FP64, prims=None, smax_bits=None):
+def srhd_grid_prims(cons, prec=PREC_FP64, prims=None, smax_bits=None, guess=None):
     """Interior cons [P][5][8][8][8] -> (prims in the step's bulk type, S_max bits int64 [1])."""
     _need_cuda(cons)
     P = cons.shape[0]
@@ -253,8 +261,9 @@ def srhd_grid_prims(cons, prec=PREC_FP64, prims=None, smax_bits=None):
     if smax_bits is None:
         smax_bits = torch.empty(1, dtype=torch.int64, device=cons.device)
     _need_cuda(prims, smax_bits)
+    g = guess if guess is not None else srhd_guess(GUESS_ANALYTIC, None, 0)
     _check(_lib.srhd_grid_prims(int(prec), P, _ptr(cons), _ptr(prims), _ptr(smax_bits),
-                                _stream()))
+                                ctypes.byref(g), _stream()))
     return prims, smax_bits
 
 
@@ -300,6 +309,72 @@ def srhd_fluid_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, dt_
                                      _ptr(cons_out), _ptr(prims_out), _ptr(smax_out),
                                      _ptr(dt_used), ctypes.byref(prm), _ptr(stats), _stream()))
     return cons_out, prims_out, smax_out
+
+
+# ------------------------------------------------------------------------------- learned guess
+class Mlp:
+    """Device parameters of the learned guess plus the ctypes descriptors that point at them.
+
+    w: uint16 BF16 weights [4352] (W1[64][3], W2[64][64], W3[64]); bias: float32 [129];
+    norm: float32 [8] (input mean[3], input std[3], output mean, output std)."""
+
+    def __init__(self, w, bias, norm):
+        self.w, self.bias, self.norm = w, bias, norm
+        _need_cuda(w, bias, norm)
+        if w.data_ptr() % 16:
+            raise ValueError("weights must be 16-byte aligned")
+        self.desc = srhd_mlp(w.data_ptr(), bias.data_ptr(), norm.data_ptr())
+
+    def guess(self, max_iter=0):
+        g = srhd_guess(GUESS_MLP, ctypes.pointer(self.desc), max_iter)
+        g._keep = self        # keep the parameters alive with the descriptor
+        return g
+
+
+def srhd_mlp_features(cons, prim=None, feat=None, target=None):
+    """cons [5][n] (and optionally prim [5][n]) -> feat float32 [3][n] (and target log ht [n])."""
+    _need_cuda(cons, prim)
+    n = cons.shape[-1]
+    if feat is None:
+        feat = torch.empty((3, n), dtype=torch.float32, device=cons.device)
+    if prim is not None and target is None:
+        target = torch.empty(n, dtype=torch.float32, device=cons.device)
+    _check(_lib.srhd_mlp_features(_dtype_code(cons), n, _ptr(cons), _ptr(prim), _ptr(feat),
+                                  _ptr(target), _stream()))
+    return feat, target
+
+
+def srhd_mlp_forward(mlp, feat, y=None):
+    _need_cuda(feat)
+    n = feat.shape[-1]
+    if y is None:
+        y = torch.empty(n, dtype=torch.float32, device=feat.device)
+    _check(_lib.srhd_mlp_forward(ctypes.byref(mlp.desc), n, _ptr(feat), _ptr(y), _stream()))
+    return y
+
+
+def srhd_mlp_workspace_bytes(batch):
+    return int(_lib.srhd_mlp_workspace_bytes(int(batch)))
+
+
+def srhd_mlp_grad(mlp, feat, target, grad=None, loss=None, ws=None):
+    _need_cuda(feat, target)
+    n = feat.shape[-1]
+    dev = feat.device
+    if grad is None:
+        grad = torch.empty(MLP_NPARAM, dtype=torch.float32, device=dev)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+    if ws is None:
+        ws = torch.empty(srhd_mlp_workspace_bytes(n), dtype=torch.uint8, device=dev)
+    _check(_lib.srhd_mlp_grad(ctypes.byref(mlp.desc), n, _ptr(feat), _ptr(target), _ptr(grad),
+                              _ptr(loss), _ptr(ws), _stream()))
+    return grad, loss
+
+
+def srhd_mlp_adam(master, m1, m2, grad, step, lr, mlp):
+    _check(_lib.srhd_mlp_adam(_ptr(master), _ptr(m1), _ptr(m2), _ptr(grad), int(step),
+                              float(lr), _ptr(mlp.w), _ptr(mlp.bias), _stream()))
 
 
 def abi_version():
