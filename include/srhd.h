@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define SRHD_ABI_VERSION 1
+#define SRHD_ABI_VERSION 2
 
 typedef enum { SRHD_F64 = 0, SRHD_F32 = 1 } srhd_dtype;
 
@@ -127,12 +127,27 @@ int srhd_cfl_dt(int dtype, int64_t n_patch, const void *interior, int n_level,
                 const double *dh /* host [n_level] */, double c_cfl, double *dt_lev,
                 void *work, void *stream);
 
+/* How the patches of a step are spread over the GPU (a launch choice, not part of the method;
+ * results are identical for every schedule).  groups == 0: one workgroup per patch, each XCD
+ * given a contiguous range of patch indices.  groups > 0: a persistent grid of `groups`
+ * workgroups; each claims `chunk` patches at a time from one queue counter per XCD (over that
+ * XCD's contiguous range, then the other XCDs' ranges in turn) until the list is exhausted.
+ * queue: device memory of SRHD_QUEUE_WORDS uint64 words, required when groups > 0, zeroed by the
+ * call on its stream; calls in flight at the same time must not share it. */
+#define SRHD_QUEUE_WORDS 8
+typedef struct {
+  int groups;              /* 0, or 1 .. 65535 persistent workgroups */
+  int chunk;               /* patches per claim, 1 .. 64 (ignored when groups == 0) */
+  uint64_t *queue;         /* device [SRHD_QUEUE_WORDS], or NULL when groups == 0 */
+} srhd_sched;
+
 typedef struct {
   double theta;            /* limiter coefficient of the generalized minmod (default 1.5) */
   int riemann;             /* srhd_riemann */
   int prec;                /* srhd_prec */
   int max_retry;           /* reductions theta *= 0.75 before the final theta = 0 attempt */
   srhd_guess guess;        /* initial guess for every inversion in the step */
+  srhd_sched sched;        /* launch schedule; all-zero = one workgroup per patch */
 } srhd_step_params;
 
 /* Device counters, accumulated (never reset by the step; see srhd_stats_reset). */
@@ -158,6 +173,29 @@ int srhd_stats_reset(srhd_step_stats *stats, void *stream);
  * out: [n_patch][5][8][8][8] FP64; must not overlap in->padded.  stats may be NULL. */
 int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
                     const srhd_step_params *prm, srhd_step_stats *stats, void *stream);
+
+/* Workgroups of the step kernel that fit on one compute unit at once for the given precision,
+ * guess kind (srhd_guess_kind) and layout (gather = 1: srhd_fluid_step_grid, 0: srhd_fluid_step);
+ * multiplied by the device's compute-unit count it sizes a persistent schedule.  Returns the
+ * count (> 0), or a negative srhd_err. */
+int srhd_step_occupancy(int prec, int guess_kind, int gather);
+
+/* Schedule autotuner for srhd_fluid_step.  Runs the step on `in` (writing `out`) once per
+ * candidate schedule as a warm-up and then `reps` timed times, timed with events on `stream`,
+ * and writes the fastest candidate into prm->sched (keeping prm->sched.queue, which must be
+ * set).  Candidates: one workgroup per patch, and persistent grids of 1, 2 and 4 times the
+ * resident workgroups (srhd_step_occupancy x compute units) with chunk 1, 2 and 4.  table (host,
+ * may be NULL) receives up to table_cap entries {groups, chunk, ms per step} in trial order and
+ * *n_table their number.  Unlike the other calls this one synchronises `stream`.  stats counters
+ * are not touched. */
+typedef struct {
+  int groups;
+  int chunk;
+  float ms;
+} srhd_tune_entry;
+int srhd_autotune_step(const srhd_patches *in, void *out, const double *dt_lev,
+                       srhd_step_params *prm, int reps, srhd_tune_entry *table, int table_cap,
+                       int *n_table, void *stream);
 
 /* ---------------------------------------------------------------------------------------- */
 /* The same step on a block of same-level patches without padded copies                     */

@@ -52,6 +52,25 @@ int check_guess(const srhd_guess *g, srhd::GuessArgs &out)
   return fail(SRHD_EINVAL, "unknown guess kind %d", g->kind);
 }
 
+// Launch schedule of a step (include/srhd.h, srhd_sched).
+int check_sched(const srhd_sched &sc, srhd::StepArgs &s, const char *who)
+{
+  s.queue = nullptr;
+  s.groups = 0;
+  s.chunk = 1;
+  if (sc.groups == 0) return SRHD_OK;
+  if (sc.groups < 0 || sc.groups > 65535)
+    return fail(SRHD_EINVAL, "%s: sched.groups %d not in [0, 65535]", who, sc.groups);
+  if (sc.chunk < 1 || sc.chunk > 64)
+    return fail(SRHD_EINVAL, "%s: sched.chunk %d not in [1, 64]", who, sc.chunk);
+  if (!sc.queue || !aligned(sc.queue, 8))
+    return fail(SRHD_EINVAL, "%s: a persistent schedule needs an 8-byte aligned sched.queue", who);
+  s.queue = (unsigned long long *)sc.queue;
+  s.groups = sc.groups;
+  s.chunk = sc.chunk;
+  return SRHD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -196,7 +215,87 @@ int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
   s.c_cfl = 0.0;
   s.dt_out = nullptr;
   s.xcd_remap = 0;
+  rc = check_sched(prm->sched, s, "srhd_fluid_step");
+  if (rc) return rc;
+  if (s.queue) {
+    const char *q = (const char *)s.queue;
+    if (q < b + bbytes && b < q + SRHD_QUEUE_WORDS * 8)
+      return fail(SRHD_EINVAL, "srhd_fluid_step: sched.queue overlaps out");
+  }
   return hip_status(srhd::launch_step(prm->prec, s, (hipStream_t)stream), "srhd_fluid_step");
+}
+
+int srhd_step_occupancy(int prec, int guess_kind, int gather)
+{
+  if (prec != SRHD_PREC_FP64 && prec != SRHD_PREC_MIXED)
+    return fail(SRHD_EINVAL, "srhd_step_occupancy: bad precision %d", prec);
+  if (guess_kind != SRHD_GUESS_ANALYTIC && guess_kind != SRHD_GUESS_MLP)
+    return fail(SRHD_EINVAL, "srhd_step_occupancy: unknown guess kind %d", guess_kind);
+  int n = srhd::step_occupancy(prec, gather != 0, guess_kind == SRHD_GUESS_MLP);
+  if (n <= 0) return fail(SRHD_EHIP, "srhd_step_occupancy: occupancy query failed");
+  return n;
+}
+
+int srhd_autotune_step(const srhd_patches *in, void *out, const double *dt_lev,
+                       srhd_step_params *prm, int reps, srhd_tune_entry *table, int table_cap,
+                       int *n_table, void *stream)
+{
+  if (!prm) return fail(SRHD_EINVAL, "srhd_autotune_step: NULL parameters");
+  if (!prm->sched.queue) return fail(SRHD_EINVAL, "srhd_autotune_step: prm->sched.queue must be set");
+  if (reps < 1 || reps > 100) return fail(SRHD_EINVAL, "srhd_autotune_step: reps %d not in [1, 100]", reps);
+  if (table_cap < 0) return fail(SRHD_EINVAL, "srhd_autotune_step: table_cap < 0");
+  int occ = srhd_step_occupancy(prm->prec, prm->guess.kind, 0);
+  if (occ <= 0) return occ < 0 ? occ : fail(SRHD_EHIP, "srhd_autotune_step: occupancy 0");
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_status(e, "srhd_autotune_step");
+  struct Cand { int groups, chunk; };
+  Cand cand[10];
+  int nc = 0;
+  cand[nc++] = {0, 1};
+  for (int m : {1, 2, 4})
+    for (int c : {1, 2, 4}) {
+      long g = (long)m * occ * cus;
+      cand[nc++] = {(int)(g > 65535 ? 65535 : g), c};
+    }
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_status(e, "srhd_autotune_step: event");
+  }
+  srhd_step_params trial = *prm;
+  int best = -1, rc = SRHD_OK;
+  float best_ms = 0.0f;
+  if (n_table) *n_table = 0;
+  for (int i = 0; i < nc && rc == SRHD_OK; ++i) {
+    trial.sched.groups = cand[i].groups;
+    trial.sched.chunk = cand[i].chunk;
+    rc = srhd_fluid_step(in, out, dt_lev, &trial, nullptr, stream);          // warm-up
+    if (rc) break;
+    e = hipEventRecord(e0, st);
+    for (int r = 0; r < reps && rc == SRHD_OK && e == hipSuccess; ++r)
+      rc = srhd_fluid_step(in, out, dt_lev, &trial, nullptr, stream);
+    if (rc) break;
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) { rc = hip_status(e, "srhd_autotune_step: timing"); break; }
+    ms /= (float)reps;
+    if (table && i < table_cap) table[i] = srhd_tune_entry{cand[i].groups, cand[i].chunk, ms};
+    if (n_table && i < table_cap) *n_table = i + 1;
+    if (best < 0 || ms < best_ms) { best = i; best_ms = ms; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  prm->sched.groups = cand[best].groups;
+  prm->sched.chunk = cand[best].chunk;
+  return SRHD_OK;
 }
 
 int srhd_grid_prims(int prec, int64_t n_patch, const double *cons, void *prims,
@@ -350,6 +449,8 @@ int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_
   s.c_cfl = c_cfl;
   s.dt_out = dt_used;
   s.xcd_remap = 1;
+  rc = check_sched(prm->sched, s, "srhd_fluid_step_grid");
+  if (rc) return rc;
   return hip_status(srhd::launch_step_grid(prm->prec, s, (hipStream_t)stream),
                     "srhd_fluid_step_grid");
 }

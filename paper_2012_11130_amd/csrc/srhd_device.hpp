@@ -220,12 +220,13 @@ __device__ __forceinline__ bool admissible(T D, T Mx, T My, T Mz, T Et, T eps, T
   return L > eps;
 }
 
-// Inversion from a known, admissible L.  `guess` <= 0 selects the analytic guess; otherwise
-// the supplied guess is tried first and the analytic guess is the fallback (status FALLBACK
-// when it rescues the inversion).
+// Inversion from a known, admissible L.  With `have_guess` the supplied guess is tried first
+// and the analytic guess is the fallback (status FALLBACK when the supplied guess is not a
+// positive finite number or its Newton iteration fails and the analytic one converges);
+// otherwise the analytic guess is used directly.
 template <class T>
-__device__ __forceinline__ void invert_with_L(T D, T Mx, T My, T Mz, T L, T guess, T tol,
-                                              int max_iter, InvOut<T> &o)
+__device__ __forceinline__ void invert_with_L(T D, T Mx, T My, T Mz, T L, T guess, bool have_guess,
+                                              T tol, int max_iter, InvOut<T> &o)
 {
   T iD = dv(T(1), D);
   T mx = Mx * iD, my = My * iD, mz = Mz * iD;
@@ -233,9 +234,9 @@ __device__ __forceinline__ void invert_with_L(T D, T Mx, T My, T Mz, T L, T gues
   T ht;
   int it1 = 0, it2 = 0;
   o.status = ST_OK;
-  bool ok;
-  if (guess > T(0)) {
-    ok = newton_htilde(L, m2, guess, tol, max_iter, ht, it1);
+  bool ok = false;
+  if (have_guess) {
+    if (guess > T(0) && finiteT(guess)) ok = newton_htilde(L, m2, guess, tol, max_iter, ht, it1);
     if (!ok) {
       ok = newton_htilde(L, m2, guess_analytic(L, m2), tol, max_iter, ht, it2);
       o.status = ok ? ST_FALLBACK : ST_NOCONV;

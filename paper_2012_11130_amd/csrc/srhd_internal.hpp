@@ -54,9 +54,15 @@ struct StepArgs {
   double c_cfl;
   double *dt_out;                       // optional [n_level]: the dt the step used
   int xcd_remap;                        // give each XCD a contiguous range of patches
+  // persistent schedule (queue != NULL): `groups` workgroups claim `chunk` patches at a time
+  // from SRHD_QUEUE_WORDS counters (zeroed by the launcher)
+  unsigned long long *queue;
+  int groups;
+  int chunk;
 };
 
 hipError_t launch_step(int prec, const StepArgs &a, hipStream_t s);
+int step_occupancy(int prec, bool gather, bool mlp);   // workgroups per CU, 0 on error
 
 size_t mlp_workspace_bytes(int64_t batch);
 hipError_t launch_mlp_features(int dtype, int64_t n, const void *cons, const void *prim,

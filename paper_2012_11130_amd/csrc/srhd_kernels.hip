@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(kBlock) k_cons2prim(int64_t n, const T *__rest
     InvOut<T> o;
     T L;
     if (admissible(D, Mx, My, Mz, Et, T(Tol<T>::eps), L))
-      invert_with_L(D, Mx, My, Mz, L, guess, T(Tol<T>::v), max_iter, o);
+      invert_with_L(D, Mx, My, Mz, L, guess, MLP, T(Tol<T>::v), max_iter, o);
     else
       set_unphysical(o);
     prim[i] = o.rho;
@@ -155,7 +155,7 @@ __global__ void __launch_bounds__(kBlock) k_cfl_smax(int64_t n_patch,
     T L;
     if (!admissible(D, Mx, My, Mz, Et, T(Tol<T>::eps), L)) continue;
     InvOut<T> o;
-    invert_with_L(D, Mx, My, Mz, L, T(-1), T(Tol<T>::v), 30, o);
+    invert_with_L(D, Mx, My, Mz, L, T(-1), false, T(Tol<T>::v), 30, o);
     double S = signal_smax(o.rho, o.ux, o.uy, o.uz, o.p);
     if (S > vmax) vmax = S;
   }

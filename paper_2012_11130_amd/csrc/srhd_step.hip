@@ -88,6 +88,7 @@ struct Tile {
   double red[NT / 64];   // per-wavefront maxima
   unsigned int cnt[8];   // workgroup counters
   int nb[32];            // neighbour table row (gather mode)
+  unsigned long long claim;  // queue position claimed by the workgroup (persistent schedule)
 };
 
 __device__ __forceinline__ int bidx(int i, int j, int k) { return ((k + 2) * BX + (j + 2)) * BX + (i + 2); }
@@ -112,7 +113,7 @@ __device__ __forceinline__ double L_of(const Cons<float> &u) { return lhs_L_from
 
 template <class T>
 __device__ __forceinline__ bool invert_face(const Cons<T> &u, Prim<T> &w, int &iters, int &status,
-                                            double guess)
+                                            double guess, bool have_guess)
 {
   double D = u.D, Mx = u.m[0], My = u.m[1], Mz = u.m[2], Et = u.E;
   bool ok = finiteT(D) && finiteT(Mx) && finiteT(My) && finiteT(Mz) && finiteT(Et) &&
@@ -120,7 +121,7 @@ __device__ __forceinline__ bool invert_face(const Cons<T> &u, Prim<T> &w, int &i
   double L = ok ? L_of(u) : 0.0;
   ok = ok && L > DBL_EPSILON;
   InvOut<double> o;
-  if (ok) invert_with_L(D, Mx, My, Mz, L, guess, StepTol<T>::v, 30, o);
+  if (ok) invert_with_L(D, Mx, My, Mz, L, guess, have_guess, StepTol<T>::v, 30, o);
   else set_unphysical(o);
   w.rho = (T)o.rho;
   w.u[0] = (T)o.ux;
@@ -164,7 +165,7 @@ __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, in
   // the learned guess is evaluated by every lane of the wavefront (a wavefront handles one
   // direction and all its lanes are active here)
   double guess = MLP ? mlp_guess(mlp, u.D, u.m[0], u.m[1], u.m[2], u.E) : -1.0;
-  return invert_face(u, w, iters, status, guess);
+  return invert_face(u, w, iters, status, guess, MLP);
 }
 
 struct IfaceCount {
@@ -227,14 +228,9 @@ __device__ __forceinline__ int64_t patch_of_block(int64_t n_patch, int remap)
 //                 updated cell is inverted at the end -- its primitives and the workgroup's
 //                 maximum signal speed (Eqs. 26-27) feed the next step.
 template <class T, bool GATHER, bool MLP>
-__global__ void __launch_bounds__(NT) k_step(StepArgs a)
+__device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const MlpDev &mlp, const int64_t p)
 {
-  const MlpDev mlp = {a.guess.w, a.guess.bias, a.guess.norm};
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  Tile<T> &s = *reinterpret_cast<Tile<T> *>(smem_raw);
   const int tid = threadIdx.x;
-  const int64_t p = patch_of_block(a.n_patch, a.xcd_remap);
-  if (p >= a.n_patch) return;                          // whole workgroup: uniform exit
   const int g = a.ghost;
   const int N = 8 + 2 * g;
   const int N3 = N * N * N;
@@ -245,7 +241,7 @@ __global__ void __launch_bounds__(NT) k_step(StepArgs a)
   double dt;
   if (a.dt_lev) dt = a.dt_lev[lv];
   else dt = a.c_cfl * dh / __longlong_as_double((long long)a.smax_in[0]);
-  if (GATHER && a.dt_out && blockIdx.x == 0 && tid < a.n_level)
+  if (GATHER && a.dt_out && p == 0 && tid < a.n_level)
     a.dt_out[tid] = a.dt_lev ? a.dt_lev[tid]
                              : a.c_cfl * a.dh[tid] / __longlong_as_double((long long)a.smax_in[0]);
 
@@ -300,7 +296,7 @@ __global__ void __launch_bounds__(NT) k_step(StepArgs a)
       InvOut<double> o;
       double guess = MLP ? mlp_guess(mlp, D, Mx, My, Mz, Et) : -1.0;
       if (!valid) continue;
-      if (admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L)) invert_with_L(D, Mx, My, Mz, L, guess, StepTol<T>::v, 30, o);
+      if (admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L)) invert_with_L(D, Mx, My, Mz, L, guess, MLP, StepTol<T>::v, 30, o);
       else set_unphysical(o);
       centre_bad |= o.status == ST_UNPHYSICAL;
       centre_unphys += o.status == ST_UNPHYSICAL;
@@ -419,7 +415,7 @@ __global__ void __launch_bounds__(NT) k_step(StepArgs a)
         // the updated cell's primitives and signal speed, for the next step
         InvOut<double> w;
         double guess = MLP ? mlp_guess(mlp, un[0], un[1], un[2], un[3], un[4]) : -1.0;
-        if (ok_out) invert_with_L(un[0], un[1], un[2], un[3], Lo, guess, StepTol<T>::v, 30, w);
+        if (ok_out) invert_with_L(un[0], un[1], un[2], un[3], Lo, guess, MLP, StepTol<T>::v, 30, w);
         else set_unphysical(w);
         my_iters += w.iters;
         my_inv += 1;
@@ -468,6 +464,43 @@ __global__ void __launch_bounds__(NT) k_step(StepArgs a)
   }
 }
 
+// One patch per workgroup (a.queue == NULL), or a persistent grid of a.groups workgroups that
+// claim a.chunk patches at a time.  The persistent schedule keeps one queue counter per XCD over
+// that XCD's contiguous range of patches (the same ranges as the one-per-patch mapping); a
+// workgroup drains its own XCD's range first and then helps the others in turn, so every
+// workgroup leaves the loop once all eight ranges are exhausted.
+template <class T, bool GATHER, bool MLP>
+__global__ void __launch_bounds__(NT) k_step(StepArgs a)
+{
+  const MlpDev mlp = {a.guess.w, a.guess.bias, a.guess.norm};
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Tile<T> &s = *reinterpret_cast<Tile<T> *>(smem_raw);
+  if (!a.queue) {
+    const int64_t p = patch_of_block(a.n_patch, a.xcd_remap);
+    if (p < a.n_patch) step_patch<T, GATHER, MLP>(a, s, mlp, p);     // uniform per workgroup
+    return;
+  }
+  const int64_t range = (a.n_patch + 7) / 8;
+  const int home = blockIdx.x % 8;
+  for (int k = 0; k < 8; ++k) {
+    const int x = (home + k) % 8;
+    const int64_t lo = x * range;
+    const int64_t hi = lo + range < a.n_patch ? lo + range : a.n_patch;
+    for (;;) {
+      __syncthreads();                               // the tile and s.claim are free again
+      if (threadIdx.x == 0) s.claim = atomicAdd(&a.queue[x], (unsigned long long)a.chunk);
+      __syncthreads();
+      const int64_t p0 = lo + (int64_t)s.claim;
+      if (p0 >= hi) break;                           // uniform: every thread read the same claim
+      const int64_t p1 = p0 + a.chunk < hi ? p0 + a.chunk : hi;
+      for (int64_t p = p0; p < p1; ++p) {
+        step_patch<T, GATHER, MLP>(a, s, mlp, p);
+        __syncthreads();
+      }
+    }
+  }
+}
+
 // Inversion of every interior cell into the bulk type, with the maximum signal speed (the
 // entry state of the gather-mode step).  Same inversion and tolerance as the step's own output
 // inversion, so a chain of steps sees identically computed primitives throughout.
@@ -490,7 +523,7 @@ __global__ void __launch_bounds__(256) k_grid_prims(int64_t n_patch, const doubl
     InvOut<double> w;
     double guess = MLP ? mlp_guess(mlp, u[0], u[512], u[1024], u[1536], u[2048]) : -1.0;
     bool ok = admissible(u[0], u[512], u[1024], u[1536], u[2048], DBL_EPSILON, L);
-    if (ok) invert_with_L(u[0], u[512], u[1024], u[1536], L, guess, StepTol<T>::v, 30, w);
+    if (ok) invert_with_L(u[0], u[512], u[1024], u[1536], L, guess, MLP, StepTol<T>::v, 30, w);
     else set_unphysical(w);
     T *po = prims + pp * 5 * 512 + c;
     po[0] = (T)w.rho;
@@ -514,6 +547,24 @@ __global__ void k_zero_bits(unsigned long long *p)
   if (threadIdx.x == 0) p[0] = 0ull;
 }
 
+__global__ void k_zero_queue(unsigned long long *q)
+{
+  if (threadIdx.x < SRHD_QUEUE_WORDS) q[threadIdx.x] = 0ull;
+}
+
+template <class T, bool GATHER, bool MLP>
+int occupancy_k()
+{
+  int n = 0;
+  const size_t bytes = sizeof(Tile<T>);
+  if (hipFuncSetAttribute((const void *)k_step<T, GATHER, MLP>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<T, GATHER, MLP>, NT, bytes) != hipSuccess)
+    return 0;
+  return n;
+}
+
 template <class T, bool GATHER, bool MLP>
 hipError_t launch_step_k(const StepArgs &a, hipStream_t st)
 {
@@ -522,7 +573,13 @@ hipError_t launch_step_k(const StepArgs &a, hipStream_t st)
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
   if (GATHER) hipLaunchKernelGGL(k_zero_bits, dim3(1), dim3(64), 0, st, a.smax_out);
-  int64_t blocks = a.xcd_remap ? 8 * ((a.n_patch + 7) / 8) : a.n_patch;
+  int64_t blocks;
+  if (a.queue) {
+    hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(64), 0, st, a.queue);
+    blocks = a.groups;
+  } else {
+    blocks = a.xcd_remap ? 8 * ((a.n_patch + 7) / 8) : a.n_patch;
+  }
   hipLaunchKernelGGL((k_step<T, GATHER, MLP>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
   return hipGetLastError();
 }
@@ -540,6 +597,15 @@ hipError_t launch_step(int prec, const StepArgs &a, hipStream_t st)
 {
   if (a.n_patch == 0) return hipSuccess;
   return prec == SRHD_PREC_MIXED ? launch_step_t<float, false>(a, st) : launch_step_t<double, false>(a, st);
+}
+
+int step_occupancy(int prec, bool gather, bool mlp)
+{
+  if (prec == SRHD_PREC_MIXED)
+    return gather ? (mlp ? occupancy_k<float, true, true>() : occupancy_k<float, true, false>())
+                  : (mlp ? occupancy_k<float, false, true>() : occupancy_k<float, false, false>());
+  return gather ? (mlp ? occupancy_k<double, true, true>() : occupancy_k<double, true, false>())
+                : (mlp ? occupancy_k<double, false, true>() : occupancy_k<double, false, false>());
 }
 
 hipError_t launch_step_grid(int prec, const StepArgs &a, hipStream_t st)

@@ -49,9 +49,20 @@ class srhd_grid(ctypes.Structure):
                 ("level", _vp), ("n_level", _int), ("dh", ctypes.c_double * MAX_LEVEL)]
 
 
+class srhd_sched(ctypes.Structure):
+    _fields_ = [("groups", _int), ("chunk", _int), ("queue", _vp)]
+
+
 class srhd_step_params(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("riemann", _int), ("prec", _int),
-                ("max_retry", _int), ("guess", srhd_guess)]
+                ("max_retry", _int), ("guess", srhd_guess), ("sched", srhd_sched)]
+
+
+class srhd_tune_entry(ctypes.Structure):
+    _fields_ = [("groups", _int), ("chunk", _int), ("ms", ctypes.c_float)]
+
+
+QUEUE_WORDS = 8
 
 
 class srhd_step_stats(ctypes.Structure):
@@ -80,6 +91,10 @@ _sig = {
     "srhd_mlp_adam": [_vp, _vp, _vp, _vp, _int, ctypes.c_float, _vp, _vp, _vp],
     "srhd_fluid_step_grid": [ctypes.POINTER(srhd_grid), _vp, ctypes.c_double, _vp, _vp, _vp,
                              _vp, _vp, ctypes.POINTER(srhd_step_params), _vp, _vp],
+    "srhd_step_occupancy": [_int, _int, _int],
+    "srhd_autotune_step": [ctypes.POINTER(srhd_patches), _vp, _vp,
+                           ctypes.POINTER(srhd_step_params), _int,
+                           ctypes.POINTER(srhd_tune_entry), _int, ctypes.POINTER(_int), _vp],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -217,8 +232,75 @@ def srhd_stats_reset(stats):
     _check(_lib.srhd_stats_reset(_ptr(stats), _stream()))
 
 
+class Sched:
+    """Launch schedule of a step: groups == 0 is one workgroup per patch; groups > 0 a
+    persistent grid claiming `chunk` patches at a time from a device queue (owned here)."""
+
+    def __init__(self, groups=0, chunk=1, device="cuda:0"):
+        self.groups, self.chunk = int(groups), int(chunk)
+        self.queue = torch.zeros(QUEUE_WORDS, dtype=torch.int64, device=device)
+
+    def c(self):
+        return srhd_sched(self.groups, self.chunk, self.queue.data_ptr())
+
+    def __repr__(self):
+        return "Sched(groups=%d, chunk=%d)" % (self.groups, self.chunk)
+
+
+def _patches(padded, dh, level, ghost):
+    P = padded.shape[0]
+    N = padded.shape[-1]
+    d = srhd_patches()
+    d.n_patch = P
+    d.ghost = (N - 8) // 2 if ghost is None else ghost
+    d.dtype = _dtype_code(padded)
+    d.padded = padded.data_ptr()
+    d.level = None if level is None else level.data_ptr()
+    dh = [float(x) for x in dh]
+    d.n_level = len(dh)
+    for i, h in enumerate(dh):
+        d.dh[i] = h
+    return d
+
+
+def _params(theta, riemann, prec, max_retry, guess, sched):
+    prm = srhd_step_params()
+    prm.theta = float(theta)
+    prm.riemann = int(riemann)
+    prm.prec = int(prec)
+    prm.max_retry = int(max_retry)
+    prm.guess = guess if guess is not None else srhd_guess(GUESS_ANALYTIC, None, 0)
+    prm.sched = sched.c() if sched is not None else srhd_sched(0, 1, None)
+    return prm
+
+
+def srhd_step_occupancy(prec, guess_kind=GUESS_ANALYTIC, gather=False):
+    rc = _lib.srhd_step_occupancy(int(prec), int(guess_kind), int(bool(gather)))
+    _check(min(rc, 0))
+    return rc
+
+
+def srhd_autotune_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann=HLLC,
+                       prec=PREC_FP64, max_retry=4, ghost=None, guess=None, reps=2):
+    """Times the candidate schedules of srhd_fluid_step on these patches; returns (Sched of the
+    fastest, [(groups, chunk, ms per step), ...])."""
+    _need_cuda(padded, dt_lev, level)
+    P = padded.shape[0]
+    if out is None:
+        out = torch.empty((P, 5, 8, 8, 8), dtype=torch.float64, device=padded.device)
+    sch = Sched(0, 1, padded.device)
+    d = _patches(padded, dh, level, ghost)
+    prm = _params(theta, riemann, prec, max_retry, guess, sch)
+    table = (srhd_tune_entry * 16)()
+    n = _int(0)
+    _check(_lib.srhd_autotune_step(ctypes.byref(d), _ptr(out), _ptr(dt_lev), ctypes.byref(prm),
+                                   int(reps), table, 16, ctypes.byref(n), _stream()))
+    sch.groups, sch.chunk = prm.sched.groups, prm.sched.chunk
+    return sch, [(table[i].groups, table[i].chunk, table[i].ms) for i in range(n.value)]
+
+
 def srhd_fluid_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann=HLLC,
-                    prec=PREC_FP64, max_retry=4, stats=None, ghost=None, guess=None):
+                    prec=PREC_FP64, max_retry=4, stats=None, ghost=None, guess=None, sched=None):
     """One MUSCL-Hancock step: padded cons [P][5][N][N][N] -> interior [P][5][8][8][8]."""
     _need_cuda(padded, dt_lev, level, stats)
     P = padded.shape[0]
@@ -227,22 +309,8 @@ def srhd_fluid_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann
     if out is None:
         out = torch.empty((P, 5, 8, 8, 8), dtype=torch.float64, device=padded.device)
     _need_cuda(out)
-    dh = [float(x) for x in dh]
-    d = srhd_patches()
-    d.n_patch = P
-    d.ghost = g
-    d.dtype = _dtype_code(padded)
-    d.padded = padded.data_ptr()
-    d.level = None if level is None else level.data_ptr()
-    d.n_level = len(dh)
-    for i, h in enumerate(dh):
-        d.dh[i] = h
-    prm = srhd_step_params()
-    prm.theta = float(theta)
-    prm.riemann = int(riemann)
-    prm.prec = int(prec)
-    prm.max_retry = int(max_retry)
-    prm.guess = guess if guess is not None else srhd_guess(GUESS_ANALYTIC, None, 0)
+    d = _patches(padded, dh, level, g)
+    prm = _params(theta, riemann, prec, max_retry, guess, sched)
     _check(_lib.srhd_fluid_step(ctypes.byref(d), _ptr(out), _ptr(dt_lev), ctypes.byref(prm),
                                 _ptr(stats), _stream()))
     return out
@@ -275,7 +343,7 @@ def smax_value(bits):
 def srhd_fluid_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, dt_lev=None,
                          level=None, cons_out=None, prims_out=None, smax_out=None, dt_used=None,
                          theta=1.5, riemann=HLLC, prec=PREC_FP64, max_retry=4, stats=None,
-                         guess=None):
+                         guess=None, sched=None):
     """One step of a block of same-level patches (ghosts gathered from neighbour interiors).
     Returns (cons_out, prims_out, smax_out)."""
     _need_cuda(cons, prims, neighbor, smax_in, dt_lev, level, stats)
@@ -299,12 +367,7 @@ def srhd_fluid_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, dt_
     gr.n_level = len(dh)
     for i, h in enumerate(dh):
         gr.dh[i] = h
-    prm = srhd_step_params()
-    prm.theta = float(theta)
-    prm.riemann = int(riemann)
-    prm.prec = int(prec)
-    prm.max_retry = int(max_retry)
-    prm.guess = guess if guess is not None else srhd_guess(GUESS_ANALYTIC, None, 0)
+    prm = _params(theta, riemann, prec, max_retry, guess, sched)
     _check(_lib.srhd_fluid_step_grid(ctypes.byref(gr), _ptr(smax_in), float(c_cfl), _ptr(dt_lev),
                                      _ptr(cons_out), _ptr(prims_out), _ptr(smax_out),
                                      _ptr(dt_used), ctypes.byref(prm), _ptr(stats), _stream()))

@@ -49,7 +49,7 @@ def test_argument_errors_are_reported_without_a_gpu(lib):
     assert b"overlap" in lib.srhd_last_error()
     assert lib.srhd_prim2cons(0, 1, a + 1, a + 400, None) == -1      # misaligned
     lib.srhd_abi_version.restype = ctypes.c_int
-    assert lib.srhd_abi_version() == 1
+    assert lib.srhd_abi_version() == 2
 
 
 def test_step_descriptor_checks(lib):
@@ -73,3 +73,41 @@ def test_step_descriptor_checks(lib):
     d.dtype = 1
     rc = S._lib.srhd_fluid_step(ctypes.byref(d), None, None, ctypes.byref(prm), None, None)
     assert rc == -3
+
+
+def test_schedule_checks(lib):
+    # every call below fails its host-side checks before any launch (host buffers stand in for
+    # device arrays and are never touched)
+    from paper_2012_11130_amd import srhd as S
+    pad = ctypes.create_string_buffer(4 * 5 * 14 ** 3 * 8 + 64)
+    out = ctypes.create_string_buffer(4 * 5 * 512 * 8 + 64)
+    dt = ctypes.create_string_buffer(64)
+    al = lambda b: (ctypes.addressof(b) + 63) // 64 * 64
+    d = S.srhd_patches()
+    d.n_patch, d.ghost, d.dtype, d.n_level = 4, 3, 0, 1
+    d.dh[0] = 0.1
+    d.padded = al(pad)
+    prm = S.srhd_step_params()
+    prm.theta, prm.max_retry = 1.5, 4
+    call = lambda: S._lib.srhd_fluid_step(ctypes.byref(d), al(out), al(dt), ctypes.byref(prm),
+                                          None, None)
+    prm.sched = S.srhd_sched(-1, 1, None)
+    assert call() == -1 and b"groups" in S._lib.srhd_last_error()
+    prm.sched = S.srhd_sched(512, 1, None)
+    assert call() == -1 and b"queue" in S._lib.srhd_last_error()
+    q = ctypes.create_string_buffer(128)
+    prm.sched = S.srhd_sched(512, 0, al(q))
+    assert call() == -1 and b"chunk" in S._lib.srhd_last_error()
+    prm.sched = S.srhd_sched(512, 65, al(q))
+    assert call() == -1 and b"chunk" in S._lib.srhd_last_error()
+    n = ctypes.c_int(0)
+    prm.sched = S.srhd_sched(0, 1, None)
+    rc = S._lib.srhd_autotune_step(ctypes.byref(d), al(out), al(dt), ctypes.byref(prm), 2, None,
+                                   0, ctypes.byref(n), None)
+    assert rc == -1 and b"queue" in S._lib.srhd_last_error()
+    prm.sched = S.srhd_sched(0, 1, al(q))
+    rc = S._lib.srhd_autotune_step(ctypes.byref(d), al(out), al(dt), ctypes.byref(prm), 0, None,
+                                   0, ctypes.byref(n), None)
+    assert rc == -1 and b"reps" in S._lib.srhd_last_error()
+    assert S._lib.srhd_step_occupancy(5, 0, 0) == -1
+    assert S._lib.srhd_step_occupancy(0, 7, 0) == -1

@@ -321,7 +321,49 @@ def jet_labels(pl, patches=None, ghost=3):
         cx = (corner[sel, 0][:, None] + o[None, :] + 0.5) * dh - 0.5
         cy = (corner[sel, 1][:, None] + o[None, :] + 0.5) * dh - 0.5
         cz = (corner[sel, 2][:, None] + o[None, :] + 0.5) * dh
-        r2 = cx[:, None, None, :] ** 2 + cy[:, None, :, None] ** 2
-        inside = (r2 < pl["r_jet"] ** 2) & (cz[:, :, None, None] < pl["z_jet"])
+        r2 = cx[:, None, None, :] * cx[:, None, None, :] + cy[:, None, :, None] * cy[:, None, :, None]
+        inside = (r2 < pl["r_jet"] * pl["r_jet"]) & (cz[:, :, None, None] < pl["z_jet"])
         out[s:s + sel.size] = inside
+    return out
+
+
+def jet_labels_torch(pl, device, ghost=3, chunk=16384):
+    """jet_labels of every patch, computed on a torch device with the same IEEE operations in
+    the same order (so the labels equal jet_labels' bit for bit)."""
+    import torch
+    corner = torch.as_tensor(pl["corner"], device=device)
+    level = torch.as_tensor(pl["level"].astype(np.int64), device=device)
+    dh_lev = torch.as_tensor(pl["dh_lev"], dtype=torch.float64, device=device)
+    P = corner.shape[0]
+    N = PS + 2 * ghost
+    o = torch.arange(-ghost, PS + ghost, device=device)
+    r2max = pl["r_jet"] * pl["r_jet"]
+    out = torch.empty((P, N, N, N), dtype=torch.uint8, device=device)
+    for s in range(0, P, chunk):
+        sl = slice(s, min(P, s + chunk))
+        dh = dh_lev[level[sl]][:, None]
+        cx = ((corner[sl, 0][:, None] + o[None, :]).double() + 0.5) * dh - 0.5
+        cy = ((corner[sl, 1][:, None] + o[None, :]).double() + 0.5) * dh - 0.5
+        cz = ((corner[sl, 2][:, None] + o[None, :]).double() + 0.5) * dh
+        r2 = cx[:, None, None, :] * cx[:, None, None, :] + cy[:, None, :, None] * cy[:, None, :, None]
+        out[sl] = ((r2 < r2max) & (cz[:, :, None, None] < pl["z_jet"])).to(torch.uint8)
+    return out
+
+
+def assemble_labeled(labels, states):
+    """Padded patches [p][5][N][N][N] whose cell c holds states[labels[c]] (states [k][5]).
+
+    Works on numpy arrays or torch tensors (labels uint8, states float64); a pure selection."""
+    if isinstance(labels, np.ndarray):
+        st = np.asarray(states, dtype=np.float64)
+        return np.ascontiguousarray(np.moveaxis(st[labels.astype(np.int64)], -1, 1))
+    import torch
+    st = torch.as_tensor(np.asarray(states, dtype=np.float64), device=labels.device)
+    P = labels.shape[0]
+    out = torch.empty((P, 5) + tuple(labels.shape[1:]), dtype=torch.float64, device=labels.device)
+    chunk = 8192
+    for s in range(0, P, chunk):
+        lab = labels[s:s + chunk].long()
+        for f in range(5):
+            out[s:s + chunk, f] = st[:, f][lab]
     return out
