@@ -7,7 +7,10 @@ the fused MUSCL-Hancock patch step (inversions, PLM, half step, HLLC, update, li
 The timed run is K steps from the initial state (10 by default, as the workload specifies) with the
 inputs resident in HBM.  The headline value is the mixed-precision step (FP32 reconstruction /
 flux / update increment, FP64 inversion); the plain FP64 step is measured beside it on the same
-inputs, with the per-field difference after one step.
+inputs, with the per-field difference after one step.  With trained weights present
+(paper_2012_11130_amd/mlp_guess.npz) the headline step uses the learned Newton guess and the
+mixed step with the analytic guess is measured beside it; Newton iterations per inversion and the
+fallback rate of each are reported.
 
 Printed: one JSON line (metric, value, ...) with a `roofline` object for the dominant kernel (the
 patch step) and a `cpu_baseline` object (the CPU oracle on a bounded sample of the same workload).
@@ -36,6 +39,10 @@ FLOP_HALF_CELL = 570     # 15 slopes, 6 face states -> prim2cons + flux, half-st
 FLOP_FACE = 105          # slope + face state + prim2cons + correction (inversion counted apart)
 FLOP_RIEMANN = 260       # HLLC: 2 prim2cons, 2 fluxes, 4 signal speeds, HLL averages, star state
 FLOP_UPDATE = 180        # flux differences, update, exact-L admissibility check of the output
+FLOP_MLP_VALU = 1088     # learned guess, VALU part: features and standardisation (~20), layer 1
+                         # (64 x 3 FMA = 384), 128 SiLU (exp, add, reciprocal, multiply = 512),
+                         # layer 3 (64 FMA = 128), partner-lane sum and exponential (~44)
+MFMA_FLOP_MLP = 2 * 64 * 64   # layer 2 on the matrix cores per evaluation
 HALF_CELLS, INTERFACES, OUT_CELLS = 896, 1728, 512
 IO_BYTES_PER_PATCH = {                         # what one patch's step consumes and produces
     "padded": (1376 + 512) * 5 * 8,            # FP64 tile cells + FP64 output
@@ -58,53 +65,147 @@ def step_sources_hash():
     return h.hexdigest()[:16]
 
 
-def step_flops(n_patch, stats):
-    """Algorithmic FLOPs of one step launch from its device counters."""
+def step_flops(n_patch, stats, mlp=False):
+    """Algorithmic VALU FLOPs of one step launch from its device counters (with the learned
+    guess, its VALU work per inversion is included; its matrix-core work is counted apart)."""
     attempts = n_patch + stats["n_retry"]
     return (attempts * (HALF_CELLS * FLOP_HALF_CELL + 2 * INTERFACES * FLOP_FACE
                         + INTERFACES * FLOP_RIEMANN + OUT_CELLS * FLOP_UPDATE)
-            + stats["n_inversions"] * FLOP_INVERSION + stats["newton_iters"] * FLOP_NEWTON_ITER)
+            + stats["n_inversions"] * (FLOP_INVERSION + (FLOP_MLP_VALU if mlp else 0))
+            + stats["newton_iters"] * FLOP_NEWTON_ITER)
 
 
 def summarize_profile(d, calib_mib):
-    """Per-kernel table from rocprofv3 databases of three runs of this script under `d`:
-    prof_trace (--kernel-trace --stats), prof_fetch (--pmc FETCH_SIZE), prof_write
-    (--pmc WRITE_SIZE).  Byte counters are rescaled by what they read for the calibration copy
-    (--calib-copy MiB read once and written once)."""
+    """Per-kernel tables from rocprofv3 databases of runs of this script under `d`: prof_trace
+    (--kernel-trace --stats) and any number of counter runs prof_<name> (--pmc ...).  Byte
+    counters are rescaled by what they read for the calibration copy (--calib-copy MiB read once
+    and written once); instruction counters are per launch, summed over the whole device."""
     import collections
     import glob
     import re
     import sqlite3
 
     def short(kn):
-        m = re.search(r"srhd::\(anonymous namespace\)::(k_\w+(<\w+>)?)", kn)
+        m = re.search(r"srhd::\(anonymous namespace\)::(k_\w+(<[^>]*>)?)", kn)
         if m:
-            return m.group(1)
+            return m.group(1).replace(" ", "")
         if "MulFunctor" in kn:
             return "calibration_copy"
         return kn.split("(")[0][-40:]
 
-    def rows(sub, query):
-        out = collections.defaultdict(list)
-        for path in glob.glob(os.path.join(d, sub, "*results.db")):
-            for kn, v in sqlite3.connect(path).execute(query):
-                out[short(kn)].append(v)
-        return out
-
-    dur = rows("prof_trace", "select name, duration from kernels")
-    fet = rows("prof_fetch", "select kernel_name, value from counters_collection")
-    wri = rows("prof_write", "select kernel_name, value from counters_collection")
+    dur = collections.defaultdict(list)
+    info = {}
+    for path in glob.glob(os.path.join(d, "prof_trace", "*results.db")):
+        db = sqlite3.connect(path)
+        for kn, v in db.execute("select name, duration from kernels"):
+            dur[short(kn)].append(v)
+    cnt = collections.defaultdict(lambda: collections.defaultdict(list))
+    for path in glob.glob(os.path.join(d, "prof_*", "*results.db")):
+        if os.sep + "prof_trace" + os.sep in path:
+            continue
+        db = sqlite3.connect(path)
+        q = ("select kernel_name, counter_name, value, vgpr_count, accum_vgpr_count, sgpr_count, "
+             "lds_block_size, scratch_size from counters_collection")
+        for kn, cn, v, vg, ag, sg, lds, scr in db.execute(q):
+            k = short(kn)
+            cnt[k][cn].append(v)
+            info[k] = (vg, ag, sg, lds, scr)
     avg = lambda v: sum(v) / len(v) if v else float("nan")
     kib = calib_mib * 1024.0
-    ff = kib / avg(fet["calibration_copy"]) if fet.get("calibration_copy") else float("nan")
-    fw = kib / avg(wri["calibration_copy"]) if wri.get("calibration_copy") else float("nan")
+    cal = cnt.get("calibration_copy", {})
+    ff = kib / avg(cal["FETCH_SIZE"]) if cal.get("FETCH_SIZE") else float("nan")
+    fw = kib / avg(cal["WRITE_SIZE"]) if cal.get("WRITE_SIZE") else float("nan")
     print("calibration: FETCH_SIZE x %.3f, WRITE_SIZE x %.3f (copy of %d MiB)" % (ff, fw, calib_mib))
-    print("| kernel | calls | avg us | HBM read MB/launch | HBM write MB/launch |")
-    print("|---|---|---|---|---|")
+    print("| kernel | calls | avg us | HBM read MB/launch | HBM write MB/launch | arch VGPR | acc VGPR | SGPR | LDS B | scratch B |")
+    print("|---|---|---|---|---|---|---|---|---|---|")
     for k in sorted(dur, key=lambda k: -sum(dur[k])):
-        print("| %s | %d | %.1f | %.1f | %.1f |" % (k, len(dur[k]), avg(dur[k]) / 1e3,
-                                                  avg(fet.get(k, [])) * ff * 1.024e-3,
-                                                  avg(wri.get(k, [])) * fw * 1.024e-3))
+        c = cnt.get(k, {})
+        vg, ag, sg, lds, scr = info.get(k, ("", "", "", "", ""))
+        print("| %s | %d | %.1f | %.1f | %.1f | %s | %s | %s | %s | %s |"
+              % (k, len(dur[k]), avg(dur[k]) / 1e3, avg(c.get("FETCH_SIZE", [])) * ff * 1.024e-3,
+                 avg(c.get("WRITE_SIZE", [])) * fw * 1.024e-3, vg, ag, sg, lds, scr))
+    # VALU work from the instruction counters (64 lanes per instruction, FMA = 2 flops)
+    f64 = ("SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_TRANS_F64")
+    f32 = ("SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_MUL_F32", "SQ_INSTS_VALU_TRANS_F32")
+    rows = [k for k in sorted(dur, key=lambda k: -sum(dur[k])) if "SQ_INSTS_VALU" in cnt.get(k, {})
+            or "SQ_INSTS_VALU_FMA_F64" in cnt.get(k, {})]
+    if rows:
+        issue_peak = 256 * 4 * 2.4e9 / 4      # wave64 VALU instructions/s (4 SIMDs x 16 lanes per CU)
+        print()
+        print("| kernel | FP64 flops/launch | FP32 flops/launch | VALU TFLOP/s (FP64+FP32) | of 78.6 | VALU instr/launch | VALU issue of peak | LDS instr/launch | LDS bank-conflict cycles / LDS active cycles |")
+        print("|---|---|---|---|---|---|---|---|---|")
+        for k in rows:
+            c = cnt[k]
+            t = avg(dur[k]) * 1e-9
+            def fl(names):
+                if not all(n in c for n in names):
+                    return float("nan")
+                return 64 * (2 * avg(c[names[0]]) + avg(c[names[1]]) + avg(c[names[2]]) + avg(c[names[3]]))
+            a64, a32 = fl(f64), fl(f32)
+            vi = avg(c.get("SQ_INSTS_VALU", []))
+            bc = avg(c.get("SQ_LDS_BANK_CONFLICT", [])) / avg(c.get("SQ_LDS_IDX_ACTIVE", [])) \
+                if c.get("SQ_LDS_IDX_ACTIVE") else float("nan")
+            print("| %s | %.3e | %.3e | %.2f | %.1f %% | %.3e | %.1f %% | %.3e | %.3f |"
+                  % (k, a64, a32, (a64 + a32) / t / 1e12, 100 * (a64 + a32) / t / PEAK_ALU, vi,
+                     100 * vi / t / issue_peak, avg(c.get("SQ_INSTS_LDS", [])), bc))
+
+
+def run_jet(args, S, W, dev, stream, guess, guess_name):
+    """The multi-level jet list: padded patches whose ghosts hold the analytic initial state,
+    one step = the CFL reduction + one launch of the step over every patch, under the schedule
+    the autotuner picks.  Every timed step starts from the same initial state."""
+    import torch
+    pl = W.jet_patch_list(n_patch=args.jet)
+    P = pl["corner"].shape[0]
+    dh = pl["dh_lev"]
+    states = S.srhd_prim2cons(torch.from_numpy(W.jet_states().T.copy()).to(dev)).T.cpu().numpy()
+    lab = W.jet_labels_torch(pl, dev)
+    pad = W.assemble_labeled(lab, states)
+    del lab
+    level = torch.from_numpy(pl["level"]).to(dev)
+    interior = pad[:, :, 3:11, 3:11, 3:11].contiguous()
+    dt = torch.empty(len(dh), dtype=torch.float64, device=dev)
+    out = torch.empty((P, 5, 8, 8, 8), dtype=torch.float64, device=dev)
+    stats = S.new_stats(dev)
+    S.srhd_cfl_dt(interior, dh, 0.5, dt_lev=dt)
+    res = {"patches": P, "cells": P * 512, "levels": [int((pl["level"] == l).sum()) for l in range(len(dh))]}
+    for name, prec, g in (("mixed", S.PREC_MIXED, guess), ("fp64", S.PREC_FP64, None)):
+        sch, table = S.srhd_autotune_step(pad, dt, dh, level=level, out=out, prec=prec, guess=g, reps=2)
+        for _ in range(args.warmup):
+            S.srhd_cfl_dt(interior, dh, 0.5, dt_lev=dt)
+            S.srhd_fluid_step(pad, dt, dh, level=level, out=out, prec=prec, guess=g, sched=sch)
+        S.srhd_stats_reset(stats)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        ks = []
+        e0.record(stream)
+        for _ in range(args.steps):
+            S.srhd_cfl_dt(interior, dh, 0.5, dt_lev=dt)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            S.srhd_fluid_step(pad, dt, dh, level=level, out=out, prec=prec, guess=g, sched=sch,
+                              stats=stats)
+            b.record(stream)
+            ks.append((a, b))
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        st = S.stats_dict(stats)
+        inv = max(st["n_inversions"], 1)
+        res[name] = {"value": P * 512 / (ms * 1e-3), "unit": "cell updates/s", "ms_per_step": ms,
+                     "step_kernel_ms": float(np.mean([x.elapsed_time(y) for x, y in ks])),
+                     "guess": guess_name if g is not None else "analytic",
+                     "schedule": {"groups": sch.groups, "chunk": sch.chunk, "occupancy": sch.occupancy},
+                     "autotune_ms": [[t[0], t[1], t[2], round(t[3], 3)] for t in table],
+                     "iters_per_inversion": st["newton_iters"] / inv,
+                     "fallback_rate": st["n_fallback"] / inv,
+                     "retries_per_step": st["n_retry"] / args.steps}
+        print("# jet %s: %.2f ms per step, schedule %s" % (name, ms, sch), file=sys.stderr, flush=True)
+    del pad, interior, out
+    torch.cuda.empty_cache()
+    return res
 
 
 def parse():
@@ -120,8 +221,13 @@ def parse():
     ap.add_argument("--conversion", type=int, default=100_000_000,
                     help="states of the standalone conversion batch (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--jet", type=int, default=400_000,
+                    help="patches of the multi-level jet list measured beside the headline (0 = skip)")
     ap.add_argument("--path", choices=("grid", "padded"), default="grid",
                     help="grid: gather-mode step chain (default); padded: CFL + fill + step")
+    ap.add_argument("--guess", choices=("learned", "analytic"), default="learned",
+                    help="Newton guess of the headline mixed step (learned needs the weights file)")
+    ap.add_argument("--weights", default=None, help="weights of the learned guess (.npz)")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB of a plain elementwise copy run once before the steps, as the "
                          "calibration kernel for hardware byte counters (0 = none)")
@@ -172,7 +278,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    def run_padded(prec, n_steps, time_kernel=False):
+    def run_padded(prec, n_steps, time_kernel=False, guess=None, sched=None):
         """n_steps from the initial state with CFL kernel + ghost fill + padded step."""
         bufs[0].copy_(cons0)
         cur = 0
@@ -189,7 +295,8 @@ def main():
                 a = torch.cuda.Event(enable_timing=True)
                 b = torch.cuda.Event(enable_timing=True)
                 a.record(stream)
-            S.srhd_fluid_step(pad, dt, dh, out=bufs[1 - cur], prec=prec, stats=stats)
+            S.srhd_fluid_step(pad, dt, dh, out=bufs[1 - cur], prec=prec, stats=stats, guess=guess,
+                              sched=sched)
             if time_kernel:
                 b.record(stream)
                 evs.append((a, b))
@@ -202,7 +309,7 @@ def main():
 
     pbufs = {}
 
-    def run_grid(prec, n_steps, time_kernel=False):
+    def run_grid(prec, n_steps, time_kernel=False, guess=None, sched=None):
         """n_steps from the initial state with the gather-mode step: each step is one kernel
         that reads ghosts from neighbour interiors and returns the next S_max; the entry
         inversion of the initial state is inside the timed region."""
@@ -220,7 +327,7 @@ def main():
         e_end = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e_start.record(stream)
-        S.srhd_grid_prims(bufs[0], prec=prec, prims=pb[0], smax_bits=sb[0])
+        S.srhd_grid_prims(bufs[0], prec=prec, prims=pb[0], smax_bits=sb[0], guess=guess)
         for _ in range(n_steps):
             if time_kernel:
                 a = torch.cuda.Event(enable_timing=True)
@@ -228,7 +335,8 @@ def main():
                 a.record(stream)
             S.srhd_fluid_step_grid(bufs[cur], pb[cur], nb, dh, smax_in=sb[cur], c_cfl=0.5,
                                    cons_out=bufs[1 - cur], prims_out=pb[1 - cur],
-                                   smax_out=sb[1 - cur], prec=prec, stats=stats)
+                                   smax_out=sb[1 - cur], prec=prec, stats=stats, guess=guess,
+                                   sched=sched)
             if time_kernel:
                 b.record(stream)
                 evs.append((a, b))
@@ -241,27 +349,69 @@ def main():
 
     run = run_grid if args.path == "grid" else run_padded
 
-    def measure(prec):
+    def tune(prec, guess):
+        """The autotuner's schedule for this configuration, on the initial state."""
+        if args.path == "grid":
+            prims, smax = S.srhd_grid_prims(cons0, prec=prec, guess=guess)
+            sch, table = S.srhd_autotune_step_grid(cons0, prims, nb, dh, smax_in=smax, prec=prec,
+                                                   guess=guess, reps=2)
+        else:
+            S.srhd_cfl_dt(cons0, dh, 0.5, dt_lev=dt)
+            S.srhd_fill_ghosts(cons0, nb, 3, padded=pad)
+            sch, table = S.srhd_autotune_step(pad, dt, dh, prec=prec, guess=guess, reps=2)
+        return sch, [[t[0], t[1], t[2], round(t[3], 4)] for t in table]
+
+    schedules = {}
+
+    def measure(prec, guess=None, name=""):
+        sch, table = tune(prec, guess)
+        schedules[name] = {"groups": sch.groups, "chunk": sch.chunk, "occupancy": sch.occupancy,
+                           "autotune_ms": table}
         if args.warmup:
-            run(prec, args.warmup)
-        ms, kms, st, final = run(prec, args.steps, time_kernel=True)
+            run(prec, args.warmup, guess=guess, sched=sch)
+        ms, kms, st, final = run(prec, args.steps, time_kernel=True, guess=guess, sched=sch)
         return ms, kms, st, final.clone()
 
-    ms_mx, kms_mx, st_mx, fin_mx = measure(S.PREC_MIXED)
-    print("# mixed: %.2f ms for %d steps (step kernel %.3f ms avg); stats %s"
-          % (ms_mx, args.steps, float(np.mean(kms_mx)), st_mx), file=sys.stderr, flush=True)
+    def newton_summary(st):
+        inv = max(st["n_inversions"], 1)
+        return {"iters_per_inversion": st["newton_iters"] / inv,
+                "fallback_rate": st["n_fallback"] / inv, "noconv": st["n_noconv"]}
+
+    mlp = None
+    if args.guess == "learned":
+        from paper_2012_11130_amd import mlp_train
+        mlp = mlp_train.load(args.weights or mlp_train.DEFAULT_WEIGHTS, device="cuda:0")
+        if mlp is None:
+            print("# no weights of the learned guess: headline uses the analytic guess",
+                  file=sys.stderr, flush=True)
+    guess = mlp.guess() if mlp is not None else None
+    guess_name = "learned (BF16 MLP)" if mlp is not None else "analytic"
+
+    ms_mx, kms_mx, st_mx, fin_mx = measure(S.PREC_MIXED, guess, "headline")
+    print("# mixed, %s guess: %.2f ms for %d steps (step kernel %.3f ms avg); stats %s"
+          % (guess_name, ms_mx, args.steps, float(np.mean(kms_mx)), st_mx), file=sys.stderr, flush=True)
     value = n_cells * args.steps / (ms_mx * 1e-3)
+    res = {"newton": {"headline": newton_summary(st_mx)}}
+    if mlp is not None:
+        ms_an, kms_an, st_an, fin_an = measure(S.PREC_MIXED, None, "mixed_analytic")
+        print("# mixed, analytic guess: %.2f ms for %d steps (step kernel %.3f ms avg); stats %s"
+              % (ms_an, args.steps, float(np.mean(kms_an)), st_an), file=sys.stderr, flush=True)
+        a, b = fin_mx.cpu().numpy(), fin_an.cpu().numpy()
+        res["mixed_analytic"] = {"value": n_cells * args.steps / (ms_an * 1e-3),
+                                 "ms_per_step": ms_an / args.steps,
+                                 "step_kernel_ms": float(np.mean(kms_an)), "stats": st_an,
+                                 "max_abs_diff_vs_headline": float(np.max(np.abs(a - b)))}
+        res["newton"]["mixed_analytic"] = newton_summary(st_an)
 
     # per-field difference of one mixed step against one FP64 step from the same state
-    res = {}
     if not args.no_fp64:
-        ms_64, kms_64, st_64, fin_64 = measure(S.PREC_FP64)
+        ms_64, kms_64, st_64, fin_64 = measure(S.PREC_FP64, None, "fp64")
         print("# fp64: %.2f ms for %d steps (step kernel %.3f ms avg); stats %s"
               % (ms_64, args.steps, float(np.mean(kms_64)), st_64), file=sys.stderr, flush=True)
         S.srhd_cfl_dt(cons0, dh, 0.5, dt_lev=dt)
         S.srhd_fill_ghosts(cons0, nb, 3, padded=pad)
         o64 = S.srhd_fluid_step(pad, dt, dh, prec=S.PREC_FP64).cpu().numpy()
-        omx = S.srhd_fluid_step(pad, dt, dh, prec=S.PREC_MIXED).cpu().numpy()
+        omx = S.srhd_fluid_step(pad, dt, dh, prec=S.PREC_MIXED, guess=guess).cpu().numpy()
         mscale = max(float(np.max(np.sqrt((o64[:, 1:4] ** 2).sum(axis=1)))), 1e-300)
         err1 = {"D": float(np.max(np.abs(omx[:, 0] / o64[:, 0] - 1))),
                 "Et": float(np.max(np.abs(omx[:, 4] / o64[:, 4] - 1))),
@@ -273,21 +423,28 @@ def main():
                 "M": float(np.max(np.abs(a[:, 1:4] - b[:, 1:4]))) / ms2}
         res["fp64"] = {"value": n_cells * args.steps / (ms_64 * 1e-3), "ms_per_step": ms_64 / args.steps,
                        "step_kernel_ms": float(np.mean(kms_64)), "stats": st_64}
+        res["newton"]["fp64"] = newton_summary(st_64)
         res["mixed_vs_fp64_rel_err"] = {"one_step": err1, "after_%d_steps" % args.steps: errK}
 
     # ---------------------------------------------------------------- roofline of the step kernel
     kavg = float(np.mean(kms_mx)) * 1e-3
-    flops = step_flops(P, {k: v / args.steps for k, v in st_mx.items()})
+    per_launch = {k: v / args.steps for k, v in st_mx.items()}
+    flops = step_flops(P, per_launch, mlp=mlp is not None)
     traffic = None
     if (step_sources_hash() == PROFILED_TRAFFIC["sources_sha256_16"] and args.cells == 256
             and args.path == PROFILED_TRAFFIC.get("path", "padded")):
         traffic = PROFILED_TRAFFIC["read"] + PROFILED_TRAFFIC["write"]
     roofline = {"bound": "alu", "achieved": flops / kavg / 1e12, "peak": PEAK_ALU / 1e12,
                 "unit": "TFLOP/s", "frac": flops / kavg / PEAK_ALU, "traffic": traffic,
-                "kernel": "k_step<float,%s> (mixed)" % ("gather" if args.path == "grid" else "padded"),
+                "kernel": "k_step<float,%s,%s> (mixed)" % ("gather" if args.path == "grid" else "padded",
+                                                           "mlp" if mlp is not None else "analytic"),
                 "launch_ms": kavg * 1e3,
                 "hbm_GBps_algorithmic": IO_BYTES_PER_PATCH[args.path] * P / kavg / 1e9,
                 "flops_per_launch": flops}
+    if mlp is not None:
+        mf = per_launch["n_inversions"] * MFMA_FLOP_MLP
+        roofline["mfma_bf16"] = {"flops_per_launch": mf, "achieved_TFLOPs": mf / kavg / 1e12,
+                                 "frac_of_2500": mf / kavg / 2.5e15}
 
     # ---------------------------------------------------------------- standalone conversions
     if args.conversion:
@@ -310,26 +467,36 @@ def main():
         cc = S.srhd_prim2cons(cp)
         out = torch.empty_like(cc)
         stt = torch.empty(n, dtype=torch.int8, device=dev)
+        its = torch.empty(n, dtype=torch.uint8, device=dev)
         conv = {}
-        for name, src in (("fp64", cc), ("fp32", cc.float())):
-            o = out if name == "fp64" else torch.empty_like(src)
-            S.srhd_cons2prim(src, prim=o, status=stt)
+        variants = [("fp64", cc, None), ("fp32", cc.float(), None)]
+        if mlp is not None:
+            variants += [("fp64_learned_guess", cc, guess), ("fp32_learned_guess", variants[1][1], guess)]
+        for name, src, gs in variants:
+            o = out if src.dtype == torch.float64 else torch.empty_like(src)
+            S.srhd_cons2prim(src, prim=o, status=stt, iters=its, guess=gs)
             torch.cuda.synchronize()
+            mean_it = float(its.double().mean().item())
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             reps = 5
             e0.record(stream)
             for _ in range(reps):
-                S.srhd_cons2prim(src, prim=o, status=stt)
+                S.srhd_cons2prim(src, prim=o, status=stt, guess=gs)
             e1.record(stream)
             torch.cuda.synchronize()
             t = e0.elapsed_time(e1) / reps * 1e-3
             bpe = 2 * 5 * src.element_size() + 1
             conv[name] = {"states_per_s": n / t, "ms": t * 1e3,
-                          "hbm_frac": n * bpe / t / PEAK_HBM,
-                          "unphysical_frac": float((stt == 1).float().mean().item())}
+                          "hbm_frac": n * bpe / t / PEAK_HBM, "newton_iters_mean": mean_it,
+                          "unphysical_frac": float((stt == 1).float().mean().item()),
+                          "fallback_frac": float((stt == 2).float().mean().item())}
         res["conversion_batch_1e8"] = conv
-        del cp, cc, out, stt
+        del cp, cc, out, stt, its, variants
+
+    # ---------------------------------------------------------------- jet patch list
+    if args.jet:
+        res["jet_patch_list"] = run_jet(args, S, W, dev, stream, guess, guess_name)
 
     # ---------------------------------------------------------------- CPU baseline (the oracle)
     cpu = None
@@ -364,9 +531,10 @@ def main():
         "config": {"workload": "blast_%d^3_periodic_%dpatches_mixed_precision" % (args.cells, P),
                    "path": args.path, "patch_order": "morton",
                    "cells": n_cells, "patches": P, "ghost": 3, "riemann": "HLLC",
-                   "limiter_theta": 1.5, "guess": "analytic", "steps_per_run": args.steps},
+                   "limiter_theta": 1.5, "guess": guess_name, "steps_per_run": args.steps},
         "roofline": roofline, "cpu_baseline": cpu, "mixed_stats": st_mx,
     }
+    line["schedules"] = schedules
     line.update(res)
     print(json.dumps(line), flush=True)
 

@@ -133,11 +133,15 @@ int srhd_cfl_dt(int dtype, int64_t n_patch, const void *interior, int n_level,
  * workgroups; each claims `chunk` patches at a time from one queue counter per XCD (over that
  * XCD's contiguous range, then the other XCDs' ranges in turn) until the list is exhausted.
  * queue: device memory of SRHD_QUEUE_WORDS uint64 words, required when groups > 0, zeroed by the
- * call on its stream; calls in flight at the same time must not share it. */
+ * call on its stream; calls in flight at the same time must not share it.
+ * occupancy: 0 selects the step kernel compiled for its natural register budget; 2 selects a
+ * variant compiled for at most 128 VGPRs per lane so that two 512-thread workgroups share a
+ * compute unit (mixed precision with the analytic guess only: otherwise SRHD_EUNSUPPORTED). */
 #define SRHD_QUEUE_WORDS 8
 typedef struct {
   int groups;              /* 0, or 1 .. 65535 persistent workgroups */
   int chunk;               /* patches per claim, 1 .. 64 (ignored when groups == 0) */
+  int occupancy;           /* 0 or 2 */
   uint64_t *queue;         /* device [SRHD_QUEUE_WORDS], or NULL when groups == 0 */
 } srhd_sched;
 
@@ -175,22 +179,24 @@ int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
                     const srhd_step_params *prm, srhd_step_stats *stats, void *stream);
 
 /* Workgroups of the step kernel that fit on one compute unit at once for the given precision,
- * guess kind (srhd_guess_kind) and layout (gather = 1: srhd_fluid_step_grid, 0: srhd_fluid_step);
- * multiplied by the device's compute-unit count it sizes a persistent schedule.  Returns the
- * count (> 0), or a negative srhd_err. */
-int srhd_step_occupancy(int prec, int guess_kind, int gather);
+ * guess kind (srhd_guess_kind), layout (gather = 1: srhd_fluid_step_grid, 0: srhd_fluid_step) and
+ * register variant (occupancy field of srhd_sched); multiplied by the device's compute-unit count
+ * it sizes a persistent schedule.  Returns the count (> 0), or a negative srhd_err. */
+int srhd_step_occupancy(int prec, int guess_kind, int gather, int occupancy);
 
 /* Schedule autotuner for srhd_fluid_step.  Runs the step on `in` (writing `out`) once per
  * candidate schedule as a warm-up and then `reps` timed times, timed with events on `stream`,
  * and writes the fastest candidate into prm->sched (keeping prm->sched.queue, which must be
- * set).  Candidates: one workgroup per patch, and persistent grids of 1, 2 and 4 times the
- * resident workgroups (srhd_step_occupancy x compute units) with chunk 1, 2 and 4.  table (host,
- * may be NULL) receives up to table_cap entries {groups, chunk, ms per step} in trial order and
- * *n_table their number.  Unlike the other calls this one synchronises `stream`.  stats counters
- * are not touched. */
+ * set).  Candidates, for each register variant the precision and guess allow (occupancy 0, and 2
+ * for mixed precision with the analytic guess): one workgroup per patch, and persistent grids of
+ * 1, 2 and 4 times the resident workgroups (srhd_step_occupancy x compute units) with chunk 1, 2
+ * and 4.  table (host, may be NULL) receives up to table_cap entries {groups, chunk, occupancy,
+ * ms per step} in trial order and *n_table their number.  Unlike the other calls this one
+ * synchronises `stream`.  stats counters are not touched. */
 typedef struct {
   int groups;
   int chunk;
+  int occupancy;
   float ms;
 } srhd_tune_entry;
 int srhd_autotune_step(const srhd_patches *in, void *out, const double *dt_lev,
@@ -237,6 +243,13 @@ int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_
                          const double *dt_lev, double *cons_out, void *prims_out,
                          uint64_t *smax_out, double *dt_used, const srhd_step_params *prm,
                          srhd_step_stats *stats, void *stream);
+
+/* The schedule autotuner of srhd_autotune_step for srhd_fluid_step_grid on the same arguments
+ * (outputs written, prm->sched set to the fastest candidate; synchronises `stream`). */
+int srhd_autotune_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_cfl,
+                            const double *dt_lev, double *cons_out, void *prims_out,
+                            uint64_t *smax_out, srhd_step_params *prm, int reps,
+                            srhd_tune_entry *table, int table_cap, int *n_table, void *stream);
 
 /* ---------------------------------------------------------------------------------------- */
 /* The learned guess: inference and training                                                */

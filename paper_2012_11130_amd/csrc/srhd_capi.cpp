@@ -53,11 +53,19 @@ int check_guess(const srhd_guess *g, srhd::GuessArgs &out)
 }
 
 // Launch schedule of a step (include/srhd.h, srhd_sched).
-int check_sched(const srhd_sched &sc, srhd::StepArgs &s, const char *who)
+int check_sched(const srhd_sched &sc, int prec, int guess_kind, srhd::StepArgs &s, const char *who)
 {
   s.queue = nullptr;
   s.groups = 0;
   s.chunk = 1;
+  s.occ2 = 0;
+  if (sc.occupancy != 0 && sc.occupancy != 2)
+    return fail(SRHD_EINVAL, "%s: sched.occupancy %d is neither 0 nor 2", who, sc.occupancy);
+  if (sc.occupancy == 2) {
+    if (prec != SRHD_PREC_MIXED || guess_kind != SRHD_GUESS_ANALYTIC)
+      return fail(SRHD_EUNSUPPORTED, "%s: sched.occupancy 2 needs mixed precision and the analytic guess", who);
+    s.occ2 = 1;
+  }
   if (sc.groups == 0) return SRHD_OK;
   if (sc.groups < 0 || sc.groups > 65535)
     return fail(SRHD_EINVAL, "%s: sched.groups %d not in [0, 65535]", who, sc.groups);
@@ -215,7 +223,7 @@ int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
   s.c_cfl = 0.0;
   s.dt_out = nullptr;
   s.xcd_remap = 0;
-  rc = check_sched(prm->sched, s, "srhd_fluid_step");
+  rc = check_sched(prm->sched, prm->prec, g.kind, s, "srhd_fluid_step");
   if (rc) return rc;
   if (s.queue) {
     const char *q = (const char *)s.queue;
@@ -225,47 +233,60 @@ int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
   return hip_status(srhd::launch_step(prm->prec, s, (hipStream_t)stream), "srhd_fluid_step");
 }
 
-int srhd_step_occupancy(int prec, int guess_kind, int gather)
+int srhd_step_occupancy(int prec, int guess_kind, int gather, int occupancy)
 {
   if (prec != SRHD_PREC_FP64 && prec != SRHD_PREC_MIXED)
     return fail(SRHD_EINVAL, "srhd_step_occupancy: bad precision %d", prec);
   if (guess_kind != SRHD_GUESS_ANALYTIC && guess_kind != SRHD_GUESS_MLP)
     return fail(SRHD_EINVAL, "srhd_step_occupancy: unknown guess kind %d", guess_kind);
-  int n = srhd::step_occupancy(prec, gather != 0, guess_kind == SRHD_GUESS_MLP);
+  if (occupancy != 0 && occupancy != 2)
+    return fail(SRHD_EINVAL, "srhd_step_occupancy: occupancy %d is neither 0 nor 2", occupancy);
+  if (occupancy == 2 && (prec != SRHD_PREC_MIXED || guess_kind != SRHD_GUESS_ANALYTIC))
+    return fail(SRHD_EUNSUPPORTED, "srhd_step_occupancy: occupancy 2 needs mixed precision and the analytic guess");
+  int n = srhd::step_occupancy(prec, gather != 0, guess_kind == SRHD_GUESS_MLP, occupancy == 2);
   if (n <= 0) return fail(SRHD_EHIP, "srhd_step_occupancy: occupancy query failed");
   return n;
 }
 
-int srhd_autotune_step(const srhd_patches *in, void *out, const double *dt_lev,
-                       srhd_step_params *prm, int reps, srhd_tune_entry *table, int table_cap,
-                       int *n_table, void *stream)
+}  // extern "C"
+
+namespace {
+
+// Times `run(trial)` for every candidate schedule and leaves the fastest in prm->sched.
+template <class Run>
+int autotune(srhd_step_params *prm, int gather, int reps, srhd_tune_entry *table, int table_cap,
+             int *n_table, void *stream, const char *who, Run run)
 {
-  if (!prm) return fail(SRHD_EINVAL, "srhd_autotune_step: NULL parameters");
-  if (!prm->sched.queue) return fail(SRHD_EINVAL, "srhd_autotune_step: prm->sched.queue must be set");
-  if (reps < 1 || reps > 100) return fail(SRHD_EINVAL, "srhd_autotune_step: reps %d not in [1, 100]", reps);
-  if (table_cap < 0) return fail(SRHD_EINVAL, "srhd_autotune_step: table_cap < 0");
-  int occ = srhd_step_occupancy(prm->prec, prm->guess.kind, 0);
-  if (occ <= 0) return occ < 0 ? occ : fail(SRHD_EHIP, "srhd_autotune_step: occupancy 0");
+  if (!prm) return fail(SRHD_EINVAL, "%s: NULL parameters", who);
+  if (!prm->sched.queue) return fail(SRHD_EINVAL, "%s: prm->sched.queue must be set", who);
+  if (reps < 1 || reps > 100) return fail(SRHD_EINVAL, "%s: reps %d not in [1, 100]", who, reps);
+  if (table_cap < 0) return fail(SRHD_EINVAL, "%s: table_cap < 0", who);
   int dev = 0, cus = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e != hipSuccess) return hip_status(e, "srhd_autotune_step");
-  struct Cand { int groups, chunk; };
-  Cand cand[10];
+  if (e != hipSuccess) return hip_status(e, who);
+  struct Cand { int groups, chunk, occ; };
+  Cand cand[20];
   int nc = 0;
-  cand[nc++] = {0, 1};
-  for (int m : {1, 2, 4})
-    for (int c : {1, 2, 4}) {
-      long g = (long)m * occ * cus;
-      cand[nc++] = {(int)(g > 65535 ? 65535 : g), c};
-    }
+  const bool two = prm->prec == SRHD_PREC_MIXED && prm->guess.kind == SRHD_GUESS_ANALYTIC;
+  for (int occ : {0, 2}) {
+    if (occ == 2 && !two) continue;
+    int per_cu = srhd_step_occupancy(prm->prec, prm->guess.kind, gather, occ);
+    if (per_cu <= 0) return per_cu < 0 ? per_cu : fail(SRHD_EHIP, "%s: occupancy 0", who);
+    cand[nc++] = {0, 1, occ};
+    for (int m : {1, 2, 4})
+      for (int c : {1, 2, 4}) {
+        long g = (long)m * per_cu * cus;
+        cand[nc++] = {(int)(g > 65535 ? 65535 : g), c, occ};
+      }
+  }
   hipStream_t st = (hipStream_t)stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   if (e != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
-    return hip_status(e, "srhd_autotune_step: event");
+    return hip_status(e, who);
   }
   srhd_step_params trial = *prm;
   int best = -1, rc = SRHD_OK;
@@ -274,19 +295,19 @@ int srhd_autotune_step(const srhd_patches *in, void *out, const double *dt_lev,
   for (int i = 0; i < nc && rc == SRHD_OK; ++i) {
     trial.sched.groups = cand[i].groups;
     trial.sched.chunk = cand[i].chunk;
-    rc = srhd_fluid_step(in, out, dt_lev, &trial, nullptr, stream);          // warm-up
+    trial.sched.occupancy = cand[i].occ;
+    rc = run(&trial);                                           // warm-up
     if (rc) break;
     e = hipEventRecord(e0, st);
-    for (int r = 0; r < reps && rc == SRHD_OK && e == hipSuccess; ++r)
-      rc = srhd_fluid_step(in, out, dt_lev, &trial, nullptr, stream);
+    for (int r = 0; r < reps && rc == SRHD_OK && e == hipSuccess; ++r) rc = run(&trial);
     if (rc) break;
     if (e == hipSuccess) e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.0f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    if (e != hipSuccess) { rc = hip_status(e, "srhd_autotune_step: timing"); break; }
+    if (e != hipSuccess) { rc = hip_status(e, who); break; }
     ms /= (float)reps;
-    if (table && i < table_cap) table[i] = srhd_tune_entry{cand[i].groups, cand[i].chunk, ms};
+    if (table && i < table_cap) table[i] = srhd_tune_entry{cand[i].groups, cand[i].chunk, cand[i].occ, ms};
     if (n_table && i < table_cap) *n_table = i + 1;
     if (best < 0 || ms < best_ms) { best = i; best_ms = ms; }
   }
@@ -295,7 +316,32 @@ int srhd_autotune_step(const srhd_patches *in, void *out, const double *dt_lev,
   if (rc) return rc;
   prm->sched.groups = cand[best].groups;
   prm->sched.chunk = cand[best].chunk;
+  prm->sched.occupancy = cand[best].occ;
   return SRHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int srhd_autotune_step(const srhd_patches *in, void *out, const double *dt_lev,
+                       srhd_step_params *prm, int reps, srhd_tune_entry *table, int table_cap,
+                       int *n_table, void *stream)
+{
+  return autotune(prm, 0, reps, table, table_cap, n_table, stream, "srhd_autotune_step",
+                  [&](const srhd_step_params *t) { return srhd_fluid_step(in, out, dt_lev, t, nullptr, stream); });
+}
+
+int srhd_autotune_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_cfl,
+                            const double *dt_lev, double *cons_out, void *prims_out,
+                            uint64_t *smax_out, srhd_step_params *prm, int reps,
+                            srhd_tune_entry *table, int table_cap, int *n_table, void *stream)
+{
+  return autotune(prm, 1, reps, table, table_cap, n_table, stream, "srhd_autotune_step_grid",
+                  [&](const srhd_step_params *t) {
+                    return srhd_fluid_step_grid(in, smax_in, c_cfl, dt_lev, cons_out, prims_out,
+                                                smax_out, nullptr, t, nullptr, stream);
+                  });
 }
 
 int srhd_grid_prims(int prec, int64_t n_patch, const double *cons, void *prims,
@@ -449,7 +495,7 @@ int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_
   s.c_cfl = c_cfl;
   s.dt_out = dt_used;
   s.xcd_remap = 1;
-  rc = check_sched(prm->sched, s, "srhd_fluid_step_grid");
+  rc = check_sched(prm->sched, prm->prec, g.kind, s, "srhd_fluid_step_grid");
   if (rc) return rc;
   return hip_status(srhd::launch_step_grid(prm->prec, s, (hipStream_t)stream),
                     "srhd_fluid_step_grid");

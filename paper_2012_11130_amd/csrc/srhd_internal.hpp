@@ -59,10 +59,11 @@ struct StepArgs {
   unsigned long long *queue;
   int groups;
   int chunk;
+  int occ2;                             // the kernel variant that fits two workgroups per CU
 };
 
 hipError_t launch_step(int prec, const StepArgs &a, hipStream_t s);
-int step_occupancy(int prec, bool gather, bool mlp);   // workgroups per CU, 0 on error
+int step_occupancy(int prec, bool gather, bool mlp, bool occ2);   // workgroups per CU, 0 on error
 
 size_t mlp_workspace_bytes(int64_t batch);
 hipError_t launch_mlp_features(int dtype, int64_t n, const void *cons, const void *prim,

@@ -470,7 +470,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
 // workgroup drains its own XCD's range first and then helps the others in turn, so every
 // workgroup leaves the loop once all eight ranges are exhausted.
 template <class T, bool GATHER, bool MLP>
-__global__ void __launch_bounds__(NT) k_step(StepArgs a)
+__device__ __forceinline__ void step_body(const StepArgs &a)
 {
   const MlpDev mlp = {a.guess.w, a.guess.bias, a.guess.norm};
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -499,6 +499,21 @@ __global__ void __launch_bounds__(NT) k_step(StepArgs a)
       }
     }
   }
+}
+
+template <class T, bool GATHER, bool MLP>
+__global__ void __launch_bounds__(NT) k_step(StepArgs a)
+{
+  step_body<T, GATHER, MLP>(a);
+}
+
+// The same kernel compiled for at most 128 VGPRs (four waves per SIMD), so that two 512-thread
+// workgroups share a CU when their LDS tiles fit (the mixed-precision tile takes 78 KB); the
+// compiler then keeps a few values of the per-patch setup in scratch instead of registers.
+template <class T, bool GATHER, bool MLP>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) k_step_occ2(StepArgs a)
+{
+  step_body<T, GATHER, MLP>(a);
 }
 
 // Inversion of every interior cell into the bulk type, with the maximum signal speed (the
@@ -552,16 +567,26 @@ __global__ void k_zero_queue(unsigned long long *q)
   if (threadIdx.x < SRHD_QUEUE_WORDS) q[threadIdx.x] = 0ull;
 }
 
+// Kernel of a (precision, layout, guess, register budget) combination.  The two-workgroup
+// variant exists for the mixed-precision kernels with the analytic guess only: the FP64 tile
+// fills the LDS of a CU by itself, and the learned guess needs its registers.
 template <class T, bool GATHER, bool MLP>
-int occupancy_k()
+const void *step_kernel(bool occ2)
+{
+  if constexpr (sizeof(T) == 4 && !MLP)
+    if (occ2) return (const void *)k_step_occ2<T, GATHER, false>;
+  return (const void *)k_step<T, GATHER, MLP>;
+}
+
+template <class T, bool GATHER, bool MLP>
+int occupancy_k(bool occ2)
 {
   int n = 0;
   const size_t bytes = sizeof(Tile<T>);
-  if (hipFuncSetAttribute((const void *)k_step<T, GATHER, MLP>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
+  const void *fn = step_kernel<T, GATHER, MLP>(occ2);
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<T, GATHER, MLP>, NT, bytes) != hipSuccess)
-    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, NT, bytes) != hipSuccess) return 0;
   return n;
 }
 
@@ -569,7 +594,8 @@ template <class T, bool GATHER, bool MLP>
 hipError_t launch_step_k(const StepArgs &a, hipStream_t st)
 {
   const size_t bytes = sizeof(Tile<T>);
-  hipError_t e = hipFuncSetAttribute((const void *)k_step<T, GATHER, MLP>,
+  const bool occ2 = a.occ2 && !MLP && sizeof(T) == 4;
+  hipError_t e = hipFuncSetAttribute(step_kernel<T, GATHER, MLP>(occ2),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
   if (GATHER) hipLaunchKernelGGL(k_zero_bits, dim3(1), dim3(64), 0, st, a.smax_out);
@@ -579,6 +605,12 @@ hipError_t launch_step_k(const StepArgs &a, hipStream_t st)
     blocks = a.groups;
   } else {
     blocks = a.xcd_remap ? 8 * ((a.n_patch + 7) / 8) : a.n_patch;
+  }
+  if constexpr (sizeof(T) == 4 && !MLP) {
+    if (occ2) {
+      hipLaunchKernelGGL((k_step_occ2<T, GATHER, false>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
+      return hipGetLastError();
+    }
   }
   hipLaunchKernelGGL((k_step<T, GATHER, MLP>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
   return hipGetLastError();
@@ -599,13 +631,13 @@ hipError_t launch_step(int prec, const StepArgs &a, hipStream_t st)
   return prec == SRHD_PREC_MIXED ? launch_step_t<float, false>(a, st) : launch_step_t<double, false>(a, st);
 }
 
-int step_occupancy(int prec, bool gather, bool mlp)
+int step_occupancy(int prec, bool gather, bool mlp, bool occ2)
 {
   if (prec == SRHD_PREC_MIXED)
-    return gather ? (mlp ? occupancy_k<float, true, true>() : occupancy_k<float, true, false>())
-                  : (mlp ? occupancy_k<float, false, true>() : occupancy_k<float, false, false>());
-  return gather ? (mlp ? occupancy_k<double, true, true>() : occupancy_k<double, true, false>())
-                : (mlp ? occupancy_k<double, false, true>() : occupancy_k<double, false, false>());
+    return gather ? (mlp ? occupancy_k<float, true, true>(occ2) : occupancy_k<float, true, false>(occ2))
+                  : (mlp ? occupancy_k<float, false, true>(occ2) : occupancy_k<float, false, false>(occ2));
+  return gather ? (mlp ? occupancy_k<double, true, true>(occ2) : occupancy_k<double, true, false>(occ2))
+                : (mlp ? occupancy_k<double, false, true>(occ2) : occupancy_k<double, false, false>(occ2));
 }
 
 hipError_t launch_step_grid(int prec, const StepArgs &a, hipStream_t st)

@@ -50,7 +50,7 @@ class srhd_grid(ctypes.Structure):
 
 
 class srhd_sched(ctypes.Structure):
-    _fields_ = [("groups", _int), ("chunk", _int), ("queue", _vp)]
+    _fields_ = [("groups", _int), ("chunk", _int), ("occupancy", _int), ("queue", _vp)]
 
 
 class srhd_step_params(ctypes.Structure):
@@ -59,7 +59,7 @@ class srhd_step_params(ctypes.Structure):
 
 
 class srhd_tune_entry(ctypes.Structure):
-    _fields_ = [("groups", _int), ("chunk", _int), ("ms", ctypes.c_float)]
+    _fields_ = [("groups", _int), ("chunk", _int), ("occupancy", _int), ("ms", ctypes.c_float)]
 
 
 QUEUE_WORDS = 8
@@ -91,10 +91,13 @@ _sig = {
     "srhd_mlp_adam": [_vp, _vp, _vp, _vp, _int, ctypes.c_float, _vp, _vp, _vp],
     "srhd_fluid_step_grid": [ctypes.POINTER(srhd_grid), _vp, ctypes.c_double, _vp, _vp, _vp,
                              _vp, _vp, ctypes.POINTER(srhd_step_params), _vp, _vp],
-    "srhd_step_occupancy": [_int, _int, _int],
+    "srhd_step_occupancy": [_int, _int, _int, _int],
     "srhd_autotune_step": [ctypes.POINTER(srhd_patches), _vp, _vp,
                            ctypes.POINTER(srhd_step_params), _int,
                            ctypes.POINTER(srhd_tune_entry), _int, ctypes.POINTER(_int), _vp],
+    "srhd_autotune_step_grid": [ctypes.POINTER(srhd_grid), _vp, ctypes.c_double, _vp, _vp, _vp,
+                                _vp, ctypes.POINTER(srhd_step_params), _int,
+                                ctypes.POINTER(srhd_tune_entry), _int, ctypes.POINTER(_int), _vp],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -234,17 +237,18 @@ def srhd_stats_reset(stats):
 
 class Sched:
     """Launch schedule of a step: groups == 0 is one workgroup per patch; groups > 0 a
-    persistent grid claiming `chunk` patches at a time from a device queue (owned here)."""
+    persistent grid claiming `chunk` patches at a time from a device queue (owned here);
+    occupancy 2 selects the kernel variant that fits two workgroups per compute unit."""
 
-    def __init__(self, groups=0, chunk=1, device="cuda:0"):
-        self.groups, self.chunk = int(groups), int(chunk)
+    def __init__(self, groups=0, chunk=1, device="cuda:0", occupancy=0):
+        self.groups, self.chunk, self.occupancy = int(groups), int(chunk), int(occupancy)
         self.queue = torch.zeros(QUEUE_WORDS, dtype=torch.int64, device=device)
 
     def c(self):
-        return srhd_sched(self.groups, self.chunk, self.queue.data_ptr())
+        return srhd_sched(self.groups, self.chunk, self.occupancy, self.queue.data_ptr())
 
     def __repr__(self):
-        return "Sched(groups=%d, chunk=%d)" % (self.groups, self.chunk)
+        return "Sched(groups=%d, chunk=%d, occupancy=%d)" % (self.groups, self.chunk, self.occupancy)
 
 
 def _patches(padded, dh, level, ghost):
@@ -270,20 +274,24 @@ def _params(theta, riemann, prec, max_retry, guess, sched):
     prm.prec = int(prec)
     prm.max_retry = int(max_retry)
     prm.guess = guess if guess is not None else srhd_guess(GUESS_ANALYTIC, None, 0)
-    prm.sched = sched.c() if sched is not None else srhd_sched(0, 1, None)
+    prm.sched = sched.c() if sched is not None else srhd_sched(0, 1, 0, None)
     return prm
 
 
-def srhd_step_occupancy(prec, guess_kind=GUESS_ANALYTIC, gather=False):
-    rc = _lib.srhd_step_occupancy(int(prec), int(guess_kind), int(bool(gather)))
+def srhd_step_occupancy(prec, guess_kind=GUESS_ANALYTIC, gather=False, occupancy=0):
+    rc = _lib.srhd_step_occupancy(int(prec), int(guess_kind), int(bool(gather)), int(occupancy))
     _check(min(rc, 0))
     return rc
+
+
+def _table(table, n):
+    return [(table[i].groups, table[i].chunk, table[i].occupancy, table[i].ms) for i in range(n.value)]
 
 
 def srhd_autotune_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann=HLLC,
                        prec=PREC_FP64, max_retry=4, ghost=None, guess=None, reps=2):
     """Times the candidate schedules of srhd_fluid_step on these patches; returns (Sched of the
-    fastest, [(groups, chunk, ms per step), ...])."""
+    fastest, [(groups, chunk, occupancy, ms per step), ...])."""
     _need_cuda(padded, dt_lev, level)
     P = padded.shape[0]
     if out is None:
@@ -291,12 +299,48 @@ def srhd_autotune_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riem
     sch = Sched(0, 1, padded.device)
     d = _patches(padded, dh, level, ghost)
     prm = _params(theta, riemann, prec, max_retry, guess, sch)
-    table = (srhd_tune_entry * 16)()
+    table = (srhd_tune_entry * 32)()
     n = _int(0)
     _check(_lib.srhd_autotune_step(ctypes.byref(d), _ptr(out), _ptr(dt_lev), ctypes.byref(prm),
-                                   int(reps), table, 16, ctypes.byref(n), _stream()))
-    sch.groups, sch.chunk = prm.sched.groups, prm.sched.chunk
-    return sch, [(table[i].groups, table[i].chunk, table[i].ms) for i in range(n.value)]
+                                   int(reps), table, 32, ctypes.byref(n), _stream()))
+    sch.groups, sch.chunk, sch.occupancy = prm.sched.groups, prm.sched.chunk, prm.sched.occupancy
+    return sch, _table(table, n)
+
+
+def _grid(cons, prims, neighbor, dh, level):
+    gr = srhd_grid()
+    gr.n_patch = cons.shape[0]
+    gr.cons = cons.data_ptr()
+    gr.prims = prims.data_ptr()
+    gr.neighbor = neighbor.data_ptr()
+    gr.level = None if level is None else level.data_ptr()
+    dh = [float(x) for x in dh]
+    gr.n_level = len(dh)
+    for i, h in enumerate(dh):
+        gr.dh[i] = h
+    return gr
+
+
+def srhd_autotune_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, dt_lev=None,
+                            level=None, theta=1.5, riemann=HLLC, prec=PREC_FP64, max_retry=4,
+                            guess=None, reps=2):
+    """Times the candidate schedules of srhd_fluid_step_grid on this block; returns (Sched of
+    the fastest, [(groups, chunk, occupancy, ms per step), ...])."""
+    _need_cuda(cons, prims, neighbor, smax_in, dt_lev, level)
+    cons_out = torch.empty_like(cons)
+    prims_out = torch.empty_like(prims)
+    smax_out = torch.empty(1, dtype=torch.int64, device=cons.device)
+    sch = Sched(0, 1, cons.device)
+    gr = _grid(cons, prims, neighbor, dh, level)
+    prm = _params(theta, riemann, prec, max_retry, guess, sch)
+    table = (srhd_tune_entry * 32)()
+    n = _int(0)
+    _check(_lib.srhd_autotune_step_grid(ctypes.byref(gr), _ptr(smax_in), float(c_cfl), _ptr(dt_lev),
+                                        _ptr(cons_out), _ptr(prims_out), _ptr(smax_out),
+                                        ctypes.byref(prm), int(reps), table, 32, ctypes.byref(n),
+                                        _stream()))
+    sch.groups, sch.chunk, sch.occupancy = prm.sched.groups, prm.sched.chunk, prm.sched.occupancy
+    return sch, _table(table, n)
 
 
 def srhd_fluid_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann=HLLC,
@@ -357,16 +401,7 @@ def srhd_fluid_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, dt_
     _need_cuda(cons_out, prims_out, smax_out, dt_used)
     if prims.dtype != prims_dtype(prec) or prims_out.dtype != prims_dtype(prec):
         raise TypeError("primitives must be %s for this precision" % prims_dtype(prec))
-    dh = [float(x) for x in dh]
-    gr = srhd_grid()
-    gr.n_patch = P
-    gr.cons = cons.data_ptr()
-    gr.prims = prims.data_ptr()
-    gr.neighbor = neighbor.data_ptr()
-    gr.level = None if level is None else level.data_ptr()
-    gr.n_level = len(dh)
-    for i, h in enumerate(dh):
-        gr.dh[i] = h
+    gr = _grid(cons, prims, neighbor, dh, level)
     prm = _params(theta, riemann, prec, max_retry, guess, sched)
     _check(_lib.srhd_fluid_step_grid(ctypes.byref(gr), _ptr(smax_in), float(c_cfl), _ptr(dt_lev),
                                      _ptr(cons_out), _ptr(prims_out), _ptr(smax_out),

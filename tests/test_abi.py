@@ -91,23 +91,31 @@ def test_schedule_checks(lib):
     prm.theta, prm.max_retry = 1.5, 4
     call = lambda: S._lib.srhd_fluid_step(ctypes.byref(d), al(out), al(dt), ctypes.byref(prm),
                                           None, None)
-    prm.sched = S.srhd_sched(-1, 1, None)
+    prm.sched = S.srhd_sched(-1, 1, 0, None)
     assert call() == -1 and b"groups" in S._lib.srhd_last_error()
-    prm.sched = S.srhd_sched(512, 1, None)
+    prm.sched = S.srhd_sched(512, 1, 0, None)
     assert call() == -1 and b"queue" in S._lib.srhd_last_error()
     q = ctypes.create_string_buffer(128)
-    prm.sched = S.srhd_sched(512, 0, al(q))
+    prm.sched = S.srhd_sched(512, 0, 0, al(q))
     assert call() == -1 and b"chunk" in S._lib.srhd_last_error()
-    prm.sched = S.srhd_sched(512, 65, al(q))
+    prm.sched = S.srhd_sched(512, 65, 0, al(q))
     assert call() == -1 and b"chunk" in S._lib.srhd_last_error()
     n = ctypes.c_int(0)
-    prm.sched = S.srhd_sched(0, 1, None)
+    prm.sched = S.srhd_sched(0, 1, 0, None)
     rc = S._lib.srhd_autotune_step(ctypes.byref(d), al(out), al(dt), ctypes.byref(prm), 2, None,
                                    0, ctypes.byref(n), None)
     assert rc == -1 and b"queue" in S._lib.srhd_last_error()
-    prm.sched = S.srhd_sched(0, 1, al(q))
+    prm.sched = S.srhd_sched(0, 1, 0, al(q))
     rc = S._lib.srhd_autotune_step(ctypes.byref(d), al(out), al(dt), ctypes.byref(prm), 0, None,
                                    0, ctypes.byref(n), None)
     assert rc == -1 and b"reps" in S._lib.srhd_last_error()
-    assert S._lib.srhd_step_occupancy(5, 0, 0) == -1
-    assert S._lib.srhd_step_occupancy(0, 7, 0) == -1
+    # the two-workgroup variant exists for mixed precision with the analytic guess only
+    prm.sched = S.srhd_sched(0, 1, 2, None)
+    assert call() == -3 and b"occupancy" in S._lib.srhd_last_error()
+    prm.sched = S.srhd_sched(0, 1, 3, None)
+    assert call() == -1 and b"occupancy" in S._lib.srhd_last_error()
+    assert S._lib.srhd_step_occupancy(5, 0, 0, 0) == -1
+    assert S._lib.srhd_step_occupancy(0, 7, 0, 0) == -1
+    assert S._lib.srhd_step_occupancy(1, 0, 0, 1) == -1
+    assert S._lib.srhd_step_occupancy(0, 0, 0, 2) == -3
+    assert S._lib.srhd_step_occupancy(1, 1, 0, 2) == -3
