@@ -143,8 +143,8 @@ def summarize_profile(d, calib_mib):
                 return 64 * (2 * avg(c[names[0]]) + avg(c[names[1]]) + avg(c[names[2]]) + avg(c[names[3]]))
             a64, a32 = fl(f64), fl(f32)
             vi = avg(c.get("SQ_INSTS_VALU", []))
-            bc = avg(c.get("SQ_LDS_BANK_CONFLICT", [])) / avg(c.get("SQ_LDS_IDX_ACTIVE", [])) \
-                if c.get("SQ_LDS_IDX_ACTIVE") else float("nan")
+            act = avg(c.get("SQ_LDS_IDX_ACTIVE", []))
+            bc = avg(c.get("SQ_LDS_BANK_CONFLICT", [])) / act if act > 0 else float("nan")
             print("| %s | %.3e | %.3e | %.2f | %.1f %% | %.3e | %.1f %% | %.3e | %.3f |"
                   % (k, a64, a32, (a64 + a32) / t / 1e12, 100 * (a64 + a32) / t / PEAK_ALU, vi,
                      100 * vi / t / issue_peak, avg(c.get("SQ_INSTS_LDS", [])), bc))
@@ -385,7 +385,8 @@ def main():
             print("# no weights of the learned guess: headline uses the analytic guess",
                   file=sys.stderr, flush=True)
     guess = mlp.guess() if mlp is not None else None
-    guess_name = "learned (BF16 MLP)" if mlp is not None else "analytic"
+    guess_name = ("learned (BF16 MLP on log L, log m, log x; consulted where L > %g)" % mlp.gate
+                  if mlp is not None else "analytic")
 
     ms_mx, kms_mx, st_mx, fin_mx = measure(S.PREC_MIXED, guess, "headline")
     print("# mixed, %s guess: %.2f ms for %d steps (step kernel %.3f ms avg); stats %s"
@@ -402,6 +403,16 @@ def main():
                                  "step_kernel_ms": float(np.mean(kms_an)), "stats": st_an,
                                  "max_abs_diff_vs_headline": float(np.max(np.abs(a - b)))}
         res["newton"]["mixed_analytic"] = newton_summary(st_an)
+        mlp_c = mlp_train.load(mlp_train.CONS_WEIGHTS, device="cuda:0")
+        if mlp_c is not None:
+            ms_c, kms_c, st_c, _ = measure(S.PREC_MIXED, mlp_c.guess(), "mixed_learned_cons_inputs")
+            print("# mixed, learned guess on (log D, log m, log x), every state: %.2f ms for %d steps"
+                  % (ms_c, args.steps), file=sys.stderr, flush=True)
+            res["mixed_learned_cons_inputs"] = {"value": n_cells * args.steps / (ms_c * 1e-3),
+                                                "ms_per_step": ms_c / args.steps,
+                                                "step_kernel_ms": float(np.mean(kms_c)),
+                                                "stats": st_c}
+            res["newton"]["mixed_learned_cons_inputs"] = newton_summary(st_c)
 
     # per-field difference of one mixed step against one FP64 step from the same state
     if not args.no_fp64:

@@ -55,15 +55,23 @@ typedef enum { SRHD_HLLC = 0, SRHD_HLLE = 1 } srhd_riemann;
  * the left-hand side L of Eq. 15 and the Newton inversion in FP64 (state storage stays FP64). */
 typedef enum { SRHD_PREC_FP64 = 0, SRHD_PREC_MIXED = 1 } srhd_prec;
 
-/* Learned initial guess: device parameters of a 3-64-64-1 SiLU perceptron that maps the
- * standardised features (log D, log max(|M|/D, 1e-300), log(Et/D)) to the standardised log of the
- * Newton unknown ht (see srhd_mlp_*).  Not in the paper: an addition whose Newton refinement
- * and analytic fallback keep the inversion's result unchanged. */
+/* Learned initial guess: device parameters of a 3-64-64-1 SiLU perceptron that maps three
+ * standardised log-scaled invariants of the conserved state to the standardised log of the
+ * Newton unknown ht (see srhd_mlp_*).  Feature sets:
+ *   SRHD_FEAT_CONS: (log D, log max(|M|/D, 1e-300), log(Et/D));
+ *   SRHD_FEAT_L:    (log L, log max(|M|/D, 1e-300), log(Et/D)), L the left-hand side of Eq. 15
+ *                   as the inversion computes it (error-free, before any guess is needed).
+ * The network is consulted only for states with L > gate_L (0: every state); the others, and
+ * every state whose network guess fails, use the analytic guess of App. A.  Not in the paper: an
+ * addition whose Newton refinement and analytic fallback keep the inversion's result unchanged. */
+enum { SRHD_FEAT_CONS = 0, SRHD_FEAT_L = 1 };
 typedef struct {
   const uint16_t *w_bf16;  /* BF16 weights, 16-byte aligned: W1[64][3], W2[64][64] (row = output
                               unit), W3[64] -- 4352 values */
   const float *bias;       /* FP32 biases: b1[64], b2[64], b3 -- 129 values */
   const float *norm;       /* FP32 [8]: input mean[3], input std[3], output mean, output std */
+  int features;            /* SRHD_FEAT_CONS or SRHD_FEAT_L */
+  double gate_L;           /* >= 0 */
 } srhd_mlp;
 
 typedef struct {
@@ -257,11 +265,12 @@ int srhd_autotune_step_grid(const srhd_grid *in, const uint64_t *smax_in, double
 
 #define SRHD_MLP_NPARAM 4481   /* W1[64][3], b1[64], W2[64][64], b2[64], W3[64], b3 */
 
-/* Features (log D, log max(|M|/D, 1e-300), log(Et/D)) of cons[5][n] into feat[3][n] (FP32).
- * With prim[5][n] (the states' primitives, same dtype) also the training target
- * target[n] = log ht, ht from Eq. 22 at Theta = p/rho; prim and target are both NULL or both set. */
-int srhd_mlp_features(int dtype, int64_t n, const void *cons, const void *prim, float *feat,
-                      float *target, void *stream);
+/* Features (feature set `features`, see srhd_mlp) of cons[5][n] into feat[3][n] (FP32).  With
+ * prim[5][n] (the states' primitives, same dtype) also the training target target[n] = log ht,
+ * ht from Eq. 22 at Theta = p/rho; prim and target are both NULL or both set.  States that are
+ * not admissible (Eq. 30) get L = 0 (log L = -inf). */
+int srhd_mlp_features(int dtype, int features, int64_t n, const void *cons, const void *prim,
+                      float *feat, float *target, void *stream);
 
 /* y[n] = de-standardised network output (the guess of log ht) for raw features feat[3][n]; the
  * hidden layer runs on the matrix cores (BF16 operands, FP32 accumulation). */

@@ -53,12 +53,22 @@ def dsilu(a):
     return s * (1.0 + a * (1.0 - s))
 
 
-def features(cons):
-    """cons [5][n] (D, Mx, My, Mz, Et) -> raw features [3][n]."""
+def features(cons, kind=0):
+    """cons [5][n] (D, Mx, My, Mz, Et) -> raw features [3][n]: kind 0 (log D, log max(|M|/D,
+    1e-300), log(Et/D)); kind 1 the same with log L first, L of Eq. 15 correctly rounded (the
+    oracle's), 0 for states that are not admissible (Eq. 30)."""
     cons = np.asarray(cons, dtype=np.float64)
     D = cons[0]
     m = np.sqrt((cons[1:4] ** 2).sum(axis=0)) / D
-    return np.stack([np.log(D), np.log(np.maximum(m, 1e-300)), np.log(cons[4] / D)])
+    if kind == 1:
+        from oracle import L_batch
+        L = L_batch(cons)
+        ok = (D > 0) & (cons[4] > 0) & np.isfinite(L) & (L > np.finfo(np.float64).eps)
+        with np.errstate(divide="ignore"):
+            first = np.log(np.where(ok, L, 0.0))
+    else:
+        first = np.log(D)
+    return np.stack([first, np.log(np.maximum(m, 1e-300)), np.log(cons[4] / D)])
 
 
 def forward(theta, x, bf16_round=True):

@@ -33,7 +33,7 @@ bool valid_dtype(int dtype) { return dtype == SRHD_F64 || dtype == SRHD_F32; }
 
 int check_guess(const srhd_guess *g, srhd::GuessArgs &out)
 {
-  out = srhd::GuessArgs{SRHD_GUESS_ANALYTIC, 30, nullptr, nullptr, nullptr};
+  out = srhd::GuessArgs{SRHD_GUESS_ANALYTIC, 30, nullptr, nullptr, nullptr, 0, 0.0};
   if (!g) return SRHD_OK;
   if (g->max_iter > 255) return fail(SRHD_EINVAL, "guess.max_iter %d exceeds 255", g->max_iter);
   out.max_iter = g->max_iter > 0 ? g->max_iter : 30;
@@ -43,10 +43,15 @@ int check_guess(const srhd_guess *g, srhd::GuessArgs &out)
       return fail(SRHD_EINVAL, "learned guess: missing network parameters");
     if (!aligned(g->mlp->w_bf16, 16) || !aligned(g->mlp->bias, 4) || !aligned(g->mlp->norm, 4))
       return fail(SRHD_EINVAL, "learned guess: misaligned parameters (weights need 16 bytes)");
+    if (g->mlp->features != SRHD_FEAT_CONS && g->mlp->features != SRHD_FEAT_L)
+      return fail(SRHD_EINVAL, "learned guess: unknown feature set %d", g->mlp->features);
+    if (!(g->mlp->gate_L >= 0.0)) return fail(SRHD_EINVAL, "learned guess: gate_L must be >= 0");
     out.kind = SRHD_GUESS_MLP;
     out.w = g->mlp->w_bf16;
     out.bias = g->mlp->bias;
     out.norm = g->mlp->norm;
+    out.features = g->mlp->features;
+    out.gate = g->mlp->gate_L;
     return SRHD_OK;
   }
   return fail(SRHD_EINVAL, "unknown guess kind %d", g->kind);
@@ -375,10 +380,12 @@ static int check_mlp(const srhd_mlp *m, const char *who)
   return SRHD_OK;
 }
 
-int srhd_mlp_features(int dtype, int64_t n, const void *cons, const void *prim, float *feat,
-                      float *target, void *stream)
+int srhd_mlp_features(int dtype, int features, int64_t n, const void *cons, const void *prim,
+                      float *feat, float *target, void *stream)
 {
   if (!valid_dtype(dtype)) return fail(SRHD_EINVAL, "srhd_mlp_features: bad dtype %d", dtype);
+  if (features != SRHD_FEAT_CONS && features != SRHD_FEAT_L)
+    return fail(SRHD_EINVAL, "srhd_mlp_features: unknown feature set %d", features);
   if (n < 0) return fail(SRHD_EINVAL, "srhd_mlp_features: n < 0");
   if (n == 0) return SRHD_OK;
   if (!cons || !feat) return fail(SRHD_EINVAL, "srhd_mlp_features: NULL array");
@@ -386,7 +393,7 @@ int srhd_mlp_features(int dtype, int64_t n, const void *cons, const void *prim, 
     return fail(SRHD_EINVAL, "srhd_mlp_features: misaligned array");
   if ((prim == nullptr) != (target == nullptr))
     return fail(SRHD_EINVAL, "srhd_mlp_features: prim and target go together");
-  return hip_status(srhd::launch_mlp_features(dtype, n, cons, prim, feat, target, (hipStream_t)stream),
+  return hip_status(srhd::launch_mlp_features(dtype, features, n, cons, prim, feat, target, (hipStream_t)stream),
                     "srhd_mlp_features");
 }
 
@@ -398,7 +405,7 @@ int srhd_mlp_forward(const srhd_mlp *m, int64_t n, const float *feat, float *y, 
   if (n == 0) return SRHD_OK;
   if (!feat || !y) return fail(SRHD_EINVAL, "srhd_mlp_forward: NULL array");
   if (!aligned(feat, 4) || !aligned(y, 4)) return fail(SRHD_EINVAL, "srhd_mlp_forward: misaligned array");
-  srhd::MlpDev d = {m->w_bf16, m->bias, m->norm};
+  srhd::MlpDev d = {m->w_bf16, m->bias, m->norm, m->features, m->gate_L};
   return hip_status(srhd::launch_mlp_forward(d, n, feat, y, (hipStream_t)stream), "srhd_mlp_forward");
 }
 
@@ -413,7 +420,7 @@ int srhd_mlp_grad(const srhd_mlp *m, int64_t batch, const float *feat, const flo
   if (!feat || !target || !grad || !loss || !ws) return fail(SRHD_EINVAL, "srhd_mlp_grad: NULL array");
   if (!aligned(feat, 4) || !aligned(target, 4) || !aligned(grad, 4) || !aligned(loss, 4) || !aligned(ws, 4))
     return fail(SRHD_EINVAL, "srhd_mlp_grad: misaligned array");
-  srhd::MlpDev d = {m->w_bf16, m->bias, m->norm};
+  srhd::MlpDev d = {m->w_bf16, m->bias, m->norm, m->features, m->gate_L};
   return hip_status(srhd::launch_mlp_grad(d, batch, feat, target, grad, loss, ws, (hipStream_t)stream),
                     "srhd_mlp_grad");
 }

@@ -14,6 +14,9 @@ struct GuessArgs {
   const uint16_t *w;       // MLP weights (BF16), NULL for the analytic guess
   const float *bias;
   const float *norm;
+  int features;            // SRHD_FEAT_*
+  double gate;             // the network is consulted for L > gate
+  __host__ __device__ MlpDev dev() const { return MlpDev{w, bias, norm, features, gate}; }
 };
 
 struct LevelArgs {
@@ -66,7 +69,7 @@ hipError_t launch_step(int prec, const StepArgs &a, hipStream_t s);
 int step_occupancy(int prec, bool gather, bool mlp, bool occ2);   // workgroups per CU, 0 on error
 
 size_t mlp_workspace_bytes(int64_t batch);
-hipError_t launch_mlp_features(int dtype, int64_t n, const void *cons, const void *prim,
+hipError_t launch_mlp_features(int dtype, int features, int64_t n, const void *cons, const void *prim,
                                float *feat, float *target, hipStream_t s);
 hipError_t launch_mlp_forward(const MlpDev &m, int64_t n, const float *feat, float *y, hipStream_t s);
 hipError_t launch_mlp_grad(const MlpDev &m, int64_t n, const float *feat, const float *target,

@@ -65,13 +65,15 @@ __global__ void __launch_bounds__(kBlock) k_cons2prim(int64_t n, const T *__rest
     const int64_t j = in ? i : 0;
     T D = cons[j], Mx = cons[n + j], My = cons[2 * n + j], Mz = cons[3 * n + j],
       Et = cons[4 * n + j];
+    T L;
+    const bool adm = admissible(D, Mx, My, Mz, Et, T(Tol<T>::eps), L);
+    bool consulted = false;
     T guess = T(-1);
-    if (MLP) guess = (T)mlp_guess(mlp, D, Mx, My, Mz, Et);
+    if (MLP) guess = (T)mlp_guess(mlp, D, Mx, My, Mz, Et, (in && adm) ? (double)L : 0.0, consulted);
     if (!in) continue;
     InvOut<T> o;
-    T L;
-    if (admissible(D, Mx, My, Mz, Et, T(Tol<T>::eps), L))
-      invert_with_L(D, Mx, My, Mz, L, guess, MLP, T(Tol<T>::v), max_iter, o);
+    if (adm)
+      invert_with_L(D, Mx, My, Mz, L, guess, consulted, T(Tol<T>::v), max_iter, o);
     else
       set_unphysical(o);
     prim[i] = o.rho;
@@ -205,7 +207,7 @@ hipError_t launch_cons2prim(int dtype, int64_t n, const void *cons, void *prim, 
 {
   if (n == 0) return hipSuccess;
   int mi = g.max_iter > 0 ? g.max_iter : 30;
-  MlpDev m = {g.w, g.bias, g.norm};
+  MlpDev m = g.dev();
   const bool mlp = g.kind == SRHD_GUESS_MLP;
   if (dtype == SRHD_F64) {
     if (mlp)

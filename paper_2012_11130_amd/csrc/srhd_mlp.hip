@@ -6,6 +6,8 @@
 // treats the BF16 rounding of the first layer's activations as the identity.  Gradients are
 // summed over the minibatch by one thread per parameter in sample order, so they are
 // bit-reproducible.
+#include <float.h>
+
 #include "srhd_device.hpp"
 #include "srhd_internal.hpp"
 #include "srhd_mlp.hpp"
@@ -16,10 +18,25 @@ namespace {
 constexpr int kBlk = 256;
 
 // ------------------------------------------------------------------------------ features
+// L of Eq. 15 as the inversion computes it (0 when the state is not admissible, Eq. 30).
+__device__ __forceinline__ double feature_L(double D, double Mx, double My, double Mz, double Et)
+{
+  double L;
+  return admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L) ? L : 0.0;
+}
+__device__ __forceinline__ double feature_L(float D, float Mx, float My, float Mz, float Et)
+{
+  if (!(finiteT(D) && finiteT(Mx) && finiteT(My) && finiteT(Mz) && finiteT(Et)) ||
+      !(D > 0.0f) || !(Et > 0.0f))
+    return 0.0;
+  const double L = lhs_L_from_f32(D, Mx, My, Mz, Et);
+  return L > DBL_EPSILON ? L : 0.0;
+}
+
 // Features of each state and, when its primitives are given, the training target log ht with
 // ht from Eq. 22 at Theta = p / rho.
 template <class T>
-__global__ void __launch_bounds__(kBlk) k_mlp_features(int64_t n, const T *__restrict__ cons,
+__global__ void __launch_bounds__(kBlk) k_mlp_features(int set, int64_t n, const T *__restrict__ cons,
                                                        const T *__restrict__ prim,
                                                        float *__restrict__ feat,
                                                        float *__restrict__ target)
@@ -27,7 +44,10 @@ __global__ void __launch_bounds__(kBlk) k_mlp_features(int64_t n, const T *__res
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     float f0, f1, f2;
-    mlp_features(cons[i], cons[n + i], cons[2 * n + i], cons[3 * n + i], cons[4 * n + i], f0, f1, f2);
+    const T D = cons[i], Mx = cons[n + i], My = cons[2 * n + i], Mz = cons[3 * n + i],
+            Et = cons[4 * n + i];
+    const double L = set ? feature_L(D, Mx, My, Mz, Et) : 0.0;
+    mlp_features(set, D, Mx, My, Mz, Et, L, f0, f1, f2);
     feat[i] = f0;
     feat[n + i] = f1;
     feat[2 * n + i] = f2;
@@ -174,15 +194,15 @@ inline int grid_of(int64_t n)
 
 size_t mlp_workspace_bytes(int64_t batch) { return (size_t)batch * (3 + 4 * 64 + 2) * 4 + 256; }
 
-hipError_t launch_mlp_features(int dtype, int64_t n, const void *cons, const void *prim,
+hipError_t launch_mlp_features(int dtype, int features, int64_t n, const void *cons, const void *prim,
                                float *feat, float *target, hipStream_t s)
 {
   if (n == 0) return hipSuccess;
   if (dtype == SRHD_F64)
-    hipLaunchKernelGGL(k_mlp_features<double>, dim3(grid_of(n)), dim3(kBlk), 0, s, n,
+    hipLaunchKernelGGL(k_mlp_features<double>, dim3(grid_of(n)), dim3(kBlk), 0, s, features, n,
                        (const double *)cons, (const double *)prim, feat, target);
   else
-    hipLaunchKernelGGL(k_mlp_features<float>, dim3(grid_of(n)), dim3(kBlk), 0, s, n,
+    hipLaunchKernelGGL(k_mlp_features<float>, dim3(grid_of(n)), dim3(kBlk), 0, s, features, n,
                        (const float *)cons, (const float *)prim, feat, target);
   return hipGetLastError();
 }

@@ -1,9 +1,12 @@
 // srhd_mlp.hpp -- learned initial guess for the Newton inversion: inference of a 3-64-64-1
 // perceptron with SiLU activations on the matrix cores of gfx950.
 //
-// Inputs are three log-scaled invariants of the conserved state, f = (log D, log max(|M|/D,
-// 1e-300), log(Et/D)), standardised with the training set's mean and deviation; the output is the
-// standardised log of the reduced enthalpy ht, the unknown of Eq. 15.
+// Inputs are three log-scaled invariants of the conserved state, standardised with the training
+// set's mean and deviation: f = (log D, log max(|M|/D, 1e-300), log(Et/D)) (feature set 0), or
+// f = (log L, log max(|M|/D, 1e-300), log(Et/D)) with L the left-hand side of Eq. 15 as the
+// inversion computes it (feature set 1).  The output is the standardised log of the reduced
+// enthalpy ht, the unknown of Eq. 15.  The network is consulted only for states with L above a
+// gate; the others keep the analytic guess.
 //
 // One call evaluates the network for the 64 states held by the 64 lanes of a wavefront (every
 // lane must be active).  Layer 1 (3 -> 64) is lane-local FP32.  Layer 2 (64 -> 64) runs on
@@ -30,6 +33,8 @@ struct MlpDev {
   const uint16_t *w;    // BF16 weights: W1[64][3], W2[64][64] (row = output unit), W3[64]
   const float *bias;    // b1[64], b2[64], b3
   const float *norm;    // mean_in[3], std_in[3], mean_out, std_out
+  int features;         // 0: log D first; 1: log L first
+  double gate;          // consulted for L > gate only
 };
 
 // SiLU(a) = a sigmoid(a) with the hardware exponential and reciprocal.
@@ -133,29 +138,39 @@ __device__ __forceinline__ float mlp_eval(const MlpDev &m, float f0, float f1, f
   return part + other + m.bias[MLP_B3];
 }
 
-// Features of a conserved state, the network's input before standardisation.  The ratios are
-// formed in double (|M| can exceed the FP32 range when squared); the logarithms in FP32.
-// log max(|M|/D, 1e-300) is taken as max(log(|M|/D), log 1e-300).
-__device__ __forceinline__ void mlp_features(double D, double Mx, double My, double Mz, double Et,
-                                             float &f0, float &f1, float &f2)
+// Natural logarithm of a positive double, in FP32 arithmetic over the whole double range: the
+// binary exponent is taken exactly and the log of the mantissa by the hardware log2.
+__device__ __forceinline__ float log_wide(double v)
 {
-  double iD = 1.0 / D;
-  double m = sqrt(Mx * Mx + My * My + Mz * Mz) * iD;
-  f0 = __logf((float)D);
-  if (m >= 1e-37) f1 = __logf((float)m);
-  else if (m > 1e-300) f1 = (float)log(m);               // below the FP32 normal range
-  else f1 = -690.77552789821368f;                        // log(1e-300): states at rest
-  f2 = __logf((float)(Et * iD));
+  int e;
+  const double mnt = frexp(v, &e);          // v = mnt 2^e, mnt in [0.5, 1)
+  return ((float)e + __log2f((float)mnt)) * 0.693147180559945309f;
 }
 
-// Guess of ht for this lane's state from the network (exp of the de-standardised output).
-__device__ __forceinline__ double mlp_guess(const MlpDev &m, double D, double Mx, double My,
-                                            double Mz, double Et)
+// Features of a conserved state, the network's input before standardisation; L is the
+// left-hand side of Eq. 15 (used by feature set 1).
+__device__ __forceinline__ void mlp_features(int set, double D, double Mx, double My, double Mz,
+                                             double Et, double L, float &f0, float &f1, float &f2)
 {
+  const double iD = 1.0 / D;
+  const double m = sqrt(Mx * Mx + My * My + Mz * Mz) * iD;
+  f0 = log_wide(set ? L : D);
+  f1 = m > 1e-300 ? log_wide(m) : -690.77552789821368f;     // log(1e-300): states at rest
+  f2 = log_wide(Et * iD);
+}
+
+// Guess of ht for this lane's state from the network (exp of the de-standardised output), or -1
+// where the network is not consulted (L at or below the gate, or L not admissible: pass L = 0).
+// The whole wavefront must call it; the network runs only if some lane needs it.
+__device__ __forceinline__ double mlp_guess(const MlpDev &m, double D, double Mx, double My,
+                                            double Mz, double Et, double L, bool &consulted)
+{
+  consulted = L > m.gate;
+  if (!__any(consulted)) return -1.0;
   float f0, f1, f2;
-  mlp_features(D, Mx, My, Mz, Et, f0, f1, f2);
-  float z = mlp_eval(m, f0, f1, f2);
-  return (double)__expf(m.norm[6] + m.norm[7] * z);
+  mlp_features(m.features, D, Mx, My, Mz, Et, L, f0, f1, f2);
+  const float z = mlp_eval(m, f0, f1, f2);
+  return consulted ? (double)__expf(m.norm[6] + m.norm[7] * z) : -1.0;
 }
 
 }  // namespace srhd

@@ -111,15 +111,23 @@ __device__ __forceinline__ Prim<T> load_prim(const Tile<T> &s, int b)
 __device__ __forceinline__ double L_of(const Cons<double> &u) { return lhs_L(u.D, u.m[0], u.m[1], u.m[2], u.E); }
 __device__ __forceinline__ double L_of(const Cons<float> &u) { return lhs_L_from_f32(u.D, u.m[0], u.m[1], u.m[2], u.E); }
 
+// Admissibility (Eq. 30) of a face state and its L (0 when not admissible).
 template <class T>
-__device__ __forceinline__ bool invert_face(const Cons<T> &u, Prim<T> &w, int &iters, int &status,
-                                            double guess, bool have_guess)
+__device__ __forceinline__ bool face_L(const Cons<T> &u, double &L)
 {
-  double D = u.D, Mx = u.m[0], My = u.m[1], Mz = u.m[2], Et = u.E;
-  bool ok = finiteT(D) && finiteT(Mx) && finiteT(My) && finiteT(Mz) && finiteT(Et) &&
-            D > 0.0 && Et > 0.0;
-  double L = ok ? L_of(u) : 0.0;
+  bool ok = finiteT(u.D) && finiteT(u.m[0]) && finiteT(u.m[1]) && finiteT(u.m[2]) &&
+            finiteT(u.E) && u.D > T(0) && u.E > T(0);
+  L = ok ? L_of(u) : 0.0;
   ok = ok && L > DBL_EPSILON;
+  if (!ok) L = 0.0;
+  return ok;
+}
+
+template <class T>
+__device__ __forceinline__ bool invert_face(const Cons<T> &u, bool ok, double L, Prim<T> &w,
+                                            int &iters, int &status, double guess, bool have_guess)
+{
+  double D = u.D, Mx = u.m[0], My = u.m[1], Mz = u.m[2];
   InvOut<double> o;
   if (ok) invert_with_L(D, Mx, My, Mz, L, guess, have_guess, StepTol<T>::v, 30, o);
   else set_unphysical(o);
@@ -164,8 +172,11 @@ __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, in
   u.E += s.C[4][hb];
   // the learned guess is evaluated by every lane of the wavefront (a wavefront handles one
   // direction and all its lanes are active here)
-  double guess = MLP ? mlp_guess(mlp, u.D, u.m[0], u.m[1], u.m[2], u.E) : -1.0;
-  return invert_face(u, w, iters, status, guess, MLP);
+  double L;
+  const bool ok = face_L(u, L);
+  bool consulted = false;
+  double guess = MLP ? mlp_guess(mlp, u.D, u.m[0], u.m[1], u.m[2], u.E, L, consulted) : -1.0;
+  return invert_face(u, ok, L, w, iters, status, guess, consulted);
 }
 
 struct IfaceCount {
@@ -294,9 +305,11 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
              Et = q[4 * N3 + off];
       double L;
       InvOut<double> o;
-      double guess = MLP ? mlp_guess(mlp, D, Mx, My, Mz, Et) : -1.0;
+      const bool adm = admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L);
+      bool consulted = false;
+      double guess = MLP ? mlp_guess(mlp, D, Mx, My, Mz, Et, (valid && adm) ? L : 0.0, consulted) : -1.0;
       if (!valid) continue;
-      if (admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L)) invert_with_L(D, Mx, My, Mz, L, guess, MLP, StepTol<T>::v, 30, o);
+      if (adm) invert_with_L(D, Mx, My, Mz, L, guess, consulted, StepTol<T>::v, 30, o);
       else set_unphysical(o);
       centre_bad |= o.status == ST_UNPHYSICAL;
       centre_unphys += o.status == ST_UNPHYSICAL;
@@ -414,8 +427,9 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
       if (GATHER) {
         // the updated cell's primitives and signal speed, for the next step
         InvOut<double> w;
-        double guess = MLP ? mlp_guess(mlp, un[0], un[1], un[2], un[3], un[4]) : -1.0;
-        if (ok_out) invert_with_L(un[0], un[1], un[2], un[3], Lo, guess, MLP, StepTol<T>::v, 30, w);
+        bool consulted = false;
+        double guess = MLP ? mlp_guess(mlp, un[0], un[1], un[2], un[3], un[4], ok_out ? Lo : 0.0, consulted) : -1.0;
+        if (ok_out) invert_with_L(un[0], un[1], un[2], un[3], Lo, guess, consulted, StepTol<T>::v, 30, w);
         else set_unphysical(w);
         my_iters += w.iters;
         my_inv += 1;
@@ -472,7 +486,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
 template <class T, bool GATHER, bool MLP>
 __device__ __forceinline__ void step_body(const StepArgs &a)
 {
-  const MlpDev mlp = {a.guess.w, a.guess.bias, a.guess.norm};
+  const MlpDev mlp = a.guess.dev();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Tile<T> &s = *reinterpret_cast<Tile<T> *>(smem_raw);
   if (!a.queue) {
@@ -536,9 +550,10 @@ __global__ void __launch_bounds__(256) k_grid_prims(int64_t n_patch, const doubl
     const double *u = cons + pp * 5 * 512 + c;
     double L;
     InvOut<double> w;
-    double guess = MLP ? mlp_guess(mlp, u[0], u[512], u[1024], u[1536], u[2048]) : -1.0;
     bool ok = admissible(u[0], u[512], u[1024], u[1536], u[2048], DBL_EPSILON, L);
-    if (ok) invert_with_L(u[0], u[512], u[1024], u[1536], L, guess, MLP, StepTol<T>::v, 30, w);
+    bool consulted = false;
+    double guess = MLP ? mlp_guess(mlp, u[0], u[512], u[1024], u[1536], u[2048], ok ? L : 0.0, consulted) : -1.0;
+    if (ok) invert_with_L(u[0], u[512], u[1024], u[1536], L, guess, consulted, StepTol<T>::v, 30, w);
     else set_unphysical(w);
     T *po = prims + pp * 5 * 512 + c;
     po[0] = (T)w.rho;
@@ -657,7 +672,7 @@ hipError_t launch_grid_prims(int prec, int64_t n_patch, const double *cons, void
     int64_t total = n_patch * 512;
     int blocks = (int)((total + 511) / 512);
     if (blocks > 256 * 64) blocks = 256 * 64;
-    MlpDev m = {g.w, g.bias, g.norm};
+    MlpDev m = g.dev();
     const bool mlp = g.kind == SRHD_GUESS_MLP;
     if (prec == SRHD_PREC_MIXED) {
       if (mlp) hipLaunchKernelGGL((k_grid_prims<float, true>), dim3(blocks), dim3(256), 0, st, n_patch, cons, (float *)prims, smax_bits, m);

@@ -4,12 +4,16 @@ Training states follow the conversion-batch distribution (rho log-uniform in [1e
 in [1e-8, 1e4], gamma in [1, 1e6], isotropic four-velocity), drawn on the device from a seeded
 generator.  Their conserved variables come from srhd_prim2cons; the label of each state is
 log ht of srhd_cons2prim applied to those stored conserved variables (not of the generating
-primitives, which differ from it by the conversion's round-off); unphysical states are dropped.
+primitives, which differ from it by the conversion's round-off); unphysical states are dropped,
+and so are states at or below the gate (L <= gate), where the network is never consulted.
 Features and labels are standardised with the training set's mean and deviation.  The loss is
 the mean squared error of the standardised output (srhd_mlp_grad); the optimiser is Adam
 (srhd_mlp_adam) with a cosine-decayed learning rate.
 
-    python -m paper_2012_11130_amd.mlp_train --out paper_2012_11130_amd/mlp_guess.npz
+Two networks are kept:
+    python -m paper_2012_11130_amd.mlp_train                      # log L features, gate 0.1
+    python -m paper_2012_11130_amd.mlp_train --features 0 --gate 0 \
+        --out paper_2012_11130_amd/mlp_guess_cons.npz              # (log D, ...) on every state
 """
 import argparse
 import math
@@ -23,6 +27,7 @@ from . import srhd as S
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_WEIGHTS = os.path.join(HERE, "mlp_guess.npz")
+CONS_WEIGHTS = os.path.join(HERE, "mlp_guess_cons.npz")
 
 
 def draw_states(n, seed, device):
@@ -44,8 +49,9 @@ def draw_states(n, seed, device):
     return prim
 
 
-def labelled_set(n, seed, device, chunk=1 << 22):
-    """Features float32 [3][m] and labels log ht float32 [m] of the physical states among n."""
+def labelled_set(n, seed, device, features=S.FEAT_L, gate=0.1, chunk=1 << 22):
+    """Features float32 [3][m] and labels log ht float32 [m] of the physical states with L > gate
+    among n draws (m <= n)."""
     feats, targets = [], []
     done = 0
     k = 0
@@ -55,7 +61,10 @@ def labelled_set(n, seed, device, chunk=1 << 22):
         cons = S.srhd_prim2cons(prim)
         w, st, _ = S.srhd_cons2prim(cons, status=True)
         ok = st == S.ST_OK
-        f, t = S.srhd_mlp_features(cons, prim=w)
+        f, t = S.srhd_mlp_features(cons, prim=w, features=features)
+        if gate > 0:
+            fl, _ = S.srhd_mlp_features(cons, features=S.FEAT_L)
+            ok &= fl[0].double() > math.log(gate)
         feats.append(f[:, ok])
         targets.append(t[ok])
         done += c
@@ -84,9 +93,9 @@ def split_params(master):
     return w, bias
 
 
-def make_mlp(master, norm):
+def make_mlp(master, norm, features, gate):
     w, bias = split_params(master)
-    return S.Mlp(w.contiguous(), bias.contiguous(), norm.contiguous())
+    return S.Mlp(w.contiguous(), bias.contiguous(), norm.contiguous(), features, gate)
 
 
 def test_loss(mlp, feat, target, std_out):
@@ -95,17 +104,17 @@ def test_loss(mlp, feat, target, std_out):
 
 
 def train(n_train=10_000_000, n_test=1_000_000, epochs=20, batch=8192, lr=1e-3, seed=2000,
-          device="cuda:0", log=print):
+          features=S.FEAT_L, gate=0.1, device="cuda:0", log=print):
     t0 = time.time()
     dev = torch.device(device)
-    feat, target = labelled_set(n_train, seed, dev)
-    tfeat, ttarget = labelled_set(n_test, seed + 1, dev)
+    feat, target = labelled_set(n_train, seed, dev, features, gate)
+    tfeat, ttarget = labelled_set(n_test, seed + 1, dev, features, gate)
     mu, sd = feat.mean(dim=1), feat.std(dim=1)
     norm = torch.cat([mu, sd, target.mean().reshape(1), target.std().reshape(1)]).float()
     master = torch.from_numpy(glorot(seed)).to(dev)
     m1 = torch.zeros_like(master)
     m2 = torch.zeros_like(master)
-    mlp = make_mlp(master, norm)
+    mlp = make_mlp(master, norm, features, gate)
     m = feat.shape[1]
     steps_per_epoch = m // batch
     total = steps_per_epoch * epochs
@@ -140,7 +149,7 @@ def train(n_train=10_000_000, n_test=1_000_000, epochs=20, batch=8192, lr=1e-3, 
     return {"w": mlp.w.cpu().numpy().view(np.uint16), "bias": mlp.bias.cpu().numpy(),
             "norm": norm.cpu().numpy(), "master": master.cpu().numpy(),
             "initial_test_loss": l0, "history": history, "n_train": m,
-            "seconds": time.time() - t0}
+            "seconds": time.time() - t0, "features": features, "gate": gate}
 
 
 def save(res, path):
@@ -148,7 +157,8 @@ def save(res, path):
              test_loss=np.array(res["history"]["test_loss"]),
              train_loss=np.array(res["history"]["train_loss"]),
              initial_test_loss=np.array([res["initial_test_loss"]]),
-             n_train=np.array([res["n_train"]]), seconds=np.array([res["seconds"]]))
+             n_train=np.array([res["n_train"]]), seconds=np.array([res["seconds"]]),
+             features=np.array([res["features"]]), gate=np.array([res["gate"]]))
 
 
 def load(path=DEFAULT_WEIGHTS, device="cuda:0"):
@@ -160,7 +170,9 @@ def load(path=DEFAULT_WEIGHTS, device="cuda:0"):
     w = torch.from_numpy(z["w"].view(np.int16).copy()).to(dev)
     bias = torch.from_numpy(z["bias"].astype(np.float32)).to(dev)
     norm = torch.from_numpy(z["norm"].astype(np.float32)).to(dev)
-    return S.Mlp(w, bias, norm)
+    features = int(z["features"][0]) if "features" in z.files else S.FEAT_CONS
+    gate = float(z["gate"][0]) if "gate" in z.files else 0.0
+    return S.Mlp(w, bias, norm, features, gate)
 
 
 def main():
@@ -171,8 +183,11 @@ def main():
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--features", type=int, default=S.FEAT_L, choices=(S.FEAT_CONS, S.FEAT_L))
+    ap.add_argument("--gate", type=float, default=0.1,
+                    help="train on, and consult the network for, states with L > gate only")
     a = ap.parse_args()
-    res = train(a.n_train, a.n_test, a.epochs, a.batch, a.lr)
+    res = train(a.n_train, a.n_test, a.epochs, a.batch, a.lr, features=a.features, gate=a.gate)
     save(res, a.out)
     print("# saved", a.out, flush=True)
 

@@ -22,6 +22,7 @@ F64, F32 = 0, 1
 OK, EINVAL, EHIP, EUNSUPPORTED = 0, -1, -2, -3
 ST_OK, ST_UNPHYSICAL, ST_FALLBACK, ST_NOCONV = 0, 1, 2, 3
 GUESS_ANALYTIC, GUESS_MLP = 0, 1
+FEAT_CONS, FEAT_L = 0, 1
 HLLC, HLLE = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 MAX_LEVEL = 8
@@ -32,7 +33,8 @@ _int = ctypes.c_int
 
 
 class srhd_mlp(ctypes.Structure):
-    _fields_ = [("w_bf16", _vp), ("bias", _vp), ("norm", _vp)]
+    _fields_ = [("w_bf16", _vp), ("bias", _vp), ("norm", _vp), ("features", _int),
+                ("gate_L", ctypes.c_double)]
 
 
 class srhd_guess(ctypes.Structure):
@@ -85,7 +87,7 @@ _sig = {
     "srhd_fluid_step": [ctypes.POINTER(srhd_patches), _vp, _vp,
                         ctypes.POINTER(srhd_step_params), _vp, _vp],
     "srhd_grid_prims": [_int, _i64, _vp, _vp, _vp, ctypes.POINTER(srhd_guess), _vp],
-    "srhd_mlp_features": [_int, _i64, _vp, _vp, _vp, _vp, _vp],
+    "srhd_mlp_features": [_int, _int, _i64, _vp, _vp, _vp, _vp, _vp],
     "srhd_mlp_forward": [ctypes.POINTER(srhd_mlp), _i64, _vp, _vp, _vp],
     "srhd_mlp_grad": [ctypes.POINTER(srhd_mlp), _i64, _vp, _vp, _vp, _vp, _vp, _vp],
     "srhd_mlp_adam": [_vp, _vp, _vp, _vp, _int, ctypes.c_float, _vp, _vp, _vp],
@@ -414,14 +416,17 @@ class Mlp:
     """Device parameters of the learned guess plus the ctypes descriptors that point at them.
 
     w: uint16 BF16 weights [4352] (W1[64][3], W2[64][64], W3[64]); bias: float32 [129];
-    norm: float32 [8] (input mean[3], input std[3], output mean, output std)."""
+    norm: float32 [8] (input mean[3], input std[3], output mean, output std); features: FEAT_CONS
+    or FEAT_L; gate: the network is consulted for states with L > gate only."""
 
-    def __init__(self, w, bias, norm):
+    def __init__(self, w, bias, norm, features=FEAT_CONS, gate=0.0):
         self.w, self.bias, self.norm = w, bias, norm
+        self.features, self.gate = int(features), float(gate)
         _need_cuda(w, bias, norm)
         if w.data_ptr() % 16:
             raise ValueError("weights must be 16-byte aligned")
-        self.desc = srhd_mlp(w.data_ptr(), bias.data_ptr(), norm.data_ptr())
+        self.desc = srhd_mlp(w.data_ptr(), bias.data_ptr(), norm.data_ptr(), self.features,
+                             self.gate)
 
     def guess(self, max_iter=0):
         g = srhd_guess(GUESS_MLP, ctypes.pointer(self.desc), max_iter)
@@ -429,7 +434,7 @@ class Mlp:
         return g
 
 
-def srhd_mlp_features(cons, prim=None, feat=None, target=None):
+def srhd_mlp_features(cons, prim=None, feat=None, target=None, features=FEAT_CONS):
     """cons [5][n] (and optionally prim [5][n]) -> feat float32 [3][n] (and target log ht [n])."""
     _need_cuda(cons, prim)
     n = cons.shape[-1]
@@ -437,8 +442,8 @@ def srhd_mlp_features(cons, prim=None, feat=None, target=None):
         feat = torch.empty((3, n), dtype=torch.float32, device=cons.device)
     if prim is not None and target is None:
         target = torch.empty(n, dtype=torch.float32, device=cons.device)
-    _check(_lib.srhd_mlp_features(_dtype_code(cons), n, _ptr(cons), _ptr(prim), _ptr(feat),
-                                  _ptr(target), _stream()))
+    _check(_lib.srhd_mlp_features(_dtype_code(cons), int(features), n, _ptr(cons), _ptr(prim),
+                                  _ptr(feat), _ptr(target), _stream()))
     return feat, target
 
 

@@ -23,13 +23,13 @@ def S():
     return srhd
 
 
-def _net(S, theta, norm):
+def _net(S, theta, norm, features=0, gate=0.0):
     """Device parameters for a flat FP64 parameter vector (BF16 weights as the kernels read)."""
     p = M.unpack(theta)
     w = np.concatenate([p["W1"].ravel(), p["W2"].ravel(), p["W3"].ravel()]).astype(np.float32)
     wb = torch.from_numpy(w).to(torch.bfloat16).view(torch.int16).to(DEV)
     b = torch.from_numpy(np.concatenate([p["b1"], p["b2"], p["b3"]]).astype(np.float32)).to(DEV)
-    return S.Mlp(wb.contiguous(), b, torch.tensor(norm, dtype=torch.float32, device=DEV))
+    return S.Mlp(wb.contiguous(), b, torch.tensor(norm, dtype=torch.float32, device=DEV), features, gate)
 
 
 def _rand_theta(seed):
@@ -100,6 +100,19 @@ def test_adam_matches_formula(S):
     assert np.allclose(wb[:192], M.bf16(ref[:192]), rtol=0, atol=0)
 
 
+@pytest.mark.parametrize("kind", [0, 1])
+def test_features_match_reference(S, kind):
+    prim = W.conversion_batch(100_000, seed=44)
+    cons = O.prim2cons(prim)
+    cons[:, :50] = cons[:, 50:100] * np.array([[1.0], [1.0], [1.0], [1.0], [-1.0]])   # Et < 0
+    ref = M.features(cons, kind)
+    got, _ = S.srhd_mlp_features(torch.from_numpy(cons).to(DEV), features=kind)
+    got = got.cpu().numpy().astype(np.float64)
+    fin = np.isfinite(ref)
+    assert np.array_equal(fin, np.isfinite(got))
+    assert np.all(np.abs(got[fin] - ref[fin]) <= 2e-6 * (1 + np.abs(ref[fin])))
+
+
 def test_learned_guess_never_changes_the_inversion(S):
     # a (random, untrained) network as the first guess: Newton + analytic fallback must return
     # the same primitives as the analytic guess alone, within the parity tolerance
@@ -133,6 +146,27 @@ def test_poisoned_network_falls_back_everywhere(S):
     assert max(prim_errors(w.cpu().numpy(), ref, ok).values()) <= 1e-12
 
 
+@pytest.mark.parametrize("kind,gate", [(0, 0.0), (1, 0.1)])
+def test_gated_guess_never_changes_the_inversion(S, kind, gate):
+    # a random network consulted only above the gate: results as with the analytic guess, and
+    # states at or below the gate never report a fallback
+    prim = W.conversion_batch(50_000, seed=45)
+    cons = O.prim2cons(prim)
+    ref, st_ref, _ = O.cons2prim(cons)
+    f = M.features(cons, kind)
+    good = np.isfinite(f).all(axis=0)
+    norm = np.concatenate([f[:, good].mean(axis=1), f[:, good].std(axis=1), [-5.0, 8.0]])
+    net = _net(S, _rand_theta(6), norm, kind, gate)
+    w, st, _ = S.srhd_cons2prim(torch.from_numpy(cons).to(DEV), status=True, guess=net.guess())
+    w, st = w.cpu().numpy(), st.cpu().numpy()
+    bad = st_ref == O.ST_UNPHYSICAL
+    assert np.array_equal(st == S.ST_UNPHYSICAL, bad)
+    assert max(prim_errors(w, ref, ~bad).values()) <= 1e-12
+    L = O.L_batch(cons)
+    if gate > 0:
+        assert not np.any(st[(L <= gate) & ~bad] == S.ST_FALLBACK)
+
+
 def test_step_with_learned_guess_matches_oracle(S):
     # the 64^3 blast, one step of the gather path with the network guessing every inversion
     from tests.parity import oracle_cons, step_errors
@@ -140,12 +174,12 @@ def test_step_with_learned_guess_matches_oracle(S):
     cons = oracle_cons(g)
     f = M.features(O.prim2cons(W.conversion_batch(20_000, seed=43)))
     norm = np.concatenate([f.mean(axis=1), f.std(axis=1), [-5.0, 8.0]])
-    net = _net(S, _rand_theta(5), norm)
     c = torch.from_numpy(cons).to(DEV)
     nb = torch.from_numpy(g.neighbor).to(DEV)
     dt_o, _, _ = O.cfl_dt(cons, None, g.dh_lev, 0.5)
     ref, _ = O.fluid_step(O.fill_ghosts(cons, g.neighbor, 3), dt_o, g.dh_lev)
-    for prec in (0, 1):
+    for prec, kind, gate in ((0, 0, 0.0), (1, 0, 0.0), (0, 1, 0.1), (1, 1, 0.1)):
+        net = _net(S, _rand_theta(5), norm, kind, gate)
         prims, smax = S.srhd_grid_prims(c, prec=prec, guess=net.guess())
         st = S.new_stats(DEV)
         out, _, _ = S.srhd_fluid_step_grid(c, prims, nb, g.dh_lev, dt_lev=torch.from_numpy(dt_o).to(DEV),

@@ -293,6 +293,8 @@ def jet_patch_list(n_patch=400_000, n_base=256, fractions=(0.05, 0.10, 0.25, 0.6
         zz = np.arange(nzp)
         score = rr[:, None] + 0.25 * (zz[None, :] + 0.5) / nzp
         score = score + 0.02 * rng.random(score.shape) / npl
+        if score.size < cnt:
+            raise ValueError("level %d holds %d candidate patches, %d requested" % (lv, score.size, cnt))
         flat = np.argsort(score, axis=None, kind="stable")[:cnt]
         a, b = np.unravel_index(flat, score.shape)
         c = np.stack([gx[a], gy[a], zz[b]], axis=1) * PS
