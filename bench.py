@@ -414,7 +414,23 @@ def main():
                                                 "stats": st_c}
             res["newton"]["mixed_learned_cons_inputs"] = newton_summary(st_c)
 
-    # per-field difference of one mixed step against one FP64 step from the same state
+    # the FP32-inversion mode (FP32 Newton after the exact FP64 L) with the headline's guess
+    ms_32, kms_32, st_32, fin_32 = measure(S.PREC_FP32, guess, "fp32_inversion")
+    print("# fp32 inversion, %s guess: %.2f ms for %d steps (step kernel %.3f ms avg); stats %s"
+          % (guess_name, ms_32, args.steps, float(np.mean(kms_32)), st_32), file=sys.stderr, flush=True)
+    res["fp32_inversion"] = {"value": n_cells * args.steps / (ms_32 * 1e-3), "ms_per_step": ms_32 / args.steps,
+                             "step_kernel_ms": float(np.mean(kms_32)), "stats": st_32,
+                             "guess": guess_name}
+    res["newton"]["fp32_inversion"] = newton_summary(st_32)
+
+    def field_err(x, ref):
+        ms = max(float(np.max(np.sqrt((ref[:, 1:4] ** 2).sum(axis=1)))), 1e-300)
+        return {"D": float(np.max(np.abs(x[:, 0] / ref[:, 0] - 1))),
+                "Et": float(np.max(np.abs(x[:, 4] / ref[:, 4] - 1))),
+                "M": float(np.max(np.abs(x[:, 1:4] - ref[:, 1:4]))) / ms}
+
+    # per-field difference of one FP32-bulk step against one FP64 step from the same state, and
+    # after the timed run (each from its own state)
     if not args.no_fp64:
         ms_64, kms_64, st_64, fin_64 = measure(S.PREC_FP64, None, "fp64")
         print("# fp64: %.2f ms for %d steps (step kernel %.3f ms avg); stats %s"
@@ -423,19 +439,16 @@ def main():
         S.srhd_fill_ghosts(cons0, nb, 3, padded=pad)
         o64 = S.srhd_fluid_step(pad, dt, dh, prec=S.PREC_FP64).cpu().numpy()
         omx = S.srhd_fluid_step(pad, dt, dh, prec=S.PREC_MIXED, guess=guess).cpu().numpy()
-        mscale = max(float(np.max(np.sqrt((o64[:, 1:4] ** 2).sum(axis=1)))), 1e-300)
-        err1 = {"D": float(np.max(np.abs(omx[:, 0] / o64[:, 0] - 1))),
-                "Et": float(np.max(np.abs(omx[:, 4] / o64[:, 4] - 1))),
-                "M": float(np.max(np.abs(omx[:, 1:4] - o64[:, 1:4]))) / mscale}
-        a, b = fin_mx.cpu().numpy(), fin_64.cpu().numpy()
-        ms2 = max(float(np.max(np.sqrt((b[:, 1:4] ** 2).sum(axis=1)))), 1e-300)
-        errK = {"D": float(np.max(np.abs(a[:, 0] / b[:, 0] - 1))),
-                "Et": float(np.max(np.abs(a[:, 4] / b[:, 4] - 1))),
-                "M": float(np.max(np.abs(a[:, 1:4] - b[:, 1:4]))) / ms2}
+        o32 = S.srhd_fluid_step(pad, dt, dh, prec=S.PREC_FP32, guess=guess).cpu().numpy()
+        b = fin_64.cpu().numpy()
         res["fp64"] = {"value": n_cells * args.steps / (ms_64 * 1e-3), "ms_per_step": ms_64 / args.steps,
                        "step_kernel_ms": float(np.mean(kms_64)), "stats": st_64}
         res["newton"]["fp64"] = newton_summary(st_64)
-        res["mixed_vs_fp64_rel_err"] = {"one_step": err1, "after_%d_steps" % args.steps: errK}
+        res["mixed_vs_fp64_rel_err"] = {"one_step": field_err(omx, o64),
+                                        "after_%d_steps" % args.steps: field_err(fin_mx.cpu().numpy(), b)}
+        res["fp32_inversion"]["vs_fp64_rel_err"] = {
+            "one_step": field_err(o32, o64),
+            "after_%d_steps" % args.steps: field_err(fin_32.cpu().numpy(), b)}
 
     # ---------------------------------------------------------------- roofline of the step kernel
     kavg = float(np.mean(kms_mx)) * 1e-3

@@ -52,8 +52,11 @@ enum {
 typedef enum { SRHD_GUESS_ANALYTIC = 0, SRHD_GUESS_MLP = 1 } srhd_guess_kind;
 typedef enum { SRHD_HLLC = 0, SRHD_HLLE = 1 } srhd_riemann;
 /* FP64: every stage in FP64.  MIXED: reconstruction, fluxes and the update increment in FP32;
- * the left-hand side L of Eq. 15 and the Newton inversion in FP64 (state storage stays FP64). */
-typedef enum { SRHD_PREC_FP64 = 0, SRHD_PREC_MIXED = 1 } srhd_prec;
+ * the left-hand side L of Eq. 15 and the Newton inversion in FP64.  FP32: reconstruction,
+ * fluxes, update increment and the Newton inversion in FP32; only the subtraction inside L
+ * (the cancellation of Eq. 20) is formed in FP64, exactly, from the FP32 variables.  State
+ * storage stays FP64 in every mode. */
+typedef enum { SRHD_PREC_FP64 = 0, SRHD_PREC_MIXED = 1, SRHD_PREC_FP32 = 2 } srhd_prec;
 
 /* Learned initial guess: device parameters of a 3-64-64-1 SiLU perceptron that maps three
  * standardised log-scaled invariants of the conserved state to the standardised log of the
@@ -144,7 +147,8 @@ int srhd_cfl_dt(int dtype, int64_t n_patch, const void *interior, int n_level,
  * call on its stream; calls in flight at the same time must not share it.
  * occupancy: 0 selects the step kernel compiled for its natural register budget; 2 selects a
  * variant compiled for at most 128 VGPRs per lane so that two 512-thread workgroups share a
- * compute unit (mixed precision with the analytic guess only: otherwise SRHD_EUNSUPPORTED). */
+ * compute unit (an FP32 bulk, i.e. SRHD_PREC_MIXED or SRHD_PREC_FP32, only: otherwise
+ * SRHD_EUNSUPPORTED). */
 #define SRHD_QUEUE_WORDS 8
 typedef struct {
   int groups;              /* 0, or 1 .. 65535 persistent workgroups */
@@ -195,8 +199,8 @@ int srhd_step_occupancy(int prec, int guess_kind, int gather, int occupancy);
 /* Schedule autotuner for srhd_fluid_step.  Runs the step on `in` (writing `out`) once per
  * candidate schedule as a warm-up and then `reps` timed times, timed with events on `stream`,
  * and writes the fastest candidate into prm->sched (keeping prm->sched.queue, which must be
- * set).  Candidates, for each register variant the precision and guess allow (occupancy 0, and 2
- * for mixed precision with the analytic guess): one workgroup per patch, and persistent grids of
+ * set).  Candidates, for each register variant the precision allows (occupancy 0, and 2 for
+ * an FP32 bulk): one workgroup per patch, and persistent grids of
  * 1, 2 and 4 times the resident workgroups (srhd_step_occupancy x compute units) with chunk 1, 2
  * and 4.  table (host, may be NULL) receives up to table_cap entries {groups, chunk, occupancy,
  * ms per step} in trial order and *n_table their number.  Unlike the other calls this one
@@ -224,7 +228,8 @@ typedef struct {
   int64_t n_patch;
   const double *cons;      /* [n_patch][5][8][8][8] FP64 conserved interiors */
   const void *prims;       /* [n_patch][5][8][8][8] primitives of `cons` in the step's bulk type:
-                              float for SRHD_PREC_MIXED, double for SRHD_PREC_FP64 */
+                              float for SRHD_PREC_MIXED and SRHD_PREC_FP32, double for
+                              SRHD_PREC_FP64 */
   const int32_t *neighbor; /* [n_patch][27] int32, as for srhd_fill_ghosts (indices < n_patch) */
   const int8_t *level;     /* [n_patch] or NULL */
   int n_level;

@@ -67,8 +67,8 @@ int check_sched(const srhd_sched &sc, int prec, int guess_kind, srhd::StepArgs &
   if (sc.occupancy != 0 && sc.occupancy != 2)
     return fail(SRHD_EINVAL, "%s: sched.occupancy %d is neither 0 nor 2", who, sc.occupancy);
   if (sc.occupancy == 2) {
-    if (prec != SRHD_PREC_MIXED || guess_kind != SRHD_GUESS_ANALYTIC)
-      return fail(SRHD_EUNSUPPORTED, "%s: sched.occupancy 2 needs mixed precision and the analytic guess", who);
+    if (prec == SRHD_PREC_FP64)
+      return fail(SRHD_EUNSUPPORTED, "%s: sched.occupancy 2 needs an FP32 bulk", who);
     s.occ2 = 1;
   }
   if (sc.groups == 0) return SRHD_OK;
@@ -184,7 +184,7 @@ int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
   if (in->n_level < 1 || in->n_level > SRHD_MAX_LEVEL)
     return fail(SRHD_EINVAL, "srhd_fluid_step: n_level %d not in [1, %d]", in->n_level, SRHD_MAX_LEVEL);
   if (in->n_patch > 0x7fffffffLL) return fail(SRHD_EINVAL, "srhd_fluid_step: too many patches");
-  if (prm->prec != SRHD_PREC_FP64 && prm->prec != SRHD_PREC_MIXED)
+  if (prm->prec != SRHD_PREC_FP64 && prm->prec != SRHD_PREC_MIXED && prm->prec != SRHD_PREC_FP32)
     return fail(SRHD_EINVAL, "srhd_fluid_step: bad precision %d", prm->prec);
   if (prm->riemann != SRHD_HLLC && prm->riemann != SRHD_HLLE)
     return fail(SRHD_EINVAL, "srhd_fluid_step: bad Riemann solver %d", prm->riemann);
@@ -240,14 +240,14 @@ int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
 
 int srhd_step_occupancy(int prec, int guess_kind, int gather, int occupancy)
 {
-  if (prec != SRHD_PREC_FP64 && prec != SRHD_PREC_MIXED)
+  if (prec != SRHD_PREC_FP64 && prec != SRHD_PREC_MIXED && prec != SRHD_PREC_FP32)
     return fail(SRHD_EINVAL, "srhd_step_occupancy: bad precision %d", prec);
   if (guess_kind != SRHD_GUESS_ANALYTIC && guess_kind != SRHD_GUESS_MLP)
     return fail(SRHD_EINVAL, "srhd_step_occupancy: unknown guess kind %d", guess_kind);
   if (occupancy != 0 && occupancy != 2)
     return fail(SRHD_EINVAL, "srhd_step_occupancy: occupancy %d is neither 0 nor 2", occupancy);
-  if (occupancy == 2 && (prec != SRHD_PREC_MIXED || guess_kind != SRHD_GUESS_ANALYTIC))
-    return fail(SRHD_EUNSUPPORTED, "srhd_step_occupancy: occupancy 2 needs mixed precision and the analytic guess");
+  if (occupancy == 2 && prec == SRHD_PREC_FP64)
+    return fail(SRHD_EUNSUPPORTED, "srhd_step_occupancy: occupancy 2 needs an FP32 bulk");
   int n = srhd::step_occupancy(prec, gather != 0, guess_kind == SRHD_GUESS_MLP, occupancy == 2);
   if (n <= 0) return fail(SRHD_EHIP, "srhd_step_occupancy: occupancy query failed");
   return n;
@@ -273,7 +273,7 @@ int autotune(srhd_step_params *prm, int gather, int reps, srhd_tune_entry *table
   struct Cand { int groups, chunk, occ; };
   Cand cand[20];
   int nc = 0;
-  const bool two = prm->prec == SRHD_PREC_MIXED && prm->guess.kind == SRHD_GUESS_ANALYTIC;
+  const bool two = prm->prec != SRHD_PREC_FP64;
   for (int occ : {0, 2}) {
     if (occ == 2 && !two) continue;
     int per_cu = srhd_step_occupancy(prm->prec, prm->guess.kind, gather, occ);
@@ -355,12 +355,12 @@ int srhd_grid_prims(int prec, int64_t n_patch, const double *cons, void *prims,
   srhd::GuessArgs g;
   int rc = check_guess(guess, g);
   if (rc) return rc;
-  if (prec != SRHD_PREC_FP64 && prec != SRHD_PREC_MIXED)
+  if (prec != SRHD_PREC_FP64 && prec != SRHD_PREC_MIXED && prec != SRHD_PREC_FP32)
     return fail(SRHD_EINVAL, "srhd_grid_prims: bad precision %d", prec);
   if (n_patch < 0) return fail(SRHD_EINVAL, "srhd_grid_prims: n_patch < 0");
   if (!smax_bits || (n_patch > 0 && (!cons || !prims)))
     return fail(SRHD_EINVAL, "srhd_grid_prims: NULL argument");
-  size_t ps = prec == SRHD_PREC_MIXED ? 4 : 8;
+  size_t ps = prec == SRHD_PREC_FP64 ? 8 : 4;
   if (!aligned(cons, 8) || !aligned(prims, ps) || !aligned(smax_bits, 8))
     return fail(SRHD_EINVAL, "srhd_grid_prims: misaligned array");
   const char *a = (const char *)cons, *b = (const char *)prims;
@@ -446,7 +446,7 @@ int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_
     return fail(SRHD_EINVAL, "srhd_fluid_step_grid: too many patches");
   if (in->n_level < 1 || in->n_level > SRHD_MAX_LEVEL)
     return fail(SRHD_EINVAL, "srhd_fluid_step_grid: n_level %d not in [1, %d]", in->n_level, SRHD_MAX_LEVEL);
-  if (prm->prec != SRHD_PREC_FP64 && prm->prec != SRHD_PREC_MIXED)
+  if (prm->prec != SRHD_PREC_FP64 && prm->prec != SRHD_PREC_MIXED && prm->prec != SRHD_PREC_FP32)
     return fail(SRHD_EINVAL, "srhd_fluid_step_grid: bad precision %d", prm->prec);
   if (prm->riemann != SRHD_HLLC && prm->riemann != SRHD_HLLE)
     return fail(SRHD_EINVAL, "srhd_fluid_step_grid: bad Riemann solver %d", prm->riemann);
@@ -462,7 +462,7 @@ int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_
     return fail(SRHD_EINVAL, "srhd_fluid_step_grid: need dt_lev, or smax_in and c_cfl > 0");
   for (int l = 0; l < in->n_level; ++l)
     if (!(in->dh[l] > 0.0)) return fail(SRHD_EINVAL, "srhd_fluid_step_grid: dh[%d] must be positive", l);
-  size_t ps = prm->prec == SRHD_PREC_MIXED ? 4 : 8;
+  size_t ps = prm->prec == SRHD_PREC_FP64 ? 8 : 4;
   if (in->n_patch > 0) {
     if (!in->cons || !in->prims || !in->neighbor || !cons_out || !prims_out)
       return fail(SRHD_EINVAL, "srhd_fluid_step_grid: NULL array");

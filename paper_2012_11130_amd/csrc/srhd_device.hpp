@@ -132,9 +132,16 @@ template <class T>
 __device__ __forceinline__ T guess_analytic(T L, T m2)
 {
   T a = T(1) + m2;
-  T thr = dv(T(1800) * a, T(437) * m2 + T(117));
-  thr *= thr;
-  if (L > thr) return T(4.0 / 3.0) * sq(L);
+  bool hot;
+  if constexpr (sizeof(T) == 8) {
+    // L > (1800 a / c)^2 with c = 437 m^2 + 117, without the division (no overflow in double)
+    T c = T(437) * m2 + T(117), u = T(1800) * a;
+    hot = L * c * c > u * u;
+  } else {
+    T thr = dv(T(1800) * a, T(437) * m2 + T(117));
+    hot = L > thr * thr;
+  }
+  if (hot) return T(4.0 / 3.0) * sq(L);
   T b = T(43) * m2 + T(63);
   return dv(T(125) * a * L, T(75) * a + sq(T(125) * a * b * L + T(5625) * a * a));
 }
@@ -154,16 +161,29 @@ __device__ __forceinline__ bool newton_htilde(T L, T m2, T x, T tol, int max_ite
 {
   for (int it = 1; it <= max_iter; ++it) {
     T h = x + T(1);
-    T s = sq(T(9) * h * h + T(16));
-    T iden = dv(T(1), T(5) * h + s);
-    T th = T(2) * x * (x + T(2)) * iden;
-    T dth = (T(4) * h - th * (T(5) + dv(T(9) * h, s))) * iden;
     T h2 = h * h;
-    T iq = dv(T(1), h2 + m2);
+    T s2 = T(9) * h2 + T(16);
+    T s = sq(s2);
+    T iden, iq, is;
+    if constexpr (sizeof(T) == 8) {
+      // one division for 1/den, 1/q and 1/s: the product den q s^2 stays far inside the double
+      // range for any iterate that can still converge (an overflow ends in a non-finite step)
+      T den = T(5) * h + s, q = h2 + m2;
+      T inv = dv(T(1), den * q * s2);
+      iden = q * s2 * inv;
+      iq = den * s2 * inv;
+      is = s * den * q * inv;
+    } else {
+      iden = dv(T(1), T(5) * h + s);
+      iq = dv(T(1), h2 + m2);
+      is = dv(T(1), s);
+    }
+    T th = T(2) * x * (x + T(2)) * iden;
+    T dth = (T(4) * h - th * (T(5) + T(9) * h * is)) * iden;
     T r = h2 * iq;
-    T omr = m2 * iq;
     T f = x * (x + T(2)) - T(2) * th * h + th * th * r;
-    T fp = T(2) * (h - th - h * dth + th * dth * r + dv(th * th * r * omr, h));
+    // the last term of Eq. A1, Theta^2 r (m^2/q) / h, is Theta^2 h m^2 / q^2
+    T fp = T(2) * (h - th - h * dth + th * dth * r + th * th * h * m2 * iq * iq);
     T dx = dv(f - L, fp);
     x -= dx;
     if (!(x > T(0)) || !finiteT(x)) { iters = it; ht = x; return false; }
@@ -193,8 +213,17 @@ __device__ __forceinline__ void recover(T D, T Mx, T My, T Mz, T ht, InvOut<T> &
   o.uy = My * iDh;
   o.uz = Mz * iDh;
   T gam = sq(T(1) + o.ux * o.ux + o.uy * o.uy + o.uz * o.uz);
-  o.rho = dv(D, gam);
-  o.p = o.rho * theta_of_htilde(ht);
+  if constexpr (sizeof(T) == 8) {
+    // rho = D / gamma and Theta of Eq. 16 share one division
+    T h = ht + T(1);
+    T den = T(5) * h + sq(T(9) * h * h + T(16));
+    T inv = dv(T(1), gam * den);
+    o.rho = D * den * inv;
+    o.p = o.rho * (T(2) * ht * (ht + T(2)) * gam * inv);
+  } else {
+    o.rho = dv(D, gam);
+    o.p = o.rho * theta_of_htilde(ht);
+  }
   o.ht = ht;
 }
 

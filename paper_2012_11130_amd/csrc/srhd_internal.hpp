@@ -66,6 +66,17 @@ struct StepArgs {
 };
 
 hipError_t launch_step(int prec, const StepArgs &a, hipStream_t s);
+
+// per-precision launchers of the step (srhd_step_fp64.hip, srhd_step_mixed.hip, srhd_step_fp32.hip)
+#define SRHD_STEP_MODE(name)                                                                   \
+  hipError_t step_launch_##name(const StepArgs &a, bool gather, hipStream_t st);               \
+  int step_occupancy_##name(bool gather, bool mlp, bool occ2);                                 \
+  hipError_t grid_prims_##name(int64_t n_patch, const double *cons, void *prims,               \
+                               unsigned long long *smax_bits, const GuessArgs &g, hipStream_t st);
+SRHD_STEP_MODE(fp64)
+SRHD_STEP_MODE(mixed)
+SRHD_STEP_MODE(fp32)
+#undef SRHD_STEP_MODE
 int step_occupancy(int prec, bool gather, bool mlp, bool occ2);   // workgroups per CU, 0 on error
 
 size_t mlp_workspace_bytes(int64_t batch);

@@ -1,0 +1,701 @@
+// srhd_step_impl.hpp -- one unsplit MUSCL-Hancock step (Sec. 3.2) of a batch of padded 8^3 patches
+// on gfx950: one workgroup of 512 threads (8 wavefronts) per patch, with the patch's
+// primitive tile, half-step corrections and interface fluxes staged in LDS.
+//
+// Work per patch (interior coordinates i in [0, 8); ghosts at -1, -2, 8, 9 are used):
+//   A. cell-centre inversions of the 1376 cells the stencil touches       -> LDS W (12^3 box)
+//   B. for the 896 cells whose face states the full step needs (the interior and the first
+//      ghost layer across each face): PLM slopes in x, y, z, the six face states, their
+//      conserved variables and physical fluxes, and the half-step correction
+//      C = -(dt / 2dh) sum_d [F_d(W_{d,+}) - F_d(W_{d,-})]                  -> LDS C (10^3 box)
+//   C. for the 3 x 576 interfaces: the two half-step face states U(W_face) + C, their
+//      inversions, and the HLLC / HLLE flux                                  -> LDS F (ring)
+//   D. the full update U^{n+1} = U^n - (dt/dh) sum_d (F_{+1/2} - F_{-1/2}) with the Eq. 30
+//      check of every output cell.
+// Phase C runs over the flat list of 1728 interfaces in rounds of 512; a two-direction ring
+// buffer of fluxes lets each thread fold a direction's flux differences into its own cell as
+// soon as that direction is complete (x after round 1, y after round 2, z after round 3).
+// If any half-step face state or output cell is unphysical, the whole patch repeats B-D with
+// theta *= 0.75 (max_retry times), then theta = 0 (Sec. 3.4); A is not repeated.
+#pragma once
+#include <float.h>
+
+#include "srhd_device.hpp"
+#include "srhd_internal.hpp"
+
+namespace srhd {
+namespace {
+
+constexpr int NT = 512;          // threads per workgroup (one per interior cell)
+constexpr int BX = 12;           // primitive box [-2, 10)^3
+constexpr int NB = BX * BX * BX;
+constexpr int HX = 10;           // half-step box [-1, 9)^3
+constexpr int NHB = HX * HX * HX;
+constexpr int NPC = 1376;        // centre inversions per patch
+constexpr int NHC = 896;         // half-step cells per patch
+constexpr int NIF = 576;         // interfaces per direction (9 x 8 x 8)
+
+constexpr bool in_half(int i, int j, int k)
+{
+  int c[3] = {i, j, k};
+  int out = 0;
+  for (int d = 0; d < 3; ++d) {
+    if (c[d] >= 0 && c[d] < 8) continue;
+    if (c[d] == -1 || c[d] == 8) ++out;
+    else return false;
+  }
+  return out <= 1;
+}
+
+constexpr bool in_prim(int i, int j, int k)
+{
+  return in_half(i, j, k) || in_half(i - 1, j, k) || in_half(i + 1, j, k) ||
+         in_half(i, j - 1, k) || in_half(i, j + 1, k) || in_half(i, j, k - 1) ||
+         in_half(i, j, k + 1);
+}
+
+struct Tables {
+  uint16_t pcell[NPC];   // 12-box index of each centre cell, increasing (x fastest)
+  uint16_t hcell[NHC];   // 10-box index of each half-step cell, increasing
+};
+
+constexpr Tables make_tables()
+{
+  Tables t{};
+  int np = 0, nh = 0;
+  for (int k = -2; k < 10; ++k)
+    for (int j = -2; j < 10; ++j)
+      for (int i = -2; i < 10; ++i) {
+        if (in_prim(i, j, k)) t.pcell[np++] = (uint16_t)(((k + 2) * BX + (j + 2)) * BX + (i + 2));
+        if (in_half(i, j, k)) t.hcell[nh++] = (uint16_t)(((k + 1) * HX + (j + 1)) * HX + (i + 1));
+      }
+  return t;
+}
+
+constexpr Tables kTabInit = make_tables();
+static_assert(kTabInit.pcell[NPC - 1] != 0 && kTabInit.hcell[NHC - 1] != 0, "cell tables");
+__constant__ Tables kTab = kTabInit;
+
+// Newton tolerance by (bulk type T, inversion type I): FP64 to ~2^-54; an FP64 inversion whose
+// result is consumed in FP32 to ~2^-28; an FP32 inversion to FP32 accuracy.
+template <class T, class I> struct StepTol;
+template <> struct StepTol<double, double> { static constexpr double v = 0x1p-27; };
+template <> struct StepTol<float, double> { static constexpr double v = 0x1p-14; };
+template <> struct StepTol<float, float> { static constexpr double v = 0x1p-12; };
+
+// LDS tile.  Field-major so that neighbouring lanes touch neighbouring words.
+template <class T>
+struct Tile {
+  T W[5][NB];            // centre primitives (rho, Ux, Uy, Uz, p), 12^3 box
+  T C[5][NHB];           // half-step corrections, 10^3 box
+  T F[2][5][NIF];        // interface fluxes of two directions (ring)
+  double red[NT / 64];   // per-wavefront maxima
+  unsigned int cnt[8];   // workgroup counters
+  int nb[32];            // neighbour table row (gather mode)
+  unsigned long long claim;  // queue position claimed by the workgroup (persistent schedule)
+};
+
+__device__ __forceinline__ int bidx(int i, int j, int k) { return ((k + 2) * BX + (j + 2)) * BX + (i + 2); }
+__device__ __forceinline__ int hidx(int i, int j, int k) { return ((k + 1) * HX + (j + 1)) * HX + (i + 1); }
+
+template <class T>
+__device__ __forceinline__ Prim<T> load_prim(const Tile<T> &s, int b)
+{
+  Prim<T> w;
+  w.rho = s.W[0][b];
+  w.u[0] = s.W[1][b];
+  w.u[1] = s.W[2][b];
+  w.u[2] = s.W[3][b];
+  w.p = s.W[4][b];
+  return w;
+}
+
+// Double inversion of bulk-type conserved variables (FP64 path: lhs_L in double; mixed path:
+// the float values' products are exact in double).
+__device__ __forceinline__ double L_of(const Cons<double> &u) { return lhs_L(u.D, u.m[0], u.m[1], u.m[2], u.E); }
+__device__ __forceinline__ double L_of(const Cons<float> &u) { return lhs_L_from_f32(u.D, u.m[0], u.m[1], u.m[2], u.E); }
+
+// Admissibility (Eq. 30) of a face state and its L (0 when not admissible).
+template <class T>
+__device__ __forceinline__ bool face_L(const Cons<T> &u, double &L)
+{
+  bool ok = finiteT(u.D) && finiteT(u.m[0]) && finiteT(u.m[1]) && finiteT(u.m[2]) &&
+            finiteT(u.E) && u.D > T(0) && u.E > T(0);
+  L = ok ? L_of(u) : 0.0;
+  ok = ok && L > DBL_EPSILON;
+  if (!ok) L = 0.0;
+  return ok;
+}
+
+// Inversion of a face state in the inversion type I from its (exact, FP64) L.
+template <class I, class T>
+__device__ __forceinline__ bool invert_face(const Cons<T> &u, bool ok, double L, Prim<T> &w,
+                                            int &iters, int &status, double guess, bool have_guess)
+{
+  I D = u.D, Mx = u.m[0], My = u.m[1], Mz = u.m[2];
+  InvOut<I> o;
+  if (ok) invert_with_L<I>(D, Mx, My, Mz, (I)L, (I)guess, have_guess, (I)StepTol<T, I>::v, 30, o);
+  else set_unphysical(o);
+  w.rho = (T)o.rho;
+  w.u[0] = (T)o.ux;
+  w.u[1] = (T)o.uy;
+  w.u[2] = (T)o.uz;
+  w.p = (T)o.p;
+  iters = o.iters;
+  status = o.status;
+  return ok;
+}
+
+// Face state of cell (i, j, k) on side `side` (0: minus, 1: plus) of direction d: PLM along d,
+// prim -> cons, plus the cell's half-step correction, then the inversion.
+template <int d, bool MLP, class I, class T>
+__device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, int j, int k,
+                                           T theta, const MlpDev &mlp, Prim<T> &w, int &iters,
+                                           int &status)
+{
+  constexpr int sd = d == 0 ? 1 : (d == 1 ? BX : BX * BX);
+  int b = bidx(i, j, k);
+  int hb = hidx(i, j, k);
+  T half = side ? T(0.5) : T(-0.5);
+  Prim<T> wf;
+  T v[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    T wc = s.W[f][b];
+    v[f] = wc + half * limited_slope(s.W[f][b - sd], wc, s.W[f][b + sd], theta);
+  }
+  wf.rho = v[0];
+  wf.u[0] = v[1];
+  wf.u[1] = v[2];
+  wf.u[2] = v[3];
+  wf.p = v[4];
+  Cons<T> u = prim2cons(wf);
+  u.D += s.C[0][hb];
+  u.m[0] += s.C[1][hb];
+  u.m[1] += s.C[2][hb];
+  u.m[2] += s.C[3][hb];
+  u.E += s.C[4][hb];
+  // the learned guess is evaluated by every lane of the wavefront (a wavefront handles one
+  // direction and all its lanes are active here)
+  double L;
+  const bool ok = face_L(u, L);
+  bool consulted = false;
+  double guess = MLP ? mlp_guess(mlp, u.D, u.m[0], u.m[1], u.m[2], u.E, L, consulted) : -1.0;
+  return invert_face<I>(u, ok, L, w, iters, status, guess, consulted);
+}
+
+struct IfaceCount {
+  unsigned int iters, inv, fb, nc, unphys;
+};
+
+// Flux through interface r of direction d (between cells c-1 and c along d, interfaces numbered
+// with x fastest, then y, then z), written to the ring slot of d.
+template <int d, bool MLP, class I, class T>
+__device__ __forceinline__ bool interface_flux(Tile<T> &s, int r, T theta, int solver,
+                                               const MlpDev &mlp, IfaceCount &cnt)
+{
+  // x is the fastest index in every direction, so the lanes of a wavefront read neighbouring
+  // LDS words (a y- or z-fastest order would put them 12 or 144 words apart, on few banks)
+  int cr[3];
+  if (d == 0) { cr[0] = r % 9; cr[1] = (r / 9) & 7; cr[2] = r / 72; }         // x in [0, 9)
+  else if (d == 1) { cr[0] = r & 7; cr[1] = (r >> 3) % 9; cr[2] = r / 72; }   // y in [0, 9)
+  else { cr[0] = r & 7; cr[1] = (r >> 3) & 7; cr[2] = r >> 6; }               // z in [0, 9)
+  int cl[3] = {cr[0], cr[1], cr[2]};
+  cl[d] -= 1;
+  Prim<T> wl, wr;
+  int itl, itr, stl, str;
+  bool okl = face_state<d, MLP, I>(s, 1, cl[0], cl[1], cl[2], theta, mlp, wl, itl, stl);
+  bool okr = face_state<d, MLP, I>(s, 0, cr[0], cr[1], cr[2], theta, mlp, wr, itr, str);
+  cnt.iters += itl + itr;
+  cnt.inv += 2;
+  cnt.fb += (stl == ST_FALLBACK) + (str == ST_FALLBACK);
+  cnt.nc += (stl == ST_NOCONV) + (str == ST_NOCONV);
+  cnt.unphys += !okl + !okr;
+  Cons<T> F = solver == SRHD_HLLE ? hlle<d>(wl, wr) : hllc<d>(wl, wr);
+  constexpr int slot = d & 1;
+  s.F[slot][0][r] = F.D;
+  s.F[slot][1][r] = F.m[0];
+  s.F[slot][2][r] = F.m[1];
+  s.F[slot][3][r] = F.m[2];
+  s.F[slot][4][r] = F.E;
+  return okl && okr;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2); this mapping
+// hands each XCD a contiguous range of patches so that neighbouring patches, whose cells the
+// gather reads, are processed under the same L2.
+__device__ __forceinline__ int64_t patch_of_block(int64_t n_patch, int remap)
+{
+  if (!remap) return blockIdx.x;
+  int64_t chunk = (n_patch + 7) / 8;
+  return (int64_t)(blockIdx.x % 8) * chunk + blockIdx.x / 8;
+}
+
+// GATHER = false: padded conserved patches, cell-centre inversions in phase A.
+// GATHER = true : the 1,376 tile cells' primitives are read from the interiors of the patch and
+//                 its 26 neighbours (outflow clamping where a face neighbour is -1), and every
+//                 updated cell is inverted at the end -- its primitives and the workgroup's
+//                 maximum signal speed (Eqs. 26-27) feed the next step.
+template <class T, class I, bool GATHER, bool MLP>
+__device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const MlpDev &mlp, const int64_t p)
+{
+  const int tid = threadIdx.x;
+  const int g = a.ghost;
+  const int N = 8 + 2 * g;
+  const int N3 = N * N * N;
+  const double *__restrict__ q = GATHER ? nullptr : a.padded + p * 5 * N3;
+  int lv = a.level ? (int)a.level[p] : 0;
+  lv = lv < 0 ? 0 : (lv >= a.n_level ? a.n_level - 1 : lv);     // never index past dt_lev
+  const double dh = a.dh[lv];
+  double dt;
+  if (a.dt_lev) dt = a.dt_lev[lv];
+  else dt = a.c_cfl * dh / __longlong_as_double((long long)a.smax_in[0]);
+  if (GATHER && a.dt_out && p == 0 && tid < a.n_level)
+    a.dt_out[tid] = a.dt_lev ? a.dt_lev[tid]
+                             : a.c_cfl * a.dh[tid] / __longlong_as_double((long long)a.smax_in[0]);
+
+  if (tid < 8) s.cnt[tid] = 0u;
+  if (GATHER && tid < 27) s.nb[tid] = a.neighbor[p * 27 + tid];
+  unsigned int my_iters = 0, my_inv = 0, my_fb = 0, my_nc = 0;
+  __syncthreads();
+
+  // ---------------------------------------------------------------- A: centre primitives
+  bool centre_bad = false;
+  unsigned int centre_unphys = 0;
+  for (int r0 = 0; r0 < NPC; r0 += NT) {
+    // every lane runs every round (the learned guess needs whole wavefronts); lanes past the
+    // end of the list work on the first cell again and store nothing
+    const int r = r0 + tid;
+    const bool valid = r < NPC;
+    int b = kTab.pcell[valid ? r : 0];
+    int bi = b % BX, bj = (b / BX) % BX, bk = b / (BX * BX);
+    if (GATHER) {
+      if (!valid) continue;
+      const T *__restrict__ pr = (const T *)a.prims;
+      int c[3] = {bi - 2, bj - 2, bk - 2};
+      const int fs[3] = {1, 3, 9};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        int o = c[d] < 0 ? -1 : (c[d] >= 8 ? 1 : 0);
+        if (o != 0 && s.nb[13 + o * fs[d]] < 0) c[d] = o < 0 ? 0 : 7;     // outflow
+      }
+      int o0 = c[0] < 0 ? -1 : (c[0] >= 8 ? 1 : 0);
+      int o1 = c[1] < 0 ? -1 : (c[1] >= 8 ? 1 : 0);
+      int o2 = c[2] < 0 ? -1 : (c[2] >= 8 ? 1 : 0);
+      int64_t src = s.nb[(o2 + 1) * 9 + (o1 + 1) * 3 + (o0 + 1)];
+      bool okc = src >= 0 && src < a.n_patch;
+      int sc = ((c[2] - 8 * o2) * 8 + (c[1] - 8 * o1)) * 8 + (c[0] - 8 * o0);
+      const T nan = T(__builtin_nan(""));
+      const T *w = pr + (okc ? src : 0) * 5 * 512 + sc;
+      T v0 = okc ? w[0] : nan, v1 = okc ? w[512] : nan, v2 = okc ? w[1024] : nan,
+        v3 = okc ? w[1536] : nan, v4 = okc ? w[2048] : nan;
+      bool bad = !(v0 > T(0)) || !(v4 > T(0)) || !finiteT(v1) || !finiteT(v2) || !finiteT(v3);
+      centre_bad |= bad;
+      centre_unphys += bad;
+      s.W[0][b] = v0;
+      s.W[1][b] = v1;
+      s.W[2][b] = v2;
+      s.W[3][b] = v3;
+      s.W[4][b] = v4;
+    } else {
+      int off = ((bk + g - 2) * N + (bj + g - 2)) * N + (bi + g - 2);
+      double D = q[off], Mx = q[N3 + off], My = q[2 * N3 + off], Mz = q[3 * N3 + off],
+             Et = q[4 * N3 + off];
+      double L;
+      InvOut<I> o;
+      const bool adm = admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L);
+      bool consulted = false;
+      double guess = MLP ? mlp_guess(mlp, D, Mx, My, Mz, Et, (valid && adm) ? L : 0.0, consulted) : -1.0;
+      if (!valid) continue;
+      if (adm) invert_with_L<I>((I)D, (I)Mx, (I)My, (I)Mz, (I)L, (I)guess, consulted, (I)StepTol<T, I>::v, 30, o);
+      else set_unphysical(o);
+      centre_bad |= o.status == ST_UNPHYSICAL;
+      centre_unphys += o.status == ST_UNPHYSICAL;
+      my_iters += o.iters;
+      my_inv += 1;
+      my_nc += o.status == ST_NOCONV;
+      s.W[0][b] = (T)o.rho;
+      s.W[1][b] = (T)o.ux;
+      s.W[2][b] = (T)o.uy;
+      s.W[3][b] = (T)o.uz;
+      s.W[4][b] = (T)o.p;
+    }
+  }
+  centre_bad = __syncthreads_or(centre_bad);
+
+  // this thread's interior cell for phase D
+  const int ci = tid & 7, cj = (tid >> 3) & 7, ck = tid >> 6;
+  const int cq = ((ck + g) * N + (cj + g)) * N + (ci + g);
+
+  T theta = (T)a.theta;
+  unsigned int retries = 0, unphys = 0;
+  for (int attempt = 0;; ++attempt) {
+    // -------------------------------------------------------------- B: half-step corrections
+    const T half = T(0.5 * dt / dh);
+    for (int r = tid; r < NHC; r += NT) {
+      int hb = kTab.hcell[r];
+      int i = hb % HX - 1, j = (hb / HX) % HX - 1, k = hb / (HX * HX) - 1;
+      int b = bidx(i, j, k);
+      Prim<T> wc = load_prim(s, b);
+      T acc[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int sd = d == 0 ? 1 : (d == 1 ? BX : BX * BX);
+        Prim<T> wm = load_prim(s, b - sd), wp = load_prim(s, b + sd);
+        T sl[5];
+        sl[0] = limited_slope(wm.rho, wc.rho, wp.rho, theta);
+        sl[1] = limited_slope(wm.u[0], wc.u[0], wp.u[0], theta);
+        sl[2] = limited_slope(wm.u[1], wc.u[1], wp.u[1], theta);
+        sl[3] = limited_slope(wm.u[2], wc.u[2], wp.u[2], theta);
+        sl[4] = limited_slope(wm.p, wc.p, wp.p, theta);
+        Prim<T> fm, fp;
+        fm.rho = wc.rho - T(0.5) * sl[0];  fp.rho = wc.rho + T(0.5) * sl[0];
+        fm.u[0] = wc.u[0] - T(0.5) * sl[1]; fp.u[0] = wc.u[0] + T(0.5) * sl[1];
+        fm.u[1] = wc.u[1] - T(0.5) * sl[2]; fp.u[1] = wc.u[1] + T(0.5) * sl[2];
+        fm.u[2] = wc.u[2] - T(0.5) * sl[3]; fp.u[2] = wc.u[2] + T(0.5) * sl[3];
+        fm.p = wc.p - T(0.5) * sl[4];      fp.p = wc.p + T(0.5) * sl[4];
+        Cons<T> Fm, Fp;
+        if (d == 0) { Fm = phys_flux<0>(fm, prim2cons(fm)); Fp = phys_flux<0>(fp, prim2cons(fp)); }
+        else if (d == 1) { Fm = phys_flux<1>(fm, prim2cons(fm)); Fp = phys_flux<1>(fp, prim2cons(fp)); }
+        else { Fm = phys_flux<2>(fm, prim2cons(fm)); Fp = phys_flux<2>(fp, prim2cons(fp)); }
+        acc[0] += Fp.D - Fm.D;
+        acc[1] += Fp.m[0] - Fm.m[0];
+        acc[2] += Fp.m[1] - Fm.m[1];
+        acc[3] += Fp.m[2] - Fm.m[2];
+        acc[4] += Fp.E - Fm.E;
+      }
+#pragma unroll
+      for (int f = 0; f < 5; ++f) s.C[f][hb] = -half * acc[f];
+    }
+    __syncthreads();
+
+    // -------------------------------------------------------------- C + D: fluxes, update
+    bool fail = false;
+    T dU[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll 1
+    for (int round = 0; round < 4; ++round) {
+      int qi = round * NT + tid;
+      if (qi < 3 * NIF) {
+        // 576 = 9 x 64: the direction is uniform across each wavefront
+        int d = qi / NIF;
+        int r = qi - d * NIF;
+        IfaceCount ic = {0, 0, 0, 0, 0};
+        bool ok;
+        if (d == 0) ok = interface_flux<0, MLP, I>(s, r, theta, a.riemann, mlp, ic);
+        else if (d == 1) ok = interface_flux<1, MLP, I>(s, r, theta, a.riemann, mlp, ic);
+        else ok = interface_flux<2, MLP, I>(s, r, theta, a.riemann, mlp, ic);
+        fail |= !ok;
+        my_iters += ic.iters;
+        my_inv += ic.inv;
+        my_fb += ic.fb;
+        my_nc += ic.nc;
+        unphys += ic.unphys;
+      }
+      __syncthreads();
+      if (round >= 1) {
+        // direction round-1 is complete: fold F_{+1/2} - F_{-1/2} into this thread's cell
+        int d = round - 1;
+        int slot = d & 1;
+        // this cell's lower face along d, and the step to its upper face, in the order above
+        int r = d == 0 ? (ck * 8 + cj) * 9 + ci : (d == 1 ? (ck * 9 + cj) * 8 + ci : (ck * 8 + cj) * 8 + ci);
+        int up = d == 0 ? 1 : (d == 1 ? 8 : 64);
+#pragma unroll
+        for (int f = 0; f < 5; ++f) dU[f] += s.F[slot][f][r + up] - s.F[slot][f][r];
+        __syncthreads();
+      }
+    }
+    const double full = dt / dh;
+    double un[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      double u0 = GATHER ? a.cons[(p * 5 + f) * 512 + tid] : q[f * N3 + cq];
+      un[f] = u0 - full * (double)dU[f];
+    }
+    double Lo;
+    bool ok_out = admissible(un[0], un[1], un[2], un[3], un[4], DBL_EPSILON, Lo);
+    fail |= !ok_out;
+    fail = __syncthreads_or(fail);
+    bool last = !fail || centre_bad || theta == T(0);
+    if (last) {
+      double *o = a.out + p * 5 * 512 + tid;
+#pragma unroll
+      for (int f = 0; f < 5; ++f) o[f * 512] = un[f];
+      unphys += !ok_out;
+      if (GATHER) {
+        // the updated cell's primitives and signal speed, for the next step
+        InvOut<I> w;
+        bool consulted = false;
+        double guess = MLP ? mlp_guess(mlp, un[0], un[1], un[2], un[3], un[4], ok_out ? Lo : 0.0, consulted) : -1.0;
+        if (ok_out)
+          invert_with_L<I>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)Lo, (I)guess, consulted,
+                           (I)StepTol<T, I>::v, 30, w);
+        else set_unphysical(w);
+        my_iters += w.iters;
+        my_inv += 1;
+        my_nc += w.status == ST_NOCONV;
+        T *po = (T *)a.prims_out + p * 5 * 512 + tid;
+        po[0] = (T)w.rho;
+        po[512] = (T)w.ux;
+        po[1024] = (T)w.uy;
+        po[1536] = (T)w.uz;
+        po[2048] = (T)w.p;
+        double sm = ok_out ? signal_smax((double)w.rho, (double)w.ux, (double)w.uy, (double)w.uz,
+                                         (double)w.p) : 0.0;
+        sm = wave_max(sm);
+        if ((tid & 63) == 0) s.red[tid >> 6] = sm;
+        __syncthreads();
+        if (tid == 0) {
+          double m = s.red[0];
+#pragma unroll
+          for (int w8 = 1; w8 < NT / 64; ++w8) m = fmax(m, s.red[w8]);
+          atomicMax(a.smax_out, (unsigned long long)__double_as_longlong(m));
+        }
+      }
+      break;
+    }
+    ++retries;
+    unphys = 0;
+    theta = attempt < a.max_retry ? theta * T(0.75) : T(0);
+  }
+
+  // ---------------------------------------------------------------- counters
+  if (a.stats) {
+    atomicAdd(&s.cnt[0], unphys + centre_unphys);
+    atomicAdd(&s.cnt[1], my_fb);
+    atomicAdd(&s.cnt[2], my_nc);
+    atomicAdd(&s.cnt[3], my_iters);
+    atomicAdd(&s.cnt[4], my_inv);
+    __syncthreads();
+    if (tid == 0) {
+      unsigned long long *st = (unsigned long long *)a.stats;
+      if (s.cnt[0]) atomicAdd(&st[0], (unsigned long long)s.cnt[0]);
+      if (s.cnt[1]) atomicAdd(&st[1], (unsigned long long)s.cnt[1]);
+      if (s.cnt[2]) atomicAdd(&st[2], (unsigned long long)s.cnt[2]);
+      atomicAdd(&st[3], (unsigned long long)s.cnt[3]);
+      atomicAdd(&st[4], (unsigned long long)s.cnt[4]);
+      if (retries) atomicAdd(&st[5], (unsigned long long)retries);
+    }
+  }
+}
+
+// One patch per workgroup (a.queue == NULL), or a persistent grid of a.groups workgroups that
+// claim a.chunk patches at a time.  The persistent schedule keeps one queue counter per XCD over
+// that XCD's contiguous range of patches (the same ranges as the one-per-patch mapping); a
+// workgroup drains its own XCD's range first and then helps the others in turn, so every
+// workgroup leaves the loop once all eight ranges are exhausted.
+template <class T, class I, bool GATHER, bool MLP>
+__device__ __forceinline__ void step_body(const StepArgs &a)
+{
+  const MlpDev mlp = a.guess.dev();
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Tile<T> &s = *reinterpret_cast<Tile<T> *>(smem_raw);
+  if (!a.queue) {
+    const int64_t p = patch_of_block(a.n_patch, a.xcd_remap);
+    if (p < a.n_patch) step_patch<T, I, GATHER, MLP>(a, s, mlp, p);     // uniform per workgroup
+    return;
+  }
+  const int64_t range = (a.n_patch + 7) / 8;
+  const int home = blockIdx.x % 8;
+  for (int k = 0; k < 8; ++k) {
+    const int x = (home + k) % 8;
+    const int64_t lo = x * range;
+    const int64_t hi = lo + range < a.n_patch ? lo + range : a.n_patch;
+    for (;;) {
+      __syncthreads();                               // the tile and s.claim are free again
+      if (threadIdx.x == 0) s.claim = atomicAdd(&a.queue[x], (unsigned long long)a.chunk);
+      __syncthreads();
+      const int64_t p0 = lo + (int64_t)s.claim;
+      if (p0 >= hi) break;                           // uniform: every thread read the same claim
+      const int64_t p1 = p0 + a.chunk < hi ? p0 + a.chunk : hi;
+      for (int64_t p = p0; p < p1; ++p) {
+        step_patch<T, I, GATHER, MLP>(a, s, mlp, p);
+        __syncthreads();
+      }
+    }
+  }
+}
+
+template <class T, class I, bool GATHER, bool MLP>
+__global__ void __launch_bounds__(NT) k_step(StepArgs a)
+{
+  step_body<T, I, GATHER, MLP>(a);
+}
+
+// The same kernel compiled for at most 128 VGPRs (four waves per SIMD), so that two 512-thread
+// workgroups share a CU when their LDS tiles fit (the mixed-precision tile takes 78 KB); the
+// compiler then keeps a few values of the per-patch setup in scratch instead of registers.
+template <class T, class I, bool GATHER, bool MLP>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) k_step_occ2(StepArgs a)
+{
+  step_body<T, I, GATHER, MLP>(a);
+}
+
+// Inversion of every interior cell into the bulk type, with the maximum signal speed (the
+// entry state of the gather-mode step).  Same inversion and tolerance as the step's own output
+// inversion, so a chain of steps sees identically computed primitives throughout.
+template <class T, class I, bool MLP>
+__global__ void __launch_bounds__(256) k_grid_prims(int64_t n_patch, const double *__restrict__ cons,
+                                                    T *__restrict__ prims,
+                                                    unsigned long long *__restrict__ smax_bits,
+                                                    MlpDev mlp)
+{
+  __shared__ double red[4];
+  const int64_t total = n_patch * 512;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  double vmax = 0.0;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += stride) {
+    const int64_t t = base + threadIdx.x;       // total is a multiple of 512: always in range
+    int64_t pp = t >> 9;
+    int c = (int)(t & 511);
+    const double *u = cons + pp * 5 * 512 + c;
+    double L;
+    InvOut<I> w;
+    bool ok = admissible(u[0], u[512], u[1024], u[1536], u[2048], DBL_EPSILON, L);
+    bool consulted = false;
+    double guess = MLP ? mlp_guess(mlp, u[0], u[512], u[1024], u[1536], u[2048], ok ? L : 0.0, consulted) : -1.0;
+    if (ok)
+      invert_with_L<I>((I)u[0], (I)u[512], (I)u[1024], (I)u[1536], (I)L, (I)guess, consulted,
+                       (I)StepTol<T, I>::v, 30, w);
+    else set_unphysical(w);
+    T *po = prims + pp * 5 * 512 + c;
+    po[0] = (T)w.rho;
+    po[512] = (T)w.ux;
+    po[1024] = (T)w.uy;
+    po[1536] = (T)w.uz;
+    po[2048] = (T)w.p;
+    if (ok) vmax = fmax(vmax, signal_smax((double)w.rho, (double)w.ux, (double)w.uy, (double)w.uz, (double)w.p));
+  }
+  vmax = wave_max(vmax);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = vmax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    atomicMax(smax_bits, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+__global__ void k_zero_bits(unsigned long long *p)
+{
+  if (threadIdx.x == 0) p[0] = 0ull;
+}
+
+__global__ void k_zero_queue(unsigned long long *q)
+{
+  if (threadIdx.x < SRHD_QUEUE_WORDS) q[threadIdx.x] = 0ull;
+}
+
+// Kernel of a (precision, layout, guess, register budget) combination.  The two-workgroup
+// variant exists for the FP32-bulk kernels only: the FP64 tile fills the LDS of a CU by itself.
+// With the learned guess it spills around the network's evaluation, which runs only in
+// wavefronts that consult it.
+template <class T, class I, bool GATHER, bool MLP>
+const void *step_kernel(bool occ2)
+{
+  if constexpr (sizeof(T) == 4)
+    if (occ2) return (const void *)k_step_occ2<T, I, GATHER, MLP>;
+  return (const void *)k_step<T, I, GATHER, MLP>;
+}
+
+template <class T, class I, bool GATHER, bool MLP>
+int occupancy_k(bool occ2)
+{
+  int n = 0;
+  const size_t bytes = sizeof(Tile<T>);
+  const void *fn = step_kernel<T, I, GATHER, MLP>(occ2);
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, NT, bytes) != hipSuccess) return 0;
+  return n;
+}
+
+template <class T, class I, bool GATHER, bool MLP>
+hipError_t launch_step_k(const StepArgs &a, hipStream_t st)
+{
+  const size_t bytes = sizeof(Tile<T>);
+  const bool occ2 = a.occ2 && sizeof(T) == 4;
+  hipError_t e = hipFuncSetAttribute(step_kernel<T, I, GATHER, MLP>(occ2),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  if (GATHER) hipLaunchKernelGGL(k_zero_bits, dim3(1), dim3(64), 0, st, a.smax_out);
+  int64_t blocks;
+  if (a.queue) {
+    hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(64), 0, st, a.queue);
+    blocks = a.groups;
+  } else {
+    blocks = a.xcd_remap ? 8 * ((a.n_patch + 7) / 8) : a.n_patch;
+  }
+  if constexpr (sizeof(T) == 4) {
+    if (occ2) {
+      hipLaunchKernelGGL((k_step_occ2<T, I, GATHER, MLP>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_step<T, I, GATHER, MLP>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
+  return hipGetLastError();
+}
+
+template <class T, class I, bool GATHER>
+hipError_t launch_step_t(const StepArgs &a, hipStream_t st)
+{
+  return a.guess.kind == SRHD_GUESS_MLP ? launch_step_k<T, I, GATHER, true>(a, st)
+                                        : launch_step_k<T, I, GATHER, false>(a, st);
+}
+
+template <class T, class I>
+int occupancy_ti(bool gather, bool mlp, bool occ2)
+{
+  return gather ? (mlp ? occupancy_k<T, I, true, true>(occ2) : occupancy_k<T, I, true, false>(occ2))
+                : (mlp ? occupancy_k<T, I, false, true>(occ2) : occupancy_k<T, I, false, false>(occ2));
+}
+
+template <class T, class I>
+void launch_grid_prims_ti(int64_t n_patch, const double *cons, void *prims,
+                          unsigned long long *smax_bits, const MlpDev &m, bool mlp, int blocks,
+                          hipStream_t st)
+{
+  if (mlp)
+    hipLaunchKernelGGL((k_grid_prims<T, I, true>), dim3(blocks), dim3(256), 0, st, n_patch, cons, (T *)prims, smax_bits, m);
+  else
+    hipLaunchKernelGGL((k_grid_prims<T, I, false>), dim3(blocks), dim3(256), 0, st, n_patch, cons, (T *)prims, smax_bits, m);
+}
+
+// Entry points of one precision mode (bulk type T, inversion type I); each mode is compiled in
+// a translation unit of its own.
+template <class T, class I>
+hipError_t step_launch_ti(const StepArgs &a, bool gather, hipStream_t st)
+{
+  if (gather) {
+    if (a.n_patch == 0) {
+      hipLaunchKernelGGL(k_zero_bits, dim3(1), dim3(64), 0, st, a.smax_out);
+      return hipGetLastError();
+    }
+    return launch_step_t<T, I, true>(a, st);
+  }
+  if (a.n_patch == 0) return hipSuccess;
+  return launch_step_t<T, I, false>(a, st);
+}
+
+template <class T, class I>
+hipError_t grid_prims_ti(int64_t n_patch, const double *cons, void *prims,
+                         unsigned long long *smax_bits, const GuessArgs &g, hipStream_t st)
+{
+  hipLaunchKernelGGL(k_zero_bits, dim3(1), dim3(64), 0, st, smax_bits);
+  if (n_patch > 0) {
+    const int64_t total = n_patch * 512;
+    int blocks = (int)((total + 511) / 512);
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    launch_grid_prims_ti<T, I>(n_patch, cons, prims, smax_bits, g.dev(), g.kind == SRHD_GUESS_MLP,
+                               blocks, st);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace srhd

@@ -24,7 +24,7 @@ ST_OK, ST_UNPHYSICAL, ST_FALLBACK, ST_NOCONV = 0, 1, 2, 3
 GUESS_ANALYTIC, GUESS_MLP = 0, 1
 FEAT_CONS, FEAT_L = 0, 1
 HLLC, HLLE = 0, 1
-PREC_FP64, PREC_MIXED = 0, 1
+PREC_FP64, PREC_MIXED, PREC_FP32 = 0, 1, 2
 MAX_LEVEL = 8
 
 _vp = ctypes.c_void_p
@@ -363,7 +363,7 @@ def srhd_fluid_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann
 
 
 def prims_dtype(prec):
-    return torch.float32 if prec == PREC_MIXED else torch.float64
+    return torch.float64 if prec == PREC_FP64 else torch.float32
 
 
 def srhd_grid_prims(cons, prec=PREC_FP64, prims=None, smax_bits=None, guess=None):

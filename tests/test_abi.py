@@ -109,7 +109,7 @@ def test_schedule_checks(lib):
     rc = S._lib.srhd_autotune_step(ctypes.byref(d), al(out), al(dt), ctypes.byref(prm), 0, None,
                                    0, ctypes.byref(n), None)
     assert rc == -1 and b"reps" in S._lib.srhd_last_error()
-    # the two-workgroup variant exists for mixed precision with the analytic guess only
+    # the two-workgroup variant exists for mixed precision only
     prm.sched = S.srhd_sched(0, 1, 2, None)
     assert call() == -3 and b"occupancy" in S._lib.srhd_last_error()
     prm.sched = S.srhd_sched(0, 1, 3, None)
@@ -118,4 +118,4 @@ def test_schedule_checks(lib):
     assert S._lib.srhd_step_occupancy(0, 7, 0, 0) == -1
     assert S._lib.srhd_step_occupancy(1, 0, 0, 1) == -1
     assert S._lib.srhd_step_occupancy(0, 0, 0, 2) == -3
-    assert S._lib.srhd_step_occupancy(1, 1, 0, 2) == -3
+    assert S._lib.srhd_step_occupancy(0, 1, 0, 2) == -3

@@ -80,28 +80,29 @@ def test_queue_is_reset_between_calls(S, blast):
         assert torch.equal(out, ref), n
 
 
+@pytest.mark.parametrize("prec", [1, 2])
 @pytest.mark.parametrize("gather", [False, True])
-def test_two_workgroup_variant_is_bitwise_identical(S, blast, gather):
-    # the kernel compiled for two workgroups per CU (mixed precision, analytic guess)
+def test_two_workgroup_variant_is_bitwise_identical(S, blast, gather, prec):
+    # the kernel compiled for two workgroups per CU (FP32 bulk, analytic guess)
     g, c, nb, dt, pad = blast
-    o0 = S.srhd_step_occupancy(1, S.GUESS_ANALYTIC, gather, 0)
-    o2 = S.srhd_step_occupancy(1, S.GUESS_ANALYTIC, gather, 2)
+    o0 = S.srhd_step_occupancy(prec, S.GUESS_ANALYTIC, gather, 0)
+    o2 = S.srhd_step_occupancy(prec, S.GUESS_ANALYTIC, gather, 2)
     print("workgroups per CU (gather=%s): natural %d, two-workgroup variant %d" % (gather, o0, o2))
     assert o2 >= 2
     for sch in (S.Sched(0, 1, DEV, occupancy=2), S.Sched(1024, 2, DEV, occupancy=2)):
         if gather:
-            prims, smax = S.srhd_grid_prims(c, prec=1)
+            prims, smax = S.srhd_grid_prims(c, prec=prec)
             st0, st1 = S.new_stats(DEV), S.new_stats(DEV)
-            r = S.srhd_fluid_step_grid(c, prims, nb, g.dh_lev, smax_in=smax, prec=1, stats=st0)
-            o = S.srhd_fluid_step_grid(c, prims, nb, g.dh_lev, smax_in=smax, prec=1, stats=st1,
+            r = S.srhd_fluid_step_grid(c, prims, nb, g.dh_lev, smax_in=smax, prec=prec, stats=st0)
+            o = S.srhd_fluid_step_grid(c, prims, nb, g.dh_lev, smax_in=smax, prec=prec, stats=st1,
                                        sched=sch)
             torch.cuda.synchronize()
             for x, y in zip(r, o):
                 assert torch.equal(x, y)
         else:
             st0, st1 = S.new_stats(DEV), S.new_stats(DEV)
-            r = S.srhd_fluid_step(pad, dt, g.dh_lev, prec=1, stats=st0)
-            o = S.srhd_fluid_step(pad, dt, g.dh_lev, prec=1, stats=st1, sched=sch)
+            r = S.srhd_fluid_step(pad, dt, g.dh_lev, prec=prec, stats=st0)
+            o = S.srhd_fluid_step(pad, dt, g.dh_lev, prec=prec, stats=st1, sched=sch)
             torch.cuda.synchronize()
             assert torch.equal(o, r)
         assert S.stats_dict(st0) == S.stats_dict(st1)

@@ -113,12 +113,15 @@ def test_conservation_on_gpu(S):
         assert abs(b[:, f].sum() - a[:, f].sum()) <= 1e-13 * tot, f
 
 
-def test_mixed_precision_error_is_stated(S):
-    # FP32 reconstruction / fluxes / increment with FP64 inversion: per-field error against the
-    # FP64 oracle after one step of the shock tube and of the 64^3 blast.
+@pytest.mark.parametrize("prec", [1, 2])
+def test_mixed_precision_error_is_stated(S, prec):
+    # FP32 reconstruction / fluxes / increment with an FP64 (prec 1) or FP32 (prec 2) inversion
+    # after the exact FP64 L: per-field error against the FP64 oracle after one step of the
+    # shock tube and of the 64^3 blast.
     for g in (W.shock_tube_32(), W.blast(64, seed=3)):
-        r = _one_step_pair(S, g, oracle_cons(g), prec=1)
+        r = _one_step_pair(S, g, oracle_cons(g), prec=prec)
         e = step_errors(r["out"], r["ref"])
+        print(prec, g.name, e)
         assert e["D"] < 1e-5 and e["Et"] < 1e-4 and max(e["Mx"], e["My"], e["Mz"]) < 1e-4, (g.name, e)
 
 
@@ -162,7 +165,7 @@ def _grid_chain(S, g, cons, n_steps, prec=0, dt_fixed=None):
     return out, S.stats_dict(st)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_grid_step_equals_padded_step_bitwise(S, prec):
     # Same arithmetic, ghosts gathered instead of copied: bit-identical output (outflow and
     # periodic blocks, patches in Morton order).
