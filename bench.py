@@ -49,29 +49,31 @@ IO_BYTES_PER_PATCH = {                         # what one patch's step consumes 
     "grid": 1376 * 5 * 4 + 512 * 5 * (8 + 8 + 4),   # FP32 tile prims, cons in/out, prims out
 }
 
-# HBM bytes per launch of the mixed step kernel on this workload, from the rocprofv3
-# FETCH_SIZE / WRITE_SIZE runs summarised in profiles/step_blast256_mixed.md; valid only for the
-# kernel sources they were taken on (hash of the step kernel and its device header).
-PROFILED_TRAFFIC = {"sources_sha256_16": "13c733f46a8f4176", "read": 3769.6e6, "write": 673.2e6,
-                    "summary": "profiles/step_blast256_mixed.md"}
+# HBM bytes per launch of the headline step kernel (mixed precision, learned guess, gather layout,
+# the two-workgroup register variant) on this workload, from the rocprofv3 FETCH_SIZE /
+# WRITE_SIZE runs summarised in profiles/step_blast256_grid_learned.md; valid only for the kernel
+# sources they were taken on (hash of the files that make up the step kernel).
+PROFILED_TRAFFIC = {"sources_sha256_16": "afa2dfdd853bb95d", "read": 3182.2e6, "write": 2955.8e6,
+                    "path": "grid", "summary": "profiles/step_blast256_grid_learned.md"}
+STEP_SOURCES = ("srhd_step_impl.hpp", "srhd_step_mixed.hip", "srhd_device.hpp", "srhd_mlp.hpp")
 
 
 def step_sources_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("srhd_step.hip", "srhd_device.hpp"):
+    for f in STEP_SOURCES:
         with open(os.path.join(ROOT, "paper_2012_11130_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def step_flops(n_patch, stats, mlp=False):
-    """Algorithmic VALU FLOPs of one step launch from its device counters (with the learned
-    guess, its VALU work per inversion is included; its matrix-core work is counted apart)."""
+def step_flops(n_patch, stats):
+    """Algorithmic VALU FLOPs of one step launch from its device counters; the learned guess's
+    VALU work counts per network evaluation (n_mlp), its matrix-core work apart."""
     attempts = n_patch + stats["n_retry"]
     return (attempts * (HALF_CELLS * FLOP_HALF_CELL + 2 * INTERFACES * FLOP_FACE
                         + INTERFACES * FLOP_RIEMANN + OUT_CELLS * FLOP_UPDATE)
-            + stats["n_inversions"] * (FLOP_INVERSION + (FLOP_MLP_VALU if mlp else 0))
+            + stats["n_inversions"] * FLOP_INVERSION + stats.get("n_mlp", 0) * FLOP_MLP_VALU
             + stats["newton_iters"] * FLOP_NEWTON_ITER)
 
 
@@ -228,6 +230,12 @@ def parse():
     ap.add_argument("--guess", choices=("learned", "analytic"), default="learned",
                     help="Newton guess of the headline mixed step (learned needs the weights file)")
     ap.add_argument("--weights", default=None, help="weights of the learned guess (.npz)")
+    ap.add_argument("--sched", default="auto",
+                    help="launch schedule of the step: auto (the autotuner's choice per "
+                         "configuration) or groups,chunk,occupancy")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="measure the headline configuration only (no analytic-guess, "
+                         "configured-input or FP32-inversion comparisons)")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB of a plain elementwise copy run once before the steps, as the "
                          "calibration kernel for hardware byte counters (0 = none)")
@@ -351,6 +359,11 @@ def main():
 
     def tune(prec, guess):
         """The autotuner's schedule for this configuration, on the initial state."""
+        if args.sched != "auto":
+            gr, ch, oc = (int(v) for v in args.sched.split(","))
+            if prec == S.PREC_FP64:
+                oc = 0
+            return S.Sched(gr, ch, dev, occupancy=oc), []
         if args.path == "grid":
             prims, smax = S.srhd_grid_prims(cons0, prec=prec, guess=guess)
             sch, table = S.srhd_autotune_step_grid(cons0, prims, nb, dh, smax_in=smax, prec=prec,
@@ -393,7 +406,7 @@ def main():
           % (guess_name, ms_mx, args.steps, float(np.mean(kms_mx)), st_mx), file=sys.stderr, flush=True)
     value = n_cells * args.steps / (ms_mx * 1e-3)
     res = {"newton": {"headline": newton_summary(st_mx)}}
-    if mlp is not None:
+    if mlp is not None and not args.only_headline:
         ms_an, kms_an, st_an, fin_an = measure(S.PREC_MIXED, None, "mixed_analytic")
         print("# mixed, analytic guess: %.2f ms for %d steps (step kernel %.3f ms avg); stats %s"
               % (ms_an, args.steps, float(np.mean(kms_an)), st_an), file=sys.stderr, flush=True)
@@ -415,13 +428,14 @@ def main():
             res["newton"]["mixed_learned_cons_inputs"] = newton_summary(st_c)
 
     # the FP32-inversion mode (FP32 Newton after the exact FP64 L) with the headline's guess
-    ms_32, kms_32, st_32, fin_32 = measure(S.PREC_FP32, guess, "fp32_inversion")
-    print("# fp32 inversion, %s guess: %.2f ms for %d steps (step kernel %.3f ms avg); stats %s"
-          % (guess_name, ms_32, args.steps, float(np.mean(kms_32)), st_32), file=sys.stderr, flush=True)
-    res["fp32_inversion"] = {"value": n_cells * args.steps / (ms_32 * 1e-3), "ms_per_step": ms_32 / args.steps,
-                             "step_kernel_ms": float(np.mean(kms_32)), "stats": st_32,
-                             "guess": guess_name}
-    res["newton"]["fp32_inversion"] = newton_summary(st_32)
+    if not args.only_headline:
+        ms_32, kms_32, st_32, fin_32 = measure(S.PREC_FP32, guess, "fp32_inversion")
+        print("# fp32 inversion, %s guess: %.2f ms for %d steps (step kernel %.3f ms avg); stats %s"
+              % (guess_name, ms_32, args.steps, float(np.mean(kms_32)), st_32), file=sys.stderr, flush=True)
+        res["fp32_inversion"] = {"value": n_cells * args.steps / (ms_32 * 1e-3), "ms_per_step": ms_32 / args.steps,
+                                 "step_kernel_ms": float(np.mean(kms_32)), "stats": st_32,
+                                 "guess": guess_name}
+        res["newton"]["fp32_inversion"] = newton_summary(st_32)
 
     def field_err(x, ref):
         ms = max(float(np.max(np.sqrt((ref[:, 1:4] ** 2).sum(axis=1)))), 1e-300)
@@ -439,24 +453,27 @@ def main():
         S.srhd_fill_ghosts(cons0, nb, 3, padded=pad)
         o64 = S.srhd_fluid_step(pad, dt, dh, prec=S.PREC_FP64).cpu().numpy()
         omx = S.srhd_fluid_step(pad, dt, dh, prec=S.PREC_MIXED, guess=guess).cpu().numpy()
-        o32 = S.srhd_fluid_step(pad, dt, dh, prec=S.PREC_FP32, guess=guess).cpu().numpy()
+
         b = fin_64.cpu().numpy()
         res["fp64"] = {"value": n_cells * args.steps / (ms_64 * 1e-3), "ms_per_step": ms_64 / args.steps,
                        "step_kernel_ms": float(np.mean(kms_64)), "stats": st_64}
         res["newton"]["fp64"] = newton_summary(st_64)
         res["mixed_vs_fp64_rel_err"] = {"one_step": field_err(omx, o64),
                                         "after_%d_steps" % args.steps: field_err(fin_mx.cpu().numpy(), b)}
-        res["fp32_inversion"]["vs_fp64_rel_err"] = {
-            "one_step": field_err(o32, o64),
-            "after_%d_steps" % args.steps: field_err(fin_32.cpu().numpy(), b)}
+        if "fp32_inversion" in res:
+            o32 = S.srhd_fluid_step(pad, dt, dh, prec=S.PREC_FP32, guess=guess).cpu().numpy()
+            res["fp32_inversion"]["vs_fp64_rel_err"] = {
+                "one_step": field_err(o32, o64),
+                "after_%d_steps" % args.steps: field_err(fin_32.cpu().numpy(), b)}
 
     # ---------------------------------------------------------------- roofline of the step kernel
     kavg = float(np.mean(kms_mx)) * 1e-3
     per_launch = {k: v / args.steps for k, v in st_mx.items()}
-    flops = step_flops(P, per_launch, mlp=mlp is not None)
+    flops = step_flops(P, per_launch)
     traffic = None
     if (step_sources_hash() == PROFILED_TRAFFIC["sources_sha256_16"] and args.cells == 256
-            and args.path == PROFILED_TRAFFIC.get("path", "padded")):
+            and args.path == PROFILED_TRAFFIC.get("path", "padded") and mlp is not None
+            and schedules.get("headline", {}).get("occupancy") == 2):
         traffic = PROFILED_TRAFFIC["read"] + PROFILED_TRAFFIC["write"]
     roofline = {"bound": "alu", "achieved": flops / kavg / 1e12, "peak": PEAK_ALU / 1e12,
                 "unit": "TFLOP/s", "frac": flops / kavg / PEAK_ALU, "traffic": traffic,
@@ -466,7 +483,7 @@ def main():
                 "hbm_GBps_algorithmic": IO_BYTES_PER_PATCH[args.path] * P / kavg / 1e9,
                 "flops_per_launch": flops}
     if mlp is not None:
-        mf = per_launch["n_inversions"] * MFMA_FLOP_MLP
+        mf = per_launch["n_mlp"] * MFMA_FLOP_MLP
         roofline["mfma_bf16"] = {"flops_per_launch": mf, "achieved_TFLOPs": mf / kavg / 1e12,
                                  "frac_of_2500": mf / kavg / 2.5e15}
 

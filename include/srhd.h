@@ -174,7 +174,8 @@ typedef struct {
   uint64_t newton_iters;   /* Newton iterations over all inversions of all attempts */
   uint64_t n_inversions;   /* inversions performed (all attempts) */
   uint64_t n_retry;        /* extra attempts with a reduced limiter coefficient */
-  uint64_t reserved[2];
+  uint64_t n_mlp;          /* learned-guess evaluations: lanes of wavefronts that ran the network */
+  uint64_t reserved;
 } srhd_step_stats;
 
 int srhd_stats_reset(srhd_step_stats *stats, void *stream);

@@ -182,8 +182,12 @@ __device__ __forceinline__ bool newton_htilde(T L, T m2, T x, T tol, int max_ite
     T dth = (T(4) * h - th * (T(5) + T(9) * h * is)) * iden;
     T r = h2 * iq;
     T f = x * (x + T(2)) - T(2) * th * h + th * th * r;
-    // the last term of Eq. A1, Theta^2 r (m^2/q) / h, is Theta^2 h m^2 / q^2
-    T fp = T(2) * (h - th - h * dth + th * dth * r + th * th * h * m2 * iq * iq);
+    // the last term of Eq. A1, Theta^2 r (m^2/q) / h: in double as Theta^2 h m^2 / q^2 (no
+    // division); in float as written, whose products stay inside the FP32 range
+    T last;
+    if constexpr (sizeof(T) == 8) last = th * th * h * m2 * iq * iq;
+    else last = dv(th * th * r * (m2 * iq), h);
+    T fp = T(2) * (h - th - h * dth + th * dth * r + last);
     T dx = dv(f - L, fp);
     x -= dx;
     if (!(x > T(0)) || !finiteT(x)) { iters = it; ht = x; return false; }

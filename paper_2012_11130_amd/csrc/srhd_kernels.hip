@@ -68,8 +68,9 @@ __global__ void __launch_bounds__(kBlock) k_cons2prim(int64_t n, const T *__rest
     T L;
     const bool adm = admissible(D, Mx, My, Mz, Et, T(Tol<T>::eps), L);
     bool consulted = false;
+    unsigned int evals = 0;
     T guess = T(-1);
-    if (MLP) guess = (T)mlp_guess(mlp, D, Mx, My, Mz, Et, (in && adm) ? (double)L : 0.0, consulted);
+    if (MLP) guess = (T)mlp_guess(mlp, D, Mx, My, Mz, Et, (in && adm) ? (double)L : 0.0, consulted, evals);
     if (!in) continue;
     InvOut<T> o;
     if (adm)

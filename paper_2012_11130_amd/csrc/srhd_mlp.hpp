@@ -57,10 +57,12 @@ union Frag8 {
 };
 
 // Standardised network output z for this lane's features (f0, f1, f2).
-// The 64 hidden units of layer 1 are produced in four slabs of 16 (the K extent of one matrix
-// instruction); each slab is packed to BF16, lane-swapped into the two state tiles' B operands
-// and accumulated at once into the four 32x32 output tiles [hidden tile][state tile], so only
-// one slab of activations is live at a time.
+// The two 32-row halves of the hidden layer are produced one after the other, each from four
+// K-slabs of 16 layer-1 units (the K extent of one matrix instruction): a slab is packed to
+// BF16, lane-swapped into the two state tiles' B operands and accumulated into the half's two
+// 32x32 output tiles [state tile].  Layer 1 is evaluated once per half, so only 32 accumulator
+// registers and one slab of activations are live at a time (the step kernels run this inside
+// code that needs its registers).
 __device__ __forceinline__ float mlp_eval(const MlpDev &m, float f0, float f1, float f2)
 {
   const int lane = threadIdx.x & 63;
@@ -68,38 +70,39 @@ __device__ __forceinline__ float mlp_eval(const MlpDev &m, float f0, float f1, f
   const float x1 = (f1 - m.norm[1]) / m.norm[4];
   const float x2 = (f2 - m.norm[2]) / m.norm[5];
 
-  f32x16_t acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};   // [hidden tile][state tile]
+  float part0 = 0.0f, part1 = 0.0f;     // layer-3 partial sums of state tiles 0 and 1
 #pragma unroll 1
-  for (int ks = 0; ks < 4; ++ks) {
-    Frag8 lo, hi;
+  for (int mt = 0; mt < 2; ++mt) {
+    f32x16_t acc0 = {}, acc1 = {};      // rows 32 mt .. 32 mt + 31, state tiles 0 and 1
+#pragma unroll 1
+    for (int ks = 0; ks < 4; ++ks) {
+      Frag8 lo, hi;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      // hidden units k0 and k0 + 1 of this slab; j < 4 fills the low half, j >= 4 the high half
-      const int k0 = 16 * ks + 2 * j;
-      float h[2];
+      for (int j = 0; j < 8; ++j) {
+        // hidden units k0 and k0 + 1 of this slab; j < 4 fills the low half, j >= 4 the high half
+        const int k0 = 16 * ks + 2 * j;
+        float h[2];
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const int k = k0 + e;
-        float a = m.bias[MLP_B1 + k];
-        a = __builtin_fmaf(bf16_to_f(m.w[MLP_W1 + 3 * k + 0]), x0, a);
-        a = __builtin_fmaf(bf16_to_f(m.w[MLP_W1 + 3 * k + 1]), x1, a);
-        a = __builtin_fmaf(bf16_to_f(m.w[MLP_W1 + 3 * k + 2]), x2, a);
-        h[e] = silu_f(a);
+        for (int e = 0; e < 2; ++e) {
+          const int k = k0 + e;
+          float a = m.bias[MLP_B1 + k];
+          a = __builtin_fmaf(bf16_to_f(m.w[MLP_W1 + 3 * k + 0]), x0, a);
+          a = __builtin_fmaf(bf16_to_f(m.w[MLP_W1 + 3 * k + 1]), x1, a);
+          a = __builtin_fmaf(bf16_to_f(m.w[MLP_W1 + 3 * k + 2]), x2, a);
+          h[e] = silu_f(a);
+        }
+        if (j < 4) lo.u[j] = pack_bf16(h[0], h[1]);
+        else hi.u[j - 4] = pack_bf16(h[0], h[1]);
       }
-      if (j < 4) lo.u[j] = pack_bf16(h[0], h[1]);
-      else hi.u[j - 4] = pack_bf16(h[0], h[1]);
-    }
-    // lanes < 32 keep their own low half and receive the low half of lane + 32 (second tile);
-    // lanes >= 32 receive the high half of lane - 32 (first tile) and keep their own high half
-    Frag8 t0, t1;
+      // lanes < 32 keep their own low half and receive the low half of lane + 32 (second
+      // tile); lanes >= 32 receive the high half of lane - 32 (first tile), keep their own high
+      Frag8 t0, t1;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      auto r = __builtin_amdgcn_permlane32_swap(lo.u[j], hi.u[j], false, false);
-      t0.u[j] = r[0];
-      t1.u[j] = r[1];
-    }
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
+      for (int j = 0; j < 4; ++j) {
+        auto r = __builtin_amdgcn_permlane32_swap(lo.u[j], hi.u[j], false, false);
+        t0.u[j] = r[0];
+        t1.u[j] = r[1];
+      }
       // A[h][k] = W2[32 mt + lane % 32][16 ks + 8 (lane / 32) + 0..7]: 16 contiguous bytes
       const uint4 wv = *reinterpret_cast<const uint4 *>(
           m.w + MLP_W2 + (32 * mt + (lane & 31)) * 64 + 16 * ks + 8 * (lane >> 5));
@@ -108,27 +111,19 @@ __device__ __forceinline__ float mlp_eval(const MlpDev &m, float f0, float f1, f
       a.u[1] = wv.y;
       a.u[2] = wv.z;
       a.u[3] = wv.w;
-      if (mt == 0) {
-        acc00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, t0.v, acc00, 0, 0, 0);
-        acc01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, t1.v, acc01, 0, 0, 0);
-      } else {
-        acc10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, t0.v, acc10, 0, 0, 0);
-        acc11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, t1.v, acc11, 0, 0, 0);
-      }
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, t0.v, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, t1.v, acc1, 0, 0, 0);
     }
-  }
-  // layer 3: acc_mt_nt[v] = D[32 mt + 8 (v / 4) + 4 (lane / 32) + v % 4][32 nt + lane % 32]
-  float part0 = 0.0f, part1 = 0.0f;
-#pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
+    // layer 3 on this half: acc_nt[v] = D[32 mt + 8 (v / 4) + 4 (lane / 32) + v % 4][32 nt + lane % 32]
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int hrow = 32 * mt + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
       const float w3 = bf16_to_f(m.w[MLP_W3 + hrow]);
       const float b2 = m.bias[MLP_B2 + hrow];
-      part0 = __builtin_fmaf(w3, silu_f((mt ? acc10[v] : acc00[v]) + b2), part0);
-      part1 = __builtin_fmaf(w3, silu_f((mt ? acc11[v] : acc01[v]) + b2), part1);
+      part0 = __builtin_fmaf(w3, silu_f(acc0[v] + b2), part0);
+      part1 = __builtin_fmaf(w3, silu_f(acc1[v] + b2), part1);
     }
+  }
   // the other half of the 64 rows of a state's column sits in lane ^ 32; the state of this lane
   // is column lane % 32 of tile lane / 32
   const float part = lane < 32 ? part0 : part1;
@@ -161,12 +156,15 @@ __device__ __forceinline__ void mlp_features(int set, double D, double Mx, doubl
 
 // Guess of ht for this lane's state from the network (exp of the de-standardised output), or -1
 // where the network is not consulted (L at or below the gate, or L not admissible: pass L = 0).
-// The whole wavefront must call it; the network runs only if some lane needs it.
+// The whole wavefront must call it; the network runs only if some lane needs it, and then
+// `evals` is incremented (per lane: the count of network evaluations performed).
 __device__ __forceinline__ double mlp_guess(const MlpDev &m, double D, double Mx, double My,
-                                            double Mz, double Et, double L, bool &consulted)
+                                            double Mz, double Et, double L, bool &consulted,
+                                            unsigned int &evals)
 {
   consulted = L > m.gate;
   if (!__any(consulted)) return -1.0;
+  ++evals;
   float f0, f1, f2;
   mlp_features(m.features, D, Mx, My, Mz, Et, L, f0, f1, f2);
   const float z = mlp_eval(m, f0, f1, f2);

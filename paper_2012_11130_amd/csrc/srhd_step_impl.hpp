@@ -151,7 +151,7 @@ __device__ __forceinline__ bool invert_face(const Cons<T> &u, bool ok, double L,
 template <int d, bool MLP, class I, class T>
 __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, int j, int k,
                                            T theta, const MlpDev &mlp, Prim<T> &w, int &iters,
-                                           int &status)
+                                           int &status, unsigned int &evals)
 {
   constexpr int sd = d == 0 ? 1 : (d == 1 ? BX : BX * BX);
   int b = bidx(i, j, k);
@@ -180,12 +180,12 @@ __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, in
   double L;
   const bool ok = face_L(u, L);
   bool consulted = false;
-  double guess = MLP ? mlp_guess(mlp, u.D, u.m[0], u.m[1], u.m[2], u.E, L, consulted) : -1.0;
+  double guess = MLP ? mlp_guess(mlp, u.D, u.m[0], u.m[1], u.m[2], u.E, L, consulted, evals) : -1.0;
   return invert_face<I>(u, ok, L, w, iters, status, guess, consulted);
 }
 
 struct IfaceCount {
-  unsigned int iters, inv, fb, nc, unphys;
+  unsigned int iters, inv, fb, nc, unphys, mlp;
 };
 
 // Flux through interface r of direction d (between cells c-1 and c along d, interfaces numbered
@@ -204,8 +204,8 @@ __device__ __forceinline__ bool interface_flux(Tile<T> &s, int r, T theta, int s
   cl[d] -= 1;
   Prim<T> wl, wr;
   int itl, itr, stl, str;
-  bool okl = face_state<d, MLP, I>(s, 1, cl[0], cl[1], cl[2], theta, mlp, wl, itl, stl);
-  bool okr = face_state<d, MLP, I>(s, 0, cr[0], cr[1], cr[2], theta, mlp, wr, itr, str);
+  bool okl = face_state<d, MLP, I>(s, 1, cl[0], cl[1], cl[2], theta, mlp, wl, itl, stl, cnt.mlp);
+  bool okr = face_state<d, MLP, I>(s, 0, cr[0], cr[1], cr[2], theta, mlp, wr, itr, str, cnt.mlp);
   cnt.iters += itl + itr;
   cnt.inv += 2;
   cnt.fb += (stl == ST_FALLBACK) + (str == ST_FALLBACK);
@@ -263,7 +263,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
 
   if (tid < 8) s.cnt[tid] = 0u;
   if (GATHER && tid < 27) s.nb[tid] = a.neighbor[p * 27 + tid];
-  unsigned int my_iters = 0, my_inv = 0, my_fb = 0, my_nc = 0;
+  unsigned int my_iters = 0, my_inv = 0, my_fb = 0, my_nc = 0, my_mlp = 0;
   __syncthreads();
 
   // ---------------------------------------------------------------- A: centre primitives
@@ -312,7 +312,9 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
       InvOut<I> o;
       const bool adm = admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L);
       bool consulted = false;
-      double guess = MLP ? mlp_guess(mlp, D, Mx, My, Mz, Et, (valid && adm) ? L : 0.0, consulted) : -1.0;
+      unsigned int ev = 0;
+      double guess = MLP ? mlp_guess(mlp, D, Mx, My, Mz, Et, (valid && adm) ? L : 0.0, consulted, ev) : -1.0;
+      my_mlp += valid ? ev : 0u;
       if (!valid) continue;
       if (adm) invert_with_L<I>((I)D, (I)Mx, (I)My, (I)Mz, (I)L, (I)guess, consulted, (I)StepTol<T, I>::v, 30, o);
       else set_unphysical(o);
@@ -386,13 +388,14 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
         // 576 = 9 x 64: the direction is uniform across each wavefront
         int d = qi / NIF;
         int r = qi - d * NIF;
-        IfaceCount ic = {0, 0, 0, 0, 0};
+        IfaceCount ic = {0, 0, 0, 0, 0, 0};
         bool ok;
         if (d == 0) ok = interface_flux<0, MLP, I>(s, r, theta, a.riemann, mlp, ic);
         else if (d == 1) ok = interface_flux<1, MLP, I>(s, r, theta, a.riemann, mlp, ic);
         else ok = interface_flux<2, MLP, I>(s, r, theta, a.riemann, mlp, ic);
         fail |= !ok;
         my_iters += ic.iters;
+        my_mlp += ic.mlp;
         my_inv += ic.inv;
         my_fb += ic.fb;
         my_nc += ic.nc;
@@ -432,7 +435,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
         // the updated cell's primitives and signal speed, for the next step
         InvOut<I> w;
         bool consulted = false;
-        double guess = MLP ? mlp_guess(mlp, un[0], un[1], un[2], un[3], un[4], ok_out ? Lo : 0.0, consulted) : -1.0;
+        double guess = MLP ? mlp_guess(mlp, un[0], un[1], un[2], un[3], un[4], ok_out ? Lo : 0.0, consulted, my_mlp) : -1.0;
         if (ok_out)
           invert_with_L<I>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)Lo, (I)guess, consulted,
                            (I)StepTol<T, I>::v, 30, w);
@@ -472,6 +475,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
     atomicAdd(&s.cnt[2], my_nc);
     atomicAdd(&s.cnt[3], my_iters);
     atomicAdd(&s.cnt[4], my_inv);
+    if (MLP) atomicAdd(&s.cnt[5], my_mlp);
     __syncthreads();
     if (tid == 0) {
       unsigned long long *st = (unsigned long long *)a.stats;
@@ -480,6 +484,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
       if (s.cnt[2]) atomicAdd(&st[2], (unsigned long long)s.cnt[2]);
       atomicAdd(&st[3], (unsigned long long)s.cnt[3]);
       atomicAdd(&st[4], (unsigned long long)s.cnt[4]);
+      if (MLP && s.cnt[5]) atomicAdd(&st[6], (unsigned long long)s.cnt[5]);
       if (retries) atomicAdd(&st[5], (unsigned long long)retries);
     }
   }
@@ -559,7 +564,8 @@ __global__ void __launch_bounds__(256) k_grid_prims(int64_t n_patch, const doubl
     InvOut<I> w;
     bool ok = admissible(u[0], u[512], u[1024], u[1536], u[2048], DBL_EPSILON, L);
     bool consulted = false;
-    double guess = MLP ? mlp_guess(mlp, u[0], u[512], u[1024], u[1536], u[2048], ok ? L : 0.0, consulted) : -1.0;
+    unsigned int evals = 0;
+    double guess = MLP ? mlp_guess(mlp, u[0], u[512], u[1024], u[1536], u[2048], ok ? L : 0.0, consulted, evals) : -1.0;
     if (ok)
       invert_with_L<I>((I)u[0], (I)u[512], (I)u[1024], (I)u[1536], (I)L, (I)guess, consulted,
                        (I)StepTol<T, I>::v, 30, w);

@@ -71,11 +71,11 @@ class srhd_step_stats(ctypes.Structure):
     _fields_ = [("n_unphysical", ctypes.c_uint64), ("n_fallback", ctypes.c_uint64),
                 ("n_noconv", ctypes.c_uint64), ("newton_iters", ctypes.c_uint64),
                 ("n_inversions", ctypes.c_uint64), ("n_retry", ctypes.c_uint64),
-                ("reserved", ctypes.c_uint64 * 2)]
+                ("n_mlp", ctypes.c_uint64), ("reserved", ctypes.c_uint64)]
 
 
 STATS_FIELDS = ("n_unphysical", "n_fallback", "n_noconv", "newton_iters", "n_inversions",
-                "n_retry")
+                "n_retry", "n_mlp")
 
 _sig = {
     "srhd_prim2cons": [_int, _i64, _vp, _vp, _vp],

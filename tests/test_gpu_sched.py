@@ -136,3 +136,29 @@ def test_grid_autotuner(S, blast):
     for x, y in zip(r, o):
         assert torch.equal(x, y)
     print("grid autotune table %s -> %s" % (table, sch))
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_learned_guess_under_every_schedule_is_bitwise_identical(S, blast, prec):
+    # the trained, gated network: the register variants (which spill around its evaluation)
+    # and the persistent grid leave outputs and counters unchanged
+    from paper_2012_11130_amd import mlp_train
+    mlp = mlp_train.load(device=DEV)
+    assert mlp is not None
+    g, c, nb, dt, pad = blast
+    prims, smax = S.srhd_grid_prims(c, prec=prec, guess=mlp.guess())
+    st0 = S.new_stats(DEV)
+    ref = S.srhd_fluid_step_grid(c, prims, nb, g.dh_lev, smax_in=smax, prec=prec,
+                                 guess=mlp.guess(), stats=st0)
+    torch.cuda.synchronize()
+    a = S.stats_dict(st0)
+    assert a["n_mlp"] > 0
+    for sch in (S.Sched(0, 1, DEV, occupancy=2), S.Sched(1024, 2, DEV, occupancy=2),
+                S.Sched(512, 4, DEV)):
+        st1 = S.new_stats(DEV)
+        out = S.srhd_fluid_step_grid(c, prims, nb, g.dh_lev, smax_in=smax, prec=prec,
+                                     guess=mlp.guess(), stats=st1, sched=sch)
+        torch.cuda.synchronize()
+        for x, y in zip(ref, out):
+            assert torch.equal(x, y), sch
+        assert S.stats_dict(st1) == a, sch
