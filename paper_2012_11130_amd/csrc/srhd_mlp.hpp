@@ -171,4 +171,14 @@ __device__ __forceinline__ double mlp_guess(const MlpDev &m, double D, double Mx
   return consulted ? (double)__expf(m.norm[6] + m.norm[7] * z) : -1.0;
 }
 
+// The same from features already formed (the caller decided `consulted`, L > gate).
+__device__ __forceinline__ double mlp_guess_f(const MlpDev &m, float f0, float f1, float f2,
+                                              bool consulted, unsigned int &evals)
+{
+  if (!__any(consulted)) return -1.0;
+  ++evals;
+  const float z = mlp_eval(m, f0, f1, f2);
+  return consulted ? (double)__expf(m.norm[6] + m.norm[7] * z) : -1.0;
+}
+
 }  // namespace srhd

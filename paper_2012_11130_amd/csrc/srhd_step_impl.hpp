@@ -95,6 +95,9 @@ struct Tile {
   unsigned long long claim;  // queue position claimed by the workgroup (persistent schedule)
 };
 
+// the updated state of the final inversion (5 doubles per thread) is parked in the primitive tile
+static_assert(sizeof(float) * 5 * NB >= sizeof(double) * 5 * NT, "parking space in the tile");
+
 __device__ __forceinline__ int bidx(int i, int j, int k) { return ((k + 2) * BX + (j + 2)) * BX + (i + 2); }
 __device__ __forceinline__ int hidx(int i, int j, int k) { return ((k + 1) * HX + (j + 1)) * HX + (i + 1); }
 
@@ -415,10 +418,14 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
       }
     }
     const double full = dt / dh;
+    // this thread's offsets into the interior arrays, formed here: hoisted out of the retry
+    // loop they would hold fifteen 64-bit per-lane addresses across the whole patch
+    int lt = tid, lq = cq;
+    asm volatile("" : "+v"(lt), "+v"(lq));
     double un[5];
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
-      double u0 = GATHER ? a.cons[(p * 5 + f) * 512 + tid] : q[f * N3 + cq];
+      double u0 = GATHER ? a.cons[(p * 5 + f) * 512 + lt] : q[f * N3 + lq];
       un[f] = u0 - full * (double)dU[f];
     }
     double Lo;
@@ -427,7 +434,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
     fail = __syncthreads_or(fail);
     bool last = !fail || centre_bad || theta == T(0);
     if (last) {
-      double *o = a.out + p * 5 * 512 + tid;
+      double *o = a.out + p * 5 * 512 + lt;
 #pragma unroll
       for (int f = 0; f < 5; ++f) o[f * 512] = un[f];
       unphys += !ok_out;
@@ -435,7 +442,22 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
         // the updated cell's primitives and signal speed, for the next step
         InvOut<I> w;
         bool consulted = false;
-        double guess = MLP ? mlp_guess(mlp, un[0], un[1], un[2], un[3], un[4], ok_out ? Lo : 0.0, consulted, my_mlp) : -1.0;
+        double guess = -1.0;
+        if (MLP) {
+          // the network needs most of the registers: park the updated state in the (now unused)
+          // primitive tile while it runs instead of spilling it
+          consulted = ok_out && Lo > mlp.gate;
+          float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
+          if (__any(consulted)) mlp_features(mlp.features, un[0], un[1], un[2], un[3], un[4], Lo, f0, f1, f2);
+          double *park = reinterpret_cast<double *>(&s.W[0][0]) + tid;
+#pragma unroll
+          for (int f = 0; f < 5; ++f) park[f * NT] = un[f];
+          asm volatile("" ::: "memory");
+          guess = mlp_guess_f(mlp, f0, f1, f2, consulted, my_mlp);
+          asm volatile("" ::: "memory");
+#pragma unroll
+          for (int f = 0; f < 5; ++f) un[f] = park[f * NT];
+        }
         if (ok_out)
           invert_with_L<I>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)Lo, (I)guess, consulted,
                            (I)StepTol<T, I>::v, 30, w);
@@ -443,7 +465,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
         my_iters += w.iters;
         my_inv += 1;
         my_nc += w.status == ST_NOCONV;
-        T *po = (T *)a.prims_out + p * 5 * 512 + tid;
+        T *po = (T *)a.prims_out + p * 5 * 512 + lt;
         po[0] = (T)w.rho;
         po[512] = (T)w.ux;
         po[1024] = (T)w.uy;
@@ -516,7 +538,8 @@ __device__ __forceinline__ void step_body(const StepArgs &a)
       __syncthreads();                               // the tile and s.claim are free again
       if (threadIdx.x == 0) s.claim = atomicAdd(&a.queue[x], (unsigned long long)a.chunk);
       __syncthreads();
-      const int64_t p0 = lo + (int64_t)s.claim;
+      // every thread read the same claim: make that visible to the compiler (scalar registers)
+      const int64_t p0 = lo + (int64_t)__builtin_amdgcn_readfirstlane((int)s.claim);
       if (p0 >= hi) break;                           // uniform: every thread read the same claim
       const int64_t p1 = p0 + a.chunk < hi ? p0 + a.chunk : hi;
       for (int64_t p = p0; p < p1; ++p) {
