@@ -256,8 +256,10 @@ __device__ __forceinline__ bool admissible(T D, T Mx, T My, T Mz, T Et, T eps, T
 // Inversion from a known, admissible L.  With `have_guess` the supplied guess is tried first
 // and the analytic guess is the fallback (status FALLBACK when the supplied guess is not a
 // positive finite number or its Newton iteration fails and the analytic one converges);
-// otherwise the analytic guess is used directly.
-template <class T>
+// otherwise the analytic guess is used directly.  The analytic guess is formed in G (a starting
+// point only: FP32 suffices where the result is consumed in FP32); one Newton loop serves both
+// starts.
+template <class T, class G = T>
 __device__ __forceinline__ void invert_with_L(T D, T Mx, T My, T Mz, T L, T guess, bool have_guess,
                                               T tol, int max_iter, InvOut<T> &o)
 {
@@ -265,20 +267,22 @@ __device__ __forceinline__ void invert_with_L(T D, T Mx, T My, T Mz, T L, T gues
   T mx = Mx * iD, my = My * iD, mz = Mz * iD;
   T m2 = mx * mx + my * my + mz * mz;
   T ht;
-  int it1 = 0, it2 = 0;
-  o.status = ST_OK;
+  const bool supplied = have_guess && guess > T(0) && finiteT(guess);
+  bool fell_back = have_guess && !supplied;
+  T x0 = supplied ? guess : T(guess_analytic<G>(G(L), G(m2)));
   bool ok = false;
-  if (have_guess) {
-    if (guess > T(0) && finiteT(guess)) ok = newton_htilde(L, m2, guess, tol, max_iter, ht, it1);
-    if (!ok) {
-      ok = newton_htilde(L, m2, guess_analytic(L, m2), tol, max_iter, ht, it2);
-      o.status = ok ? ST_FALLBACK : ST_NOCONV;
-    }
-  } else {
-    ok = newton_htilde(L, m2, guess_analytic(L, m2), tol, max_iter, ht, it1);
-    if (!ok) o.status = ST_NOCONV;
+  int its = 0;
+#pragma unroll 1
+  for (int a = 0; a < 2; ++a) {
+    int it = 0;
+    ok = newton_htilde(L, m2, x0, tol, max_iter, ht, it);
+    its += it;
+    if (ok || fell_back || !have_guess) break;
+    fell_back = true;                       // the supplied guess failed: restart from App. A
+    x0 = T(guess_analytic<G>(G(L), G(m2)));
   }
-  o.iters = it1 + it2;
+  o.status = ok ? (fell_back ? ST_FALLBACK : ST_OK) : ST_NOCONV;
+  o.iters = its;
   recover(D, Mx, My, Mz, ht, o);
 }
 

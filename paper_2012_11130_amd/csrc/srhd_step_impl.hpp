@@ -19,6 +19,7 @@
 // theta *= 0.75 (max_retry times), then theta = 0 (Sec. 3.4); A is not repeated.
 #pragma once
 #include <float.h>
+#include <type_traits>
 
 #include "srhd_device.hpp"
 #include "srhd_internal.hpp"
@@ -75,6 +76,10 @@ constexpr Tables make_tables()
 constexpr Tables kTabInit = make_tables();
 static_assert(kTabInit.pcell[NPC - 1] != 0 && kTabInit.hcell[NHC - 1] != 0, "cell tables");
 __constant__ Tables kTab = kTabInit;
+
+// The analytic guess's type: FP32 whenever the bulk is FP32 (only a starting point), else I.
+template <class T, class I>
+using GuessT = typename std::conditional<sizeof(T) == 4, float, I>::type;
 
 // Newton tolerance by (bulk type T, inversion type I): FP64 to ~2^-54; an FP64 inversion whose
 // result is consumed in FP32 to ~2^-28; an FP32 inversion to FP32 accuracy.
@@ -137,7 +142,7 @@ __device__ __forceinline__ bool invert_face(const Cons<T> &u, bool ok, double L,
 {
   I D = u.D, Mx = u.m[0], My = u.m[1], Mz = u.m[2];
   InvOut<I> o;
-  if (ok) invert_with_L<I>(D, Mx, My, Mz, (I)L, (I)guess, have_guess, (I)StepTol<T, I>::v, 30, o);
+  if (ok) invert_with_L<I, GuessT<T, I>>(D, Mx, My, Mz, (I)L, (I)guess, have_guess, (I)StepTol<T, I>::v, 30, o);
   else set_unphysical(o);
   w.rho = (T)o.rho;
   w.u[0] = (T)o.ux;
@@ -319,7 +324,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
       double guess = MLP ? mlp_guess(mlp, D, Mx, My, Mz, Et, (valid && adm) ? L : 0.0, consulted, ev) : -1.0;
       my_mlp += valid ? ev : 0u;
       if (!valid) continue;
-      if (adm) invert_with_L<I>((I)D, (I)Mx, (I)My, (I)Mz, (I)L, (I)guess, consulted, (I)StepTol<T, I>::v, 30, o);
+      if (adm) invert_with_L<I, GuessT<T, I>>((I)D, (I)Mx, (I)My, (I)Mz, (I)L, (I)guess, consulted, (I)StepTol<T, I>::v, 30, o);
       else set_unphysical(o);
       centre_bad |= o.status == ST_UNPHYSICAL;
       centre_unphys += o.status == ST_UNPHYSICAL;
@@ -459,7 +464,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
           for (int f = 0; f < 5; ++f) un[f] = park[f * NT];
         }
         if (ok_out)
-          invert_with_L<I>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)Lo, (I)guess, consulted,
+          invert_with_L<I, GuessT<T, I>>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)Lo, (I)guess, consulted,
                            (I)StepTol<T, I>::v, 30, w);
         else set_unphysical(w);
         my_iters += w.iters;
@@ -590,7 +595,7 @@ __global__ void __launch_bounds__(256) k_grid_prims(int64_t n_patch, const doubl
     unsigned int evals = 0;
     double guess = MLP ? mlp_guess(mlp, u[0], u[512], u[1024], u[1536], u[2048], ok ? L : 0.0, consulted, evals) : -1.0;
     if (ok)
-      invert_with_L<I>((I)u[0], (I)u[512], (I)u[1024], (I)u[1536], (I)L, (I)guess, consulted,
+      invert_with_L<I, GuessT<T, I>>((I)u[0], (I)u[512], (I)u[1024], (I)u[1536], (I)L, (I)guess, consulted,
                        (I)StepTol<T, I>::v, 30, w);
     else set_unphysical(w);
     T *po = prims + pp * 5 * 512 + c;
