@@ -82,7 +82,8 @@ __device__ __forceinline__ T lhs_L(T D, T Mx, T My, T Mz, T Et)
   t[6] = -(My * My);    t[7] = -fmaT(My, My, t[6]);
   t[8] = -(Mz * Mz);    t[9] = -fmaT(Mz, Mz, t[8]);
   T N = sum_k3(t);
-  return dv(dv(N, D), D);
+  if constexpr (sizeof(T) == 8) return N / (D * D);      // one division (D^2 stays in range)
+  else return dv(dv(N, D), D);
 }
 
 // The same in double from FP32 conserved variables: products of floats are exact in double.
@@ -97,7 +98,7 @@ __device__ __forceinline__ double lhs_L_from_f32(float D, float Mx, float My, fl
   t[3] = -(y * y);
   t[4] = -(z * z);
   double N = sum_k3(t);
-  return (N / d) / d;
+  return N / (d * d);
 }
 
 // ------------------------------------------------------------------------------ EoS
@@ -355,11 +356,12 @@ __device__ __forceinline__ void signal_speeds(const Prim<T> &w, T &lm, T &lp)
   lp = (c + s) * iden;
 }
 
-// HLLE: HLL flux with S_L^- = min(S_L, 0), S_R^+ = max(S_R, 0).
+// HLLE: HLL flux with S_L^- = min(S_L, 0), S_R^+ = max(S_R, 0).  ul, ur are the conserved
+// variables of wl, wr (the states the primitives were inverted from, where the caller has them).
 template <int d, class T>
-__device__ __forceinline__ Cons<T> hlle(const Prim<T> &wl, const Prim<T> &wr)
+__device__ __forceinline__ Cons<T> hlle(const Prim<T> &wl, const Prim<T> &wr, const Cons<T> &ul,
+                                        const Cons<T> &ur)
 {
-  Cons<T> ul = prim2cons(wl), ur = prim2cons(wr);
   Cons<T> fl = phys_flux<d>(wl, ul), fr = phys_flux<d>(wr, ur);
   T lmL, lpL, lmR, lpR;
   signal_speeds<d>(wl, lmL, lpL);
@@ -393,9 +395,9 @@ __device__ __forceinline__ Cons<T> sel(bool c, const Cons<T> &a, const Cons<T> &
 // pressure p* = F^m - l* F^E, and the reduced-energy star state
 // Et* = [Et (S - v) + p* l* - p v] / (S - l*), which carries no rest-mass cancellation.
 template <int d, class T>
-__device__ __forceinline__ Cons<T> hllc(const Prim<T> &wl, const Prim<T> &wr)
+__device__ __forceinline__ Cons<T> hllc(const Prim<T> &wl, const Prim<T> &wr, const Cons<T> &ul,
+                                        const Cons<T> &ur)
 {
-  Cons<T> ul = prim2cons(wl), ur = prim2cons(wr);
   Cons<T> fl = phys_flux<d>(wl, ul), fr = phys_flux<d>(wr, ur);
   T lmL, lpL, lmR, lpR;
   signal_speeds<d>(wl, lmL, lpL);
@@ -469,6 +471,18 @@ __device__ __forceinline__ T limited_slope(T wl, T wc, T wr, T theta)
   T s = minT(vl, minT(theta * absT(dl), theta * absT(dr)));
   s = dl > T(0) ? s : -s;
   return mono ? s : T(0);
+}
+
+// The Riemann fluxes from primitives alone.
+template <int d, class T>
+__device__ __forceinline__ Cons<T> hlle(const Prim<T> &wl, const Prim<T> &wr)
+{
+  return hlle<d>(wl, wr, prim2cons(wl), prim2cons(wr));
+}
+template <int d, class T>
+__device__ __forceinline__ Cons<T> hllc(const Prim<T> &wl, const Prim<T> &wr)
+{
+  return hllc<d>(wl, wr, prim2cons(wl), prim2cons(wr));
 }
 
 }  // namespace srhd

@@ -158,8 +158,8 @@ __device__ __forceinline__ bool invert_face(const Cons<T> &u, bool ok, double L,
 // prim -> cons, plus the cell's half-step correction, then the inversion.
 template <int d, bool MLP, class I, class T>
 __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, int j, int k,
-                                           T theta, const MlpDev &mlp, Prim<T> &w, int &iters,
-                                           int &status, unsigned int &evals)
+                                           T theta, const MlpDev &mlp, Prim<T> &w, Cons<T> &u,
+                                           int &iters, int &status, unsigned int &evals)
 {
   constexpr int sd = d == 0 ? 1 : (d == 1 ? BX : BX * BX);
   int b = bidx(i, j, k);
@@ -177,7 +177,7 @@ __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, in
   wf.u[1] = v[2];
   wf.u[2] = v[3];
   wf.p = v[4];
-  Cons<T> u = prim2cons(wf);
+  u = prim2cons(wf);
   u.D += s.C[0][hb];
   u.m[0] += s.C[1][hb];
   u.m[1] += s.C[2][hb];
@@ -211,15 +211,18 @@ __device__ __forceinline__ bool interface_flux(Tile<T> &s, int r, T theta, int s
   int cl[3] = {cr[0], cr[1], cr[2]};
   cl[d] -= 1;
   Prim<T> wl, wr;
+  Cons<T> ul, ur;
   int itl, itr, stl, str;
-  bool okl = face_state<d, MLP, I>(s, 1, cl[0], cl[1], cl[2], theta, mlp, wl, itl, stl, cnt.mlp);
-  bool okr = face_state<d, MLP, I>(s, 0, cr[0], cr[1], cr[2], theta, mlp, wr, itr, str, cnt.mlp);
+  bool okl = face_state<d, MLP, I>(s, 1, cl[0], cl[1], cl[2], theta, mlp, wl, ul, itl, stl, cnt.mlp);
+  bool okr = face_state<d, MLP, I>(s, 0, cr[0], cr[1], cr[2], theta, mlp, wr, ur, itr, str, cnt.mlp);
   cnt.iters += itl + itr;
   cnt.inv += 2;
   cnt.fb += (stl == ST_FALLBACK) + (str == ST_FALLBACK);
   cnt.nc += (stl == ST_NOCONV) + (str == ST_NOCONV);
   cnt.unphys += !okl + !okr;
-  Cons<T> F = solver == SRHD_HLLE ? hlle<d>(wl, wr) : hllc<d>(wl, wr);
+  // the face states' conserved variables are the ones just inverted: no round trip through
+  // prim -> cons
+  Cons<T> F = solver == SRHD_HLLE ? hlle<d>(wl, wr, ul, ur) : hllc<d>(wl, wr, ul, ur);
   constexpr int slot = d & 1;
   s.F[slot][0][r] = F.D;
   s.F[slot][1][r] = F.m[0];
