@@ -187,7 +187,9 @@ int srhd_stats_reset(srhd_step_stats *stats, void *stream);
  *   out[p] = U^n - dt_l/dh_l sum_d (F_{d,+1/2} - F_{d,-1/2}).
  * A patch meeting an unphysical state is redone with theta *= 0.75 (max_retry times) and then
  * theta = 0 (Sec. 3.4).  dt_lev: device double[n_level] (e.g. from srhd_cfl_dt).
- * out: [n_patch][5][8][8][8] FP64; must not overlap in->padded.  stats may be NULL. */
+ * out: [n_patch][5][8][8][8] FP64; must not overlap in->padded (nor prm->sched.queue).
+ * stats may be NULL.  Precision (prm->prec) and launch schedule (prm->sched) are described at
+ * srhd_prec and srhd_sched; every schedule gives the same results bit for bit. */
 int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
                     const srhd_step_params *prm, srhd_step_stats *stats, void *stream);
 
@@ -238,7 +240,8 @@ typedef struct {
 } srhd_grid;
 
 /* Entry state of a chain of srhd_fluid_step_grid calls: inverts every interior cell (as
- * srhd_cons2prim with the analytic guess, Newton tolerance of the step's precision), writes the
+ * srhd_cons2prim, from the guess `guess` selects -- NULL: the analytic guess -- with the Newton
+ * tolerance and inversion type of the step's precision), writes the
  * primitives in the step's bulk type, and the maximum S_max (Eqs. 26-27) over the cells as the
  * bit pattern of a positive double in *smax_bits (device; zeroed first).  Unphysical cells get
  * NaN primitives and do not enter the maximum. */
