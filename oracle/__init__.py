@@ -71,7 +71,11 @@ def lib():
         fn.argtypes = [ctypes.c_int, _p, _p, _p]
         fn.restype = None
     L.or_fluid_step.argtypes = [_i64, ctypes.c_int, _p, _p, _p, _p, _d, ctypes.c_int,
-                                ctypes.c_int, _p, _p]
+                                ctypes.c_int, ctypes.c_int, _p, _p]
+    L.or_prim2cons_total.argtypes = [_i64, _p, _p]
+    L.or_prim2cons_total.restype = None
+    L.or_cons2prim_total_one.argtypes = [_p, _p, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_int)]
+    L.or_cons2prim_total_one.restype = ctypes.c_int
     L.or_is_physical.argtypes = [_p]
     L.or_is_physical.restype = ctypes.c_int
     L.or_fluid_step.restype = ctypes.c_int
@@ -184,13 +188,24 @@ def riemann(d, wl, wr, solver=HLLC):
 
 
 # ---------------------------------------------------------------- batch forms
-def prim2cons(prim):
-    """prim [5][n] (rho, Ux, Uy, Uz, p) -> cons [5][n] (D, Mx, My, Mz, Et), FP64."""
+def prim2cons(prim, scheme=0):
+    """prim [5][n] (rho, Ux, Uy, Uz, p) -> cons [5][n] (D, Mx, My, Mz, Et), FP64; with scheme=1
+    the original scheme's (D, Mx, My, Mz, E), E the total energy of Eq. 5c."""
     prim = _f64(prim)
     n = prim.shape[-1]
     cons = np.empty_like(prim)
-    lib().or_prim2cons(n, _ptr(prim), _ptr(cons))
+    (lib().or_prim2cons_total if scheme else lib().or_prim2cons)(n, _ptr(prim), _ptr(cons))
     return cons
+
+
+def cons2prim_total_one(u):
+    """Original scheme: (D, M, E) -> (prim, status) with the naive L of Eq. 21."""
+    u = _f64(u)
+    w = np.empty(5)
+    ht = ctypes.c_double()
+    it = ctypes.c_int()
+    st = lib().or_cons2prim_total_one(_ptr(u), _ptr(w), ctypes.byref(ht), ctypes.byref(it))
+    return w, st
 
 
 def cons2prim(cons):
@@ -253,7 +268,7 @@ def extract_interior(padded, ghost=3):
 
 
 def fluid_step(padded, dt_lev, dh_lev, level=None, theta=1.5, solver=HLLC, ghost=3,
-               max_retry=4):
+               max_retry=4, scheme=0):
     """One MUSCL-Hancock step of every padded patch [P][5][N][N][N] -> interior [P][5][8][8][8].
 
     Returns (out, counts) with counts = (unphysical states in the final attempt, non-converged
@@ -268,7 +283,7 @@ def fluid_step(padded, dt_lev, dh_lev, level=None, theta=1.5, solver=HLLC, ghost
     lv = None if level is None else np.ascontiguousarray(level, dtype=np.int8)
     rc = lib().or_fluid_step(P, ghost, _ptr(padded), None if lv is None else _ptr(lv),
                              _ptr(dh_lev), _ptr(dt_lev), float(theta), int(solver),
-                             int(max_retry), _ptr(out), _ptr(counts))
+                             int(max_retry), int(scheme), _ptr(out), _ptr(counts))
     if rc != 0:
         raise ValueError("ghost depth must be at least 2")
     return out, counts

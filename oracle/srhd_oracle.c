@@ -27,6 +27,10 @@
  *                            the reduced energy (E = Et + D); fluxes of Eqs. 4a, 4b, 7
  *   MUSCL-Hancock step       Sec. 3.2 (unsplit half step + full step)
  *   ghost fill               Sec. 3.1 (8^3 patches), periodic or outflow (zero gradient)
+ *   original scheme          Sec. 2.3 / 4: the total energy E (Eq. 5c) evolved with flux M
+ *                            (Eq. 4b), L = (E/D)^2 - (|M|/D)^2 - 1 from the divided variables
+ *                            (the cancellation Eq. 21 quantifies); kept to reproduce the
+ *                            paper's comparison (Sec. 4.1, Eq. 32)
  *
  * "Parity unpinned" items: none of the functions above lacks a pin; see the test suite.
  */
@@ -320,6 +324,65 @@ int or_cons2prim_one(const double u[5], double w[5], double *ht_out, int *iters)
   return OR_ST_OK;
 }
 
+/* Original scheme: prim -> (D, Mx, My, Mz, E) with E = rho h gamma^2 - p (Eq. 5c), h of Eq. 10. */
+void or_prim2cons_total_one(const double w[5], double u[5])
+{
+  double rho = w[0], ux = w[1], uy = w[2], uz = w[3], p = w[4];
+  double U2 = ux * ux + uy * uy + uz * uz;
+  double gam = sqrt(1.0 + U2);
+  double D = rho * gam;
+  double h = or_h_of_theta(p / rho);
+  double Dh = D * h;
+  u[0] = D;
+  u[1] = Dh * ux;
+  u[2] = Dh * uy;
+  u[3] = Dh * uz;
+  u[4] = Dh * gam - p;
+}
+
+/* Original scheme: (D, M, E) -> prim with L = (E/D)^2 - (|M|/D)^2 - 1 evaluated from the divided
+ * variables (Eq. 21's cancellation), the same root of Eq. 15 and the same recovery. */
+int or_cons2prim_total_one(const double u[5], double w[5], double *ht_out, int *iters)
+{
+  double D = u[0], Mx = u[1], My = u[2], Mz = u[3], E = u[4];
+  int it = 0;
+  double L = (isfinite(D) && isfinite(Mx) && isfinite(My) && isfinite(Mz) && isfinite(E) &&
+              D > 0.0 && E > 0.0) ? or_L_total_energy(D, Mx, My, Mz, E) : 0.0;
+  if (!(L > DBL_EPSILON)) {
+    for (int k = 0; k < 5; k++) w[k] = NAN;
+    if (ht_out) *ht_out = NAN;
+    if (iters) *iters = 0;
+    return OR_ST_UNPHYSICAL;
+  }
+  double mx = Mx / D, my = My / D, mz = Mz / D;
+  double m2 = mx * mx + my * my + mz * mz;
+  double ht = or_solve_htilde(L, m2, &it);
+  double h = 1.0 + ht;
+  double ux = Mx / (D * h), uy = My / (D * h), uz = Mz / (D * h);
+  double gam = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
+  double rho = D / gam;
+  double th = or_theta_of_htilde(ht);
+  w[0] = rho;
+  w[1] = ux;
+  w[2] = uy;
+  w[3] = uz;
+  w[4] = rho * th;
+  if (ht_out) *ht_out = ht;
+  if (iters) *iters = it;
+  return OR_ST_OK;
+}
+
+void or_prim2cons_total(int64_t n, const double *prim, double *cons)
+{
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; i++) {
+    double w[5], u[5];
+    for (int k = 0; k < 5; k++) w[k] = prim[k * n + i];
+    or_prim2cons_total_one(w, u);
+    for (int k = 0; k < 5; k++) cons[k * n + i] = u[k];
+  }
+}
+
 /* Batch forms over structure-of-arrays [5][n]. */
 void or_prim2cons(int64_t n, const double *prim, double *cons)
 {
@@ -454,15 +517,43 @@ void or_wavespeeds(int d, const double w[5], double *lm, double *lp)
   *lp = (gam * Ud * a + s) / den;
 }
 
+/* The energy variable of a scheme: 0 the reduced energy Et (this paper), 1 the total energy E
+ * (the original scheme, evolved with the flux M_d of Eq. 4b). */
+static void sc_prim2cons(int scheme, const double w[5], double u[5])
+{
+  if (scheme) or_prim2cons_total_one(w, u);
+  else or_prim2cons_one(w, u);
+}
+
+static int sc_cons2prim(int scheme, const double u[5], double w[5], int *iters)
+{
+  return scheme ? or_cons2prim_total_one(u, w, NULL, iters) : or_cons2prim_one(u, w, NULL, iters);
+}
+
+static void sc_flux(int scheme, int d, const double w[5], const double u[5], double F[5])
+{
+  or_flux(d, w, u, F);
+  if (scheme) F[4] = u[1 + d];              /* (E + p) v_d = M_d */
+}
+
+static int sc_is_physical(int scheme, const double u[5])
+{
+  if (!scheme) return or_is_physical(u);
+  if (!(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]) && isfinite(u[3]) && isfinite(u[4])))
+    return 0;
+  if (!(u[0] > 0.0) || !(u[4] > 0.0)) return 0;
+  return or_L_total_energy(u[0], u[1], u[2], u[3], u[4]) > DBL_EPSILON;
+}
+
 /* HLLE flux along d between left/right primitive states. */
-void or_hlle(int d, const double wl[5], const double wr[5], double F[5])
+static void sc_hlle(int scheme, int d, const double wl[5], const double wr[5], double F[5])
 {
   double ul[5], ur[5], fl[5], fr[5];
   double lmL, lpL, lmR, lpR;
-  or_prim2cons_one(wl, ul);
-  or_prim2cons_one(wr, ur);
-  or_flux(d, wl, ul, fl);
-  or_flux(d, wr, ur, fr);
+  sc_prim2cons(scheme, wl, ul);
+  sc_prim2cons(scheme, wr, ur);
+  sc_flux(scheme, d, wl, ul, fl);
+  sc_flux(scheme, d, wr, ur, fr);
   or_wavespeeds(d, wl, &lmL, &lpL);
   or_wavespeeds(d, wr, &lmR, &lpR);
   double sl = fmin(fmin(lmL, lmR), 0.0);
@@ -470,6 +561,8 @@ void or_hlle(int d, const double wl[5], const double wr[5], double F[5])
   for (int k = 0; k < 5; k++)
     F[k] = (sr * fl[k] - sl * fr[k] + sr * sl * (ur[k] - ul[k])) / (sr - sl);
 }
+
+void or_hlle(int d, const double wl[5], const double wr[5], double F[5]) { sc_hlle(0, d, wl, wr, F); }
 
 /* HLLC flux along d (Mignone & Bodo 2005, as adapted in Sec. 3.2 to the TM sound speed and to
  * the reduced energy).  The HLL average of the total energy E = Et + D (flux M_d) and of M_d
@@ -480,14 +573,14 @@ void or_hlle(int d, const double wl[5], const double wr[5], double F[5])
  *   M_d* = [M_d (S - v) + p* - p] / (S - l*),
  *   Et* = [Et (S - v) + p* l* - p v] / (S - l*)   (= E* - D*, no rest-mass cancellation),
  * and F* = F_K + S (U* - U_K). */
-void or_hllc(int d, const double wl[5], const double wr[5], double F[5])
+static void sc_hllc(int scheme, int d, const double wl[5], const double wr[5], double F[5])
 {
   double ul[5], ur[5], fl[5], fr[5];
   double lmL, lpL, lmR, lpR;
-  or_prim2cons_one(wl, ul);
-  or_prim2cons_one(wr, ur);
-  or_flux(d, wl, ul, fl);
-  or_flux(d, wr, ur, fr);
+  sc_prim2cons(scheme, wl, ul);
+  sc_prim2cons(scheme, wr, ur);
+  sc_flux(scheme, d, wl, ul, fl);
+  sc_flux(scheme, d, wr, ur, fr);
   or_wavespeeds(d, wl, &lmL, &lpL);
   or_wavespeeds(d, wr, &lmR, &lpR);
   double sl = fmin(lmL, lmR);
@@ -499,8 +592,8 @@ void or_hllc(int d, const double wl[5], const double wr[5], double F[5])
     uh[k] = (sr * ur[k] - sl * ul[k] + fl[k] - fr[k]) / (sr - sl);
     fh[k] = (sl * sr * (ur[k] - ul[k]) + sr * fl[k] - sl * fr[k]) / (sr - sl);
   }
-  double E = uh[4] + uh[0];          /* total energy of the HLL state */
-  double FE = fh[4] + fh[0];         /* its flux */
+  double E = scheme ? uh[4] : uh[4] + uh[0];     /* total energy of the HLL state */
+  double FE = scheme ? fh[4] : fh[4] + fh[0];    /* its flux */
   double m = uh[1 + d];
   double Fm = fh[1 + d];
   double B = E + Fm;
@@ -520,9 +613,11 @@ void or_hllc(int d, const double wl[5], const double wr[5], double F[5])
   us[0] = u[0] * (S - v) * inv;
   for (int k = 0; k < 3; k++) us[1 + k] = u[1 + k] * (S - v) * inv;
   us[1 + d] = (u[1 + d] * (S - v) + ps - p) * inv;
-  us[4] = (u[4] * (S - v) + ps * ls - p * v) * inv;
+  us[4] = (u[4] * (S - v) + ps * ls - p * v) * inv;     /* the same form for Et* and E* */
   for (int k = 0; k < 5; k++) F[k] = f[k] + S * (us[k] - u[k]);
 }
+
+void or_hllc(int d, const double wl[5], const double wr[5], double F[5]) { sc_hllc(0, d, wl, wr, F); }
 
 /* ===================================================================================== */
 /* MUSCL-Hancock step on one padded patch                                                */
@@ -572,6 +667,7 @@ typedef struct {
   unsigned char have[OB * OB * OB];
   const or_patch *P;
   or_counts *cnt;
+  int scheme;
 } or_prim_cache;
 
 static const double *or_cell_prim(or_prim_cache *C, int i, int j, int k)
@@ -581,7 +677,7 @@ static const double *or_cell_prim(or_prim_cache *C, int i, int j, int k)
     double u[5];
     int it = 0;
     for (int f = 0; f < 5; f++) u[f] = or_get(C->P, f, i, j, k);
-    int st = or_cons2prim_one(u, C->w[id], NULL, &it);
+    int st = sc_cons2prim(C->scheme, u, C->w[id], &it);
     if (st == OR_ST_UNPHYSICAL) { C->cnt->unphys++; C->cnt->centre_bad = 1; }
     C->cnt->iters += it;
     C->have[id] = 1;
@@ -592,11 +688,12 @@ static const double *or_cell_prim(or_prim_cache *C, int i, int j, int k)
 /* Step of one patch with limiter coefficient theta.  Writes out[5][512], the updated interior
  * conserved variables, and returns the number of them that fail the physical check (Eq. 30). */
 static int or_step_patch(const or_patch *P, double dt, double dh, double theta, int riemann,
-                          double *out, or_counts *cnt)
+                          int scheme, double *out, or_counts *cnt)
 {
   or_prim_cache *C = (or_prim_cache *)calloc(1, sizeof(or_prim_cache));
   C->P = P;
   C->cnt = cnt;
+  C->scheme = scheme;
   /* Half-step face conserved states U_face^{n+1/2} of the cells that need them:
    * hf[cell][d][s][field], s = 0 for the minus face, 1 for the plus face. */
   double (*hf)[3][2][5] = (double (*)[3][2][5])calloc(OB * OB * OB, sizeof(*hf));
@@ -617,8 +714,8 @@ static int or_step_patch(const or_patch *P, double dt, double dh, double theta, 
             wf[d][1][f] = wc[f] + 0.5 * s;
           }
           for (int s = 0; s < 2; s++) {
-            or_prim2cons_one(wf[d][s], uf[d][s]);
-            or_flux(d, wf[d][s], uf[d][s], ff[d][s]);
+            sc_prim2cons(scheme, wf[d][s], uf[d][s]);
+            sc_flux(scheme, d, wf[d][s], uf[d][s], ff[d][s]);
           }
         }
         double corr[5];
@@ -647,14 +744,14 @@ static int or_step_patch(const or_patch *P, double dt, double dh, double theta, 
           cl[d] = c - 1;
           double wl[5], wr[5];
           int itl = 0, itr = 0;
-          int stl = or_cons2prim_one(hf[OIDX(cl[0], cl[1], cl[2])][d][1], wl, NULL, &itl);
-          int str = or_cons2prim_one(hf[OIDX(cr[0], cr[1], cr[2])][d][0], wr, NULL, &itr);
+          int stl = sc_cons2prim(scheme, hf[OIDX(cl[0], cl[1], cl[2])][d][1], wl, &itl);
+          int str = sc_cons2prim(scheme, hf[OIDX(cr[0], cr[1], cr[2])][d][0], wr, &itr);
           cnt->unphys += (stl == OR_ST_UNPHYSICAL) + (str == OR_ST_UNPHYSICAL);
           if (stl == OR_ST_UNPHYSICAL || str == OR_ST_UNPHYSICAL) cnt->face_bad = 1;
           cnt->iters += itl + itr;
           double *F = fx[(d * 64 + a * 8 + b) * 9 + c];
-          if (riemann == OR_HLLE) or_hlle(d, wl, wr, F);
-          else or_hllc(d, wl, wr, F);
+          if (riemann == OR_HLLE) sc_hlle(scheme, d, wl, wr, F);
+          else sc_hllc(scheme, d, wl, wr, F);
         }
   /* Full update: U^{n+1} = U^n - (dt/dh) sum_d (F_{+1/2} - F_{-1/2}). */
   double full = dt / dh;
@@ -678,7 +775,7 @@ static int or_step_patch(const or_patch *P, double dt, double dh, double theta, 
   for (int c = 0; c < 512; c++) {
     double u[5];
     for (int f = 0; f < 5; f++) u[f] = out[f * 512 + c];
-    nbad += !or_is_physical(u);
+    nbad += !sc_is_physical(scheme, u);
   }
   free(fx);
   free(hf);
@@ -695,7 +792,7 @@ static int or_step_patch(const or_patch *P, double dt, double dh, double theta, 
  *           inversions, solver iterations, retried attempts}. */
 int or_fluid_step(int64_t n_patch, int ghost, const double *padded, const int8_t *level,
                   const double *dh_lev, const double *dt_lev, double theta, int riemann,
-                  int max_retry, double *out, int64_t *counts)
+                  int max_retry, int scheme, double *out, int64_t *counts)
 {
   if (ghost < 2) return -1;
   int N = PS + 2 * ghost;
@@ -708,7 +805,7 @@ int or_fluid_step(int64_t n_patch, int ghost, const double *padded, const int8_t
     double th = theta;
     for (int attempt = 0;; attempt++) {
       or_counts c = {0, 0, 0, 0, 0};
-      int nbad = or_step_patch(&P, dt_lev[lv], dh_lev[lv], th, riemann, out + p * NF * 512, &c);
+      int nbad = or_step_patch(&P, dt_lev[lv], dh_lev[lv], th, riemann, scheme, out + p * NF * 512, &c);
       iters += c.iters;
       int fail = c.face_bad || nbad > 0;
       if (!fail || c.centre_bad || th == 0.0) {

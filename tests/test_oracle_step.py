@@ -122,41 +122,18 @@ def test_mirror_symmetry():
         assert np.allclose(a[f], b[f], rtol=1e-12, atol=1e-12 * np.abs(a[f]).max()), f
 
 
-def _sine_1d(n, theta0, amp, t_frac, theta_lim=1.5):
-    """Right-moving linear acoustic wave along x on an n-cell periodic row; returns the L1
-    density error (Eq. 31) after t_frac of a period."""
-    g = W.PatchGrid("w", np.zeros((n // 8, 5, 8, 8, 8)), n // 8, 1, 1, True, 1.0 / n)
-    x, _, _ = W.patch_cell_centres(n // 8, 1, 1, 1.0 / n)
-    rho0, p0 = 1.0, theta0
-    cs2 = O.cs2(theta0)
-    cs = math.sqrt(cs2)
-    h0 = O.h_of_theta(theta0)
-    s = np.sin(2 * np.pi * x)
-    # linear eigenvector of a right-moving sound wave: dp = h cs^2 drho, dv = cs drho / rho
-    g.prim[:, 0] = rho0 * (1 + amp * s)
-    g.prim[:, 4] = p0 + h0 * cs2 * rho0 * amp * s
-    g.prim[:, 1] = cs * amp * s
-    # the grid average of sin over a cell is sin(centre) * sinc(dh): compare like with like
-    t_end = t_frac / cs
-    c0 = drv.initial_cons(g)
-    c1, t, k = drv.run(g, c0, t_end=t_end, theta=theta_lim)
-    w, _ = drv.to_prim(c1)
-    exact = rho0 * (1 + amp * np.sin(2 * np.pi * (x - cs * t)))
-    return np.mean(np.abs(1 - w[:, 0] / exact))
-
-
 @pytest.mark.slow
 def test_smooth_wave_second_order():
     # Sec. 4.1: PLM + MUSCL-Hancock converges as N^-2 in both temperature limits.
     for th in (1e10, 1e-10):
-        e = [_sine_1d(n, th, 1e-6, 0.25) for n in (16, 32, 64)]
+        e = [drv.sine_x_l1(n, th, 1e-6, 0.25) for n in (16, 32, 64)]
         r1, r2 = e[0] / e[1], e[1] / e[2]
         assert r1 > 3.0 and r2 > 3.0, (th, e)
 
 
 def test_zero_limiter_is_first_order():
     # theta -> 0 makes every slope zero: piecewise-constant reconstruction (Sec. 3.4).
-    e = [_sine_1d(n, 1.0, 1e-6, 0.25, theta_lim=0.0) for n in (16, 32)]
+    e = [drv.sine_x_l1(n, 1.0, 1e-6, 0.25, theta_lim=0.0) for n in (16, 32)]
     r = e[0] / e[1]
     assert 1.5 < r < 2.6, e
 
