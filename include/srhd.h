@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define SRHD_ABI_VERSION 2
+#define SRHD_ABI_VERSION 3
 
 typedef enum { SRHD_F64 = 0, SRHD_F32 = 1 } srhd_dtype;
 
@@ -57,6 +57,16 @@ typedef enum { SRHD_HLLC = 0, SRHD_HLLE = 1 } srhd_riemann;
  * (the cancellation of Eq. 20) is formed in FP64, exactly, from the FP32 variables.  State
  * storage stays FP64 in every mode. */
 typedef enum { SRHD_PREC_FP64 = 0, SRHD_PREC_MIXED = 1, SRHD_PREC_FP32 = 2 } srhd_prec;
+
+/* The energy variable a step evolves (Sec. 4 compares the two).  REDUCED: Et = E - D (Eq. 23),
+ * this paper's scheme, with the flux (Et + p) v_d and L formed without cancellation (Eq. 15).
+ * TOTAL: the original scheme -- the fifth conserved slot holds the total energy E of Eq. 5c,
+ * evolved with the flux M_d, and every inversion forms L = (E/D)^2 - (|M|/D)^2 - 1 from the
+ * divided variables in the inversion's arithmetic (Eq. 21), whose relative error grows as
+ * 4 eps / (3 Theta) for a cold gas (Eq. 32).  TOTAL runs in srhd_fluid_step with
+ * SRHD_PREC_FP64 or SRHD_PREC_FP32 and the analytic guess only (else SRHD_EUNSUPPORTED); the
+ * physical check of its states is D > 0, E > 0 and that L > DBL_EPSILON. */
+typedef enum { SRHD_ENERGY_REDUCED = 0, SRHD_ENERGY_TOTAL = 1 } srhd_energy;
 
 /* Learned initial guess: device parameters of a 3-64-64-1 SiLU perceptron that maps three
  * standardised log-scaled invariants of the conserved state to the standardised log of the
@@ -164,6 +174,7 @@ typedef struct {
   int max_retry;           /* reductions theta *= 0.75 before the final theta = 0 attempt */
   srhd_guess guess;        /* initial guess for every inversion in the step */
   srhd_sched sched;        /* launch schedule; all-zero = one workgroup per patch */
+  int energy;              /* srhd_energy (0: this paper's reduced energy) */
 } srhd_step_params;
 
 /* Device counters, accumulated (never reset by the step; see srhd_stats_reset). */
@@ -188,16 +199,18 @@ int srhd_stats_reset(srhd_step_stats *stats, void *stream);
  * A patch meeting an unphysical state is redone with theta *= 0.75 (max_retry times) and then
  * theta = 0 (Sec. 3.4).  dt_lev: device double[n_level] (e.g. from srhd_cfl_dt).
  * out: [n_patch][5][8][8][8] FP64; must not overlap in->padded (nor prm->sched.queue).
- * stats may be NULL.  Precision (prm->prec) and launch schedule (prm->sched) are described at
- * srhd_prec and srhd_sched; every schedule gives the same results bit for bit. */
+ * stats may be NULL.  Precision (prm->prec), launch schedule (prm->sched) and energy variable
+ * (prm->energy) are described at srhd_prec, srhd_sched and srhd_energy; every schedule gives the
+ * same results bit for bit. */
 int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
                     const srhd_step_params *prm, srhd_step_stats *stats, void *stream);
 
 /* Workgroups of the step kernel that fit on one compute unit at once for the given precision,
- * guess kind (srhd_guess_kind), layout (gather = 1: srhd_fluid_step_grid, 0: srhd_fluid_step) and
- * register variant (occupancy field of srhd_sched); multiplied by the device's compute-unit count
- * it sizes a persistent schedule.  Returns the count (> 0), or a negative srhd_err. */
-int srhd_step_occupancy(int prec, int guess_kind, int gather, int occupancy);
+ * guess kind (srhd_guess_kind), layout (gather = 1: srhd_fluid_step_grid, 0: srhd_fluid_step),
+ * register variant (occupancy field of srhd_sched) and energy variable (srhd_energy);
+ * multiplied by the device's compute-unit count it sizes a persistent schedule.  Returns the
+ * count (> 0), or a negative srhd_err (SRHD_EUNSUPPORTED for a combination that has no kernel). */
+int srhd_step_occupancy(int prec, int guess_kind, int gather, int occupancy, int energy);
 
 /* Schedule autotuner for srhd_fluid_step.  Runs the step on `in` (writing `out`) once per
  * candidate schedule as a warm-up and then `reps` timed times, timed with events on `stream`,
@@ -255,7 +268,8 @@ int srhd_grid_prims(int prec, int64_t n_patch, const double *cons, void *prims,
  * prims_out (bulk type) and *smax_out (zeroed, then the maximum over the updated cells);
  * dt_used (device double[n_level], may be NULL) receives the time step used.
  * Outputs must not overlap the inputs.  Patches are mapped to workgroups so that each XCD works
- * on a contiguous range of patch indices (order patches along a space-filling curve). */
+ * on a contiguous range of patch indices (order patches along a space-filling curve).  The
+ * reduced energy only (prm->energy = SRHD_ENERGY_TOTAL gives SRHD_EUNSUPPORTED). */
 int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_cfl,
                          const double *dt_lev, double *cons_out, void *prims_out,
                          uint64_t *smax_out, double *dt_used, const srhd_step_params *prm,

@@ -57,6 +57,20 @@ int check_guess(const srhd_guess *g, srhd::GuessArgs &out)
   return fail(SRHD_EINVAL, "unknown guess kind %d", g->kind);
 }
 
+// Energy variable of a step (include/srhd.h, srhd_energy): the original scheme has kernels for the
+// padded layout with equal bulk and inversion types and the analytic guess.
+int check_energy(int energy, int prec, int guess_kind, int gather, const char *who)
+{
+  if (energy == SRHD_ENERGY_REDUCED) return SRHD_OK;
+  if (energy != SRHD_ENERGY_TOTAL) return fail(SRHD_EINVAL, "%s: unknown energy variable %d", who, energy);
+  if (gather) return fail(SRHD_EUNSUPPORTED, "%s: the total-energy scheme runs on padded patches only", who);
+  if (prec == SRHD_PREC_MIXED)
+    return fail(SRHD_EUNSUPPORTED, "%s: the total-energy scheme runs in FP64 or FP32 only", who);
+  if (guess_kind != SRHD_GUESS_ANALYTIC)
+    return fail(SRHD_EUNSUPPORTED, "%s: the total-energy scheme takes the analytic guess only", who);
+  return SRHD_OK;
+}
+
 // Launch schedule of a step (include/srhd.h, srhd_sched).
 int check_sched(const srhd_sched &sc, int prec, int guess_kind, srhd::StepArgs &s, const char *who)
 {
@@ -195,6 +209,8 @@ int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
   srhd::GuessArgs g;
   int rc = check_guess(&prm->guess, g);
   if (rc) return rc;
+  rc = check_energy(prm->energy, prm->prec, g.kind, 0, "srhd_fluid_step");
+  if (rc) return rc;
   if (in->n_patch == 0) return SRHD_OK;
   if (!in->padded || !out || !dt_lev) return fail(SRHD_EINVAL, "srhd_fluid_step: NULL array");
   if (!aligned(in->padded, 8) || !aligned(out, 8) || !aligned(dt_lev, 8))
@@ -228,6 +244,7 @@ int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
   s.c_cfl = 0.0;
   s.dt_out = nullptr;
   s.xcd_remap = 0;
+  s.energy = prm->energy;
   rc = check_sched(prm->sched, prm->prec, g.kind, s, "srhd_fluid_step");
   if (rc) return rc;
   if (s.queue) {
@@ -238,7 +255,7 @@ int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
   return hip_status(srhd::launch_step(prm->prec, s, (hipStream_t)stream), "srhd_fluid_step");
 }
 
-int srhd_step_occupancy(int prec, int guess_kind, int gather, int occupancy)
+int srhd_step_occupancy(int prec, int guess_kind, int gather, int occupancy, int energy)
 {
   if (prec != SRHD_PREC_FP64 && prec != SRHD_PREC_MIXED && prec != SRHD_PREC_FP32)
     return fail(SRHD_EINVAL, "srhd_step_occupancy: bad precision %d", prec);
@@ -248,7 +265,10 @@ int srhd_step_occupancy(int prec, int guess_kind, int gather, int occupancy)
     return fail(SRHD_EINVAL, "srhd_step_occupancy: occupancy %d is neither 0 nor 2", occupancy);
   if (occupancy == 2 && prec == SRHD_PREC_FP64)
     return fail(SRHD_EUNSUPPORTED, "srhd_step_occupancy: occupancy 2 needs an FP32 bulk");
-  int n = srhd::step_occupancy(prec, gather != 0, guess_kind == SRHD_GUESS_MLP, occupancy == 2);
+  int rc = check_energy(energy, prec, guess_kind, gather, "srhd_step_occupancy");
+  if (rc) return rc;
+  const int kind = energy == SRHD_ENERGY_TOTAL ? 2 : (guess_kind == SRHD_GUESS_MLP ? 1 : 0);
+  int n = srhd::step_occupancy(prec, gather != 0, kind, occupancy == 2);
   if (n <= 0) return fail(SRHD_EHIP, "srhd_step_occupancy: occupancy query failed");
   return n;
 }
@@ -276,7 +296,7 @@ int autotune(srhd_step_params *prm, int gather, int reps, srhd_tune_entry *table
   const bool two = prm->prec != SRHD_PREC_FP64;
   for (int occ : {0, 2}) {
     if (occ == 2 && !two) continue;
-    int per_cu = srhd_step_occupancy(prm->prec, prm->guess.kind, gather, occ);
+    int per_cu = srhd_step_occupancy(prm->prec, prm->guess.kind, gather, occ, prm->energy);
     if (per_cu <= 0) return per_cu < 0 ? per_cu : fail(SRHD_EHIP, "%s: occupancy 0", who);
     cand[nc++] = {0, 1, occ};
     for (int m : {1, 2, 4})
@@ -457,6 +477,8 @@ int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_
   srhd::GuessArgs g;
   int rc = check_guess(&prm->guess, g);
   if (rc) return rc;
+  rc = check_energy(prm->energy, prm->prec, g.kind, 1, "srhd_fluid_step_grid");
+  if (rc) return rc;
   if (!smax_out) return fail(SRHD_EINVAL, "srhd_fluid_step_grid: NULL smax_out");
   if (!dt_lev && (!smax_in || !(c_cfl > 0.0)))
     return fail(SRHD_EINVAL, "srhd_fluid_step_grid: need dt_lev, or smax_in and c_cfl > 0");
@@ -502,6 +524,7 @@ int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_
   s.c_cfl = c_cfl;
   s.dt_out = dt_used;
   s.xcd_remap = 1;
+  s.energy = SRHD_ENERGY_REDUCED;
   rc = check_sched(prm->sched, prm->prec, g.kind, s, "srhd_fluid_step_grid");
   if (rc) return rc;
   return hip_status(srhd::launch_step_grid(prm->prec, s, (hipStream_t)stream),

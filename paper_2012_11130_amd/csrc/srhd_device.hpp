@@ -9,10 +9,11 @@
 //   * prim -> cons (Eqs. 8, 5a, 5b, 22, 15, 23) and the recovery after the root (Eqs. 17, 8,
 //     5a, 16, 18);
 //   * fluxes (Eqs. 4a, 4b, 7), signal speeds and the HLLE / HLLC Riemann solvers adapted to
-//     the TM sound speed and to the reduced energy (Sec. 3.2).
-// Templates take the bulk arithmetic type T (double, or float on the mixed-precision path).
-// The inversion always runs in double.
+//     the TM sound speed and to the reduced energy (Sec. 3.2);
+//   * the original scheme's total-energy variables, flux and naive L (Sec. 4, Eqs. 5c, 21).
+// Templates take the bulk arithmetic type T (double or float) and the inversion type.
 #pragma once
+#include <float.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -317,11 +318,57 @@ __device__ __forceinline__ Cons<T> prim2cons(const Prim<T> &w)
   return u;
 }
 
+// The original scheme's conserved variables (Sec. 4): D and M as above and, in the energy slot,
+// the total energy E = D h gamma - p of Eq. 5c (h = 1 + ht, Eq. 10) instead of Et.
+template <class T>
+__device__ __forceinline__ Cons<T> prim2cons_total(const Prim<T> &w)
+{
+  T U2 = w.u[0] * w.u[0] + w.u[1] * w.u[1] + w.u[2] * w.u[2];
+  T gam = sq(T(1) + U2);
+  T D = w.rho * gam;
+  T h = T(1) + htilde_of_theta(dv(w.p, w.rho));
+  T Dh = D * h;
+  Cons<T> u;
+  u.D = D;
+  u.m[0] = Dh * w.u[0];
+  u.m[1] = Dh * w.u[1];
+  u.m[2] = Dh * w.u[2];
+  u.E = Dh * gam - w.p;
+  return u;
+}
+
+template <bool TOT, class T>
+__device__ __forceinline__ Cons<T> prim2cons_s(const Prim<T> &w)
+{
+  if constexpr (TOT) return prim2cons_total(w);
+  else return prim2cons(w);
+}
+
+// The original scheme's physical check and left-hand side of Eq. 15: L = (E/D)^2 - (|M|/D)^2 - 1
+// formed from the divided variables in the arithmetic of type I (Eq. 21), with correctly rounded
+// divisions and no fused multiply-adds, so that its cancellation is that of the plain formula.
+// Returns whether the state is finite with D > 0, E > 0 and L > DBL_EPSILON; L = 0 otherwise.
+template <class I>
+__device__ __forceinline__ bool admissible_total(I D, I Mx, I My, I Mz, I E, double &L)
+{
+#pragma clang fp contract(off)
+  L = 0.0;
+  if (!(finiteT(D) && finiteT(Mx) && finiteT(My) && finiteT(Mz) && finiteT(E)) ||
+      !(D > I(0)) || !(E > I(0)))
+    return false;
+  const I e = E / D, mx = Mx / D, my = My / D, mz = Mz / D;
+  const I l = e * e - (mx * mx + my * my + mz * mz) - I(1);
+  const bool ok = (double)l > DBL_EPSILON;
+  if (ok) L = (double)l;
+  return ok;
+}
+
 // ------------------------------------------------------------------------------ fluxes
 // The direction d is a template parameter so that every component index is a constant.
 
-// Physical flux along d (Eqs. 4a, 4b, 7) with v_d = U_d / gamma.
-template <int d, class T>
+// Physical flux along d (Eqs. 4a, 4b, 7) with v_d = U_d / gamma.  TOT: the original scheme, whose
+// energy variable E has the flux (E + p) v_d = M_d.
+template <int d, bool TOT = false, class T>
 __device__ __forceinline__ Cons<T> phys_flux(const Prim<T> &w, const Cons<T> &u)
 {
   T gam = sq(T(1) + w.u[0] * w.u[0] + w.u[1] * w.u[1] + w.u[2] * w.u[2]);
@@ -332,7 +379,8 @@ __device__ __forceinline__ Cons<T> phys_flux(const Prim<T> &w, const Cons<T> &u)
   F.m[1] = u.m[1] * v;
   F.m[2] = u.m[2] * v;
   F.m[d] += w.p;
-  F.E = (u.E + w.p) * v;
+  if constexpr (TOT) F.E = u.m[d];
+  else F.E = (u.E + w.p) * v;
   return F;
 }
 
@@ -358,11 +406,12 @@ __device__ __forceinline__ void signal_speeds(const Prim<T> &w, T &lm, T &lp)
 
 // HLLE: HLL flux with S_L^- = min(S_L, 0), S_R^+ = max(S_R, 0).  ul, ur are the conserved
 // variables of wl, wr (the states the primitives were inverted from, where the caller has them).
-template <int d, class T>
+// TOT: the original scheme's variables (total energy E).
+template <int d, bool TOT = false, class T>
 __device__ __forceinline__ Cons<T> hlle(const Prim<T> &wl, const Prim<T> &wr, const Cons<T> &ul,
                                         const Cons<T> &ur)
 {
-  Cons<T> fl = phys_flux<d>(wl, ul), fr = phys_flux<d>(wr, ur);
+  Cons<T> fl = phys_flux<d, TOT>(wl, ul), fr = phys_flux<d, TOT>(wr, ur);
   T lmL, lpL, lmR, lpR;
   signal_speeds<d>(wl, lmL, lpL);
   signal_speeds<d>(wr, lmR, lpR);
@@ -394,11 +443,13 @@ __device__ __forceinline__ Cons<T> sel(bool c, const Cons<T> &a, const Cons<T> &
 // F^E l^2 - (E + F^m) l + m = 0 (root 2 m / (B + sqrt(B^2 - 4 F^E m)), B = E + F^m), the star
 // pressure p* = F^m - l* F^E, and the reduced-energy star state
 // Et* = [Et (S - v) + p* l* - p v] / (S - l*), which carries no rest-mass cancellation.
-template <int d, class T>
+// TOT: the original scheme, whose energy slot already holds E (and its flux M_d); its star state
+// E* takes the same form.
+template <int d, bool TOT = false, class T>
 __device__ __forceinline__ Cons<T> hllc(const Prim<T> &wl, const Prim<T> &wr, const Cons<T> &ul,
                                         const Cons<T> &ur)
 {
-  Cons<T> fl = phys_flux<d>(wl, ul), fr = phys_flux<d>(wr, ur);
+  Cons<T> fl = phys_flux<d, TOT>(wl, ul), fr = phys_flux<d, TOT>(wr, ur);
   T lmL, lpL, lmR, lpR;
   signal_speeds<d>(wl, lmL, lpL);
   signal_speeds<d>(wr, lmR, lpR);
@@ -408,10 +459,10 @@ __device__ __forceinline__ Cons<T> hllc(const Prim<T> &wl, const Prim<T> &wr, co
   T srl = sl * sr;
   // HLL averages of the quantities the contact speed needs
   T Dh = (sr * ur.D - sl * ul.D + fl.D - fr.D) * inv;
-  T Eh = (sr * ur.E - sl * ul.E + fl.E - fr.E) * inv + Dh;
+  T Eh = (sr * ur.E - sl * ul.E + fl.E - fr.E) * inv + (TOT ? T(0) : Dh);
   T mh = (sr * ur.m[d] - sl * ul.m[d] + fl.m[d] - fr.m[d]) * inv;
   T FDh = (srl * (ur.D - ul.D) + sr * fl.D - sl * fr.D) * inv;
-  T FEh = (srl * (ur.E - ul.E) + sr * fl.E - sl * fr.E) * inv + FDh;
+  T FEh = (srl * (ur.E - ul.E) + sr * fl.E - sl * fr.E) * inv + (TOT ? T(0) : FDh);
   T Fmh = (srl * (ur.m[d] - ul.m[d]) + sr * fl.m[d] - sl * fr.m[d]) * inv;
   T B = Eh + Fmh;
   T disc = maxT(B * B - T(4) * FEh * mh, T(0));

@@ -63,6 +63,7 @@ struct StepArgs {
   int groups;
   int chunk;
   int occ2;                             // the kernel variant that fits two workgroups per CU
+  int energy;                           // srhd_energy: SRHD_ENERGY_TOTAL runs the original scheme
 };
 
 hipError_t launch_step(int prec, const StepArgs &a, hipStream_t s);
@@ -70,14 +71,15 @@ hipError_t launch_step(int prec, const StepArgs &a, hipStream_t s);
 // per-precision launchers of the step (srhd_step_fp64.hip, srhd_step_mixed.hip, srhd_step_fp32.hip)
 #define SRHD_STEP_MODE(name)                                                                   \
   hipError_t step_launch_##name(const StepArgs &a, bool gather, hipStream_t st);               \
-  int step_occupancy_##name(bool gather, bool mlp, bool occ2);                                 \
+  int step_occupancy_##name(bool gather, int kind, bool occ2);                                 \
   hipError_t grid_prims_##name(int64_t n_patch, const double *cons, void *prims,               \
                                unsigned long long *smax_bits, const GuessArgs &g, hipStream_t st);
 SRHD_STEP_MODE(fp64)
 SRHD_STEP_MODE(mixed)
 SRHD_STEP_MODE(fp32)
 #undef SRHD_STEP_MODE
-int step_occupancy(int prec, bool gather, bool mlp, bool occ2);   // workgroups per CU, 0 on error
+// workgroups per CU, 0 on error; kind: 0 analytic guess, 1 learned guess, 2 original scheme
+int step_occupancy(int prec, bool gather, int kind, bool occ2);
 
 size_t mlp_workspace_bytes(int64_t batch);
 hipError_t launch_mlp_features(int dtype, int features, int64_t n, const void *cons, const void *prim,

@@ -18,11 +18,11 @@ hipError_t launch_step_grid(int prec, const StepArgs &a, hipStream_t st)
   return step_launch_fp64(a, true, st);
 }
 
-int step_occupancy(int prec, bool gather, bool mlp, bool occ2)
+int step_occupancy(int prec, bool gather, int kind, bool occ2)
 {
-  if (prec == SRHD_PREC_MIXED) return step_occupancy_mixed(gather, mlp, occ2);
-  if (prec == SRHD_PREC_FP32) return step_occupancy_fp32(gather, mlp, occ2);
-  return step_occupancy_fp64(gather, mlp, occ2);
+  if (prec == SRHD_PREC_MIXED) return step_occupancy_mixed(gather, kind, occ2);
+  if (prec == SRHD_PREC_FP32) return step_occupancy_fp32(gather, kind, occ2);
+  return step_occupancy_fp64(gather, kind, occ2);
 }
 
 hipError_t launch_grid_prims(int prec, int64_t n_patch, const double *cons, void *prims,

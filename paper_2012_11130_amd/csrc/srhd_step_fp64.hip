@@ -8,7 +8,7 @@ hipError_t step_launch_fp64(const StepArgs &a, bool gather, hipStream_t st)
   return step_launch_ti<double, double>(a, gather, st);
 }
 
-int step_occupancy_fp64(bool gather, bool mlp, bool occ2) { return occupancy_ti<double, double>(gather, mlp, occ2); }
+int step_occupancy_fp64(bool gather, int kind, bool occ2) { return occupancy_ti<double, double>(gather, kind, occ2); }
 
 hipError_t grid_prims_fp64(int64_t n_patch, const double *cons, void *prims,
                          unsigned long long *smax_bits, const GuessArgs &g, hipStream_t st)

@@ -17,6 +17,11 @@
 // soon as that direction is complete (x after round 1, y after round 2, z after round 3).
 // If any half-step face state or output cell is unphysical, the whole patch repeats B-D with
 // theta *= 0.75 (max_retry times), then theta = 0 (Sec. 3.4); A is not repeated.
+//
+// Kernel variants K: the analytic guess of App. A, the learned guess, and the original scheme of
+// Sec. 4 (the total energy E of Eq. 5c in the energy slot, evolved with the flux M_d, and every
+// inversion from the naive L = (E/D)^2 - (|M|/D)^2 - 1 of Eq. 21 in the inversion type; analytic
+// guess, padded layout, equal bulk and inversion types only).
 #pragma once
 #include <float.h>
 #include <type_traits>
@@ -76,6 +81,8 @@ constexpr Tables make_tables()
 constexpr Tables kTabInit = make_tables();
 static_assert(kTabInit.pcell[NPC - 1] != 0 && kTabInit.hcell[NHC - 1] != 0, "cell tables");
 __constant__ Tables kTab = kTabInit;
+
+enum : int { KV_ANALYTIC = 0, KV_MLP = 1, KV_TOTAL = 2 };
 
 // The analytic guess's type: FP32 whenever the bulk is FP32 (only a starting point), else I.
 template <class T, class I>
@@ -156,7 +163,7 @@ __device__ __forceinline__ bool invert_face(const Cons<T> &u, bool ok, double L,
 
 // Face state of cell (i, j, k) on side `side` (0: minus, 1: plus) of direction d: PLM along d,
 // prim -> cons, plus the cell's half-step correction, then the inversion.
-template <int d, bool MLP, class I, class T>
+template <int d, int K, class I, class T>
 __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, int j, int k,
                                            T theta, const MlpDev &mlp, Prim<T> &w, Cons<T> &u,
                                            int &iters, int &status, unsigned int &evals)
@@ -177,7 +184,8 @@ __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, in
   wf.u[1] = v[2];
   wf.u[2] = v[3];
   wf.p = v[4];
-  u = prim2cons(wf);
+  constexpr bool MLP = K == KV_MLP;
+  u = prim2cons_s<K == KV_TOTAL>(wf);
   u.D += s.C[0][hb];
   u.m[0] += s.C[1][hb];
   u.m[1] += s.C[2][hb];
@@ -186,7 +194,9 @@ __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, in
   // the learned guess is evaluated by every lane of the wavefront (a wavefront handles one
   // direction and all its lanes are active here)
   double L;
-  const bool ok = face_L(u, L);
+  bool ok;
+  if constexpr (K == KV_TOTAL) ok = admissible_total<I>(u.D, u.m[0], u.m[1], u.m[2], u.E, L);
+  else ok = face_L(u, L);
   bool consulted = false;
   double guess = MLP ? mlp_guess(mlp, u.D, u.m[0], u.m[1], u.m[2], u.E, L, consulted, evals) : -1.0;
   return invert_face<I>(u, ok, L, w, iters, status, guess, consulted);
@@ -198,7 +208,7 @@ struct IfaceCount {
 
 // Flux through interface r of direction d (between cells c-1 and c along d, interfaces numbered
 // with x fastest, then y, then z), written to the ring slot of d.
-template <int d, bool MLP, class I, class T>
+template <int d, int K, class I, class T>
 __device__ __forceinline__ bool interface_flux(Tile<T> &s, int r, T theta, int solver,
                                                const MlpDev &mlp, IfaceCount &cnt)
 {
@@ -213,8 +223,8 @@ __device__ __forceinline__ bool interface_flux(Tile<T> &s, int r, T theta, int s
   Prim<T> wl, wr;
   Cons<T> ul, ur;
   int itl, itr, stl, str;
-  bool okl = face_state<d, MLP, I>(s, 1, cl[0], cl[1], cl[2], theta, mlp, wl, ul, itl, stl, cnt.mlp);
-  bool okr = face_state<d, MLP, I>(s, 0, cr[0], cr[1], cr[2], theta, mlp, wr, ur, itr, str, cnt.mlp);
+  bool okl = face_state<d, K, I>(s, 1, cl[0], cl[1], cl[2], theta, mlp, wl, ul, itl, stl, cnt.mlp);
+  bool okr = face_state<d, K, I>(s, 0, cr[0], cr[1], cr[2], theta, mlp, wr, ur, itr, str, cnt.mlp);
   cnt.iters += itl + itr;
   cnt.inv += 2;
   cnt.fb += (stl == ST_FALLBACK) + (str == ST_FALLBACK);
@@ -222,7 +232,8 @@ __device__ __forceinline__ bool interface_flux(Tile<T> &s, int r, T theta, int s
   cnt.unphys += !okl + !okr;
   // the face states' conserved variables are the ones just inverted: no round trip through
   // prim -> cons
-  Cons<T> F = solver == SRHD_HLLE ? hlle<d>(wl, wr, ul, ur) : hllc<d>(wl, wr, ul, ur);
+  constexpr bool TOT = K == KV_TOTAL;
+  Cons<T> F = solver == SRHD_HLLE ? hlle<d, TOT>(wl, wr, ul, ur) : hllc<d, TOT>(wl, wr, ul, ur);
   constexpr int slot = d & 1;
   s.F[slot][0][r] = F.D;
   s.F[slot][1][r] = F.m[0];
@@ -254,9 +265,12 @@ __device__ __forceinline__ int64_t patch_of_block(int64_t n_patch, int remap)
 //                 its 26 neighbours (outflow clamping where a face neighbour is -1), and every
 //                 updated cell is inverted at the end -- its primitives and the workgroup's
 //                 maximum signal speed (Eqs. 26-27) feed the next step.
-template <class T, class I, bool GATHER, bool MLP>
+template <class T, class I, bool GATHER, int K>
 __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const MlpDev &mlp, const int64_t p)
 {
+  constexpr bool MLP = K == KV_MLP;
+  constexpr bool TOT = K == KV_TOTAL;
+  static_assert(!TOT || (!GATHER && sizeof(T) == sizeof(I)), "original scheme: padded, one type");
   const int tid = threadIdx.x;
   const int g = a.ghost;
   const int N = 8 + 2 * g;
@@ -321,7 +335,9 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
              Et = q[4 * N3 + off];
       double L;
       InvOut<I> o;
-      const bool adm = admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L);
+      bool adm;
+      if constexpr (TOT) adm = admissible_total<I>((I)D, (I)Mx, (I)My, (I)Mz, (I)Et, L);
+      else adm = admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L);
       bool consulted = false;
       unsigned int ev = 0;
       double guess = MLP ? mlp_guess(mlp, D, Mx, My, Mz, Et, (valid && adm) ? L : 0.0, consulted, ev) : -1.0;
@@ -375,9 +391,9 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
         fm.u[2] = wc.u[2] - T(0.5) * sl[3]; fp.u[2] = wc.u[2] + T(0.5) * sl[3];
         fm.p = wc.p - T(0.5) * sl[4];      fp.p = wc.p + T(0.5) * sl[4];
         Cons<T> Fm, Fp;
-        if (d == 0) { Fm = phys_flux<0>(fm, prim2cons(fm)); Fp = phys_flux<0>(fp, prim2cons(fp)); }
-        else if (d == 1) { Fm = phys_flux<1>(fm, prim2cons(fm)); Fp = phys_flux<1>(fp, prim2cons(fp)); }
-        else { Fm = phys_flux<2>(fm, prim2cons(fm)); Fp = phys_flux<2>(fp, prim2cons(fp)); }
+        if (d == 0) { Fm = phys_flux<0, TOT>(fm, prim2cons_s<TOT>(fm)); Fp = phys_flux<0, TOT>(fp, prim2cons_s<TOT>(fp)); }
+        else if (d == 1) { Fm = phys_flux<1, TOT>(fm, prim2cons_s<TOT>(fm)); Fp = phys_flux<1, TOT>(fp, prim2cons_s<TOT>(fp)); }
+        else { Fm = phys_flux<2, TOT>(fm, prim2cons_s<TOT>(fm)); Fp = phys_flux<2, TOT>(fp, prim2cons_s<TOT>(fp)); }
         acc[0] += Fp.D - Fm.D;
         acc[1] += Fp.m[0] - Fm.m[0];
         acc[2] += Fp.m[1] - Fm.m[1];
@@ -401,9 +417,9 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
         int r = qi - d * NIF;
         IfaceCount ic = {0, 0, 0, 0, 0, 0};
         bool ok;
-        if (d == 0) ok = interface_flux<0, MLP, I>(s, r, theta, a.riemann, mlp, ic);
-        else if (d == 1) ok = interface_flux<1, MLP, I>(s, r, theta, a.riemann, mlp, ic);
-        else ok = interface_flux<2, MLP, I>(s, r, theta, a.riemann, mlp, ic);
+        if (d == 0) ok = interface_flux<0, K, I>(s, r, theta, a.riemann, mlp, ic);
+        else if (d == 1) ok = interface_flux<1, K, I>(s, r, theta, a.riemann, mlp, ic);
+        else ok = interface_flux<2, K, I>(s, r, theta, a.riemann, mlp, ic);
         fail |= !ok;
         my_iters += ic.iters;
         my_mlp += ic.mlp;
@@ -437,7 +453,9 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
       un[f] = u0 - full * (double)dU[f];
     }
     double Lo;
-    bool ok_out = admissible(un[0], un[1], un[2], un[3], un[4], DBL_EPSILON, Lo);
+    bool ok_out;
+    if constexpr (TOT) ok_out = admissible_total<I>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)un[4], Lo);
+    else ok_out = admissible(un[0], un[1], un[2], un[3], un[4], DBL_EPSILON, Lo);
     fail |= !ok_out;
     fail = __syncthreads_or(fail);
     bool last = !fail || centre_bad || theta == T(0);
@@ -525,7 +543,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
 // that XCD's contiguous range of patches (the same ranges as the one-per-patch mapping); a
 // workgroup drains its own XCD's range first and then helps the others in turn, so every
 // workgroup leaves the loop once all eight ranges are exhausted.
-template <class T, class I, bool GATHER, bool MLP>
+template <class T, class I, bool GATHER, int K>
 __device__ __forceinline__ void step_body(const StepArgs &a)
 {
   const MlpDev mlp = a.guess.dev();
@@ -533,7 +551,7 @@ __device__ __forceinline__ void step_body(const StepArgs &a)
   Tile<T> &s = *reinterpret_cast<Tile<T> *>(smem_raw);
   if (!a.queue) {
     const int64_t p = patch_of_block(a.n_patch, a.xcd_remap);
-    if (p < a.n_patch) step_patch<T, I, GATHER, MLP>(a, s, mlp, p);     // uniform per workgroup
+    if (p < a.n_patch) step_patch<T, I, GATHER, K>(a, s, mlp, p);     // uniform per workgroup
     return;
   }
   const int64_t range = (a.n_patch + 7) / 8;
@@ -551,26 +569,26 @@ __device__ __forceinline__ void step_body(const StepArgs &a)
       if (p0 >= hi) break;                           // uniform: every thread read the same claim
       const int64_t p1 = p0 + a.chunk < hi ? p0 + a.chunk : hi;
       for (int64_t p = p0; p < p1; ++p) {
-        step_patch<T, I, GATHER, MLP>(a, s, mlp, p);
+        step_patch<T, I, GATHER, K>(a, s, mlp, p);
         __syncthreads();
       }
     }
   }
 }
 
-template <class T, class I, bool GATHER, bool MLP>
+template <class T, class I, bool GATHER, int K>
 __global__ void __launch_bounds__(NT) k_step(StepArgs a)
 {
-  step_body<T, I, GATHER, MLP>(a);
+  step_body<T, I, GATHER, K>(a);
 }
 
 // The same kernel compiled for at most 128 VGPRs (four waves per SIMD), so that two 512-thread
 // workgroups share a CU when their LDS tiles fit (the mixed-precision tile takes 78 KB); the
 // compiler then keeps a few values of the per-patch setup in scratch instead of registers.
-template <class T, class I, bool GATHER, bool MLP>
+template <class T, class I, bool GATHER, int K>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) k_step_occ2(StepArgs a)
 {
-  step_body<T, I, GATHER, MLP>(a);
+  step_body<T, I, GATHER, K>(a);
 }
 
 // Inversion of every interior cell into the bulk type, with the maximum signal speed (the
@@ -632,32 +650,32 @@ __global__ void k_zero_queue(unsigned long long *q)
 // variant exists for the FP32-bulk kernels only: the FP64 tile fills the LDS of a CU by itself.
 // With the learned guess it spills around the network's evaluation, which runs only in
 // wavefronts that consult it.
-template <class T, class I, bool GATHER, bool MLP>
+template <class T, class I, bool GATHER, int K>
 const void *step_kernel(bool occ2)
 {
   if constexpr (sizeof(T) == 4)
-    if (occ2) return (const void *)k_step_occ2<T, I, GATHER, MLP>;
-  return (const void *)k_step<T, I, GATHER, MLP>;
+    if (occ2) return (const void *)k_step_occ2<T, I, GATHER, K>;
+  return (const void *)k_step<T, I, GATHER, K>;
 }
 
-template <class T, class I, bool GATHER, bool MLP>
+template <class T, class I, bool GATHER, int K>
 int occupancy_k(bool occ2)
 {
   int n = 0;
   const size_t bytes = sizeof(Tile<T>);
-  const void *fn = step_kernel<T, I, GATHER, MLP>(occ2);
+  const void *fn = step_kernel<T, I, GATHER, K>(occ2);
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
     return 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, NT, bytes) != hipSuccess) return 0;
   return n;
 }
 
-template <class T, class I, bool GATHER, bool MLP>
+template <class T, class I, bool GATHER, int K>
 hipError_t launch_step_k(const StepArgs &a, hipStream_t st)
 {
   const size_t bytes = sizeof(Tile<T>);
   const bool occ2 = a.occ2 && sizeof(T) == 4;
-  hipError_t e = hipFuncSetAttribute(step_kernel<T, I, GATHER, MLP>(occ2),
+  hipError_t e = hipFuncSetAttribute(step_kernel<T, I, GATHER, K>(occ2),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
   if (GATHER) hipLaunchKernelGGL(k_zero_bits, dim3(1), dim3(64), 0, st, a.smax_out);
@@ -670,26 +688,44 @@ hipError_t launch_step_k(const StepArgs &a, hipStream_t st)
   }
   if constexpr (sizeof(T) == 4) {
     if (occ2) {
-      hipLaunchKernelGGL((k_step_occ2<T, I, GATHER, MLP>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
+      hipLaunchKernelGGL((k_step_occ2<T, I, GATHER, K>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_step<T, I, GATHER, MLP>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
+  hipLaunchKernelGGL((k_step<T, I, GATHER, K>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
   return hipGetLastError();
 }
+
+// The original scheme exists where it can run: padded layout, bulk type = inversion type.
+template <class T, class I, bool GATHER>
+constexpr bool has_total() { return !GATHER && sizeof(T) == sizeof(I); }
 
 template <class T, class I, bool GATHER>
 hipError_t launch_step_t(const StepArgs &a, hipStream_t st)
 {
-  return a.guess.kind == SRHD_GUESS_MLP ? launch_step_k<T, I, GATHER, true>(a, st)
-                                        : launch_step_k<T, I, GATHER, false>(a, st);
+  if (a.energy == SRHD_ENERGY_TOTAL) {
+    if constexpr (has_total<T, I, GATHER>()) return launch_step_k<T, I, GATHER, KV_TOTAL>(a, st);
+    else return hipErrorInvalidValue;
+  }
+  return a.guess.kind == SRHD_GUESS_MLP ? launch_step_k<T, I, GATHER, KV_MLP>(a, st)
+                                        : launch_step_k<T, I, GATHER, KV_ANALYTIC>(a, st);
 }
 
-template <class T, class I>
-int occupancy_ti(bool gather, bool mlp, bool occ2)
+template <class T, class I, bool GATHER>
+int occupancy_g(int kind, bool occ2)
 {
-  return gather ? (mlp ? occupancy_k<T, I, true, true>(occ2) : occupancy_k<T, I, true, false>(occ2))
-                : (mlp ? occupancy_k<T, I, false, true>(occ2) : occupancy_k<T, I, false, false>(occ2));
+  if (kind == KV_TOTAL) {
+    if constexpr (has_total<T, I, GATHER>()) return occupancy_k<T, I, GATHER, KV_TOTAL>(occ2);
+    else return 0;
+  }
+  return kind == KV_MLP ? occupancy_k<T, I, GATHER, KV_MLP>(occ2) : occupancy_k<T, I, GATHER, KV_ANALYTIC>(occ2);
+}
+
+// kind: 0 analytic guess, 1 learned guess, 2 original scheme
+template <class T, class I>
+int occupancy_ti(bool gather, int kind, bool occ2)
+{
+  return gather ? occupancy_g<T, I, true>(kind, occ2) : occupancy_g<T, I, false>(kind, occ2);
 }
 
 template <class T, class I>

@@ -8,7 +8,7 @@ hipError_t step_launch_mixed(const StepArgs &a, bool gather, hipStream_t st)
   return step_launch_ti<float, double>(a, gather, st);
 }
 
-int step_occupancy_mixed(bool gather, bool mlp, bool occ2) { return occupancy_ti<float, double>(gather, mlp, occ2); }
+int step_occupancy_mixed(bool gather, int kind, bool occ2) { return occupancy_ti<float, double>(gather, kind, occ2); }
 
 hipError_t grid_prims_mixed(int64_t n_patch, const double *cons, void *prims,
                          unsigned long long *smax_bits, const GuessArgs &g, hipStream_t st)
