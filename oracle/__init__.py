@@ -71,7 +71,7 @@ def lib():
         fn.argtypes = [ctypes.c_int, _p, _p, _p]
         fn.restype = None
     L.or_fluid_step.argtypes = [_i64, ctypes.c_int, _p, _p, _p, _p, _d, ctypes.c_int,
-                                ctypes.c_int, ctypes.c_int, _p, _p]
+                                ctypes.c_int, ctypes.c_int, ctypes.c_int, _p, _p]
     L.or_prim2cons_total.argtypes = [_i64, _p, _p]
     L.or_prim2cons_total.restype = None
     L.or_cons2prim_total_one.argtypes = [_p, _p, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_int)]
@@ -268,7 +268,7 @@ def extract_interior(padded, ghost=3):
 
 
 def fluid_step(padded, dt_lev, dh_lev, level=None, theta=1.5, solver=HLLC, ghost=3,
-               max_retry=4, scheme=0):
+               max_retry=4, scheme=0, integrator=0):
     """One MUSCL-Hancock step of every padded patch [P][5][N][N][N] -> interior [P][5][8][8][8].
 
     Returns (out, counts) with counts = (unphysical states in the final attempt, non-converged
@@ -283,9 +283,9 @@ def fluid_step(padded, dt_lev, dh_lev, level=None, theta=1.5, solver=HLLC, ghost
     lv = None if level is None else np.ascontiguousarray(level, dtype=np.int8)
     rc = lib().or_fluid_step(P, ghost, _ptr(padded), None if lv is None else _ptr(lv),
                              _ptr(dh_lev), _ptr(dt_lev), float(theta), int(solver),
-                             int(max_retry), int(scheme), _ptr(out), _ptr(counts))
+                             int(max_retry), int(scheme), int(integrator), _ptr(out), _ptr(counts))
     if rc != 0:
-        raise ValueError("ghost depth must be at least 2")
+        raise ValueError("ghost depth must be at least %d" % (3 if integrator else 2))
     return out, counts
 
 

@@ -26,6 +26,9 @@
  *   Riemann fluxes           Sec. 3.2: relativistic HLLC / HLLE with the TM sound speed and
  *                            the reduced energy (E = Et + D); fluxes of Eqs. 4a, 4b, 7
  *   MUSCL-Hancock step       Sec. 3.2 (unsplit half step + full step)
+ *   VL step                  Sec. 3.1 names the scheme (Falle 1991; van Leer 2006): a
+ *                            first-order (piecewise-constant) half-step predictor, then PLM of
+ *                            the half-step primitives and the full step with their fluxes
  *   ghost fill               Sec. 3.1 (8^3 patches), periodic or outflow (zero gradient)
  *   original scheme          Sec. 2.3 / 4: the total energy E (Eq. 5c) evolved with flux M
  *                            (Eq. 4b), L = (E/D)^2 - (|M|/D)^2 - 1 from the divided variables
@@ -783,18 +786,157 @@ static int or_step_patch(const or_patch *P, double dt, double dh, double theta, 
   return nbad;
 }
 
+/* ===================================================================================== */
+/* VL predictor-corrector step on one padded patch                                       */
+/* ===================================================================================== */
+
+/* Box [-3, 11)^3: the predictor reads the neighbours of cells up to two layers outside. */
+#define VB 14
+#define VIDX(i, j, k) ((((k) + 3) * VB + ((j) + 3)) * VB + ((i) + 3))
+
+/* Cells whose half-step primitives the corrector reads: along each axis d the cells with
+ * coordinate d in [-2, 10) and the other two coordinates inside the patch. */
+static int or_in_vl_half(int i, int j, int k)
+{
+  int c[3] = {i, j, k};
+  int out = 0;
+  for (int d = 0; d < 3; d++) {
+    if (c[d] >= 0 && c[d] < PS) continue;
+    if (c[d] >= -2 && c[d] < PS + 2) out++;
+    else return 0;
+  }
+  return out <= 1;
+}
+
+typedef struct {
+  double w[VB * VB * VB][5];
+  unsigned char have[VB * VB * VB];
+  const or_patch *P;
+  or_counts *cnt;
+  int scheme;
+} or_vl_cache;
+
+static const double *or_vl_prim(or_vl_cache *C, int i, int j, int k)
+{
+  int id = VIDX(i, j, k);
+  if (!C->have[id]) {
+    double u[5];
+    int it = 0;
+    for (int f = 0; f < 5; f++) u[f] = or_get(C->P, f, i, j, k);
+    int st = sc_cons2prim(C->scheme, u, C->w[id], &it);
+    if (st == OR_ST_UNPHYSICAL) { C->cnt->unphys++; C->cnt->centre_bad = 1; }
+    C->cnt->iters += it;
+    C->have[id] = 1;
+  }
+  return C->w[id];
+}
+
+static void sc_riemann(int scheme, int riemann, int d, const double wl[5], const double wr[5],
+                       double F[5])
+{
+  if (riemann == OR_HLLE) sc_hlle(scheme, d, wl, wr, F);
+  else sc_hllc(scheme, d, wl, wr, F);
+}
+
+/* One VL step of one patch with limiter coefficient theta (the corrector's PLM):
+ *   predictor  U*(c) = U^n(c) - (dt / 2dh) sum_d [F_d(W_c, W_{c+d}) - F_d(W_{c-d}, W_c)] with
+ *              the cell-centre primitives as the face states, then W*(c) = cons -> prim of U*;
+ *   corrector  the interface flux from PLM face states of W* (W* -/+ slope/2 on either side),
+ *              U^{n+1} = U^n - (dt/dh) sum_d (F_{+1/2} - F_{-1/2}).
+ * A predictor state that fails the inversion cannot be cured by the limiter and ends the
+ * attempts (centre_bad).  Returns the number of output cells failing Eq. 30. */
+static int or_vl_step_patch(const or_patch *P, double dt, double dh, double theta, int riemann,
+                            int scheme, double *out, or_counts *cnt)
+{
+  or_vl_cache *C = (or_vl_cache *)calloc(1, sizeof(or_vl_cache));
+  C->P = P;
+  C->cnt = cnt;
+  C->scheme = scheme;
+  double (*wh)[5] = (double (*)[5])calloc(VB * VB * VB, sizeof(*wh));
+  double half = 0.5 * dt / dh;
+  for (int k = -2; k < PS + 2; k++)
+    for (int j = -2; j < PS + 2; j++)
+      for (int i = -2; i < PS + 2; i++) {
+        if (!or_in_vl_half(i, j, k)) continue;
+        const double *wc = or_vl_prim(C, i, j, k);
+        double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int d = 0; d < 3; d++) {
+          int di = (d == 0), dj = (d == 1), dk = (d == 2);
+          const double *wm = or_vl_prim(C, i - di, j - dj, k - dk);
+          const double *wp = or_vl_prim(C, i + di, j + dj, k + dk);
+          double Fm[5], Fp[5];
+          sc_riemann(scheme, riemann, d, wm, wc, Fm);
+          sc_riemann(scheme, riemann, d, wc, wp, Fp);
+          for (int f = 0; f < 5; f++) acc[f] += Fp[f] - Fm[f];
+        }
+        double u[5];
+        for (int f = 0; f < 5; f++) u[f] = or_get(P, f, i, j, k) - half * acc[f];
+        int it = 0;
+        int st = sc_cons2prim(scheme, u, wh[VIDX(i, j, k)], &it);
+        cnt->iters += it;
+        if (st == OR_ST_UNPHYSICAL) { cnt->unphys++; cnt->centre_bad = 1; }
+      }
+  double (*fx)[5] = (double (*)[5])calloc(3 * 9 * 64, sizeof(*fx));
+  for (int d = 0; d < 3; d++)
+    for (int a = 0; a < PS; a++)
+      for (int b = 0; b < PS; b++)
+        for (int c = 0; c <= PS; c++) {
+          int t0 = (d == 0) ? 1 : 0, t1 = (d == 2) ? 1 : 2;
+          int cr[3];
+          cr[d] = c; cr[t0] = b; cr[t1] = a;
+          int e[3] = {d == 0, d == 1, d == 2};
+          /* cells c-2, c-1 (left side) and c, c+1 (right side) along d */
+          const double *w[4];
+          for (int q = 0; q < 4; q++)
+            w[q] = wh[VIDX(cr[0] + (q - 2) * e[0], cr[1] + (q - 2) * e[1], cr[2] + (q - 2) * e[2])];
+          double wl[5], wr[5];
+          for (int f = 0; f < 5; f++) {
+            wl[f] = w[1][f] + 0.5 * or_slope(w[0][f], w[1][f], w[2][f], theta);
+            wr[f] = w[2][f] - 0.5 * or_slope(w[1][f], w[2][f], w[3][f], theta);
+          }
+          sc_riemann(scheme, riemann, d, wl, wr, fx[(d * 64 + a * 8 + b) * 9 + c]);
+        }
+  double full = dt / dh;
+  for (int k = 0; k < PS; k++)
+    for (int j = 0; j < PS; j++)
+      for (int i = 0; i < PS; i++) {
+        int ci[3] = {i, j, k};
+        for (int f = 0; f < 5; f++) {
+          double acc = 0.0;
+          for (int d = 0; d < 3; d++) {
+            int t0 = (d == 0) ? 1 : 0, t1 = (d == 2) ? 1 : 2;
+            int a = ci[t1], b = ci[t0], c = ci[d];
+            acc += fx[(d * 64 + a * 8 + b) * 9 + c + 1][f] - fx[(d * 64 + a * 8 + b) * 9 + c][f];
+          }
+          out[f * 512 + (k * PS + j) * PS + i] = or_get(P, f, i, j, k) - full * acc;
+        }
+      }
+  int nbad = 0;
+  for (int c = 0; c < 512; c++) {
+    double u[5];
+    for (int f = 0; f < 5; f++) u[f] = out[f * 512 + c];
+    nbad += !sc_is_physical(scheme, u);
+  }
+  free(fx);
+  free(wh);
+  free(C);
+  return nbad;
+}
+
 /* Step of every patch.  When a patch's step meets an unphysical state -- a half-step face
  * state that fails the inversion, or an updated cell that fails Eq. 30 -- the patch is redone
  * with the limiter coefficient reduced by 0.75 (Sec. 3.4, "SRHD solver"), at most max_retry
  * times, and finally once with a zero coefficient (piecewise-constant reconstruction).  An
  * unphysical input cell cannot be cured by reconstruction and ends the attempts.
+ * integrator 0: MUSCL-Hancock (ghost >= 2); 1: VL (ghost >= 3; only updated cells trigger
+ * the retry, a predictor state that fails ends the attempts).
  * counts = {unphysical inversions + failed output cells of the final attempt, non-converged
  *           inversions, solver iterations, retried attempts}. */
 int or_fluid_step(int64_t n_patch, int ghost, const double *padded, const int8_t *level,
                   const double *dh_lev, const double *dt_lev, double theta, int riemann,
-                  int max_retry, int scheme, double *out, int64_t *counts)
+                  int max_retry, int scheme, int integrator, double *out, int64_t *counts)
 {
-  if (ghost < 2) return -1;
+  if (ghost < (integrator ? 3 : 2)) return -1;
   int N = PS + 2 * ghost;
   int64_t per = (int64_t)NF * N * N * N;
   int64_t unphys = 0, noconv = 0, iters = 0, retries = 0;
@@ -805,7 +947,9 @@ int or_fluid_step(int64_t n_patch, int ghost, const double *padded, const int8_t
     double th = theta;
     for (int attempt = 0;; attempt++) {
       or_counts c = {0, 0, 0, 0, 0};
-      int nbad = or_step_patch(&P, dt_lev[lv], dh_lev[lv], th, riemann, scheme, out + p * NF * 512, &c);
+      int nbad = integrator
+                     ? or_vl_step_patch(&P, dt_lev[lv], dh_lev[lv], th, riemann, scheme, out + p * NF * 512, &c)
+                     : or_step_patch(&P, dt_lev[lv], dh_lev[lv], th, riemann, scheme, out + p * NF * 512, &c);
       iters += c.iters;
       int fail = c.face_bad || nbad > 0;
       if (!fail || c.centre_bad || th == 0.0) {

@@ -42,7 +42,7 @@ void or_hllc(int d, const double wl[5], const double wr[5], double F[5]);
 int or_is_physical(const double u[5]);
 int or_fluid_step(int64_t n_patch, int ghost, const double *padded, const int8_t *level,
                   const double *dh_lev, const double *dt_lev, double theta, int riemann,
-                  int max_retry, int scheme, double *out, int64_t *counts);
+                  int max_retry, int scheme, int integrator, double *out, int64_t *counts);
 void or_prim2cons_total_one(const double w[5], double u[5]);
 int or_cons2prim_total_one(const double u[5], double w[5], double *ht_out, int *iters);
 void or_prim2cons_total(int64_t n, const double *prim, double *cons);

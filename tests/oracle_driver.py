@@ -29,10 +29,11 @@ def to_prim(cons, scheme=0):
 
 
 def run(grid, cons, n_steps=None, t_end=None, c_cfl=0.5, theta=1.5, solver=O.HLLC, ghost=3,
-        dt_fixed=None, stats=None, scheme=0):
+        dt_fixed=None, stats=None, scheme=0, integrator=0):
     """Advance ``cons`` [P][5][8][8][8]; returns (cons, time, steps).  ``stats`` (a list)
     receives the per-step oracle counters.  scheme=1 runs the original scheme on (D, M, E); its
-    CFL time step is taken from Et = E - D (the time step only needs the signal speeds)."""
+    CFL time step is taken from Et = E - D (the time step only needs the signal speeds).
+    integrator=1 runs the VL predictor-corrector instead of MUSCL-Hancock."""
     t, k = 0.0, 0
     while True:
         if n_steps is not None and k >= n_steps:
@@ -51,7 +52,8 @@ def run(grid, cons, n_steps=None, t_end=None, c_cfl=0.5, theta=1.5, solver=O.HLL
         if t_end is not None:
             dt = min(dt, t_end - t)
         pad = O.fill_ghosts(cons, grid.neighbor, ghost)
-        cons, cnt = O.fluid_step(pad, [dt], grid.dh_lev, None, theta, solver, ghost, scheme=scheme)
+        cons, cnt = O.fluid_step(pad, [dt], grid.dh_lev, None, theta, solver, ghost, scheme=scheme,
+                                 integrator=integrator)
         assert cnt[0] == 0, "unphysical inversion"
         if stats is not None:
             stats.append(cnt)
@@ -60,7 +62,7 @@ def run(grid, cons, n_steps=None, t_end=None, c_cfl=0.5, theta=1.5, solver=O.HLL
     return cons, t, k
 
 
-def sine_x_l1(n, theta0, amp, t_frac, theta_lim=1.5, scheme=0):
+def sine_x_l1(n, theta0, amp, t_frac, theta_lim=1.5, scheme=0, integrator=0):
     """Right-moving linear acoustic wave along x on an n-cell periodic row; returns the L1
     density error (Eq. 31) after t_frac of a period; scheme=1 runs the original scheme."""
     g = W.PatchGrid("w", np.zeros((n // 8, 5, 8, 8, 8)), n // 8, 1, 1, True, 1.0 / n)
@@ -77,7 +79,7 @@ def sine_x_l1(n, theta0, amp, t_frac, theta_lim=1.5, scheme=0):
     # the grid average of sin over a cell is sin(centre) * sinc(dh): compare like with like
     t_end = t_frac / cs
     c0 = initial_cons(g, scheme)
-    c1, t, k = run(g, c0, t_end=t_end, theta=theta_lim, scheme=scheme)
+    c1, t, k = run(g, c0, t_end=t_end, theta=theta_lim, scheme=scheme, integrator=integrator)
     w, _ = to_prim(c1, scheme)
     exact = rho0 * (1 + amp * np.sin(2 * np.pi * (x - cs * t)))
     return np.mean(np.abs(1 - w[:, 0] / exact))

@@ -1,0 +1,128 @@
+"""Pins of the oracle's VL integrator (Sec. 3.1 names it; Falle 1991, van Leer 2006): a first-order
+half-step predictor with the cell-centre primitives as face states, then PLM of the half-step
+primitives and the full step with their fluxes.
+
+Checked against what the mathematics fixes: uniform states kept bit for bit, conservation under
+periodic boundaries, axis-permutation symmetry, second-order convergence of a smooth wave in
+the cold, warm and hot limits (first order with the limiter off, where the scheme is a two-stage
+first-order method), the shock tubes converging to the exact solution of App. C, and a gas with
+uniform pressure and velocity (a pure contact profile) keeping its pressure and velocity.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from oracle.exact_riemann import RiemannTM
+from tests import oracle_driver as drv
+
+
+def test_needs_three_ghost_layers():
+    g = W.blast(16, seed=3)
+    pad = O.fill_ghosts(drv.initial_cons(g), g.neighbor, 2)
+    with pytest.raises(ValueError):
+        O.fluid_step(pad, [1e-3], g.dh_lev, ghost=2, integrator=1)
+
+
+def test_uniform_state_is_preserved_bitwise():
+    for w in ([1.0, 0.0, 0.0, 0.0, 1e-6], [0.3, 2.0, -1.0, 0.5, 7.0], [1e-3, 1e3, 0.0, 0.0, 1e2]):
+        g = W.PatchGrid("u", np.zeros((8, 5, 8, 8, 8)), 2, 2, 2, True, 1 / 16)
+        for k in range(5):
+            g.prim[:, k] = w[k]
+        c0 = drv.initial_cons(g)
+        c1, _, _ = drv.run(g, c0, n_steps=2, integrator=1)
+        assert np.array_equal(c0, c1), w
+
+
+def test_conservation_under_periodic_boundaries():
+    g = W.blast(32, seed=3)
+    g.prim[:, 4] = np.where(g.extra["labels"] == 1, 1.0, 0.1)
+    _, _, z = W.patch_cell_centres(4, 4, 4, 1 / 32)
+    g.prim[:, 1] = 0.3 * np.sin(2 * np.pi * z)
+    c0 = drv.initial_cons(g)
+    stats = []
+    c1, _, _ = drv.run(g, c0, n_steps=3, stats=stats, integrator=1)
+    assert all(s[3] == 0 for s in stats)
+    for f in range(5):
+        s0, s1 = c0[:, f].sum(), c1[:, f].sum()
+        tot = np.abs(c0[:, f]).sum() + np.abs(c1[:, f]).sum()
+        assert abs(s1 - s0) <= 1e-13 * tot, f
+    assert not np.array_equal(c0, c1)
+
+
+def test_axis_permutation_symmetry():
+    L = (1.0, 0.0, 0.0, 0.0, 1e3)
+    R = (0.5, 0.0, 0.0, 0.0, 1e-6)
+    res = []
+    for axis in range(3):
+        dims = [1, 1, 1]
+        dims[axis] = 4
+        g = W.PatchGrid("p", np.zeros((4, 5, 8, 8, 8)), *dims, False, 1 / 32)
+        coord = W.patch_cell_centres(*dims, 1 / 32)[axis]
+        for k in range(5):
+            g.prim[:, k] = np.where(coord < 0.5, L[k], R[k])
+        c1, _, _ = drv.run(g, drv.initial_cons(g), n_steps=3, integrator=1)
+        line = np.moveaxis(W.interior_to_grid(c1, *dims), 3 - axis, 3)
+        res.append([np.ascontiguousarray(f) for f in (line[0], line[1 + axis], line[4])])
+    for r in res[1:]:
+        for a, b in zip(res[0], r):
+            assert np.allclose(a, b, rtol=1e-14, atol=1e-14 * np.abs(a).max())
+
+
+@pytest.mark.parametrize("theta0", [1e-10, 1.0, 1e10])
+def test_smooth_wave_second_order(theta0):
+    e = [drv.sine_x_l1(n, theta0, 1e-6, 0.25, integrator=1) for n in (16, 32, 64)]
+    assert e[0] / e[1] > 3.5 and e[1] / e[2] > 3.5, e
+    # the same order as MUSCL-Hancock, with an error constant of the same size
+    m = drv.sine_x_l1(32, theta0, 1e-6, 0.25)
+    assert 0.5 < e[1] / m < 2.0, (e, m)
+
+
+def test_zero_limiter_is_first_order():
+    e = [drv.sine_x_l1(n, 1.0, 1e-6, 0.25, theta_lim=0.0, integrator=1) for n in (16, 32, 64)]
+    r = [e[0] / e[1], e[1] / e[2]]
+    assert all(1.6 < x < 2.3 for x in r), e
+
+
+def test_pressure_and_velocity_equilibrium_is_kept_to_round_off_of_a_contact():
+    # density varies, pressure and velocity are uniform: a contact moving at v.  HLLC keeps p
+    # and U uniform across an isolated contact; the predictor's upwind mixture of two contact
+    # states moves p and U away only by the EoS's nonlinearity in rho, which is second order in
+    # the density jump between neighbours.
+    n = 64
+    g = W.PatchGrid("c", np.zeros((n // 8, 5, 8, 8, 8)), n // 8, 1, 1, True, 1.0 / n)
+    x, _, _ = W.patch_cell_centres(n // 8, 1, 1, 1.0 / n)
+    g.prim[:, 0] = 1.0 + 0.01 * np.sin(2 * np.pi * x)
+    g.prim[:, 1] = 0.5
+    g.prim[:, 4] = 1e-2
+    c1, _, _ = drv.run(g, drv.initial_cons(g), n_steps=10, integrator=1)
+    w, _ = drv.to_prim(c1)
+    assert np.max(np.abs(w[:, 4] / 1e-2 - 1)) < 1e-6
+    assert np.max(np.abs(w[:, 1] / 0.5 - 1)) < 1e-6
+
+
+def _tube_l1(n, left, right, t_end, integrator):
+    l5 = (left[0], left[1], 0.0, 0.0, left[2])
+    r5 = (right[0], right[1], 0.0, 0.0, right[2])
+    g = W.riemann_1d(n, l5, r5, x0=0.5)
+    c, t, _ = drv.run(g, drv.initial_cons(g), t_end=t_end, integrator=integrator)
+    w, _ = drv.to_prim(c)
+    x = g.extra["x"][:, 0, 0, :].reshape(-1)
+    rho = w[:, 0, 0, 0, :].reshape(-1)
+    ex = RiemannTM(left, right, x0=0.5)
+    ref = np.array([float(ex.sample(xx, t)[0]) for xx in x])
+    return np.mean(np.abs(1 - rho / ref))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("left,right", [((1.0, 0.0, 1.0), (0.125, 0.0, 0.1)),
+                                        ((1.0, 0.0, 1e-2), (0.1, 0.0, 1e-5))])
+def test_shock_tube_converges_to_exact_solution(left, right):
+    e = [_tube_l1(n, left, right, 0.3, 1) for n in (32, 64, 128)]
+    assert e[1] < 0.7 * e[0] and e[2] < 0.7 * e[1], e
+    assert e[2] < 0.02, e
+    # comparable to MUSCL-Hancock at the finest resolution
+    m = _tube_l1(128, left, right, 0.3, 0)
+    assert 0.5 < e[2] / m < 2.0, (e, m)
