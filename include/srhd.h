@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define SRHD_ABI_VERSION 3
+#define SRHD_ABI_VERSION 4
 
 typedef enum { SRHD_F64 = 0, SRHD_F32 = 1 } srhd_dtype;
 
@@ -67,6 +67,16 @@ typedef enum { SRHD_PREC_FP64 = 0, SRHD_PREC_MIXED = 1, SRHD_PREC_FP32 = 2 } srh
  * SRHD_PREC_FP64 or SRHD_PREC_FP32 and the analytic guess only (else SRHD_EUNSUPPORTED); the
  * physical check of its states is D > 0, E > 0 and that L > DBL_EPSILON. */
 typedef enum { SRHD_ENERGY_REDUCED = 0, SRHD_ENERGY_TOTAL = 1 } srhd_energy;
+
+/* Time integrator of a step (Sec. 3.1 names both).  MHM: MUSCL-Hancock (Sec. 3.2), described at
+ * srhd_fluid_step.  VL: the van Leer predictor-corrector (Falle 1991; van Leer 2006) -- a
+ * first-order half step U* = U^n - (dt/2dh) sum_d [F_d(W_c, W_{c+d}) - F_d(W_{c-d}, W_c)] with
+ * the cell-centre primitives as face states, W* = cons -> prim of U*, then the full step with
+ * the fluxes of PLM face states of W*.  Only an updated cell failing Eq. 30 triggers the limiter
+ * retry (a predictor state that fails the inversion ends the attempts, as an unphysical input
+ * cell does).  VL runs in srhd_fluid_step with ghost >= 3, the analytic guess and the reduced
+ * energy, in every precision mode (else SRHD_EUNSUPPORTED). */
+typedef enum { SRHD_MHM = 0, SRHD_VL = 1 } srhd_integrator;
 
 /* Learned initial guess: device parameters of a 3-64-64-1 SiLU perceptron that maps three
  * standardised log-scaled invariants of the conserved state to the standardised log of the
@@ -175,6 +185,7 @@ typedef struct {
   srhd_guess guess;        /* initial guess for every inversion in the step */
   srhd_sched sched;        /* launch schedule; all-zero = one workgroup per patch */
   int energy;              /* srhd_energy (0: this paper's reduced energy) */
+  int integrator;          /* srhd_integrator (0: MUSCL-Hancock) */
 } srhd_step_params;
 
 /* Device counters, accumulated (never reset by the step; see srhd_stats_reset). */
@@ -204,13 +215,15 @@ int srhd_stats_reset(srhd_step_stats *stats, void *stream);
  * same results bit for bit. */
 int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
                     const srhd_step_params *prm, srhd_step_stats *stats, void *stream);
+/* (prm->integrator selects MUSCL-Hancock or VL: see srhd_integrator.) */
 
-/* Workgroups of the step kernel that fit on one compute unit at once for the given precision,
- * guess kind (srhd_guess_kind), layout (gather = 1: srhd_fluid_step_grid, 0: srhd_fluid_step),
- * register variant (occupancy field of srhd_sched) and energy variable (srhd_energy);
- * multiplied by the device's compute-unit count it sizes a persistent schedule.  Returns the
- * count (> 0), or a negative srhd_err (SRHD_EUNSUPPORTED for a combination that has no kernel). */
-int srhd_step_occupancy(int prec, int guess_kind, int gather, int occupancy, int energy);
+/* Workgroups of the step kernel that fit on one compute unit at once for the kernel that
+ * prm (host) selects -- its precision, guess kind, register variant (prm->sched.occupancy),
+ * energy variable and integrator -- and the layout (gather = 1: srhd_fluid_step_grid, 0:
+ * srhd_fluid_step); multiplied by the device's compute-unit count it sizes a persistent
+ * schedule.  prm->sched.groups and .queue are ignored.  Returns the count (> 0), or a negative
+ * srhd_err (SRHD_EUNSUPPORTED for a combination that has no kernel). */
+int srhd_step_occupancy(const srhd_step_params *prm, int gather);
 
 /* Schedule autotuner for srhd_fluid_step.  Runs the step on `in` (writing `out`) once per
  * candidate schedule as a warm-up and then `reps` timed times, timed with events on `stream`,
@@ -269,7 +282,8 @@ int srhd_grid_prims(int prec, int64_t n_patch, const double *cons, void *prims,
  * dt_used (device double[n_level], may be NULL) receives the time step used.
  * Outputs must not overlap the inputs.  Patches are mapped to workgroups so that each XCD works
  * on a contiguous range of patch indices (order patches along a space-filling curve).  The
- * reduced energy only (prm->energy = SRHD_ENERGY_TOTAL gives SRHD_EUNSUPPORTED). */
+ * reduced energy and MUSCL-Hancock only (prm->energy = SRHD_ENERGY_TOTAL or prm->integrator =
+ * SRHD_VL gives SRHD_EUNSUPPORTED). */
 int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_cfl,
                          const double *dt_lev, double *cons_out, void *prims_out,
                          uint64_t *smax_out, double *dt_used, const srhd_step_params *prm,

@@ -57,12 +57,25 @@ int check_guess(const srhd_guess *g, srhd::GuessArgs &out)
   return fail(SRHD_EINVAL, "unknown guess kind %d", g->kind);
 }
 
-// Energy variable of a step (include/srhd.h, srhd_energy): the original scheme has kernels for the
-// padded layout with equal bulk and inversion types and the analytic guess.
-int check_energy(int energy, int prec, int guess_kind, int gather, const char *who)
+// Energy variable and integrator of a step (include/srhd.h, srhd_energy, srhd_integrator): the
+// original scheme has kernels for the padded layout with equal bulk and inversion types and the
+// analytic guess; the VL integrator for the padded layout, the analytic guess and the reduced
+// energy.
+int check_variant(int energy, int integrator, int prec, int guess_kind, int gather, const char *who)
 {
+  if (integrator != SRHD_MHM && integrator != SRHD_VL)
+    return fail(SRHD_EINVAL, "%s: unknown integrator %d", who, integrator);
+  if (energy != SRHD_ENERGY_REDUCED && energy != SRHD_ENERGY_TOTAL)
+    return fail(SRHD_EINVAL, "%s: unknown energy variable %d", who, energy);
+  if (integrator == SRHD_VL) {
+    if (gather) return fail(SRHD_EUNSUPPORTED, "%s: the VL integrator runs on padded patches only", who);
+    if (energy != SRHD_ENERGY_REDUCED)
+      return fail(SRHD_EUNSUPPORTED, "%s: the VL integrator evolves the reduced energy only", who);
+    if (guess_kind != SRHD_GUESS_ANALYTIC)
+      return fail(SRHD_EUNSUPPORTED, "%s: the VL integrator takes the analytic guess only", who);
+    return SRHD_OK;
+  }
   if (energy == SRHD_ENERGY_REDUCED) return SRHD_OK;
-  if (energy != SRHD_ENERGY_TOTAL) return fail(SRHD_EINVAL, "%s: unknown energy variable %d", who, energy);
   if (gather) return fail(SRHD_EUNSUPPORTED, "%s: the total-energy scheme runs on padded patches only", who);
   if (prec == SRHD_PREC_MIXED)
     return fail(SRHD_EUNSUPPORTED, "%s: the total-energy scheme runs in FP64 or FP32 only", who);
@@ -209,8 +222,10 @@ int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
   srhd::GuessArgs g;
   int rc = check_guess(&prm->guess, g);
   if (rc) return rc;
-  rc = check_energy(prm->energy, prm->prec, g.kind, 0, "srhd_fluid_step");
+  rc = check_variant(prm->energy, prm->integrator, prm->prec, g.kind, 0, "srhd_fluid_step");
   if (rc) return rc;
+  if (prm->integrator == SRHD_VL && in->ghost < 3)
+    return fail(SRHD_EINVAL, "srhd_fluid_step: the VL integrator needs ghost >= 3 (got %d)", in->ghost);
   if (in->n_patch == 0) return SRHD_OK;
   if (!in->padded || !out || !dt_lev) return fail(SRHD_EINVAL, "srhd_fluid_step: NULL array");
   if (!aligned(in->padded, 8) || !aligned(out, 8) || !aligned(dt_lev, 8))
@@ -245,6 +260,7 @@ int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
   s.dt_out = nullptr;
   s.xcd_remap = 0;
   s.energy = prm->energy;
+  s.integrator = prm->integrator;
   rc = check_sched(prm->sched, prm->prec, g.kind, s, "srhd_fluid_step");
   if (rc) return rc;
   if (s.queue) {
@@ -255,8 +271,10 @@ int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
   return hip_status(srhd::launch_step(prm->prec, s, (hipStream_t)stream), "srhd_fluid_step");
 }
 
-int srhd_step_occupancy(int prec, int guess_kind, int gather, int occupancy, int energy)
+int srhd_step_occupancy(const srhd_step_params *prm, int gather)
 {
+  if (!prm) return fail(SRHD_EINVAL, "srhd_step_occupancy: NULL parameters");
+  const int prec = prm->prec, guess_kind = prm->guess.kind, occupancy = prm->sched.occupancy;
   if (prec != SRHD_PREC_FP64 && prec != SRHD_PREC_MIXED && prec != SRHD_PREC_FP32)
     return fail(SRHD_EINVAL, "srhd_step_occupancy: bad precision %d", prec);
   if (guess_kind != SRHD_GUESS_ANALYTIC && guess_kind != SRHD_GUESS_MLP)
@@ -265,10 +283,11 @@ int srhd_step_occupancy(int prec, int guess_kind, int gather, int occupancy, int
     return fail(SRHD_EINVAL, "srhd_step_occupancy: occupancy %d is neither 0 nor 2", occupancy);
   if (occupancy == 2 && prec == SRHD_PREC_FP64)
     return fail(SRHD_EUNSUPPORTED, "srhd_step_occupancy: occupancy 2 needs an FP32 bulk");
-  int rc = check_energy(energy, prec, guess_kind, gather, "srhd_step_occupancy");
+  int rc = check_variant(prm->energy, prm->integrator, prec, guess_kind, gather, "srhd_step_occupancy");
   if (rc) return rc;
-  const int kind = energy == SRHD_ENERGY_TOTAL ? 2 : (guess_kind == SRHD_GUESS_MLP ? 1 : 0);
-  int n = srhd::step_occupancy(prec, gather != 0, kind, occupancy == 2);
+  const int kind = prm->energy == SRHD_ENERGY_TOTAL ? 2 : (guess_kind == SRHD_GUESS_MLP ? 1 : 0);
+  int n = prm->integrator == SRHD_VL ? srhd::step_occupancy_vl(prec, occupancy == 2)
+                                     : srhd::step_occupancy(prec, gather != 0, kind, occupancy == 2);
   if (n <= 0) return fail(SRHD_EHIP, "srhd_step_occupancy: occupancy query failed");
   return n;
 }
@@ -296,7 +315,9 @@ int autotune(srhd_step_params *prm, int gather, int reps, srhd_tune_entry *table
   const bool two = prm->prec != SRHD_PREC_FP64;
   for (int occ : {0, 2}) {
     if (occ == 2 && !two) continue;
-    int per_cu = srhd_step_occupancy(prm->prec, prm->guess.kind, gather, occ, prm->energy);
+    srhd_step_params q = *prm;
+    q.sched.occupancy = occ;
+    int per_cu = srhd_step_occupancy(&q, gather);
     if (per_cu <= 0) return per_cu < 0 ? per_cu : fail(SRHD_EHIP, "%s: occupancy 0", who);
     cand[nc++] = {0, 1, occ};
     for (int m : {1, 2, 4})
@@ -477,7 +498,7 @@ int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_
   srhd::GuessArgs g;
   int rc = check_guess(&prm->guess, g);
   if (rc) return rc;
-  rc = check_energy(prm->energy, prm->prec, g.kind, 1, "srhd_fluid_step_grid");
+  rc = check_variant(prm->energy, prm->integrator, prm->prec, g.kind, 1, "srhd_fluid_step_grid");
   if (rc) return rc;
   if (!smax_out) return fail(SRHD_EINVAL, "srhd_fluid_step_grid: NULL smax_out");
   if (!dt_lev && (!smax_in || !(c_cfl > 0.0)))
@@ -525,6 +546,7 @@ int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_
   s.dt_out = dt_used;
   s.xcd_remap = 1;
   s.energy = SRHD_ENERGY_REDUCED;
+  s.integrator = SRHD_MHM;
   rc = check_sched(prm->sched, prm->prec, g.kind, s, "srhd_fluid_step_grid");
   if (rc) return rc;
   return hip_status(srhd::launch_step_grid(prm->prec, s, (hipStream_t)stream),

@@ -64,9 +64,13 @@ struct StepArgs {
   int chunk;
   int occ2;                             // the kernel variant that fits two workgroups per CU
   int energy;                           // srhd_energy: SRHD_ENERGY_TOTAL runs the original scheme
+  int integrator;                       // srhd_integrator: SRHD_VL runs srhd_step_vl.hip's kernel
 };
 
 hipError_t launch_step(int prec, const StepArgs &a, hipStream_t s);
+// the VL integrator (srhd_step_vl.hip): padded layout, analytic guess, reduced energy
+hipError_t launch_step_vl(int prec, const StepArgs &a, hipStream_t s);
+int step_occupancy_vl(int prec, bool occ2);
 
 // per-precision launchers of the step (srhd_step_fp64.hip, srhd_step_mixed.hip, srhd_step_fp32.hip)
 #define SRHD_STEP_MODE(name)                                                                   \

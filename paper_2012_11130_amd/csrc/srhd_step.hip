@@ -6,6 +6,7 @@ namespace srhd {
 
 hipError_t launch_step(int prec, const StepArgs &a, hipStream_t st)
 {
+  if (a.integrator == SRHD_VL) return launch_step_vl(prec, a, st);
   if (prec == SRHD_PREC_MIXED) return step_launch_mixed(a, false, st);
   if (prec == SRHD_PREC_FP32) return step_launch_fp32(a, false, st);
   return step_launch_fp64(a, false, st);

@@ -26,6 +26,7 @@ FEAT_CONS, FEAT_L = 0, 1
 HLLC, HLLE = 0, 1
 PREC_FP64, PREC_MIXED, PREC_FP32 = 0, 1, 2
 ENERGY_REDUCED, ENERGY_TOTAL = 0, 1
+MHM, VL = 0, 1
 MAX_LEVEL = 8
 
 _vp = ctypes.c_void_p
@@ -59,7 +60,7 @@ class srhd_sched(ctypes.Structure):
 class srhd_step_params(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("riemann", _int), ("prec", _int),
                 ("max_retry", _int), ("guess", srhd_guess), ("sched", srhd_sched),
-                ("energy", _int)]
+                ("energy", _int), ("integrator", _int)]
 
 
 class srhd_tune_entry(ctypes.Structure):
@@ -95,7 +96,7 @@ _sig = {
     "srhd_mlp_adam": [_vp, _vp, _vp, _vp, _int, ctypes.c_float, _vp, _vp, _vp],
     "srhd_fluid_step_grid": [ctypes.POINTER(srhd_grid), _vp, ctypes.c_double, _vp, _vp, _vp,
                              _vp, _vp, ctypes.POINTER(srhd_step_params), _vp, _vp],
-    "srhd_step_occupancy": [_int, _int, _int, _int, _int],
+    "srhd_step_occupancy": [ctypes.POINTER(srhd_step_params), _int],
     "srhd_autotune_step": [ctypes.POINTER(srhd_patches), _vp, _vp,
                            ctypes.POINTER(srhd_step_params), _int,
                            ctypes.POINTER(srhd_tune_entry), _int, ctypes.POINTER(_int), _vp],
@@ -271,7 +272,7 @@ def _patches(padded, dh, level, ghost):
     return d
 
 
-def _params(theta, riemann, prec, max_retry, guess, sched, energy=ENERGY_REDUCED):
+def _params(theta, riemann, prec, max_retry, guess, sched, energy=ENERGY_REDUCED, integrator=MHM):
     prm = srhd_step_params()
     prm.theta = float(theta)
     prm.riemann = int(riemann)
@@ -280,13 +281,16 @@ def _params(theta, riemann, prec, max_retry, guess, sched, energy=ENERGY_REDUCED
     prm.guess = guess if guess is not None else srhd_guess(GUESS_ANALYTIC, None, 0)
     prm.sched = sched.c() if sched is not None else srhd_sched(0, 1, 0, None)
     prm.energy = int(energy)
+    prm.integrator = int(integrator)
     return prm
 
 
 def srhd_step_occupancy(prec, guess_kind=GUESS_ANALYTIC, gather=False, occupancy=0,
-                        energy=ENERGY_REDUCED):
-    rc = _lib.srhd_step_occupancy(int(prec), int(guess_kind), int(bool(gather)), int(occupancy),
-                                  int(energy))
+                        energy=ENERGY_REDUCED, integrator=MHM):
+    prm = _params(1.5, HLLC, prec, 4, srhd_guess(int(guess_kind), None, 0), None, energy,
+                  integrator)
+    prm.sched = srhd_sched(0, 1, int(occupancy), None)
+    rc = _lib.srhd_step_occupancy(ctypes.byref(prm), int(bool(gather)))
     _check(min(rc, 0))
     return rc
 
@@ -297,7 +301,7 @@ def _table(table, n):
 
 def srhd_autotune_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann=HLLC,
                        prec=PREC_FP64, max_retry=4, ghost=None, guess=None, reps=2,
-                       energy=ENERGY_REDUCED):
+                       energy=ENERGY_REDUCED, integrator=MHM):
     """Times the candidate schedules of srhd_fluid_step on these patches; returns (Sched of the
     fastest, [(groups, chunk, occupancy, ms per step), ...])."""
     _need_cuda(padded, dt_lev, level)
@@ -306,7 +310,7 @@ def srhd_autotune_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riem
         out = torch.empty((P, 5, 8, 8, 8), dtype=torch.float64, device=padded.device)
     sch = Sched(0, 1, padded.device)
     d = _patches(padded, dh, level, ghost)
-    prm = _params(theta, riemann, prec, max_retry, guess, sch, energy)
+    prm = _params(theta, riemann, prec, max_retry, guess, sch, energy, integrator)
     table = (srhd_tune_entry * 32)()
     n = _int(0)
     _check(_lib.srhd_autotune_step(ctypes.byref(d), _ptr(out), _ptr(dt_lev), ctypes.byref(prm),
@@ -353,9 +357,9 @@ def srhd_autotune_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, 
 
 def srhd_fluid_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann=HLLC,
                     prec=PREC_FP64, max_retry=4, stats=None, ghost=None, guess=None, sched=None,
-                    energy=ENERGY_REDUCED):
-    """One MUSCL-Hancock step: padded cons [P][5][N][N][N] -> interior [P][5][8][8][8].
-    energy=ENERGY_TOTAL runs the original scheme on (D, M, E)."""
+                    energy=ENERGY_REDUCED, integrator=MHM):
+    """One MUSCL-Hancock (or, integrator=VL, VL) step: padded cons [P][5][N][N][N] -> interior
+    [P][5][8][8][8].  energy=ENERGY_TOTAL runs the original scheme on (D, M, E)."""
     _need_cuda(padded, dt_lev, level, stats)
     P = padded.shape[0]
     N = padded.shape[-1]
@@ -364,7 +368,7 @@ def srhd_fluid_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann
         out = torch.empty((P, 5, 8, 8, 8), dtype=torch.float64, device=padded.device)
     _need_cuda(out)
     d = _patches(padded, dh, level, g)
-    prm = _params(theta, riemann, prec, max_retry, guess, sched, energy)
+    prm = _params(theta, riemann, prec, max_retry, guess, sched, energy, integrator)
     _check(_lib.srhd_fluid_step(ctypes.byref(d), _ptr(out), _ptr(dt_lev), ctypes.byref(prm),
                                 _ptr(stats), _stream()))
     return out

@@ -49,7 +49,7 @@ def test_argument_errors_are_reported_without_a_gpu(lib):
     assert b"overlap" in lib.srhd_last_error()
     assert lib.srhd_prim2cons(0, 1, a + 1, a + 400, None) == -1      # misaligned
     lib.srhd_abi_version.restype = ctypes.c_int
-    assert lib.srhd_abi_version() == 3
+    assert lib.srhd_abi_version() == 4
 
 
 def test_step_descriptor_checks(lib):
@@ -114,11 +114,17 @@ def test_schedule_checks(lib):
     assert call() == -3 and b"occupancy" in S._lib.srhd_last_error()
     prm.sched = S.srhd_sched(0, 1, 3, None)
     assert call() == -1 and b"occupancy" in S._lib.srhd_last_error()
-    assert S._lib.srhd_step_occupancy(5, 0, 0, 0, 0) == -1
-    assert S._lib.srhd_step_occupancy(0, 7, 0, 0, 0) == -1
-    assert S._lib.srhd_step_occupancy(1, 0, 0, 1, 0) == -1
-    assert S._lib.srhd_step_occupancy(0, 0, 0, 2, 0) == -3
-    assert S._lib.srhd_step_occupancy(0, 1, 0, 2, 0) == -3
+    def occ(prec, kind, gather, occupancy, energy=0, integrator=0):
+        q = S.srhd_step_params()
+        q.prec, q.guess, q.energy, q.integrator = prec, S.srhd_guess(kind, None, 0), energy, integrator
+        q.sched = S.srhd_sched(0, 1, occupancy, None)
+        return S._lib.srhd_step_occupancy(ctypes.byref(q), gather)
+    assert S._lib.srhd_step_occupancy(None, 0) == -1
+    assert occ(5, 0, 0, 0) == -1
+    assert occ(0, 7, 0, 0) == -1
+    assert occ(1, 0, 0, 1) == -1
+    assert occ(0, 0, 0, 2) == -3
+    assert occ(0, 1, 0, 2) == -3
     # the original (total-energy) scheme: padded layout, FP64 or FP32, analytic guess
     prm.sched = S.srhd_sched(0, 1, 0, None)
     prm.energy = 2
@@ -131,7 +137,20 @@ def test_schedule_checks(lib):
     assert call() == -1                      # learned guess without weights: rejected first
     prm.guess = S.srhd_guess(0, None, 0)
     prm.energy = 0
-    assert S._lib.srhd_step_occupancy(0, 0, 0, 0, 2) == -1
-    assert S._lib.srhd_step_occupancy(1, 0, 0, 0, 1) == -3
-    assert S._lib.srhd_step_occupancy(0, 1, 0, 0, 1) == -3
-    assert S._lib.srhd_step_occupancy(0, 0, 1, 0, 1) == -3 and b"padded" in S._lib.srhd_last_error()
+    assert occ(0, 0, 0, 0, energy=2) == -1
+    assert occ(1, 0, 0, 0, energy=1) == -3
+    assert occ(0, 1, 0, 0, energy=1) == -3
+    assert occ(0, 0, 1, 0, energy=1) == -3 and b"padded" in S._lib.srhd_last_error()
+    # the VL integrator: padded layout, analytic guess, reduced energy, ghost >= 3
+    prm.integrator = 2
+    assert call() == -1 and b"integrator" in S._lib.srhd_last_error()
+    prm.integrator = 1
+    prm.energy = 1
+    assert call() == -3 and b"VL" in S._lib.srhd_last_error()
+    prm.energy = 0
+    d.ghost = 2
+    assert call() == -1 and b"ghost" in S._lib.srhd_last_error()
+    d.ghost = 3
+    prm.integrator = 0
+    assert occ(0, 0, 1, 0, integrator=1) == -3
+    assert occ(2, 1, 0, 0, integrator=1) == -3
