@@ -71,7 +71,14 @@ def lib():
         fn.argtypes = [ctypes.c_int, _p, _p, _p]
         fn.restype = None
     L.or_fluid_step.argtypes = [_i64, ctypes.c_int, _p, _p, _p, _p, _d, ctypes.c_int,
-                                ctypes.c_int, ctypes.c_int, ctypes.c_int, _p, _p]
+                                ctypes.c_int, ctypes.c_int, ctypes.c_int, _p, _p, _p]
+    L.or_fill_ghosts_coarse.argtypes = [_i64, ctypes.c_int, _p, _p, _p, _i64, ctypes.c_int, _p, _p,
+                                        _d, _d, _p, _p]
+    L.or_fill_ghosts_coarse.restype = ctypes.c_int
+    L.or_restrict.argtypes = [_i64, _p, _p, _p, _p]
+    L.or_restrict.restype = None
+    L.or_flux_correct.argtypes = [_i64, _p, _p, _p, _p, _d]
+    L.or_flux_correct.restype = _i64
     L.or_prim2cons_total.argtypes = [_i64, _p, _p]
     L.or_prim2cons_total.restype = None
     L.or_cons2prim_total_one.argtypes = [_p, _p, ctypes.POINTER(_d), ctypes.POINTER(ctypes.c_int)]
@@ -268,24 +275,29 @@ def extract_interior(padded, ghost=3):
 
 
 def fluid_step(padded, dt_lev, dh_lev, level=None, theta=1.5, solver=HLLC, ghost=3,
-               max_retry=4, scheme=0, integrator=0):
+               max_retry=4, scheme=0, integrator=0, bflux=False):
     """One MUSCL-Hancock step of every padded patch [P][5][N][N][N] -> interior [P][5][8][8][8].
 
     Returns (out, counts) with counts = (unphysical states in the final attempt, non-converged
-    inversions, solver iterations, retried patch attempts).
+    inversions, solver iterations, retried patch attempts, VL predictor fallbacks); with
+    bflux=True, (out, counts, fluxes [P][6][5][64] through the patch faces in the final attempt).
     """
     padded = _f64(padded)
     P = padded.shape[0]
     out = np.empty((P, 5, 8, 8, 8))
-    counts = np.zeros(4, dtype=np.int64)
+    counts = np.zeros(5, dtype=np.int64)
+    bf = np.empty((P, 6, 5, 64)) if bflux else None
     dt_lev = _f64(np.atleast_1d(dt_lev))
     dh_lev = _f64(np.atleast_1d(dh_lev))
     lv = None if level is None else np.ascontiguousarray(level, dtype=np.int8)
     rc = lib().or_fluid_step(P, ghost, _ptr(padded), None if lv is None else _ptr(lv),
                              _ptr(dh_lev), _ptr(dt_lev), float(theta), int(solver),
-                             int(max_retry), int(scheme), int(integrator), _ptr(out), _ptr(counts))
+                             int(max_retry), int(scheme), int(integrator), _ptr(out), _ptr(counts),
+                             None if bf is None else _ptr(bf))
     if rc != 0:
         raise ValueError("ghost depth must be at least %d" % (3 if integrator else 2))
+    if bflux:
+        return out, counts, bf
     return out, counts
 
 
@@ -295,3 +307,46 @@ def num_threads():
 
 def set_num_threads(n):
     lib().or_set_num_threads(int(n))
+
+
+# ---------------------------------------------------------------- AMR neighbour operations
+NB_COARSE = -2
+
+
+def fill_ghosts_coarse(fine_padded, neighbor, parent, octant, coarse_old, coarse_new=None,
+                       alpha=0.0, theta=1.5, ghost=3, ghost_c=3):
+    """Fill, in place, the ghost cells of fine padded patches whose neighbour slot is NB_COARSE
+    by limited linear interpolation from the padded parents (conserved variables; primitive
+    variables where the conserved result fails Eq. 30).  Returns (interpolated, fallbacks)."""
+    assert fine_padded.flags.c_contiguous and fine_padded.dtype == np.float64
+    neighbor = np.ascontiguousarray(neighbor, dtype=np.int32)
+    parent = np.ascontiguousarray(parent, dtype=np.int32)
+    octant = np.ascontiguousarray(octant, dtype=np.int8)
+    co = _f64(coarse_old)
+    cn = None if coarse_new is None else _f64(coarse_new)
+    counts = np.zeros(2, dtype=np.int64)
+    rc = lib().or_fill_ghosts_coarse(fine_padded.shape[0], ghost, _ptr(neighbor), _ptr(parent),
+                                     _ptr(octant), co.shape[0], ghost_c, _ptr(co),
+                                     None if cn is None else _ptr(cn), float(alpha), float(theta),
+                                     _ptr(fine_padded), _ptr(counts))
+    if rc != 0:
+        raise ValueError("bad parent index or too few coarse ghost layers")
+    return int(counts[0]), int(counts[1])
+
+
+def restrict(coarse, parent_of, child, fine):
+    """Overwrite coarse[parent_of[p]] with the average of its eight children child[p][0..7]."""
+    assert coarse.flags.c_contiguous and coarse.dtype == np.float64
+    parent_of = np.ascontiguousarray(parent_of, dtype=np.int32)
+    child = np.ascontiguousarray(child, dtype=np.int32)
+    fine = _f64(fine)
+    lib().or_restrict(parent_of.shape[0], _ptr(parent_of), _ptr(child), _ptr(fine), _ptr(coarse))
+
+
+def flux_correct(coarse, faces, coarse_flux, fine_flux, dh_c):
+    """Coarse-fine flux correction in place; faces [n][6] = (coarse, side, fine[4]).  Returns
+    the number of coarse cells left uncorrected because the corrected state fails Eq. 30."""
+    assert coarse.flags.c_contiguous and coarse.dtype == np.float64
+    faces = np.ascontiguousarray(faces, dtype=np.int32).reshape(-1, 6)
+    return int(lib().or_flux_correct(faces.shape[0], _ptr(faces), _ptr(coarse),
+                                     _ptr(_f64(coarse_flux)), _ptr(_f64(fine_flux)), float(dh_c)))

@@ -662,6 +662,7 @@ typedef struct {
   int64_t iters;
   int centre_bad;           /* an input cell of the stencil is unphysical (no retry helps) */
   int face_bad;             /* a half-step face state failed the inversion */
+  int64_t pred_fallback;    /* VL predictor states replaced by the cell's state at t^n */
 } or_counts;
 
 /* Centre primitives, computed once per needed cell. */
@@ -690,8 +691,23 @@ static const double *or_cell_prim(or_prim_cache *C, int i, int j, int k)
 
 /* Step of one patch with limiter coefficient theta.  Writes out[5][512], the updated interior
  * conserved variables, and returns the number of them that fail the physical check (Eq. 30). */
+/* Boundary fluxes of a patch: bflux[s][f][b * 8 + a] for face s = 2 d + u (u = 1: the upper
+ * face), (a, b) the transverse coordinates in increasing axis order; interface fluxes fx are
+ * indexed (d * 64 + a' * 8 + b') * 9 + c as in the steps below, with a' the higher and b' the
+ * lower transverse axis. */
+static void or_boundary_fluxes(const double (*fx)[5], double *bflux)
+{
+  if (!bflux) return;
+  for (int d = 0; d < 3; d++)
+    for (int u = 0; u < 2; u++)
+      for (int b = 0; b < PS; b++)
+        for (int a = 0; a < PS; a++)
+          for (int f = 0; f < NF; f++)
+            bflux[((2 * d + u) * NF + f) * 64 + b * 8 + a] = fx[(d * 64 + b * 8 + a) * 9 + (u ? PS : 0)][f];
+}
+
 static int or_step_patch(const or_patch *P, double dt, double dh, double theta, int riemann,
-                          int scheme, double *out, or_counts *cnt)
+                          int scheme, double *out, or_counts *cnt, double *bflux)
 {
   or_prim_cache *C = (or_prim_cache *)calloc(1, sizeof(or_prim_cache));
   C->P = P;
@@ -774,6 +790,7 @@ static int or_step_patch(const or_patch *P, double dt, double dh, double theta, 
           out[f * 512 + (k * PS + j) * PS + i] = or_get(P, f, i, j, k) - full * acc;
         }
       }
+  or_boundary_fluxes((const double (*)[5])fx, bflux);
   int nbad = 0;
   for (int c = 0; c < 512; c++) {
     double u[5];
@@ -843,10 +860,11 @@ static void sc_riemann(int scheme, int riemann, int d, const double wl[5], const
  *              the cell-centre primitives as the face states, then W*(c) = cons -> prim of U*;
  *   corrector  the interface flux from PLM face states of W* (W* -/+ slope/2 on either side),
  *              U^{n+1} = U^n - (dt/dh) sum_d (F_{+1/2} - F_{-1/2}).
- * A predictor state that fails the inversion cannot be cured by the limiter and ends the
- * attempts (centre_bad).  Returns the number of output cells failing Eq. 30. */
+ * A predictor state that fails the inversion (no limiter acts on it) is replaced by the cell's
+ * state at t^n, W* = W^n: the half step is dropped for that cell.  Returns the number of output
+ * cells failing Eq. 30. */
 static int or_vl_step_patch(const or_patch *P, double dt, double dh, double theta, int riemann,
-                            int scheme, double *out, or_counts *cnt)
+                            int scheme, double *out, or_counts *cnt, double *bflux)
 {
   or_vl_cache *C = (or_vl_cache *)calloc(1, sizeof(or_vl_cache));
   C->P = P;
@@ -874,7 +892,10 @@ static int or_vl_step_patch(const or_patch *P, double dt, double dh, double thet
         int it = 0;
         int st = sc_cons2prim(scheme, u, wh[VIDX(i, j, k)], &it);
         cnt->iters += it;
-        if (st == OR_ST_UNPHYSICAL) { cnt->unphys++; cnt->centre_bad = 1; }
+        if (st == OR_ST_UNPHYSICAL) {
+          for (int f = 0; f < 5; f++) wh[VIDX(i, j, k)][f] = wc[f];
+          cnt->pred_fallback++;
+        }
       }
   double (*fx)[5] = (double (*)[5])calloc(3 * 9 * 64, sizeof(*fx));
   for (int d = 0; d < 3; d++)
@@ -911,6 +932,7 @@ static int or_vl_step_patch(const or_patch *P, double dt, double dh, double thet
           out[f * 512 + (k * PS + j) * PS + i] = or_get(P, f, i, j, k) - full * acc;
         }
       }
+  or_boundary_fluxes((const double (*)[5])fx, bflux);
   int nbad = 0;
   for (int c = 0; c < 512; c++) {
     double u[5];
@@ -929,39 +951,47 @@ static int or_vl_step_patch(const or_patch *P, double dt, double dh, double thet
  * times, and finally once with a zero coefficient (piecewise-constant reconstruction).  An
  * unphysical input cell cannot be cured by reconstruction and ends the attempts.
  * integrator 0: MUSCL-Hancock (ghost >= 2); 1: VL (ghost >= 3; only updated cells trigger
- * the retry, a predictor state that fails ends the attempts).
+ * the retry; a predictor state that fails is replaced by the cell's state at t^n).  bflux (or NULL): [P][6][5][64]
+ * fluxes through the six faces of each patch in its final attempt (layout of
+ * or_boundary_fluxes).
  * counts = {unphysical inversions + failed output cells of the final attempt, non-converged
- *           inversions, solver iterations, retried attempts}. */
+ *           inversions, solver iterations, retried attempts, VL predictor fallbacks of the final
+ *           attempt}. */
 int or_fluid_step(int64_t n_patch, int ghost, const double *padded, const int8_t *level,
                   const double *dh_lev, const double *dt_lev, double theta, int riemann,
-                  int max_retry, int scheme, int integrator, double *out, int64_t *counts)
+                  int max_retry, int scheme, int integrator, double *out, int64_t *counts,
+                  double *bflux)
 {
   if (ghost < (integrator ? 3 : 2)) return -1;
   int N = PS + 2 * ghost;
   int64_t per = (int64_t)NF * N * N * N;
-  int64_t unphys = 0, noconv = 0, iters = 0, retries = 0;
-#pragma omp parallel for schedule(dynamic, 1) reduction(+ : unphys, noconv, iters, retries)
+  int64_t unphys = 0, noconv = 0, iters = 0, retries = 0, pfb = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : unphys, noconv, iters, retries, pfb)
   for (int64_t p = 0; p < n_patch; p++) {
     or_patch P = {ghost, N, padded + p * per};
     int lv = level ? level[p] : 0;
     double th = theta;
     for (int attempt = 0;; attempt++) {
-      or_counts c = {0, 0, 0, 0, 0};
+      or_counts c = {0, 0, 0, 0, 0, 0};
+      double *bf = bflux ? bflux + p * 6 * NF * 64 : NULL;
       int nbad = integrator
-                     ? or_vl_step_patch(&P, dt_lev[lv], dh_lev[lv], th, riemann, scheme, out + p * NF * 512, &c)
-                     : or_step_patch(&P, dt_lev[lv], dh_lev[lv], th, riemann, scheme, out + p * NF * 512, &c);
+                     ? or_vl_step_patch(&P, dt_lev[lv], dh_lev[lv], th, riemann, scheme, out + p * NF * 512, &c, bf)
+                     : or_step_patch(&P, dt_lev[lv], dh_lev[lv], th, riemann, scheme, out + p * NF * 512, &c, bf);
       iters += c.iters;
       int fail = c.face_bad || nbad > 0;
       if (!fail || c.centre_bad || th == 0.0) {
         unphys += c.unphys + nbad;
         noconv += c.noconv;
+        pfb += c.pred_fallback;
         break;
       }
       retries++;
       th = (attempt < max_retry) ? 0.75 * th : 0.0;
     }
   }
-  if (counts) { counts[0] = unphys; counts[1] = noconv; counts[2] = iters; counts[3] = retries; }
+  if (counts) {
+    counts[0] = unphys; counts[1] = noconv; counts[2] = iters; counts[3] = retries; counts[4] = pfb;
+  }
   return 0;
 }
 
@@ -987,17 +1017,18 @@ int or_fill_ghosts(int64_t n_patch, int ghost, int64_t n_src, const double *inte
       for (int y = 0; y < N; y++)
         for (int x = 0; x < N; x++) {
           int c[3] = {x - ghost, y - ghost, z - ghost};
-          /* clamp toward the domain where a face neighbour is missing */
+          /* clamp toward the domain where a face neighbour is the domain boundary (-1) */
           for (int d = 0; d < 3; d++) {
             int o = (c[d] < 0) ? -1 : (c[d] >= PS ? 1 : 0);
             if (o == 0) continue;
             int face = 13 + o * (d == 0 ? 1 : (d == 1 ? 3 : 9));
-            if (nb[face] < 0) c[d] = (o < 0) ? 0 : PS - 1;
+            if (nb[face] == -1) c[d] = (o < 0) ? 0 : PS - 1;
           }
           int o[3];
           for (int d = 0; d < 3; d++) o[d] = (c[d] < 0) ? -1 : (c[d] >= PS ? 1 : 0);
           int slot = (o[2] + 1) * 9 + (o[1] + 1) * 3 + (o[0] + 1);
           int64_t src = nb[slot];
+          if (src == OR_NB_COARSE) continue;      /* filled from the coarser level */
           if (src < 0 || src >= n_src) { bad = 1; continue; }
           int si = c[0] - PS * o[0], sj = c[1] - PS * o[1], sk = c[2] - PS * o[2];
           for (int f = 0; f < NF; f++)
@@ -1006,6 +1037,188 @@ int or_fill_ghosts(int64_t n_patch, int ghost, int64_t n_src, const double *inte
         }
   }
   return bad ? -1 : 0;
+}
+
+/* ===================================================================================== */
+/* AMR neighbour operations (Sec. 3.4 items 3 and 4; refinement ratio 2)                 */
+/* ===================================================================================== */
+
+/* The neighbour slot that a padded cell's value comes from, after the outflow clamp; writes the
+ * (possibly clamped) interior coordinates to c. */
+static int or_ghost_slot(const int32_t *nb, int c[3])
+{
+  for (int d = 0; d < 3; d++) {
+    int o = (c[d] < 0) ? -1 : (c[d] >= PS ? 1 : 0);
+    if (o == 0) continue;
+    int face = 13 + o * (d == 0 ? 1 : (d == 1 ? 3 : 9));
+    if (nb[face] == -1) c[d] = (o < 0) ? 0 : PS - 1;
+  }
+  int o[3];
+  for (int d = 0; d < 3; d++) o[d] = (c[d] < 0) ? -1 : (c[d] >= PS ? 1 : 0);
+  return (o[2] + 1) * 9 + (o[1] + 1) * 3 + (o[0] + 1);
+}
+
+/* Coarse-to-fine ghost fill.  A ghost cell of fine patch p whose neighbour slot is
+ * OR_NB_COARSE lies on the parent level: with I = 8 b + c the cell's fine index relative to the
+ * parent (b the patch's octant bit along that axis, c its coordinate in the patch), the coarse
+ * cell is C = floor(I / 2) and the fine cell's centre sits at -1/4 or +1/4 of a coarse cell from
+ * C's centre.  The value is the coarse state (time-interpolated, (1 - alpha) old + alpha new)
+ * plus the limited coarse slope along each axis times that offset -- a linear interpolation
+ * whose eight children average back to the coarse value.  The conserved variables are
+ * interpolated; if the result fails Eq. 30 the primitive variables of the same coarse cells are
+ * interpolated instead and converted back (Sec. 3.4, ghost-zone interpolation).
+ * coarse_*: padded parents [n_coarse][5][Nc^3] with ghost_c >= ghost / 2 + 2 layers. */
+static void or_coarse_state(const double *co, const double *cn, double alpha, int Nc, int gc,
+                            int ci, int cj, int ck, double u[5])
+{
+  int64_t N3 = (int64_t)Nc * Nc * Nc;
+  int64_t off = ((int64_t)(ck + gc) * Nc + (cj + gc)) * Nc + (ci + gc);
+  for (int f = 0; f < 5; f++) {
+    double a = co[f * N3 + off];
+    u[f] = cn ? (1.0 - alpha) * a + alpha * cn[f * N3 + off] : a;
+  }
+}
+
+int or_fill_ghosts_coarse(int64_t n_fine, int ghost, const int32_t *neighbor, const int32_t *parent,
+                          const int8_t *octant, int64_t n_coarse, int ghost_c,
+                          const double *coarse_old, const double *coarse_new, double alpha,
+                          double theta, double *fine_padded, int64_t *counts)
+{
+  if (ghost_c < ghost / 2 + 2) return -1;
+  int N = PS + 2 * ghost, Nc = PS + 2 * ghost_c;
+  int64_t per = (int64_t)NF * N * N * N, perc = (int64_t)NF * Nc * Nc * Nc;
+  int64_t n_interp = 0, n_fallback = 0;
+  int bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : n_interp, n_fallback) reduction(| : bad)
+  for (int64_t p = 0; p < n_fine; p++) {
+    const int32_t *nb = neighbor + p * 27;
+    int64_t par = parent[p];
+    if (par < 0 || par >= n_coarse) { bad = 1; continue; }
+    const double *co = coarse_old + par * perc;
+    const double *cn = coarse_new ? coarse_new + par * perc : NULL;
+    int bit[3] = {octant[p] & 1, (octant[p] >> 1) & 1, (octant[p] >> 2) & 1};
+    for (int z = 0; z < N; z++)
+      for (int y = 0; y < N; y++)
+        for (int x = 0; x < N; x++) {
+          int c[3] = {x - ghost, y - ghost, z - ghost};
+          if (c[0] >= 0 && c[0] < PS && c[1] >= 0 && c[1] < PS && c[2] >= 0 && c[2] < PS) continue;
+          int cc[3] = {c[0], c[1], c[2]};
+          if (nb[or_ghost_slot(nb, cc)] != OR_NB_COARSE) continue;
+          int C[3];
+          double sgn[3];
+          for (int d = 0; d < 3; d++) {
+            int I = 8 * bit[d] + c[d];
+            C[d] = (I >= 0) ? I / 2 : -((1 - I) / 2);       /* floor(I / 2) */
+            sgn[d] = (I - 2 * C[d]) ? 0.25 : -0.25;
+          }
+          double u0[5], um[3][5], up[3][5];
+          or_coarse_state(co, cn, alpha, Nc, ghost_c, C[0], C[1], C[2], u0);
+          for (int d = 0; d < 3; d++) {
+            int e[3] = {d == 0, d == 1, d == 2};
+            or_coarse_state(co, cn, alpha, Nc, ghost_c, C[0] - e[0], C[1] - e[1], C[2] - e[2], um[d]);
+            or_coarse_state(co, cn, alpha, Nc, ghost_c, C[0] + e[0], C[1] + e[1], C[2] + e[2], up[d]);
+          }
+          double u[5];
+          for (int f = 0; f < 5; f++) {
+            u[f] = u0[f];
+            for (int d = 0; d < 3; d++) u[f] += sgn[d] * or_slope(um[d][f], u0[f], up[d][f], theta);
+          }
+          n_interp++;
+          if (!or_is_physical(u)) {
+            double w0[5], wm[3][5], wp[3][5], w[5];
+            int it;
+            or_cons2prim_one(u0, w0, NULL, &it);
+            for (int d = 0; d < 3; d++) {
+              or_cons2prim_one(um[d], wm[d], NULL, &it);
+              or_cons2prim_one(up[d], wp[d], NULL, &it);
+            }
+            for (int f = 0; f < 5; f++) {
+              w[f] = w0[f];
+              for (int d = 0; d < 3; d++) w[f] += sgn[d] * or_slope(wm[d][f], w0[f], wp[d][f], theta);
+            }
+            or_prim2cons_one(w, u);
+            n_fallback++;
+          }
+          for (int f = 0; f < NF; f++)
+            fine_padded[p * per + (((int64_t)f * N + z) * N + y) * N + x] = u[f];
+        }
+  }
+  if (counts) { counts[0] = n_interp; counts[1] = n_fallback; }
+  return bad ? -1 : 0;
+}
+
+/* Restriction: each parent cell becomes the average of its eight children (the volume-weighted
+ * average of Sec. 3.4, exact conservation).  child[p][o] (o = octant bits x | y << 1 | z << 2)
+ * lists the children of coarse patch parent_of[p]; coarse[parent_of[p]] is overwritten. */
+void or_restrict(int64_t n, const int32_t *parent_of, const int32_t *child, const double *fine,
+                 double *coarse)
+{
+  for (int64_t p = 0; p < n; p++) {
+    double *cp = coarse + (int64_t)parent_of[p] * NF * 512;
+    for (int k = 0; k < PS; k++)
+      for (int j = 0; j < PS; j++)
+        for (int i = 0; i < PS; i++) {
+          int o = (i >= 4) | ((j >= 4) << 1) | ((k >= 4) << 2);
+          const double *fp = fine + (int64_t)child[p * 8 + o] * NF * 512;
+          int fi = 2 * (i & 3), fj = 2 * (j & 3), fk = 2 * (k & 3);
+          for (int f = 0; f < NF; f++) {
+            double s = 0.0;
+            for (int dz = 0; dz < 2; dz++)
+              for (int dy = 0; dy < 2; dy++)
+                for (int dx = 0; dx < 2; dx++)
+                  s += fp[f * 512 + ((fk + dz) * PS + (fj + dy)) * PS + (fi + dx)];
+            cp[f * 512 + (k * PS + j) * PS + i] = 0.125 * s;
+          }
+        }
+  }
+}
+
+/* Coarse-fine flux correction (Sec. 3.4 item 4).  Face record q: coarse patch faces[q].coarse,
+ * side s = 2 d + u (axis d, u = 1 upper), and the four fine patches across that face, fine[t]
+ * for the quadrant t = (a >= 4) + 2 (b >= 4) of the face cell (a, b) (transverse coordinates in
+ * increasing axis order).  Fluxes are per face cell, [patch][6][5][64], time-integrated by the
+ * caller: coarse_flux = dt_c F_c, fine_flux = sum over the fine steps of dt_f F_f.  The coarse
+ * cell at the face gets dU = (u ? -1 : +1) (<fine> - coarse) / dh_c, <fine> the mean of the four
+ * fine face cells covering it; a cell whose corrected state fails Eq. 30 keeps its state.  The
+ * records are applied side by side (s = 0 .. 5): a corner cell on faces of several sides gets
+ * each correction in that order. */
+int64_t or_flux_correct(int64_t n_face, const int32_t *faces /* [n][6]: coarse, side, fine[4] */,
+                        double *coarse, const double *coarse_flux, const double *fine_flux,
+                        double dh_c)
+{
+  int64_t skipped = 0;
+  for (int side = 0; side < 6; side++)
+  for (int64_t q = 0; q < n_face; q++) {
+    const int32_t *r = faces + q * 6;
+    if (r[1] != side) continue;
+    int64_t P = r[0];
+    int s = r[1], d = s >> 1, up = s & 1;
+    int t0 = (d == 0) ? 1 : 0, t1 = (d == 2) ? 1 : 2;
+    for (int b = 0; b < PS; b++)
+      for (int a = 0; a < PS; a++) {
+        int child = r[2 + (a >= 4) + 2 * (b >= 4)];
+        int ci[3];
+        ci[d] = up ? PS - 1 : 0;
+        ci[t0] = a;
+        ci[t1] = b;
+        int64_t cell = (int64_t)(ci[2] * PS + ci[1]) * PS + ci[0];
+        double u[5];
+        for (int f = 0; f < NF; f++) {
+          double fc = coarse_flux[((P * 6 + s) * NF + f) * 64 + b * 8 + a];
+          double ff = 0.0;
+          for (int db = 0; db < 2; db++)
+            for (int da = 0; da < 2; da++) {
+              int fa = 2 * (a & 3) + da, fb = 2 * (b & 3) + db;
+              ff += fine_flux[(((int64_t)child * 6 + (s ^ 1)) * NF + f) * 64 + fb * 8 + fa];
+            }
+          ff *= 0.25;
+          u[f] = coarse[(P * NF + f) * 512 + cell] + (up ? -1.0 : 1.0) * (ff - fc) / dh_c;
+        }
+        if (!or_is_physical(u)) { skipped++; continue; }
+        for (int f = 0; f < NF; f++) coarse[(P * NF + f) * 512 + cell] = u[f];
+      }
+  }
+  return skipped;
 }
 
 /* Copy the interior of padded patches into a compact [P][5][8^3] array. */

@@ -42,7 +42,18 @@ void or_hllc(int d, const double wl[5], const double wr[5], double F[5]);
 int or_is_physical(const double u[5]);
 int or_fluid_step(int64_t n_patch, int ghost, const double *padded, const int8_t *level,
                   const double *dh_lev, const double *dt_lev, double theta, int riemann,
-                  int max_retry, int scheme, int integrator, double *out, int64_t *counts);
+                  int max_retry, int scheme, int integrator, double *out, int64_t *counts,
+                  double *bflux);
+/* AMR neighbour operations (refinement ratio 2). */
+#define OR_NB_COARSE (-2)   /* neighbour slot covered by the next coarser level */
+int or_fill_ghosts_coarse(int64_t n_fine, int ghost, const int32_t *neighbor, const int32_t *parent,
+                          const int8_t *octant, int64_t n_coarse, int ghost_c,
+                          const double *coarse_old, const double *coarse_new, double alpha,
+                          double theta, double *fine_padded, int64_t *counts);
+void or_restrict(int64_t n, const int32_t *parent_of, const int32_t *child, const double *fine,
+                 double *coarse);
+int64_t or_flux_correct(int64_t n_face, const int32_t *faces, double *coarse,
+                        const double *coarse_flux, const double *fine_flux, double dh_c);
 void or_prim2cons_total_one(const double w[5], double u[5]);
 int or_cons2prim_total_one(const double u[5], double w[5], double *ht_out, int *iters);
 void or_prim2cons_total(int64_t n, const double *prim, double *cons);

@@ -83,3 +83,56 @@ def sine_x_l1(n, theta0, amp, t_frac, theta_lim=1.5, scheme=0, integrator=0):
     w, _ = to_prim(c1, scheme)
     exact = rho0 * (1 + amp * np.sin(2 * np.pi * (x - cs * t)))
     return np.mean(np.abs(1 - w[:, 0] / exact))
+
+
+def amr_setup(nc, lo, hi, prim_fn):
+    """Two-level hierarchy of workloads.two_level with primitive state prim_fn(x, y, z) -> [5] arrays;
+    returns (geometry, coarse cons, fine cons), the refined coarse patches holding the average of
+    their children."""
+    t = W.two_level(nc, lo, hi)
+    def cons_of(xyz):
+        x, y, z = xyz
+        w = np.stack(prim_fn(x, y, z), axis=1)                  # [P][5][8][8][8]
+        P = w.shape[0]
+        c = O.prim2cons(w.reshape(P, 5, 512).transpose(1, 0, 2).reshape(5, -1))
+        return np.ascontiguousarray(c.reshape(5, P, 512).transpose(1, 0, 2)).reshape(P, 5, 8, 8, 8)
+    cc = cons_of(t["coarse_xyz"])
+    cf = cons_of(t["fine_xyz"])
+    O.restrict(cc, t["parent_of"], t["child"], cf)
+    return t, cc, cf
+
+
+def amr_step(t, cc, cf, c_cfl=0.5, theta=1.5, correct=True, integrator=0):
+    """One coarse step and two fine sub-steps of the two-level hierarchy with the oracle:
+    same-level ghost fill, coarse-to-fine ghost interpolation (time-interpolated for the second
+    sub-step), restriction and coarse-fine flux correction.  Returns (cc, cf, dt_c, info)."""
+    dh = [t["dh_c"], t["dh_f"]]
+    both = np.concatenate([cc, cf])
+    lev = np.concatenate([np.zeros(cc.shape[0]), np.ones(cf.shape[0])])
+    dt_lev, _, _ = O.cfl_dt(both, lev, dh, c_cfl)
+    pad_c = O.fill_ghosts(cc, t["coarse_neighbor"], 3)
+    cn, cnt_c, fc = O.fluid_step(pad_c, [dt_lev[0]], [dh[0]], theta=theta, bflux=True,
+                                 integrator=integrator)
+    pad_cn = O.fill_ghosts(cn, t["coarse_neighbor"], 3)
+    ff = np.zeros((cf.shape[0], 6, 5, 64))
+    f = cf
+    info = {"coarse_counts": cnt_c, "fine_counts": [], "interp": []}
+    for sub in range(2):
+        pad_f = O.fill_ghosts(f, t["fine_neighbor"], 3)
+        info["interp"].append(O.fill_ghosts_coarse(pad_f, t["fine_neighbor"], t["parent"], t["octant"],
+                                                   pad_c, pad_cn if sub else None, 0.5 * sub, theta))
+        f, cnt_f, flux = O.fluid_step(pad_f, [dt_lev[1]], [dh[1]], theta=theta, bflux=True,
+                                      integrator=integrator)
+        ff += dt_lev[1] * flux
+        info["fine_counts"].append(cnt_f)
+    O.restrict(cn, t["parent_of"], t["child"], f)
+    info["skipped"] = O.flux_correct(cn, t["faces"], dt_lev[0] * fc, ff, dh[0]) if correct else 0
+    return cn, f, dt_lev[0], info
+
+
+def amr_totals(t, cc, cf):
+    """Sum of each conserved variable times the cell volume over the unrefined coarse cells and
+    the fine cells."""
+    keep = ~t["refined"]
+    return (cc[keep].sum(axis=(0, 2, 3, 4)) * t["dh_c"] ** 3 +
+            cf.sum(axis=(0, 2, 3, 4)) * t["dh_f"] ** 3)

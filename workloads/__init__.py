@@ -253,6 +253,92 @@ def riemann_1d(n_cells_x, left, right, x0=0.5, length=1.0, ny=1, nz=1):
                      extra={"x": np.ascontiguousarray(x)})
 
 
+# ----------------------------------------------------------------------------- two AMR levels
+def two_level(nc, lo, hi):
+    """Geometry of a periodic two-level patch hierarchy (refinement ratio 2).
+
+    Level 0: nc^3 patches (lexicographic ids, cell size 1 / (8 nc)).  The coarse patches
+    [lo, hi)^3 (strictly inside the box) are refined: each has eight children on level 1, which
+    form an nf^3 block of fine patches, nf = 2 (hi - lo), fine id ((fz nf) + fy) nf + fx relative
+    to the block.  Returns a dict with
+      coarse_neighbor [Pc][27]        same-level table (periodic)
+      fine_neighbor   [Pf][27]        fine ids inside the block, -2 where level 0 covers the slot
+      parent, octant  [Pf]            coarse id of the parent; child position bx | by<<1 | bz<<2
+      parent_of [Pr], child [Pr][8]   refined coarse ids and their children (for restriction)
+      faces [Nf][6]                   (coarse id, side 2 d + u, fine[4]) for every face of an
+                                      unrefined coarse patch that touches a refined one; fine[t]
+                                      covers the face cells (a, b) with t = (a >= 4) + 2 (b >= 4)
+      refined [Pc] bool, dh_c, dh_f, coarse_xyz, fine_xyz (cell centres [P][8][8][8] each)
+    """
+    assert 0 < lo < hi < nc
+    nf = 2 * (hi - lo)
+    cnb = neighbor_table(nc, nc, nc, True)
+    cid = lambda x, y, z: ((z % nc) * nc + (y % nc)) * nc + (x % nc)
+    refined = np.zeros(nc ** 3, dtype=bool)
+    for z in range(lo, hi):
+        for y in range(lo, hi):
+            for x in range(lo, hi):
+                refined[cid(x, y, z)] = True
+    Pf = nf ** 3
+    fid = lambda x, y, z: ((z - 2 * lo) * nf + (y - 2 * lo)) * nf + (x - 2 * lo)
+    inside = lambda x, y, z: all(2 * lo <= v < 2 * hi for v in (x, y, z))
+    fnb = np.full((Pf, 27), -2, dtype=np.int32)
+    parent = np.empty(Pf, dtype=np.int32)
+    octant = np.empty(Pf, dtype=np.int8)
+    fxyz = np.empty((Pf, 3), dtype=np.int64)
+    for fz in range(2 * lo, 2 * hi):
+        for fy in range(2 * lo, 2 * hi):
+            for fx in range(2 * lo, 2 * hi):
+                i = fid(fx, fy, fz)
+                fxyz[i] = (fx, fy, fz)
+                parent[i] = cid(fx // 2, fy // 2, fz // 2)
+                octant[i] = (fx & 1) | ((fy & 1) << 1) | ((fz & 1) << 2)
+                for oz in (-1, 0, 1):
+                    for oy in (-1, 0, 1):
+                        for ox in (-1, 0, 1):
+                            q = (fx + ox, fy + oy, fz + oz)
+                            if inside(*q):
+                                fnb[i, (oz + 1) * 9 + (oy + 1) * 3 + (ox + 1)] = fid(*q)
+    parent_of = np.flatnonzero(refined).astype(np.int32)
+    child = np.empty((parent_of.size, 8), dtype=np.int32)
+    for k, P in enumerate(parent_of):
+        px, py, pz = P % nc, (P // nc) % nc, P // (nc * nc)
+        for o in range(8):
+            child[k, o] = fid(2 * px + (o & 1), 2 * py + ((o >> 1) & 1), 2 * pz + ((o >> 2) & 1))
+    faces = []
+    for P in np.flatnonzero(~refined):
+        c = [P % nc, (P // nc) % nc, P // (nc * nc)]
+        for d in range(3):
+            for u in (0, 1):
+                q = list(c)
+                q[d] += 1 if u else -1
+                Q = cid(*q)
+                if not refined[Q]:
+                    continue
+                qx, qy, qz = q[0] % nc, q[1] % nc, q[2] % nc
+                t0, t1 = (1, 2) if d == 0 else ((0, 2) if d == 1 else (0, 1))
+                fine = []
+                for t in range(4):
+                    bits = [0, 0, 0]
+                    bits[d] = 0 if u else 1                 # the children on P's side of Q
+                    bits[t0], bits[t1] = t & 1, t >> 1
+                    fine.append(fid(2 * qx + bits[0], 2 * qy + bits[1], 2 * qz + bits[2]))
+                faces.append([P, 2 * d + u] + fine)
+    dh_c = 1.0 / (8 * nc)
+    cx, cy, cz = patch_cell_centres(nc, nc, nc, dh_c)
+    dh_f = dh_c / 2
+    c = np.arange(PS)
+    fx = (fxyz[:, 0, None, None, None] * PS + c[None, None, None, :] + 0.5) * dh_f
+    fy = (fxyz[:, 1, None, None, None] * PS + c[None, None, :, None] + 0.5) * dh_f
+    fz = (fxyz[:, 2, None, None, None] * PS + c[None, :, None, None] + 0.5) * dh_f
+    shape = (Pf, PS, PS, PS)
+    return {"coarse_neighbor": cnb, "fine_neighbor": fnb, "parent": parent, "octant": octant,
+            "parent_of": parent_of, "child": child, "faces": np.array(faces, dtype=np.int32),
+            "refined": refined, "dh_c": dh_c, "dh_f": dh_f, "nc": nc, "nf": nf,
+            "coarse_xyz": (cx, cy, cz),
+            "fine_xyz": tuple(np.broadcast_to(v, shape) for v in (fx, fy, fz))}
+
+
 # ----------------------------------------------------------------------------- jet patch list
 def jet_states():
     """Nozzle and ambient primitive states of the jet workload."""
