@@ -233,6 +233,8 @@ def parse():
     ap.add_argument("--sched", default="auto",
                     help="launch schedule of the step: auto (the autotuner's choice per "
                          "configuration) or groups,chunk,occupancy")
+    ap.add_argument("--no-vl", dest="vl", action="store_false",
+                    help="skip the VL integrator's runs")
     ap.add_argument("--only-headline", action="store_true",
                     help="measure the headline configuration only (no analytic-guess, "
                          "configured-input or FP32-inversion comparisons)")
@@ -286,7 +288,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    def run_padded(prec, n_steps, time_kernel=False, guess=None, sched=None):
+    def run_padded(prec, n_steps, time_kernel=False, guess=None, sched=None, integrator=0):
         """n_steps from the initial state with CFL kernel + ghost fill + padded step."""
         bufs[0].copy_(cons0)
         cur = 0
@@ -304,7 +306,7 @@ def main():
                 b = torch.cuda.Event(enable_timing=True)
                 a.record(stream)
             S.srhd_fluid_step(pad, dt, dh, out=bufs[1 - cur], prec=prec, stats=stats, guess=guess,
-                              sched=sched)
+                              sched=sched, integrator=integrator)
             if time_kernel:
                 b.record(stream)
                 evs.append((a, b))
@@ -465,6 +467,31 @@ def main():
             res["fp32_inversion"]["vs_fp64_rel_err"] = {
                 "one_step": field_err(o32, o64),
                 "after_%d_steps" % args.steps: field_err(fin_32.cpu().numpy(), b)}
+
+    # the VL integrator (padded layout: CFL kernel + ghost fill + VL step per step), analytic guess
+    if args.vl and not args.only_headline:
+        res["vl"] = {}
+        finals = {}
+        for prec, name in ((S.PREC_MIXED, "mixed"), (S.PREC_FP64, "fp64")):
+            S.srhd_cfl_dt(cons0, dh, 0.5, dt_lev=dt)
+            S.srhd_fill_ghosts(cons0, nb, 3, padded=pad)
+            sch, table = S.srhd_autotune_step(pad, dt, dh, prec=prec, reps=2, integrator=S.VL)
+            schedules["vl_" + name] = {"groups": sch.groups, "chunk": sch.chunk,
+                                       "occupancy": sch.occupancy,
+                                       "autotune_ms": [[t[0], t[1], t[2], round(t[3], 4)] for t in table]}
+            if args.warmup:
+                run_padded(prec, args.warmup, sched=sch, integrator=S.VL)
+            ms_v, kms_v, st_v, fin_v = run_padded(prec, args.steps, time_kernel=True, sched=sch,
+                                                  integrator=S.VL)
+            finals[name] = fin_v.cpu().numpy()
+            print("# VL %s: %.2f ms for %d steps (step kernel %.3f ms avg); stats %s"
+                  % (name, ms_v, args.steps, float(np.mean(kms_v)), st_v), file=sys.stderr, flush=True)
+            res["vl"][name] = {"value": n_cells * args.steps / (ms_v * 1e-3),
+                               "ms_per_step": ms_v / args.steps,
+                               "step_kernel_ms": float(np.mean(kms_v)), "stats": st_v,
+                               "newton": newton_summary(st_v)}
+        res["vl"]["mixed_vs_fp64_rel_err_after_%d_steps" % args.steps] = field_err(finals["mixed"],
+                                                                                 finals["fp64"])
 
     # ---------------------------------------------------------------- roofline of the step kernel
     kavg = float(np.mean(kms_mx)) * 1e-3

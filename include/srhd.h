@@ -73,9 +73,10 @@ typedef enum { SRHD_ENERGY_REDUCED = 0, SRHD_ENERGY_TOTAL = 1 } srhd_energy;
  * first-order half step U* = U^n - (dt/2dh) sum_d [F_d(W_c, W_{c+d}) - F_d(W_{c-d}, W_c)] with
  * the cell-centre primitives as face states, W* = cons -> prim of U*, then the full step with
  * the fluxes of PLM face states of W*.  Only an updated cell failing Eq. 30 triggers the limiter
- * retry (a predictor state that fails the inversion ends the attempts, as an unphysical input
- * cell does).  VL runs in srhd_fluid_step with ghost >= 3, the analytic guess and the reduced
- * energy, in every precision mode (else SRHD_EUNSUPPORTED). */
+ * retry.  VL runs in srhd_fluid_step with ghost >= 3, the analytic guess and the reduced
+ * energy, in every precision mode (else SRHD_EUNSUPPORTED).  A predictor state that fails the
+ * inversion is replaced by the cell's state at t^n (W* = W^n: the half step is dropped for that
+ * cell) and counted in n_pred_fallback. */
 typedef enum { SRHD_MHM = 0, SRHD_VL = 1 } srhd_integrator;
 
 /* Learned initial guess: device parameters of a 3-64-64-1 SiLU perceptron that maps three
@@ -140,10 +141,14 @@ typedef struct {
  * holds the index in `interior` of the same-level patch at offset (ox, oy, oz); slot 13 is the
  * patch's own index (so a table listing a subset of patches fills only those).  -1 in a face slot
  * marks a domain boundary: ghost cells beyond it copy the nearest interior cell (outflow,
- * zero gradient).  Periodic domains list wrapped neighbours.
+ * zero gradient).  SRHD_NB_COARSE (-2) marks a region covered only by the next coarser level:
+ * those ghost cells are left untouched here and filled by srhd_fill_ghosts_coarse.  Periodic
+ * domains list wrapped neighbours.
  * Fills every ghost cell of padded[n_patch][5][N][N][N] (faces, edges and corners) from
  * interior[n_src][5][8][8][8]; also copies the interior.  A cell whose source index is outside
- * [0, n_src) -- e.g. -1 in an edge slot while no face slot marks a boundary -- is set to NaN. */
+ * [0, n_src) and not SRHD_NB_COARSE -- e.g. -1 in an edge slot while no face slot marks a
+ * boundary -- is set to NaN. */
+#define SRHD_NB_COARSE (-2)
 int srhd_fill_ghosts(int dtype, int64_t n_patch, int ghost, int64_t n_src, const void *interior,
                      const int32_t *neighbor, void *padded, void *stream);
 
@@ -186,6 +191,12 @@ typedef struct {
   srhd_sched sched;        /* launch schedule; all-zero = one workgroup per patch */
   int energy;              /* srhd_energy (0: this paper's reduced energy) */
   int integrator;          /* srhd_integrator (0: MUSCL-Hancock) */
+  double *flux_out;        /* device [n_patch][6][5][64] or NULL: the Riemann fluxes of the final
+                              attempt through the six faces of each patch, face s = 2 d + u (axis
+                              d; u = 1 the upper face), face cell b * 8 + a with (a, b) the two
+                              transverse coordinates in increasing axis order.  Overwritten, not
+                              accumulated (see srhd_flux_accumulate); for the flux correction of
+                              coarse-fine interfaces.  Must not overlap the other arrays. */
 } srhd_step_params;
 
 /* Device counters, accumulated (never reset by the step; see srhd_stats_reset). */
@@ -197,7 +208,8 @@ typedef struct {
   uint64_t n_inversions;   /* inversions performed (all attempts) */
   uint64_t n_retry;        /* extra attempts with a reduced limiter coefficient */
   uint64_t n_mlp;          /* learned-guess evaluations: lanes of wavefronts that ran the network */
-  uint64_t reserved;
+  uint64_t n_pred_fallback; /* VL: predictor states that failed the inversion and were replaced
+                               by the cell's state at t^n (final attempts) */
 } srhd_step_stats;
 
 int srhd_stats_reset(srhd_step_stats *stats, void *stream);
@@ -330,6 +342,59 @@ int srhd_mlp_adam(float *master, float *m1, float *m2, const float *grad, int st
 
 /* Thread-local description of the last non-zero return. */
 const char *srhd_last_error(void);
+/* ---------------------------------------------------------------------------------------- */
+/* AMR neighbours of the step (Sec. 3.4 items 3 and 4), refinement ratio 2                      */
+/* ---------------------------------------------------------------------------------------- */
+
+/* Coarse-to-fine ghost-zone interpolation (Sec. 3.4, "ghost-zone interpolation").  For each fine
+ * patch p, every ghost cell of fine_padded[p] whose neighbour slot (after the outflow clamp of
+ * srhd_fill_ghosts) is SRHD_NB_COARSE is filled from the parent coarse_old[parent[p]] (padded,
+ * ghost_c layers, ghost_c >= ghost / 2 + 2): with I = 8 b + c the cell's fine index relative to
+ * the parent (b the patch's octant bit along that axis, octant[p] = bx | by << 1 | bz << 2; c its
+ * coordinate in the patch), the coarse cell is C = floor(I / 2) and the fine centre lies -1/4 or
+ * +1/4 of a coarse cell from C's centre; the value is u_C plus, per axis, that offset times the
+ * limited slope (the PLM limiter with coefficient theta) of u_{C-1}, u_C, u_{C+1} -- so the eight
+ * children of a coarse cell average to it.  The coarse state is (1 - alpha) old + alpha new when
+ * coarse_new is given (time interpolation for fine sub-steps).  The conserved variables are
+ * interpolated first; where that state fails Eq. 30, the primitive variables of the same coarse
+ * cells (FP64 inversions, analytic guess) are interpolated instead and converted back.
+ * counts (device uint64[2], may be NULL) accumulates {cells interpolated, primitive fallbacks}.
+ * Arrays FP64 on the device; fine_padded is read-modify-written (fill the same-level ghosts with
+ * srhd_fill_ghosts first). */
+int srhd_fill_ghosts_coarse(int64_t n_fine, int ghost, const int32_t *neighbor,
+                            const int32_t *parent, const int8_t *octant, int64_t n_coarse,
+                            int ghost_c, const double *coarse_old, const double *coarse_new,
+                            double alpha, double theta, double *fine_padded, uint64_t *counts,
+                            void *stream);
+
+/* Restriction: coarse[parent_of[q]] = the average of its eight children (the volume-weighted
+ * average that keeps a parent equal to its children, Sec. 3.4): child[q][o], o = bx | by << 1 |
+ * bz << 2, indices into fine[n_fine][5][8][8][8]; parent_of[q] into coarse[n_coarse][5][8][8][8].
+ * n_parent entries; FP64 device arrays; entries with indices out of range are skipped. */
+int srhd_restrict(int64_t n_parent, const int32_t *parent_of, const int32_t *child,
+                  int64_t n_fine, const double *fine, int64_t n_coarse, double *coarse,
+                  void *stream);
+
+/* acc[i] = beta * acc[i] + weight * flux[i] for i < n (device FP64): time-integrates the
+ * boundary fluxes a step writes to flux_out (beta = 0 starts a sum). */
+int srhd_flux_accumulate(int64_t n, double *acc, const double *flux, double beta, double weight,
+                         void *stream);
+
+/* Coarse-fine flux correction (Sec. 3.4 item 4).  faces[n_face][6] (device int32): coarse patch,
+ * side s = 2 d + u of that patch, and the four fine patches across the face, fine[t] holding the
+ * coarse face cells (a, b) with t = (a >= 4) + 2 (b >= 4).  coarse_flux [Pc][6][5][64] holds
+ * dt_c F_c, fine_flux [Pf][6][5][64] the sum over the fine sub-steps of dt_f F_f (both from
+ * flux_out through srhd_flux_accumulate).  Each coarse cell at such a face gets
+ * dU = (u ? -1 : +1) (<fine> - coarse) / dh_c, <fine> the mean of the four fine face cells
+ * covering it; a cell whose corrected state fails Eq. 30 keeps its state (counted in *skipped,
+ * device uint64, may be NULL).  coarse: [Pc][5][8][8][8] FP64, updated in place.  The records are
+ * applied side by side (s = 0 .. 5), so a cell touching faces on several sides gets each
+ * correction in that order; at most one record per (coarse patch, side).  Records whose indices
+ * fall outside [0, n_coarse) / [0, n_fine) are skipped. */
+int srhd_flux_correct(int64_t n_face, const int32_t *faces, int64_t n_coarse, double *coarse,
+                      const double *coarse_flux, int64_t n_fine, const double *fine_flux,
+                      double dh_c, uint64_t *skipped, void *stream);
+
 int srhd_abi_version(void);
 
 #ifdef __cplusplus

@@ -27,6 +27,13 @@ int hip_status(hipError_t e, const char *what)
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
+// [a, a + an) and [b, b + bn) share no byte
+bool disjoint(const void *a, size_t an, const void *b, size_t bn)
+{
+  const char *x = (const char *)a, *y = (const char *)b;
+  return !(x < y + bn && y < x + an);
+}
+
 size_t dsize(int dtype) { return dtype == SRHD_F64 ? 8 : 4; }
 
 bool valid_dtype(int dtype) { return dtype == SRHD_F64 || dtype == SRHD_F32; }
@@ -170,6 +177,89 @@ int srhd_fill_ghosts(int dtype, int64_t n_patch, int ghost, int64_t n_src, const
                     "srhd_fill_ghosts");
 }
 
+// ---------------------------------------------------------------- AMR neighbour operations
+int srhd_fill_ghosts_coarse(int64_t n_fine, int ghost, const int32_t *neighbor,
+                            const int32_t *parent, const int8_t *octant, int64_t n_coarse,
+                            int ghost_c, const double *coarse_old, const double *coarse_new,
+                            double alpha, double theta, double *fine_padded, uint64_t *counts,
+                            void *stream)
+{
+  const char *who = "srhd_fill_ghosts_coarse";
+  if (n_fine < 0 || n_coarse < 0) return fail(SRHD_EINVAL, "%s: negative count", who);
+  if (ghost < 1 || ghost > 8) return fail(SRHD_EINVAL, "%s: ghost %d not in [1, 8]", who, ghost);
+  if (ghost_c < ghost / 2 + 2 || ghost_c > 8)
+    return fail(SRHD_EINVAL, "%s: ghost_c %d not in [%d, 8]", who, ghost_c, ghost / 2 + 2);
+  if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(SRHD_EINVAL, "%s: alpha %g not in [0, 1]", who, alpha);
+  if (!(theta >= 0.0 && theta <= 2.0)) return fail(SRHD_EINVAL, "%s: theta %g not in [0, 2]", who, theta);
+  if (n_fine == 0) return SRHD_OK;
+  if (!neighbor || !parent || !octant || !coarse_old || !fine_padded)
+    return fail(SRHD_EINVAL, "%s: NULL array", who);
+  if (!aligned(neighbor, 4) || !aligned(parent, 4) || !aligned(coarse_old, 8) ||
+      !aligned(fine_padded, 8) || (coarse_new && !aligned(coarse_new, 8)) || (counts && !aligned(counts, 8)))
+    return fail(SRHD_EINVAL, "%s: misaligned array", who);
+  const int N = 8 + 2 * ghost, Nc = 8 + 2 * ghost_c;
+  const size_t fb = (size_t)n_fine * 5 * N * N * N * 8, cb = (size_t)n_coarse * 5 * Nc * Nc * Nc * 8;
+  if (!disjoint(fine_padded, fb, coarse_old, cb) || (coarse_new && !disjoint(fine_padded, fb, coarse_new, cb)))
+    return fail(SRHD_EINVAL, "%s: fine_padded overlaps a coarse array", who);
+  return hip_status(srhd::launch_fill_ghosts_coarse(n_fine, ghost, neighbor, parent, octant, n_coarse,
+                                                    ghost_c, coarse_old, coarse_new, alpha, theta,
+                                                    fine_padded, (unsigned long long *)counts,
+                                                    (hipStream_t)stream),
+                    who);
+}
+
+int srhd_restrict(int64_t n_parent, const int32_t *parent_of, const int32_t *child,
+                  int64_t n_fine, const double *fine, int64_t n_coarse, double *coarse,
+                  void *stream)
+{
+  const char *who = "srhd_restrict";
+  if (n_parent < 0 || n_fine < 0 || n_coarse < 0) return fail(SRHD_EINVAL, "%s: negative count", who);
+  if (n_parent > 0x7fffffffLL) return fail(SRHD_EINVAL, "%s: too many parents", who);
+  if (n_parent == 0) return SRHD_OK;
+  if (!parent_of || !child || !fine || !coarse) return fail(SRHD_EINVAL, "%s: NULL array", who);
+  if (!aligned(parent_of, 4) || !aligned(child, 4) || !aligned(fine, 8) || !aligned(coarse, 8))
+    return fail(SRHD_EINVAL, "%s: misaligned array", who);
+  if (!disjoint(fine, (size_t)n_fine * 5 * 512 * 8, coarse, (size_t)n_coarse * 5 * 512 * 8))
+    return fail(SRHD_EINVAL, "%s: fine and coarse overlap", who);
+  return hip_status(srhd::launch_restrict(n_parent, parent_of, child, n_fine, fine, n_coarse, coarse,
+                                          (hipStream_t)stream),
+                    who);
+}
+
+int srhd_flux_accumulate(int64_t n, double *acc, const double *flux, double beta, double weight,
+                         void *stream)
+{
+  const char *who = "srhd_flux_accumulate";
+  if (n < 0) return fail(SRHD_EINVAL, "%s: n < 0", who);
+  if (n == 0) return SRHD_OK;
+  if (!acc || !flux) return fail(SRHD_EINVAL, "%s: NULL array", who);
+  if (!aligned(acc, 8) || !aligned(flux, 8)) return fail(SRHD_EINVAL, "%s: misaligned array", who);
+  if (!disjoint(acc, (size_t)n * 8, flux, (size_t)n * 8)) return fail(SRHD_EINVAL, "%s: acc overlaps flux", who);
+  return hip_status(srhd::launch_flux_accumulate(n, acc, flux, beta, weight, (hipStream_t)stream), who);
+}
+
+int srhd_flux_correct(int64_t n_face, const int32_t *faces, int64_t n_coarse, double *coarse,
+                      const double *coarse_flux, int64_t n_fine, const double *fine_flux,
+                      double dh_c, uint64_t *skipped, void *stream)
+{
+  const char *who = "srhd_flux_correct";
+  if (n_face < 0 || n_coarse < 0 || n_fine < 0) return fail(SRHD_EINVAL, "%s: negative count", who);
+  if (!(dh_c > 0.0)) return fail(SRHD_EINVAL, "%s: dh_c must be positive", who);
+  if (n_face == 0) return SRHD_OK;
+  if (!faces || !coarse || !coarse_flux || !fine_flux) return fail(SRHD_EINVAL, "%s: NULL array", who);
+  if (!aligned(faces, 4) || !aligned(coarse, 8) || !aligned(coarse_flux, 8) || !aligned(fine_flux, 8) ||
+      (skipped && !aligned(skipped, 8)))
+    return fail(SRHD_EINVAL, "%s: misaligned array", who);
+  const size_t cb = (size_t)n_coarse * 5 * 512 * 8;
+  if (!disjoint(coarse, cb, coarse_flux, (size_t)n_coarse * 6 * 5 * 64 * 8) ||
+      !disjoint(coarse, cb, fine_flux, (size_t)n_fine * 6 * 5 * 64 * 8))
+    return fail(SRHD_EINVAL, "%s: coarse overlaps a flux array", who);
+  return hip_status(srhd::launch_flux_correct(n_face, faces, n_coarse, coarse, coarse_flux, n_fine,
+                                              fine_flux, dh_c, (unsigned long long *)skipped,
+                                              (hipStream_t)stream),
+                    who);
+}
+
 size_t srhd_cfl_work_bytes(void) { return 256; }
 
 int srhd_cfl_dt(int dtype, int64_t n_patch, const void *interior, int n_level, const double *dh,
@@ -261,6 +351,13 @@ int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
   s.xcd_remap = 0;
   s.energy = prm->energy;
   s.integrator = prm->integrator;
+  s.flux_out = prm->flux_out;
+  if (s.flux_out) {
+    if (!aligned(s.flux_out, 8)) return fail(SRHD_EINVAL, "srhd_fluid_step: misaligned flux_out");
+    if (!disjoint(s.flux_out, (size_t)in->n_patch * 6 * 5 * 64 * 8, a, abytes) ||
+        !disjoint(s.flux_out, (size_t)in->n_patch * 6 * 5 * 64 * 8, b, bbytes))
+      return fail(SRHD_EINVAL, "srhd_fluid_step: flux_out overlaps the patches");
+  }
   rc = check_sched(prm->sched, prm->prec, g.kind, s, "srhd_fluid_step");
   if (rc) return rc;
   if (s.queue) {
@@ -547,6 +644,9 @@ int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_
   s.xcd_remap = 1;
   s.energy = SRHD_ENERGY_REDUCED;
   s.integrator = SRHD_MHM;
+  s.flux_out = nullptr;
+  if (prm->flux_out)
+    return fail(SRHD_EUNSUPPORTED, "srhd_fluid_step_grid: boundary fluxes are written by srhd_fluid_step only");
   rc = check_sched(prm->sched, prm->prec, g.kind, s, "srhd_fluid_step_grid");
   if (rc) return rc;
   return hip_status(srhd::launch_step_grid(prm->prec, s, (hipStream_t)stream),

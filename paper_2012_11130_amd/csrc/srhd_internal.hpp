@@ -65,7 +65,22 @@ struct StepArgs {
   int occ2;                             // the kernel variant that fits two workgroups per CU
   int energy;                           // srhd_energy: SRHD_ENERGY_TOTAL runs the original scheme
   int integrator;                       // srhd_integrator: SRHD_VL runs srhd_step_vl.hip's kernel
+  double *flux_out;                     // padded layout: [P][6][5][64] boundary fluxes, or NULL
 };
+
+// Fluxes of the interfaces on the two faces (lower, upper) of direction d from the step's
+// two-direction ring F[slot][5][NIF] (interface numbering of the step kernels: x fastest, the
+// coordinate along d in [0, 9)) to flux_out[p][2 d + u][5][b * 8 + a]; 128 threads.
+template <class T>
+__device__ __forceinline__ void write_boundary_fluxes(double *flux_out, int64_t p, int d,
+                                                      const T *ring, int nif, int t)
+{
+  const int u = t >> 6, a = t & 7, b = (t >> 3) & 7, c = u ? 8 : 0;
+  const int r = d == 0 ? (b * 8 + a) * 9 + c : (d == 1 ? (b * 9 + c) * 8 + a : (c * 8 + b) * 8 + a);
+  double *o = flux_out + ((p * 6 + 2 * d + u) * 5) * 64 + b * 8 + a;
+#pragma unroll
+  for (int f = 0; f < 5; ++f) o[f * 64] = (double)ring[f * nif + r];
+}
 
 hipError_t launch_step(int prec, const StepArgs &a, hipStream_t s);
 // the VL integrator (srhd_step_vl.hip): padded layout, analytic guess, reduced energy
@@ -96,5 +111,21 @@ hipError_t launch_mlp_adam(float *master, float *m1, float *m2, const float *gra
 hipError_t launch_step_grid(int prec, const StepArgs &a, hipStream_t s);
 hipError_t launch_grid_prims(int prec, int64_t n_patch, const double *cons, void *prims,
                              unsigned long long *smax_bits, const GuessArgs &g, hipStream_t s);
+
+// AMR neighbour operations (srhd_amr.hip)
+hipError_t launch_fill_ghosts_coarse(int64_t n_fine, int ghost, const int32_t *neighbor,
+                                     const int32_t *parent, const int8_t *octant, int64_t n_coarse,
+                                     int ghost_c, const double *coarse_old, const double *coarse_new,
+                                     double alpha, double theta, double *fine_padded,
+                                     unsigned long long *counts, hipStream_t s);
+hipError_t launch_restrict(int64_t n_parent, const int32_t *parent_of, const int32_t *child,
+                           int64_t n_fine, const double *fine, int64_t n_coarse, double *coarse,
+                           hipStream_t s);
+hipError_t launch_flux_accumulate(int64_t n, double *acc, const double *flux, double beta,
+                                  double weight, hipStream_t s);
+hipError_t launch_flux_correct(int64_t n_face, const int32_t *faces, int64_t n_coarse,
+                               double *coarse, const double *coarse_flux, int64_t n_fine,
+                               const double *fine_flux, double dh_c, unsigned long long *skipped,
+                               hipStream_t s);
 
 }  // namespace srhd

@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(kBlock) k_fill_ghosts(int64_t n_patch, int g, 
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       int o = ci[d] < 0 ? -1 : (ci[d] >= 8 ? 1 : 0);
-      if (o != 0 && np[13 + o * fstride[d]] < 0) ci[d] = o < 0 ? 0 : 7;
+      if (o != 0 && np[13 + o * fstride[d]] == -1) ci[d] = o < 0 ? 0 : 7;
     }
     int o0 = ci[0] < 0 ? -1 : (ci[0] >= 8 ? 1 : 0);
     int o1 = ci[1] < 0 ? -1 : (ci[1] >= 8 ? 1 : 0);
@@ -119,6 +119,7 @@ __global__ void __launch_bounds__(kBlock) k_fill_ghosts(int64_t n_patch, int g, 
     int slot = (o2 + 1) * 9 + (o1 + 1) * 3 + (o0 + 1);
     int64_t src = np[slot];
     T *dst = padded + p * 5 * N3 + c;
+    if (src == SRHD_NB_COARSE) continue;             // filled from the coarser level
     if (src < 0 || src >= n_src) {
 #pragma unroll
       for (int f = 0; f < 5; ++f) dst[(int64_t)f * N3] = T(__builtin_nan(""));

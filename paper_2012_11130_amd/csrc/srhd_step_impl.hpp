@@ -438,6 +438,9 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
         int up = d == 0 ? 1 : (d == 1 ? 8 : 64);
 #pragma unroll
         for (int f = 0; f < 5; ++f) dU[f] += s.F[slot][f][r + up] - s.F[slot][f][r];
+        if constexpr (!GATHER) {
+          if (a.flux_out && tid < 128) write_boundary_fluxes(a.flux_out, p, d, &s.F[slot][0][0], NIF, tid);
+        }
         __syncthreads();
       }
     }

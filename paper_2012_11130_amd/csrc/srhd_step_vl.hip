@@ -16,7 +16,7 @@
 // The face states of C are primitives (no inversion); the limiter keeps rho and p between
 // neighbouring values, so only an output cell can fail: then C-D are redone with
 // theta *= 0.75 (max_retry times) and theta = 0 (Sec. 3.4).  A predictor state that fails the
-// inversion cannot be cured by the limiter and ends the attempts, as an unphysical input does.
+// inversion (no limiter acts on it) is replaced by the cell's state at t^n.
 #include "srhd_step_impl.hpp"
 
 namespace srhd {
@@ -231,7 +231,7 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
   const double dt = a.dt_lev[lv];
 
   if (tid < 8) s.cnt[tid] = 0u;
-  unsigned int my_iters = 0, my_inv = 0, my_nc = 0, bad_in = 0;
+  unsigned int my_iters = 0, my_inv = 0, my_nc = 0, bad_in = 0, my_pfb = 0;
   __syncthreads();
 
   // ---------------------------------------------------------------- A: centre primitives
@@ -303,15 +303,22 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
         invert_with_L<I, GuessT<T, I>>((I)u[0], (I)u[1], (I)u[2], (I)u[3], (I)L, (I)-1.0, false,
                                        (I)StepTol<T, I>::v, 30, o);
       else set_unphysical(o);
-      bad_in += o.status == ST_UNPHYSICAL;
       my_iters += o.iters;
       my_inv += 1;
       my_nc += o.status == ST_NOCONV;
-      acc[h][0] = (T)o.rho;
-      acc[h][1] = (T)o.ux;
-      acc[h][2] = (T)o.uy;
-      acc[h][3] = (T)o.uz;
-      acc[h][4] = (T)o.p;
+      if (o.status == ST_UNPHYSICAL) {
+        // the half step is dropped for this cell: W* = W^n (still in the tile)
+        const int b = bidx(i, j, k);
+#pragma unroll
+        for (int f = 0; f < 5; ++f) acc[h][f] = s.W[f][b];
+        ++my_pfb;
+      } else {
+        acc[h][0] = (T)o.rho;
+        acc[h][1] = (T)o.ux;
+        acc[h][2] = (T)o.uy;
+        acc[h][3] = (T)o.uz;
+        acc[h][4] = (T)o.p;
+      }
     }
   }
   // every read of the centre primitives ended at the last barrier above: overwrite with W*
@@ -354,6 +361,7 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
         const int up = d == 0 ? 1 : (d == 1 ? 8 : 64);
 #pragma unroll
         for (int f = 0; f < 5; ++f) dU[f] += s.B[(slot * 5 + f) * NIF + r + up] - s.B[(slot * 5 + f) * NIF + r];
+        if (a.flux_out && tid < 128) write_boundary_fluxes(a.flux_out, p, d, &s.B[slot * 5 * NIF], NIF, tid);
         __syncthreads();
       }
     }
@@ -383,11 +391,13 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
     atomicAdd(&s.cnt[2], my_nc);
     atomicAdd(&s.cnt[3], my_iters);
     atomicAdd(&s.cnt[4], my_inv);
+    atomicAdd(&s.cnt[7], my_pfb);
     __syncthreads();
     if (tid == 0) {
       unsigned long long *st = (unsigned long long *)a.stats;
       if (s.cnt[0]) atomicAdd(&st[0], (unsigned long long)s.cnt[0]);
       if (s.cnt[2]) atomicAdd(&st[2], (unsigned long long)s.cnt[2]);
+      if (s.cnt[7]) atomicAdd(&st[7], (unsigned long long)s.cnt[7]);
       atomicAdd(&st[3], (unsigned long long)s.cnt[3]);
       atomicAdd(&st[4], (unsigned long long)s.cnt[4]);
       if (retries) atomicAdd(&st[5], (unsigned long long)retries);

@@ -60,7 +60,7 @@ class srhd_sched(ctypes.Structure):
 class srhd_step_params(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("riemann", _int), ("prec", _int),
                 ("max_retry", _int), ("guess", srhd_guess), ("sched", srhd_sched),
-                ("energy", _int), ("integrator", _int)]
+                ("energy", _int), ("integrator", _int), ("flux_out", _vp)]
 
 
 class srhd_tune_entry(ctypes.Structure):
@@ -74,11 +74,11 @@ class srhd_step_stats(ctypes.Structure):
     _fields_ = [("n_unphysical", ctypes.c_uint64), ("n_fallback", ctypes.c_uint64),
                 ("n_noconv", ctypes.c_uint64), ("newton_iters", ctypes.c_uint64),
                 ("n_inversions", ctypes.c_uint64), ("n_retry", ctypes.c_uint64),
-                ("n_mlp", ctypes.c_uint64), ("reserved", ctypes.c_uint64)]
+                ("n_mlp", ctypes.c_uint64), ("n_pred_fallback", ctypes.c_uint64)]
 
 
 STATS_FIELDS = ("n_unphysical", "n_fallback", "n_noconv", "newton_iters", "n_inversions",
-                "n_retry", "n_mlp")
+                "n_retry", "n_mlp", "n_pred_fallback")
 
 _sig = {
     "srhd_prim2cons": [_int, _i64, _vp, _vp, _vp],
@@ -100,6 +100,11 @@ _sig = {
     "srhd_autotune_step": [ctypes.POINTER(srhd_patches), _vp, _vp,
                            ctypes.POINTER(srhd_step_params), _int,
                            ctypes.POINTER(srhd_tune_entry), _int, ctypes.POINTER(_int), _vp],
+    "srhd_fill_ghosts_coarse": [_i64, _int, _vp, _vp, _vp, _i64, _int, _vp, _vp, ctypes.c_double,
+                                ctypes.c_double, _vp, _vp, _vp],
+    "srhd_restrict": [_i64, _vp, _vp, _i64, _vp, _i64, _vp, _vp],
+    "srhd_flux_accumulate": [_i64, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp],
+    "srhd_flux_correct": [_i64, _vp, _i64, _vp, _vp, _i64, _vp, ctypes.c_double, _vp, _vp],
     "srhd_autotune_step_grid": [ctypes.POINTER(srhd_grid), _vp, ctypes.c_double, _vp, _vp, _vp,
                                 _vp, ctypes.POINTER(srhd_step_params), _int,
                                 ctypes.POINTER(srhd_tune_entry), _int, ctypes.POINTER(_int), _vp],
@@ -272,7 +277,8 @@ def _patches(padded, dh, level, ghost):
     return d
 
 
-def _params(theta, riemann, prec, max_retry, guess, sched, energy=ENERGY_REDUCED, integrator=MHM):
+def _params(theta, riemann, prec, max_retry, guess, sched, energy=ENERGY_REDUCED, integrator=MHM,
+            flux_out=None):
     prm = srhd_step_params()
     prm.theta = float(theta)
     prm.riemann = int(riemann)
@@ -282,6 +288,7 @@ def _params(theta, riemann, prec, max_retry, guess, sched, energy=ENERGY_REDUCED
     prm.sched = sched.c() if sched is not None else srhd_sched(0, 1, 0, None)
     prm.energy = int(energy)
     prm.integrator = int(integrator)
+    prm.flux_out = None if flux_out is None else flux_out.data_ptr()
     return prm
 
 
@@ -357,10 +364,11 @@ def srhd_autotune_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, 
 
 def srhd_fluid_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann=HLLC,
                     prec=PREC_FP64, max_retry=4, stats=None, ghost=None, guess=None, sched=None,
-                    energy=ENERGY_REDUCED, integrator=MHM):
+                    energy=ENERGY_REDUCED, integrator=MHM, flux_out=None):
     """One MUSCL-Hancock (or, integrator=VL, VL) step: padded cons [P][5][N][N][N] -> interior
-    [P][5][8][8][8].  energy=ENERGY_TOTAL runs the original scheme on (D, M, E)."""
-    _need_cuda(padded, dt_lev, level, stats)
+    [P][5][8][8][8].  energy=ENERGY_TOTAL runs the original scheme on (D, M, E); flux_out
+    ([P][6][5][64] FP64) receives the fluxes through the patch faces."""
+    _need_cuda(padded, dt_lev, level, stats, flux_out)
     P = padded.shape[0]
     N = padded.shape[-1]
     g = (N - 8) // 2 if ghost is None else ghost
@@ -368,7 +376,7 @@ def srhd_fluid_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann
         out = torch.empty((P, 5, 8, 8, 8), dtype=torch.float64, device=padded.device)
     _need_cuda(out)
     d = _patches(padded, dh, level, g)
-    prm = _params(theta, riemann, prec, max_retry, guess, sched, energy, integrator)
+    prm = _params(theta, riemann, prec, max_retry, guess, sched, energy, integrator, flux_out)
     _check(_lib.srhd_fluid_step(ctypes.byref(d), _ptr(out), _ptr(dt_lev), ctypes.byref(prm),
                                 _ptr(stats), _stream()))
     return out
@@ -494,3 +502,47 @@ def srhd_mlp_adam(master, m1, m2, grad, step, lr, mlp):
 
 def abi_version():
     return _lib.srhd_abi_version()
+
+
+# ---------------------------------------------------------------- AMR neighbour operations
+NB_COARSE = -2
+
+
+def srhd_fill_ghosts_coarse(fine_padded, neighbor, parent, octant, coarse_old, coarse_new=None,
+                            alpha=0.0, theta=1.5, counts=None):
+    """Fills, in place, the ghost cells of fine_padded [Pf][5][N][N][N] whose neighbour slot is
+    NB_COARSE from the padded parents coarse_old (and coarse_new, time weight alpha).  counts: an
+    optional uint64 [2] device tensor accumulating (interpolated cells, primitive fallbacks)."""
+    _need_cuda(fine_padded, neighbor, parent, octant, coarse_old, coarse_new, counts)
+    g = (fine_padded.shape[-1] - 8) // 2
+    gc = (coarse_old.shape[-1] - 8) // 2
+    _check(_lib.srhd_fill_ghosts_coarse(fine_padded.shape[0], g, _ptr(neighbor), _ptr(parent),
+                                        _ptr(octant), coarse_old.shape[0], gc, _ptr(coarse_old),
+                                        _ptr(coarse_new), float(alpha), float(theta),
+                                        _ptr(fine_padded), _ptr(counts), _stream()))
+    return fine_padded
+
+
+def srhd_restrict(coarse, parent_of, child, fine):
+    """coarse[parent_of[q]] = average of the children child[q][0..7] of fine, in place."""
+    _need_cuda(coarse, parent_of, child, fine)
+    _check(_lib.srhd_restrict(parent_of.shape[0], _ptr(parent_of), _ptr(child), fine.shape[0],
+                              _ptr(fine), coarse.shape[0], _ptr(coarse), _stream()))
+    return coarse
+
+
+def srhd_flux_accumulate(acc, flux, beta, weight):
+    """acc = beta * acc + weight * flux (same shapes, FP64)."""
+    _need_cuda(acc, flux)
+    _check(_lib.srhd_flux_accumulate(acc.numel(), _ptr(acc), _ptr(flux), float(beta), float(weight),
+                                     _stream()))
+    return acc
+
+
+def srhd_flux_correct(coarse, faces, coarse_flux, fine_flux, dh_c, skipped=None):
+    """Coarse-fine flux correction of coarse [Pc][5][8][8][8] in place; faces int32 [n][6]."""
+    _need_cuda(coarse, faces, coarse_flux, fine_flux, skipped)
+    _check(_lib.srhd_flux_correct(faces.shape[0], _ptr(faces), coarse.shape[0], _ptr(coarse),
+                                  _ptr(coarse_flux), fine_flux.shape[0], _ptr(fine_flux),
+                                  float(dh_c), _ptr(skipped), _stream()))
+    return coarse
