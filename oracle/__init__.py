@@ -75,6 +75,10 @@ def lib():
     L.or_fill_ghosts_coarse.argtypes = [_i64, ctypes.c_int, _p, _p, _p, _i64, ctypes.c_int, _p, _p,
                                         _d, _d, _p, _p]
     L.or_fill_ghosts_coarse.restype = ctypes.c_int
+    L.or_set_eos.argtypes = [_d]
+    L.or_set_eos.restype = ctypes.c_int
+    L.or_get_eos.argtypes = []
+    L.or_get_eos.restype = _d
     L.or_restrict.argtypes = [_i64, _p, _p, _p, _p]
     L.or_restrict.restype = None
     L.or_flux_correct.argtypes = [_i64, _p, _p, _p, _p, _d]
@@ -350,3 +354,23 @@ def flux_correct(coarse, faces, coarse_flux, fine_flux, dh_c):
     faces = np.ascontiguousarray(faces, dtype=np.int32).reshape(-1, 6)
     return int(lib().or_flux_correct(faces.shape[0], _ptr(faces), _ptr(coarse),
                                      _ptr(_f64(coarse_flux)), _ptr(_f64(fine_flux)), float(dh_c)))
+
+
+
+# ---------------------------------------------------------------- equation of state
+class eos:
+    """Context manager selecting the oracle's EoS: eos(0) the TM EoS (the default), eos(Gamma)
+    the polytropic EoS h = 1 + Gamma Theta / (Gamma - 1), 1 < Gamma <= 2."""
+
+    def __init__(self, gamma):
+        self.gamma = float(gamma)
+
+    def __enter__(self):
+        self.prev = lib().or_get_eos()
+        if lib().or_set_eos(self.gamma) != 0:
+            raise ValueError("Gamma must lie in (1, 2]")
+        return self
+
+    def __exit__(self, *exc):
+        lib().or_set_eos(self.prev)
+        return False

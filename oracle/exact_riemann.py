@@ -18,6 +18,9 @@ arithmetic (mpmath), in four-velocity throughout:
 
 States are (rho, U, p) with U the x four-velocity.  The wave pattern is chosen by the sign of
 each side: p* < p_K gives a rarefaction on side K, p* >= p_K a shock.
+
+The same construction holds for the polytropic EoS of Sec. 2.2 (GammaLaw): only h(Theta), its
+inverse, the sound speed and the isentrope (Theta = K rho^(Gamma - 1)) change.
 """
 import mpmath as mp
 
@@ -54,26 +57,71 @@ def relative(U1, U2):
     return U1 * mp.sqrt(1 + U2 * U2) - U2 * mp.sqrt(1 + U1 * U1)
 
 
+class TaubMathews:
+    """The TM EoS (Eqs. 10, 14, 16) and its isentrope (Eq. C2b)."""
+    h_of = staticmethod(h_of)
+    theta_of_h = staticmethod(theta_of_h)
+    cs2_of = staticmethod(cs2_of)
+
+    @staticmethod
+    def isentrope_constant(rho, th, h):
+        return th * (h - th) / rho ** (_f(2) / 3)                        # Eq. C2b
+
+    @staticmethod
+    def theta_isentrope(K, rho):
+        C = K * rho ** (_f(2) / 3)
+        return C / mp.sqrt(1 + 3 * C)
+
+    def rho_isentrope(self, K, p, rho0, p0):
+        lr = mp.findroot(lambda lr: mp.exp(lr) * self.theta_isentrope(K, mp.exp(lr)) - p,
+                         mp.log(rho0 * (p / p0) ** (_f(3) / 5)))
+        return mp.exp(lr)
+
+
+class GammaLaw:
+    """The polytropic EoS h = 1 + Gamma Theta / (Gamma - 1) (Sec. 2.2): c_s^2 = Gamma Theta / h and
+    the isentrope p = K rho^Gamma."""
+
+    def __init__(self, gamma):
+        self.g = _f(gamma)
+
+    def h_of(self, th):
+        return 1 + self.g * th / (self.g - 1)
+
+    def theta_of_h(self, h):
+        return (h - 1) * (self.g - 1) / self.g
+
+    def cs2_of(self, th):
+        return self.g * th / self.h_of(th)
+
+    def isentrope_constant(self, rho, th, h):
+        return th / rho ** (self.g - 1)
+
+    def theta_isentrope(self, K, rho):
+        return K * rho ** (self.g - 1)
+
+    def rho_isentrope(self, K, p, rho0, p0):
+        return (p / K) ** (1 / self.g)
+
+
 class Side:
-    def __init__(self, rho, U, p):
+    def __init__(self, rho, U, p, eos=None):
+        self.eos = eos if eos is not None else TaubMathews()
         self.rho, self.U, self.p = _f(rho), _f(U), _f(p)
         self.th = self.p / self.rho
-        self.h = h_of(self.th)
-        self.K = self.th * (self.h - self.th) / self.rho ** (_f(2) / 3)   # Eq. C2b
+        self.h = self.eos.h_of(self.th)
+        self.K = self.eos.isentrope_constant(self.rho, self.th, self.h)
 
     def theta_isentrope(self, rho):
-        C = self.K * rho ** (_f(2) / 3)
-        return C / mp.sqrt(1 + 3 * C)
+        return self.eos.theta_isentrope(self.K, rho)
 
     def rho_isentrope(self, p):
         """Density on this state's isentrope at pressure p (p = rho Theta, Theta(rho) above)."""
-        lr = mp.findroot(lambda lr: mp.exp(lr) * self.theta_isentrope(mp.exp(lr)) - p,
-                         mp.log(self.rho * (p / self.p) ** (_f(3) / 5)))
-        return mp.exp(lr)
+        return self.eos.rho_isentrope(self.K, p, self.rho, self.p)
 
     def riemann_integral(self, rho):
         """int_{rho_K}^{rho} c_s / rho' drho' along the isentrope (Eq. C2a)."""
-        f = lambda lr: mp.sqrt(cs2_of(self.theta_isentrope(mp.exp(lr))))
+        f = lambda lr: mp.sqrt(self.eos.cs2_of(self.theta_isentrope(mp.exp(lr))))
         return mp.quad(f, [mp.log(self.rho), mp.log(rho)])
 
     def behind_rarefaction(self, p, sign):
@@ -87,14 +135,14 @@ class Side:
         hu, ru, pu = self.h, self.rho, self.p
 
         def taub(hd):
-            rd = p / theta_of_h(hd)
+            rd = p / self.eos.theta_of_h(hd)
             return hu * hu - hd * hd - (hd / rd + hu / ru) * (pu - p)
         # the downstream enthalpy lies above the upstream one for p > p_u; bracket it
         lo, hi = hu, hu * 2
         while taub(hi) > 0:
             hi *= 2
         hd = mp.findroot(taub, (lo, hi), solver="anderson")
-        rd = p / theta_of_h(hd)
+        rd = p / self.eos.theta_of_h(hd)
         J = mp.sqrt((p - pu) / (hu / ru - hd / rd))                        # Eq. C4
         a = J / ru
         Us = sign * a * mp.sqrt(1 + self.U ** 2) + self.U * mp.sqrt(1 + a * a)   # Eq. C5
@@ -113,10 +161,12 @@ class Side:
 
 
 class RiemannTM:
-    """Exact solution for left/right states (rho, U, p) with the discontinuity at x0."""
+    """Exact solution for left/right states (rho, U, p) with the discontinuity at x0; eos: the TM
+    EoS (default) or a GammaLaw."""
 
-    def __init__(self, left, right, x0=0.0):
-        self.L, self.R = Side(*left), Side(*right)
+    def __init__(self, left, right, x0=0.0, eos=None):
+        self.eos = eos if eos is not None else TaubMathews()
+        self.L, self.R = Side(*left, eos=self.eos), Side(*right, eos=self.eos)
         self.x0 = _f(x0)
         g = lambda lp: self.L.behind(mp.exp(lp), -1)[0] - self.R.behind(mp.exp(lp), +1)[0]
         lo = mp.log(min(self.L.p, self.R.p)) - 40
@@ -140,21 +190,21 @@ class RiemannTM:
         return U / mp.sqrt(1 + U * U)
 
     def _fan_left_edges(self):
-        csL = mp.sqrt(cs2_of(self.L.th))
+        csL = mp.sqrt(self.eos.cs2_of(self.L.th))
         vL = self._speed(self.L.U)
         head = (vL - csL) / (1 - vL * csL)
         ths = self.p_star / self.rho_L_star
-        css = mp.sqrt(cs2_of(ths))
+        css = mp.sqrt(self.eos.cs2_of(ths))
         vs = self._speed(self.U_star)
         tail = (vs - css) / (1 - vs * css)
         return head, tail
 
     def _fan_right_edges(self):
-        csR = mp.sqrt(cs2_of(self.R.th))
+        csR = mp.sqrt(self.eos.cs2_of(self.R.th))
         vR = self._speed(self.R.U)
         head = (vR + csR) / (1 + vR * csR)
         ths = self.p_star / self.rho_R_star
-        css = mp.sqrt(cs2_of(ths))
+        css = mp.sqrt(self.eos.cs2_of(ths))
         vs = self._speed(self.U_star_R)
         tail = (vs + css) / (1 + vs * css)
         return head, tail
@@ -164,14 +214,14 @@ class RiemannTM:
         and rapidity(U) = rapidity(U_K) + sign int c_s drho/rho."""
         def g(lr):
             rho = mp.exp(lr)
-            cs = mp.sqrt(cs2_of(side.theta_isentrope(rho)))
+            cs = mp.sqrt(self.eos.cs2_of(side.theta_isentrope(rho)))
             return (rapidity(side.U) + sign * side.riemann_integral(rho)) - (mp.atanh(xi) - sign * mp.atanh(cs))
         lo = mp.log(min(side.rho, self.rho_L_star if sign < 0 else self.rho_R_star))
         hi = mp.log(side.rho)
         lr = mp.findroot(g, (lo, hi), solver="anderson")
         rho = mp.exp(lr)
         th = side.theta_isentrope(rho)
-        cs = mp.sqrt(cs2_of(th))
+        cs = mp.sqrt(self.eos.cs2_of(th))
         U = mp.sinh(mp.atanh(xi) - sign * mp.atanh(cs))
         return rho, U, rho * th
 

@@ -14,7 +14,9 @@
  *
  * Functions and the passage each follows:
  *   EoS                      Sec. 2.2, Eq. 10 (h), Eq. 22 (ht of Theta), Eq. 16 (Theta of ht),
- *                            Eq. 14 (sound speed), Eq. A2 (dTheta/dht)
+ *                            Eq. 14 (sound speed), Eq. A2 (dTheta/dht); or the polytropic EoS
+ *                            of Sec. 2.2 (or_set_eos), the same functions for h = 1 +
+ *                            Gamma Theta / (Gamma - 1)
  *   inversion equation       Sec. 2.3, Eq. 15 (f), Eq. A1 (df/dht)
  *   initial guesses          App. A, Eqs. A3-A7 (A4 read as the positive root of A3)
  *   prim -> cons             Eqs. 8, 5a, 5b, 22, 15, 23
@@ -55,12 +57,31 @@
 /* EoS (Sec. 2.2)                                                                        */
 /* ===================================================================================== */
 
-/* Eq. 10: TM specific enthalpy h(Theta). */
-double or_h_of_theta(double th) { return 2.5 * th + sqrt(2.25 * th * th + 1.0); }
+/* The equation of state of every function below: 0 selects TM (Eq. 10); Gamma in (1, 2]
+ * selects the polytropic EoS h = 1 + Gamma Theta / (Gamma - 1) of Sec. 2.2.  Set before a call,
+ * not while one runs. */
+static double or_gamma = 0.0;
+
+int or_set_eos(double gamma)
+{
+  if (gamma != 0.0 && !(gamma > 1.0 && gamma <= 2.0)) return -1;
+  or_gamma = gamma;
+  return 0;
+}
+
+double or_get_eos(void) { return or_gamma; }
+
+/* Eq. 10: TM specific enthalpy h(Theta); polytropic: 1 + Gamma Theta / (Gamma - 1). */
+double or_h_of_theta(double th)
+{
+  if (or_gamma != 0.0) return 1.0 + or_gamma * th / (or_gamma - 1.0);
+  return 2.5 * th + sqrt(2.25 * th * th + 1.0);
+}
 
 /* Eq. 22: reduced enthalpy ht = h - 1 written without a subtraction. */
 double or_htilde_of_theta(double th)
 {
+  if (or_gamma != 0.0) return or_gamma * th / (or_gamma - 1.0);
   double a = 2.25 * th * th;
   return 2.5 * th + a / (1.0 + sqrt(a + 1.0));
 }
@@ -68,6 +89,7 @@ double or_htilde_of_theta(double th)
 /* Eq. 16: Theta from the reduced enthalpy (inverse of Eq. 10). */
 double or_theta_of_htilde(double ht)
 {
+  if (or_gamma != 0.0) return (or_gamma - 1.0) * ht / or_gamma;
   double num = 2.0 * ht * ht + 4.0 * ht;
   double den = 5.0 * ht + 5.0 + sqrt(9.0 * ht * ht + 18.0 * ht + 25.0);
   return num / den;
@@ -76,14 +98,16 @@ double or_theta_of_htilde(double ht)
 /* Eq. A2: dTheta/dht. */
 double or_dtheta_dhtilde(double ht)
 {
+  if (or_gamma != 0.0) return (or_gamma - 1.0) / or_gamma;
   double s = sqrt(9.0 * ht * ht + 18.0 * ht + 25.0);
   double den = 5.0 * ht + 5.0 + s;
   return (4.0 * ht + 4.0) / den - (2.0 * ht * ht + 4.0 * ht) * ((9.0 * ht + 9.0) / s + 5.0) / (den * den);
 }
 
-/* Eq. 14: squared sound speed of the TM EoS. */
+/* Eq. 14: squared sound speed of the TM EoS; polytropic: Gamma Theta / h. */
 double or_cs2(double th)
 {
+  if (or_gamma != 0.0) return or_gamma * th / or_h_of_theta(th);
   double h = or_h_of_theta(th);
   return th / (3.0 * h) * (5.0 * h - 8.0 * th) / (h - th);
 }

@@ -44,6 +44,9 @@ int or_fluid_step(int64_t n_patch, int ghost, const double *padded, const int8_t
                   const double *dh_lev, const double *dt_lev, double theta, int riemann,
                   int max_retry, int scheme, int integrator, double *out, int64_t *counts,
                   double *bflux);
+/* EoS selection: 0 = TM, Gamma in (1, 2] = polytropic.  Returns -1 for another value. */
+int or_set_eos(double gamma);
+double or_get_eos(void);
 /* AMR neighbour operations (refinement ratio 2). */
 #define OR_NB_COARSE (-2)   /* neighbour slot covered by the next coarser level */
 int or_fill_ghosts_coarse(int64_t n_fine, int ghost, const int32_t *neighbor, const int32_t *parent,
