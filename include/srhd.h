@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define SRHD_ABI_VERSION 4
+#define SRHD_ABI_VERSION 5
 
 typedef enum { SRHD_F64 = 0, SRHD_F32 = 1 } srhd_dtype;
 
@@ -104,22 +104,38 @@ typedef struct {
   int max_iter;            /* Newton iterations per guess; <= 0 selects 30 */
 } srhd_guess;
 
+/* Equation of state (Sec. 2.2).  SRHD_EOS_TM: the Taub-Mathews EoS of Eq. 10, the default
+ * wherever an srhd_eos pointer is NULL or zero-initialised.  SRHD_EOS_POLYTROPIC: the polytropic
+ * EoS h = 1 + Gamma Theta / (Gamma - 1) with 1 < gamma <= 2, whose sound speed is
+ * c_s^2 = Gamma Theta / h; its inversion starts Newton from ht = L / ((1 - k)(2 + sqrt(L))),
+ * k = (Gamma - 1) / Gamma (App. A's guess belongs to TM).  The polytropic EoS runs in the
+ * conversions, the CFL time step and srhd_fluid_step with MUSCL-Hancock and the reduced energy
+ * (every precision mode, analytic guess); elsewhere SRHD_EUNSUPPORTED. */
+typedef enum { SRHD_EOS_TM = 0, SRHD_EOS_POLYTROPIC = 1 } srhd_eos_kind;
+typedef struct {
+  int kind;                /* srhd_eos_kind */
+  double gamma;            /* ratio of specific heats (SRHD_EOS_POLYTROPIC only) */
+} srhd_eos;
+
 /* ---------------------------------------------------------------------------------------- */
 /* Conversions (Sec. 2.3)                                                                   */
 /* ---------------------------------------------------------------------------------------- */
 
 /* prim[5][n] -> cons[5][n] by Eqs. 8, 5a, 22, 5b, 15 and 23 (no root finding).  dtype selects
- * FP64 or FP32 storage and arithmetic.  prim and cons must not overlap. */
-int srhd_prim2cons(int dtype, int64_t n, const void *prim, void *cons, void *stream);
+ * FP64 or FP32 storage and arithmetic.  prim and cons must not overlap.  eos (host, may be
+ * NULL: TM). */
+int srhd_prim2cons(int dtype, int64_t n, const void *prim, void *cons, const srhd_eos *eos,
+                   void *stream);
 
 /* cons[5][n] -> prim[5][n]: L = x^2 + 2x - m^2 (x = Et/D, m = |M|/D) from error-free products
  * and a compensated sum, the physical check L > eps (Eq. 30), the root ht of f(ht) = L
  * (Eq. 15) by Newton's method (Eqs. A1-A2) from the guess selected by `guess` (NULL: the
  * analytic guess of App. A, Eqs. A3-A7), then Eqs. 17, 8, 5a, 16 and 18.
  * status[n] (int8, SRHD_ST_*) and iters[n] (uint8, Newton iterations) may be NULL.
- * FP32: L, Newton and recovery in FP32.  FP64: all in FP64. */
+ * FP32: L, Newton and recovery in FP32.  FP64: all in FP64.  eos (host, may be NULL: TM); the
+ * learned guess is for TM only. */
 int srhd_cons2prim(int dtype, int64_t n, const void *cons, void *prim, int8_t *status,
-                   uint8_t *iters, const srhd_guess *guess, void *stream);
+                   uint8_t *iters, const srhd_guess *guess, const srhd_eos *eos, void *stream);
 
 /* ---------------------------------------------------------------------------------------- */
 /* Patches (Sec. 3.1: 8^3-cell patches with ghost zones)                                    */
@@ -161,7 +177,7 @@ int srhd_fill_ghosts(int dtype, int64_t n_patch, int ghost, int64_t n_src, const
 size_t srhd_cfl_work_bytes(void);
 int srhd_cfl_dt(int dtype, int64_t n_patch, const void *interior, int n_level,
                 const double *dh /* host [n_level] */, double c_cfl, double *dt_lev,
-                void *work, void *stream);
+                void *work, const srhd_eos *eos /* host, may be NULL: TM */, void *stream);
 
 /* How the patches of a step are spread over the GPU (a launch choice, not part of the method;
  * results are identical for every schedule).  groups == 0: one workgroup per patch, each XCD
@@ -191,6 +207,7 @@ typedef struct {
   srhd_sched sched;        /* launch schedule; all-zero = one workgroup per patch */
   int energy;              /* srhd_energy (0: this paper's reduced energy) */
   int integrator;          /* srhd_integrator (0: MUSCL-Hancock) */
+  srhd_eos eos;            /* equation of state (zero: TM) */
   double *flux_out;        /* device [n_patch][6][5][64] or NULL: the Riemann fluxes of the final
                               attempt through the six faces of each patch, face s = 2 d + u (axis
                               d; u = 1 the upper face), face cell b * 8 + a with (a, b) the two

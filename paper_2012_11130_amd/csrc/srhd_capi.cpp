@@ -64,6 +64,19 @@ int check_guess(const srhd_guess *g, srhd::GuessArgs &out)
   return fail(SRHD_EINVAL, "unknown guess kind %d", g->kind);
 }
 
+// Equation of state (include/srhd.h, srhd_eos): k = (Gamma - 1) / Gamma of the polytropic EoS,
+// 0 for TM (NULL or kind SRHD_EOS_TM).
+int check_eos(const srhd_eos *eos, double &k, const char *who)
+{
+  k = 0.0;
+  if (!eos || eos->kind == SRHD_EOS_TM) return SRHD_OK;
+  if (eos->kind != SRHD_EOS_POLYTROPIC) return fail(SRHD_EINVAL, "%s: unknown EoS kind %d", who, eos->kind);
+  if (!(eos->gamma > 1.0 && eos->gamma <= 2.0))
+    return fail(SRHD_EINVAL, "%s: polytropic gamma %g not in (1, 2]", who, eos->gamma);
+  k = (eos->gamma - 1.0) / eos->gamma;
+  return SRHD_OK;
+}
+
 // Energy variable and integrator of a step (include/srhd.h, srhd_energy, srhd_integrator): the
 // original scheme has kernels for the padded layout with equal bulk and inversion types and the
 // analytic guess; the VL integrator for the padded layout, the analytic guess and the reduced
@@ -88,6 +101,19 @@ int check_variant(int energy, int integrator, int prec, int guess_kind, int gath
     return fail(SRHD_EUNSUPPORTED, "%s: the total-energy scheme runs in FP64 or FP32 only", who);
   if (guess_kind != SRHD_GUESS_ANALYTIC)
     return fail(SRHD_EUNSUPPORTED, "%s: the total-energy scheme takes the analytic guess only", who);
+  return SRHD_OK;
+}
+
+// The EoS of a step: the polytropic EoS runs in the padded MUSCL-Hancock kernels with the
+// reduced energy and the analytic guess.
+int check_eos_step(const srhd_step_params *prm, int gather, double &k, const char *who)
+{
+  int rc = check_eos(&prm->eos, k, who);
+  if (rc || k == 0.0) return rc;
+  if (gather) return fail(SRHD_EUNSUPPORTED, "%s: the polytropic EoS runs on padded patches only", who);
+  if (prm->integrator != SRHD_MHM || prm->energy != SRHD_ENERGY_REDUCED || prm->guess.kind != SRHD_GUESS_ANALYTIC)
+    return fail(SRHD_EUNSUPPORTED, "%s: the polytropic EoS runs with MUSCL-Hancock, the reduced energy "
+                "and the analytic guess only", who);
   return SRHD_OK;
 }
 
@@ -126,9 +152,13 @@ const char *srhd_last_error(void) { return g_err; }
 
 int srhd_abi_version(void) { return SRHD_ABI_VERSION; }
 
-int srhd_prim2cons(int dtype, int64_t n, const void *prim, void *cons, void *stream)
+int srhd_prim2cons(int dtype, int64_t n, const void *prim, void *cons, const srhd_eos *eos,
+                   void *stream)
 {
   if (!valid_dtype(dtype)) return fail(SRHD_EINVAL, "srhd_prim2cons: bad dtype %d", dtype);
+  double k;
+  int rc = check_eos(eos, k, "srhd_prim2cons");
+  if (rc) return rc;
   if (n < 0) return fail(SRHD_EINVAL, "srhd_prim2cons: n = %lld < 0", (long long)n);
   if (n == 0) return SRHD_OK;
   if (!prim || !cons) return fail(SRHD_EINVAL, "srhd_prim2cons: NULL array");
@@ -137,18 +167,23 @@ int srhd_prim2cons(int dtype, int64_t n, const void *prim, void *cons, void *str
   const char *a = (const char *)prim, *b = (const char *)cons;
   size_t bytes = (size_t)n * 5 * dsize(dtype);
   if (a < b + bytes && b < a + bytes) return fail(SRHD_EINVAL, "srhd_prim2cons: prim and cons overlap");
-  return hip_status(srhd::launch_prim2cons(dtype, n, prim, cons, (hipStream_t)stream),
+  return hip_status(srhd::launch_prim2cons(dtype, n, prim, cons, k, (hipStream_t)stream),
                     "srhd_prim2cons");
 }
 
 int srhd_cons2prim(int dtype, int64_t n, const void *cons, void *prim, int8_t *status,
-                   uint8_t *iters, const srhd_guess *guess, void *stream)
+                   uint8_t *iters, const srhd_guess *guess, const srhd_eos *eos, void *stream)
 {
   if (!valid_dtype(dtype)) return fail(SRHD_EINVAL, "srhd_cons2prim: bad dtype %d", dtype);
   if (n < 0) return fail(SRHD_EINVAL, "srhd_cons2prim: n = %lld < 0", (long long)n);
   srhd::GuessArgs g;
   int rc = check_guess(guess, g);
   if (rc) return rc;
+  double k;
+  rc = check_eos(eos, k, "srhd_cons2prim");
+  if (rc) return rc;
+  if (k > 0.0 && g.kind == SRHD_GUESS_MLP)
+    return fail(SRHD_EUNSUPPORTED, "srhd_cons2prim: the learned guess is for the TM EoS only");
   if (n == 0) return SRHD_OK;
   if (!prim || !cons) return fail(SRHD_EINVAL, "srhd_cons2prim: NULL array");
   if (!aligned(prim, dsize(dtype)) || !aligned(cons, dsize(dtype)))
@@ -156,7 +191,7 @@ int srhd_cons2prim(int dtype, int64_t n, const void *cons, void *prim, int8_t *s
   const char *a = (const char *)prim, *b = (const char *)cons;
   size_t bytes = (size_t)n * 5 * dsize(dtype);
   if (a < b + bytes && b < a + bytes) return fail(SRHD_EINVAL, "srhd_cons2prim: prim and cons overlap");
-  return hip_status(srhd::launch_cons2prim(dtype, n, cons, prim, status, iters, g,
+  return hip_status(srhd::launch_cons2prim(dtype, n, cons, prim, status, iters, g, k,
                                            (hipStream_t)stream),
                     "srhd_cons2prim");
 }
@@ -263,9 +298,12 @@ int srhd_flux_correct(int64_t n_face, const int32_t *faces, int64_t n_coarse, do
 size_t srhd_cfl_work_bytes(void) { return 256; }
 
 int srhd_cfl_dt(int dtype, int64_t n_patch, const void *interior, int n_level, const double *dh,
-                double c_cfl, double *dt_lev, void *work, void *stream)
+                double c_cfl, double *dt_lev, void *work, const srhd_eos *eos, void *stream)
 {
   if (!valid_dtype(dtype)) return fail(SRHD_EINVAL, "srhd_cfl_dt: bad dtype %d", dtype);
+  double k;
+  int rc = check_eos(eos, k, "srhd_cfl_dt");
+  if (rc) return rc;
   if (n_patch < 0) return fail(SRHD_EINVAL, "srhd_cfl_dt: n_patch < 0");
   if (n_level < 1 || n_level > SRHD_MAX_LEVEL)
     return fail(SRHD_EINVAL, "srhd_cfl_dt: n_level %d not in [1, %d]", n_level, SRHD_MAX_LEVEL);
@@ -278,7 +316,7 @@ int srhd_cfl_dt(int dtype, int64_t n_patch, const void *interior, int n_level, c
   for (int l = 0; l < SRHD_MAX_LEVEL; ++l) lv.dh[l] = l < n_level ? dh[l] : 0.0;
   for (int l = 0; l < n_level; ++l)
     if (!(dh[l] > 0.0)) return fail(SRHD_EINVAL, "srhd_cfl_dt: dh[%d] must be positive", l);
-  return hip_status(srhd::launch_cfl(dtype, n_patch, interior, lv, c_cfl, dt_lev, work,
+  return hip_status(srhd::launch_cfl(dtype, n_patch, interior, lv, c_cfl, dt_lev, work, k,
                                      (hipStream_t)stream),
                     "srhd_cfl_dt");
 }
@@ -313,6 +351,9 @@ int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
   int rc = check_guess(&prm->guess, g);
   if (rc) return rc;
   rc = check_variant(prm->energy, prm->integrator, prm->prec, g.kind, 0, "srhd_fluid_step");
+  if (rc) return rc;
+  double eos_k;
+  rc = check_eos_step(prm, 0, eos_k, "srhd_fluid_step");
   if (rc) return rc;
   if (prm->integrator == SRHD_VL && in->ghost < 3)
     return fail(SRHD_EINVAL, "srhd_fluid_step: the VL integrator needs ghost >= 3 (got %d)", in->ghost);
@@ -351,6 +392,7 @@ int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
   s.xcd_remap = 0;
   s.energy = prm->energy;
   s.integrator = prm->integrator;
+  s.eos_k = eos_k;
   s.flux_out = prm->flux_out;
   if (s.flux_out) {
     if (!aligned(s.flux_out, 8)) return fail(SRHD_EINVAL, "srhd_fluid_step: misaligned flux_out");
@@ -382,7 +424,11 @@ int srhd_step_occupancy(const srhd_step_params *prm, int gather)
     return fail(SRHD_EUNSUPPORTED, "srhd_step_occupancy: occupancy 2 needs an FP32 bulk");
   int rc = check_variant(prm->energy, prm->integrator, prec, guess_kind, gather, "srhd_step_occupancy");
   if (rc) return rc;
-  const int kind = prm->energy == SRHD_ENERGY_TOTAL ? 2 : (guess_kind == SRHD_GUESS_MLP ? 1 : 0);
+  double eos_k;
+  rc = check_eos_step(prm, gather, eos_k, "srhd_step_occupancy");
+  if (rc) return rc;
+  const int kind = prm->energy == SRHD_ENERGY_TOTAL ? 2
+                 : (eos_k > 0.0 ? 3 : (guess_kind == SRHD_GUESS_MLP ? 1 : 0));
   int n = prm->integrator == SRHD_VL ? srhd::step_occupancy_vl(prec, occupancy == 2)
                                      : srhd::step_occupancy(prec, gather != 0, kind, occupancy == 2);
   if (n <= 0) return fail(SRHD_EHIP, "srhd_step_occupancy: occupancy query failed");
@@ -597,6 +643,9 @@ int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_
   if (rc) return rc;
   rc = check_variant(prm->energy, prm->integrator, prm->prec, g.kind, 1, "srhd_fluid_step_grid");
   if (rc) return rc;
+  double eos_k;
+  rc = check_eos_step(prm, 1, eos_k, "srhd_fluid_step_grid");
+  if (rc) return rc;
   if (!smax_out) return fail(SRHD_EINVAL, "srhd_fluid_step_grid: NULL smax_out");
   if (!dt_lev && (!smax_in || !(c_cfl > 0.0)))
     return fail(SRHD_EINVAL, "srhd_fluid_step_grid: need dt_lev, or smax_in and c_cfl > 0");
@@ -644,6 +693,7 @@ int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_
   s.xcd_remap = 1;
   s.energy = SRHD_ENERGY_REDUCED;
   s.integrator = SRHD_MHM;
+  s.eos_k = 0.0;
   s.flux_out = nullptr;
   if (prm->flux_out)
     return fail(SRHD_EUNSUPPORTED, "srhd_fluid_step_grid: boundary fluxes are written by srhd_fluid_step only");

@@ -10,12 +10,15 @@
 //     5a, 16, 18);
 //   * fluxes (Eqs. 4a, 4b, 7), signal speeds and the HLLE / HLLC Riemann solvers adapted to
 //     the TM sound speed and to the reduced energy (Sec. 3.2);
-//   * the original scheme's total-energy variables, flux and naive L (Sec. 4, Eqs. 5c, 21).
+//   * the original scheme's total-energy variables, flux and naive L (Sec. 4, Eqs. 5c, 21);
+//   * the polytropic EoS of Sec. 2.2 as an alternative EoS type (EosPoly).
 // Templates take the bulk arithmetic type T (double or float) and the inversion type.
 #pragma once
 #include <float.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 namespace srhd {
 
@@ -125,6 +128,25 @@ __device__ __forceinline__ T sound_speed2(T th)
 {
   T h = T(2.5) * th + sq(T(2.25) * th * th + T(1));
   return dv(th * (T(5) * h - T(8) * th), T(3) * h * (h - th));
+}
+
+// The polytropic EoS of Sec. 2.2, h = 1 + Theta / k with k = (Gamma - 1) / Gamma, as an
+// alternative to the TM EoS above (EosTm, the default of every function taking an EoS).
+struct EosTm {};
+struct EosPoly {
+  double k;      // (Gamma - 1) / Gamma
+};
+
+template <class T> __device__ __forceinline__ T htilde_of_theta(T th, EosTm) { return htilde_of_theta(th); }
+template <class T> __device__ __forceinline__ T htilde_of_theta(T th, const EosPoly &e) { return dv(th, T(e.k)); }
+template <class T> __device__ __forceinline__ T theta_of_htilde(T ht, EosTm) { return theta_of_htilde(ht); }
+template <class T> __device__ __forceinline__ T theta_of_htilde(T ht, const EosPoly &e) { return T(e.k) * ht; }
+template <class T> __device__ __forceinline__ T sound_speed2(T th, EosTm) { return sound_speed2(th); }
+// c_s^2 = Gamma Theta / h = k Theta / ((1 - k)(k + Theta))
+template <class T> __device__ __forceinline__ T sound_speed2(T th, const EosPoly &e)
+{
+  const T k = T(e.k);
+  return dv(k * th, (T(1) - k) * (k + th));
 }
 
 // ------------------------------------------------------------------------------ inversion
@@ -255,37 +277,94 @@ __device__ __forceinline__ bool admissible(T D, T Mx, T My, T Mz, T Et, T eps, T
   return L > eps;
 }
 
+// The polytropic EoS: a starting point with the small-ht slope f ~ 2 (1 - k) ht and the
+// large-ht growth f ~ (1 - k)^2 ht^2 (App. A's guess belongs to the TM EoS), the Newton
+// iteration of Eqs. 15 and A1 with Theta = k ht and Theta' = k, and the recovery.
+template <class T>
+__device__ __forceinline__ T guess_poly(T L, T k)
+{
+  return dv(L, (T(1) - k) * (T(2) + sq(L)));
+}
+
+template <class T>
+__device__ __forceinline__ bool newton_htilde_poly(T L, T m2, T x, T k, T tol, int max_iter, T &ht,
+                                                   int &iters)
+{
+  for (int it = 1; it <= max_iter; ++it) {
+    T h = x + T(1);
+    T h2 = h * h;
+    T iq = dv(T(1), h2 + m2);
+    T th = k * x;
+    T r = h2 * iq;
+    T f = x * (x + T(2)) - T(2) * th * h + th * th * r;
+    T fp = T(2) * (h - th - h * k + th * k * r + dv(th * th * r * (m2 * iq), h));
+    T dx = dv(f - L, fp);
+    x -= dx;
+    if (!(x > T(0)) || !finiteT(x)) { iters = it; ht = x; return false; }
+    if (absT(dx) <= tol * x) { iters = it; ht = x; return true; }
+  }
+  iters = max_iter;
+  ht = x;
+  return false;
+}
+
+template <class T>
+__device__ __forceinline__ void recover_poly(T D, T Mx, T My, T Mz, T ht, T k, InvOut<T> &o)
+{
+  T iDh = dv(T(1), D * (T(1) + ht));
+  o.ux = Mx * iDh;
+  o.uy = My * iDh;
+  o.uz = Mz * iDh;
+  T gam = sq(T(1) + o.ux * o.ux + o.uy * o.uy + o.uz * o.uz);
+  o.rho = dv(D, gam);
+  o.p = o.rho * (k * ht);
+  o.ht = ht;
+}
+
+// The analytic starting point of the EoS (App. A for TM), formed in G.
+template <class T, class G, class E>
+__device__ __forceinline__ T start_guess(T L, T m2, T k)
+{
+  if constexpr (std::is_same<E, EosPoly>::value) return guess_poly(L, k);
+  else return T(guess_analytic<G>(G(L), G(m2)));
+}
+
 // Inversion from a known, admissible L.  With `have_guess` the supplied guess is tried first
 // and the analytic guess is the fallback (status FALLBACK when the supplied guess is not a
 // positive finite number or its Newton iteration fails and the analytic one converges);
 // otherwise the analytic guess is used directly.  The analytic guess is formed in G (a starting
 // point only: FP32 suffices where the result is consumed in FP32); one Newton loop serves both
 // starts.
-template <class T, class G = T>
+template <class T, class G = T, class E = EosTm>
 __device__ __forceinline__ void invert_with_L(T D, T Mx, T My, T Mz, T L, T guess, bool have_guess,
-                                              T tol, int max_iter, InvOut<T> &o)
+                                              T tol, int max_iter, InvOut<T> &o, const E &eos = E())
 {
+  constexpr bool poly = std::is_same<E, EosPoly>::value;
   T iD = dv(T(1), D);
   T mx = Mx * iD, my = My * iD, mz = Mz * iD;
   T m2 = mx * mx + my * my + mz * mz;
   T ht;
+  T k = T(0);
+  if constexpr (poly) k = T(eos.k);
   const bool supplied = have_guess && guess > T(0) && finiteT(guess);
   bool fell_back = have_guess && !supplied;
-  T x0 = supplied ? guess : T(guess_analytic<G>(G(L), G(m2)));
+  T x0 = supplied ? guess : start_guess<T, G, E>(L, m2, k);
   bool ok = false;
   int its = 0;
 #pragma unroll 1
   for (int a = 0; a < 2; ++a) {
     int it = 0;
-    ok = newton_htilde(L, m2, x0, tol, max_iter, ht, it);
+    if constexpr (poly) ok = newton_htilde_poly(L, m2, x0, k, tol, max_iter, ht, it);
+    else ok = newton_htilde(L, m2, x0, tol, max_iter, ht, it);
     its += it;
     if (ok || fell_back || !have_guess) break;
     fell_back = true;                       // the supplied guess failed: restart from App. A
-    x0 = T(guess_analytic<G>(G(L), G(m2)));
+    x0 = start_guess<T, G, E>(L, m2, k);
   }
   o.status = ok ? (fell_back ? ST_FALLBACK : ST_OK) : ST_NOCONV;
   o.iters = its;
-  recover(D, Mx, My, Mz, ht, o);
+  if constexpr (poly) recover_poly(D, Mx, My, Mz, ht, k, o);
+  else recover(D, Mx, My, Mz, ht, o);
 }
 
 // ------------------------------------------------------------------------------ prim -> cons
@@ -295,14 +374,14 @@ template <class T>
 struct Cons { T D, m[3], E; };   // E is the reduced energy Et
 
 // Eqs. 8, 5a, 22, 5b, 15 (with Theta = p / rho known), 23.
-template <class T>
-__device__ __forceinline__ Cons<T> prim2cons(const Prim<T> &w)
+template <class T, class E = EosTm>
+__device__ __forceinline__ Cons<T> prim2cons(const Prim<T> &w, const E &eos = E())
 {
   T U2 = w.u[0] * w.u[0] + w.u[1] * w.u[1] + w.u[2] * w.u[2];
   T gam = sq(T(1) + U2);
   T D = w.rho * gam;
   T th = dv(w.p, w.rho);
-  T ht = htilde_of_theta(th);
+  T ht = htilde_of_theta(th, eos);
   T h = T(1) + ht;
   T Dh = D * h;
   T h2 = h * h;
@@ -337,11 +416,11 @@ __device__ __forceinline__ Cons<T> prim2cons_total(const Prim<T> &w)
   return u;
 }
 
-template <bool TOT, class T>
-__device__ __forceinline__ Cons<T> prim2cons_s(const Prim<T> &w)
+template <bool TOT, class T, class E = EosTm>
+__device__ __forceinline__ Cons<T> prim2cons_s(const Prim<T> &w, const E &eos = E())
 {
   if constexpr (TOT) return prim2cons_total(w);
-  else return prim2cons(w);
+  else return prim2cons(w, eos);
 }
 
 // The original scheme's physical check and left-hand side of Eq. 15: L = (E/D)^2 - (|M|/D)^2 - 1
@@ -386,11 +465,11 @@ __device__ __forceinline__ Cons<T> phys_flux(const Prim<T> &w, const Cons<T> &u)
 
 // Signal speeds along d in four-velocity form:
 // lambda_pm = [gamma U_d (1 - cs^2) +- cs sqrt(1 + U_perp^2 (1 - cs^2))] / (1 + U^2 (1 - cs^2)).
-template <int d, class T>
-__device__ __forceinline__ void signal_speeds(const Prim<T> &w, T &lm, T &lp)
+template <int d, class T, class E = EosTm>
+__device__ __forceinline__ void signal_speeds(const Prim<T> &w, T &lm, T &lp, const E &eos = E())
 {
   constexpr int a1 = d == 0 ? 1 : 0, a2 = d == 2 ? 1 : 2;
-  T cs2 = sound_speed2(dv(w.p, w.rho));
+  T cs2 = sound_speed2(dv(w.p, w.rho), eos);
   T cs = sq(cs2);
   T Ud = w.u[d];
   T Up2 = w.u[a1] * w.u[a1] + w.u[a2] * w.u[a2];
@@ -407,14 +486,14 @@ __device__ __forceinline__ void signal_speeds(const Prim<T> &w, T &lm, T &lp)
 // HLLE: HLL flux with S_L^- = min(S_L, 0), S_R^+ = max(S_R, 0).  ul, ur are the conserved
 // variables of wl, wr (the states the primitives were inverted from, where the caller has them).
 // TOT: the original scheme's variables (total energy E).
-template <int d, bool TOT = false, class T>
+template <int d, bool TOT = false, class T, class E = EosTm>
 __device__ __forceinline__ Cons<T> hlle(const Prim<T> &wl, const Prim<T> &wr, const Cons<T> &ul,
-                                        const Cons<T> &ur)
+                                        const Cons<T> &ur, const E &eos = E())
 {
   Cons<T> fl = phys_flux<d, TOT>(wl, ul), fr = phys_flux<d, TOT>(wr, ur);
   T lmL, lpL, lmR, lpR;
-  signal_speeds<d>(wl, lmL, lpL);
-  signal_speeds<d>(wr, lmR, lpR);
+  signal_speeds<d>(wl, lmL, lpL, eos);
+  signal_speeds<d>(wr, lmR, lpR, eos);
   T sl = minT(minT(lmL, lmR), T(0));
   T sr = maxT(maxT(lpL, lpR), T(0));
   T inv = dv(T(1), sr - sl);
@@ -445,14 +524,14 @@ __device__ __forceinline__ Cons<T> sel(bool c, const Cons<T> &a, const Cons<T> &
 // Et* = [Et (S - v) + p* l* - p v] / (S - l*), which carries no rest-mass cancellation.
 // TOT: the original scheme, whose energy slot already holds E (and its flux M_d); its star state
 // E* takes the same form.
-template <int d, bool TOT = false, class T>
+template <int d, bool TOT = false, class T, class E = EosTm>
 __device__ __forceinline__ Cons<T> hllc(const Prim<T> &wl, const Prim<T> &wr, const Cons<T> &ul,
-                                        const Cons<T> &ur)
+                                        const Cons<T> &ur, const E &eos = E())
 {
   Cons<T> fl = phys_flux<d, TOT>(wl, ul), fr = phys_flux<d, TOT>(wr, ur);
   T lmL, lpL, lmR, lpR;
-  signal_speeds<d>(wl, lmL, lpL);
-  signal_speeds<d>(wr, lmR, lpR);
+  signal_speeds<d>(wl, lmL, lpL, eos);
+  signal_speeds<d>(wr, lmR, lpR, eos);
   T sl = minT(lmL, lmR);
   T sr = maxT(lpL, lpR);
   T inv = dv(T(1), sr - sl);
@@ -501,9 +580,11 @@ __device__ __forceinline__ Cons<T> hllc(const Prim<T> &wl, const Prim<T> &wr, co
 // ------------------------------------------------------------------------------ CFL
 // Eqs. 26-27 for one cell (the sum over |Ux| + |Uy| + |Uz|): U_max = gamma_s sum |U_i| +
 // 3 gamma U_s, S_max = U_max / sqrt(1 + U_max^2).  Always in double.
-__device__ __forceinline__ double signal_smax(double rho, double ux, double uy, double uz, double p)
+template <class E = EosTm>
+__device__ __forceinline__ double signal_smax(double rho, double ux, double uy, double uz, double p,
+                                              const E &eos = E())
 {
-  double cs2 = sound_speed2(p / rho);
+  double cs2 = sound_speed2(p / rho, eos);
   double gs = 1.0 / sqrt(1.0 - cs2);                  // gamma_s
   double Us = sqrt(cs2) * gs;                         // U_s = c_s / sqrt(1 - c_s^2)
   double gam = sqrt(1.0 + ux * ux + uy * uy + uz * uz);

@@ -24,13 +24,15 @@ struct LevelArgs {
   double dh[SRHD_MAX_LEVEL];
 };
 
-hipError_t launch_prim2cons(int dtype, int64_t n, const void *prim, void *cons, hipStream_t s);
+// eos_k: (Gamma - 1) / Gamma of the polytropic EoS, or 0 for TM
+hipError_t launch_prim2cons(int dtype, int64_t n, const void *prim, void *cons, double eos_k,
+                            hipStream_t s);
 hipError_t launch_cons2prim(int dtype, int64_t n, const void *cons, void *prim, int8_t *status,
-                            uint8_t *iters, const GuessArgs &g, hipStream_t s);
+                            uint8_t *iters, const GuessArgs &g, double eos_k, hipStream_t s);
 hipError_t launch_fill_ghosts(int dtype, int64_t n_patch, int ghost, int64_t n_src, const void *interior,
                               const int32_t *neighbor, void *padded, hipStream_t s);
 hipError_t launch_cfl(int dtype, int64_t n_patch, const void *interior, const LevelArgs &lv,
-                      double c_cfl, double *dt_lev, void *work, hipStream_t s);
+                      double c_cfl, double *dt_lev, void *work, double eos_k, hipStream_t s);
 hipError_t launch_stats_reset(srhd_step_stats *st, hipStream_t s);
 
 struct StepArgs {
@@ -66,6 +68,7 @@ struct StepArgs {
   int energy;                           // srhd_energy: SRHD_ENERGY_TOTAL runs the original scheme
   int integrator;                       // srhd_integrator: SRHD_VL runs srhd_step_vl.hip's kernel
   double *flux_out;                     // padded layout: [P][6][5][64] boundary fluxes, or NULL
+  double eos_k;                         // polytropic EoS: (Gamma - 1) / Gamma; 0 selects TM
 };
 
 // Fluxes of the interfaces on the two faces (lower, upper) of direction d from the step's
@@ -97,7 +100,8 @@ SRHD_STEP_MODE(fp64)
 SRHD_STEP_MODE(mixed)
 SRHD_STEP_MODE(fp32)
 #undef SRHD_STEP_MODE
-// workgroups per CU, 0 on error; kind: 0 analytic guess, 1 learned guess, 2 original scheme
+// workgroups per CU, 0 on error; kind: 0 analytic guess, 1 learned guess, 2 original scheme,
+// 3 polytropic EoS
 int step_occupancy(int prec, bool gather, int kind, bool occ2);
 
 size_t mlp_workspace_bytes(int64_t batch);

@@ -27,9 +27,9 @@ template <> struct Tol<double> { static constexpr double v = 0x1p-27; static con
 template <> struct Tol<float> { static constexpr float v = 0x1p-12f; static constexpr float eps = FLT_EPSILON; };
 
 // ------------------------------------------------------------------------------ conversions
-template <class T>
+template <class T, class E>
 __global__ void __launch_bounds__(kBlock) k_prim2cons(int64_t n, const T *__restrict__ prim,
-                                                      T *__restrict__ cons)
+                                                      T *__restrict__ cons, E eos)
 {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(kBlock) k_prim2cons(int64_t n, const T *__rest
     w.u[1] = prim[2 * n + i];
     w.u[2] = prim[3 * n + i];
     w.p = prim[4 * n + i];
-    Cons<T> u = prim2cons(w);
+    Cons<T> u = prim2cons(w, eos);
     cons[i] = u.D;
     cons[n + i] = u.m[0];
     cons[2 * n + i] = u.m[1];
@@ -51,12 +51,12 @@ __global__ void __launch_bounds__(kBlock) k_prim2cons(int64_t n, const T *__rest
 // With MLP, the learned guess is tried first and the analytic guess is the fallback.  The loop
 // runs the same number of times in every lane of a wavefront (the network's matrix instructions
 // need all lanes); lanes past the end work on a dummy state and store nothing.
-template <class T, bool MLP>
+template <class T, bool MLP, class E>
 __global__ void __launch_bounds__(kBlock) k_cons2prim(int64_t n, const T *__restrict__ cons,
                                                       T *__restrict__ prim,
                                                       int8_t *__restrict__ status,
                                                       uint8_t *__restrict__ iters, int max_iter,
-                                                      MlpDev mlp)
+                                                      MlpDev mlp, E eos)
 {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(kBlock) k_cons2prim(int64_t n, const T *__rest
     if (!in) continue;
     InvOut<T> o;
     if (adm)
-      invert_with_L(D, Mx, My, Mz, L, guess, consulted, T(Tol<T>::v), max_iter, o);
+      invert_with_L<T, T>(D, Mx, My, Mz, L, guess, consulted, T(Tol<T>::v), max_iter, o, eos);
     else
       set_unphysical(o);
     prim[i] = o.rho;
@@ -142,10 +142,11 @@ __device__ __forceinline__ double wave_max(double v)
 
 // Eqs. 26-27 per interior cell, maximum over the workgroup, then an integer atomic maximum on
 // the bit pattern (order preserving for non-negative doubles) -- exact and order independent.
-template <class T>
+template <class T, class E>
 __global__ void __launch_bounds__(kBlock) k_cfl_smax(int64_t n_patch,
                                                      const T *__restrict__ interior,
-                                                     unsigned long long *__restrict__ smax_bits)
+                                                     unsigned long long *__restrict__ smax_bits,
+                                                     E eos)
 {
   __shared__ double red[kBlock / 64];
   const int64_t total = n_patch * 512;
@@ -159,8 +160,8 @@ __global__ void __launch_bounds__(kBlock) k_cfl_smax(int64_t n_patch,
     T L;
     if (!admissible(D, Mx, My, Mz, Et, T(Tol<T>::eps), L)) continue;
     InvOut<T> o;
-    invert_with_L(D, Mx, My, Mz, L, T(-1), false, T(Tol<T>::v), 30, o);
-    double S = signal_smax(o.rho, o.ux, o.uy, o.uz, o.p);
+    invert_with_L<T, T>(D, Mx, My, Mz, L, T(-1), false, T(Tol<T>::v), 30, o, eos);
+    double S = signal_smax(o.rho, o.ux, o.uy, o.uz, o.p, eos);
     if (S > vmax) vmax = S;
   }
   vmax = wave_max(vmax);
@@ -192,39 +193,54 @@ __global__ void k_cfl_finish(const unsigned long long *__restrict__ smax_bits, L
 }  // namespace
 
 // ------------------------------------------------------------------------------ launchers
-hipError_t launch_prim2cons(int dtype, int64_t n, const void *prim, void *cons, hipStream_t s)
+template <class T, class E>
+void prim2cons_e(int64_t n, const void *prim, void *cons, E eos, hipStream_t s)
+{
+  hipLaunchKernelGGL((k_prim2cons<T, E>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, (const T *)prim,
+                     (T *)cons, eos);
+}
+
+hipError_t launch_prim2cons(int dtype, int64_t n, const void *prim, void *cons, double eos_k,
+                            hipStream_t s)
 {
   if (n == 0) return hipSuccess;
-  if (dtype == SRHD_F64)
-    hipLaunchKernelGGL(k_prim2cons<double>, dim3(grid_for(n)), dim3(kBlock), 0, s, n,
-                       (const double *)prim, (double *)cons);
-  else
-    hipLaunchKernelGGL(k_prim2cons<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, n,
-                       (const float *)prim, (float *)cons);
+  if (eos_k > 0.0) {
+    if (dtype == SRHD_F64) prim2cons_e<double>(n, prim, cons, EosPoly{eos_k}, s);
+    else prim2cons_e<float>(n, prim, cons, EosPoly{eos_k}, s);
+  } else {
+    if (dtype == SRHD_F64) prim2cons_e<double>(n, prim, cons, EosTm{}, s);
+    else prim2cons_e<float>(n, prim, cons, EosTm{}, s);
+  }
   return hipGetLastError();
 }
 
+template <class T, bool MLP, class E>
+void cons2prim_e(int64_t n, const void *cons, void *prim, int8_t *status, uint8_t *iters, int mi,
+                 const MlpDev &m, E eos, hipStream_t s)
+{
+  hipLaunchKernelGGL((k_cons2prim<T, MLP, E>), dim3(grid_for(n)), dim3(kBlock), 0, s, n,
+                     (const T *)cons, (T *)prim, status, iters, mi, m, eos);
+}
+
+// The learned guess exists for the TM EoS only (the caller rejects it with eos_k > 0).
 hipError_t launch_cons2prim(int dtype, int64_t n, const void *cons, void *prim, int8_t *status,
-                            uint8_t *iters, const GuessArgs &g, hipStream_t s)
+                            uint8_t *iters, const GuessArgs &g, double eos_k, hipStream_t s)
 {
   if (n == 0) return hipSuccess;
   int mi = g.max_iter > 0 ? g.max_iter : 30;
   MlpDev m = g.dev();
   const bool mlp = g.kind == SRHD_GUESS_MLP;
-  if (dtype == SRHD_F64) {
-    if (mlp)
-      hipLaunchKernelGGL((k_cons2prim<double, true>), dim3(grid_for(n)), dim3(kBlock), 0, s, n,
-                         (const double *)cons, (double *)prim, status, iters, mi, m);
-    else
-      hipLaunchKernelGGL((k_cons2prim<double, false>), dim3(grid_for(n)), dim3(kBlock), 0, s, n,
-                         (const double *)cons, (double *)prim, status, iters, mi, m);
+  const bool f64 = dtype == SRHD_F64;
+  if (eos_k > 0.0) {
+    if (mlp) return hipErrorInvalidValue;
+    if (f64) cons2prim_e<double, false>(n, cons, prim, status, iters, mi, m, EosPoly{eos_k}, s);
+    else cons2prim_e<float, false>(n, cons, prim, status, iters, mi, m, EosPoly{eos_k}, s);
+  } else if (mlp) {
+    if (f64) cons2prim_e<double, true>(n, cons, prim, status, iters, mi, m, EosTm{}, s);
+    else cons2prim_e<float, true>(n, cons, prim, status, iters, mi, m, EosTm{}, s);
   } else {
-    if (mlp)
-      hipLaunchKernelGGL((k_cons2prim<float, true>), dim3(grid_for(n)), dim3(kBlock), 0, s, n,
-                         (const float *)cons, (float *)prim, status, iters, mi, m);
-    else
-      hipLaunchKernelGGL((k_cons2prim<float, false>), dim3(grid_for(n)), dim3(kBlock), 0, s, n,
-                         (const float *)cons, (float *)prim, status, iters, mi, m);
+    if (f64) cons2prim_e<double, false>(n, cons, prim, status, iters, mi, m, EosTm{}, s);
+    else cons2prim_e<float, false>(n, cons, prim, status, iters, mi, m, EosTm{}, s);
   }
   return hipGetLastError();
 }
@@ -244,19 +260,28 @@ hipError_t launch_fill_ghosts(int dtype, int64_t n_patch, int ghost, int64_t n_s
   return hipGetLastError();
 }
 
+template <class T, class E>
+void cfl_e(int64_t n_patch, const void *interior, unsigned long long *bits, E eos, hipStream_t s)
+{
+  const int64_t total = n_patch * 512;
+  hipLaunchKernelGGL((k_cfl_smax<T, E>), dim3(grid_for(total, 2)), dim3(kBlock), 0, s, n_patch,
+                     (const T *)interior, bits, eos);
+}
+
 hipError_t launch_cfl(int dtype, int64_t n_patch, const void *interior, const LevelArgs &lv,
-                      double c_cfl, double *dt_lev, void *work, hipStream_t s)
+                      double c_cfl, double *dt_lev, void *work, double eos_k, hipStream_t s)
 {
   unsigned long long *bits = (unsigned long long *)work;
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, bits, 1);
   if (n_patch > 0) {
-    int64_t total = n_patch * 512;
-    if (dtype == SRHD_F64)
-      hipLaunchKernelGGL(k_cfl_smax<double>, dim3(grid_for(total, 2)), dim3(kBlock), 0, s,
-                         n_patch, (const double *)interior, bits);
-    else
-      hipLaunchKernelGGL(k_cfl_smax<float>, dim3(grid_for(total, 2)), dim3(kBlock), 0, s,
-                         n_patch, (const float *)interior, bits);
+    const bool f64 = dtype == SRHD_F64;
+    if (eos_k > 0.0) {
+      if (f64) cfl_e<double>(n_patch, interior, bits, EosPoly{eos_k}, s);
+      else cfl_e<float>(n_patch, interior, bits, EosPoly{eos_k}, s);
+    } else {
+      if (f64) cfl_e<double>(n_patch, interior, bits, EosTm{}, s);
+      else cfl_e<float>(n_patch, interior, bits, EosTm{}, s);
+    }
   }
   hipLaunchKernelGGL(k_cfl_finish, dim3(1), dim3(64), 0, s, (const unsigned long long *)bits,
                      lv, c_cfl, dt_lev);

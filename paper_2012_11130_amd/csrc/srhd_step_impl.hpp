@@ -18,10 +18,11 @@
 // If any half-step face state or output cell is unphysical, the whole patch repeats B-D with
 // theta *= 0.75 (max_retry times), then theta = 0 (Sec. 3.4); A is not repeated.
 //
-// Kernel variants K: the analytic guess of App. A, the learned guess, and the original scheme of
+// Kernel variants K: the analytic guess of App. A, the learned guess, the original scheme of
 // Sec. 4 (the total energy E of Eq. 5c in the energy slot, evolved with the flux M_d, and every
 // inversion from the naive L = (E/D)^2 - (|M|/D)^2 - 1 of Eq. 21 in the inversion type; analytic
-// guess, padded layout, equal bulk and inversion types only).
+// guess, padded layout, equal bulk and inversion types only), and the polytropic EoS of Sec. 2.2
+// (padded layout).
 #pragma once
 #include <float.h>
 #include <type_traits>
@@ -82,7 +83,18 @@ constexpr Tables kTabInit = make_tables();
 static_assert(kTabInit.pcell[NPC - 1] != 0 && kTabInit.hcell[NHC - 1] != 0, "cell tables");
 __constant__ Tables kTab = kTabInit;
 
-enum : int { KV_ANALYTIC = 0, KV_MLP = 1, KV_TOTAL = 2 };
+enum : int { KV_ANALYTIC = 0, KV_MLP = 1, KV_TOTAL = 2, KV_POLY = 3 };
+
+// The EoS of a variant: the polytropic EoS (Sec. 2.2) for KV_POLY (analytic-type guess, padded
+// layout), TM otherwise.
+template <int K> struct KEos { using type = EosTm; };
+template <> struct KEos<KV_POLY> { using type = EosPoly; };
+template <int K>
+__device__ __forceinline__ typename KEos<K>::type make_eos(const StepArgs &a)
+{
+  if constexpr (K == KV_POLY) return EosPoly{a.eos_k};
+  else return EosTm{};
+}
 
 // The analytic guess's type: FP32 whenever the bulk is FP32 (only a starting point), else I.
 template <class T, class I>
@@ -143,13 +155,14 @@ __device__ __forceinline__ bool face_L(const Cons<T> &u, double &L)
 }
 
 // Inversion of a face state in the inversion type I from its (exact, FP64) L.
-template <class I, class T>
+template <class I, class T, class E>
 __device__ __forceinline__ bool invert_face(const Cons<T> &u, bool ok, double L, Prim<T> &w,
-                                            int &iters, int &status, double guess, bool have_guess)
+                                            int &iters, int &status, double guess, bool have_guess,
+                                            const E &eos)
 {
   I D = u.D, Mx = u.m[0], My = u.m[1], Mz = u.m[2];
   InvOut<I> o;
-  if (ok) invert_with_L<I, GuessT<T, I>>(D, Mx, My, Mz, (I)L, (I)guess, have_guess, (I)StepTol<T, I>::v, 30, o);
+  if (ok) invert_with_L<I, GuessT<T, I>>(D, Mx, My, Mz, (I)L, (I)guess, have_guess, (I)StepTol<T, I>::v, 30, o, eos);
   else set_unphysical(o);
   w.rho = (T)o.rho;
   w.u[0] = (T)o.ux;
@@ -166,7 +179,8 @@ __device__ __forceinline__ bool invert_face(const Cons<T> &u, bool ok, double L,
 template <int d, int K, class I, class T>
 __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, int j, int k,
                                            T theta, const MlpDev &mlp, Prim<T> &w, Cons<T> &u,
-                                           int &iters, int &status, unsigned int &evals)
+                                           int &iters, int &status, unsigned int &evals,
+                                           const typename KEos<K>::type &eos)
 {
   constexpr int sd = d == 0 ? 1 : (d == 1 ? BX : BX * BX);
   int b = bidx(i, j, k);
@@ -185,7 +199,7 @@ __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, in
   wf.u[2] = v[3];
   wf.p = v[4];
   constexpr bool MLP = K == KV_MLP;
-  u = prim2cons_s<K == KV_TOTAL>(wf);
+  u = prim2cons_s<K == KV_TOTAL>(wf, eos);
   u.D += s.C[0][hb];
   u.m[0] += s.C[1][hb];
   u.m[1] += s.C[2][hb];
@@ -199,7 +213,7 @@ __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, in
   else ok = face_L(u, L);
   bool consulted = false;
   double guess = MLP ? mlp_guess(mlp, u.D, u.m[0], u.m[1], u.m[2], u.E, L, consulted, evals) : -1.0;
-  return invert_face<I>(u, ok, L, w, iters, status, guess, consulted);
+  return invert_face<I>(u, ok, L, w, iters, status, guess, consulted, eos);
 }
 
 struct IfaceCount {
@@ -210,7 +224,8 @@ struct IfaceCount {
 // with x fastest, then y, then z), written to the ring slot of d.
 template <int d, int K, class I, class T>
 __device__ __forceinline__ bool interface_flux(Tile<T> &s, int r, T theta, int solver,
-                                               const MlpDev &mlp, IfaceCount &cnt)
+                                               const MlpDev &mlp, IfaceCount &cnt,
+                                               const typename KEos<K>::type &eos)
 {
   // x is the fastest index in every direction, so the lanes of a wavefront read neighbouring
   // LDS words (a y- or z-fastest order would put them 12 or 144 words apart, on few banks)
@@ -223,8 +238,8 @@ __device__ __forceinline__ bool interface_flux(Tile<T> &s, int r, T theta, int s
   Prim<T> wl, wr;
   Cons<T> ul, ur;
   int itl, itr, stl, str;
-  bool okl = face_state<d, K, I>(s, 1, cl[0], cl[1], cl[2], theta, mlp, wl, ul, itl, stl, cnt.mlp);
-  bool okr = face_state<d, K, I>(s, 0, cr[0], cr[1], cr[2], theta, mlp, wr, ur, itr, str, cnt.mlp);
+  bool okl = face_state<d, K, I>(s, 1, cl[0], cl[1], cl[2], theta, mlp, wl, ul, itl, stl, cnt.mlp, eos);
+  bool okr = face_state<d, K, I>(s, 0, cr[0], cr[1], cr[2], theta, mlp, wr, ur, itr, str, cnt.mlp, eos);
   cnt.iters += itl + itr;
   cnt.inv += 2;
   cnt.fb += (stl == ST_FALLBACK) + (str == ST_FALLBACK);
@@ -233,7 +248,7 @@ __device__ __forceinline__ bool interface_flux(Tile<T> &s, int r, T theta, int s
   // the face states' conserved variables are the ones just inverted: no round trip through
   // prim -> cons
   constexpr bool TOT = K == KV_TOTAL;
-  Cons<T> F = solver == SRHD_HLLE ? hlle<d, TOT>(wl, wr, ul, ur) : hllc<d, TOT>(wl, wr, ul, ur);
+  Cons<T> F = solver == SRHD_HLLE ? hlle<d, TOT>(wl, wr, ul, ur, eos) : hllc<d, TOT>(wl, wr, ul, ur, eos);
   constexpr int slot = d & 1;
   s.F[slot][0][r] = F.D;
   s.F[slot][1][r] = F.m[0];
@@ -271,6 +286,8 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
   constexpr bool MLP = K == KV_MLP;
   constexpr bool TOT = K == KV_TOTAL;
   static_assert(!TOT || (!GATHER && sizeof(T) == sizeof(I)), "original scheme: padded, one type");
+  static_assert(K != KV_POLY || !GATHER, "polytropic EoS: padded layout");
+  const auto eos = make_eos<K>(a);
   const int tid = threadIdx.x;
   const int g = a.ghost;
   const int N = 8 + 2 * g;
@@ -343,7 +360,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
       double guess = MLP ? mlp_guess(mlp, D, Mx, My, Mz, Et, (valid && adm) ? L : 0.0, consulted, ev) : -1.0;
       my_mlp += valid ? ev : 0u;
       if (!valid) continue;
-      if (adm) invert_with_L<I, GuessT<T, I>>((I)D, (I)Mx, (I)My, (I)Mz, (I)L, (I)guess, consulted, (I)StepTol<T, I>::v, 30, o);
+      if (adm) invert_with_L<I, GuessT<T, I>>((I)D, (I)Mx, (I)My, (I)Mz, (I)L, (I)guess, consulted, (I)StepTol<T, I>::v, 30, o, eos);
       else set_unphysical(o);
       centre_bad |= o.status == ST_UNPHYSICAL;
       centre_unphys += o.status == ST_UNPHYSICAL;
@@ -391,9 +408,9 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
         fm.u[2] = wc.u[2] - T(0.5) * sl[3]; fp.u[2] = wc.u[2] + T(0.5) * sl[3];
         fm.p = wc.p - T(0.5) * sl[4];      fp.p = wc.p + T(0.5) * sl[4];
         Cons<T> Fm, Fp;
-        if (d == 0) { Fm = phys_flux<0, TOT>(fm, prim2cons_s<TOT>(fm)); Fp = phys_flux<0, TOT>(fp, prim2cons_s<TOT>(fp)); }
-        else if (d == 1) { Fm = phys_flux<1, TOT>(fm, prim2cons_s<TOT>(fm)); Fp = phys_flux<1, TOT>(fp, prim2cons_s<TOT>(fp)); }
-        else { Fm = phys_flux<2, TOT>(fm, prim2cons_s<TOT>(fm)); Fp = phys_flux<2, TOT>(fp, prim2cons_s<TOT>(fp)); }
+        if (d == 0) { Fm = phys_flux<0, TOT>(fm, prim2cons_s<TOT>(fm, eos)); Fp = phys_flux<0, TOT>(fp, prim2cons_s<TOT>(fp, eos)); }
+        else if (d == 1) { Fm = phys_flux<1, TOT>(fm, prim2cons_s<TOT>(fm, eos)); Fp = phys_flux<1, TOT>(fp, prim2cons_s<TOT>(fp, eos)); }
+        else { Fm = phys_flux<2, TOT>(fm, prim2cons_s<TOT>(fm, eos)); Fp = phys_flux<2, TOT>(fp, prim2cons_s<TOT>(fp, eos)); }
         acc[0] += Fp.D - Fm.D;
         acc[1] += Fp.m[0] - Fm.m[0];
         acc[2] += Fp.m[1] - Fm.m[1];
@@ -417,9 +434,9 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
         int r = qi - d * NIF;
         IfaceCount ic = {0, 0, 0, 0, 0, 0};
         bool ok;
-        if (d == 0) ok = interface_flux<0, K, I>(s, r, theta, a.riemann, mlp, ic);
-        else if (d == 1) ok = interface_flux<1, K, I>(s, r, theta, a.riemann, mlp, ic);
-        else ok = interface_flux<2, K, I>(s, r, theta, a.riemann, mlp, ic);
+        if (d == 0) ok = interface_flux<0, K, I>(s, r, theta, a.riemann, mlp, ic, eos);
+        else if (d == 1) ok = interface_flux<1, K, I>(s, r, theta, a.riemann, mlp, ic, eos);
+        else ok = interface_flux<2, K, I>(s, r, theta, a.riemann, mlp, ic, eos);
         fail |= !ok;
         my_iters += ic.iters;
         my_mlp += ic.mlp;
@@ -699,7 +716,8 @@ hipError_t launch_step_k(const StepArgs &a, hipStream_t st)
   return hipGetLastError();
 }
 
-// The original scheme exists where it can run: padded layout, bulk type = inversion type.
+// The original scheme exists where it can run: padded layout, bulk type = inversion type; the
+// polytropic EoS for the padded layout.
 template <class T, class I, bool GATHER>
 constexpr bool has_total() { return !GATHER && sizeof(T) == sizeof(I); }
 
@@ -708,6 +726,10 @@ hipError_t launch_step_t(const StepArgs &a, hipStream_t st)
 {
   if (a.energy == SRHD_ENERGY_TOTAL) {
     if constexpr (has_total<T, I, GATHER>()) return launch_step_k<T, I, GATHER, KV_TOTAL>(a, st);
+    else return hipErrorInvalidValue;
+  }
+  if (a.eos_k > 0.0) {
+    if constexpr (!GATHER) return launch_step_k<T, I, GATHER, KV_POLY>(a, st);
     else return hipErrorInvalidValue;
   }
   return a.guess.kind == SRHD_GUESS_MLP ? launch_step_k<T, I, GATHER, KV_MLP>(a, st)
@@ -721,10 +743,14 @@ int occupancy_g(int kind, bool occ2)
     if constexpr (has_total<T, I, GATHER>()) return occupancy_k<T, I, GATHER, KV_TOTAL>(occ2);
     else return 0;
   }
+  if (kind == KV_POLY) {
+    if constexpr (!GATHER) return occupancy_k<T, I, GATHER, KV_POLY>(occ2);
+    else return 0;
+  }
   return kind == KV_MLP ? occupancy_k<T, I, GATHER, KV_MLP>(occ2) : occupancy_k<T, I, GATHER, KV_ANALYTIC>(occ2);
 }
 
-// kind: 0 analytic guess, 1 learned guess, 2 original scheme
+// kind: 0 analytic guess, 1 learned guess, 2 original scheme, 3 polytropic EoS
 template <class T, class I>
 int occupancy_ti(bool gather, int kind, bool occ2)
 {

@@ -53,6 +53,18 @@ class srhd_grid(ctypes.Structure):
                 ("level", _vp), ("n_level", _int), ("dh", ctypes.c_double * MAX_LEVEL)]
 
 
+class srhd_eos(ctypes.Structure):
+    _fields_ = [("kind", _int), ("gamma", ctypes.c_double)]
+
+
+EOS_TM, EOS_POLYTROPIC = 0, 1
+
+
+def _eos(gamma):
+    """srhd_eos for the TM EoS (gamma None) or the polytropic EoS with this Gamma."""
+    return srhd_eos(EOS_TM, 0.0) if gamma is None else srhd_eos(EOS_POLYTROPIC, float(gamma))
+
+
 class srhd_sched(ctypes.Structure):
     _fields_ = [("groups", _int), ("chunk", _int), ("occupancy", _int), ("queue", _vp)]
 
@@ -60,7 +72,7 @@ class srhd_sched(ctypes.Structure):
 class srhd_step_params(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("riemann", _int), ("prec", _int),
                 ("max_retry", _int), ("guess", srhd_guess), ("sched", srhd_sched),
-                ("energy", _int), ("integrator", _int), ("flux_out", _vp)]
+                ("energy", _int), ("integrator", _int), ("eos", srhd_eos), ("flux_out", _vp)]
 
 
 class srhd_tune_entry(ctypes.Structure):
@@ -81,11 +93,12 @@ STATS_FIELDS = ("n_unphysical", "n_fallback", "n_noconv", "newton_iters", "n_inv
                 "n_retry", "n_mlp", "n_pred_fallback")
 
 _sig = {
-    "srhd_prim2cons": [_int, _i64, _vp, _vp, _vp],
-    "srhd_cons2prim": [_int, _i64, _vp, _vp, _vp, _vp, ctypes.POINTER(srhd_guess), _vp],
+    "srhd_prim2cons": [_int, _i64, _vp, _vp, ctypes.POINTER(srhd_eos), _vp],
+    "srhd_cons2prim": [_int, _i64, _vp, _vp, _vp, _vp, ctypes.POINTER(srhd_guess),
+                       ctypes.POINTER(srhd_eos), _vp],
     "srhd_fill_ghosts": [_int, _i64, _int, _i64, _vp, _vp, _vp, _vp],
     "srhd_cfl_dt": [_int, _i64, _vp, _int, ctypes.POINTER(ctypes.c_double), ctypes.c_double,
-                    _vp, _vp, _vp],
+                    _vp, _vp, ctypes.POINTER(srhd_eos), _vp],
     "srhd_stats_reset": [_vp, _vp],
     "srhd_fluid_step": [ctypes.POINTER(srhd_patches), _vp, _vp,
                         ctypes.POINTER(srhd_step_params), _vp, _vp],
@@ -161,19 +174,22 @@ def _need_cuda(*ts):
 
 
 # ------------------------------------------------------------------------------- conversions
-def srhd_prim2cons(prim, cons=None):
-    """prim [5][n] -> cons [5][n] (same dtype)."""
+def srhd_prim2cons(prim, cons=None, gamma=None):
+    """prim [5][n] -> cons [5][n] (same dtype); gamma selects the polytropic EoS."""
     _need_cuda(prim)
     if cons is None:
         cons = torch.empty_like(prim)
     _need_cuda(cons)
     n = prim.shape[-1]
-    _check(_lib.srhd_prim2cons(_dtype_code(prim), n, _ptr(prim), _ptr(cons), _stream()))
+    e = _eos(gamma)
+    _check(_lib.srhd_prim2cons(_dtype_code(prim), n, _ptr(prim), _ptr(cons), ctypes.byref(e),
+                               _stream()))
     return cons
 
 
-def srhd_cons2prim(cons, prim=None, status=None, iters=None, guess=None, max_iter=0):
-    """cons [5][n] -> prim [5][n]; status int8 [n] and iters uint8 [n] if given (or True)."""
+def srhd_cons2prim(cons, prim=None, status=None, iters=None, guess=None, max_iter=0, gamma=None):
+    """cons [5][n] -> prim [5][n]; status int8 [n] and iters uint8 [n] if given (or True);
+    gamma selects the polytropic EoS."""
     _need_cuda(cons)
     n = cons.shape[-1]
     if prim is None:
@@ -184,8 +200,9 @@ def srhd_cons2prim(cons, prim=None, status=None, iters=None, guess=None, max_ite
         iters = torch.empty(n, dtype=torch.uint8, device=cons.device)
     _need_cuda(prim, status, iters)
     g = guess if guess is not None else srhd_guess(GUESS_ANALYTIC, None, max_iter)
+    e = _eos(gamma)
     _check(_lib.srhd_cons2prim(_dtype_code(cons), n, _ptr(cons), _ptr(prim), _ptr(status),
-                               _ptr(iters), ctypes.byref(g), _stream()))
+                               _ptr(iters), ctypes.byref(g), ctypes.byref(e), _stream()))
     return prim, status, iters
 
 
@@ -217,8 +234,9 @@ def _work(device):
     return _cfl_work[key]
 
 
-def srhd_cfl_dt(interior, dh, c_cfl=0.5, dt_lev=None, work=None):
-    """Per-level time step (device float64 [n_level]) from interior cons [P][5][8][8][8]."""
+def srhd_cfl_dt(interior, dh, c_cfl=0.5, dt_lev=None, work=None, gamma=None):
+    """Per-level time step (device float64 [n_level]) from interior cons [P][5][8][8][8];
+    gamma selects the polytropic EoS."""
     _need_cuda(interior)
     dh = [float(x) for x in dh]
     nl = len(dh)
@@ -227,8 +245,9 @@ def srhd_cfl_dt(interior, dh, c_cfl=0.5, dt_lev=None, work=None):
     if work is None:
         work = _work(interior.device)
     arr = (ctypes.c_double * nl)(*dh)
+    e = _eos(gamma)
     _check(_lib.srhd_cfl_dt(_dtype_code(interior), interior.shape[0], _ptr(interior), nl, arr,
-                            float(c_cfl), _ptr(dt_lev), _ptr(work), _stream()))
+                            float(c_cfl), _ptr(dt_lev), _ptr(work), ctypes.byref(e), _stream()))
     return dt_lev
 
 
@@ -278,7 +297,7 @@ def _patches(padded, dh, level, ghost):
 
 
 def _params(theta, riemann, prec, max_retry, guess, sched, energy=ENERGY_REDUCED, integrator=MHM,
-            flux_out=None):
+            flux_out=None, gamma=None):
     prm = srhd_step_params()
     prm.theta = float(theta)
     prm.riemann = int(riemann)
@@ -289,13 +308,14 @@ def _params(theta, riemann, prec, max_retry, guess, sched, energy=ENERGY_REDUCED
     prm.energy = int(energy)
     prm.integrator = int(integrator)
     prm.flux_out = None if flux_out is None else flux_out.data_ptr()
+    prm.eos = _eos(gamma)
     return prm
 
 
 def srhd_step_occupancy(prec, guess_kind=GUESS_ANALYTIC, gather=False, occupancy=0,
-                        energy=ENERGY_REDUCED, integrator=MHM):
+                        energy=ENERGY_REDUCED, integrator=MHM, gamma=None):
     prm = _params(1.5, HLLC, prec, 4, srhd_guess(int(guess_kind), None, 0), None, energy,
-                  integrator)
+                  integrator, gamma=gamma)
     prm.sched = srhd_sched(0, 1, int(occupancy), None)
     rc = _lib.srhd_step_occupancy(ctypes.byref(prm), int(bool(gather)))
     _check(min(rc, 0))
@@ -364,10 +384,11 @@ def srhd_autotune_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, 
 
 def srhd_fluid_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann=HLLC,
                     prec=PREC_FP64, max_retry=4, stats=None, ghost=None, guess=None, sched=None,
-                    energy=ENERGY_REDUCED, integrator=MHM, flux_out=None):
+                    energy=ENERGY_REDUCED, integrator=MHM, flux_out=None, gamma=None):
     """One MUSCL-Hancock (or, integrator=VL, VL) step: padded cons [P][5][N][N][N] -> interior
     [P][5][8][8][8].  energy=ENERGY_TOTAL runs the original scheme on (D, M, E); flux_out
-    ([P][6][5][64] FP64) receives the fluxes through the patch faces."""
+    ([P][6][5][64] FP64) receives the fluxes through the patch faces; gamma selects the
+    polytropic EoS."""
     _need_cuda(padded, dt_lev, level, stats, flux_out)
     P = padded.shape[0]
     N = padded.shape[-1]
@@ -376,7 +397,7 @@ def srhd_fluid_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann
         out = torch.empty((P, 5, 8, 8, 8), dtype=torch.float64, device=padded.device)
     _need_cuda(out)
     d = _patches(padded, dh, level, g)
-    prm = _params(theta, riemann, prec, max_retry, guess, sched, energy, integrator, flux_out)
+    prm = _params(theta, riemann, prec, max_retry, guess, sched, energy, integrator, flux_out, gamma)
     _check(_lib.srhd_fluid_step(ctypes.byref(d), _ptr(out), _ptr(dt_lev), ctypes.byref(prm),
                                 _ptr(stats), _stream()))
     return out
@@ -409,7 +430,7 @@ def smax_value(bits):
 def srhd_fluid_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, dt_lev=None,
                          level=None, cons_out=None, prims_out=None, smax_out=None, dt_used=None,
                          theta=1.5, riemann=HLLC, prec=PREC_FP64, max_retry=4, stats=None,
-                         guess=None, sched=None):
+                         guess=None, sched=None, gamma=None):
     """One step of a block of same-level patches (ghosts gathered from neighbour interiors).
     Returns (cons_out, prims_out, smax_out)."""
     _need_cuda(cons, prims, neighbor, smax_in, dt_lev, level, stats)
@@ -424,7 +445,7 @@ def srhd_fluid_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, dt_
     if prims.dtype != prims_dtype(prec) or prims_out.dtype != prims_dtype(prec):
         raise TypeError("primitives must be %s for this precision" % prims_dtype(prec))
     gr = _grid(cons, prims, neighbor, dh, level)
-    prm = _params(theta, riemann, prec, max_retry, guess, sched)
+    prm = _params(theta, riemann, prec, max_retry, guess, sched, gamma=gamma)
     _check(_lib.srhd_fluid_step_grid(ctypes.byref(gr), _ptr(smax_in), float(c_cfl), _ptr(dt_lev),
                                      _ptr(cons_out), _ptr(prims_out), _ptr(smax_out),
                                      _ptr(dt_used), ctypes.byref(prm), _ptr(stats), _stream()))

@@ -36,20 +36,20 @@ def test_argument_errors_are_reported_without_a_gpu(lib):
     lib.srhd_prim2cons.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p]
     lib.srhd_last_error.restype = ctypes.c_char_p
-    assert lib.srhd_prim2cons(7, 10, None, None, None) == -1
+    assert lib.srhd_prim2cons(7, 10, None, None, None, None) == -1
     assert b"dtype" in lib.srhd_last_error()
-    assert lib.srhd_prim2cons(0, -1, None, None, None) == -1
-    assert lib.srhd_prim2cons(0, 10, None, None, None) == -1
+    assert lib.srhd_prim2cons(0, -1, None, None, None, None) == -1
+    assert lib.srhd_prim2cons(0, 10, None, None, None, None) == -1
     assert b"NULL" in lib.srhd_last_error()
-    assert lib.srhd_prim2cons(0, 0, None, None, None) == 0       # empty batch is a no-op
+    assert lib.srhd_prim2cons(0, 0, None, None, None, None) == 0       # empty batch is a no-op
     # overlapping arrays are rejected before any launch (host addresses are never touched)
     buf = ctypes.create_string_buffer(800)
     a = ctypes.addressof(buf)
-    assert lib.srhd_prim2cons(0, 10, a, a + 8, None) == -1
+    assert lib.srhd_prim2cons(0, 10, a, a + 8, None, None) == -1
     assert b"overlap" in lib.srhd_last_error()
-    assert lib.srhd_prim2cons(0, 1, a + 1, a + 400, None) == -1      # misaligned
+    assert lib.srhd_prim2cons(0, 1, a + 1, a + 400, None, None) == -1      # misaligned
     lib.srhd_abi_version.restype = ctypes.c_int
-    assert lib.srhd_abi_version() == 4
+    assert lib.srhd_abi_version() == 5
 
 
 def test_step_descriptor_checks(lib):
@@ -154,3 +154,20 @@ def test_schedule_checks(lib):
     prm.integrator = 0
     assert occ(0, 0, 1, 0, integrator=1) == -3
     assert occ(2, 1, 0, 0, integrator=1) == -3
+    # the polytropic EoS: 1 < gamma <= 2; padded MUSCL-Hancock, reduced energy, analytic guess
+    prm.eos = S.srhd_eos(1, 2.5)
+    assert call() == -1 and b"gamma" in S._lib.srhd_last_error()
+    prm.eos = S.srhd_eos(7, 1.5)
+    assert call() == -1 and b"EoS" in S._lib.srhd_last_error()
+    prm.eos = S.srhd_eos(1, 5.0 / 3.0)
+    prm.integrator = 1
+    assert call() == -3 and b"polytropic" in S._lib.srhd_last_error()
+    prm.integrator = 0
+    prm.eos = S.srhd_eos(0, 0.0)
+    q = S.srhd_step_params()
+    q.eos = S.srhd_eos(1, 4.0 / 3.0)
+    assert S._lib.srhd_step_occupancy(ctypes.byref(q), 1) == -3
+    bad = S.srhd_eos(1, 1.0)
+    assert S._lib.srhd_prim2cons(0, 10, None, None, ctypes.byref(bad), None) == -1
+    assert S._lib.srhd_cfl_dt(0, 0, None, 1, (ctypes.c_double * 1)(0.1), 0.5, None, None,
+                              ctypes.byref(bad), None) == -1
