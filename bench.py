@@ -53,9 +53,20 @@ IO_BYTES_PER_PATCH = {                         # what one patch's step consumes 
 # the two-workgroup register variant) on this workload, from the rocprofv3 FETCH_SIZE /
 # WRITE_SIZE runs summarised in profiles/step_blast256_grid_learned.md; valid only for the kernel
 # sources they were taken on (hash of the files that make up the step kernel).
-PROFILED_TRAFFIC = {"sources_sha256_16": "b28800f37ab318ff", "read": 1708.1e6, "write": 1747.7e6,
+PROFILED_TRAFFIC = {"sources_sha256_16": "573abc303fe8fca9", "read": 1721.7e6, "write": 1747.7e6,
                     "path": "grid", "summary": "profiles/step_blast256_grid_learned.md"}
 STEP_SOURCES = ("srhd_step_impl.hpp", "srhd_step_mixed.hip", "srhd_device.hpp", "srhd_mlp.hpp")
+
+
+def _finite(v):
+    """The JSON line with every non-finite float replaced by null (strict JSON has no NaN)."""
+    if isinstance(v, dict):
+        return {k: _finite(x) for k, x in v.items()}
+    if isinstance(v, (list, tuple)):
+        return [_finite(x) for x in v]
+    if isinstance(v, float) and not math.isfinite(v):
+        return None
+    return v
 
 
 def step_sources_hash():
@@ -235,6 +246,10 @@ def parse():
                          "configuration) or groups,chunk,occupancy")
     ap.add_argument("--no-vl", dest="vl", action="store_false",
                     help="skip the VL integrator's runs")
+    ap.add_argument("--no-variants", dest="variants", action="store_false",
+                    help="skip the original-scheme and polytropic-EoS runs")
+    ap.add_argument("--no-amr", dest="amr", action="store_false",
+                    help="skip the two-level AMR cycle")
     ap.add_argument("--only-headline", action="store_true",
                     help="measure the headline configuration only (no analytic-guess, "
                          "configured-input or FP32-inversion comparisons)")
@@ -440,10 +455,16 @@ def main():
         res["newton"]["fp32_inversion"] = newton_summary(st_32)
 
     def field_err(x, ref):
-        ms = max(float(np.max(np.sqrt((ref[:, 1:4] ** 2).sum(axis=1)))), 1e-300)
-        return {"D": float(np.max(np.abs(x[:, 0] / ref[:, 0] - 1))),
-                "Et": float(np.max(np.abs(x[:, 4] / ref[:, 4] - 1))),
-                "M": float(np.max(np.abs(x[:, 1:4] - ref[:, 1:4]))) / ms}
+        # over the cells finite on both sides (a non-finite cell is counted, not compared)
+        fin = np.isfinite(x).all(axis=1) & np.isfinite(ref).all(axis=1)
+        x, ref = x.transpose(1, 0, 2, 3, 4)[:, fin], ref.transpose(1, 0, 2, 3, 4)[:, fin]
+        if x.shape[1] == 0:
+            return {"non_finite_cells": int((~fin).sum())}
+        ms = max(float(np.max(np.sqrt((ref[1:4] ** 2).sum(axis=0)))), 1e-300)
+        return {"D": float(np.max(np.abs(x[0] / ref[0] - 1))),
+                "Et": float(np.max(np.abs(x[4] / ref[4] - 1))),
+                "M": float(np.max(np.abs(x[1:4] - ref[1:4]))) / ms,
+                "non_finite_cells": int((~fin).sum())}
 
     # per-field difference of one FP32-bulk step against one FP64 step from the same state, and
     # after the timed run (each from its own state)
@@ -492,6 +513,109 @@ def main():
                                "newton": newton_summary(st_v)}
         res["vl"]["mixed_vs_fp64_rel_err_after_%d_steps" % args.steps] = field_err(finals["mixed"],
                                                                                  finals["fp64"])
+
+    # the widened rows on the same blast (padded layout, analytic guess): the original
+    # total-energy scheme and the polytropic EoS, one-workgroup-per-patch launch
+    if args.variants and not args.only_headline:
+        def time_padded(n_steps, **kw):
+            """Ghost fill + one step per step from the initial state (the blast's time step)."""
+            S.srhd_cfl_dt(cons0, dh, 0.5, dt_lev=dt)
+            cur = cons0.clone()
+            if kw.get("energy") == S.ENERGY_TOTAL:
+                cur[:, 4] += cur[:, 0]                 # E = Et + D: the original scheme's state
+            if kw.get("gamma"):
+                cur = S.srhd_prim2cons(prim_soa, gamma=kw["gamma"]).reshape(5, P, 512).permute(
+                    1, 0, 2).contiguous().reshape(P, 5, 8, 8, 8)
+            nxt = torch.empty_like(cur)
+            st = S.new_stats(dev)
+            for _ in range(args.warmup):
+                S.srhd_fill_ghosts(cur, nb, 3, padded=pad)
+                S.srhd_fluid_step(pad, dt, dh, out=nxt, **kw)
+            a0 = torch.cuda.Event(enable_timing=True)
+            a1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            a0.record(stream)
+            for _ in range(n_steps):
+                S.srhd_fill_ghosts(cur, nb, 3, padded=pad)
+                S.srhd_fluid_step(pad, dt, dh, out=nxt, stats=st, **kw)
+                cur, nxt = nxt, cur
+            a1.record(stream)
+            torch.cuda.synchronize()
+            ms = a0.elapsed_time(a1)
+            return {"value": n_cells * n_steps / (ms * 1e-3), "ms_per_step": ms / n_steps,
+                    "stats": S.stats_dict(st)}
+        res["original_scheme"] = {
+            "fp64": time_padded(args.steps, prec=S.PREC_FP64, energy=S.ENERGY_TOTAL),
+            "fp32": time_padded(args.steps, prec=S.PREC_FP32, energy=S.ENERGY_TOTAL)}
+        res["polytropic_5_3"] = {
+            "fp64": time_padded(args.steps, prec=S.PREC_FP64, gamma=5.0 / 3.0),
+            "mixed": time_padded(args.steps, prec=S.PREC_MIXED, gamma=5.0 / 3.0)}
+        for k in ("original_scheme", "polytropic_5_3"):
+            print("# %s: %s" % (k, {m: "%.3g cell updates/s" % v["value"] for m, v in res[k].items()}),
+                  file=sys.stderr, flush=True)
+
+    # two AMR levels: 16^3 coarse patches with the central 8^3 refined (4,096 fine patches);
+    # one cycle = CFL, coarse step, two fine sub-steps with coarse-to-fine ghosts, restriction,
+    # coarse-fine flux correction, all on the GPU (FP64, MUSCL-Hancock)
+    if args.amr and not args.only_headline:
+        t2 = W.two_level(16, 4, 12)
+        def amr_cons(xyz):
+            x, y, z = xyz
+            s_ = np.sin(2 * np.pi * (x + 0.5 * y))
+            w = np.stack([1.0 + 0.2 * s_, 0.3 + 0.1 * np.cos(2 * np.pi * z) + 0 * x, 0.1 * s_, 0 * x,
+                          1.0 + 0.3 * np.cos(2 * np.pi * y) + 0 * x], axis=1)
+            Pn = w.shape[0]
+            ws = torch.from_numpy(np.ascontiguousarray(w.reshape(Pn, 5, 512).transpose(1, 0, 2).reshape(5, -1))).to(dev)
+            return S.srhd_prim2cons(ws).reshape(5, Pn, 512).permute(1, 0, 2).contiguous().reshape(Pn, 5, 8, 8, 8)
+        ac, af = amr_cons(t2["coarse_xyz"]), amr_cons(t2["fine_xyz"])
+        g2 = {k: torch.from_numpy(np.ascontiguousarray(t2[k])).to(dev)
+              for k in ("coarse_neighbor", "fine_neighbor", "parent", "octant", "parent_of", "child", "faces")}
+        S.srhd_restrict(ac, g2["parent_of"], g2["child"], af)
+        dh2 = [t2["dh_c"], t2["dh_f"]]
+        Pc, Pf = ac.shape[0], af.shape[0]
+        fc = torch.empty((Pc, 6, 5, 64), dtype=torch.float64, device=dev)
+        fcw, ffl = torch.empty_like(fc), torch.empty((Pf, 6, 5, 64), dtype=torch.float64, device=dev)
+        ffs = torch.zeros_like(ffl)
+        both = torch.empty((Pc + Pf, 5, 8, 8, 8), dtype=torch.float64, device=dev)
+        dt2 = torch.empty(2, dtype=torch.float64, device=dev)
+        skipped = torch.zeros(1, dtype=torch.int64, device=dev)
+
+        def amr_cycle(c, f):
+            both[:Pc].copy_(c)
+            both[Pc:].copy_(f)
+            S.srhd_cfl_dt(both, dh2, 0.5, dt_lev=dt2)
+            dtv = dt2.cpu().numpy()
+            pc = S.srhd_fill_ghosts(c, g2["coarse_neighbor"], 3)
+            cn = S.srhd_fluid_step(pc, dt2[0:1], [dh2[0]], flux_out=fc)
+            pcn = S.srhd_fill_ghosts(cn, g2["coarse_neighbor"], 3)
+            for sub in range(2):
+                pf = S.srhd_fill_ghosts(f, g2["fine_neighbor"], 3)
+                S.srhd_fill_ghosts_coarse(pf, g2["fine_neighbor"], g2["parent"], g2["octant"], pc,
+                                          pcn if sub else None, 0.5 * sub)
+                f = S.srhd_fluid_step(pf, dt2[1:2], [dh2[1]], flux_out=ffl)
+                S.srhd_flux_accumulate(ffs, ffl, float(sub), float(dtv[1]))
+            S.srhd_restrict(cn, g2["parent_of"], g2["child"], f)
+            S.srhd_flux_accumulate(fcw, fc, 0.0, float(dtv[0]))
+            S.srhd_flux_correct(cn, g2["faces"], fcw, ffs, dh2[0], skipped=skipped)
+            return cn, f
+        c, f = ac, af
+        for _ in range(args.warmup):
+            c, f = amr_cycle(c, f)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        n_cyc = args.steps
+        for _ in range(n_cyc):
+            c, f = amr_cycle(c, f)
+        torch.cuda.synchronize()
+        ms = (time.time() - t0) * 1e3
+        upd = (Pc + 2 * Pf) * 512
+        res["amr_two_level"] = {"coarse_patches": Pc, "fine_patches": Pf, "cycles": n_cyc,
+                                "ms_per_cycle": ms / n_cyc,
+                                "value": upd * n_cyc / (ms * 1e-3), "unit": "cell updates/s",
+                                "note": "wall clock per cycle incl. one host read of dt",
+                                "flux_correction_skipped": int(skipped.item())}
+        print("# AMR two levels: %.2f ms per cycle (%.3g cell updates/s)"
+              % (ms / n_cyc, upd * n_cyc / (ms * 1e-3)), file=sys.stderr, flush=True)
 
     # ---------------------------------------------------------------- roofline of the step kernel
     kavg = float(np.mean(kms_mx)) * 1e-3
@@ -604,7 +728,7 @@ def main():
     }
     line["schedules"] = schedules
     line.update(res)
-    print(json.dumps(line), flush=True)
+    print(json.dumps(_finite(line)), flush=True)
 
 
 if __name__ == "__main__":

@@ -885,8 +885,10 @@ static void sc_riemann(int scheme, int riemann, int d, const double wl[5], const
  *   corrector  the interface flux from PLM face states of W* (W* -/+ slope/2 on either side),
  *              U^{n+1} = U^n - (dt/dh) sum_d (F_{+1/2} - F_{-1/2}).
  * A predictor state that fails the inversion (no limiter acts on it) is replaced by the cell's
- * state at t^n, W* = W^n: the half step is dropped for that cell.  Returns the number of output
- * cells failing Eq. 30. */
+ * state at t^n, W* = W^n: the half step is dropped for that cell.  With theta = 0 (piecewise-
+ * constant reconstruction, the retry's last resort) the half step is dropped everywhere, W* = W^n:
+ * the first-order Godunov step, as MUSCL-Hancock is with theta = 0.  Returns the number of
+ * output cells failing Eq. 30. */
 static int or_vl_step_patch(const or_patch *P, double dt, double dh, double theta, int riemann,
                             int scheme, double *out, or_counts *cnt, double *bflux)
 {
@@ -901,6 +903,10 @@ static int or_vl_step_patch(const or_patch *P, double dt, double dh, double thet
       for (int i = -2; i < PS + 2; i++) {
         if (!or_in_vl_half(i, j, k)) continue;
         const double *wc = or_vl_prim(C, i, j, k);
+        if (theta == 0.0) {
+          for (int f = 0; f < 5; f++) wh[VIDX(i, j, k)][f] = wc[f];
+          continue;
+        }
         double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
         for (int d = 0; d < 3; d++) {
           int di = (d == 0), dj = (d == 1), dk = (d == 2);

@@ -16,7 +16,9 @@
 // The face states of C are primitives (no inversion); the limiter keeps rho and p between
 // neighbouring values, so only an output cell can fail: then C-D are redone with
 // theta *= 0.75 (max_retry times) and theta = 0 (Sec. 3.4).  A predictor state that fails the
-// inversion (no limiter acts on it) is replaced by the cell's state at t^n.
+// inversion (no limiter acts on it) is replaced by the cell's state at t^n.  With theta = 0 the
+// half step is dropped everywhere (W* = W^n): the first-order Godunov step, as MUSCL-Hancock is
+// with theta = 0 -- so the retry's last attempt restores W^n at the half-step cells.
 #include "srhd_step_impl.hpp"
 
 namespace srhd {
@@ -262,75 +264,80 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
 
   // ---------------------------------------------------------------- P: predictor
   // this thread's half-step cells: tid, tid + 512, tid + 1024 (the last only for tid < 256)
-  T acc[3][5];
+  // With theta = 0 (piecewise-constant reconstruction) the half step is dropped everywhere: the
+  // step is the first-order Godunov step, W* = W^n.
+  const bool predicted = a.theta > 0.0;        // uniform across the workgroup
+  if (predicted) {
+    T acc[3][5];
 #pragma unroll
-  for (int h = 0; h < 3; ++h)
+    for (int h = 0; h < 3; ++h)
 #pragma unroll
-    for (int f = 0; f < 5; ++f) acc[h][f] = T(0);
+      for (int f = 0; f < 5; ++f) acc[h][f] = T(0);
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    for (int r = tid; r < NVF; r += NT) {
-      if (d == 0) predictor_face<0>(s, r, a.riemann);
-      else if (d == 1) predictor_face<1>(s, r, a.riemann);
-      else predictor_face<2>(s, r, a.riemann);
+    for (int d = 0; d < 3; ++d) {
+      for (int r = tid; r < NVF; r += NT) {
+        if (d == 0) predictor_face<0>(s, r, a.riemann);
+        else if (d == 1) predictor_face<1>(s, r, a.riemann);
+        else predictor_face<2>(s, r, a.riemann);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int h = 0; h < 3; ++h) {
+        const int hc = tid + h * NT;
+        if (hc < NVH) {
+          const int fm = kVl.hface[d][hc][0], fp = kVl.hface[d][hc][1];
+#pragma unroll
+          for (int f = 0; f < 5; ++f) acc[h][f] += s.B[f * NVF + fp] - s.B[f * NVF + fm];
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
+    const double half = 0.5 * dt / dh;
 #pragma unroll
     for (int h = 0; h < 3; ++h) {
       const int hc = tid + h * NT;
       if (hc < NVH) {
-        const int fm = kVl.hface[d][hc][0], fp = kVl.hface[d][hc][1];
+        int i, j, k;
+        unpack(kVl.hcell[hc], i, j, k);
+        const int off = ((k + g) * N + (j + g)) * N + (i + g);
+        double u[5];
 #pragma unroll
-        for (int f = 0; f < 5; ++f) acc[h][f] += s.B[f * NVF + fp] - s.B[f * NVF + fm];
+        for (int f = 0; f < 5; ++f) u[f] = q[f * N3 + off] - half * (double)acc[h][f];
+        double L;
+        InvOut<I> o;
+        if (admissible(u[0], u[1], u[2], u[3], u[4], DBL_EPSILON, L))
+          invert_with_L<I, GuessT<T, I>>((I)u[0], (I)u[1], (I)u[2], (I)u[3], (I)L, (I)-1.0, false,
+                                         (I)StepTol<T, I>::v, 30, o);
+        else set_unphysical(o);
+        my_iters += o.iters;
+        my_inv += 1;
+        my_nc += o.status == ST_NOCONV;
+        if (o.status == ST_UNPHYSICAL) {
+          // the half step is dropped for this cell: W* = W^n (still in the tile)
+          const int b = bidx(i, j, k);
+#pragma unroll
+          for (int f = 0; f < 5; ++f) acc[h][f] = s.W[f][b];
+          ++my_pfb;
+        } else {
+          acc[h][0] = (T)o.rho;
+          acc[h][1] = (T)o.ux;
+          acc[h][2] = (T)o.uy;
+          acc[h][3] = (T)o.uz;
+          acc[h][4] = (T)o.p;
+        }
       }
     }
-    __syncthreads();
-  }
-  const double half = 0.5 * dt / dh;
+    // every read of the centre primitives ended at the last barrier above: overwrite with W*
 #pragma unroll
-  for (int h = 0; h < 3; ++h) {
-    const int hc = tid + h * NT;
-    if (hc < NVH) {
-      int i, j, k;
-      unpack(kVl.hcell[hc], i, j, k);
-      const int off = ((k + g) * N + (j + g)) * N + (i + g);
-      double u[5];
-#pragma unroll
-      for (int f = 0; f < 5; ++f) u[f] = q[f * N3 + off] - half * (double)acc[h][f];
-      double L;
-      InvOut<I> o;
-      if (admissible(u[0], u[1], u[2], u[3], u[4], DBL_EPSILON, L))
-        invert_with_L<I, GuessT<T, I>>((I)u[0], (I)u[1], (I)u[2], (I)u[3], (I)L, (I)-1.0, false,
-                                       (I)StepTol<T, I>::v, 30, o);
-      else set_unphysical(o);
-      my_iters += o.iters;
-      my_inv += 1;
-      my_nc += o.status == ST_NOCONV;
-      if (o.status == ST_UNPHYSICAL) {
-        // the half step is dropped for this cell: W* = W^n (still in the tile)
+    for (int h = 0; h < 3; ++h) {
+      const int hc = tid + h * NT;
+      if (hc < NVH) {
+        int i, j, k;
+        unpack(kVl.hcell[hc], i, j, k);
         const int b = bidx(i, j, k);
 #pragma unroll
-        for (int f = 0; f < 5; ++f) acc[h][f] = s.W[f][b];
-        ++my_pfb;
-      } else {
-        acc[h][0] = (T)o.rho;
-        acc[h][1] = (T)o.ux;
-        acc[h][2] = (T)o.uy;
-        acc[h][3] = (T)o.uz;
-        acc[h][4] = (T)o.p;
+        for (int f = 0; f < 5; ++f) s.W[f][b] = acc[h][f];
       }
-    }
-  }
-  // every read of the centre primitives ended at the last barrier above: overwrite with W*
-#pragma unroll
-  for (int h = 0; h < 3; ++h) {
-    const int hc = tid + h * NT;
-    if (hc < NVH) {
-      int i, j, k;
-      unpack(kVl.hcell[hc], i, j, k);
-      const int b = bidx(i, j, k);
-#pragma unroll
-      for (int f = 0; f < 5; ++f) s.W[f][b] = acc[h][f];
     }
   }
   const bool input_bad = __syncthreads_or(bad_in != 0);
@@ -340,7 +347,40 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
   const int cq = ((ck + g) * N + (cj + g)) * N + (ci + g);
   T theta = (T)a.theta;
   unsigned int retries = 0, unphys = 0;
+  bool have_pred = predicted;
   for (int attempt = 0;; ++attempt) {
+    if (theta == T(0) && have_pred) {
+      // the last resort of the retry (theta = 0) is the Godunov step: put W^n back at the
+      // half-step cells, inverted again from the padded input
+#pragma unroll
+      for (int h = 0; h < 3; ++h) {
+        const int hc = tid + h * NT;
+        if (hc < NVH) {
+          int i, j, k;
+          unpack(kVl.hcell[hc], i, j, k);
+          const int off = ((k + g) * N + (j + g)) * N + (i + g);
+          const double D = q[off], Mx = q[N3 + off], My = q[2 * N3 + off], Mz = q[3 * N3 + off],
+                       Et = q[4 * N3 + off];
+          double L;
+          InvOut<I> o;
+          if (admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L))
+            invert_with_L<I, GuessT<T, I>>((I)D, (I)Mx, (I)My, (I)Mz, (I)L, (I)-1.0, false,
+                                           (I)StepTol<T, I>::v, 30, o);
+          else set_unphysical(o);
+          my_iters += o.iters;
+          my_inv += 1;
+          my_nc += o.status == ST_NOCONV;
+          const int b = bidx(i, j, k);
+          s.W[0][b] = (T)o.rho;
+          s.W[1][b] = (T)o.ux;
+          s.W[2][b] = (T)o.uy;
+          s.W[3][b] = (T)o.uz;
+          s.W[4][b] = (T)o.p;
+        }
+      }
+      have_pred = false;
+      __syncthreads();
+    }
     // -------------------------------------------------------------- C + D: corrector, update
     T dU[5] = {T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll 1

@@ -135,3 +135,37 @@ def test_full_size_blast_sampled_patches(S):
     e = step_errors(out.cpu().numpy()[sample], ref)
     print("VL 256^3 sampled (%d patches): %s" % (sample.size, e))
     assert max(e.values()) <= 1e-10, e
+
+
+def test_zero_limiter_and_the_last_resort(S):
+    # theta = 0 from the start: the Godunov step (no predictor) against the oracle
+    g = W.blast(64, seed=3)
+    cons = oracle_cons(g)
+    dt_o, _, _ = O.cfl_dt(cons, None, g.dh_lev, 0.5)
+    pad_o = O.fill_ghosts(cons, g.neighbor, 3)
+    ref, cnt = O.fluid_step(pad_o, dt_o, g.dh_lev, theta=0.0, integrator=1)
+    out = S.srhd_fluid_step(_gpu(pad_o), _gpu(dt_o), g.dh_lev, theta=0.0, integrator=S.VL)
+    torch.cuda.synchronize()
+    e = step_errors(out.cpu().numpy(), ref)
+    assert max(e.values()) <= 1e-10, e
+    # 12 steps of the 128^3 blast: in FP64 every output cell is physical (predictor fallbacks and,
+    # as the last resort, the Godunov step); with an FP32 bulk the predictor's flux differences
+    # next to the hot ellipsoid carry FP32 errors above the cold gas's Et, and some cold cells
+    # stay unphysical after every attempt -- recorded here, not required (MUSCL-Hancock's half
+    # step is local to the cell, and its limiter retries avoid this on the same run)
+    g = W.blast(128, seed=3, order="morton")
+    c0 = _gpu(oracle_cons(g))
+    nb = _gpu(g.neighbor)
+    for prec in (0, 1):
+        c = c0
+        bad = 0
+        for k in range(12):
+            dt = S.srhd_cfl_dt(c, g.dh_lev)
+            pad = S.srhd_fill_ghosts(c, nb)
+            st = S.new_stats(DEV)
+            c = S.srhd_fluid_step(pad, dt, g.dh_lev, prec=prec, stats=st, integrator=S.VL)
+            sd = S.stats_dict(st)
+            bad += sd["n_unphysical"]
+        print("VL prec %d 128^3, 12 steps: %d unphysical output cells; last stats %s" % (prec, bad, sd))
+        if prec == 0:
+            assert bad == 0
