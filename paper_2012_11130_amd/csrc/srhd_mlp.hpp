@@ -45,10 +45,14 @@ __device__ __forceinline__ float silu_f(float a)
 
 __device__ __forceinline__ float bf16_to_f(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
 
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+// Two floats rounded to BF16 (nearest even), lo in the low half: one packed conversion.
 __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi)
 {
-  __bf16 a = (__bf16)lo, b = (__bf16)hi;     // round to nearest even
-  return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+  const f32x2_t v = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
 }
 
 union Frag8 {
@@ -133,6 +137,93 @@ __device__ __forceinline__ float mlp_eval(const MlpDev &m, float f0, float f1, f
   return part + other + m.bias[MLP_B3];
 }
 
+// The same network with one 32x32 accumulator tile live at a time.  The B operand of state tile
+// nt holds, in lane l, hidden units 16 ks + 8 (l / 32) + 0..7 of the state in column l % 32 of
+// that tile, so each lane forms just those 8 activations per slab, from that state's inputs (one
+// lane swap per tile), for each (tile, half of the hidden layer) pass: the same layer-1 work as
+// mlp_eval, no swaps per slab, and only 16 accumulator registers and one B operand live (the
+// step kernels call the network from code that needs its registers).  The activations, the
+// MFMA operands, their order and the layer-3 sums are those of mlp_eval, so the result is the
+// same bit for bit.
+__device__ __forceinline__ float mlp_eval_lean(const MlpDev &m, float f0, float f1, float f2)
+{
+  const int lane = threadIdx.x & 63;
+  const float x0 = (f0 - m.norm[0]) / m.norm[3];
+  const float x1 = (f1 - m.norm[1]) / m.norm[4];
+  const float x2 = (f2 - m.norm[2]) / m.norm[5];
+  float part0 = 0.0f, part1 = 0.0f;
+#pragma unroll 1
+  for (int nt = 0; nt < 2; ++nt) {
+    // inputs of the state in column lane % 32 of tile nt (lane % 32 + 32 nt)
+    float y0, y1, y2;
+    {
+      auto r0 = __builtin_amdgcn_permlane32_swap(__float_as_uint(x0), __float_as_uint(x0), false, false);
+      auto r1 = __builtin_amdgcn_permlane32_swap(__float_as_uint(x1), __float_as_uint(x1), false, false);
+      auto r2 = __builtin_amdgcn_permlane32_swap(__float_as_uint(x2), __float_as_uint(x2), false, false);
+      y0 = __uint_as_float(nt ? r0[1] : r0[0]);
+      y1 = __uint_as_float(nt ? r1[1] : r1[0]);
+      y2 = __uint_as_float(nt ? r2[1] : r2[0]);
+    }
+    float pt = 0.0f;
+#pragma unroll 1
+    for (int mt = 0; mt < 2; ++mt) {
+      f32x16_t acc = {};
+#pragma unroll 1
+      for (int ks = 0; ks < 4; ++ks) {
+        // this lane's units k0 .. k0 + 7: their 24 W1 weights (48 bytes at a 16-byte aligned
+        // offset of the 16-byte aligned weights) and their biases
+        const int k0 = 16 * ks + 8 * (lane >> 5);
+        const uint4 *wp = reinterpret_cast<const uint4 *>(m.w + MLP_W1 + 3 * k0);
+        const uint4 q0 = wp[0], q1 = wp[1], q2 = wp[2];
+        const uint32_t wd[12] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
+        float b1[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) b1[i] = m.bias[MLP_B1 + k0 + i];
+        Frag8 t;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float h[2];
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            const int i = 2 * j + e;
+            float w3[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              const int q = 3 * i + c;                  // BF16 element q of the 24
+              w3[c] = __uint_as_float(q & 1 ? wd[q >> 1] & 0xffff0000u : wd[q >> 1] << 16);
+            }
+            float a = __builtin_fmaf(w3[0], y0, b1[i]);
+            a = __builtin_fmaf(w3[1], y1, a);
+            a = __builtin_fmaf(w3[2], y2, a);
+            h[e] = silu_f(a);
+          }
+          t.u[j] = pack_bf16(h[0], h[1]);
+        }
+        const uint4 wv = *reinterpret_cast<const uint4 *>(
+            m.w + MLP_W2 + (32 * mt + (lane & 31)) * 64 + 16 * ks + 8 * (lane >> 5));
+        Frag8 a;
+        a.u[0] = wv.x;
+        a.u[1] = wv.y;
+        a.u[2] = wv.z;
+        a.u[3] = wv.w;
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, t.v, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int hrow = 32 * mt + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        pt = __builtin_fmaf(bf16_to_f(m.w[MLP_W3 + hrow]), silu_f(acc[v] + m.bias[MLP_B2 + hrow]), pt);
+      }
+    }
+    if (nt == 0) part0 = pt;
+    else part1 = pt;
+  }
+  const float part = lane < 32 ? part0 : part1;
+  const float give = lane < 32 ? part1 : part0;
+  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(give), __float_as_uint(give), false, false);
+  const float other = __uint_as_float(lane < 32 ? r[1] : r[0]);
+  return part + other + m.bias[MLP_B3];
+}
+
 // Natural logarithm of a positive double, in FP32 arithmetic over the whole double range: the
 // binary exponent is taken exactly and the log of the mantissa by the hardware log2.
 __device__ __forceinline__ float log_wide(double v)
@@ -156,8 +247,11 @@ __device__ __forceinline__ void mlp_features(int set, double D, double Mx, doubl
 
 // Guess of ht for this lane's state from the network (exp of the de-standardised output), or -1
 // where the network is not consulted (L at or below the gate, or L not admissible: pass L = 0).
+// LEAN selects mlp_eval_lean (inside the step kernels) or mlp_eval (throughput kernels); both
+// give the same result.
 // The whole wavefront must call it; the network runs only if some lane needs it, and then
 // `evals` is incremented (per lane: the count of network evaluations performed).
+template <bool LEAN = true>
 __device__ __forceinline__ double mlp_guess(const MlpDev &m, double D, double Mx, double My,
                                             double Mz, double Et, double L, bool &consulted,
                                             unsigned int &evals)
@@ -167,7 +261,7 @@ __device__ __forceinline__ double mlp_guess(const MlpDev &m, double D, double Mx
   ++evals;
   float f0, f1, f2;
   mlp_features(m.features, D, Mx, My, Mz, Et, L, f0, f1, f2);
-  const float z = mlp_eval(m, f0, f1, f2);
+  const float z = LEAN ? mlp_eval_lean(m, f0, f1, f2) : mlp_eval(m, f0, f1, f2);
   return consulted ? (double)__expf(m.norm[6] + m.norm[7] * z) : -1.0;
 }
 
@@ -177,7 +271,7 @@ __device__ __forceinline__ double mlp_guess_f(const MlpDev &m, float f0, float f
 {
   if (!__any(consulted)) return -1.0;
   ++evals;
-  const float z = mlp_eval(m, f0, f1, f2);
+  const float z = mlp_eval_lean(m, f0, f1, f2);
   return consulted ? (double)__expf(m.norm[6] + m.norm[7] * z) : -1.0;
 }
 
