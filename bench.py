@@ -518,41 +518,56 @@ def main():
     # total-energy scheme and the polytropic EoS, one-workgroup-per-patch launch
     if args.variants and not args.only_headline:
         def time_padded(n_steps, **kw):
-            """Ghost fill + one step per step from the initial state (the blast's time step)."""
-            S.srhd_cfl_dt(cons0, dh, 0.5, dt_lev=dt)
+            """n_steps from the initial state: ghost fill + one step per step.  Reduced-energy
+            runs take the CFL time step of the current state every step (the CFL kernel is
+            inside the timed region); the original scheme's total-energy state has no CFL
+            entry, so its runs keep 0.8 x the initial state's CFL step throughout (the blast's
+            S_max grows by less than 10 % over these steps)."""
+            gamma = kw.get("gamma")
             cur = cons0.clone()
-            if kw.get("energy") == S.ENERGY_TOTAL:
-                cur[:, 4] += cur[:, 0]                 # E = Et + D: the original scheme's state
-            if kw.get("gamma"):
-                cur = S.srhd_prim2cons(prim_soa, gamma=kw["gamma"]).reshape(5, P, 512).permute(
+            if gamma:
+                cur = S.srhd_prim2cons(prim_soa, gamma=gamma).reshape(5, P, 512).permute(
                     1, 0, 2).contiguous().reshape(P, 5, 8, 8, 8)
+            total = kw.get("energy") == S.ENERGY_TOTAL
+            if total:
+                S.srhd_cfl_dt(cur, dh, 0.5 * 0.8, dt_lev=dt)
+                cur[:, 4] += cur[:, 0]                 # E = Et + D: the original scheme's state
+            start = cur.clone()
             nxt = torch.empty_like(cur)
             st = S.new_stats(dev)
-            for _ in range(args.warmup):
+
+            def one(stats):
+                nonlocal cur, nxt
+                if not total:
+                    S.srhd_cfl_dt(cur, dh, 0.5, dt_lev=dt, gamma=gamma)
                 S.srhd_fill_ghosts(cur, nb, 3, padded=pad)
-                S.srhd_fluid_step(pad, dt, dh, out=nxt, **kw)
+                S.srhd_fluid_step(pad, dt, dh, out=nxt, stats=stats, **kw)
+                cur, nxt = nxt, cur
+            for _ in range(args.warmup):
+                one(None)
+            cur.copy_(start)
             a0 = torch.cuda.Event(enable_timing=True)
             a1 = torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
             a0.record(stream)
             for _ in range(n_steps):
-                S.srhd_fill_ghosts(cur, nb, 3, padded=pad)
-                S.srhd_fluid_step(pad, dt, dh, out=nxt, stats=st, **kw)
-                cur, nxt = nxt, cur
+                one(st)
             a1.record(stream)
             torch.cuda.synchronize()
             ms = a0.elapsed_time(a1)
             return {"value": n_cells * n_steps / (ms * 1e-3), "ms_per_step": ms / n_steps,
-                    "stats": S.stats_dict(st)}
+                    "stats": S.stats_dict(st),
+                    "non_finite_cells": int((~torch.isfinite(cur)).any(dim=1).sum().item())}
         res["original_scheme"] = {
             "fp64": time_padded(args.steps, prec=S.PREC_FP64, energy=S.ENERGY_TOTAL),
             "fp32": time_padded(args.steps, prec=S.PREC_FP32, energy=S.ENERGY_TOTAL)}
-        res["polytropic_5_3"] = {
-            "fp64": time_padded(args.steps, prec=S.PREC_FP64, gamma=5.0 / 3.0),
-            "mixed": time_padded(args.steps, prec=S.PREC_MIXED, gamma=5.0 / 3.0)}
-        for k in ("original_scheme", "polytropic_5_3"):
-            print("# %s: %s" % (k, {m: "%.3g cell updates/s" % v["value"] for m, v in res[k].items()}),
-                  file=sys.stderr, flush=True)
+        # Gamma = 4/3, the hot limit of TM: the blast's source gas has Theta = 1e6
+        res["polytropic_4_3"] = {
+            "fp64": time_padded(args.steps, prec=S.PREC_FP64, gamma=4.0 / 3.0),
+            "mixed": time_padded(args.steps, prec=S.PREC_MIXED, gamma=4.0 / 3.0)}
+        for k in ("original_scheme", "polytropic_4_3"):
+            print("# %s: %s" % (k, {m: "%.3g cell updates/s, %d unphysical" % (v["value"], v["stats"]["n_unphysical"])
+                                     for m, v in res[k].items()}), file=sys.stderr, flush=True)
 
     # two AMR levels: 16^3 coarse patches with the central 8^3 refined (4,096 fine patches);
     # one cycle = CFL, coarse step, two fine sub-steps with coarse-to-fine ghosts, restriction,

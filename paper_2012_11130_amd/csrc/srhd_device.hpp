@@ -593,12 +593,16 @@ __device__ __forceinline__ double signal_smax(double rho, double ux, double uy, 
 }
 
 // ------------------------------------------------------------------------------ PLM
-// Hybrid van Leer / generalized minmod slope (zero at extrema).
+// Hybrid van Leer / generalized minmod slope (zero at extrema).  One-sided differences below
+// the smallest normal number count as zero: in FP32 the harmonic mean's division is a hardware
+// reciprocal, which flushes a denormal denominator to zero, and 0 * inf would make the slope NaN
+// (for any theta, 0 included).  In FP64 such differences give a zero slope either way.
 template <class T>
 __device__ __forceinline__ T limited_slope(T wl, T wc, T wr, T theta)
 {
+  constexpr T tiny = sizeof(T) == 4 ? T(FLT_MIN) : T(DBL_MIN);
   T dl = wc - wl, dr = wr - wc;
-  bool mono = (dl > T(0) && dr > T(0)) || (dl < T(0) && dr < T(0));
+  bool mono = (dl >= tiny && dr >= tiny) || (dl <= -tiny && dr <= -tiny);
   T vl = absT(dv(T(2) * dl * dr, dl + dr));
   T s = minT(vl, minT(theta * absT(dl), theta * absT(dr)));
   s = dl > T(0) ? s : -s;
