@@ -334,8 +334,10 @@ __device__ __forceinline__ T start_guess(T L, T m2, T k)
 // positive finite number or its Newton iteration fails and the analytic one converges);
 // otherwise the analytic guess is used directly.  The analytic guess is formed in G (a starting
 // point only: FP32 suffices where the result is consumed in FP32); one Newton loop serves both
-// starts.
-template <class T, class G = T, class E = EosTm>
+// starts.  The recovery of the primitives from the root (Eqs. 17, 8, 5a, 16, 18: no cancellation,
+// each a few correctly rounded or 1-ulp operations) runs in R, FP32 where the primitives are
+// consumed in FP32; L and the Newton iteration keep T.
+template <class T, class G = T, class R = T, class E = EosTm>
 __device__ __forceinline__ void invert_with_L(T D, T Mx, T My, T Mz, T L, T guess, bool have_guess,
                                               T tol, int max_iter, InvOut<T> &o, const E &eos = E())
 {
@@ -363,8 +365,20 @@ __device__ __forceinline__ void invert_with_L(T D, T Mx, T My, T Mz, T L, T gues
   }
   o.status = ok ? (fell_back ? ST_FALLBACK : ST_OK) : ST_NOCONV;
   o.iters = its;
-  if constexpr (poly) recover_poly(D, Mx, My, Mz, ht, k, o);
-  else recover(D, Mx, My, Mz, ht, o);
+  if constexpr (std::is_same<R, T>::value) {
+    if constexpr (poly) recover_poly(D, Mx, My, Mz, ht, k, o);
+    else recover(D, Mx, My, Mz, ht, o);
+  } else {
+    InvOut<R> r;
+    if constexpr (poly) recover_poly((R)D, (R)Mx, (R)My, (R)Mz, (R)ht, (R)k, r);
+    else recover((R)D, (R)Mx, (R)My, (R)Mz, (R)ht, r);
+    o.rho = r.rho;
+    o.ux = r.ux;
+    o.uy = r.uy;
+    o.uz = r.uz;
+    o.p = r.p;
+    o.ht = ht;
+  }
 }
 
 // ------------------------------------------------------------------------------ prim -> cons

@@ -96,7 +96,8 @@ __device__ __forceinline__ typename KEos<K>::type make_eos(const StepArgs &a)
   else return EosTm{};
 }
 
-// The analytic guess's type: FP32 whenever the bulk is FP32 (only a starting point), else I.
+// The analytic guess's type and the recovery's: FP32 whenever the bulk is FP32 (a starting point,
+// and primitives consumed in FP32), else I.
 template <class T, class I>
 using GuessT = typename std::conditional<sizeof(T) == 4, float, I>::type;
 
@@ -162,7 +163,7 @@ __device__ __forceinline__ bool invert_face(const Cons<T> &u, bool ok, double L,
 {
   I D = u.D, Mx = u.m[0], My = u.m[1], Mz = u.m[2];
   InvOut<I> o;
-  if (ok) invert_with_L<I, GuessT<T, I>>(D, Mx, My, Mz, (I)L, (I)guess, have_guess, (I)StepTol<T, I>::v, 30, o, eos);
+  if (ok) invert_with_L<I, GuessT<T, I>, GuessT<T, I>>(D, Mx, My, Mz, (I)L, (I)guess, have_guess, (I)StepTol<T, I>::v, 30, o, eos);
   else set_unphysical(o);
   w.rho = (T)o.rho;
   w.u[0] = (T)o.ux;
@@ -360,7 +361,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
       double guess = MLP ? mlp_guess(mlp, D, Mx, My, Mz, Et, (valid && adm) ? L : 0.0, consulted, ev) : -1.0;
       my_mlp += valid ? ev : 0u;
       if (!valid) continue;
-      if (adm) invert_with_L<I, GuessT<T, I>>((I)D, (I)Mx, (I)My, (I)Mz, (I)L, (I)guess, consulted, (I)StepTol<T, I>::v, 30, o, eos);
+      if (adm) invert_with_L<I, GuessT<T, I>, GuessT<T, I>>((I)D, (I)Mx, (I)My, (I)Mz, (I)L, (I)guess, consulted, (I)StepTol<T, I>::v, 30, o, eos);
       else set_unphysical(o);
       centre_bad |= o.status == ST_UNPHYSICAL;
       centre_unphys += o.status == ST_UNPHYSICAL;
@@ -505,7 +506,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
           for (int f = 0; f < 5; ++f) un[f] = park[f * NT];
         }
         if (ok_out)
-          invert_with_L<I, GuessT<T, I>>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)Lo, (I)guess, consulted,
+          invert_with_L<I, GuessT<T, I>, GuessT<T, I>>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)Lo, (I)guess, consulted,
                            (I)StepTol<T, I>::v, 30, w);
         else set_unphysical(w);
         my_iters += w.iters;
@@ -636,7 +637,7 @@ __global__ void __launch_bounds__(256) k_grid_prims(int64_t n_patch, const doubl
     unsigned int evals = 0;
     double guess = MLP ? mlp_guess<false>(mlp, u[0], u[512], u[1024], u[1536], u[2048], ok ? L : 0.0, consulted, evals) : -1.0;
     if (ok)
-      invert_with_L<I, GuessT<T, I>>((I)u[0], (I)u[512], (I)u[1024], (I)u[1536], (I)L, (I)guess, consulted,
+      invert_with_L<I, GuessT<T, I>, GuessT<T, I>>((I)u[0], (I)u[512], (I)u[1024], (I)u[1536], (I)L, (I)guess, consulted,
                        (I)StepTol<T, I>::v, 30, w);
     else set_unphysical(w);
     T *po = prims + pp * 5 * 512 + c;
