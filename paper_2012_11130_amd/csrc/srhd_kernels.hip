@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(kBlock) k_cons2prim(int64_t n, const T *__rest
     bool consulted = false;
     unsigned int evals = 0;
     T guess = T(-1);
-    if (MLP) guess = (T)mlp_guess<false>(mlp, D, Mx, My, Mz, Et, (in && adm) ? (double)L : 0.0, consulted, evals);
+    if (MLP) guess = (T)mlp_guess(mlp, D, Mx, My, Mz, Et, (in && adm) ? (double)L : 0.0, consulted, evals);
     if (!in) continue;
     InvOut<T> o;
     if (adm)

@@ -155,16 +155,24 @@ __device__ __forceinline__ bool face_L(const Cons<T> &u, double &L)
   return ok;
 }
 
-// Inversion of a face state in the inversion type I from its (exact, FP64) L.
-template <class I, class T, class E>
+// Inversion of a face state in the inversion type I from its (exact, FP64) L.  With a learned
+// guess (MLP) the wavefront takes the guess-free inversion unless one of its lanes has a guess:
+// that inversion is the analytic-guess build's code, with the supplied-guess start and its
+// fallback attempt compiled out.
+template <class I, bool MLP, class T, class E>
 __device__ __forceinline__ bool invert_face(const Cons<T> &u, bool ok, double L, Prim<T> &w,
                                             int &iters, int &status, double guess, bool have_guess,
                                             const E &eos)
 {
   I D = u.D, Mx = u.m[0], My = u.m[1], Mz = u.m[2];
   InvOut<I> o;
-  if (ok) invert_with_L<I, GuessT<T, I>, GuessT<T, I>>(D, Mx, My, Mz, (I)L, (I)guess, have_guess, (I)StepTol<T, I>::v, 30, o, eos);
-  else set_unphysical(o);
+  const bool any_guess = MLP && __any(have_guess);
+  if (ok) {
+    if (any_guess)
+      invert_with_L<I, GuessT<T, I>, GuessT<T, I>>(D, Mx, My, Mz, (I)L, (I)guess, have_guess, (I)StepTol<T, I>::v, 30, o, eos);
+    else
+      invert_with_L<I, GuessT<T, I>, GuessT<T, I>>(D, Mx, My, Mz, (I)L, (I)-1.0, false, (I)StepTol<T, I>::v, 30, o, eos);
+  } else set_unphysical(o);
   w.rho = (T)o.rho;
   w.u[0] = (T)o.ux;
   w.u[1] = (T)o.uy;
@@ -214,7 +222,7 @@ __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, in
   else ok = face_L(u, L);
   bool consulted = false;
   double guess = MLP ? mlp_guess(mlp, u.D, u.m[0], u.m[1], u.m[2], u.E, L, consulted, evals) : -1.0;
-  return invert_face<I>(u, ok, L, w, iters, status, guess, consulted, eos);
+  return invert_face<I, MLP>(u, ok, L, w, iters, status, guess, consulted, eos);
 }
 
 struct IfaceCount {
@@ -505,10 +513,16 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
 #pragma unroll
           for (int f = 0; f < 5; ++f) un[f] = park[f * NT];
         }
-        if (ok_out)
-          invert_with_L<I, GuessT<T, I>, GuessT<T, I>>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)Lo, (I)guess, consulted,
-                           (I)StepTol<T, I>::v, 30, w);
-        else set_unphysical(w);
+        // as in invert_face: the guess-free inversion unless a lane of the wavefront has a guess
+        const bool any_guess = MLP && __any(consulted);
+        if (ok_out) {
+          if (any_guess)
+            invert_with_L<I, GuessT<T, I>, GuessT<T, I>>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)Lo, (I)guess,
+                                                         consulted, (I)StepTol<T, I>::v, 30, w);
+          else
+            invert_with_L<I, GuessT<T, I>, GuessT<T, I>>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)Lo, (I)-1.0,
+                                                         false, (I)StepTol<T, I>::v, 30, w);
+        } else set_unphysical(w);
         my_iters += w.iters;
         my_inv += 1;
         my_nc += w.status == ST_NOCONV;
@@ -635,7 +649,7 @@ __global__ void __launch_bounds__(256) k_grid_prims(int64_t n_patch, const doubl
     bool ok = admissible(u[0], u[512], u[1024], u[1536], u[2048], DBL_EPSILON, L);
     bool consulted = false;
     unsigned int evals = 0;
-    double guess = MLP ? mlp_guess<false>(mlp, u[0], u[512], u[1024], u[1536], u[2048], ok ? L : 0.0, consulted, evals) : -1.0;
+    double guess = MLP ? mlp_guess(mlp, u[0], u[512], u[1024], u[1536], u[2048], ok ? L : 0.0, consulted, evals) : -1.0;
     if (ok)
       invert_with_L<I, GuessT<T, I>, GuessT<T, I>>((I)u[0], (I)u[512], (I)u[1024], (I)u[1536], (I)L, (I)guess, consulted,
                        (I)StepTol<T, I>::v, 30, w);
