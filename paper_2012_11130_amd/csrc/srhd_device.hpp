@@ -27,6 +27,16 @@ namespace srhd {
 // in float, where the bulk of the mixed-precision path tolerates FP32 rounding anyway.
 __device__ __forceinline__ double dv(double a, double b) { return a / b; }
 __device__ __forceinline__ float dv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+// Reciprocal to about 1 ulp where no correctly rounded quotient is needed: the hardware estimate
+// refined by two Newton-Raphson steps (6 instructions in FP64 against 11 for a division).  For
+// normal, finite arguments of moderate exponent only (no scaling of extreme exponents).
+__device__ __forceinline__ double rcp_nr(double b)
+{
+  double r = __builtin_amdgcn_rcp(b);
+  r = __builtin_fma(r, __builtin_fma(-b, r, 1.0), r);
+  return __builtin_fma(r, __builtin_fma(-b, r, 1.0), r);
+}
+__device__ __forceinline__ float rcp_nr(float b) { return __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double sq(double a) { return __builtin_sqrt(a); }
 __device__ __forceinline__ float sq(float a) { return __builtin_amdgcn_sqrtf(a); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -193,7 +203,7 @@ __device__ __forceinline__ bool newton_htilde(T L, T m2, T x, T tol, int max_ite
       // one division for 1/den, 1/q and 1/s: the product den q s^2 stays far inside the double
       // range for any iterate that can still converge (an overflow ends in a non-finite step)
       T den = T(5) * h + s, q = h2 + m2;
-      T inv = dv(T(1), den * q * s2);
+      T inv = rcp_nr(den * q * s2);
       iden = q * s2 * inv;
       iq = den * s2 * inv;
       is = s * den * q * inv;
@@ -212,7 +222,7 @@ __device__ __forceinline__ bool newton_htilde(T L, T m2, T x, T tol, int max_ite
     if constexpr (sizeof(T) == 8) last = th * th * h * m2 * iq * iq;
     else last = dv(th * th * r * (m2 * iq), h);
     T fp = T(2) * (h - th - h * dth + th * dth * r + last);
-    T dx = dv(f - L, fp);
+    T dx = (f - L) * rcp_nr(fp);
     x -= dx;
     if (!(x > T(0)) || !finiteT(x)) { iters = it; ht = x; return false; }
     if (absT(dx) <= tol * x) { iters = it; ht = x; return true; }
@@ -342,7 +352,7 @@ __device__ __forceinline__ void invert_with_L(T D, T Mx, T My, T Mz, T L, T gues
                                               T tol, int max_iter, InvOut<T> &o, const E &eos = E())
 {
   constexpr bool poly = std::is_same<E, EosPoly>::value;
-  T iD = dv(T(1), D);
+  T iD = rcp_nr(D);
   T mx = Mx * iD, my = My * iD, mz = Mz * iD;
   T m2 = mx * mx + my * my + mz * mz;
   T ht;
