@@ -29,7 +29,10 @@ __device__ __forceinline__ double dv(double a, double b) { return a / b; }
 __device__ __forceinline__ float dv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 // Reciprocal to about 1 ulp where no correctly rounded quotient is needed: the hardware estimate
 // refined by two Newton-Raphson steps (6 instructions in FP64 against 11 for a division).  For
-// normal, finite arguments of moderate exponent only (no scaling of extreme exponents).
+// normal, finite arguments of moderate exponent only (no scaling of extreme exponents).  The
+// inversion uses it with FAST: in the FP32-bulk gather-layout and VL step kernels, where it
+// measures faster (in the padded kernels the compiler's schedule around it costs registers and
+// occupancy; FP64 keeps the division so that both layouts give the same bits).
 __device__ __forceinline__ double rcp_nr(double b)
 {
   double r = __builtin_amdgcn_rcp(b);
@@ -189,7 +192,7 @@ __device__ __forceinline__ T guess_analytic(T L, T m2)
 // f is increasing and convex, so from any positive start the iterates stay positive and
 // converge quadratically; the loop stops once the applied step is below tol * ht, which
 // leaves an error of order tol^2.  Returns false on a non-finite iterate or after max_iter.
-template <class T>
+template <class T, bool FAST = false>
 __device__ __forceinline__ bool newton_htilde(T L, T m2, T x, T tol, int max_iter, T &ht,
                                               int &iters)
 {
@@ -203,7 +206,7 @@ __device__ __forceinline__ bool newton_htilde(T L, T m2, T x, T tol, int max_ite
       // one division for 1/den, 1/q and 1/s: the product den q s^2 stays far inside the double
       // range for any iterate that can still converge (an overflow ends in a non-finite step)
       T den = T(5) * h + s, q = h2 + m2;
-      T inv = rcp_nr(den * q * s2);
+      T inv = FAST ? rcp_nr(den * q * s2) : dv(T(1), den * q * s2);
       iden = q * s2 * inv;
       iq = den * s2 * inv;
       is = s * den * q * inv;
@@ -222,7 +225,7 @@ __device__ __forceinline__ bool newton_htilde(T L, T m2, T x, T tol, int max_ite
     if constexpr (sizeof(T) == 8) last = th * th * h * m2 * iq * iq;
     else last = dv(th * th * r * (m2 * iq), h);
     T fp = T(2) * (h - th - h * dth + th * dth * r + last);
-    T dx = (f - L) * rcp_nr(fp);
+    T dx = FAST ? (f - L) * rcp_nr(fp) : dv(f - L, fp);
     x -= dx;
     if (!(x > T(0)) || !finiteT(x)) { iters = it; ht = x; return false; }
     if (absT(dx) <= tol * x) { iters = it; ht = x; return true; }
@@ -347,12 +350,13 @@ __device__ __forceinline__ T start_guess(T L, T m2, T k)
 // starts.  The recovery of the primitives from the root (Eqs. 17, 8, 5a, 16, 18: no cancellation,
 // each a few correctly rounded or 1-ulp operations) runs in R, FP32 where the primitives are
 // consumed in FP32; L and the Newton iteration keep T.
-template <class T, class G = T, class R = T, class E = EosTm>
+template <class T, class G = T, class R = T, bool FAST = false, class E = EosTm>
 __device__ __forceinline__ void invert_with_L(T D, T Mx, T My, T Mz, T L, T guess, bool have_guess,
                                               T tol, int max_iter, InvOut<T> &o, const E &eos = E())
 {
   constexpr bool poly = std::is_same<E, EosPoly>::value;
-  T iD = rcp_nr(D);
+  // (the polytropic build keeps the division: the reciprocal's registers cost it occupancy)
+  T iD = (FAST && !poly) ? rcp_nr(D) : dv(T(1), D);
   T mx = Mx * iD, my = My * iD, mz = Mz * iD;
   T m2 = mx * mx + my * my + mz * mz;
   T ht;
@@ -367,7 +371,7 @@ __device__ __forceinline__ void invert_with_L(T D, T Mx, T My, T Mz, T L, T gues
   for (int a = 0; a < 2; ++a) {
     int it = 0;
     if constexpr (poly) ok = newton_htilde_poly(L, m2, x0, k, tol, max_iter, ht, it);
-    else ok = newton_htilde(L, m2, x0, tol, max_iter, ht, it);
+    else ok = newton_htilde<T, FAST>(L, m2, x0, tol, max_iter, ht, it);
     its += it;
     if (ok || fell_back || !have_guess) break;
     fell_back = true;                       // the supplied guess failed: restart from App. A

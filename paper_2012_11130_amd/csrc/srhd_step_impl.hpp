@@ -159,7 +159,7 @@ __device__ __forceinline__ bool face_L(const Cons<T> &u, double &L)
 // guess (MLP) the wavefront takes the guess-free inversion unless one of its lanes has a guess:
 // that inversion is the analytic-guess build's code, with the supplied-guess start and its
 // fallback attempt compiled out.
-template <class I, bool MLP, class T, class E>
+template <class I, bool MLP, bool FAST, class T, class E>
 __device__ __forceinline__ bool invert_face(const Cons<T> &u, bool ok, double L, Prim<T> &w,
                                             int &iters, int &status, double guess, bool have_guess,
                                             const E &eos)
@@ -169,9 +169,9 @@ __device__ __forceinline__ bool invert_face(const Cons<T> &u, bool ok, double L,
   const bool any_guess = MLP && __any(have_guess);
   if (ok) {
     if (any_guess)
-      invert_with_L<I, GuessT<T, I>, GuessT<T, I>>(D, Mx, My, Mz, (I)L, (I)guess, have_guess, (I)StepTol<T, I>::v, 30, o, eos);
+      invert_with_L<I, GuessT<T, I>, GuessT<T, I>, FAST>(D, Mx, My, Mz, (I)L, (I)guess, have_guess, (I)StepTol<T, I>::v, 30, o, eos);
     else
-      invert_with_L<I, GuessT<T, I>, GuessT<T, I>>(D, Mx, My, Mz, (I)L, (I)-1.0, false, (I)StepTol<T, I>::v, 30, o, eos);
+      invert_with_L<I, GuessT<T, I>, GuessT<T, I>, FAST>(D, Mx, My, Mz, (I)L, (I)-1.0, false, (I)StepTol<T, I>::v, 30, o, eos);
   } else set_unphysical(o);
   w.rho = (T)o.rho;
   w.u[0] = (T)o.ux;
@@ -185,7 +185,7 @@ __device__ __forceinline__ bool invert_face(const Cons<T> &u, bool ok, double L,
 
 // Face state of cell (i, j, k) on side `side` (0: minus, 1: plus) of direction d: PLM along d,
 // prim -> cons, plus the cell's half-step correction, then the inversion.
-template <int d, int K, class I, class T>
+template <int d, int K, class I, bool FAST, class T>
 __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, int j, int k,
                                            T theta, const MlpDev &mlp, Prim<T> &w, Cons<T> &u,
                                            int &iters, int &status, unsigned int &evals,
@@ -222,7 +222,7 @@ __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, in
   else ok = face_L(u, L);
   bool consulted = false;
   double guess = MLP ? mlp_guess(mlp, u.D, u.m[0], u.m[1], u.m[2], u.E, L, consulted, evals) : -1.0;
-  return invert_face<I, MLP>(u, ok, L, w, iters, status, guess, consulted, eos);
+  return invert_face<I, MLP, FAST>(u, ok, L, w, iters, status, guess, consulted, eos);
 }
 
 struct IfaceCount {
@@ -231,7 +231,7 @@ struct IfaceCount {
 
 // Flux through interface r of direction d (between cells c-1 and c along d, interfaces numbered
 // with x fastest, then y, then z), written to the ring slot of d.
-template <int d, int K, class I, class T>
+template <int d, int K, class I, bool FAST, class T>
 __device__ __forceinline__ bool interface_flux(Tile<T> &s, int r, T theta, int solver,
                                                const MlpDev &mlp, IfaceCount &cnt,
                                                const typename KEos<K>::type &eos)
@@ -247,8 +247,8 @@ __device__ __forceinline__ bool interface_flux(Tile<T> &s, int r, T theta, int s
   Prim<T> wl, wr;
   Cons<T> ul, ur;
   int itl, itr, stl, str;
-  bool okl = face_state<d, K, I>(s, 1, cl[0], cl[1], cl[2], theta, mlp, wl, ul, itl, stl, cnt.mlp, eos);
-  bool okr = face_state<d, K, I>(s, 0, cr[0], cr[1], cr[2], theta, mlp, wr, ur, itr, str, cnt.mlp, eos);
+  bool okl = face_state<d, K, I, FAST>(s, 1, cl[0], cl[1], cl[2], theta, mlp, wl, ul, itl, stl, cnt.mlp, eos);
+  bool okr = face_state<d, K, I, FAST>(s, 0, cr[0], cr[1], cr[2], theta, mlp, wr, ur, itr, str, cnt.mlp, eos);
   cnt.iters += itl + itr;
   cnt.inv += 2;
   cnt.fb += (stl == ST_FALLBACK) + (str == ST_FALLBACK);
@@ -443,9 +443,9 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
         int r = qi - d * NIF;
         IfaceCount ic = {0, 0, 0, 0, 0, 0};
         bool ok;
-        if (d == 0) ok = interface_flux<0, K, I>(s, r, theta, a.riemann, mlp, ic, eos);
-        else if (d == 1) ok = interface_flux<1, K, I>(s, r, theta, a.riemann, mlp, ic, eos);
-        else ok = interface_flux<2, K, I>(s, r, theta, a.riemann, mlp, ic, eos);
+        if (d == 0) ok = interface_flux<0, K, I, GATHER && sizeof(T) == 4>(s, r, theta, a.riemann, mlp, ic, eos);
+        else if (d == 1) ok = interface_flux<1, K, I, GATHER && sizeof(T) == 4>(s, r, theta, a.riemann, mlp, ic, eos);
+        else ok = interface_flux<2, K, I, GATHER && sizeof(T) == 4>(s, r, theta, a.riemann, mlp, ic, eos);
         fail |= !ok;
         my_iters += ic.iters;
         my_mlp += ic.mlp;
@@ -517,10 +517,10 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
         const bool any_guess = MLP && __any(consulted);
         if (ok_out) {
           if (any_guess)
-            invert_with_L<I, GuessT<T, I>, GuessT<T, I>>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)Lo, (I)guess,
+            invert_with_L<I, GuessT<T, I>, GuessT<T, I>, GATHER && sizeof(T) == 4>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)Lo, (I)guess,
                                                          consulted, (I)StepTol<T, I>::v, 30, w);
           else
-            invert_with_L<I, GuessT<T, I>, GuessT<T, I>>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)Lo, (I)-1.0,
+            invert_with_L<I, GuessT<T, I>, GuessT<T, I>, GATHER && sizeof(T) == 4>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)Lo, (I)-1.0,
                                                          false, (I)StepTol<T, I>::v, 30, w);
         } else set_unphysical(w);
         my_iters += w.iters;
@@ -651,7 +651,7 @@ __global__ void __launch_bounds__(256) k_grid_prims(int64_t n_patch, const doubl
     unsigned int evals = 0;
     double guess = MLP ? mlp_guess(mlp, u[0], u[512], u[1024], u[1536], u[2048], ok ? L : 0.0, consulted, evals) : -1.0;
     if (ok)
-      invert_with_L<I, GuessT<T, I>, GuessT<T, I>>((I)u[0], (I)u[512], (I)u[1024], (I)u[1536], (I)L, (I)guess, consulted,
+      invert_with_L<I, GuessT<T, I>, GuessT<T, I>, sizeof(T) == 4>((I)u[0], (I)u[512], (I)u[1024], (I)u[1536], (I)L, (I)guess, consulted,
                        (I)StepTol<T, I>::v, 30, w);
     else set_unphysical(w);
     T *po = prims + pp * 5 * 512 + c;

@@ -246,7 +246,7 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
     double L;
     InvOut<I> o;
     if (admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L))
-      invert_with_L<I, GuessT<T, I>, GuessT<T, I>>((I)D, (I)Mx, (I)My, (I)Mz, (I)L, (I)-1.0, false,
+      invert_with_L<I, GuessT<T, I>, GuessT<T, I>, sizeof(T) == 4>((I)D, (I)Mx, (I)My, (I)Mz, (I)L, (I)-1.0, false,
                                      (I)StepTol<T, I>::v, 30, o);
     else set_unphysical(o);
     bad_in += o.status == ST_UNPHYSICAL;
@@ -306,7 +306,7 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
         double L;
         InvOut<I> o;
         if (admissible(u[0], u[1], u[2], u[3], u[4], DBL_EPSILON, L))
-          invert_with_L<I, GuessT<T, I>, GuessT<T, I>>((I)u[0], (I)u[1], (I)u[2], (I)u[3], (I)L, (I)-1.0, false,
+          invert_with_L<I, GuessT<T, I>, GuessT<T, I>, sizeof(T) == 4>((I)u[0], (I)u[1], (I)u[2], (I)u[3], (I)L, (I)-1.0, false,
                                          (I)StepTol<T, I>::v, 30, o);
         else set_unphysical(o);
         my_iters += o.iters;
@@ -364,7 +364,7 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
           double L;
           InvOut<I> o;
           if (admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L))
-            invert_with_L<I, GuessT<T, I>, GuessT<T, I>>((I)D, (I)Mx, (I)My, (I)Mz, (I)L, (I)-1.0, false,
+            invert_with_L<I, GuessT<T, I>, GuessT<T, I>, sizeof(T) == 4>((I)D, (I)Mx, (I)My, (I)Mz, (I)L, (I)-1.0, false,
                                            (I)StepTol<T, I>::v, 30, o);
           else set_unphysical(o);
           my_iters += o.iters;
