@@ -498,14 +498,14 @@ __device__ __forceinline__ void signal_speeds(const Prim<T> &w, T &lm, T &lp, co
 {
   constexpr int a1 = d == 0 ? 1 : 0, a2 = d == 2 ? 1 : 2;
   T cs2 = sound_speed2(dv(w.p, w.rho), eos);
-  T cs = sq(cs2);
   T Ud = w.u[d];
   T Up2 = w.u[a1] * w.u[a1] + w.u[a2] * w.u[a2];
   T U2 = Ud * Ud + Up2;
   T gam = sq(T(1) + U2);
   T a = T(1) - cs2;
   T iden = dv(T(1), T(1) + U2 * a);
-  T s = cs * sq(T(1) + Up2 * a);
+  // cs sqrt(1 + Up^2 a) as one square root in FP32
+  T s = sizeof(T) == 4 ? sq(cs2 * (T(1) + Up2 * a)) : sq(cs2) * sq(T(1) + Up2 * a);
   T c = gam * Ud * a;
   lm = (c - s) * iden;
   lp = (c + s) * iden;
@@ -618,6 +618,20 @@ __device__ __forceinline__ double signal_smax(double rho, double ux, double uy, 
   double gam = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
   double Umax = gs * (fabs(ux) + fabs(uy) + fabs(uz)) + 3.0 * gam * Us;
   return Umax / sqrt(1.0 + Umax * Umax);
+}
+
+// The same in the arithmetic of T, for primitives stored in FP32: the FP32-bulk gather steps hand
+// the next step its S_max from their FP32 output primitives (a time step needs no more than FP32
+// accuracy; the maximum over cells stays exact and order independent).
+template <class T, class E = EosTm>
+__device__ __forceinline__ T signal_smax_t(T rho, T ux, T uy, T uz, T p, const E &eos = E())
+{
+  T cs2 = sound_speed2(dv(p, rho), eos);
+  T gs = dv(T(1), sq(T(1) - cs2));
+  T Us = sq(cs2) * gs;
+  T gam = sq(T(1) + ux * ux + uy * uy + uz * uz);
+  T Umax = gs * (absT(ux) + absT(uy) + absT(uz)) + T(3) * gam * Us;
+  return dv(Umax, sq(T(1) + Umax * Umax));
 }
 
 // ------------------------------------------------------------------------------ PLM

@@ -532,8 +532,12 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
         po[1024] = (T)w.uy;
         po[1536] = (T)w.uz;
         po[2048] = (T)w.p;
-        double sm = ok_out ? signal_smax((double)w.rho, (double)w.ux, (double)w.uy, (double)w.uz,
-                                         (double)w.p) : 0.0;
+        double sm = 0.0;
+        if constexpr (sizeof(T) == 4) {
+          if (ok_out) sm = (double)signal_smax_t<T>((T)w.rho, (T)w.ux, (T)w.uy, (T)w.uz, (T)w.p);
+        } else {
+          if (ok_out) sm = signal_smax((double)w.rho, (double)w.ux, (double)w.uy, (double)w.uz, (double)w.p);
+        }
         sm = wave_max(sm);
         if ((tid & 63) == 0) s.red[tid >> 6] = sm;
         __syncthreads();
@@ -660,7 +664,12 @@ __global__ void __launch_bounds__(256) k_grid_prims(int64_t n_patch, const doubl
     po[1024] = (T)w.uy;
     po[1536] = (T)w.uz;
     po[2048] = (T)w.p;
-    if (ok) vmax = fmax(vmax, signal_smax((double)w.rho, (double)w.ux, (double)w.uy, (double)w.uz, (double)w.p));
+    // S_max as the step's own output does it (FP32 from the stored primitives with an FP32 bulk)
+    if constexpr (sizeof(T) == 4) {
+      if (ok) vmax = fmax(vmax, (double)signal_smax_t<T>((T)w.rho, (T)w.ux, (T)w.uy, (T)w.uz, (T)w.p));
+    } else {
+      if (ok) vmax = fmax(vmax, signal_smax((double)w.rho, (double)w.ux, (double)w.uy, (double)w.uz, (double)w.p));
+    }
   }
   vmax = wave_max(vmax);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = vmax;
