@@ -241,6 +241,7 @@ template <class T>
 struct InvOut {
   T rho, ux, uy, uz, p;        // primitive variables
   T ht;                        // reduced enthalpy (the root)
+  T gam, igam, cs2;            // gamma, 1 / gamma and c_s^2 (Eq. 14) of the result: FP32 TM recovery only
   int status;                  // SRHD_ST_*
   int iters;                   // Newton iterations (both guesses)
 };
@@ -262,8 +263,16 @@ __device__ __forceinline__ void recover(T D, T Mx, T My, T Mz, T ht, InvOut<T> &
     o.rho = D * den * inv;
     o.p = o.rho * (T(2) * ht * (ht + T(2)) * gam * inv);
   } else {
-    o.rho = dv(D, gam);
-    o.p = o.rho * theta_of_htilde(ht);
+    // FP32: also keep gamma, 1 / gamma and c_s^2 (Eq. 14 from Theta and h = 1 + ht), which the
+    // Riemann solver of a face state needs
+    const T igam = dv(T(1), gam);
+    const T th = theta_of_htilde(ht);
+    const T h = T(1) + ht;
+    o.rho = D * igam;
+    o.p = o.rho * th;
+    o.gam = gam;
+    o.igam = igam;
+    o.cs2 = dv(th * (T(5) * h - T(8) * th), T(3) * h * (h - th));
   }
   o.ht = ht;
 }
@@ -273,6 +282,7 @@ __device__ __forceinline__ void set_unphysical(InvOut<T> &o)
 {
   const T nan = T(__builtin_nan(""));
   o.rho = o.ux = o.uy = o.uz = o.p = o.ht = nan;
+  o.gam = o.igam = o.cs2 = nan;
   o.status = ST_UNPHYSICAL;
   o.iters = 0;
 }
@@ -392,6 +402,9 @@ __device__ __forceinline__ void invert_with_L(T D, T Mx, T My, T Mz, T L, T gues
     o.uz = r.uz;
     o.p = r.p;
     o.ht = ht;
+    o.gam = r.gam;
+    o.igam = r.igam;
+    o.cs2 = r.cs2;
   }
 }
 
@@ -473,13 +486,26 @@ __device__ __forceinline__ bool admissible_total(I D, I Mx, I My, I Mz, I E, dou
 // ------------------------------------------------------------------------------ fluxes
 // The direction d is a template parameter so that every component index is a constant.
 
+// What the Riemann solvers need of each side besides the primitives: gamma, 1 / gamma and c_s^2.
+template <class T>
+struct FaceAux { T gam, igam, cs2; };
+
+template <class T, class E = EosTm>
+__device__ __forceinline__ FaceAux<T> face_aux(const Prim<T> &w, const E &eos = E())
+{
+  FaceAux<T> x;
+  x.gam = sq(T(1) + w.u[0] * w.u[0] + w.u[1] * w.u[1] + w.u[2] * w.u[2]);
+  x.igam = dv(T(1), x.gam);
+  x.cs2 = sound_speed2(dv(w.p, w.rho), eos);
+  return x;
+}
+
 // Physical flux along d (Eqs. 4a, 4b, 7) with v_d = U_d / gamma.  TOT: the original scheme, whose
 // energy variable E has the flux (E + p) v_d = M_d.
 template <int d, bool TOT = false, class T>
-__device__ __forceinline__ Cons<T> phys_flux(const Prim<T> &w, const Cons<T> &u)
+__device__ __forceinline__ Cons<T> phys_flux(const Prim<T> &w, const Cons<T> &u, T igam)
 {
-  T gam = sq(T(1) + w.u[0] * w.u[0] + w.u[1] * w.u[1] + w.u[2] * w.u[2]);
-  T v = dv(w.u[d], gam);
+  T v = w.u[d] * igam;
   Cons<T> F;
   F.D = u.D * v;
   F.m[0] = u.m[0] * v;
@@ -490,18 +516,22 @@ __device__ __forceinline__ Cons<T> phys_flux(const Prim<T> &w, const Cons<T> &u)
   else F.E = (u.E + w.p) * v;
   return F;
 }
+template <int d, bool TOT = false, class T>
+__device__ __forceinline__ Cons<T> phys_flux(const Prim<T> &w, const Cons<T> &u)
+{
+  return phys_flux<d, TOT>(w, u, dv(T(1), sq(T(1) + w.u[0] * w.u[0] + w.u[1] * w.u[1] + w.u[2] * w.u[2])));
+}
 
 // Signal speeds along d in four-velocity form:
 // lambda_pm = [gamma U_d (1 - cs^2) +- cs sqrt(1 + U_perp^2 (1 - cs^2))] / (1 + U^2 (1 - cs^2)).
-template <int d, class T, class E = EosTm>
-__device__ __forceinline__ void signal_speeds(const Prim<T> &w, T &lm, T &lp, const E &eos = E())
+template <int d, class T>
+__device__ __forceinline__ void signal_speeds(const Prim<T> &w, const FaceAux<T> &x, T &lm, T &lp)
 {
   constexpr int a1 = d == 0 ? 1 : 0, a2 = d == 2 ? 1 : 2;
-  T cs2 = sound_speed2(dv(w.p, w.rho), eos);
+  const T cs2 = x.cs2, gam = x.gam;
   T Ud = w.u[d];
   T Up2 = w.u[a1] * w.u[a1] + w.u[a2] * w.u[a2];
   T U2 = Ud * Ud + Up2;
-  T gam = sq(T(1) + U2);
   T a = T(1) - cs2;
   T iden = dv(T(1), T(1) + U2 * a);
   // cs sqrt(1 + Up^2 a) as one square root in FP32
@@ -510,18 +540,24 @@ __device__ __forceinline__ void signal_speeds(const Prim<T> &w, T &lm, T &lp, co
   lm = (c - s) * iden;
   lp = (c + s) * iden;
 }
+template <int d, class T, class E = EosTm>
+__device__ __forceinline__ void signal_speeds(const Prim<T> &w, T &lm, T &lp, const E &eos = E())
+{
+  signal_speeds<d>(w, face_aux(w, eos), lm, lp);
+}
 
 // HLLE: HLL flux with S_L^- = min(S_L, 0), S_R^+ = max(S_R, 0).  ul, ur are the conserved
 // variables of wl, wr (the states the primitives were inverted from, where the caller has them).
 // TOT: the original scheme's variables (total energy E).
-template <int d, bool TOT = false, class T, class E = EosTm>
+// xl, xr: gamma, 1 / gamma and c_s^2 of the two sides.
+template <int d, bool TOT = false, class T>
 __device__ __forceinline__ Cons<T> hlle(const Prim<T> &wl, const Prim<T> &wr, const Cons<T> &ul,
-                                        const Cons<T> &ur, const E &eos = E())
+                                        const Cons<T> &ur, const FaceAux<T> &xl, const FaceAux<T> &xr)
 {
-  Cons<T> fl = phys_flux<d, TOT>(wl, ul), fr = phys_flux<d, TOT>(wr, ur);
+  Cons<T> fl = phys_flux<d, TOT>(wl, ul, xl.igam), fr = phys_flux<d, TOT>(wr, ur, xr.igam);
   T lmL, lpL, lmR, lpR;
-  signal_speeds<d>(wl, lmL, lpL, eos);
-  signal_speeds<d>(wr, lmR, lpR, eos);
+  signal_speeds<d>(wl, xl, lmL, lpL);
+  signal_speeds<d>(wr, xr, lmR, lpR);
   T sl = minT(minT(lmL, lmR), T(0));
   T sr = maxT(maxT(lpL, lpR), T(0));
   T inv = dv(T(1), sr - sl);
@@ -532,6 +568,12 @@ __device__ __forceinline__ Cons<T> hlle(const Prim<T> &wl, const Prim<T> &wr, co
   for (int k = 0; k < 3; ++k) F.m[k] = (sr * fl.m[k] - sl * fr.m[k] + srl * (ur.m[k] - ul.m[k])) * inv;
   F.E = (sr * fl.E - sl * fr.E + srl * (ur.E - ul.E)) * inv;
   return F;
+}
+template <int d, bool TOT = false, class T, class E = EosTm>
+__device__ __forceinline__ Cons<T> hlle(const Prim<T> &wl, const Prim<T> &wr, const Cons<T> &ul,
+                                        const Cons<T> &ur, const E &eos = E())
+{
+  return hlle<d, TOT>(wl, wr, ul, ur, face_aux(wl, eos), face_aux(wr, eos));
 }
 
 template <class T>
@@ -552,14 +594,14 @@ __device__ __forceinline__ Cons<T> sel(bool c, const Cons<T> &a, const Cons<T> &
 // Et* = [Et (S - v) + p* l* - p v] / (S - l*), which carries no rest-mass cancellation.
 // TOT: the original scheme, whose energy slot already holds E (and its flux M_d); its star state
 // E* takes the same form.
-template <int d, bool TOT = false, class T, class E = EosTm>
+template <int d, bool TOT = false, class T>
 __device__ __forceinline__ Cons<T> hllc(const Prim<T> &wl, const Prim<T> &wr, const Cons<T> &ul,
-                                        const Cons<T> &ur, const E &eos = E())
+                                        const Cons<T> &ur, const FaceAux<T> &xl, const FaceAux<T> &xr)
 {
-  Cons<T> fl = phys_flux<d, TOT>(wl, ul), fr = phys_flux<d, TOT>(wr, ur);
+  Cons<T> fl = phys_flux<d, TOT>(wl, ul, xl.igam), fr = phys_flux<d, TOT>(wr, ur, xr.igam);
   T lmL, lpL, lmR, lpR;
-  signal_speeds<d>(wl, lmL, lpL, eos);
-  signal_speeds<d>(wr, lmR, lpR, eos);
+  signal_speeds<d>(wl, xl, lmL, lpL);
+  signal_speeds<d>(wr, xr, lmR, lpR);
   T sl = minT(lmL, lmR);
   T sr = maxT(lpL, lpR);
   T inv = dv(T(1), sr - sl);
@@ -579,13 +621,8 @@ __device__ __forceinline__ Cons<T> hllc(const Prim<T> &wl, const Prim<T> &wr, co
   Cons<T> u = sel(left, ul, ur);
   Cons<T> f = sel(left, fl, fr);
   T S = left ? sl : sr;
-  T wu0 = left ? wl.u[0] : wr.u[0];
-  T wu1 = left ? wl.u[1] : wr.u[1];
-  T wu2 = left ? wl.u[2] : wr.u[2];
   T wp = left ? wl.p : wr.p;
-  T wud = d == 0 ? wu0 : (d == 1 ? wu1 : wu2);
-  T gam = sq(T(1) + wu0 * wu0 + wu1 * wu1 + wu2 * wu2);
-  T v = dv(wud, gam);
+  T v = (left ? wl.u[d] : wr.u[d]) * (left ? xl.igam : xr.igam);
   T a = S - v;
   T iS = dv(T(1), S - ls);
   Cons<T> us;
@@ -603,6 +640,12 @@ __device__ __forceinline__ Cons<T> hllc(const Prim<T> &wl, const Prim<T> &wr, co
   F = sel(sl >= T(0), fl, F);
   F = sel(sr <= T(0), fr, F);
   return F;
+}
+template <int d, bool TOT = false, class T, class E = EosTm>
+__device__ __forceinline__ Cons<T> hllc(const Prim<T> &wl, const Prim<T> &wr, const Cons<T> &ul,
+                                        const Cons<T> &ur, const E &eos = E())
+{
+  return hllc<d, TOT>(wl, wr, ul, ur, face_aux(wl, eos), face_aux(wr, eos));
 }
 
 // ------------------------------------------------------------------------------ CFL

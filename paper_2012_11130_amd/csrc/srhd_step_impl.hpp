@@ -159,10 +159,12 @@ __device__ __forceinline__ bool face_L(const Cons<T> &u, double &L)
 // guess (MLP) the wavefront takes the guess-free inversion unless one of its lanes has a guess:
 // that inversion is the analytic-guess build's code, with the supplied-guess start and its
 // fallback attempt compiled out.
+// x receives gamma, 1 / gamma and c_s^2 of the face state for the Riemann solver: from the FP32
+// TM recovery, which has them, else formed from w.
 template <class I, bool MLP, bool FAST, class T, class E>
 __device__ __forceinline__ bool invert_face(const Cons<T> &u, bool ok, double L, Prim<T> &w,
-                                            int &iters, int &status, double guess, bool have_guess,
-                                            const E &eos)
+                                            FaceAux<T> &x, int &iters, int &status, double guess,
+                                            bool have_guess, const E &eos)
 {
   I D = u.D, Mx = u.m[0], My = u.m[1], Mz = u.m[2];
   InvOut<I> o;
@@ -178,6 +180,13 @@ __device__ __forceinline__ bool invert_face(const Cons<T> &u, bool ok, double L,
   w.u[1] = (T)o.uy;
   w.u[2] = (T)o.uz;
   w.p = (T)o.p;
+  if constexpr (sizeof(T) == 4 && std::is_same<E, EosTm>::value) {
+    x.gam = (T)o.gam;
+    x.igam = (T)o.igam;
+    x.cs2 = (T)o.cs2;
+  } else {
+    x = face_aux(w, eos);
+  }
   iters = o.iters;
   status = o.status;
   return ok;
@@ -188,7 +197,7 @@ __device__ __forceinline__ bool invert_face(const Cons<T> &u, bool ok, double L,
 template <int d, int K, class I, bool FAST, class T>
 __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, int j, int k,
                                            T theta, const MlpDev &mlp, Prim<T> &w, Cons<T> &u,
-                                           int &iters, int &status, unsigned int &evals,
+                                           FaceAux<T> &x, int &iters, int &status, unsigned int &evals,
                                            const typename KEos<K>::type &eos)
 {
   constexpr int sd = d == 0 ? 1 : (d == 1 ? BX : BX * BX);
@@ -222,7 +231,7 @@ __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, in
   else ok = face_L(u, L);
   bool consulted = false;
   double guess = MLP ? mlp_guess(mlp, u.D, u.m[0], u.m[1], u.m[2], u.E, L, consulted, evals) : -1.0;
-  return invert_face<I, MLP, FAST>(u, ok, L, w, iters, status, guess, consulted, eos);
+  return invert_face<I, MLP, FAST>(u, ok, L, w, x, iters, status, guess, consulted, eos);
 }
 
 struct IfaceCount {
@@ -246,9 +255,10 @@ __device__ __forceinline__ bool interface_flux(Tile<T> &s, int r, T theta, int s
   cl[d] -= 1;
   Prim<T> wl, wr;
   Cons<T> ul, ur;
+  FaceAux<T> xl, xr;
   int itl, itr, stl, str;
-  bool okl = face_state<d, K, I, FAST>(s, 1, cl[0], cl[1], cl[2], theta, mlp, wl, ul, itl, stl, cnt.mlp, eos);
-  bool okr = face_state<d, K, I, FAST>(s, 0, cr[0], cr[1], cr[2], theta, mlp, wr, ur, itr, str, cnt.mlp, eos);
+  bool okl = face_state<d, K, I, FAST>(s, 1, cl[0], cl[1], cl[2], theta, mlp, wl, ul, xl, itl, stl, cnt.mlp, eos);
+  bool okr = face_state<d, K, I, FAST>(s, 0, cr[0], cr[1], cr[2], theta, mlp, wr, ur, xr, itr, str, cnt.mlp, eos);
   cnt.iters += itl + itr;
   cnt.inv += 2;
   cnt.fb += (stl == ST_FALLBACK) + (str == ST_FALLBACK);
@@ -257,7 +267,7 @@ __device__ __forceinline__ bool interface_flux(Tile<T> &s, int r, T theta, int s
   // the face states' conserved variables are the ones just inverted: no round trip through
   // prim -> cons
   constexpr bool TOT = K == KV_TOTAL;
-  Cons<T> F = solver == SRHD_HLLE ? hlle<d, TOT>(wl, wr, ul, ur, eos) : hllc<d, TOT>(wl, wr, ul, ur, eos);
+  Cons<T> F = solver == SRHD_HLLE ? hlle<d, TOT>(wl, wr, ul, ur, xl, xr) : hllc<d, TOT>(wl, wr, ul, ur, xl, xr);
   constexpr int slot = d & 1;
   s.F[slot][0][r] = F.D;
   s.F[slot][1][r] = F.m[0];
