@@ -118,6 +118,31 @@ __device__ __forceinline__ double lhs_L_from_f32(float D, float Mx, float My, fl
   return N / (d * d);
 }
 
+// The same for a wavefront of face states whose results are consumed in FP32: the five exact
+// products summed plainly, with relative error at most 4 u cond (u = 2^-53, cond = sum |t_i| /
+// |sum t_i|), where every lane has cond <= 2^10 (so below 5e-13: under the FP32 resolution of
+// what the inversion returns); the compensated sum otherwise.  A gas at rest has cond = 1; a
+// cold, fast gas has cond ~ U^2 / Theta and takes the compensated sum.  All lanes must call it.
+__device__ __forceinline__ double lhs_L_from_f32_adaptive(float D, float Mx, float My, float Mz, float Et)
+{
+#pragma clang fp contract(off)
+  double d = D, e = Et, x = Mx, y = My, z = Mz;
+  double t[5];
+  t[0] = e * e;
+  t[1] = 2.0 * e * d;
+  t[2] = -(x * x);
+  t[3] = -(y * y);
+  t[4] = -(z * z);
+  const double pos = t[0] + t[1], neg = (t[2] + t[3]) + t[4];
+  double N = pos + neg;
+  const bool cheap = __builtin_fabs(pos) + __builtin_fabs(neg) <= 1024.0 * __builtin_fabs(N);
+  if (__any(!cheap)) {
+    const double Nk = sum_k3(t);
+    N = cheap ? N : Nk;
+  }
+  return N / (d * d);
+}
+
 // ------------------------------------------------------------------------------ EoS
 // Eq. 22: reduced enthalpy from Theta, free of the subtraction h - 1.
 template <class T>

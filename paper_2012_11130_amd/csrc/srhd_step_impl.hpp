@@ -141,7 +141,7 @@ __device__ __forceinline__ Prim<T> load_prim(const Tile<T> &s, int b)
 // Double inversion of bulk-type conserved variables (FP64 path: lhs_L in double; mixed path:
 // the float values' products are exact in double).
 __device__ __forceinline__ double L_of(const Cons<double> &u) { return lhs_L(u.D, u.m[0], u.m[1], u.m[2], u.E); }
-__device__ __forceinline__ double L_of(const Cons<float> &u) { return lhs_L_from_f32(u.D, u.m[0], u.m[1], u.m[2], u.E); }
+__device__ __forceinline__ double L_of(const Cons<float> &u) { return lhs_L_from_f32_adaptive(u.D, u.m[0], u.m[1], u.m[2], u.E); }
 
 // Admissibility (Eq. 30) of a face state and its L (0 when not admissible).
 template <class T>
