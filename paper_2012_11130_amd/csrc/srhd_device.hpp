@@ -325,6 +325,29 @@ __device__ __forceinline__ bool admissible(T D, T Mx, T My, T Mz, T Et, T eps, T
   return L > eps;
 }
 
+// The same check for a wavefront of FP64 states whose inversion results are consumed in FP32:
+// L from the plain sum of the five rounded products (relative error at most 5 u cond, under
+// 6e-13) where every lane has cond = sum |t_i| / |sum t_i| <= 2^10, else the exact lhs_L.  Near
+// the threshold eps the condition number is above 10^15, so the decision is the exact one's.
+// All lanes must call it.
+__device__ __forceinline__ bool admissible_adaptive(double D, double Mx, double My, double Mz, double Et,
+                                                    double eps, double &L)
+{
+  const bool basic = finiteT(D) && finiteT(Mx) && finiteT(My) && finiteT(Mz) && finiteT(Et) &&
+                     D > 0.0 && Et > 0.0;
+  const double pos = Et * Et + 2.0 * Et * D;
+  const double neg = -(Mx * Mx + My * My + Mz * Mz);
+  double N = pos + neg;
+  const bool cheap = basic && __builtin_fabs(pos) + __builtin_fabs(neg) <= 1024.0 * __builtin_fabs(N);
+  double l = N / (D * D);
+  if (__any(basic && !cheap)) {
+    const double le = basic ? lhs_L(D, Mx, My, Mz, Et) : 0.0;
+    l = cheap ? l : le;
+  }
+  L = basic ? l : 0.0;
+  return basic && L > eps;
+}
+
 // The polytropic EoS: a starting point with the small-ht slope f ~ 2 (1 - k) ht and the
 // large-ht growth f ~ (1 - k)^2 ht^2 (App. A's guess belongs to the TM EoS), the Newton
 // iteration of Eqs. 15 and A1 with Theta = k ht and Theta' = k, and the recovery.

@@ -494,6 +494,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
     double Lo;
     bool ok_out;
     if constexpr (TOT) ok_out = admissible_total<I>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)un[4], Lo);
+    else if constexpr (sizeof(T) == 4) ok_out = admissible_adaptive(un[0], un[1], un[2], un[3], un[4], DBL_EPSILON, Lo);
     else ok_out = admissible(un[0], un[1], un[2], un[3], un[4], DBL_EPSILON, Lo);
     fail |= !ok_out;
     fail = __syncthreads_or(fail);
@@ -660,7 +661,10 @@ __global__ void __launch_bounds__(256) k_grid_prims(int64_t n_patch, const doubl
     const double *u = cons + pp * 5 * 512 + c;
     double L;
     InvOut<I> w;
-    bool ok = admissible(u[0], u[512], u[1024], u[1536], u[2048], DBL_EPSILON, L);
+    // the step's output check and L (adaptive with an FP32 bulk), so that both give the same bits
+    bool ok;
+    if constexpr (sizeof(T) == 4) ok = admissible_adaptive(u[0], u[512], u[1024], u[1536], u[2048], DBL_EPSILON, L);
+    else ok = admissible(u[0], u[512], u[1024], u[1536], u[2048], DBL_EPSILON, L);
     bool consulted = false;
     unsigned int evals = 0;
     double guess = MLP ? mlp_guess(mlp, u[0], u[512], u[1024], u[1536], u[2048], ok ? L : 0.0, consulted, evals) : -1.0;
