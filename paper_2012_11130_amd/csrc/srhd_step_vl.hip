@@ -173,6 +173,15 @@ __device__ __forceinline__ Cons<T> riemann(int solver, const Prim<T> &wl, const 
   return solver == SRHD_HLLE ? hlle<d>(wl, wr, ul, ur) : hllc<d>(wl, wr, ul, ur);
 }
 
+// Eq. 30 and L of an FP64 state.  With an FP32 bulk the primitives are consumed in FP32, so L may
+// come from the adaptive sum (every caller runs whole wavefronts); FP64 keeps the exact sum.
+template <class T>
+__device__ __forceinline__ bool vl_admissible(double D, double Mx, double My, double Mz, double Et, double &L)
+{
+  if constexpr (sizeof(T) == 4) return admissible_adaptive(D, Mx, My, Mz, Et, DBL_EPSILON, L);
+  else return admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L);
+}
+
 // First-order flux of predictor face r along d into the buffer.
 template <int d, class T>
 __device__ __forceinline__ void predictor_face(VlTile<T> &s, int r, int solver)
@@ -245,7 +254,7 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
                  Et = q[4 * N3 + off];
     double L;
     InvOut<I> o;
-    if (admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L))
+    if (vl_admissible<T>(D, Mx, My, Mz, Et, L))
       invert_with_L<I, GuessT<T, I>, GuessT<T, I>, sizeof(T) == 4>((I)D, (I)Mx, (I)My, (I)Mz, (I)L, (I)-1.0, false,
                                      (I)StepTol<T, I>::v, 30, o);
     else set_unphysical(o);
@@ -305,7 +314,7 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
         for (int f = 0; f < 5; ++f) u[f] = q[f * N3 + off] - half * (double)acc[h][f];
         double L;
         InvOut<I> o;
-        if (admissible(u[0], u[1], u[2], u[3], u[4], DBL_EPSILON, L))
+        if (vl_admissible<T>(u[0], u[1], u[2], u[3], u[4], L))
           invert_with_L<I, GuessT<T, I>, GuessT<T, I>, sizeof(T) == 4>((I)u[0], (I)u[1], (I)u[2], (I)u[3], (I)L, (I)-1.0, false,
                                          (I)StepTol<T, I>::v, 30, o);
         else set_unphysical(o);
@@ -363,7 +372,7 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
                        Et = q[4 * N3 + off];
           double L;
           InvOut<I> o;
-          if (admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L))
+          if (vl_admissible<T>(D, Mx, My, Mz, Et, L))
             invert_with_L<I, GuessT<T, I>, GuessT<T, I>, sizeof(T) == 4>((I)D, (I)Mx, (I)My, (I)Mz, (I)L, (I)-1.0, false,
                                            (I)StepTol<T, I>::v, 30, o);
           else set_unphysical(o);
@@ -412,7 +421,7 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
 #pragma unroll
     for (int f = 0; f < 5; ++f) un[f] = q[f * N3 + lq] - full * (double)dU[f];
     double Lo;
-    const bool ok_out = admissible(un[0], un[1], un[2], un[3], un[4], DBL_EPSILON, Lo);
+    const bool ok_out = vl_admissible<T>(un[0], un[1], un[2], un[3], un[4], Lo);
     const bool fail = __syncthreads_or(!ok_out);
     if (!fail || input_bad || theta == T(0)) {
       double *o = a.out + p * 5 * 512 + lt;
