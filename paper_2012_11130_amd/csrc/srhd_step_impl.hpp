@@ -373,6 +373,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
       InvOut<I> o;
       bool adm;
       if constexpr (TOT) adm = admissible_total<I>((I)D, (I)Mx, (I)My, (I)Mz, (I)Et, L);
+      else if constexpr (sizeof(T) == 4) adm = admissible_adaptive(D, Mx, My, Mz, Et, DBL_EPSILON, L);
       else adm = admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L);
       bool consulted = false;
       unsigned int ev = 0;
