@@ -40,6 +40,19 @@ __device__ __forceinline__ double rcp_nr(double b)
   return __builtin_fma(r, __builtin_fma(-b, r, 1.0), r);
 }
 __device__ __forceinline__ float rcp_nr(float b) { return __builtin_amdgcn_rcpf(b); }
+// Square root to about 1 ulp on the same terms: the hardware reciprocal square root refined by
+// one Newton-Raphson step on it and one on the root (Markstein's coupled iteration).
+__device__ __forceinline__ double sqrt_nr(double x)
+{
+  double y = __builtin_amdgcn_rsq(x);           // ~ 1 / sqrt(x)
+  double g = x * y, hh = 0.5 * y;               // g ~ sqrt(x), hh ~ 1 / (2 sqrt(x))
+  double r = __builtin_fma(-g, hh, 0.5);
+  g = __builtin_fma(g, r, g);
+  hh = __builtin_fma(hh, r, hh);
+  const double d = __builtin_fma(-g, g, x);
+  return __builtin_fma(d, hh, g);
+}
+__device__ __forceinline__ float sqrt_nr(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double sq(double a) { return __builtin_sqrt(a); }
 __device__ __forceinline__ float sq(float a) { return __builtin_amdgcn_sqrtf(a); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -225,7 +238,7 @@ __device__ __forceinline__ bool newton_htilde(T L, T m2, T x, T tol, int max_ite
     T h = x + T(1);
     T h2 = h * h;
     T s2 = T(9) * h2 + T(16);
-    T s = sq(s2);
+    T s = FAST ? sqrt_nr(s2) : sq(s2);
     T iden, iq, is;
     if constexpr (sizeof(T) == 8) {
       // one division for 1/den, 1/q and 1/s: the product den q s^2 stays far inside the double
