@@ -136,6 +136,7 @@ __device__ __forceinline__ double lhs_L_from_f32(float D, float Mx, float My, fl
 // |sum t_i|), where every lane has cond <= 2^10 (so below 5e-13: under the FP32 resolution of
 // what the inversion returns); the compensated sum otherwise.  A gas at rest has cond = 1; a
 // cold, fast gas has cond ~ U^2 / Theta and takes the compensated sum.  All lanes must call it.
+template <bool FAST = false>
 __device__ __forceinline__ double lhs_L_from_f32_adaptive(float D, float Mx, float My, float Mz, float Et)
 {
 #pragma clang fp contract(off)
@@ -153,7 +154,7 @@ __device__ __forceinline__ double lhs_L_from_f32_adaptive(float D, float Mx, flo
     const double Nk = sum_k3(t);
     N = cheap ? N : Nk;
   }
-  return N / (d * d);
+  return FAST ? N * rcp_nr(d * d) : N / (d * d);
 }
 
 // ------------------------------------------------------------------------------ EoS
@@ -343,6 +344,7 @@ __device__ __forceinline__ bool admissible(T D, T Mx, T My, T Mz, T Et, T eps, T
 // 6e-13) where every lane has cond = sum |t_i| / |sum t_i| <= 2^10, else the exact lhs_L.  Near
 // the threshold eps the condition number is above 10^15, so the decision is the exact one's.
 // All lanes must call it.
+template <bool FAST = false>
 __device__ __forceinline__ bool admissible_adaptive(double D, double Mx, double My, double Mz, double Et,
                                                     double eps, double &L)
 {
@@ -352,7 +354,7 @@ __device__ __forceinline__ bool admissible_adaptive(double D, double Mx, double 
   const double neg = -(Mx * Mx + My * My + Mz * Mz);
   double N = pos + neg;
   const bool cheap = basic && __builtin_fabs(pos) + __builtin_fabs(neg) <= 1024.0 * __builtin_fabs(N);
-  double l = N / (D * D);
+  double l = FAST ? N * rcp_nr(D * D) : N / (D * D);
   if (__any(basic && !cheap)) {
     const double le = basic ? lhs_L(D, Mx, My, Mz, Et) : 0.0;
     l = cheap ? l : le;

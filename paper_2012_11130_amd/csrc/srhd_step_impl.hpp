@@ -140,16 +140,18 @@ __device__ __forceinline__ Prim<T> load_prim(const Tile<T> &s, int b)
 
 // Double inversion of bulk-type conserved variables (FP64 path: lhs_L in double; mixed path:
 // the float values' products are exact in double).
+template <bool FAST>
 __device__ __forceinline__ double L_of(const Cons<double> &u) { return lhs_L(u.D, u.m[0], u.m[1], u.m[2], u.E); }
-__device__ __forceinline__ double L_of(const Cons<float> &u) { return lhs_L_from_f32_adaptive(u.D, u.m[0], u.m[1], u.m[2], u.E); }
+template <bool FAST>
+__device__ __forceinline__ double L_of(const Cons<float> &u) { return lhs_L_from_f32_adaptive<FAST>(u.D, u.m[0], u.m[1], u.m[2], u.E); }
 
 // Admissibility (Eq. 30) of a face state and its L (0 when not admissible).
-template <class T>
+template <bool FAST, class T>
 __device__ __forceinline__ bool face_L(const Cons<T> &u, double &L)
 {
   bool ok = finiteT(u.D) && finiteT(u.m[0]) && finiteT(u.m[1]) && finiteT(u.m[2]) &&
             finiteT(u.E) && u.D > T(0) && u.E > T(0);
-  L = ok ? L_of(u) : 0.0;
+  L = ok ? L_of<FAST>(u) : 0.0;
   ok = ok && L > DBL_EPSILON;
   if (!ok) L = 0.0;
   return ok;
@@ -228,7 +230,7 @@ __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, in
   double L;
   bool ok;
   if constexpr (K == KV_TOTAL) ok = admissible_total<I>(u.D, u.m[0], u.m[1], u.m[2], u.E, L);
-  else ok = face_L(u, L);
+  else ok = face_L<FAST>(u, L);
   bool consulted = false;
   double guess = MLP ? mlp_guess(mlp, u.D, u.m[0], u.m[1], u.m[2], u.E, L, consulted, evals) : -1.0;
   return invert_face<I, MLP, FAST>(u, ok, L, w, x, iters, status, guess, consulted, eos);
@@ -495,7 +497,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
     double Lo;
     bool ok_out;
     if constexpr (TOT) ok_out = admissible_total<I>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)un[4], Lo);
-    else if constexpr (sizeof(T) == 4) ok_out = admissible_adaptive(un[0], un[1], un[2], un[3], un[4], DBL_EPSILON, Lo);
+    else if constexpr (sizeof(T) == 4) ok_out = admissible_adaptive<GATHER>(un[0], un[1], un[2], un[3], un[4], DBL_EPSILON, Lo);
     else ok_out = admissible(un[0], un[1], un[2], un[3], un[4], DBL_EPSILON, Lo);
     fail |= !ok_out;
     fail = __syncthreads_or(fail);
@@ -664,7 +666,7 @@ __global__ void __launch_bounds__(256) k_grid_prims(int64_t n_patch, const doubl
     InvOut<I> w;
     // the step's output check and L (adaptive with an FP32 bulk), so that both give the same bits
     bool ok;
-    if constexpr (sizeof(T) == 4) ok = admissible_adaptive(u[0], u[512], u[1024], u[1536], u[2048], DBL_EPSILON, L);
+    if constexpr (sizeof(T) == 4) ok = admissible_adaptive<true>(u[0], u[512], u[1024], u[1536], u[2048], DBL_EPSILON, L);
     else ok = admissible(u[0], u[512], u[1024], u[1536], u[2048], DBL_EPSILON, L);
     bool consulted = false;
     unsigned int evals = 0;

@@ -178,7 +178,7 @@ __device__ __forceinline__ Cons<T> riemann(int solver, const Prim<T> &wl, const 
 template <class T>
 __device__ __forceinline__ bool vl_admissible(double D, double Mx, double My, double Mz, double Et, double &L)
 {
-  if constexpr (sizeof(T) == 4) return admissible_adaptive(D, Mx, My, Mz, Et, DBL_EPSILON, L);
+  if constexpr (sizeof(T) == 4) return admissible_adaptive<true>(D, Mx, My, Mz, Et, DBL_EPSILON, L);
   else return admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L);
 }
 
