@@ -236,6 +236,17 @@ __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, in
   return invert_face<I, MLP, FAST>(u, ok, L, w, x, iters, status, guess, consulted, eos);
 }
 
+// Physical flux along d of a face state given by its primitives, with 1 / gamma = rho / D from
+// the conserved variables just formed (one reciprocal instead of a square root and a reciprocal).
+// The original scheme (TOT) keeps its own arithmetic: it is the comparison baseline.
+template <int d, bool TOT, class T, class E>
+__device__ __forceinline__ Cons<T> state_flux(const Prim<T> &w, const E &eos)
+{
+  const Cons<T> u = prim2cons_s<TOT>(w, eos);
+  if constexpr (TOT) return phys_flux<d, TOT>(w, u);
+  else return phys_flux<d, TOT>(w, u, w.rho * dv(T(1), u.D));
+}
+
 struct IfaceCount {
   unsigned int iters, inv, fb, nc, unphys, mlp;
 };
@@ -430,9 +441,9 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
         fm.u[2] = wc.u[2] - T(0.5) * sl[3]; fp.u[2] = wc.u[2] + T(0.5) * sl[3];
         fm.p = wc.p - T(0.5) * sl[4];      fp.p = wc.p + T(0.5) * sl[4];
         Cons<T> Fm, Fp;
-        if (d == 0) { Fm = phys_flux<0, TOT>(fm, prim2cons_s<TOT>(fm, eos)); Fp = phys_flux<0, TOT>(fp, prim2cons_s<TOT>(fp, eos)); }
-        else if (d == 1) { Fm = phys_flux<1, TOT>(fm, prim2cons_s<TOT>(fm, eos)); Fp = phys_flux<1, TOT>(fp, prim2cons_s<TOT>(fp, eos)); }
-        else { Fm = phys_flux<2, TOT>(fm, prim2cons_s<TOT>(fm, eos)); Fp = phys_flux<2, TOT>(fp, prim2cons_s<TOT>(fp, eos)); }
+        if (d == 0) { Fm = state_flux<0, TOT>(fm, eos); Fp = state_flux<0, TOT>(fp, eos); }
+        else if (d == 1) { Fm = state_flux<1, TOT>(fm, eos); Fp = state_flux<1, TOT>(fp, eos); }
+        else { Fm = state_flux<2, TOT>(fm, eos); Fp = state_flux<2, TOT>(fp, eos); }
         acc[0] += Fp.D - Fm.D;
         acc[1] += Fp.m[0] - Fm.m[0];
         acc[2] += Fp.m[1] - Fm.m[1];
