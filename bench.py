@@ -265,8 +265,9 @@ def main():
         summarize_profile(args.summarize_profile, args.calib_copy or 512)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the step has no multi-GPU path (each GPU would "
+              "own a contiguous range of the Morton-ordered patch list); run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
