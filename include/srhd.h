@@ -38,7 +38,7 @@ typedef enum {
   SRHD_OK = 0,
   SRHD_EINVAL = -1,       /* bad argument (NULL pointer, negative size, misaligned pointer...) */
   SRHD_EHIP = -2,         /* the HIP runtime reported an error at launch */
-  SRHD_EUNSUPPORTED = -3  /* valid request that this build does not implement */
+  SRHD_EUNSUPPORTED = -3  /* valid request that the library does not implement */
 } srhd_err;
 
 /* Per-state status of an inversion (int8). */
