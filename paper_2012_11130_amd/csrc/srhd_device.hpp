@@ -214,8 +214,10 @@ __device__ __forceinline__ T guess_analytic(T L, T m2)
     T c = T(437) * m2 + T(117), u = T(1800) * a;
     hot = L * c * c > u * u;
   } else {
-    T thr = dv(T(1800) * a, T(437) * m2 + T(117));
-    hot = L > thr * thr;
+    // sqrt(L) c > 1800 a: the hot branch's square root, and no division (nothing overflows)
+    const T sl = sq(L);
+    hot = sl * (T(437) * m2 + T(117)) > T(1800) * a;
+    if (hot) return T(4.0 / 3.0) * sl;
   }
   if (hot) return T(4.0 / 3.0) * sq(L);
   T b = T(43) * m2 + T(63);
