@@ -53,7 +53,7 @@ IO_BYTES_PER_PATCH = {                         # what one patch's step consumes 
 # the two-workgroup register variant) on this workload, from the rocprofv3 FETCH_SIZE /
 # WRITE_SIZE runs summarised in profiles/step_blast256_grid_learned.md; valid only for the kernel
 # sources they were taken on (hash of the files that make up the step kernel).
-PROFILED_TRAFFIC = {"sources_sha256_16": "f0147079a4d3e526", "read": 1297.3e6, "write": 1009.8e6,
+PROFILED_TRAFFIC = {"sources_sha256_16": "cc158bd1257fbfe6", "read": 1299.7e6, "write": 1009.8e6,
                     "path": "grid", "summary": "profiles/step_blast256_grid_learned.md"}
 STEP_SOURCES = ("srhd_step_impl.hpp", "srhd_step_mixed.hip", "srhd_device.hpp", "srhd_mlp.hpp")
 
