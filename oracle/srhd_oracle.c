@@ -17,7 +17,9 @@
  *                            Eq. 14 (sound speed), Eq. A2 (dTheta/dht); or the polytropic EoS
  *                            of Sec. 2.2 (or_set_eos), the same functions for h = 1 +
  *                            Gamma Theta / (Gamma - 1)
- *   inversion equation       Sec. 2.3, Eq. 15 (f), Eq. A1 (df/dht)
+ *   inversion equation       Sec. 2.3, Eq. 15 (f), Eq. A1 (df/dht); its left-hand side L exactly
+ *                            (error-free products, exact sum) and, to reproduce Eq. 20 and
+ *                            App. B, as the plain expression of the divided variables
  *   initial guesses          App. A, Eqs. A3-A7 (A4 read as the positive root of A3)
  *   prim -> cons             Eqs. 8, 5a, 5b, 22, 15, 23
  *   cons -> prim             Eqs. 15, 30 (physical check), 17, 8, 5a, 16, 18; the root is

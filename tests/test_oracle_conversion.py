@@ -198,6 +198,67 @@ def test_appendix_b_error_curve():
     assert min(naive_ok[:6]) > 1e-10
 
 
+def _eq20_kappa(w):
+    """Eq. 20's amplification factor (the bracket multiplying eps) from the primitive state, in
+    50-digit arithmetic: [gamma^2 h^2 (1 + beta^2) + T^2/gamma^2 - 2 h T - 1] /
+    [h^2 + T^2/gamma^2 - 2 h T - 1], h = ht + 1, T = Theta (the denominator written as
+    ht (ht + 2) + ... so that a cold gas keeps its digits)."""
+    rho, ux, uy, uz, p = (mp.mpf(float(v)) for v in w)
+    th = p / rho
+    U2 = ux * ux + uy * uy + uz * uz
+    g2 = 1 + U2
+    beta2 = U2 / g2
+    a = mp.mpf(9) / 4 * th * th
+    ht = mp.mpf(5) / 2 * th + a / (1 + mp.sqrt(a + 1))
+    h = ht + 1
+    num = g2 * h * h * (1 + beta2) + th * th / g2 - 2 * h * th - 1
+    den = ht * (ht + 2) + th * th / g2 - 2 * h * th
+    return num / den
+
+
+def test_naive_L_rounding_and_eq20_error():
+    # The paper-literal left-hand side x^2 + 2x - m^2 from the divided variables x = Et/D,
+    # m = |M|/D.  (1) Against the same expression evaluated exactly on the correctly rounded
+    # quotients (Python's float division is IEEE's): at most a few roundings of the terms, so
+    # |error| <= 4u (x^2 + 2|x| + m^2).  (2) Against the exact L of the stored conserved
+    # variables its relative error follows Eq. 20, (1 + Mach^2) eps (App. B, Theta = 1e-8, U along
+    # x = y = z), and the bound is attained: a dropped term, a sign or a wrong quotient fails one
+    # of the two.
+    th = 1e-8
+    Us = math.sqrt(O.cs2(th) / (1 - O.cs2(th)))
+    rng = np.random.default_rng(23)
+    states = [np.array([1.0, m * Us / math.sqrt(3), m * Us / math.sqrt(3), m * Us / math.sqrt(3), th])
+              for m in np.logspace(-4, 6, 41)]
+    prim = W.conversion_batch(200, seed=31)
+    states += [prim[:, i] for i in range(prim.shape[1])]
+    worst, big = 0.0, 0
+    for w in states:
+        u = O.prim2cons_one(w)
+        Ln = O.L_naive(*u)
+        D = u[0]
+        x = Fraction(u[4] / D)
+        ms = [Fraction(u[k] / D) for k in (1, 2, 3)]
+        m2 = sum(v * v for v in ms)
+        Lq = x * x + 2 * x - m2
+        scale = x * x + 2 * abs(x) + m2
+        assert abs(Fraction(Ln) - Lq) <= 4 * Fraction(U) * scale, w
+        num, Dr = _L_rational(u)
+        L = num / (Dr * Dr)
+        if L <= 0:
+            continue
+        err = abs(float((Fraction(Ln) - L) / L))
+        kappa = float(_eq20_kappa(w))
+        assert err <= 8 * kappa * U + 8 * U, (w, err, kappa)
+        worst = max(worst, err / (kappa * U))
+        big += err > 1e-10
+    assert worst > 0.1          # the bound is attained, not vacuous
+    assert big >= 5             # and the amplification is visible at high Mach
+    # the batch entry point evaluates the same function
+    cons = np.stack([O.prim2cons_one(w) for w in states[:50]], axis=1)
+    Lb = O.L_batch(cons, mode="naive")
+    assert all(Lb[i] == O.L_naive(*cons[:, i]) for i in range(cons.shape[1]))
+
+
 def test_unphysical_states_are_flagged():
     good = O.prim2cons_one([1.0, 0.5, 0.0, 0.0, 1.0])
     assert O.cons2prim_one(good)[1] == O.ST_OK
