@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define SRHD_ABI_VERSION 5
+#define SRHD_ABI_VERSION 6
 
 typedef enum { SRHD_F64 = 0, SRHD_F32 = 1 } srhd_dtype;
 
@@ -217,7 +217,26 @@ typedef struct {
                               transverse coordinates in increasing axis order.  Overwritten, not
                               accumulated (see srhd_flux_accumulate); for the flux correction of
                               coarse-fine interfaces.  Must not overlap the other arrays. */
+  double kappa_max;        /* precision guard of the FP32-bulk modes (see below); 0: off */
+  uint64_t *defer;         /* device [n_patch + 2] workspace of the guard, or NULL when off */
 } srhd_step_params;
+
+/* Precision guard (SRHD_PREC_MIXED and SRHD_PREC_FP32, MUSCL-Hancock).  Eq. 20 puts the error of
+ * recovering the pressure from conserved variables that carry a relative rounding error eps at
+ * (1 + M^2) eps, M = U / U_s the Mach number in four-velocities (U_s^2 = c_s^2 / (1 - c_s^2)).
+ * An FP32 bulk rounds the half-step face states and the update increment to FP32, so a patch
+ * holding a cell with kappa = 1 + M^2 near 1 / eps_32 (a gamma = 10^3 jet: kappa ~ 2e6) loses its
+ * pressure there.  With kappa_max >= 1 every patch whose 12^3 primitive tile (after the
+ * cell-centre inversions, or as gathered) holds a cell with kappa > kappa_max is stepped instead
+ * by the FP64 kernel (FP64 bulk and inversion; in the gather layout from the FP32 primitives
+ * widened to FP64), in a second launch over the list of such patches; the other patches keep the
+ * FP32 bulk, whose one-step error is then of order kappa_max eps_32 per field.  kappa_max = 0
+ * turns the guard off (the FP32 bulk everywhere, like a single-precision code).  defer: device
+ * memory of n_patch + 2 uint64 words (8-byte aligned), required when the guard is on; zeroed by
+ * the call on its stream; afterwards word 0 holds the number of patches stepped in FP64 and words
+ * 2 .. their indices in no particular order.  Calls in flight at the same time must not share it.
+ * Ignored by SRHD_PREC_FP64 and by the VL integrator. */
+#define SRHD_KAPPA_MAX_DEFAULT 1024.0
 
 /* Device counters, accumulated (never reset by the step; see srhd_stats_reset). */
 typedef struct {
@@ -230,6 +249,7 @@ typedef struct {
   uint64_t n_mlp;          /* learned-guess evaluations: lanes of wavefronts that ran the network */
   uint64_t n_pred_fallback; /* VL: predictor states that failed the inversion and were replaced
                                by the cell's state at t^n (final attempts) */
+  uint64_t n_fp64_patch;   /* patches the precision guard stepped with the FP64 bulk */
 } srhd_step_stats;
 
 int srhd_stats_reset(srhd_step_stats *stats, void *stream);

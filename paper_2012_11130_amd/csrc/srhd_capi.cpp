@@ -144,6 +144,29 @@ int check_sched(const srhd_sched &sc, int prec, int guess_kind, srhd::StepArgs &
   return SRHD_OK;
 }
 
+// Precision guard of an FP32-bulk MUSCL-Hancock step (include/srhd.h, srhd_step_params):
+// kappa_max 0 (off) or >= 1; the defer workspace of n_patch + 2 words must be 8-byte aligned
+// and overlap none of the call's other arrays (regions, n_region of them, NULL entries skipped).
+int check_guard(const srhd_step_params *prm, int64_t n_patch, const void *const *regions,
+                const size_t *sizes, int n_region, srhd::StepArgs &s, const char *who)
+{
+  s.defer = nullptr;
+  s.kappa_max = 0.0;
+  const double k = prm->kappa_max;
+  if (!(k == 0.0 || k >= 1.0))
+    return fail(SRHD_EINVAL, "%s: kappa_max %g is neither 0 nor at least 1", who, k);
+  if (k == 0.0 || prm->prec == SRHD_PREC_FP64 || prm->integrator != SRHD_MHM) return SRHD_OK;
+  if (!prm->defer || !aligned(prm->defer, 8))
+    return fail(SRHD_EINVAL, "%s: the precision guard needs an 8-byte aligned defer workspace", who);
+  const size_t db = ((size_t)n_patch + 2) * 8;
+  for (int i = 0; i < n_region; ++i)
+    if (regions[i] && !disjoint(prm->defer, db, regions[i], sizes[i]))
+      return fail(SRHD_EINVAL, "%s: defer overlaps another array of the call", who);
+  s.defer = (unsigned long long *)prm->defer;
+  s.kappa_max = k;
+  return SRHD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -406,6 +429,12 @@ int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
     const char *q = (const char *)s.queue;
     if (q < b + bbytes && b < q + SRHD_QUEUE_WORDS * 8)
       return fail(SRHD_EINVAL, "srhd_fluid_step: sched.queue overlaps out");
+  }
+  {
+    const void *reg[4] = {in->padded, out, s.flux_out, s.queue};
+    const size_t sz[4] = {abytes, bbytes, (size_t)in->n_patch * 6 * 5 * 64 * 8, SRHD_QUEUE_WORDS * 8};
+    rc = check_guard(prm, in->n_patch, reg, sz, 4, s, "srhd_fluid_step");
+    if (rc) return rc;
   }
   return hip_status(srhd::launch_step(prm->prec, s, (hipStream_t)stream), "srhd_fluid_step");
 }
@@ -699,6 +728,13 @@ int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_
     return fail(SRHD_EUNSUPPORTED, "srhd_fluid_step_grid: boundary fluxes are written by srhd_fluid_step only");
   rc = check_sched(prm->sched, prm->prec, g.kind, s, "srhd_fluid_step_grid");
   if (rc) return rc;
+  {
+    const size_t cb = (size_t)in->n_patch * 5 * 512 * 8, pb = (size_t)in->n_patch * 5 * 512 * ps;
+    const void *reg[5] = {in->cons, in->prims, cons_out, prims_out, s.queue};
+    const size_t sz[5] = {cb, pb, cb, pb, SRHD_QUEUE_WORDS * 8};
+    rc = check_guard(prm, in->n_patch, reg, sz, 5, s, "srhd_fluid_step_grid");
+    if (rc) return rc;
+  }
   return hip_status(srhd::launch_step_grid(prm->prec, s, (hipStream_t)stream),
                     "srhd_fluid_step_grid");
 }

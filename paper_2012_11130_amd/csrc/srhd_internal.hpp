@@ -69,6 +69,11 @@ struct StepArgs {
   int integrator;                       // srhd_integrator: SRHD_VL runs srhd_step_vl.hip's kernel
   double *flux_out;                     // padded layout: [P][6][5][64] boundary fluxes, or NULL
   double eos_k;                         // polytropic EoS: (Gamma - 1) / Gamma; 0 selects TM
+  // precision guard of the FP32-bulk kernels (NULL: off): a patch whose tile holds a cell with
+  // 1 + M^2 > kappa_max is listed here ([0] count, [1] claim counter, [2..] patch indices) and
+  // stepped by the FP64 kernel in a second launch
+  unsigned long long *defer;
+  double kappa_max;
 };
 
 // Fluxes of the interfaces on the two faces (lower, upper) of direction d from the step's

@@ -311,10 +311,17 @@ __device__ __forceinline__ int64_t patch_of_block(int64_t n_patch, int remap)
 // GATHER = true : the 1,376 tile cells' primitives are read from the interiors of the patch and
 //                 its 26 neighbours (outflow clamping where a face neighbour is -1), and every
 //                 updated cell is inverted at the end -- its primitives and the workgroup's
-//                 maximum signal speed (Eqs. 26-27) feed the next step.
-template <class T, class I, bool GATHER, int K>
+//                 maximum signal speed (Eqs. 26-27) feed the next step.  PS is the storage type
+//                 of those primitives (T, or float for the FP64 step of a guarded FP32 chain).
+// With an FP32 bulk and the precision guard on (a.defer), a patch whose tile holds a cell with
+// 1 + M^2 > kappa_max (Eq. 20) is listed in a.defer after phase A and left to the FP64 kernel.
+// That kernel (T = double, PS = float in the gather layout) inverts the gathered FP64 conserved
+// variables of its tile: FP32-rounded primitives would put rounding-sized errors into the
+// fluxes, which the update turns into (1 + M^2) eps_32 pressure errors of the next state.
+template <class T, class I, bool GATHER, int K, class PS = T>
 __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const MlpDev &mlp, const int64_t p)
 {
+  constexpr bool GCONS = GATHER && sizeof(T) != sizeof(PS);
   constexpr bool MLP = K == KV_MLP;
   constexpr bool TOT = K == KV_TOTAL;
   static_assert(!TOT || (!GATHER && sizeof(T) == sizeof(I)), "original scheme: padded, one type");
@@ -341,8 +348,9 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
   __syncthreads();
 
   // ---------------------------------------------------------------- A: centre primitives
-  bool centre_bad = false;
+  bool centre_bad = false, hot = false;
   unsigned int centre_unphys = 0;
+  const T km1 = T(a.kappa_max - 1.0);
   for (int r0 = 0; r0 < NPC; r0 += NT) {
     // every lane runs every round (the learned guess needs whole wavefronts); lanes past the
     // end of the list work on the first cell again and store nothing
@@ -350,9 +358,13 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
     const bool valid = r < NPC;
     int b = kTab.pcell[valid ? r : 0];
     int bi = b % BX, bj = (b / BX) % BX, bk = b / (BX * BX);
+    // gather layout: the source patch and cell of this tile cell (outflow clamping where a
+    // face neighbour is -1)
+    int64_t src = 0;
+    int sc = 0;
+    bool okc = true;
     if (GATHER) {
       if (!valid) continue;
-      const T *__restrict__ pr = (const T *)a.prims;
       int c[3] = {bi - 2, bj - 2, bk - 2};
       const int fs[3] = {1, 3, 9};
 #pragma unroll
@@ -363,14 +375,19 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
       int o0 = c[0] < 0 ? -1 : (c[0] >= 8 ? 1 : 0);
       int o1 = c[1] < 0 ? -1 : (c[1] >= 8 ? 1 : 0);
       int o2 = c[2] < 0 ? -1 : (c[2] >= 8 ? 1 : 0);
-      int64_t src = s.nb[(o2 + 1) * 9 + (o1 + 1) * 3 + (o0 + 1)];
-      bool okc = src >= 0 && src < a.n_patch;
-      int sc = ((c[2] - 8 * o2) * 8 + (c[1] - 8 * o1)) * 8 + (c[0] - 8 * o0);
+      src = s.nb[(o2 + 1) * 9 + (o1 + 1) * 3 + (o0 + 1)];
+      okc = src >= 0 && src < a.n_patch;
+      sc = ((c[2] - 8 * o2) * 8 + (c[1] - 8 * o1)) * 8 + (c[0] - 8 * o0);
+    }
+    if (GATHER && !GCONS) {
+      const PS *__restrict__ pr = (const PS *)a.prims;
       const T nan = T(__builtin_nan(""));
-      const T *w = pr + (okc ? src : 0) * 5 * 512 + sc;
-      T v0 = okc ? w[0] : nan, v1 = okc ? w[512] : nan, v2 = okc ? w[1024] : nan,
-        v3 = okc ? w[1536] : nan, v4 = okc ? w[2048] : nan;
+      const PS *w = pr + (okc ? src : 0) * 5 * 512 + sc;
+      T v0 = okc ? (T)w[0] : nan, v1 = okc ? (T)w[512] : nan, v2 = okc ? (T)w[1024] : nan,
+        v3 = okc ? (T)w[1536] : nan, v4 = okc ? (T)w[2048] : nan;
       bool bad = !(v0 > T(0)) || !(v4 > T(0)) || !finiteT(v1) || !finiteT(v2) || !finiteT(v3);
+      if constexpr (sizeof(T) == 4)
+        if (a.defer) hot |= kappa_above<T>(v0, v1, v2, v3, v4, km1, eos);
       centre_bad |= bad;
       centre_unphys += bad;
       s.W[0][b] = v0;
@@ -379,9 +396,23 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
       s.W[3][b] = v3;
       s.W[4][b] = v4;
     } else {
-      int off = ((bk + g - 2) * N + (bj + g - 2)) * N + (bi + g - 2);
-      double D = q[off], Mx = q[N3 + off], My = q[2 * N3 + off], Mz = q[3 * N3 + off],
-             Et = q[4 * N3 + off];
+      double D, Mx, My, Mz, Et;
+      if (GCONS) {
+        const double nan = __builtin_nan("");
+        const double *u = a.cons + (okc ? src : 0) * 5 * 512 + sc;
+        D = okc ? u[0] : nan;
+        Mx = okc ? u[512] : nan;
+        My = okc ? u[1024] : nan;
+        Mz = okc ? u[1536] : nan;
+        Et = okc ? u[2048] : nan;
+      } else {
+        int off = ((bk + g - 2) * N + (bj + g - 2)) * N + (bi + g - 2);
+        D = q[off];
+        Mx = q[N3 + off];
+        My = q[2 * N3 + off];
+        Mz = q[3 * N3 + off];
+        Et = q[4 * N3 + off];
+      }
       double L;
       InvOut<I> o;
       bool adm;
@@ -405,9 +436,24 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
       s.W[2][b] = (T)o.uy;
       s.W[3][b] = (T)o.uz;
       s.W[4][b] = (T)o.p;
+      if constexpr (sizeof(T) == 4)
+        if (a.defer) hot |= kappa_above<T>((T)o.rho, (T)o.ux, (T)o.uy, (T)o.uz, (T)o.p, km1, eos);
     }
   }
   centre_bad = __syncthreads_or(centre_bad);
+
+  // precision guard: a patch holding a cell beyond kappa_max goes to the FP64 kernel (its
+  // unphysical centre cells are counted there)
+  bool deferred = false;
+  if constexpr (sizeof(T) == 4) {
+    if (a.defer) {
+      deferred = __syncthreads_or(hot);
+      if (deferred) {
+        centre_unphys = 0;
+        if (tid == 0) a.defer[2 + atomicAdd(&a.defer[0], 1ull)] = (unsigned long long)p;
+      }
+    }
+  }
 
   // this thread's interior cell for phase D
   const int ci = tid & 7, cj = (tid >> 3) & 7, ck = tid >> 6;
@@ -415,7 +461,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
 
   T theta = (T)a.theta;
   unsigned int retries = 0, unphys = 0;
-  for (int attempt = 0;; ++attempt) {
+  for (int attempt = 0; !deferred; ++attempt) {
     // -------------------------------------------------------------- B: half-step corrections
     const T half = T(0.5 * dt / dh);
     for (int r = tid; r < NHC; r += NT) {
@@ -551,15 +597,15 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
         my_iters += w.iters;
         my_inv += 1;
         my_nc += w.status == ST_NOCONV;
-        T *po = (T *)a.prims_out + p * 5 * 512 + lt;
-        po[0] = (T)w.rho;
-        po[512] = (T)w.ux;
-        po[1024] = (T)w.uy;
-        po[1536] = (T)w.uz;
-        po[2048] = (T)w.p;
+        PS *po = (PS *)a.prims_out + p * 5 * 512 + lt;
+        po[0] = (PS)(T)w.rho;
+        po[512] = (PS)(T)w.ux;
+        po[1024] = (PS)(T)w.uy;
+        po[1536] = (PS)(T)w.uz;
+        po[2048] = (PS)(T)w.p;
         double sm = 0.0;
-        if constexpr (sizeof(T) == 4) {
-          if (ok_out) sm = (double)signal_smax_t<T>((T)w.rho, (T)w.ux, (T)w.uy, (T)w.uz, (T)w.p);
+        if constexpr (sizeof(PS) == 4) {
+          if (ok_out) sm = (double)signal_smax_t<float>((float)(T)w.rho, (float)(T)w.ux, (float)(T)w.uy, (float)(T)w.uz, (float)(T)w.p);
         } else {
           if (ok_out) sm = signal_smax((double)w.rho, (double)w.ux, (double)w.uy, (double)w.uz, (double)w.p);
         }
@@ -655,6 +701,34 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4)))
   step_body<T, I, GATHER, K>(a);
 }
 
+// Second launch of a guarded FP32-bulk step: a persistent grid steps the patches listed in
+// a.defer with the FP64 bulk and inversion.  The original scheme and the polytropic EoS keep
+// their variant; the learned guess gives way to the analytic one (Newton refines either to the
+// same tolerance).  PS: storage type of the gather layout's primitives (the chain's FP32 ones,
+// widened to FP64 in the tile).  Every workgroup leaves once the list is exhausted.
+template <bool GATHER, int K, class PS>
+__global__ void __launch_bounds__(NT) k_step_listed_fp64(StepArgs a)
+{
+  const MlpDev mlp = a.guess.dev();
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Tile<double> &s = *reinterpret_cast<Tile<double> *>(smem_raw);
+  const unsigned long long n = a.defer[0];
+  for (;;) {
+    __syncthreads();                                 // the tile and s.claim are free again
+    if (threadIdx.x == 0) s.claim = atomicAdd(&a.defer[1], 1ull);
+    __syncthreads();
+    const unsigned long long i = s.claim;
+    if (i >= n) break;                               // uniform: every thread read the same claim
+    step_patch<double, double, GATHER, K, PS>(a, s, mlp, (int64_t)a.defer[2 + i]);
+    if (a.stats && threadIdx.x == 0) atomicAdd((unsigned long long *)&a.stats->n_fp64_patch, 1ull);
+  }
+}
+
+__global__ void k_zero_defer(unsigned long long *d)
+{
+  if (threadIdx.x < 2) d[threadIdx.x] = 0ull;
+}
+
 // Inversion of every interior cell into the bulk type, with the maximum signal speed (the
 // entry state of the gather-mode step).  Same inversion and tolerance as the step's own output
 // inversion, so a chain of steps sees identically computed primitives throughout.
@@ -742,6 +816,25 @@ int occupancy_k(bool occ2)
   return n;
 }
 
+// The FP64 step of the patches a guarded FP32-bulk step listed: one workgroup per compute unit
+// (the FP64 tile fills a CU's LDS), persistent over the list.
+template <bool GATHER, int K>
+hipError_t launch_step_listed(const StepArgs &a, hipStream_t st)
+{
+  constexpr int KD = K == KV_MLP ? KV_ANALYTIC : K;
+  const size_t bytes = sizeof(Tile<double>);
+  hipError_t e = hipFuncSetAttribute((const void *)k_step_listed_fp64<GATHER, KD, float>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  int dev = 0, cus = 0;
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  int64_t groups = cus > 0 ? cus : 1;
+  if (groups > a.n_patch) groups = a.n_patch;
+  hipLaunchKernelGGL((k_step_listed_fp64<GATHER, KD, float>), dim3((unsigned)groups), dim3(NT), bytes, st, a);
+  return hipGetLastError();
+}
+
 template <class T, class I, bool GATHER, int K>
 hipError_t launch_step_k(const StepArgs &a, hipStream_t st)
 {
@@ -750,6 +843,8 @@ hipError_t launch_step_k(const StepArgs &a, hipStream_t st)
   hipError_t e = hipFuncSetAttribute(step_kernel<T, I, GATHER, K>(occ2),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
+  const bool guard = sizeof(T) == 4 && a.defer != nullptr;
+  if (guard) hipLaunchKernelGGL(k_zero_defer, dim3(1), dim3(64), 0, st, a.defer);
   if (GATHER) hipLaunchKernelGGL(k_zero_bits, dim3(1), dim3(64), 0, st, a.smax_out);
   int64_t blocks;
   if (a.queue) {
@@ -759,13 +854,15 @@ hipError_t launch_step_k(const StepArgs &a, hipStream_t st)
     blocks = a.xcd_remap ? 8 * ((a.n_patch + 7) / 8) : a.n_patch;
   }
   if constexpr (sizeof(T) == 4) {
-    if (occ2) {
-      hipLaunchKernelGGL((k_step_occ2<T, I, GATHER, K>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
-      return hipGetLastError();
-    }
+    if (occ2) hipLaunchKernelGGL((k_step_occ2<T, I, GATHER, K>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
+    else hipLaunchKernelGGL((k_step<T, I, GATHER, K>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
+    e = hipGetLastError();
+    if (e != hipSuccess || !guard) return e;
+    return launch_step_listed<GATHER, K>(a, st);
+  } else {
+    hipLaunchKernelGGL((k_step<T, I, GATHER, K>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
+    return hipGetLastError();
   }
-  hipLaunchKernelGGL((k_step<T, I, GATHER, K>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
-  return hipGetLastError();
 }
 
 // The original scheme exists where it can run: padded layout, bulk type = inversion type; the

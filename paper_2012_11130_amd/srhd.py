@@ -72,7 +72,13 @@ class srhd_sched(ctypes.Structure):
 class srhd_step_params(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("riemann", _int), ("prec", _int),
                 ("max_retry", _int), ("guess", srhd_guess), ("sched", srhd_sched),
-                ("energy", _int), ("integrator", _int), ("eos", srhd_eos), ("flux_out", _vp)]
+                ("energy", _int), ("integrator", _int), ("eos", srhd_eos), ("flux_out", _vp),
+                ("kappa_max", ctypes.c_double), ("defer", _vp)]
+
+
+# precision guard of the FP32-bulk steps: patches holding a cell with 1 + M^2 above this are
+# stepped in FP64 (0 turns it off)
+KAPPA_MAX_DEFAULT = 1024.0
 
 
 class srhd_tune_entry(ctypes.Structure):
@@ -86,11 +92,13 @@ class srhd_step_stats(ctypes.Structure):
     _fields_ = [("n_unphysical", ctypes.c_uint64), ("n_fallback", ctypes.c_uint64),
                 ("n_noconv", ctypes.c_uint64), ("newton_iters", ctypes.c_uint64),
                 ("n_inversions", ctypes.c_uint64), ("n_retry", ctypes.c_uint64),
-                ("n_mlp", ctypes.c_uint64), ("n_pred_fallback", ctypes.c_uint64)]
+                ("n_mlp", ctypes.c_uint64), ("n_pred_fallback", ctypes.c_uint64),
+                ("n_fp64_patch", ctypes.c_uint64)]
 
 
 STATS_FIELDS = ("n_unphysical", "n_fallback", "n_noconv", "newton_iters", "n_inversions",
-                "n_retry", "n_mlp", "n_pred_fallback")
+                "n_retry", "n_mlp", "n_pred_fallback", "n_fp64_patch")
+STATS_WORDS = len(STATS_FIELDS)
 
 _sig = {
     "srhd_prim2cons": [_int, _i64, _vp, _vp, ctypes.POINTER(srhd_eos), _vp],
@@ -252,7 +260,7 @@ def srhd_cfl_dt(interior, dh, c_cfl=0.5, dt_lev=None, work=None, gamma=None):
 
 
 def new_stats(device):
-    return torch.zeros(8, dtype=torch.int64, device=device)
+    return torch.zeros(STATS_WORDS, dtype=torch.int64, device=device)
 
 
 def stats_dict(stats):
@@ -296,6 +304,25 @@ def _patches(padded, dh, level, ghost):
     return d
 
 
+def defer_workspace(n_patch, device):
+    """Workspace of the precision guard for a step of n_patch patches."""
+    return torch.empty(n_patch + 2, dtype=torch.int64, device=device)
+
+
+def _guard(prm, kappa_max, defer, n_patch, device):
+    """Set the precision guard of prm; returns the workspace (kept alive by the caller)."""
+    prm.kappa_max = float(kappa_max)
+    if prm.kappa_max == 0.0 or prm.prec == PREC_FP64:
+        prm.defer = None
+        return None
+    if defer is None:
+        defer = defer_workspace(n_patch, device)
+    elif defer.dtype != torch.int64 or defer.numel() < n_patch + 2 or not defer.is_cuda:
+        raise ValueError("defer must be a CUDA int64 tensor of at least n_patch + 2 words")
+    prm.defer = defer.data_ptr()
+    return defer
+
+
 def _params(theta, riemann, prec, max_retry, guess, sched, energy=ENERGY_REDUCED, integrator=MHM,
             flux_out=None, gamma=None):
     prm = srhd_step_params()
@@ -328,7 +355,8 @@ def _table(table, n):
 
 def srhd_autotune_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann=HLLC,
                        prec=PREC_FP64, max_retry=4, ghost=None, guess=None, reps=2,
-                       energy=ENERGY_REDUCED, integrator=MHM):
+                       energy=ENERGY_REDUCED, integrator=MHM, kappa_max=KAPPA_MAX_DEFAULT,
+                       defer=None):
     """Times the candidate schedules of srhd_fluid_step on these patches; returns (Sched of the
     fastest, [(groups, chunk, occupancy, ms per step), ...])."""
     _need_cuda(padded, dt_lev, level)
@@ -338,6 +366,7 @@ def srhd_autotune_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riem
     sch = Sched(0, 1, padded.device)
     d = _patches(padded, dh, level, ghost)
     prm = _params(theta, riemann, prec, max_retry, guess, sch, energy, integrator)
+    ws = _guard(prm, kappa_max, defer, P, padded.device)  # noqa: F841  (alive across the call)
     table = (srhd_tune_entry * 32)()
     n = _int(0)
     _check(_lib.srhd_autotune_step(ctypes.byref(d), _ptr(out), _ptr(dt_lev), ctypes.byref(prm),
@@ -362,7 +391,7 @@ def _grid(cons, prims, neighbor, dh, level):
 
 def srhd_autotune_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, dt_lev=None,
                             level=None, theta=1.5, riemann=HLLC, prec=PREC_FP64, max_retry=4,
-                            guess=None, reps=2):
+                            guess=None, reps=2, kappa_max=KAPPA_MAX_DEFAULT, defer=None):
     """Times the candidate schedules of srhd_fluid_step_grid on this block; returns (Sched of
     the fastest, [(groups, chunk, occupancy, ms per step), ...])."""
     _need_cuda(cons, prims, neighbor, smax_in, dt_lev, level)
@@ -372,6 +401,7 @@ def srhd_autotune_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, 
     sch = Sched(0, 1, cons.device)
     gr = _grid(cons, prims, neighbor, dh, level)
     prm = _params(theta, riemann, prec, max_retry, guess, sch)
+    ws = _guard(prm, kappa_max, defer, cons.shape[0], cons.device)  # noqa: F841
     table = (srhd_tune_entry * 32)()
     n = _int(0)
     _check(_lib.srhd_autotune_step_grid(ctypes.byref(gr), _ptr(smax_in), float(c_cfl), _ptr(dt_lev),
@@ -384,11 +414,14 @@ def srhd_autotune_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, 
 
 def srhd_fluid_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann=HLLC,
                     prec=PREC_FP64, max_retry=4, stats=None, ghost=None, guess=None, sched=None,
-                    energy=ENERGY_REDUCED, integrator=MHM, flux_out=None, gamma=None):
+                    energy=ENERGY_REDUCED, integrator=MHM, flux_out=None, gamma=None,
+                    kappa_max=KAPPA_MAX_DEFAULT, defer=None):
     """One MUSCL-Hancock (or, integrator=VL, VL) step: padded cons [P][5][N][N][N] -> interior
     [P][5][8][8][8].  energy=ENERGY_TOTAL runs the original scheme on (D, M, E); flux_out
     ([P][6][5][64] FP64) receives the fluxes through the patch faces; gamma selects the
-    polytropic EoS."""
+    polytropic EoS.  With an FP32 bulk (prec MIXED or FP32) the precision guard steps the patches
+    holding a cell with 1 + M^2 > kappa_max in FP64 (0 turns it off); defer (int64, >= P + 2
+    words) is its workspace, allocated per call when None."""
     _need_cuda(padded, dt_lev, level, stats, flux_out)
     P = padded.shape[0]
     N = padded.shape[-1]
@@ -398,6 +431,7 @@ def srhd_fluid_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann
     _need_cuda(out)
     d = _patches(padded, dh, level, g)
     prm = _params(theta, riemann, prec, max_retry, guess, sched, energy, integrator, flux_out, gamma)
+    ws = _guard(prm, kappa_max, defer, P, padded.device)  # noqa: F841  (alive across the call)
     _check(_lib.srhd_fluid_step(ctypes.byref(d), _ptr(out), _ptr(dt_lev), ctypes.byref(prm),
                                 _ptr(stats), _stream()))
     return out
@@ -430,7 +464,8 @@ def smax_value(bits):
 def srhd_fluid_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, dt_lev=None,
                          level=None, cons_out=None, prims_out=None, smax_out=None, dt_used=None,
                          theta=1.5, riemann=HLLC, prec=PREC_FP64, max_retry=4, stats=None,
-                         guess=None, sched=None, gamma=None):
+                         guess=None, sched=None, gamma=None, kappa_max=KAPPA_MAX_DEFAULT,
+                         defer=None):
     """One step of a block of same-level patches (ghosts gathered from neighbour interiors).
     Returns (cons_out, prims_out, smax_out)."""
     _need_cuda(cons, prims, neighbor, smax_in, dt_lev, level, stats)
@@ -446,6 +481,7 @@ def srhd_fluid_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, dt_
         raise TypeError("primitives must be %s for this precision" % prims_dtype(prec))
     gr = _grid(cons, prims, neighbor, dh, level)
     prm = _params(theta, riemann, prec, max_retry, guess, sched, gamma=gamma)
+    ws = _guard(prm, kappa_max, defer, P, cons.device)  # noqa: F841  (alive across the call)
     _check(_lib.srhd_fluid_step_grid(ctypes.byref(gr), _ptr(smax_in), float(c_cfl), _ptr(dt_lev),
                                      _ptr(cons_out), _ptr(prims_out), _ptr(smax_out),
                                      _ptr(dt_used), ctypes.byref(prm), _ptr(stats), _stream()))

@@ -41,3 +41,64 @@ def unsoa(a, P):
 
 def oracle_cons(grid):
     return unsoa(O.prim2cons(soa(grid.prim)), grid.n_patch)
+
+
+# ----------------------------------------------------------------------------- Eq. 20 bounds
+U32 = 2.0 ** -24          # unit roundoff of FP32
+U64 = 2.0 ** -53          # unit roundoff of FP64
+
+
+def kappa_prim(prim):
+    """Eq. 20's conversion condition number 1 + M^2 of primitive states [5][...] (rho, U, p),
+    M = U / U_s the Mach number in four-velocities, U_s^2 = c_s^2 / (1 - c_s^2)."""
+    rho, p = prim[0], prim[4]
+    th = (p / rho).ravel()
+    uniq, inv = np.unique(th, return_inverse=True)
+    cs2 = np.array([O.cs2(t) for t in uniq])[inv].reshape(rho.shape)
+    u2 = prim[1] ** 2 + prim[2] ** 2 + prim[3] ** 2
+    return 1.0 + u2 * (1.0 - cs2) / cs2
+
+
+def stencil_mask():
+    """The cells of a patch's [-2, 10)^3 box that one MUSCL-Hancock step reads: the half-step
+    cells (the interior and the first ghost layer across each face) and their face neighbours.
+    Boolean [12][12][12] indexed [z][y][x]."""
+    def half(i, j, k):
+        out = 0
+        for c in (i, j, k):
+            if 0 <= c < 8:
+                continue
+            if c in (-1, 8):
+                out += 1
+            else:
+                return False
+        return out <= 1
+    m = np.zeros((12, 12, 12), dtype=bool)
+    for k in range(-2, 10):
+        for j in range(-2, 10):
+            for i in range(-2, 10):
+                m[k + 2, j + 2, i + 2] = any(half(i + a, j + b, k + c) for a, b, c in
+                                             ((0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0),
+                                              (0, -1, 0), (0, 0, 1), (0, 0, -1)))
+    return m
+
+
+def tile_max(q, neighbor):
+    """Per patch, the largest value of a per-cell quantity q [P][8][8][8] over the cells its
+    step reads (ghost cells by the oracle's fill: periodic / outflow copies)."""
+    P = q.shape[0]
+    five = np.zeros((P, 5, 8, 8, 8))
+    five[:, 0] = q
+    pad = O.fill_ghosts(five, neighbor, 2)[:, 0]
+    m = stencil_mask()
+    return pad.reshape(P, -1)[:, m.ravel()].max(axis=1)
+
+
+def patch_errors(gpu, ref):
+    """Per patch [P]: the largest of the pointwise relative errors of D and Et and of the momentum
+    errors against the grid maximum of |M| (the metric of step_errors, patch by patch)."""
+    eD = np.max(np.abs(gpu[:, 0] / ref[:, 0] - 1).reshape(gpu.shape[0], -1), axis=1)
+    eE = np.max(np.abs(gpu[:, 4] / ref[:, 4] - 1).reshape(gpu.shape[0], -1), axis=1)
+    scale = max(float(np.max(np.sqrt((ref[:, 1:4] ** 2).sum(axis=1)))), 1e-300)
+    eM = np.max(np.abs(gpu[:, 1:4] - ref[:, 1:4]).reshape(gpu.shape[0], -1), axis=1) / scale
+    return np.maximum(np.maximum(eD, eE), eM)

@@ -49,7 +49,7 @@ def test_argument_errors_are_reported_without_a_gpu(lib):
     assert b"overlap" in lib.srhd_last_error()
     assert lib.srhd_prim2cons(0, 1, a + 1, a + 400, None, None) == -1      # misaligned
     lib.srhd_abi_version.restype = ctypes.c_int
-    assert lib.srhd_abi_version() == 5
+    assert lib.srhd_abi_version() == 6
 
 
 def test_step_descriptor_checks(lib):
@@ -164,6 +164,23 @@ def test_schedule_checks(lib):
     assert call() == -3 and b"polytropic" in S._lib.srhd_last_error()
     prm.integrator = 0
     prm.eos = S.srhd_eos(0, 0.0)
+    # the precision guard: kappa_max 0 or >= 1; an FP32 bulk needs an aligned workspace that
+    # overlaps no other array of the call
+    prm.prec = 1
+    for bad_k in (0.5, -1.0, float("nan")):
+        prm.kappa_max = bad_k
+        assert call() == -1 and b"kappa_max" in S._lib.srhd_last_error()
+    prm.kappa_max = 1024.0
+    prm.defer = None
+    assert call() == -1 and b"defer" in S._lib.srhd_last_error()
+    ws = ctypes.create_string_buffer(8 * 8 + 64)
+    prm.defer = al(ws) + 4
+    assert call() == -1 and b"defer" in S._lib.srhd_last_error()
+    prm.defer = al(out)
+    assert call() == -1 and b"overlaps" in S._lib.srhd_last_error()
+    prm.prec = 0
+    prm.defer = None
+    prm.kappa_max = 0.0
     q = S.srhd_step_params()
     q.eos = S.srhd_eos(1, 4.0 / 3.0)
     assert S._lib.srhd_step_occupancy(ctypes.byref(q), 1) == -3

@@ -253,6 +253,37 @@ def riemann_1d(n_cells_x, left, right, x0=0.5, length=1.0, ny=1, nz=1):
                      extra={"x": np.ascontiguousarray(x)})
 
 
+def jet_block(n_cells=32, seed=1006, radius=0.2, z_top=0.6, amp=1e-3):
+    """The jet's two states (jet_states) on a small outflow block: the nozzle state inside a
+    cylinder of the given radius around the z axis through the block centre, for z < z_top, the
+    ambient state elsewhere; every density multiplied by 1 + amp xi, xi ~ U[-1, 1).  A small
+    stand-in for the nozzle region of the jet patch list, with non-uniform nozzle cells."""
+    n = n_cells // PS
+    dh = 1.0 / n_cells
+    x, y, z = patch_cell_centres(n, n, n, dh)
+    st = jet_states()
+    inside = ((x - 0.5) ** 2 + (y - 0.5) ** 2 < radius * radius) & (z < z_top)
+    prim = np.ascontiguousarray(np.moveaxis(st[inside.astype(np.int64)], -1, 1))
+    rng = np.random.default_rng(seed)
+    prim[:, 0] *= 1.0 + amp * rng.uniform(-1.0, 1.0, size=prim[:, 0].shape)
+    return PatchGrid("jet_block_%d" % n_cells, prim, n, n, n, False, dh,
+                     extra={"labels": inside.astype(np.uint8)})
+
+
+def moving_gas(n_cells=32, U=3.0, theta=1e-2, amp=1e-3, seed=1007):
+    """Uniform flow of four-velocity magnitude U along (1, 1, 1) / sqrt(3) at temperature theta
+    (rho = 1) on a periodic block, with rho and p each multiplied by an independent 1 + amp xi,
+    xi ~ U[-1, 1)."""
+    n = n_cells // PS
+    P = n ** 3
+    rng = np.random.default_rng(seed)
+    prim = np.empty((P, 5, PS, PS, PS))
+    prim[:, 0] = 1.0 + amp * rng.uniform(-1.0, 1.0, size=(P, PS, PS, PS))
+    prim[:, 1:4] = U / np.sqrt(3.0)
+    prim[:, 4] = theta * (1.0 + amp * rng.uniform(-1.0, 1.0, size=(P, PS, PS, PS)))
+    return PatchGrid("moving_gas_%d" % n_cells, prim, n, n, n, True, 1.0 / n_cells)
+
+
 # ----------------------------------------------------------------------------- two AMR levels
 def two_level(nc, lo, hi):
     """Geometry of a periodic two-level patch hierarchy (refinement ratio 2).
