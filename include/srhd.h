@@ -269,6 +269,22 @@ int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
                     const srhd_step_params *prm, srhd_step_stats *stats, void *stream);
 /* (prm->integrator selects MUSCL-Hancock or VL: see srhd_integrator.) */
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): srhd_fluid_step with its two work buffers -- the
+ * precision guard's list (prm->defer) and the persistent schedule's counters
+ * (prm->sched.queue) -- taken from a static device array of the library instead of the caller.
+ * The array holds SRHD_QUEUE_WORDS + SRHD_STATIC_MAX_PATCH + 2 uint64 words (about 8 MiB) on
+ * every GPU the library runs on, until the process ends; its device address is looked up on
+ * the first call on each device.  Arguments and results as for srhd_fluid_step, except:
+ * prm->defer and prm->sched.queue must be NULL, and n_patch may not exceed SRHD_STATIC_MAX_PATCH
+ * (else SRHD_EINVAL before any launch).  The call allocates nothing.  Every call on one GPU
+ * shares that GPU's array (the call clears what must start at zero, on its stream): calls that
+ * overlap in time on one GPU -- on different streams, or from different threads -- race and
+ * must not be issued. */
+#define SRHD_STATIC_MAX_PATCH 1048576
+int srhd_fluid_step_static(const srhd_patches *in, void *out, const double *dt_lev,
+                           const srhd_step_params *prm, srhd_step_stats *stats, void *stream);
+
 /* Workgroups of the step kernel that fit on one compute unit at once for the kernel that
  * prm (host) selects -- its precision, guess kind, register variant (prm->sched.occupancy),
  * energy variable and integrator -- and the layout (gather = 1: srhd_fluid_step_grid, 0:

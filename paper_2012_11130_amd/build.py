@@ -15,7 +15,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsrhd.so")
 SOURCES = ["srhd_capi.cpp", "srhd_kernels.hip", "srhd_step.hip", "srhd_step_fp64.hip",
            "srhd_step_mixed.hip", "srhd_step_fp32.hip", "srhd_step_vl.hip", "srhd_amr.hip",
-           "srhd_mlp.hip"]
+           "srhd_mlp.hip", "srhd_static.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

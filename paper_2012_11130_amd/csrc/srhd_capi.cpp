@@ -19,6 +19,23 @@ int fail(int code, const char *fmt, ...)
   return code;
 }
 
+}  // namespace
+
+namespace srhd {
+
+int set_error(int code, const char *fmt, ...)
+{
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+}  // namespace srhd
+
+namespace {
+
 int hip_status(hipError_t e, const char *what)
 {
   if (e == hipSuccess) return SRHD_OK;

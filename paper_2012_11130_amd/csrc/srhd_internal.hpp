@@ -8,6 +8,9 @@
 
 namespace srhd {
 
+// Records the message that srhd_last_error() returns (this thread) and returns code.
+int set_error(int code, const char *fmt, ...);
+
 struct GuessArgs {
   int kind;                // srhd_guess_kind
   int max_iter;

@@ -110,6 +110,8 @@ _sig = {
     "srhd_stats_reset": [_vp, _vp],
     "srhd_fluid_step": [ctypes.POINTER(srhd_patches), _vp, _vp,
                         ctypes.POINTER(srhd_step_params), _vp, _vp],
+    "srhd_fluid_step_static": [ctypes.POINTER(srhd_patches), _vp, _vp,
+                               ctypes.POINTER(srhd_step_params), _vp, _vp],
     "srhd_grid_prims": [_int, _i64, _vp, _vp, _vp, ctypes.POINTER(srhd_guess), _vp],
     "srhd_mlp_features": [_int, _int, _i64, _vp, _vp, _vp, _vp, _vp],
     "srhd_mlp_forward": [ctypes.POINTER(srhd_mlp), _i64, _vp, _vp, _vp],
@@ -434,6 +436,33 @@ def srhd_fluid_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann
     ws = _guard(prm, kappa_max, defer, P, padded.device)  # noqa: F841  (alive across the call)
     _check(_lib.srhd_fluid_step(ctypes.byref(d), _ptr(out), _ptr(dt_lev), ctypes.byref(prm),
                                 _ptr(stats), _stream()))
+    return out
+
+
+STATIC_MAX_PATCH = 1048576
+
+
+def srhd_fluid_step_static(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann=HLLC,
+                           prec=PREC_FP64, max_retry=4, stats=None, ghost=None, guess=None,
+                           groups=0, chunk=1, occupancy=0, kappa_max=KAPPA_MAX_DEFAULT):
+    """srhd_fluid_step without caller work buffers: the precision guard's list and the persistent
+    schedule's counters live in the library's static device array (at most STATIC_MAX_PATCH
+    patches; concurrent calls on one GPU race).  `out` must be supplied by a caller that cannot
+    allocate; it is allocated here only for convenience."""
+    _need_cuda(padded, dt_lev, level, stats)
+    P = padded.shape[0]
+    N = padded.shape[-1]
+    g = (N - 8) // 2 if ghost is None else ghost
+    if out is None:
+        out = torch.empty((P, 5, 8, 8, 8), dtype=torch.float64, device=padded.device)
+    _need_cuda(out)
+    d = _patches(padded, dh, level, g)
+    prm = _params(theta, riemann, prec, max_retry, guess, None)
+    prm.sched = srhd_sched(int(groups), int(chunk), int(occupancy), None)
+    prm.kappa_max = float(kappa_max)
+    prm.defer = None
+    _check(_lib.srhd_fluid_step_static(ctypes.byref(d), _ptr(out), _ptr(dt_lev),
+                                       ctypes.byref(prm), _ptr(stats), _stream()))
     return out
 
 

@@ -181,6 +181,17 @@ def test_schedule_checks(lib):
     prm.prec = 0
     prm.defer = None
     prm.kappa_max = 0.0
+    # the allocation-free step: at most SRHD_STATIC_MAX_PATCH patches, no caller work buffers
+    d.n_patch = S.STATIC_MAX_PATCH + 1
+    rc = S._lib.srhd_fluid_step_static(ctypes.byref(d), al(out), al(dt), ctypes.byref(prm), None,
+                                       None)
+    assert rc == -1 and b"static" in S._lib.srhd_last_error()
+    d.n_patch = 4
+    prm.defer = al(ws)
+    rc = S._lib.srhd_fluid_step_static(ctypes.byref(d), al(out), al(dt), ctypes.byref(prm), None,
+                                       None)
+    assert rc == -1 and b"defer" in S._lib.srhd_last_error()
+    prm.defer = None
     q = S.srhd_step_params()
     q.eos = S.srhd_eos(1, 4.0 / 3.0)
     assert S._lib.srhd_step_occupancy(ctypes.byref(q), 1) == -3
