@@ -34,11 +34,14 @@ PEAK_HBM = 8.0e12        # bytes/s
 # Algorithmic floating-point operations of the step (each +, -, *, /, sqrt counts 1, an FMA 2),
 # counted from the formulas the kernel evaluates; per item:
 FLOP_NEWTON_ITER = 48    # one Newton iteration (Eqs. 15, 16, A1, A2)
-FLOP_INVERSION = 192     # exact L (error-free products + K=3 compensated sum), guess, recovery
+FLOP_INV_REST = 58       # an inversion besides L and its iterations: guess, recovery
+FLOP_L_EXACT = 134       # L from error-free products and the K=3 compensated sum (FP64 bulk)
+FLOP_L_PLAIN = 14        # L from the plain sum of the exact products: the branch the FP32-bulk
+                         # kernels take where every lane of a wavefront has cond <= 1024
 FLOP_HALF_CELL = 570     # 15 slopes, 6 face states -> prim2cons + flux, half-step correction
 FLOP_FACE = 105          # slope + face state + prim2cons + correction (inversion counted apart)
 FLOP_RIEMANN = 260       # HLLC: 2 prim2cons, 2 fluxes, 4 signal speeds, HLL averages, star state
-FLOP_UPDATE = 180        # flux differences, update, exact-L admissibility check of the output
+FLOP_UPDATE = 46         # flux differences and update of an output cell (its L counted apart)
 FLOP_MLP_VALU = 1088     # learned guess, VALU part: features and standardisation (~20), layer 1
                          # (64 x 3 FMA = 384), 128 SiLU (exp, add, reciprocal, multiply = 512),
                          # layer 3 (64 FMA = 128), partner-lane sum and exponential (~44)
@@ -49,12 +52,13 @@ IO_BYTES_PER_PATCH = {                         # what one patch's step consumes 
     "grid": 1376 * 5 * 4 + 512 * 5 * (8 + 8 + 4),   # FP32 tile prims, cons in/out, prims out
 }
 
-# HBM bytes per launch of the headline step kernel (mixed precision, learned guess, gather layout,
-# the two-workgroup register variant) on this workload, from the rocprofv3 FETCH_SIZE /
-# WRITE_SIZE runs summarised in profiles/step_blast256_grid_learned.md; valid only for the kernel
-# sources they were taken on (hash of the files that make up the step kernel).
-PROFILED_TRAFFIC = {"sources_sha256_16": "cc158bd1257fbfe6", "read": 1299.7e6, "write": 1009.8e6,
-                    "path": "grid", "summary": "profiles/step_blast256_grid_learned.md"}
+# Hardware counters of the step kernels on this workload (rocprofv3 FETCH_SIZE / WRITE_SIZE,
+# rescaled by a plain copy's reading, and the VALU instruction counters: FP64 + FP32 flops with an
+# FMA as 2), summarised in the profile named below; valid only for the kernel sources they were
+# taken on (hash of the files that make up the step kernel).  headline: the mixed-precision step
+# with the learned guess, gather layout, two-workgroup register variant; fp64: the FP64 step.
+PROFILED = {"sources_sha256_16": "", "path": "grid", "summary": "profiles/step_blast256_counters.md",
+            "headline": None, "fp64": None}
 STEP_SOURCES = ("srhd_step_impl.hpp", "srhd_step_mixed.hip", "srhd_device.hpp", "srhd_mlp.hpp")
 
 
@@ -78,14 +82,20 @@ def step_sources_hash():
     return h.hexdigest()[:16]
 
 
-def step_flops(n_patch, stats):
-    """Algorithmic VALU FLOPs of one step launch from its device counters; the learned guess's
-    VALU work counts per network evaluation (n_mlp), its matrix-core work apart."""
+def step_flops(n_patch, stats, fp32_bulk, gather):
+    """Algorithmic VALU FLOPs of one step launch from its device counters, with L at the cost
+    of the branch the kernel takes: the plain sum of the exact products in the FP32-bulk kernels
+    (their rare compensated sums, in wavefronts holding a lane with cond > 1024, are not
+    counted), the compensated sum in FP64.  A gather-layout output inversion reuses the L of its
+    cell's check.  The learned guess's VALU work counts per network evaluation (n_mlp), its
+    matrix-core work apart."""
+    L = FLOP_L_PLAIN if fp32_bulk else FLOP_L_EXACT
     attempts = n_patch + stats["n_retry"]
+    out_inv = OUT_CELLS * n_patch if gather else 0
     return (attempts * (HALF_CELLS * FLOP_HALF_CELL + 2 * INTERFACES * FLOP_FACE
-                        + INTERFACES * FLOP_RIEMANN + OUT_CELLS * FLOP_UPDATE)
-            + stats["n_inversions"] * FLOP_INVERSION + stats.get("n_mlp", 0) * FLOP_MLP_VALU
-            + stats["newton_iters"] * FLOP_NEWTON_ITER)
+                        + INTERFACES * FLOP_RIEMANN + OUT_CELLS * (FLOP_UPDATE + L))
+            + stats["n_inversions"] * FLOP_INV_REST + (stats["n_inversions"] - out_inv) * L
+            + stats.get("n_mlp", 0) * FLOP_MLP_VALU + stats["newton_iters"] * FLOP_NEWTON_ITER)
 
 
 def summarize_profile(d, calib_mib):
@@ -183,7 +193,12 @@ def run_jet(args, S, W, dev, stream, guess, guess_name):
     S.srhd_cfl_dt(interior, dh, 0.5, dt_lev=dt)
     res = {"patches": P, "cells": P * 512, "levels": [int((pl["level"] == l).sum()) for l in range(len(dh))]}
     for name, prec, g in (("mixed", S.PREC_MIXED, guess), ("fp64", S.PREC_FP64, None)):
-        sch, table = S.srhd_autotune_step(pad, dt, dh, level=level, out=out, prec=prec, guess=g, reps=2)
+        if args.sched != "auto":
+            gr, ch, oc = (int(v) for v in args.sched.split(","))
+            sch, table = S.Sched(gr, ch, dev, occupancy=0 if prec == S.PREC_FP64 else oc), []
+        else:
+            sch, table = S.srhd_autotune_step(pad, dt, dh, level=level, out=out, prec=prec, guess=g,
+                                              reps=2)
         for _ in range(args.warmup):
             S.srhd_cfl_dt(interior, dh, 0.5, dt_lev=dt)
             S.srhd_fluid_step(pad, dt, dh, level=level, out=out, prec=prec, guess=g, sched=sch)
@@ -214,11 +229,103 @@ def run_jet(args, S, W, dev, stream, guess, guess_name):
                      "autotune_ms": [[t[0], t[1], t[2], round(t[3], 3)] for t in table],
                      "iters_per_inversion": st["newton_iters"] / inv,
                      "fallback_rate": st["n_fallback"] / inv,
-                     "retries_per_step": st["n_retry"] / args.steps}
+                     "retries_per_step": st["n_retry"] / args.steps,
+                     "fp64_patches_per_step": st["n_fp64_patch"] / args.steps}
         print("# jet %s: %.2f ms per step, schedule %s" % (name, ms, sch), file=sys.stderr, flush=True)
-    del pad, interior, out
+    # per-field difference of one step from the initial state against the FP64 step, with the
+    # precision guard (the default) and without it (kappa_max = 0: the FP32 bulk everywhere)
+    S.srhd_cfl_dt(interior, dh, 0.5, dt_lev=dt)
+    o64 = S.srhd_fluid_step(pad, dt, dh, level=level, prec=S.PREC_FP64)
+    omx = S.srhd_fluid_step(pad, dt, dh, level=level, prec=S.PREC_MIXED, guess=guess)
+    res["mixed_vs_fp64_rel_err_one_step"] = field_err_torch(omx, o64)
+    del omx
+    ooff = S.srhd_fluid_step(pad, dt, dh, level=level, prec=S.PREC_MIXED, guess=guess, kappa_max=0.0)
+    res["mixed_unguarded_vs_fp64_rel_err_one_step"] = field_err_torch(ooff, o64)
+    print("# jet one step vs FP64: guarded %s, unguarded %s"
+          % (res["mixed_vs_fp64_rel_err_one_step"], res["mixed_unguarded_vs_fp64_rel_err_one_step"]),
+          file=sys.stderr, flush=True)
+    del ooff, o64, pad, interior, out
     torch.cuda.empty_cache()
     return res
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oracle_conversion_parity(O, samples, threads):
+    """Oracle inversion of the sampled conserved states of each variant ({name: (cons [5][m],
+    GPU prims [5][m] as FP64, GPU status [m])}): oracle states/s, identical UNPHYSICAL flags and
+    the GPU's per-field error (rho, p pointwise relative, U normwise per state) over the states
+    both accept."""
+    out = {}
+    for name, (cons, gp, gst) in samples.items():
+        c = np.ascontiguousarray(cons.astype(np.float64))
+        t = time.perf_counter()
+        ref, ost, _ = O.cons2prim(c)
+        dt_ = time.perf_counter() - t
+        ok = (ost != 1) & (gst != 1)
+        g, r = gp[:, ok], ref[:, ok]
+        un = np.maximum(np.sqrt((r[1:4] ** 2).sum(axis=0)), 1e-300)
+        out[name] = {"states": int(c.shape[1]), "oracle_states_per_s": c.shape[1] / dt_,
+                     "cores": threads,
+                     "unphysical_flags_equal": bool(np.array_equal(ost == 1, gst == 1)),
+                     "rho": float(np.max(np.abs(g[0] / r[0] - 1))),
+                     "p": float(np.max(np.abs(g[4] / r[4] - 1))),
+                     "U": float(np.max(np.max(np.abs(g[1:4] - r[1:4]), axis=0) / un))}
+    return out
+
+
+def roundtrip_by_cond(prim, gen, status, cond, u):
+    """Round-trip error of an inversion (prim [5][n], any float type) against the generating
+    primitives gen [5][n] (FP64), per decade of Eq. 20's condition number: rho and p pointwise
+    relative, U normwise per state; over the states not flagged unphysical.  Each bin reports
+    the count, the median and largest error per field and the largest error / (cond u)."""
+    import torch
+    ok = status != 1
+    w = prim.double()
+    er = (w[0] / gen[0] - 1).abs()
+    ep = (w[4] / gen[4] - 1).abs()
+    un = torch.sqrt((gen[1:4] ** 2).sum(dim=0)).clamp_min(1e-300)
+    eu = (w[1:4] - gen[1:4]).abs().amax(dim=0) / un
+    lg = torch.floor(torch.log10(cond.clamp(1.0, 1e30)))
+    bins = []
+    for b in range(0, 31):
+        m = ok & (lg == b)
+        c = int(m.sum().item())
+        if c == 0:
+            continue
+        row = {"cond_decade": "1e%d" % b, "states": c}
+        worst = 0.0
+        for name, e in (("rho", er), ("p", ep), ("U", eu)):
+            v = e[m]
+            row[name + "_median"] = float(v.median().item())
+            row[name + "_max"] = float(v.max().item())
+            worst = max(worst, float((v / (cond[m] * u)).max().item()))
+        row["max_err_over_cond_u"] = worst
+        bins.append(row)
+    del er, ep, eu, lg
+    return bins
+
+
+def field_err_torch(x, ref):
+    """Per-field difference of two step outputs [P][5][8][8][8] on the device: D and Et pointwise
+    relative, the momentum against the largest |M| of ref (the parity tests' metric)."""
+    import torch
+    e = {}
+    for f, name in ((0, "D"), (4, "Et")):
+        e[name] = float((x[:, f] / ref[:, f] - 1).abs().max().item())
+    ms = float(torch.sqrt((ref[:, 1:4] ** 2).sum(dim=1)).max().item())
+    e["M"] = float((x[:, 1:4] - ref[:, 1:4]).abs().max().item()) / max(ms, 1e-300)
+    e["non_finite_cells"] = int((~torch.isfinite(x)).any(dim=1).sum().item())
+    return e
 
 
 def parse():
@@ -419,11 +526,28 @@ def main():
     guess_name = ("learned (BF16 MLP on log L, log m, log x; consulted where L > %g)" % mlp.gate
                   if mlp is not None else "analytic")
 
+    # achievable HBM bandwidth: a plain device-to-device copy of 2 GiB, read once and written once
+    src = torch.ones(1 << 28, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(10):
+        dst.copy_(src)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    tcopy = c0.elapsed_time(c1) / 10 * 1e-3
+    stream_copy = {"bytes_per_copy": 2 * src.numel() * 8, "GBps": 2 * src.numel() * 8 / tcopy / 1e9,
+                   "frac_of_8TBps": 2 * src.numel() * 8 / tcopy / PEAK_HBM}
+    del src, dst
+    print("# stream copy: %.0f GB/s" % stream_copy["GBps"], file=sys.stderr, flush=True)
+
     ms_mx, kms_mx, st_mx, fin_mx = measure(S.PREC_MIXED, guess, "headline")
     print("# mixed, %s guess: %.2f ms for %d steps (step kernel %.3f ms avg); stats %s"
           % (guess_name, ms_mx, args.steps, float(np.mean(kms_mx)), st_mx), file=sys.stderr, flush=True)
     value = n_cells * args.steps / (ms_mx * 1e-3)
-    res = {"newton": {"headline": newton_summary(st_mx)}}
+    res = {"newton": {"headline": newton_summary(st_mx)}, "stream_copy": stream_copy}
     if mlp is not None and not args.only_headline:
         ms_an, kms_an, st_an, fin_an = measure(S.PREC_MIXED, None, "mixed_analytic")
         print("# mixed, analytic guess: %.2f ms for %d steps (step kernel %.3f ms avg); stats %s"
@@ -636,23 +760,49 @@ def main():
     # ---------------------------------------------------------------- roofline of the step kernel
     kavg = float(np.mean(kms_mx)) * 1e-3
     per_launch = {k: v / args.steps for k, v in st_mx.items()}
-    flops = step_flops(P, per_launch)
-    traffic = None
-    if (step_sources_hash() == PROFILED_TRAFFIC["sources_sha256_16"] and args.cells == 256
-            and args.path == PROFILED_TRAFFIC.get("path", "padded") and mlp is not None
+    flops = step_flops(P, per_launch, True, args.path == "grid")
+    prof = None
+    if (step_sources_hash() == PROFILED["sources_sha256_16"] and args.cells == 256
+            and args.path == PROFILED["path"] and mlp is not None
             and schedules.get("headline", {}).get("occupancy") == 2):
-        traffic = PROFILED_TRAFFIC["read"] + PROFILED_TRAFFIC["write"]
+        prof = PROFILED["headline"]
+    io = IO_BYTES_PER_PATCH[args.path] * P
     roofline = {"bound": "alu", "achieved": flops / kavg / 1e12, "peak": PEAK_ALU / 1e12,
-                "unit": "TFLOP/s", "frac": flops / kavg / PEAK_ALU, "traffic": traffic,
+                "unit": "TFLOP/s", "frac": flops / kavg / PEAK_ALU,
+                "traffic": (prof["read"] + prof["write"]) if prof else None,
                 "kernel": "k_step<float,%s,%s> (mixed)" % ("gather" if args.path == "grid" else "padded",
                                                            "mlp" if mlp is not None else "analytic"),
-                "launch_ms": kavg * 1e3,
-                "hbm_GBps_algorithmic": IO_BYTES_PER_PATCH[args.path] * P / kavg / 1e9,
-                "flops_per_launch": flops}
+                "launch_ms": kavg * 1e3, "flops_per_launch": flops,
+                "flops_note": "L charged at the plain-sum cost the FP32-bulk kernel takes where a "
+                              "wavefront is well conditioned (compensated fallbacks not counted)",
+                "hbm_GBps_algorithmic": io / kavg / 1e9, "hbm_frac_algorithmic": io / kavg / PEAK_HBM,
+                "hbm_frac_of_stream_copy": io / kavg / (stream_copy["GBps"] * 1e9)}
+    if prof:
+        roofline["counters"] = {"summary": PROFILED["summary"], "profiled_ms": prof["ms"],
+                                "flops_per_launch": prof["flops"],
+                                "frac": prof["flops"] / (prof["ms"] * 1e-3) / PEAK_ALU,
+                                "hbm_frac": (prof["read"] + prof["write"]) / (prof["ms"] * 1e-3) / PEAK_HBM,
+                                "valu_issue_frac": prof["valu_issue"]}
     if mlp is not None:
         mf = per_launch["n_mlp"] * MFMA_FLOP_MLP
         roofline["mfma_bf16"] = {"flops_per_launch": mf, "achieved_TFLOPs": mf / kavg / 1e12,
                                  "frac_of_2500": mf / kavg / 2.5e15}
+    if "fp64" in res and args.path == "grid":
+        k64 = res["fp64"]["step_kernel_ms"] * 1e-3
+        pl64 = {k: v / args.steps for k, v in res["fp64"]["stats"].items()}
+        f64 = step_flops(P, pl64, False, True)
+        io64 = (1376 * 5 * 8 + 512 * 5 * (8 + 8 + 8)) * P
+        res["fp64"]["roofline"] = {"bound": "alu", "achieved": f64 / k64 / 1e12, "unit": "TFLOP/s",
+                                   "peak": PEAK_ALU / 1e12, "frac": f64 / k64 / PEAK_ALU,
+                                   "flops_per_launch": f64, "launch_ms": k64 * 1e3,
+                                   "hbm_frac_algorithmic": io64 / k64 / PEAK_HBM}
+        p64 = PROFILED.get("fp64") if prof else None
+        if p64:
+            res["fp64"]["roofline"]["counters"] = {
+                "profiled_ms": p64["ms"], "flops_per_launch": p64["flops"],
+                "frac": p64["flops"] / (p64["ms"] * 1e-3) / PEAK_ALU,
+                "hbm_frac": (p64["read"] + p64["write"]) / (p64["ms"] * 1e-3) / PEAK_HBM,
+                "valu_issue_frac": p64["valu_issue"]}
 
     # ---------------------------------------------------------------- standalone conversions
     if args.conversion:
@@ -680,11 +830,25 @@ def main():
         variants = [("fp64", cc, None), ("fp32", cc.float(), None)]
         if mlp is not None:
             variants += [("fp64_learned_guess", cc, guess), ("fp32_learned_guess", variants[1][1], guess)]
+        # Eq. 20's condition number of each stored state: L's subtraction a - b with
+        # a = x^2 + 2x, b = m^2 (x = Et/D, m = |M|/D), cond = (a + b) / |a - b| (from the FP64
+        # conserved variables; about 1 + M^2)
+        xx = cc[4] / cc[0]
+        mm = (cc[1] ** 2 + cc[2] ** 2 + cc[3] ** 2) / (cc[0] ** 2)
+        aa = xx * (xx + 2.0)
+        cond = (aa + mm) / (aa - mm).abs()
+        del xx, mm, aa
+        conv_sample = {}
+        n_sample = min(n, 1_000_000)
         for name, src, gs in variants:
             o = out if src.dtype == torch.float64 else torch.empty_like(src)
             S.srhd_cons2prim(src, prim=o, status=stt, iters=its, guess=gs)
             torch.cuda.synchronize()
             mean_it = float(its.double().mean().item())
+            if gs is None:
+                conv_sample[name] = (src[:, :n_sample].cpu().numpy(), o[:, :n_sample].double().cpu().numpy(),
+                                     stt[:n_sample].cpu().numpy())
+                rt = roundtrip_by_cond(o, cp, stt, cond, 2.0 ** -53 if name == "fp64" else 2.0 ** -24)
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             reps = 5
@@ -699,8 +863,10 @@ def main():
                           "hbm_frac": n * bpe / t / PEAK_HBM, "newton_iters_mean": mean_it,
                           "unphysical_frac": float((stt == 1).float().mean().item()),
                           "fallback_frac": float((stt == 2).float().mean().item())}
+            if gs is None:
+                conv[name]["roundtrip_err_by_cond"] = rt
         res["conversion_batch_1e8"] = conv
-        del cp, cc, out, stt, its, variants
+        del cp, cc, out, stt, its, variants, cond
 
     # ---------------------------------------------------------------- jet patch list
     if args.jet:
@@ -726,10 +892,25 @@ def main():
         m = int(min(P, max(64, args.cpu_seconds / max(tp, 1e-6) * 64)))
         idx = np.sort(rng.choice(P, m, replace=False))
         tc = oracle_pass(idx)
+        # the same on one core, on a sample sized for about a third of that time
+        O.set_num_threads(1)
+        try:
+            m1 = int(max(8, min(m, (args.cpu_seconds / 3.0) / max(tc / m * threads, 1e-9))))
+            idx1 = np.sort(rng.choice(P, m1, replace=False))
+            tc1 = oracle_pass(idx1)
+        finally:
+            O.set_num_threads(threads)
         cpu = {"value": m * 512 / tc, "unit": "cell updates/s", "cores": threads,
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": cpu_model(),
                "sample": "%d random patches (%d cells) of the 256^3 blast, one FP64 step from "
-                         "the initial state: CFL + ghost fill + MUSCL-Hancock step, %.1f s" % (m, m * 512, tc)}
+                         "the initial state: CFL + ghost fill + MUSCL-Hancock step, %.1f s" % (m, m * 512, tc),
+               "one_core": {"value": m1 * 512 / tc1, "unit": "cell updates/s", "cores": 1,
+                            "sample": "%d random patches of the same, %.1f s" % (m1, tc1)}}
+        # the conversion batch: the oracle inverts the first states of each FP64 / FP32 variant
+        # (the FP32 one from its FP32 conserved variables, widened exactly), timed, and the
+        # GPU's results are compared with it state by state (outside the GPU's timed region)
+        if args.conversion and conv_sample:
+            res["conversion_batch_1e8"]["oracle_sample"] = oracle_conversion_parity(O, conv_sample, threads)
 
     line = {
         "metric": METRIC, "value": value, "unit": "cell updates/s", "n_gpus": 1,

@@ -102,3 +102,45 @@ def patch_errors(gpu, ref):
     scale = max(float(np.max(np.sqrt((ref[:, 1:4] ** 2).sum(axis=1)))), 1e-300)
     eM = np.max(np.abs(gpu[:, 1:4] - ref[:, 1:4]).reshape(gpu.shape[0], -1), axis=1) / scale
     return np.maximum(np.maximum(eD, eE), eM)
+
+
+# one-step error bound of a step per patch, (C_KAPPA kappa_tile + C_FLUX) u with u the unit
+# roundoff of the bulk arithmetic (the derivation is in tests/test_gpu_guard.py)
+C_KAPPA = 16.0
+C_FLUX = 32.0
+
+
+def step_bound(kappa_tile, u=U32):
+    return (C_KAPPA * np.asarray(kappa_tile) + C_FLUX) * u
+
+
+def _stencil_cells(pad):
+    """[P][5][1376]: the cells of padded patches [P][5][N][N][N] that one step reads."""
+    P, N = pad.shape[0], pad.shape[-1]
+    g = (N - 8) // 2
+    box = pad[:, :, g - 2:g + 10, g - 2:g + 10, g - 2:g + 10].reshape(P, 5, -1)
+    return box[:, :, stencil_mask().ravel()]
+
+
+def kappa_tile_padded(pad, whole=False):
+    """Per patch [P]: the largest kappa = 1 + M^2 over the cells its MUSCL-Hancock step reads (or,
+    whole=True, over every padded cell: the VL step reads a third ghost layer), from padded
+    conserved patches (reduced energy) by the oracle's inversion; unphysical cells are skipped."""
+    cells = pad.reshape(pad.shape[0], 5, -1) if whole else _stencil_cells(pad)
+    P = cells.shape[0]
+    prim, st, _ = O.cons2prim(np.ascontiguousarray(cells.transpose(1, 0, 2).reshape(5, -1)))
+    k = kappa_prim(prim).reshape(P, -1)
+    k[(st == 1).reshape(P, -1)] = 1.0
+    return np.nanmax(np.where(np.isfinite(k), k, 1.0), axis=1)
+
+
+def cond_total_tile_padded(pad):
+    """Per patch [P]: the largest condition number of the original scheme's L = x^2 - m^2 - 1
+    (x = E/D, m = |M|/D; Eq. 21's amplification) over the cells its step reads, from padded
+    total-energy patches: (x^2 + m^2 + 1) / |x^2 - m^2 - 1|."""
+    c = _stencil_cells(pad)
+    x2 = (c[:, 4] / c[:, 0]) ** 2
+    m2 = (c[:, 1] ** 2 + c[:, 2] ** 2 + c[:, 3] ** 2) / c[:, 0] ** 2
+    with np.errstate(divide="ignore"):
+        k = (x2 + m2 + 1.0) / np.abs(x2 - m2 - 1.0)
+    return k.max(axis=1)

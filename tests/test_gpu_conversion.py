@@ -114,9 +114,22 @@ def test_cons2prim_fp32_error_is_stated(S):
     x = Et / D
     with np.errstate(over="ignore", divide="ignore"):
         kappa = (x * x + 2 * x + M2 / D ** 2) / np.maximum(O.L_batch(cons64), 1e-300)
-    good = ok & (kappa < 1e3)
-    e = prim_errors(w, ref, good)
-    assert e["rho"] < 1e-4 and e["U"] < 1e-4 and e["p"] < 1e-3, e
+    # per state: rho and p relative, U normwise; FP32 L carries about kappa u32 of round-off
+    # (Eq. 20), which reaches Theta and p at most doubled, rho and U through gamma at most that;
+    # Newton's tolerance and the FP32 recovery add a few u32: bound 16 u32 (kappa + 4), over the
+    # states FP32 can represent at all (kappa u32 < 1e-2)
+    u32 = 2.0 ** -24
+    with np.errstate(invalid="ignore", divide="ignore"):
+        er = np.abs(w[0] / ref[0] - 1)
+        ep = np.abs(w[4] / ref[4] - 1)
+        eu = np.max(np.abs(w[1:4] - ref[1:4]), axis=0) / np.maximum(np.sqrt((ref[1:4] ** 2).sum(axis=0)), 1e-300)
+    emax = np.maximum(np.maximum(er, ep), eu)
+    rep = ok & (kappa * u32 < 1e-2)
+    ratio = emax[rep] / (u32 * (kappa[rep] + 4))
+    print("fp32 inversion: %d of %d states with kappa u32 < 1e-2; error / (u32 (kappa + 4)): "
+          "median %.3f, max %.3f; largest errors rho %.2e p %.2e U %.2e"
+          % (rep.sum(), ok.size, np.median(ratio), ratio.max(), er[rep].max(), ep[rep].max(), eu[rep].max()))
+    assert np.all(emax[rep] <= 16 * u32 * (kappa[rep] + 4))
     # Eq. 30 with the FP32 epsilon (1.2e-7) flags more states than with the FP64 one: every
     # state flagged only in FP32 must have an exact L near or below the FP32 threshold, scaled
     # by its conditioning (the FP32 L carries ~kappa eps32 of round-off)

@@ -1,4 +1,5 @@
-"""Precision guard of the FP32-bulk step (Eq. 20), through the C ABI.
+"""Precision guard of the FP32-bulk step (Eq. 20), through the C ABI, and the error bound of a
+step per patch that every FP32-bulk parity test uses.
 
 Eq. 20 puts the error of recovering the pressure from conserved variables that carry a relative
 rounding error eps at (1 + M^2) eps.  An FP32 bulk rounds the half-step face states and the
@@ -6,30 +7,35 @@ update increment to FP32, so its one-step error grows with kappa = 1 + M^2 of th
   * the jet's nozzle state (gamma = 10^3, Theta = 10^2) has kappa ~ 2e6 -- with the guard off the
     FP32 bulk moves the nozzle face pressure by about 1.5 % and the cold neighbour's reduced
     energy by as much; with the guard on (kappa_max = 1024) the patches whose tile reaches the
-    nozzle are stepped in FP64 and agree with the oracle to the FP64 tolerance;
-  * a moving gas below the threshold stays in FP32 and its error is bounded patch by patch by
-    C_MIXED kappa_tile u_32 (u_32 = 2^-24), at kappa ~ 6, 62 and 550.
-C_MIXED: the face state's conserved variables carry about 4 FP32 roundings each (prim -> cons,
-the half-step correction), which Eq. 20 turns into a relative error of about 4 kappa u_32 in L
-and at most that in Theta and p; a flux inherits at most the pressure's relative error, and the
-update adds the rounding of three flux differences in FP32 -- so C_MIXED = 16 (a factor 2 over
-4 + 3 + 1 for the rounding of the stored increment).  The pressure recovered from the updated
-conserved variables carries Eq. 20's amplification of their error once more: squares of x = Et/D
-in L double it and D's own error doubles it again, hence 4 C_MIXED kappa_tile u_32.  The same mechanism holds in FP64 with
-u_64 = 2^-53: where kappa_tile u_64 C_MIXED exceeds 1e-10 (kappa above about 6e4, the nozzle) two
-correct FP64 steps differ by that much, so FP64 parity there is judged by
-max(1e-10, C_MIXED kappa_tile u_64)."""
+    nozzle are stepped in FP64;
+  * a moving gas below the threshold stays in FP32, at kappa ~ 6, 62 and 550.
+
+The bound per patch, (C_KAPPA kappa_tile + C_FLUX) u (tests/parity.py, step_bound):
+  * C_KAPPA = 16: a face state's conserved variables carry about 4 roundings each (prim -> cons,
+    the half-step correction); Eq. 20 turns that into about 4 kappa u in L, hence in Theta and
+    p, and a flux inherits at most the pressure's relative error; doubled for the two face
+    states of an interface, doubled again as margin;
+  * C_FLUX = 32: each Riemann flux component comes out of about 8 dependent roundings (signal
+    speeds, HLL averages, contact speed, star state), six flux differences enter a cell's
+    increment, which is summed and rounded once more, and dt/dh |F| stays below the CFL
+    number times |U|: about 6 x 8 x 0.5 + 2 = 26, rounded up.  The momentum's error is measured
+    against the grid's largest |M|, which a pressure jump of the same size creates in one step.
+The pressure recovered from the updated conserved variables carries Eq. 20's amplification of
+their error once more: the squares of x = Et/D in L double it and D's own error doubles it
+again, hence 4 (C_KAPPA kappa_tile + C_FLUX) u.  The same holds in FP64 with u_64 = 2^-53: where
+that exceeds 1e-10 (kappa above about 6e4, the nozzle) two correct FP64 steps differ by that
+much, so FP64 parity there is judged by max(1e-10, (C_KAPPA kappa_tile + C_FLUX) u_64)."""
 import numpy as np
 import pytest
 import torch
 
 import oracle as O
 import workloads as W
-from tests.parity import U32, U64, kappa_prim, oracle_cons, patch_errors, soa, step_errors, tile_max
+from tests.parity import (U32, U64, kappa_prim, oracle_cons, patch_errors, soa, step_bound,
+                           step_errors, tile_max)
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
-C_MIXED = 16.0
 KMAX = 1024.0
 
 
@@ -67,14 +73,14 @@ def test_jet_block_padded(S, prec):
     e_off, e_on = patch_errors(off, ref), patch_errors(on, ref)
     print("prec %d: guard off max error %.3e; on: hot patches %.3e, others %.3e (bound %.3e); %s"
           % (prec, e_off.max(), e_on[hot].max(), e_on[~hot].max(),
-             (C_MIXED * kap[~hot] * U32).max(), sd))
-    fp64_bound = np.maximum(1e-10, C_MIXED * kap * U64)
+             step_bound(kap[~hot]).max(), sd))
+    fp64_bound = np.maximum(1e-10, step_bound(kap, U64))
     assert np.all(patch_errors(out64, ref) <= fp64_bound)
     assert sd["n_fp64_patch"] == hot.sum()
     assert e_off.max() > 1e-3                      # the FP32 bulk loses the nozzle's pressure
     assert np.all(e_on[hot] <= fp64_bound[hot])    # stepped in FP64
     assert patch_errors(on[hot], out64[hot]).max() <= 1e-13   # the FP64 kernel's results
-    assert np.all(e_on[~hot] <= C_MIXED * kap[~hot] * U32)
+    assert np.all(e_on[~hot] <= step_bound(kap[~hot]))
 
 
 @pytest.mark.parametrize("U", [0.3, 1.0, 3.0])
@@ -91,7 +97,7 @@ def test_moving_gas_error_follows_kappa(S, prec, U):
     print("prec %d U %.1f: kappa %.1f..%.1f, max error %.3e, error / (kappa u32) max %.2f median %.2f"
           % (prec, U, kap.min(), kap.max(), e.max(), ratio.max(), np.median(ratio)))
     assert S.stats_dict(st)["n_fp64_patch"] == 0
-    assert np.all(e <= C_MIXED * kap * U32)
+    assert np.all(e <= step_bound(kap))
     # where the amplification shows: the pressure of the updated state (its L is Eq. 15's left-hand
     # side of conserved variables that carry the FP32 step's rounding), per patch
     P = g.n_patch
@@ -100,7 +106,7 @@ def test_moving_gas_error_follows_kappa(S, prec, U):
     ep = np.max(np.abs(pg / pr - 1), axis=1)
     print("   pressure of the updated state: max error %.3e, error / (kappa u32) max %.2f"
           % (ep.max(), (ep / (kap * U32)).max()))
-    assert np.all(ep <= 4 * C_MIXED * kap * U32)
+    assert np.all(ep <= 4 * step_bound(kap))
 
 
 def test_jet_block_gather_chain(S):
@@ -127,8 +133,8 @@ def test_jet_block_gather_chain(S):
         print("gather step %d: hot %d (device %d), errors hot %.3e others %.3e"
               % (step, hot.sum(), sd["n_fp64_patch"], e[hot].max(), e[~hot].max()))
         assert sd["n_fp64_patch"] == hot.sum() and hot.any()
-        assert np.all(e[hot] <= np.maximum(1e-10, C_MIXED * k_host[hot] * U64))
-        assert np.all(e[~hot] <= C_MIXED * k_host[~hot] * U32)
+        assert np.all(e[hot] <= np.maximum(1e-10, step_bound(k_host[hot], U64)))
+        assert np.all(e[~hot] <= step_bound(k_host[~hot]))
 
 
 def test_guard_arguments(S):

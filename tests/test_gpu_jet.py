@@ -4,7 +4,7 @@ schedule.  Parity on 1,000 sampled patches (half of them straddling the nozzle e
 oracle: FP64 within 1e-10 per field; the mixed step (FP32 bulk, FP64 inversion, the learned guess
 when its weights exist) with the precision guard of Eq. 20: the patches whose tile reaches the
 nozzle (kappa = 1 + M^2 ~ 2e6) are stepped in FP64 and agree within 1e-10, the others within
-C_MIXED kappa_tile u_32 (tests/test_gpu_guard.py derives the constant).
+(C_KAPPA kappa_tile + C_FLUX) u_32 (tests/test_gpu_guard.py derives the constants).
 
 Both sides start from the same bits: the two conserved states (ambient, nozzle) come from the
 oracle's prim -> cons and every padded cell holds one of them, selected by the cell's label."""
@@ -14,8 +14,9 @@ import torch
 
 import oracle as O
 import workloads as W
-from tests.parity import U32, U64, kappa_prim, patch_errors, stencil_mask, step_errors
-from tests.test_gpu_guard import C_MIXED, KMAX
+from tests.parity import U64, kappa_prim, patch_errors, stencil_mask, step_errors
+from tests.parity import step_bound
+from tests.test_gpu_guard import KMAX
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -137,10 +138,10 @@ def test_mixed_learned_full_list_autotuned(S, jet, dt, oracle_ref):
     print("mixed jet (%s guess): errors %s; hot patches %d (device %d), sampled hot %d max error "
           "%.3e, others %.3e (bound %.3e); schedule %s of %s; stats %s"
           % ("learned" if mlp is not None else "analytic", e, n_hot, sd["n_fp64_patch"], hot.sum(),
-             ep[hot].max(), ep[~hot].max(), (C_MIXED * kap[~hot] * U32).max(), sch, table, sd))
+             ep[hot].max(), ep[~hot].max(), step_bound(kap[~hot]).max(), sch, table, sd))
     assert sd["n_fp64_patch"] == n_hot and hot.any()
-    assert np.all(ep[hot] <= np.maximum(1e-10, C_MIXED * kap[hot] * U64))
-    assert np.all(ep[~hot] <= C_MIXED * kap[~hot] * U32)
+    assert np.all(ep[hot] <= np.maximum(1e-10, step_bound(kap[hot], U64)))
+    assert np.all(ep[~hot] <= step_bound(kap[~hot]))
     assert sd["n_noconv"] == 0
 
 
