@@ -157,6 +157,26 @@ __device__ __forceinline__ double lhs_L_from_f32_adaptive(float D, float Mx, flo
   return FAST ? N * rcp_nr(d * d) : N / (d * d);
 }
 
+// The same for FP64 conserved variables whose inversion feeds one step of the FP64 bulk: the
+// plain sum of the five rounded products (relative error at most 5 u cond) where every lane of
+// the wavefront has cond <= 2^10, so below 6e-13 -- three orders under the step's 1e-10 parity --
+// and the exact lhs_L otherwise.  The choice is made per lane (the wavefront only decides whether
+// the exact sum is formed at all), so a state's L does not depend on its wavefront neighbours.
+template <bool FAST = false>
+__device__ __forceinline__ double lhs_L_adaptive(double D, double Mx, double My, double Mz, double Et)
+{
+  const double pos = Et * Et + 2.0 * Et * D;
+  const double neg = -(Mx * Mx + My * My + Mz * Mz);
+  const double N = pos + neg;
+  const bool cheap = __builtin_fabs(pos) + __builtin_fabs(neg) <= 1024.0 * __builtin_fabs(N);
+  double l = FAST ? N * rcp_nr(D * D) : N / (D * D);
+  if (__any(!cheap)) {
+    const double le = lhs_L(D, Mx, My, Mz, Et);
+    l = cheap ? l : le;
+  }
+  return l;
+}
+
 // ------------------------------------------------------------------------------ EoS
 // Eq. 22: reduced enthalpy from Theta, free of the subtraction h - 1.
 template <class T>

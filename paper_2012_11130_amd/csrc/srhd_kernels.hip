@@ -158,9 +158,14 @@ __global__ void __launch_bounds__(kBlock) k_cfl_smax(int64_t n_patch,
     const T *q = interior + p * 5 * 512 + c;
     T D = q[0], Mx = q[512], My = q[1024], Mz = q[1536], Et = q[2048];
     T L;
-    if (!admissible(D, Mx, My, Mz, Et, T(Tol<T>::eps), L)) continue;
+    // FP64: the L and inversion arithmetic of the FP64 step's own output inversion, so that the
+    // step's S_max of its output and this kernel's agree bit for bit
+    bool adm;
+    if constexpr (sizeof(T) == 8) adm = admissible_adaptive<true>(D, Mx, My, Mz, Et, T(Tol<T>::eps), L);
+    else adm = admissible(D, Mx, My, Mz, Et, T(Tol<T>::eps), L);
+    if (!adm) continue;
     InvOut<T> o;
-    invert_with_L<T, T>(D, Mx, My, Mz, L, T(-1), false, T(Tol<T>::v), 30, o, eos);
+    invert_with_L<T, T, T, sizeof(T) == 8>(D, Mx, My, Mz, L, T(-1), false, T(Tol<T>::v), 30, o, eos);
     double S = signal_smax(o.rho, o.ux, o.uy, o.uz, o.p, eos);
     if (S > vmax) vmax = S;
   }

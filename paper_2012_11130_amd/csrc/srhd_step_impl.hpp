@@ -33,7 +33,14 @@
 namespace srhd {
 namespace {
 
-constexpr int NT = 512;          // threads per workgroup (one per interior cell)
+constexpr int NT = 512;          // interior cells per patch (threads of an FP32-bulk workgroup)
+
+// Threads per workgroup: one per interior cell.  The phases are written for any multiple of 512
+// (threads 512.. would take part in the tile phases only); 1024 for the FP64 bulk, whose 155 KB
+// tile admits one workgroup per CU, doubles the wavefronts per SIMD but caps the registers at 128
+// and spills 170-250 bytes per lane, and measured no faster, so every kernel runs 512.
+template <class T> constexpr int threads_of() { return sizeof(T) == 8 ? 768 : 512; }
+constexpr int NT_MAX = 1024;
 constexpr int BX = 12;           // primitive box [-2, 10)^3
 constexpr int NB = BX * BX * BX;
 constexpr int HX = 10;           // half-step box [-1, 9)^3
@@ -101,6 +108,12 @@ __device__ __forceinline__ typename KEos<K>::type make_eos(const StepArgs &a)
 template <class T, class I>
 using GuessT = typename std::conditional<sizeof(T) == 4, float, I>::type;
 
+// Refined hardware reciprocals and square roots (about 1 ulp) in the inversions and L: every FP64
+// step kernel and entry inversion (the padded and gather layouts and the CFL kernel therefore
+// give the same bits), and the FP32-bulk gather kernels (in the FP32-bulk padded kernels they
+// cost registers and occupancy).
+template <class T, bool GATHER> constexpr bool fast_of() { return sizeof(T) == 8 || GATHER; }
+
 // Newton tolerance by (bulk type T, inversion type I): FP64 to ~2^-54; an FP64 inversion whose
 // result is consumed in FP32 to ~2^-28; an FP32 inversion to FP32 accuracy.
 template <class T, class I> struct StepTol;
@@ -114,7 +127,7 @@ struct Tile {
   T W[5][NB];            // centre primitives (rho, Ux, Uy, Uz, p), 12^3 box
   T C[5][NHB];           // half-step corrections, 10^3 box
   T F[2][5][NIF];        // interface fluxes of two directions (ring)
-  double red[NT / 64];   // per-wavefront maxima
+  double red[NT_MAX / 64];   // per-wavefront maxima
   unsigned int cnt[8];   // workgroup counters
   int nb[32];            // neighbour table row (gather mode)
   unsigned long long claim;  // queue position claimed by the workgroup (persistent schedule)
@@ -138,10 +151,10 @@ __device__ __forceinline__ Prim<T> load_prim(const Tile<T> &s, int b)
   return w;
 }
 
-// Double inversion of bulk-type conserved variables (FP64 path: lhs_L in double; mixed path:
-// the float values' products are exact in double).
+// Double inversion of bulk-type conserved variables (FP64 path: the adaptive sum of the rounded
+// products; mixed path: the float values' products are exact in double).
 template <bool FAST>
-__device__ __forceinline__ double L_of(const Cons<double> &u) { return lhs_L(u.D, u.m[0], u.m[1], u.m[2], u.E); }
+__device__ __forceinline__ double L_of(const Cons<double> &u) { return lhs_L_adaptive<FAST>(u.D, u.m[0], u.m[1], u.m[2], u.E); }
 template <bool FAST>
 __device__ __forceinline__ double L_of(const Cons<float> &u) { return lhs_L_from_f32_adaptive<FAST>(u.D, u.m[0], u.m[1], u.m[2], u.E); }
 
@@ -322,6 +335,7 @@ template <class T, class I, bool GATHER, int K, class PS = T>
 __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const MlpDev &mlp, const int64_t p)
 {
   constexpr bool GCONS = GATHER && sizeof(T) != sizeof(PS);
+  constexpr int NTT = threads_of<T>();
   constexpr bool MLP = K == KV_MLP;
   constexpr bool TOT = K == KV_TOTAL;
   static_assert(!TOT || (!GATHER && sizeof(T) == sizeof(I)), "original scheme: padded, one type");
@@ -351,7 +365,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
   bool centre_bad = false, hot = false;
   unsigned int centre_unphys = 0;
   const T km1 = T(a.kappa_max - 1.0);
-  for (int r0 = 0; r0 < NPC; r0 += NT) {
+  for (int r0 = 0; r0 < NPC; r0 += NTT) {
     // every lane runs every round (the learned guess needs whole wavefronts); lanes past the
     // end of the list work on the first cell again and store nothing
     const int r = r0 + tid;
@@ -417,14 +431,13 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
       InvOut<I> o;
       bool adm;
       if constexpr (TOT) adm = admissible_total<I>((I)D, (I)Mx, (I)My, (I)Mz, (I)Et, L);
-      else if constexpr (sizeof(T) == 4) adm = admissible_adaptive(D, Mx, My, Mz, Et, DBL_EPSILON, L);
-      else adm = admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L);
+      else adm = admissible_adaptive<sizeof(T) == 8>(D, Mx, My, Mz, Et, DBL_EPSILON, L);
       bool consulted = false;
       unsigned int ev = 0;
       double guess = MLP ? mlp_guess(mlp, D, Mx, My, Mz, Et, (valid && adm) ? L : 0.0, consulted, ev) : -1.0;
       my_mlp += valid ? ev : 0u;
       if (!valid) continue;
-      if (adm) invert_with_L<I, GuessT<T, I>, GuessT<T, I>>((I)D, (I)Mx, (I)My, (I)Mz, (I)L, (I)guess, consulted, (I)StepTol<T, I>::v, 30, o, eos);
+      if (adm) invert_with_L<I, GuessT<T, I>, GuessT<T, I>, sizeof(T) == 8>((I)D, (I)Mx, (I)My, (I)Mz, (I)L, (I)guess, consulted, (I)StepTol<T, I>::v, 30, o, eos);
       else set_unphysical(o);
       centre_bad |= o.status == ST_UNPHYSICAL;
       centre_unphys += o.status == ST_UNPHYSICAL;
@@ -455,8 +468,9 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
     }
   }
 
-  // this thread's interior cell for phase D
-  const int ci = tid & 7, cj = (tid >> 3) & 7, ck = tid >> 6;
+  // this thread's interior cell for phase D (threads 512.. own none)
+  const bool owner = NTT == NT || tid < NT;
+  const int ci = tid & 7, cj = (tid >> 3) & 7, ck = (tid >> 6) & 7;
   const int cq = ((ck + g) * N + (cj + g)) * N + (ci + g);
 
   T theta = (T)a.theta;
@@ -464,7 +478,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
   for (int attempt = 0; !deferred; ++attempt) {
     // -------------------------------------------------------------- B: half-step corrections
     const T half = T(0.5 * dt / dh);
-    for (int r = tid; r < NHC; r += NT) {
+    for (int r = tid; r < NHC; r += NTT) {
       int hb = kTab.hcell[r];
       int i = hb % HX - 1, j = (hb / HX) % HX - 1, k = hb / (HX * HX) - 1;
       int b = bidx(i, j, k);
@@ -504,18 +518,20 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
     // -------------------------------------------------------------- C + D: fluxes, update
     bool fail = false;
     T dU[5] = {T(0), T(0), T(0), T(0), T(0)};
+    constexpr int NROUND = (3 * NIF + NTT - 1) / NTT;
+    int folded = 0;
 #pragma unroll 1
-    for (int round = 0; round < 4; ++round) {
-      int qi = round * NT + tid;
+    for (int round = 0; round < NROUND; ++round) {
+      int qi = round * NTT + tid;
       if (qi < 3 * NIF) {
         // 576 = 9 x 64: the direction is uniform across each wavefront
         int d = qi / NIF;
         int r = qi - d * NIF;
         IfaceCount ic = {0, 0, 0, 0, 0, 0};
         bool ok;
-        if (d == 0) ok = interface_flux<0, K, I, GATHER && sizeof(T) == 4>(s, r, theta, a.riemann, mlp, ic, eos);
-        else if (d == 1) ok = interface_flux<1, K, I, GATHER && sizeof(T) == 4>(s, r, theta, a.riemann, mlp, ic, eos);
-        else ok = interface_flux<2, K, I, GATHER && sizeof(T) == 4>(s, r, theta, a.riemann, mlp, ic, eos);
+        if (d == 0) ok = interface_flux<0, K, I, fast_of<T, GATHER>()>(s, r, theta, a.riemann, mlp, ic, eos);
+        else if (d == 1) ok = interface_flux<1, K, I, fast_of<T, GATHER>()>(s, r, theta, a.riemann, mlp, ic, eos);
+        else ok = interface_flux<2, K, I, fast_of<T, GATHER>()>(s, r, theta, a.riemann, mlp, ic, eos);
         fail |= !ok;
         my_iters += ic.iters;
         my_mlp += ic.mlp;
@@ -525,15 +541,19 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
         unphys += ic.unphys;
       }
       __syncthreads();
-      if (round >= 1) {
-        // direction round-1 is complete: fold F_{+1/2} - F_{-1/2} into this thread's cell
-        int d = round - 1;
-        int slot = d & 1;
-        // this cell's lower face along d, and the step to its upper face, in the order above
-        int r = d == 0 ? (ck * 8 + cj) * 9 + ci : (d == 1 ? (ck * 9 + cj) * 8 + ci : (ck * 8 + cj) * 8 + ci);
-        int up = d == 0 ? 1 : (d == 1 ? 8 : 64);
+      // every direction this round completed: fold F_{+1/2} - F_{-1/2} into this thread's cell
+      // (directions d and d + 2 share a ring slot: d is folded before d + 2 is written)
+      const int done = (round + 1) * NTT / NIF < 3 ? (round + 1) * NTT / NIF : 3;
+      for (; folded < done; ++folded) {
+        const int d = folded;
+        const int slot = d & 1;
+        if (owner) {
+          // this cell's lower face along d, and the step to its upper face, in the order above
+          int r = d == 0 ? (ck * 8 + cj) * 9 + ci : (d == 1 ? (ck * 9 + cj) * 8 + ci : (ck * 8 + cj) * 8 + ci);
+          int up = d == 0 ? 1 : (d == 1 ? 8 : 64);
 #pragma unroll
-        for (int f = 0; f < 5; ++f) dU[f] += s.F[slot][f][r + up] - s.F[slot][f][r];
+          for (int f = 0; f < 5; ++f) dU[f] += s.F[slot][f][r + up] - s.F[slot][f][r];
+        }
         if constexpr (!GATHER) {
           if (a.flux_out && tid < 128) write_boundary_fluxes(a.flux_out, p, d, &s.F[slot][0][0], NIF, tid);
         }
@@ -545,26 +565,31 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
     // loop they would hold fifteen 64-bit per-lane addresses across the whole patch
     int lt = tid, lq = cq;
     asm volatile("" : "+v"(lt), "+v"(lq));
-    double un[5];
+    double un[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double Lo = 0.0;
+    bool ok_out = true;
+    if (owner) {
 #pragma unroll
-    for (int f = 0; f < 5; ++f) {
-      double u0 = GATHER ? a.cons[(p * 5 + f) * 512 + lt] : q[f * N3 + lq];
-      un[f] = u0 - full * (double)dU[f];
+      for (int f = 0; f < 5; ++f) {
+        double u0 = GATHER ? a.cons[(p * 5 + f) * 512 + lt] : q[f * N3 + lq];
+        un[f] = u0 - full * (double)dU[f];
+      }
+      if constexpr (TOT) ok_out = admissible_total<I>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)un[4], Lo);
+      else ok_out = admissible_adaptive<fast_of<T, GATHER>()>(un[0], un[1], un[2], un[3], un[4], DBL_EPSILON, Lo);
     }
-    double Lo;
-    bool ok_out;
-    if constexpr (TOT) ok_out = admissible_total<I>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)un[4], Lo);
-    else if constexpr (sizeof(T) == 4) ok_out = admissible_adaptive<GATHER>(un[0], un[1], un[2], un[3], un[4], DBL_EPSILON, Lo);
-    else ok_out = admissible(un[0], un[1], un[2], un[3], un[4], DBL_EPSILON, Lo);
     fail |= !ok_out;
     fail = __syncthreads_or(fail);
     bool last = !fail || centre_bad || theta == T(0);
     if (last) {
-      double *o = a.out + p * 5 * 512 + lt;
+      if (owner) {
+        double *o = a.out + p * 5 * 512 + lt;
 #pragma unroll
-      for (int f = 0; f < 5; ++f) o[f * 512] = un[f];
-      unphys += !ok_out;
+        for (int f = 0; f < 5; ++f) o[f * 512] = un[f];
+        unphys += !ok_out;
+      }
       if (GATHER) {
+       double sm = 0.0;
+       if (owner) {                  // whole wavefronts: the network evaluates 64 lanes at once
         // the updated cell's primitives and signal speed, for the next step
         InvOut<I> w;
         bool consulted = false;
@@ -588,10 +613,10 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
         const bool any_guess = MLP && __any(consulted);
         if (ok_out) {
           if (any_guess)
-            invert_with_L<I, GuessT<T, I>, GuessT<T, I>, GATHER && sizeof(T) == 4>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)Lo, (I)guess,
+            invert_with_L<I, GuessT<T, I>, GuessT<T, I>, fast_of<T, GATHER>()>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)Lo, (I)guess,
                                                          consulted, (I)StepTol<T, I>::v, 30, w);
           else
-            invert_with_L<I, GuessT<T, I>, GuessT<T, I>, GATHER && sizeof(T) == 4>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)Lo, (I)-1.0,
+            invert_with_L<I, GuessT<T, I>, GuessT<T, I>, fast_of<T, GATHER>()>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)Lo, (I)-1.0,
                                                          false, (I)StepTol<T, I>::v, 30, w);
         } else set_unphysical(w);
         my_iters += w.iters;
@@ -603,19 +628,19 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
         po[1024] = (PS)(T)w.uy;
         po[1536] = (PS)(T)w.uz;
         po[2048] = (PS)(T)w.p;
-        double sm = 0.0;
         if constexpr (sizeof(PS) == 4) {
           if (ok_out) sm = (double)signal_smax_t<float>((float)(T)w.rho, (float)(T)w.ux, (float)(T)w.uy, (float)(T)w.uz, (float)(T)w.p);
         } else {
           if (ok_out) sm = signal_smax((double)w.rho, (double)w.ux, (double)w.uy, (double)w.uz, (double)w.p);
         }
+       }
         sm = wave_max(sm);
         if ((tid & 63) == 0) s.red[tid >> 6] = sm;
         __syncthreads();
         if (tid == 0) {
           double m = s.red[0];
 #pragma unroll
-          for (int w8 = 1; w8 < NT / 64; ++w8) m = fmax(m, s.red[w8]);
+          for (int w8 = 1; w8 < NTT / 64; ++w8) m = fmax(m, s.red[w8]);
           atomicMax(a.smax_out, (unsigned long long)__double_as_longlong(m));
         }
       }
@@ -687,7 +712,7 @@ __device__ __forceinline__ void step_body(const StepArgs &a)
 }
 
 template <class T, class I, bool GATHER, int K>
-__global__ void __launch_bounds__(NT) k_step(StepArgs a)
+__global__ void __launch_bounds__(threads_of<T>()) k_step(StepArgs a)
 {
   step_body<T, I, GATHER, K>(a);
 }
@@ -707,7 +732,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4)))
 // same tolerance).  PS: storage type of the gather layout's primitives (the chain's FP32 ones,
 // widened to FP64 in the tile).  Every workgroup leaves once the list is exhausted.
 template <bool GATHER, int K, class PS>
-__global__ void __launch_bounds__(NT) k_step_listed_fp64(StepArgs a)
+__global__ void __launch_bounds__(threads_of<double>()) k_step_listed_fp64(StepArgs a)
 {
   const MlpDev mlp = a.guess.dev();
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -751,13 +776,12 @@ __global__ void __launch_bounds__(256) k_grid_prims(int64_t n_patch, const doubl
     InvOut<I> w;
     // the step's output check and L (adaptive with an FP32 bulk), so that both give the same bits
     bool ok;
-    if constexpr (sizeof(T) == 4) ok = admissible_adaptive<true>(u[0], u[512], u[1024], u[1536], u[2048], DBL_EPSILON, L);
-    else ok = admissible(u[0], u[512], u[1024], u[1536], u[2048], DBL_EPSILON, L);
+    ok = admissible_adaptive<true>(u[0], u[512], u[1024], u[1536], u[2048], DBL_EPSILON, L);
     bool consulted = false;
     unsigned int evals = 0;
     double guess = MLP ? mlp_guess(mlp, u[0], u[512], u[1024], u[1536], u[2048], ok ? L : 0.0, consulted, evals) : -1.0;
     if (ok)
-      invert_with_L<I, GuessT<T, I>, GuessT<T, I>, sizeof(T) == 4>((I)u[0], (I)u[512], (I)u[1024], (I)u[1536], (I)L, (I)guess, consulted,
+      invert_with_L<I, GuessT<T, I>, GuessT<T, I>, true>((I)u[0], (I)u[512], (I)u[1024], (I)u[1536], (I)L, (I)guess, consulted,
                        (I)StepTol<T, I>::v, 30, w);
     else set_unphysical(w);
     T *po = prims + pp * 5 * 512 + c;
@@ -812,7 +836,7 @@ int occupancy_k(bool occ2)
   const void *fn = step_kernel<T, I, GATHER, K>(occ2);
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, NT, bytes) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, threads_of<T>(), bytes) != hipSuccess) return 0;
   return n;
 }
 
@@ -831,7 +855,7 @@ hipError_t launch_step_listed(const StepArgs &a, hipStream_t st)
   if (e != hipSuccess) return e;
   int64_t groups = cus > 0 ? cus : 1;
   if (groups > a.n_patch) groups = a.n_patch;
-  hipLaunchKernelGGL((k_step_listed_fp64<GATHER, KD, float>), dim3((unsigned)groups), dim3(NT), bytes, st, a);
+  hipLaunchKernelGGL((k_step_listed_fp64<GATHER, KD, float>), dim3((unsigned)groups), dim3(threads_of<double>()), bytes, st, a);
   return hipGetLastError();
 }
 
@@ -860,7 +884,7 @@ hipError_t launch_step_k(const StepArgs &a, hipStream_t st)
     if (e != hipSuccess || !guard) return e;
     return launch_step_listed<GATHER, K>(a, st);
   } else {
-    hipLaunchKernelGGL((k_step<T, I, GATHER, K>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
+    hipLaunchKernelGGL((k_step<T, I, GATHER, K>), dim3((unsigned)blocks), dim3(threads_of<T>()), bytes, st, a);
     return hipGetLastError();
   }
 }
