@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define SRHD_ABI_VERSION 6
+#define SRHD_ABI_VERSION 7
 
 typedef enum { SRHD_F64 = 0, SRHD_F32 = 1 } srhd_dtype;
 
@@ -218,7 +218,9 @@ typedef struct {
                               accumulated (see srhd_flux_accumulate); for the flux correction of
                               coarse-fine interfaces.  Must not overlap the other arrays. */
   double kappa_max;        /* precision guard of the FP32-bulk modes (see below); 0: off */
-  uint64_t *defer;         /* device [n_patch + 2] workspace of the guard, or NULL when off */
+  int learned_split;       /* learned guess by patch (see below); 0: one launch */
+  uint64_t *defer;         /* device [2 n_patch + 4] workspace of the guard and the split, or NULL
+                              when neither is on */
 } srhd_step_params;
 
 /* Precision guard (SRHD_PREC_MIXED and SRHD_PREC_FP32, MUSCL-Hancock).  Eq. 20 puts the error of
@@ -228,14 +230,26 @@ typedef struct {
  * holding a cell with kappa = 1 + M^2 near 1 / eps_32 (a gamma = 10^3 jet: kappa ~ 2e6) loses its
  * pressure there.  With kappa_max >= 1 every patch whose 12^3 primitive tile (after the
  * cell-centre inversions, or as gathered) holds a cell with kappa > kappa_max is stepped instead
- * by the FP64 kernel (FP64 bulk and inversion; in the gather layout from the FP32 primitives
- * widened to FP64), in a second launch over the list of such patches; the other patches keep the
+ * by the FP64 kernel (FP64 bulk and inversion; in the gather layout from the gathered FP64
+ * conserved variables), in a second launch over the list of such patches; the other patches keep the
  * FP32 bulk, whose one-step error is then of order kappa_max eps_32 per field.  kappa_max = 0
- * turns the guard off (the FP32 bulk everywhere, like a single-precision code).  defer: device
- * memory of n_patch + 2 uint64 words (8-byte aligned), required when the guard is on; zeroed by
- * the call on its stream; afterwards word 0 holds the number of patches stepped in FP64 and words
- * 2 .. their indices in no particular order.  Calls in flight at the same time must not share it.
- * Ignored by SRHD_PREC_FP64 and by the VL integrator. */
+ * turns the guard off (the FP32 bulk everywhere, like a single-precision code).  Ignored by
+ * SRHD_PREC_FP64 and by the VL integrator.
+ *
+ * Learned guess by patch (learned_split = 1, a learned guess with a gate_L > 0, MUSCL-Hancock with
+ * the reduced energy and the TM EoS): the kernel without the network steps every patch and lists
+ * those whose tile holds a cell with L > gate_L (Eq. 15's left-hand side of the cell's state); a
+ * second launch steps the listed patches with the network, consulted as always where a state's
+ * L > gate_L.  The other patches run no network code: where the gate keeps the network out of a
+ * patch, its registers and code cost that patch nothing.  Results equal a single launch's up to
+ * the Newton tolerance (a face state with L above the gate in an unlisted patch starts from the
+ * analytic guess instead).  A patch the guard steps in FP64 is not listed.
+ *
+ * defer: device memory of 2 n_patch + 4 uint64 words (8-byte aligned), required when the guard or
+ * the split is on; zeroed by the call on its stream.  Afterwards word 0 holds the number of
+ * patches stepped in FP64 and words 2 .. their indices, word n_patch + 2 the number of patches
+ * stepped with the network and words n_patch + 4 .. theirs, in no particular order.  Calls in
+ * flight at the same time must not share it. */
 #define SRHD_KAPPA_MAX_DEFAULT 1024.0
 
 /* Device counters, accumulated (never reset by the step; see srhd_stats_reset). */
@@ -250,6 +264,7 @@ typedef struct {
   uint64_t n_pred_fallback; /* VL: predictor states that failed the inversion and were replaced
                                by the cell's state at t^n (final attempts) */
   uint64_t n_fp64_patch;   /* patches the precision guard stepped with the FP64 bulk */
+  uint64_t n_learned_patch; /* patches the learned-guess split stepped with the network */
 } srhd_step_stats;
 
 int srhd_stats_reset(srhd_step_stats *stats, void *stream);
@@ -271,9 +286,10 @@ int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc): srhd_fluid_step with its two work buffers -- the
- * precision guard's list (prm->defer) and the persistent schedule's counters
- * (prm->sched.queue) -- taken from a static device array of the library instead of the caller.
- * The array holds SRHD_QUEUE_WORDS + SRHD_STATIC_MAX_PATCH + 2 uint64 words (about 8 MiB) on
+ * patch lists of the precision guard and the learned-guess split (prm->defer) and the persistent
+ * schedule's counters (prm->sched.queue) -- taken from a static device array of the library
+ * instead of the caller.
+ * The array holds SRHD_QUEUE_WORDS + 2 SRHD_STATIC_MAX_PATCH + 4 uint64 words (16 MiB) on
  * every GPU the library runs on, until the process ends; its device address is looked up on
  * the first call on each device.  Arguments and results as for srhd_fluid_step, except:
  * prm->defer and prm->sched.queue must be NULL, and n_patch may not exceed SRHD_STATIC_MAX_PATCH

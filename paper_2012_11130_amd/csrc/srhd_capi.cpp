@@ -161,26 +161,43 @@ int check_sched(const srhd_sched &sc, int prec, int guess_kind, srhd::StepArgs &
   return SRHD_OK;
 }
 
-// Precision guard of an FP32-bulk MUSCL-Hancock step (include/srhd.h, srhd_step_params):
-// kappa_max 0 (off) or >= 1; the defer workspace of n_patch + 2 words must be 8-byte aligned
-// and overlap none of the call's other arrays (regions, n_region of them, NULL entries skipped).
-int check_guard(const srhd_step_params *prm, int64_t n_patch, const void *const *regions,
-                const size_t *sizes, int n_region, srhd::StepArgs &s, const char *who)
+// Patch lists of a MUSCL-Hancock step (include/srhd.h, srhd_step_params): the precision guard of
+// an FP32 bulk (kappa_max 0, off, or >= 1) and the learned-guess split (learned_split 0 or 1; a
+// learned guess with a positive gate, the reduced energy and the TM EoS).  Their workspace of
+// 2 n_patch + 4 words must be 8-byte aligned and overlap none of the call's other arrays
+// (regions, n_region of them, NULL entries skipped).
+int check_lists(const srhd_step_params *prm, const srhd::GuessArgs &g, double eos_k, int64_t n_patch,
+                const void *const *regions, const size_t *sizes, int n_region, srhd::StepArgs &s,
+                const char *who)
 {
   s.defer = nullptr;
   s.kappa_max = 0.0;
+  s.net_list = nullptr;
+  s.list = nullptr;
+  s.list_counter = 0;
   const double k = prm->kappa_max;
   if (!(k == 0.0 || k >= 1.0))
     return fail(SRHD_EINVAL, "%s: kappa_max %g is neither 0 nor at least 1", who, k);
-  if (k == 0.0 || prm->prec == SRHD_PREC_FP64 || prm->integrator != SRHD_MHM) return SRHD_OK;
+  if (prm->learned_split != 0 && prm->learned_split != 1)
+    return fail(SRHD_EINVAL, "%s: learned_split %d is neither 0 nor 1", who, prm->learned_split);
+  const bool mhm = prm->integrator == SRHD_MHM;
+  const bool guard = k > 0.0 && prm->prec != SRHD_PREC_FP64 && mhm;
+  const bool split = prm->learned_split && g.kind == SRHD_GUESS_MLP && g.gate > 0.0 && mhm &&
+                     prm->energy == SRHD_ENERGY_REDUCED && eos_k == 0.0;
+  if (!guard && !split) return SRHD_OK;
   if (!prm->defer || !aligned(prm->defer, 8))
-    return fail(SRHD_EINVAL, "%s: the precision guard needs an 8-byte aligned defer workspace", who);
-  const size_t db = ((size_t)n_patch + 2) * 8;
+    return fail(SRHD_EINVAL, "%s: the precision guard and the learned-guess split need an 8-byte "
+                "aligned defer workspace", who);
+  const size_t db = (2 * (size_t)n_patch + 4) * 8;
   for (int i = 0; i < n_region; ++i)
     if (regions[i] && !disjoint(prm->defer, db, regions[i], sizes[i]))
       return fail(SRHD_EINVAL, "%s: defer overlaps another array of the call", who);
-  s.defer = (unsigned long long *)prm->defer;
-  s.kappa_max = k;
+  unsigned long long *d = (unsigned long long *)prm->defer;
+  if (guard) {
+    s.defer = d;
+    s.kappa_max = k;
+  }
+  if (split) s.net_list = d + n_patch + 2;
   return SRHD_OK;
 }
 
@@ -450,7 +467,7 @@ int srhd_fluid_step(const srhd_patches *in, void *out, const double *dt_lev,
   {
     const void *reg[4] = {in->padded, out, s.flux_out, s.queue};
     const size_t sz[4] = {abytes, bbytes, (size_t)in->n_patch * 6 * 5 * 64 * 8, SRHD_QUEUE_WORDS * 8};
-    rc = check_guard(prm, in->n_patch, reg, sz, 4, s, "srhd_fluid_step");
+    rc = check_lists(prm, g, eos_k, in->n_patch, reg, sz, 4, s, "srhd_fluid_step");
     if (rc) return rc;
   }
   return hip_status(srhd::launch_step(prm->prec, s, (hipStream_t)stream), "srhd_fluid_step");
@@ -749,7 +766,7 @@ int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_
     const size_t cb = (size_t)in->n_patch * 5 * 512 * 8, pb = (size_t)in->n_patch * 5 * 512 * ps;
     const void *reg[5] = {in->cons, in->prims, cons_out, prims_out, s.queue};
     const size_t sz[5] = {cb, pb, cb, pb, SRHD_QUEUE_WORDS * 8};
-    rc = check_guard(prm, in->n_patch, reg, sz, 5, s, "srhd_fluid_step_grid");
+    rc = check_lists(prm, g, eos_k, in->n_patch, reg, sz, 5, s, "srhd_fluid_step_grid");
     if (rc) return rc;
   }
   return hip_status(srhd::launch_step_grid(prm->prec, s, (hipStream_t)stream),

@@ -523,6 +523,19 @@ __device__ __forceinline__ Cons<T> prim2cons(const Prim<T> &w, const E &eos = E(
   return u;
 }
 
+// Eq. 15's left-hand side L of a primitive state: f of Eq. 15 at the state's own reduced enthalpy
+// (what prim -> cons forms on its way to Et), in the arithmetic of T.
+template <class T, class E = EosTm>
+__device__ __forceinline__ T lhs_L_of_prim(T rho, T ux, T uy, T uz, T p, const E &eos = E())
+{
+  const T U2 = ux * ux + uy * uy + uz * uz;
+  const T th = dv(p, rho);
+  const T ht = htilde_of_theta(th, eos);
+  const T h = T(1) + ht;
+  const T h2 = h * h;
+  return ht * (ht + T(2)) - T(2) * th * h + dv(th * th * h2, h2 + h2 * U2);
+}
+
 // The original scheme's conserved variables (Sec. 4): D and M as above and, in the energy slot,
 // the total energy E = D h gamma - p of Eq. 5c (h = 1 + ht, Eq. 10) instead of Et.
 template <class T>

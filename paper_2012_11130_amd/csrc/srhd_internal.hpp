@@ -77,6 +77,13 @@ struct StepArgs {
   // stepped by the FP64 kernel in a second launch
   unsigned long long *defer;
   double kappa_max;
+  // learned-guess split (NULL: off): the kernel without the network lists here the patches whose
+  // tile holds a cell with L > guess.gate, and the learned kernel steps them in a second launch
+  unsigned long long *net_list;
+  // set by the launcher for a launch over a list: the list it walks and the step counter
+  // (srhd_step_stats word) each listed patch increments
+  unsigned long long *list;
+  int list_counter;
 };
 
 // Fluxes of the interfaces on the two faces (lower, upper) of direction d from the step's

@@ -1,16 +1,16 @@
-// srhd_static.hip -- srhd_fluid_step_static: the patch step with its work buffers (the precision
-// guard's patch list and the persistent schedule's queue counters) in a device array of this
-// library instead of caller memory, for callers that cannot allocate.
+// srhd_static.hip -- srhd_fluid_step_static: the patch step with its work buffers (the patch lists
+// of the precision guard and the learned-guess split, the persistent schedule's queue counters)
+// in a device array of this library instead of caller memory, for callers that cannot allocate.
 #include <mutex>
 
 #include "srhd_internal.hpp"
 
 namespace {
 
-// [0 .. SRHD_QUEUE_WORDS): queue counters; then the guard's list of SRHD_STATIC_MAX_PATCH + 2
-// words.  Each GPU holds its own copy, found by hipGetSymbolAddress (the host-side name is not
-// a device address).
-constexpr size_t kWords = SRHD_QUEUE_WORDS + SRHD_STATIC_MAX_PATCH + 2;
+// [0 .. SRHD_QUEUE_WORDS): queue counters; then the patch lists of the precision guard and the
+// learned-guess split, 2 SRHD_STATIC_MAX_PATCH + 4 words.  Each GPU holds its own copy, found by
+// hipGetSymbolAddress (the host-side name is not a device address).
+constexpr size_t kWords = SRHD_QUEUE_WORDS + 2 * (size_t)SRHD_STATIC_MAX_PATCH + 4;
 static __device__ __align__(256) unsigned long long scratch[kWords];
 
 constexpr int kMaxDevices = 64;
@@ -57,6 +57,6 @@ extern "C" int srhd_fluid_step_static(const srhd_patches *in, void *out, const d
   if (rc) return srhd::set_error(rc, "srhd_fluid_step_static: device index beyond %d", kMaxDevices);
   srhd_step_params p = *prm;
   p.sched.queue = p.sched.groups > 0 ? (uint64_t *)w : nullptr;
-  p.defer = p.kappa_max > 0.0 ? (uint64_t *)(w + SRHD_QUEUE_WORDS) : nullptr;
+  p.defer = (uint64_t *)(w + SRHD_QUEUE_WORDS);
   return srhd_fluid_step(in, out, dt_lev, &p, stats, stream);
 }

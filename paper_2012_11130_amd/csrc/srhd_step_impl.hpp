@@ -362,9 +362,12 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
   __syncthreads();
 
   // ---------------------------------------------------------------- A: centre primitives
-  bool centre_bad = false, hot = false;
+  bool centre_bad = false, hot = false, net = false;
   unsigned int centre_unphys = 0;
   const T km1 = T(a.kappa_max - 1.0);
+  // the learned-guess split's first launch (the kernel without the network) lists the patches
+  // whose tile holds a cell with L above the network's gate
+  const bool split = K == KV_ANALYTIC && a.net_list != nullptr;
   for (int r0 = 0; r0 < NPC; r0 += NTT) {
     // every lane runs every round (the learned guess needs whole wavefronts); lanes past the
     // end of the list work on the first cell again and store nothing
@@ -402,6 +405,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
       bool bad = !(v0 > T(0)) || !(v4 > T(0)) || !finiteT(v1) || !finiteT(v2) || !finiteT(v3);
       if constexpr (sizeof(T) == 4)
         if (a.defer) hot |= kappa_above<T>(v0, v1, v2, v3, v4, km1, eos);
+      if (split) net |= !bad && (double)lhs_L_of_prim<T>(v0, v1, v2, v3, v4) > a.guess.gate;
       centre_bad |= bad;
       centre_unphys += bad;
       s.W[0][b] = v0;
@@ -451,6 +455,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
       s.W[4][b] = (T)o.p;
       if constexpr (sizeof(T) == 4)
         if (a.defer) hot |= kappa_above<T>((T)o.rho, (T)o.ux, (T)o.uy, (T)o.uz, (T)o.p, km1, eos);
+      if (split) net |= adm && L > a.guess.gate;
     }
   }
   centre_bad = __syncthreads_or(centre_bad);
@@ -465,6 +470,13 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
         centre_unphys = 0;
         if (tid == 0) a.defer[2 + atomicAdd(&a.defer[0], 1ull)] = (unsigned long long)p;
       }
+    }
+  }
+  if (split && !deferred) {
+    deferred = __syncthreads_or(net);
+    if (deferred) {
+      centre_unphys = 0;
+      if (tid == 0) a.net_list[2 + atomicAdd(&a.net_list[0], 1ull)] = (unsigned long long)p;
     }
   }
 
@@ -726,26 +738,27 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4)))
   step_body<T, I, GATHER, K>(a);
 }
 
-// Second launch of a guarded FP32-bulk step: a persistent grid steps the patches listed in
-// a.defer with the FP64 bulk and inversion.  The original scheme and the polytropic EoS keep
-// their variant; the learned guess gives way to the analytic one (Newton refines either to the
-// same tolerance).  PS: storage type of the gather layout's primitives (the chain's FP32 ones,
-// widened to FP64 in the tile).  Every workgroup leaves once the list is exhausted.
-template <bool GATHER, int K, class PS>
-__global__ void __launch_bounds__(threads_of<double>()) k_step_listed_fp64(StepArgs a)
+// A launch over a list of patches written by a previous launch on the stream (a.list: [0] count,
+// [1] claim counter, [2..] indices): a persistent grid claims them one at a time; every workgroup
+// leaves once the list is exhausted.  Each listed patch adds 1 to word a.list_counter of the
+// step counters.  Serves the precision guard's FP64 pass (T = I = double; PS, the storage type
+// of the gather layout's primitives, float) and the learned-guess split's network pass.
+template <class T, class I, bool GATHER, int K, class PS>
+__global__ void __launch_bounds__(threads_of<T>()) k_step_listed(StepArgs a)
 {
   const MlpDev mlp = a.guess.dev();
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  Tile<double> &s = *reinterpret_cast<Tile<double> *>(smem_raw);
-  const unsigned long long n = a.defer[0];
+  Tile<T> &s = *reinterpret_cast<Tile<T> *>(smem_raw);
+  const unsigned long long n = a.list[0];
   for (;;) {
     __syncthreads();                                 // the tile and s.claim are free again
-    if (threadIdx.x == 0) s.claim = atomicAdd(&a.defer[1], 1ull);
+    if (threadIdx.x == 0) s.claim = atomicAdd(&a.list[1], 1ull);
     __syncthreads();
     const unsigned long long i = s.claim;
     if (i >= n) break;                               // uniform: every thread read the same claim
-    step_patch<double, double, GATHER, K, PS>(a, s, mlp, (int64_t)a.defer[2 + i]);
-    if (a.stats && threadIdx.x == 0) atomicAdd((unsigned long long *)&a.stats->n_fp64_patch, 1ull);
+    step_patch<T, I, GATHER, K, PS>(a, s, mlp, (int64_t)a.list[2 + i]);
+    if (a.stats && threadIdx.x == 0)
+      atomicAdd((unsigned long long *)a.stats + a.list_counter, 1ull);
   }
 }
 
@@ -840,23 +853,38 @@ int occupancy_k(bool occ2)
   return n;
 }
 
-// The FP64 step of the patches a guarded FP32-bulk step listed: one workgroup per compute unit
-// (the FP64 tile fills a CU's LDS), persistent over the list.
+// A persistent launch over a list of patches (k_step_listed): as many workgroups as fit on the
+// device at once (the FP64 tile fills a CU's LDS; two FP32-bulk tiles fit), at most the patches.
+template <class T, class I, bool GATHER, int K, class PS>
+hipError_t launch_listed(const StepArgs &a, unsigned long long *list, int counter, hipStream_t st)
+{
+  const size_t bytes = sizeof(Tile<T>);
+  const void *fn = (const void *)k_step_listed<T, I, GATHER, K, PS>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  int dev = 0, cus = 0, per_cu = 0;
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads_of<T>(), bytes);
+  if (e != hipSuccess) return e;
+  int64_t groups = (int64_t)(cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+  if (groups > a.n_patch) groups = a.n_patch;
+  StepArgs b = a;
+  b.list = list;
+  b.list_counter = counter;
+  b.queue = nullptr;
+  b.net_list = nullptr;
+  hipLaunchKernelGGL((k_step_listed<T, I, GATHER, K, PS>), dim3((unsigned)groups), dim3(threads_of<T>()), bytes, st, b);
+  return hipGetLastError();
+}
+
+// The FP64 step of the patches a guarded FP32-bulk step listed.
 template <bool GATHER, int K>
 hipError_t launch_step_listed(const StepArgs &a, hipStream_t st)
 {
   constexpr int KD = K == KV_MLP ? KV_ANALYTIC : K;
-  const size_t bytes = sizeof(Tile<double>);
-  hipError_t e = hipFuncSetAttribute((const void *)k_step_listed_fp64<GATHER, KD, float>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  int dev = 0, cus = 0;
-  if (e == hipSuccess) e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e != hipSuccess) return e;
-  int64_t groups = cus > 0 ? cus : 1;
-  if (groups > a.n_patch) groups = a.n_patch;
-  hipLaunchKernelGGL((k_step_listed_fp64<GATHER, KD, float>), dim3((unsigned)groups), dim3(threads_of<double>()), bytes, st, a);
-  return hipGetLastError();
+  StepArgs b = a;
+  b.defer = nullptr;
+  return launch_listed<double, double, GATHER, KD, float>(b, a.defer, 8, st);
 }
 
 template <class T, class I, bool GATHER, int K>
@@ -869,6 +897,7 @@ hipError_t launch_step_k(const StepArgs &a, hipStream_t st)
   if (e != hipSuccess) return e;
   const bool guard = sizeof(T) == 4 && a.defer != nullptr;
   if (guard) hipLaunchKernelGGL(k_zero_defer, dim3(1), dim3(64), 0, st, a.defer);
+  if (K == KV_ANALYTIC && a.net_list) hipLaunchKernelGGL(k_zero_defer, dim3(1), dim3(64), 0, st, a.net_list);
   if (GATHER) hipLaunchKernelGGL(k_zero_bits, dim3(1), dim3(64), 0, st, a.smax_out);
   int64_t blocks;
   if (a.queue) {
@@ -905,8 +934,19 @@ hipError_t launch_step_t(const StepArgs &a, hipStream_t st)
     if constexpr (!GATHER) return launch_step_k<T, I, GATHER, KV_POLY>(a, st);
     else return hipErrorInvalidValue;
   }
-  return a.guess.kind == SRHD_GUESS_MLP ? launch_step_k<T, I, GATHER, KV_MLP>(a, st)
-                                        : launch_step_k<T, I, GATHER, KV_ANALYTIC>(a, st);
+  if (a.guess.kind != SRHD_GUESS_MLP) {
+    StepArgs b = a;
+    b.net_list = nullptr;
+    return launch_step_k<T, I, GATHER, KV_ANALYTIC>(b, st);
+  }
+  if (!a.net_list) return launch_step_k<T, I, GATHER, KV_MLP>(a, st);
+  // learned-guess split: the kernel without the network steps every patch and lists those whose
+  // tile consults the network; then the learned kernel steps the listed ones
+  hipError_t e = launch_step_k<T, I, GATHER, KV_ANALYTIC>(a, st);
+  if (e != hipSuccess) return e;
+  StepArgs b = a;
+  b.defer = nullptr;
+  return launch_listed<T, I, GATHER, KV_MLP, T>(b, a.net_list, 9, st);
 }
 
 template <class T, class I, bool GATHER>

@@ -73,7 +73,7 @@ class srhd_step_params(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("riemann", _int), ("prec", _int),
                 ("max_retry", _int), ("guess", srhd_guess), ("sched", srhd_sched),
                 ("energy", _int), ("integrator", _int), ("eos", srhd_eos), ("flux_out", _vp),
-                ("kappa_max", ctypes.c_double), ("defer", _vp)]
+                ("kappa_max", ctypes.c_double), ("learned_split", _int), ("defer", _vp)]
 
 
 # precision guard of the FP32-bulk steps: patches holding a cell with 1 + M^2 above this are
@@ -93,11 +93,11 @@ class srhd_step_stats(ctypes.Structure):
                 ("n_noconv", ctypes.c_uint64), ("newton_iters", ctypes.c_uint64),
                 ("n_inversions", ctypes.c_uint64), ("n_retry", ctypes.c_uint64),
                 ("n_mlp", ctypes.c_uint64), ("n_pred_fallback", ctypes.c_uint64),
-                ("n_fp64_patch", ctypes.c_uint64)]
+                ("n_fp64_patch", ctypes.c_uint64), ("n_learned_patch", ctypes.c_uint64)]
 
 
 STATS_FIELDS = ("n_unphysical", "n_fallback", "n_noconv", "newton_iters", "n_inversions",
-                "n_retry", "n_mlp", "n_pred_fallback", "n_fp64_patch")
+                "n_retry", "n_mlp", "n_pred_fallback", "n_fp64_patch", "n_learned_patch")
 STATS_WORDS = len(STATS_FIELDS)
 
 _sig = {
@@ -307,20 +307,25 @@ def _patches(padded, dh, level, ghost):
 
 
 def defer_workspace(n_patch, device):
-    """Workspace of the precision guard for a step of n_patch patches."""
-    return torch.empty(n_patch + 2, dtype=torch.int64, device=device)
+    """Workspace of the precision guard and the learned-guess split for a step of n_patch
+    patches."""
+    return torch.empty(2 * n_patch + 4, dtype=torch.int64, device=device)
 
 
-def _guard(prm, kappa_max, defer, n_patch, device):
-    """Set the precision guard of prm; returns the workspace (kept alive by the caller)."""
+def _guard(prm, kappa_max, defer, n_patch, device, learned_split=True):
+    """Set the precision guard and the learned-guess split of prm; returns the workspace (kept
+    alive by the caller)."""
     prm.kappa_max = float(kappa_max)
-    if prm.kappa_max == 0.0 or prm.prec == PREC_FP64:
+    prm.learned_split = int(bool(learned_split))
+    guard = prm.kappa_max != 0.0 and prm.prec != PREC_FP64
+    split = prm.learned_split and prm.guess.kind == GUESS_MLP
+    if not (guard or split):
         prm.defer = None
         return None
     if defer is None:
         defer = defer_workspace(n_patch, device)
-    elif defer.dtype != torch.int64 or defer.numel() < n_patch + 2 or not defer.is_cuda:
-        raise ValueError("defer must be a CUDA int64 tensor of at least n_patch + 2 words")
+    elif defer.dtype != torch.int64 or defer.numel() < 2 * n_patch + 4 or not defer.is_cuda:
+        raise ValueError("defer must be a CUDA int64 tensor of at least 2 n_patch + 4 words")
     prm.defer = defer.data_ptr()
     return defer
 
@@ -358,7 +363,7 @@ def _table(table, n):
 def srhd_autotune_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann=HLLC,
                        prec=PREC_FP64, max_retry=4, ghost=None, guess=None, reps=2,
                        energy=ENERGY_REDUCED, integrator=MHM, kappa_max=KAPPA_MAX_DEFAULT,
-                       defer=None):
+                       defer=None, learned_split=True):
     """Times the candidate schedules of srhd_fluid_step on these patches; returns (Sched of the
     fastest, [(groups, chunk, occupancy, ms per step), ...])."""
     _need_cuda(padded, dt_lev, level)
@@ -368,7 +373,7 @@ def srhd_autotune_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riem
     sch = Sched(0, 1, padded.device)
     d = _patches(padded, dh, level, ghost)
     prm = _params(theta, riemann, prec, max_retry, guess, sch, energy, integrator)
-    ws = _guard(prm, kappa_max, defer, P, padded.device)  # noqa: F841  (alive across the call)
+    ws = _guard(prm, kappa_max, defer, P, padded.device, learned_split)  # noqa: F841
     table = (srhd_tune_entry * 32)()
     n = _int(0)
     _check(_lib.srhd_autotune_step(ctypes.byref(d), _ptr(out), _ptr(dt_lev), ctypes.byref(prm),
@@ -393,7 +398,8 @@ def _grid(cons, prims, neighbor, dh, level):
 
 def srhd_autotune_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, dt_lev=None,
                             level=None, theta=1.5, riemann=HLLC, prec=PREC_FP64, max_retry=4,
-                            guess=None, reps=2, kappa_max=KAPPA_MAX_DEFAULT, defer=None):
+                            guess=None, reps=2, kappa_max=KAPPA_MAX_DEFAULT, defer=None,
+                            learned_split=True):
     """Times the candidate schedules of srhd_fluid_step_grid on this block; returns (Sched of
     the fastest, [(groups, chunk, occupancy, ms per step), ...])."""
     _need_cuda(cons, prims, neighbor, smax_in, dt_lev, level)
@@ -403,7 +409,7 @@ def srhd_autotune_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, 
     sch = Sched(0, 1, cons.device)
     gr = _grid(cons, prims, neighbor, dh, level)
     prm = _params(theta, riemann, prec, max_retry, guess, sch)
-    ws = _guard(prm, kappa_max, defer, cons.shape[0], cons.device)  # noqa: F841
+    ws = _guard(prm, kappa_max, defer, cons.shape[0], cons.device, learned_split)  # noqa: F841
     table = (srhd_tune_entry * 32)()
     n = _int(0)
     _check(_lib.srhd_autotune_step_grid(ctypes.byref(gr), _ptr(smax_in), float(c_cfl), _ptr(dt_lev),
@@ -417,13 +423,14 @@ def srhd_autotune_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, 
 def srhd_fluid_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann=HLLC,
                     prec=PREC_FP64, max_retry=4, stats=None, ghost=None, guess=None, sched=None,
                     energy=ENERGY_REDUCED, integrator=MHM, flux_out=None, gamma=None,
-                    kappa_max=KAPPA_MAX_DEFAULT, defer=None):
+                    kappa_max=KAPPA_MAX_DEFAULT, defer=None, learned_split=True):
     """One MUSCL-Hancock (or, integrator=VL, VL) step: padded cons [P][5][N][N][N] -> interior
     [P][5][8][8][8].  energy=ENERGY_TOTAL runs the original scheme on (D, M, E); flux_out
     ([P][6][5][64] FP64) receives the fluxes through the patch faces; gamma selects the
     polytropic EoS.  With an FP32 bulk (prec MIXED or FP32) the precision guard steps the patches
-    holding a cell with 1 + M^2 > kappa_max in FP64 (0 turns it off); defer (int64, >= P + 2
-    words) is its workspace, allocated per call when None."""
+    holding a cell with 1 + M^2 > kappa_max in FP64 (0 turns it off); with a learned guess and
+    learned_split the network runs only in a second launch over the patches that consult it;
+    defer (int64, >= 2 P + 4 words) is their workspace, allocated per call when None."""
     _need_cuda(padded, dt_lev, level, stats, flux_out)
     P = padded.shape[0]
     N = padded.shape[-1]
@@ -433,7 +440,7 @@ def srhd_fluid_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann
     _need_cuda(out)
     d = _patches(padded, dh, level, g)
     prm = _params(theta, riemann, prec, max_retry, guess, sched, energy, integrator, flux_out, gamma)
-    ws = _guard(prm, kappa_max, defer, P, padded.device)  # noqa: F841  (alive across the call)
+    ws = _guard(prm, kappa_max, defer, P, padded.device, learned_split)  # noqa: F841
     _check(_lib.srhd_fluid_step(ctypes.byref(d), _ptr(out), _ptr(dt_lev), ctypes.byref(prm),
                                 _ptr(stats), _stream()))
     return out
@@ -444,7 +451,8 @@ STATIC_MAX_PATCH = 1048576
 
 def srhd_fluid_step_static(padded, dt_lev, dh, level=None, out=None, theta=1.5, riemann=HLLC,
                            prec=PREC_FP64, max_retry=4, stats=None, ghost=None, guess=None,
-                           groups=0, chunk=1, occupancy=0, kappa_max=KAPPA_MAX_DEFAULT):
+                           groups=0, chunk=1, occupancy=0, kappa_max=KAPPA_MAX_DEFAULT,
+                           learned_split=True):
     """srhd_fluid_step without caller work buffers: the precision guard's list and the persistent
     schedule's counters live in the library's static device array (at most STATIC_MAX_PATCH
     patches; concurrent calls on one GPU race).  `out` must be supplied by a caller that cannot
@@ -460,6 +468,7 @@ def srhd_fluid_step_static(padded, dt_lev, dh, level=None, out=None, theta=1.5, 
     prm = _params(theta, riemann, prec, max_retry, guess, None)
     prm.sched = srhd_sched(int(groups), int(chunk), int(occupancy), None)
     prm.kappa_max = float(kappa_max)
+    prm.learned_split = int(bool(learned_split))
     prm.defer = None
     _check(_lib.srhd_fluid_step_static(ctypes.byref(d), _ptr(out), _ptr(dt_lev),
                                        ctypes.byref(prm), _ptr(stats), _stream()))
@@ -494,7 +503,7 @@ def srhd_fluid_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, dt_
                          level=None, cons_out=None, prims_out=None, smax_out=None, dt_used=None,
                          theta=1.5, riemann=HLLC, prec=PREC_FP64, max_retry=4, stats=None,
                          guess=None, sched=None, gamma=None, kappa_max=KAPPA_MAX_DEFAULT,
-                         defer=None):
+                         defer=None, learned_split=True):
     """One step of a block of same-level patches (ghosts gathered from neighbour interiors).
     Returns (cons_out, prims_out, smax_out)."""
     _need_cuda(cons, prims, neighbor, smax_in, dt_lev, level, stats)
@@ -510,7 +519,7 @@ def srhd_fluid_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, dt_
         raise TypeError("primitives must be %s for this precision" % prims_dtype(prec))
     gr = _grid(cons, prims, neighbor, dh, level)
     prm = _params(theta, riemann, prec, max_retry, guess, sched, gamma=gamma)
-    ws = _guard(prm, kappa_max, defer, P, cons.device)  # noqa: F841  (alive across the call)
+    ws = _guard(prm, kappa_max, defer, P, cons.device, learned_split)  # noqa: F841
     _check(_lib.srhd_fluid_step_grid(ctypes.byref(gr), _ptr(smax_in), float(c_cfl), _ptr(dt_lev),
                                      _ptr(cons_out), _ptr(prims_out), _ptr(smax_out),
                                      _ptr(dt_used), ctypes.byref(prm), _ptr(stats), _stream()))

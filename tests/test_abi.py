@@ -49,7 +49,7 @@ def test_argument_errors_are_reported_without_a_gpu(lib):
     assert b"overlap" in lib.srhd_last_error()
     assert lib.srhd_prim2cons(0, 1, a + 1, a + 400, None, None) == -1      # misaligned
     lib.srhd_abi_version.restype = ctypes.c_int
-    assert lib.srhd_abi_version() == 6
+    assert lib.srhd_abi_version() == 7
 
 
 def test_step_descriptor_checks(lib):
@@ -178,9 +178,12 @@ def test_schedule_checks(lib):
     assert call() == -1 and b"defer" in S._lib.srhd_last_error()
     prm.defer = al(out)
     assert call() == -1 and b"overlaps" in S._lib.srhd_last_error()
-    prm.prec = 0
     prm.defer = None
     prm.kappa_max = 0.0
+    prm.learned_split = 2
+    assert call() == -1 and b"learned_split" in S._lib.srhd_last_error()
+    prm.learned_split = 0
+    prm.prec = 0
     # the allocation-free step: at most SRHD_STATIC_MAX_PATCH patches, no caller work buffers
     d.n_patch = S.STATIC_MAX_PATCH + 1
     rc = S._lib.srhd_fluid_step_static(ctypes.byref(d), al(out), al(dt), ctypes.byref(prm), None,
