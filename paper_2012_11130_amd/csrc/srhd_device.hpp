@@ -55,6 +55,14 @@ __device__ __forceinline__ double sqrt_nr(double x)
 __device__ __forceinline__ float sqrt_nr(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double sq(double a) { return __builtin_sqrt(a); }
 __device__ __forceinline__ float sq(float a) { return __builtin_amdgcn_sqrtf(a); }
+// Division in the step's bulk: with FX (the FP64 step kernels) a times the refined reciprocal
+// (about 1 ulp) in FP64; otherwise dv.  (The refined square root is not used there: inlined
+// into the Riemann solver it pushes the 768-thread FP64 step into scratch spills.)
+template <bool FX, class T> __device__ __forceinline__ T dvx(T a, T b)
+{
+  if constexpr (FX && sizeof(T) == 8) return a * rcp_nr(b);
+  else return dv(a, b);
+}
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 template <class T> __device__ __forceinline__ T absT(T a) { return a < T(0) ? -a : a; }
@@ -195,11 +203,11 @@ __device__ __forceinline__ T theta_of_htilde(T ht)
 }
 
 // Eq. 14: squared sound speed.
-template <class T>
+template <bool FX = false, class T>
 __device__ __forceinline__ T sound_speed2(T th)
 {
   T h = T(2.5) * th + sq(T(2.25) * th * th + T(1));
-  return dv(th * (T(5) * h - T(8) * th), T(3) * h * (h - th));
+  return dvx<FX>(th * (T(5) * h - T(8) * th), T(3) * h * (h - th));
 }
 
 // The polytropic EoS of Sec. 2.2, h = 1 + Theta / k with k = (Gamma - 1) / Gamma, as an
@@ -213,12 +221,12 @@ template <class T> __device__ __forceinline__ T htilde_of_theta(T th, EosTm) { r
 template <class T> __device__ __forceinline__ T htilde_of_theta(T th, const EosPoly &e) { return dv(th, T(e.k)); }
 template <class T> __device__ __forceinline__ T theta_of_htilde(T ht, EosTm) { return theta_of_htilde(ht); }
 template <class T> __device__ __forceinline__ T theta_of_htilde(T ht, const EosPoly &e) { return T(e.k) * ht; }
-template <class T> __device__ __forceinline__ T sound_speed2(T th, EosTm) { return sound_speed2(th); }
+template <bool FX = false, class T> __device__ __forceinline__ T sound_speed2(T th, EosTm) { return sound_speed2<FX>(th); }
 // c_s^2 = Gamma Theta / h = k Theta / ((1 - k)(k + Theta))
-template <class T> __device__ __forceinline__ T sound_speed2(T th, const EosPoly &e)
+template <bool FX = false, class T> __device__ __forceinline__ T sound_speed2(T th, const EosPoly &e)
 {
   const T k = T(e.k);
-  return dv(k * th, (T(1) - k) * (k + th));
+  return dvx<FX>(k * th, (T(1) - k) * (k + th));
 }
 
 // ------------------------------------------------------------------------------ inversion
@@ -239,9 +247,10 @@ __device__ __forceinline__ T guess_analytic(T L, T m2)
     hot = sl * (T(437) * m2 + T(117)) > T(1800) * a;
     if (hot) return T(4.0 / 3.0) * sl;
   }
-  if (hot) return T(4.0 / 3.0) * sq(L);
+  // a starting point only: in FP64 the refined reciprocal and square root (about 1 ulp) will do
+  if (hot) return T(4.0 / 3.0) * sqrt_nr(L);
   T b = T(43) * m2 + T(63);
-  return dv(T(125) * a * L, T(75) * a + sq(T(125) * a * b * L + T(5625) * a * a));
+  return T(125) * a * L * rcp_nr(T(75) * a + sqrt_nr(T(125) * a * b * L + T(5625) * a * a));
 }
 
 // Newton iteration for f(ht) = L from x.  With h = ht + 1, s = sqrt(9 h^2 + 16),
@@ -307,20 +316,23 @@ struct InvOut {
   int iters;                   // Newton iterations (both guesses)
 };
 
-// Recovery after the root: Eqs. 17, 8, 5a, 16, 18.
-template <class T>
+// Recovery after the root: Eqs. 17, 8, 5a, 16, 18.  FAST (FP64): the refined reciprocal and
+// square root (about 1 ulp) in place of IEEE division and square root.
+template <class T, bool FAST = false>
 __device__ __forceinline__ void recover(T D, T Mx, T My, T Mz, T ht, InvOut<T> &o)
 {
-  T iDh = dv(T(1), D * (T(1) + ht));
+  T iDh = FAST ? rcp_nr(D * (T(1) + ht)) : dv(T(1), D * (T(1) + ht));
   o.ux = Mx * iDh;
   o.uy = My * iDh;
   o.uz = Mz * iDh;
-  T gam = sq(T(1) + o.ux * o.ux + o.uy * o.uy + o.uz * o.uz);
+  const T g2 = T(1) + o.ux * o.ux + o.uy * o.uy + o.uz * o.uz;
+  T gam = FAST ? sqrt_nr(g2) : sq(g2);
   if constexpr (sizeof(T) == 8) {
     // rho = D / gamma and Theta of Eq. 16 share one division
     T h = ht + T(1);
-    T den = T(5) * h + sq(T(9) * h * h + T(16));
-    T inv = dv(T(1), gam * den);
+    const T s2 = T(9) * h * h + T(16);
+    T den = T(5) * h + (FAST ? sqrt_nr(s2) : sq(s2));
+    T inv = FAST ? rcp_nr(gam * den) : dv(T(1), gam * den);
     o.rho = D * den * inv;
     o.p = o.rho * (T(2) * ht * (ht + T(2)) * gam * inv);
   } else {
@@ -476,7 +488,7 @@ __device__ __forceinline__ void invert_with_L(T D, T Mx, T My, T Mz, T L, T gues
   o.iters = its;
   if constexpr (std::is_same<R, T>::value) {
     if constexpr (poly) recover_poly(D, Mx, My, Mz, ht, k, o);
-    else recover(D, Mx, My, Mz, ht, o);
+    else recover<T, FAST && !poly>(D, Mx, My, Mz, ht, o);
   } else {
     InvOut<R> r;
     if constexpr (poly) recover_poly((R)D, (R)Mx, (R)My, (R)Mz, (R)ht, (R)k, r);
@@ -588,13 +600,13 @@ __device__ __forceinline__ bool admissible_total(I D, I Mx, I My, I Mz, I E, dou
 template <class T>
 struct FaceAux { T gam, igam, cs2; };
 
-template <class T, class E = EosTm>
+template <bool FX = false, class T, class E = EosTm>
 __device__ __forceinline__ FaceAux<T> face_aux(const Prim<T> &w, const E &eos = E())
 {
   FaceAux<T> x;
   x.gam = sq(T(1) + w.u[0] * w.u[0] + w.u[1] * w.u[1] + w.u[2] * w.u[2]);
-  x.igam = dv(T(1), x.gam);
-  x.cs2 = sound_speed2(dv(w.p, w.rho), eos);
+  x.igam = dvx<FX>(T(1), x.gam);
+  x.cs2 = sound_speed2<FX>(dvx<FX>(w.p, w.rho), eos);
   return x;
 }
 
@@ -622,7 +634,7 @@ __device__ __forceinline__ Cons<T> phys_flux(const Prim<T> &w, const Cons<T> &u)
 
 // Signal speeds along d in four-velocity form:
 // lambda_pm = [gamma U_d (1 - cs^2) +- cs sqrt(1 + U_perp^2 (1 - cs^2))] / (1 + U^2 (1 - cs^2)).
-template <int d, class T>
+template <int d, bool FX = false, class T>
 __device__ __forceinline__ void signal_speeds(const Prim<T> &w, const FaceAux<T> &x, T &lm, T &lp)
 {
   constexpr int a1 = d == 0 ? 1 : 0, a2 = d == 2 ? 1 : 2;
@@ -631,7 +643,7 @@ __device__ __forceinline__ void signal_speeds(const Prim<T> &w, const FaceAux<T>
   T Up2 = w.u[a1] * w.u[a1] + w.u[a2] * w.u[a2];
   T U2 = Ud * Ud + Up2;
   T a = T(1) - cs2;
-  T iden = dv(T(1), T(1) + U2 * a);
+  T iden = dvx<FX>(T(1), T(1) + U2 * a);
   // cs sqrt(1 + Up^2 a) as one square root in FP32
   T s = sizeof(T) == 4 ? sq(cs2 * (T(1) + Up2 * a)) : sq(cs2) * sq(T(1) + Up2 * a);
   T c = gam * Ud * a;
@@ -648,17 +660,17 @@ __device__ __forceinline__ void signal_speeds(const Prim<T> &w, T &lm, T &lp, co
 // variables of wl, wr (the states the primitives were inverted from, where the caller has them).
 // TOT: the original scheme's variables (total energy E).
 // xl, xr: gamma, 1 / gamma and c_s^2 of the two sides.
-template <int d, bool TOT = false, class T>
+template <int d, bool TOT = false, bool FX = false, class T>
 __device__ __forceinline__ Cons<T> hlle(const Prim<T> &wl, const Prim<T> &wr, const Cons<T> &ul,
                                         const Cons<T> &ur, const FaceAux<T> &xl, const FaceAux<T> &xr)
 {
   Cons<T> fl = phys_flux<d, TOT>(wl, ul, xl.igam), fr = phys_flux<d, TOT>(wr, ur, xr.igam);
   T lmL, lpL, lmR, lpR;
-  signal_speeds<d>(wl, xl, lmL, lpL);
-  signal_speeds<d>(wr, xr, lmR, lpR);
+  signal_speeds<d, FX>(wl, xl, lmL, lpL);
+  signal_speeds<d, FX>(wr, xr, lmR, lpR);
   T sl = minT(minT(lmL, lmR), T(0));
   T sr = maxT(maxT(lpL, lpR), T(0));
-  T inv = dv(T(1), sr - sl);
+  T inv = dvx<FX>(T(1), sr - sl);
   T srl = sr * sl;
   Cons<T> F;
   F.D = (sr * fl.D - sl * fr.D + srl * (ur.D - ul.D)) * inv;
@@ -692,17 +704,17 @@ __device__ __forceinline__ Cons<T> sel(bool c, const Cons<T> &a, const Cons<T> &
 // Et* = [Et (S - v) + p* l* - p v] / (S - l*), which carries no rest-mass cancellation.
 // TOT: the original scheme, whose energy slot already holds E (and its flux M_d); its star state
 // E* takes the same form.
-template <int d, bool TOT = false, class T>
+template <int d, bool TOT = false, bool FX = false, class T>
 __device__ __forceinline__ Cons<T> hllc(const Prim<T> &wl, const Prim<T> &wr, const Cons<T> &ul,
                                         const Cons<T> &ur, const FaceAux<T> &xl, const FaceAux<T> &xr)
 {
   Cons<T> fl = phys_flux<d, TOT>(wl, ul, xl.igam), fr = phys_flux<d, TOT>(wr, ur, xr.igam);
   T lmL, lpL, lmR, lpR;
-  signal_speeds<d>(wl, xl, lmL, lpL);
-  signal_speeds<d>(wr, xr, lmR, lpR);
+  signal_speeds<d, FX>(wl, xl, lmL, lpL);
+  signal_speeds<d, FX>(wr, xr, lmR, lpR);
   T sl = minT(lmL, lmR);
   T sr = maxT(lpL, lpR);
-  T inv = dv(T(1), sr - sl);
+  T inv = dvx<FX>(T(1), sr - sl);
   T srl = sl * sr;
   // HLL averages of the quantities the contact speed needs
   T Dh = (sr * ur.D - sl * ul.D + fl.D - fr.D) * inv;
@@ -713,7 +725,7 @@ __device__ __forceinline__ Cons<T> hllc(const Prim<T> &wl, const Prim<T> &wr, co
   T Fmh = (srl * (ur.m[d] - ul.m[d]) + sr * fl.m[d] - sl * fr.m[d]) * inv;
   T B = Eh + Fmh;
   T disc = maxT(B * B - T(4) * FEh * mh, T(0));
-  T ls = dv(T(2) * mh, B + sq(disc));
+  T ls = dvx<FX>(T(2) * mh, B + sq(disc));
   T ps = Fmh - ls * FEh;
   bool left = ls >= T(0);
   Cons<T> u = sel(left, ul, ur);
@@ -722,7 +734,7 @@ __device__ __forceinline__ Cons<T> hllc(const Prim<T> &wl, const Prim<T> &wr, co
   T wp = left ? wl.p : wr.p;
   T v = (left ? wl.u[d] : wr.u[d]) * (left ? xl.igam : xr.igam);
   T a = S - v;
-  T iS = dv(T(1), S - ls);
+  T iS = dvx<FX>(T(1), S - ls);
   Cons<T> us;
   us.D = u.D * a * iS;
 #pragma unroll

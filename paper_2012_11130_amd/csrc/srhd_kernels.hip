@@ -73,8 +73,10 @@ __global__ void __launch_bounds__(kBlock) k_cons2prim(int64_t n, const T *__rest
     if (MLP) guess = (T)mlp_guess(mlp, D, Mx, My, Mz, Et, (in && adm) ? (double)L : 0.0, consulted, evals);
     if (!in) continue;
     InvOut<T> o;
+    // FP64: the Newton iteration and 1/D through the refined reciprocal and square root (about
+    // 1 ulp); L stays correctly rounded and the recovery keeps IEEE divisions
     if (adm)
-      invert_with_L<T, T>(D, Mx, My, Mz, L, guess, consulted, T(Tol<T>::v), max_iter, o, eos);
+      invert_with_L<T, T, T, sizeof(T) == 8>(D, Mx, My, Mz, L, guess, consulted, T(Tol<T>::v), max_iter, o, eos);
     else
       set_unphysical(o);
     prim[i] = o.rho;

@@ -113,6 +113,13 @@ using GuessT = typename std::conditional<sizeof(T) == 4, float, I>::type;
 // give the same bits), and the FP32-bulk gather kernels (in the FP32-bulk padded kernels they
 // cost registers and occupancy).
 template <class T, bool GATHER> constexpr bool fast_of() { return sizeof(T) == 8 || GATHER; }
+// Downstream of the face inversions (the face states' gamma, 1 / gamma and c_s^2, the Riemann
+// solver) the FP64 bulk divides through the refined reciprocal (about 1 ulp).  Upstream of them
+// (slopes, prim -> cons, the half-step corrections) it keeps IEEE division: an inversion turns a
+// changed rounding of its input into a change of the face state of up to kappa times it (Eq. 20),
+// about 1e-9 where kappa ~ 1e6, which would exceed the step's 1e-10 parity against the oracle.
+// The FP32 bulk keeps its own arithmetic.
+template <class T> constexpr bool fx_of() { return sizeof(T) == 8; }
 
 // Newton tolerance by (bulk type T, inversion type I): FP64 to ~2^-54; an FP64 inversion whose
 // result is consumed in FP32 to ~2^-28; an FP32 inversion to FP32 accuracy.
@@ -200,7 +207,7 @@ __device__ __forceinline__ bool invert_face(const Cons<T> &u, bool ok, double L,
     x.igam = (T)o.igam;
     x.cs2 = (T)o.cs2;
   } else {
-    x = face_aux(w, eos);
+    x = face_aux<fx_of<T>()>(w, eos);
   }
   iters = o.iters;
   status = o.status;
@@ -293,7 +300,9 @@ __device__ __forceinline__ bool interface_flux(Tile<T> &s, int r, T theta, int s
   // the face states' conserved variables are the ones just inverted: no round trip through
   // prim -> cons
   constexpr bool TOT = K == KV_TOTAL;
-  Cons<T> F = solver == SRHD_HLLE ? hlle<d, TOT>(wl, wr, ul, ur, xl, xr) : hllc<d, TOT>(wl, wr, ul, ur, xl, xr);
+  constexpr bool FX = fx_of<T>();
+  Cons<T> F = solver == SRHD_HLLE ? hlle<d, TOT, FX>(wl, wr, ul, ur, xl, xr)
+                                  : hllc<d, TOT, FX>(wl, wr, ul, ur, xl, xr);
   constexpr int slot = d & 1;
   s.F[slot][0][r] = F.D;
   s.F[slot][1][r] = F.m[0];
