@@ -171,6 +171,19 @@ def summarize_profile(d, calib_mib):
             print("| %s | %.3e | %.3e | %.2f | %.1f %% | %.3e | %.1f %% | %.3e | %.3f |"
                   % (k, a64, a32, (a64 + a32) / t / 1e12, 100 * (a64 + a32) / t / PEAK_ALU, vi,
                      100 * vi / t / issue_peak, avg(c.get("SQ_INSTS_LDS", [])), bc))
+    # where the wavefronts spend their time: fractions of SQ_WAVE_CYCLES (summed over waves)
+    wn = ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_WAIT_INST_LDS", "SQ_ACTIVE_INST_ANY",
+          "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS", "SQ_ACTIVE_INST_VMEM")
+    rows = [k for k in sorted(dur, key=lambda k: -sum(dur[k]))
+            if all(n in cnt.get(k, {}) for n in ("SQ_WAVE_CYCLES",) + wn)]
+    if rows:
+        print()
+        print("| kernel | waiting (any) | waiting on an instruction | waiting on LDS | issuing (any) | VALU | LDS | VMEM |")
+        print("|---|---|---|---|---|---|---|---|")
+        for k in rows:
+            c = cnt[k]
+            wc = avg(c["SQ_WAVE_CYCLES"])
+            print("| %s | %s |" % (k, " | ".join("%.1f %%" % (100 * avg(c[n]) / wc) for n in wn)))
 
 
 def run_jet(args, S, W, dev, stream, guess, guess_name):
