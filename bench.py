@@ -466,6 +466,10 @@ def main():
             pbufs[key] = [torch.empty(cons0.shape, dtype=pdt, device=dev) for _ in range(2)]
         pb = pbufs[key]
         sb = [torch.empty(1, dtype=torch.int64, device=dev) for _ in range(2)]
+        # the learned guess's network masks travel with the state (the split's list before each
+        # step, and its learned kernel beside the other on a second stream)
+        learned = guess is not None and guess.kind == S.GUESS_MLP
+        nmask = [S.new_net_mask(cons0.shape[0], dev) if learned else None for _ in range(2)]
         bufs[0].copy_(cons0)
         cur = 0
         S.srhd_stats_reset(stats)
@@ -474,7 +478,8 @@ def main():
         e_end = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e_start.record(stream)
-        S.srhd_grid_prims(bufs[0], prec=prec, prims=pb[0], smax_bits=sb[0], guess=guess)
+        S.srhd_grid_prims(bufs[0], prec=prec, prims=pb[0], smax_bits=sb[0], guess=guess,
+                          net_mask=nmask[0])
         for _ in range(n_steps):
             if time_kernel:
                 a = torch.cuda.Event(enable_timing=True)
@@ -483,7 +488,7 @@ def main():
             S.srhd_fluid_step_grid(bufs[cur], pb[cur], nb, dh, smax_in=sb[cur], c_cfl=0.5,
                                    cons_out=bufs[1 - cur], prims_out=pb[1 - cur],
                                    smax_out=sb[1 - cur], prec=prec, stats=stats, guess=guess,
-                                   sched=sched)
+                                   sched=sched, net_in=nmask[cur], net_out=nmask[1 - cur])
             if time_kernel:
                 b.record(stream)
                 evs.append((a, b))
@@ -504,9 +509,10 @@ def main():
                 oc = 0
             return S.Sched(gr, ch, dev, occupancy=oc), []
         if args.path == "grid":
-            prims, smax = S.srhd_grid_prims(cons0, prec=prec, guess=guess)
+            mask = S.new_net_mask(cons0.shape[0], dev)
+            prims, smax = S.srhd_grid_prims(cons0, prec=prec, guess=guess, net_mask=mask)
             sch, table = S.srhd_autotune_step_grid(cons0, prims, nb, dh, smax_in=smax, prec=prec,
-                                                   guess=guess, reps=2)
+                                                   guess=guess, reps=2, net_in=mask)
         else:
             S.srhd_cfl_dt(cons0, dh, 0.5, dt_lev=dt)
             S.srhd_fill_ghosts(cons0, nb, 3, padded=pad)

@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define SRHD_ABI_VERSION 7
+#define SRHD_ABI_VERSION 8
 
 typedef enum { SRHD_F64 = 0, SRHD_F32 = 1 } srhd_dtype;
 
@@ -243,7 +243,12 @@ typedef struct {
  * L > gate_L.  The other patches run no network code: where the gate keeps the network out of a
  * patch, its registers and code cost that patch nothing.  Results equal a single launch's up to
  * the Newton tolerance (a face state with L above the gate in an unlisted patch starts from the
- * analytic guess instead).  A patch the guard steps in FP64 is not listed.
+ * analytic guess instead).  A patch the guard steps in FP64 is not listed.  In the gather layout
+ * with the state's network masks (srhd_grid.net_mask) the list is known before the step: it holds
+ * the patches whose 12^3 tile (the patch and the two layers of its 26 neighbours next to it)
+ * holds a cell with L > gate_L, and the learned kernel steps them on a second stream of the
+ * library's, concurrently with the kernel without the network, which skips them; the call joins
+ * that stream back into `stream` before it returns (work queued later on `stream` waits for both).
  *
  * defer: device memory of 2 n_patch + 4 uint64 words (8-byte aligned), required when the guard or
  * the split is on; zeroed by the call on its stream.  Afterwards word 0 holds the number of
@@ -347,22 +352,34 @@ typedef struct {
   const int8_t *level;     /* [n_patch] or NULL */
   int n_level;
   double dh[SRHD_MAX_LEVEL];  /* host */
+  const uint32_t *net_mask; /* [n_patch] or NULL: the state's network masks, as written by
+                              srhd_grid_prims or the step that made the state (read only by the
+                              learned-guess split) */
 } srhd_grid;
+
+/* Network mask of a patch of a gather-layout state: bit (rz + 1) 9 + (ry + 1) 3 + (rx + 1) is set
+ * when the patch holds a cell whose L (Eq. 15's left-hand side, formed as for the cell's
+ * inversion) exceeds the learned guess's gate_L in region (rx, ry, rz), where along each axis
+ * r = 0 takes every cell, r = -1 the two lowest layers and r = +1 the two highest (the layers a
+ * neighbour's step reads).  Zero with the analytic guess. */
 
 /* Entry state of a chain of srhd_fluid_step_grid calls: inverts every interior cell (as
  * srhd_cons2prim, from the guess `guess` selects -- NULL: the analytic guess -- with the Newton
  * tolerance and inversion type of the step's precision), writes the
  * primitives in the step's bulk type, and the maximum S_max (Eqs. 26-27) over the cells as the
  * bit pattern of a positive double in *smax_bits (device; zeroed first).  Unphysical cells get
- * NaN primitives and do not enter the maximum. */
+ * NaN primitives and do not enter the maximum.  net_mask (device uint32 [n_patch], or NULL)
+ * receives the state's network masks. */
 int srhd_grid_prims(int prec, int64_t n_patch, const double *cons, void *prims,
-                    uint64_t *smax_bits, const srhd_guess *guess, void *stream);
+                    uint64_t *smax_bits, uint32_t *net_mask, const srhd_guess *guess,
+                    void *stream);
 
 /* One MUSCL-Hancock step of a srhd_grid, identical in arithmetic to srhd_fluid_step on the
  * padded copies of the same patches.  The time step is dt_l = c_cfl * dh[l] / S_max with S_max
  * read from *smax_in (the bits written by srhd_grid_prims or by the previous step), unless
  * dt_lev (device double[n_level]) is given.  Outputs: cons_out [n_patch][5][8][8][8] FP64,
  * prims_out (bulk type) and *smax_out (zeroed, then the maximum over the updated cells);
+ * net_out (device uint32 [n_patch], or NULL) the updated state's network masks;
  * dt_used (device double[n_level], may be NULL) receives the time step used.
  * Outputs must not overlap the inputs.  Patches are mapped to workgroups so that each XCD works
  * on a contiguous range of patch indices (order patches along a space-filling curve).  The
@@ -370,15 +387,16 @@ int srhd_grid_prims(int prec, int64_t n_patch, const double *cons, void *prims,
  * SRHD_VL gives SRHD_EUNSUPPORTED). */
 int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_cfl,
                          const double *dt_lev, double *cons_out, void *prims_out,
-                         uint64_t *smax_out, double *dt_used, const srhd_step_params *prm,
-                         srhd_step_stats *stats, void *stream);
+                         uint64_t *smax_out, uint32_t *net_out, double *dt_used,
+                         const srhd_step_params *prm, srhd_step_stats *stats, void *stream);
 
 /* The schedule autotuner of srhd_autotune_step for srhd_fluid_step_grid on the same arguments
  * (outputs written, prm->sched set to the fastest candidate; synchronises `stream`). */
 int srhd_autotune_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_cfl,
                             const double *dt_lev, double *cons_out, void *prims_out,
-                            uint64_t *smax_out, srhd_step_params *prm, int reps,
-                            srhd_tune_entry *table, int table_cap, int *n_table, void *stream);
+                            uint64_t *smax_out, uint32_t *net_out, srhd_step_params *prm,
+                            int reps, srhd_tune_entry *table, int table_cap, int *n_table,
+                            void *stream);
 
 /* ---------------------------------------------------------------------------------------- */
 /* The learned guess: inference and training                                                */

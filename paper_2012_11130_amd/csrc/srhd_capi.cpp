@@ -173,6 +173,9 @@ int check_lists(const srhd_step_params *prm, const srhd::GuessArgs &g, double eo
   s.defer = nullptr;
   s.kappa_max = 0.0;
   s.net_list = nullptr;
+  s.net_in = nullptr;
+  s.net_out = nullptr;
+  s.net_gate = __builtin_huge_val();
   s.list = nullptr;
   s.list_counter = 0;
   const double k = prm->kappa_max;
@@ -586,18 +589,20 @@ int srhd_autotune_step(const srhd_patches *in, void *out, const double *dt_lev,
 
 int srhd_autotune_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_cfl,
                             const double *dt_lev, double *cons_out, void *prims_out,
-                            uint64_t *smax_out, srhd_step_params *prm, int reps,
-                            srhd_tune_entry *table, int table_cap, int *n_table, void *stream)
+                            uint64_t *smax_out, uint32_t *net_out, srhd_step_params *prm,
+                            int reps, srhd_tune_entry *table, int table_cap, int *n_table,
+                            void *stream)
 {
   return autotune(prm, 1, reps, table, table_cap, n_table, stream, "srhd_autotune_step_grid",
                   [&](const srhd_step_params *t) {
                     return srhd_fluid_step_grid(in, smax_in, c_cfl, dt_lev, cons_out, prims_out,
-                                                smax_out, nullptr, t, nullptr, stream);
+                                                smax_out, net_out, nullptr, t, nullptr, stream);
                   });
 }
 
 int srhd_grid_prims(int prec, int64_t n_patch, const double *cons, void *prims,
-                    uint64_t *smax_bits, const srhd_guess *guess, void *stream)
+                    uint64_t *smax_bits, uint32_t *net_mask, const srhd_guess *guess,
+                    void *stream)
 {
   srhd::GuessArgs g;
   int rc = check_guess(guess, g);
@@ -608,14 +613,21 @@ int srhd_grid_prims(int prec, int64_t n_patch, const double *cons, void *prims,
   if (!smax_bits || (n_patch > 0 && (!cons || !prims)))
     return fail(SRHD_EINVAL, "srhd_grid_prims: NULL argument");
   size_t ps = prec == SRHD_PREC_FP64 ? 8 : 4;
-  if (!aligned(cons, 8) || !aligned(prims, ps) || !aligned(smax_bits, 8))
+  if (!aligned(cons, 8) || !aligned(prims, ps) || !aligned(smax_bits, 8) || !aligned(net_mask, 4))
     return fail(SRHD_EINVAL, "srhd_grid_prims: misaligned array");
   const char *a = (const char *)cons, *b = (const char *)prims;
   size_t ab = (size_t)n_patch * 5 * 512 * 8, bb = (size_t)n_patch * 5 * 512 * ps;
   if (n_patch > 0 && a < b + bb && b < a + ab)
     return fail(SRHD_EINVAL, "srhd_grid_prims: prims overlap cons");
+  if (net_mask) {
+    const size_t nb = (size_t)n_patch * 4;
+    if (!disjoint(net_mask, nb, cons, ab) || !disjoint(net_mask, nb, prims, bb) ||
+        !disjoint(net_mask, nb, smax_bits, 8))
+      return fail(SRHD_EINVAL, "srhd_grid_prims: net_mask overlaps another array");
+  }
   return hip_status(srhd::launch_grid_prims(prec, n_patch, cons, prims,
-                                            (unsigned long long *)smax_bits, g, (hipStream_t)stream),
+                                            (unsigned long long *)smax_bits, net_mask, g,
+                                            (hipStream_t)stream),
                     "srhd_grid_prims");
 }
 
@@ -684,8 +696,8 @@ int srhd_mlp_adam(float *master, float *m1, float *m2, const float *grad, int st
 
 int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_cfl,
                          const double *dt_lev, double *cons_out, void *prims_out,
-                         uint64_t *smax_out, double *dt_used, const srhd_step_params *prm,
-                         srhd_step_stats *stats, void *stream)
+                         uint64_t *smax_out, uint32_t *net_out, double *dt_used,
+                         const srhd_step_params *prm, srhd_step_stats *stats, void *stream)
 {
   if (!in || !prm) return fail(SRHD_EINVAL, "srhd_fluid_step_grid: NULL descriptor");
   if (in->n_patch < 0) return fail(SRHD_EINVAL, "srhd_fluid_step_grid: n_patch < 0");
@@ -719,7 +731,8 @@ int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_
     if (!in->cons || !in->prims || !in->neighbor || !cons_out || !prims_out)
       return fail(SRHD_EINVAL, "srhd_fluid_step_grid: NULL array");
     if (!aligned(in->cons, 8) || !aligned(cons_out, 8) || !aligned(in->prims, ps) ||
-        !aligned(prims_out, ps) || !aligned(in->neighbor, 4) || !aligned(smax_out, 8))
+        !aligned(prims_out, ps) || !aligned(in->neighbor, 4) || !aligned(smax_out, 8) ||
+        !aligned(net_out, 4) || !aligned(in->net_mask, 4))
       return fail(SRHD_EINVAL, "srhd_fluid_step_grid: misaligned array");
     size_t cb = (size_t)in->n_patch * 5 * 512 * 8, pb = (size_t)in->n_patch * 5 * 512 * ps;
     struct R { const char *p; size_t n; } ins[2] = {{(const char *)in->cons, cb}, {(const char *)in->prims, pb}},
@@ -730,6 +743,14 @@ int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_
           return fail(SRHD_EINVAL, "srhd_fluid_step_grid: an output overlaps an input");
     if (outs[0].p < outs[1].p + outs[1].n && outs[1].p < outs[0].p + outs[0].n)
       return fail(SRHD_EINVAL, "srhd_fluid_step_grid: cons_out overlaps prims_out");
+    if (net_out) {
+      const size_t nb = (size_t)in->n_patch * 4;
+      const void *others[6] = {in->cons, in->prims, cons_out, prims_out, smax_out, in->net_mask};
+      const size_t osz[6] = {cb, pb, cb, pb, 8, nb};
+      for (int i = 0; i < 6; ++i)
+        if (others[i] && !disjoint(net_out, nb, others[i], osz[i]))
+          return fail(SRHD_EINVAL, "srhd_fluid_step_grid: net_out overlaps another array");
+    }
   }
   srhd::StepArgs s;
   s.n_patch = in->n_patch;
@@ -764,10 +785,16 @@ int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_
   if (rc) return rc;
   {
     const size_t cb = (size_t)in->n_patch * 5 * 512 * 8, pb = (size_t)in->n_patch * 5 * 512 * ps;
-    const void *reg[5] = {in->cons, in->prims, cons_out, prims_out, s.queue};
-    const size_t sz[5] = {cb, pb, cb, pb, SRHD_QUEUE_WORDS * 8};
-    rc = check_lists(prm, g, eos_k, in->n_patch, reg, sz, 5, s, "srhd_fluid_step_grid");
+    const size_t nb = (size_t)in->n_patch * 4;
+    const void *reg[7] = {in->cons, in->prims, cons_out, prims_out, s.queue, in->net_mask, net_out};
+    const size_t sz[7] = {cb, pb, cb, pb, SRHD_QUEUE_WORDS * 8, nb, nb};
+    rc = check_lists(prm, g, eos_k, in->n_patch, reg, sz, 7, s, "srhd_fluid_step_grid");
     if (rc) return rc;
+  }
+  if (in->n_patch > 0) {
+    s.net_out = net_out;
+    s.net_gate = g.kind == SRHD_GUESS_MLP ? g.gate : __builtin_huge_val();
+    if (s.net_list) s.net_in = in->net_mask;
   }
   return hip_status(srhd::launch_step_grid(prm->prec, s, (hipStream_t)stream),
                     "srhd_fluid_step_grid");

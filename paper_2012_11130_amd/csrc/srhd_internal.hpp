@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "../../include/srhd.h"
 #include "srhd_mlp.hpp"
 
@@ -80,6 +82,12 @@ struct StepArgs {
   // learned-guess split (NULL: off): the kernel without the network lists here the patches whose
   // tile holds a cell with L > guess.gate, and the learned kernel steps them in a second launch
   unsigned long long *net_list;
+  // gather layout: network masks of the input state (per patch, the regions holding a cell with
+  // L > gate; with the split on they decide the list before the step) and of the output (NULL:
+  // not written), formed from the updated cells whose L exceeds net_gate
+  const unsigned int *net_in;
+  unsigned int *net_out;
+  double net_gate;
   // set by the launcher for a launch over a list: the list it walks and the step counter
   // (srhd_step_stats word) each listed patch increments
   unsigned long long *list;
@@ -110,7 +118,8 @@ int step_occupancy_vl(int prec, bool occ2);
   hipError_t step_launch_##name(const StepArgs &a, bool gather, hipStream_t st);               \
   int step_occupancy_##name(bool gather, int kind, bool occ2);                                 \
   hipError_t grid_prims_##name(int64_t n_patch, const double *cons, void *prims,               \
-                               unsigned long long *smax_bits, const GuessArgs &g, hipStream_t st);
+                               unsigned long long *smax_bits, unsigned int *net_mask,           \
+                               const GuessArgs &g, hipStream_t st);
 SRHD_STEP_MODE(fp64)
 SRHD_STEP_MODE(mixed)
 SRHD_STEP_MODE(fp32)
@@ -129,7 +138,19 @@ hipError_t launch_mlp_adam(float *master, float *m1, float *m2, const float *gra
                            float lr, uint16_t *w, float *bias, hipStream_t s);
 hipError_t launch_step_grid(int prec, const StepArgs &a, hipStream_t s);
 hipError_t launch_grid_prims(int prec, int64_t n_patch, const double *cons, void *prims,
-                             unsigned long long *smax_bits, const GuessArgs &g, hipStream_t s);
+                             unsigned long long *smax_bits, unsigned int *net_mask,
+                             const GuessArgs &g, hipStream_t s);
+
+// A second stream of the current device (default priority, non-blocking; created on first use
+// and kept until the process ends) with two events, for work forked off a caller's stream and
+// joined back into it.  The caller holds *lock from the fork's record to the join's wait, so
+// that concurrent calls do not interleave their records of the shared events.
+struct SideStream {
+  hipStream_t stream;
+  hipEvent_t fork, join;
+  std::mutex *lock;
+};
+hipError_t side_stream(SideStream &out);
 
 // AMR neighbour operations (srhd_amr.hip)
 hipError_t launch_fill_ghosts_coarse(int64_t n_fine, int ghost, const int32_t *neighbor,

@@ -319,6 +319,52 @@ __device__ __forceinline__ double wave_max(double v)
   return v;
 }
 
+// Sum over the wavefront (every lane active; every lane receives the total).  Counters are summed
+// this way before one lane per wavefront adds them to the workgroup's: an atomic add from all 64
+// lanes to one address is compiled to a loop over the lanes, which cost the whole step ~15 %.
+__device__ __forceinline__ unsigned int wave_sum(unsigned int v)
+{
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ unsigned int wave_or(unsigned int v)
+{
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Network-mask regions of interior cell (i, j, k): bit (rz + 1) 9 + (ry + 1) 3 + (rx + 1) for
+// every region it lies in, along each axis r = 0 (every cell), r = -1 (the two lowest layers),
+// r = +1 (the two highest).
+__device__ __forceinline__ unsigned int region_mask(int i, int j, int k)
+{
+  const unsigned int ax = 2u | (i < 2 ? 1u : 0u) | (i >= 6 ? 4u : 0u);
+  const unsigned int ay = 2u | (j < 2 ? 1u : 0u) | (j >= 6 ? 4u : 0u);
+  const unsigned int az = 2u | (k < 2 ? 1u : 0u) | (k >= 6 ? 4u : 0u);
+  unsigned int m = 0u;
+#pragma unroll
+  for (int z = 0; z < 3; ++z)
+#pragma unroll
+    for (int y = 0; y < 3; ++y)
+#pragma unroll
+      for (int x = 0; x < 3; ++x)
+        if (((az >> z) & (ay >> y) & (ax >> x)) & 1u) m |= 1u << (z * 9 + y * 3 + x);
+  return m;
+}
+
+// Whether the 12^3 tile of a patch with neighbours nb[27] (index (dz + 1) 9 + (dy + 1) 3 +
+// (dx + 1) for the neighbour at offset (dx, dy, dz); -1 where there is none) holds a cell that
+// set a network mask: neighbour n contributes the region next to the patch, (-dx, -dy, -dz), whose
+// bit is 26 - n.  (Where a face neighbour is missing, the tile's outflow copies come from cells
+// in regions with r = 0 along that axis, which the other entries cover.)
+__device__ __forceinline__ bool tile_hits_mask(int n, int64_t q, int64_t n_patch, const unsigned int *mask)
+{
+  return q >= 0 && q < n_patch && ((mask[q] >> (26 - n)) & 1u);
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2); this mapping
 // hands each XCD a contiguous range of patches so that neighbouring patches, whose cells the
 // gather reads, are processed under the same L2.
@@ -369,6 +415,14 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
   if (GATHER && tid < 27) s.nb[tid] = a.neighbor[p * 27 + tid];
   unsigned int my_iters = 0, my_inv = 0, my_fb = 0, my_nc = 0, my_mlp = 0;
   __syncthreads();
+  // learned-guess split with the input's network masks: a patch whose tile holds a cell above
+  // the gate is on the list that the learned kernel steps (k_net_list applies the same rule)
+  if constexpr (GATHER && K == KV_ANALYTIC) {
+    if (a.net_list && a.net_in) {
+      const bool hit = tid < 27 && tile_hits_mask(tid, s.nb[tid], a.n_patch, a.net_in);
+      if (__syncthreads_or(hit)) return;
+    }
+  }
 
   // ---------------------------------------------------------------- A: centre primitives
   bool centre_bad = false, hot = false, net = false;
@@ -376,7 +430,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
   const T km1 = T(a.kappa_max - 1.0);
   // the learned-guess split's first launch (the kernel without the network) lists the patches
   // whose tile holds a cell with L above the network's gate
-  const bool split = K == KV_ANALYTIC && a.net_list != nullptr;
+  const bool split = K == KV_ANALYTIC && a.net_list != nullptr && !(GATHER && a.net_in);
   for (int r0 = 0; r0 < NPC; r0 += NTT) {
     // every lane runs every round (the learned guess needs whole wavefronts); lanes past the
     // end of the list work on the first cell again and store nothing
@@ -655,6 +709,13 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
           if (ok_out) sm = signal_smax((double)w.rho, (double)w.ux, (double)w.uy, (double)w.uz, (double)w.p);
         }
        }
+        if (a.net_out) {
+          // the updated state's network mask: L of the output check against the gate
+          const unsigned int m = wave_or(owner && ok_out && Lo > a.net_gate ? region_mask(ci, cj, ck) : 0u);
+          if ((tid & 63) == 0 && m) atomicOr(&s.cnt[7], m);
+          __syncthreads();
+          if (tid == 0) a.net_out[p] = s.cnt[7];
+        }
         sm = wave_max(sm);
         if ((tid & 63) == 0) s.red[tid >> 6] = sm;
         __syncthreads();
@@ -674,12 +735,17 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
 
   // ---------------------------------------------------------------- counters
   if (a.stats) {
-    atomicAdd(&s.cnt[0], unphys + centre_unphys);
-    atomicAdd(&s.cnt[1], my_fb);
-    atomicAdd(&s.cnt[2], my_nc);
-    atomicAdd(&s.cnt[3], my_iters);
-    atomicAdd(&s.cnt[4], my_inv);
-    if (MLP) atomicAdd(&s.cnt[5], my_mlp);
+    const unsigned int c0 = wave_sum(unphys + centre_unphys), c1 = wave_sum(my_fb),
+                       c2 = wave_sum(my_nc), c3 = wave_sum(my_iters), c4 = wave_sum(my_inv),
+                       c5 = MLP ? wave_sum(my_mlp) : 0u;
+    if ((tid & 63) == 0) {
+      atomicAdd(&s.cnt[0], c0);
+      atomicAdd(&s.cnt[1], c1);
+      atomicAdd(&s.cnt[2], c2);
+      atomicAdd(&s.cnt[3], c3);
+      atomicAdd(&s.cnt[4], c4);
+      if (MLP) atomicAdd(&s.cnt[5], c5);
+    }
     __syncthreads();
     if (tid == 0) {
       unsigned long long *st = (unsigned long long *)a.stats;
@@ -753,7 +819,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4)))
 // step counters.  Serves the precision guard's FP64 pass (T = I = double; PS, the storage type
 // of the gather layout's primitives, float) and the learned-guess split's network pass.
 template <class T, class I, bool GATHER, int K, class PS>
-__global__ void __launch_bounds__(threads_of<T>()) k_step_listed(StepArgs a)
+__device__ __forceinline__ void listed_body(const StepArgs &a)
 {
   const MlpDev mlp = a.guess.dev();
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -771,9 +837,48 @@ __global__ void __launch_bounds__(threads_of<T>()) k_step_listed(StepArgs a)
   }
 }
 
-__global__ void k_zero_defer(unsigned long long *d)
+template <class T, class I, bool GATHER, int K, class PS>
+__global__ void __launch_bounds__(threads_of<T>()) k_step_listed(StepArgs a)
 {
-  if (threadIdx.x < 2) d[threadIdx.x] = 0ull;
+  listed_body<T, I, GATHER, K, PS>(a);
+}
+
+// The same within the two-workgroup register budget (FP32 bulk): run beside the kernel without the
+// network, a workgroup then fits into the slot one of that kernel's workgroups leaves, instead of
+// waiting for a CU whose workgroups have all left -- which, while that kernel still has patches to
+// hand out, does not happen.
+template <class T, class I, bool GATHER, int K, class PS>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) k_step_listed_occ2(StepArgs a)
+{
+  listed_body<T, I, GATHER, K, PS>(a);
+}
+
+// The counters a step starts from: the two lists' count and claim words, the output S_max and
+// the n_mask output network masks (NULL pointers skipped).
+__global__ void k_step_prologue(unsigned long long *defer, unsigned long long *net_list,
+                                unsigned long long *smax_out, unsigned int *net_out,
+                                int64_t n_mask)
+{
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (net_out && i < n_mask) net_out[i] = 0u;
+  if (i < 2) {
+    if (defer) defer[i] = 0ull;
+    if (net_list) net_list[i] = 0ull;
+  }
+  if (i == 0 && smax_out) smax_out[0] = 0ull;
+}
+
+// The learned-guess split's list from the input's network masks: every patch whose tile holds a
+// cell above the gate, in no particular order.
+__global__ void __launch_bounds__(256) k_net_list(int64_t n_patch, const int32_t *__restrict__ neighbor,
+                                                  const unsigned int *__restrict__ mask,
+                                                  unsigned long long *list)
+{
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_patch) return;
+  bool hit = false;
+  for (int k = 0; k < 27; ++k) hit |= tile_hits_mask(k, neighbor[p * 27 + k], n_patch, mask);
+  if (hit) list[2 + atomicAdd(&list[0], 1ull)] = (unsigned long long)p;
 }
 
 // Inversion of every interior cell into the bulk type, with the maximum signal speed (the
@@ -783,7 +888,8 @@ template <class T, class I, bool MLP>
 __global__ void __launch_bounds__(256) k_grid_prims(int64_t n_patch, const double *__restrict__ cons,
                                                     T *__restrict__ prims,
                                                     unsigned long long *__restrict__ smax_bits,
-                                                    MlpDev mlp)
+                                                    unsigned int *__restrict__ net_mask,
+                                                    double net_gate, MlpDev mlp)
 {
   __shared__ double red[4];
   const int64_t total = n_patch * 512;
@@ -806,6 +912,11 @@ __global__ void __launch_bounds__(256) k_grid_prims(int64_t n_patch, const doubl
       invert_with_L<I, GuessT<T, I>, GuessT<T, I>, true>((I)u[0], (I)u[512], (I)u[1024], (I)u[1536], (I)L, (I)guess, consulted,
                        (I)StepTol<T, I>::v, 30, w);
     else set_unphysical(w);
+    // the state's network mask (every wavefront's cells lie in one patch)
+    if (net_mask) {
+      const unsigned int m = wave_or(ok && L > net_gate ? region_mask(c & 7, (c >> 3) & 7, c >> 6) : 0u);
+      if ((threadIdx.x & 63) == 0 && m) atomicOr(&net_mask[pp], m);
+    }
     T *po = prims + pp * 5 * 512 + c;
     po[0] = (T)w.rho;
     po[512] = (T)w.ux;
@@ -826,11 +937,6 @@ __global__ void __launch_bounds__(256) k_grid_prims(int64_t n_patch, const doubl
     double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
     atomicMax(smax_bits, (unsigned long long)__double_as_longlong(m));
   }
-}
-
-__global__ void k_zero_bits(unsigned long long *p)
-{
-  if (threadIdx.x == 0) p[0] = 0ull;
 }
 
 __global__ void k_zero_queue(unsigned long long *q)
@@ -864,11 +970,18 @@ int occupancy_k(bool occ2)
 
 // A persistent launch over a list of patches (k_step_listed): as many workgroups as fit on the
 // device at once (the FP64 tile fills a CU's LDS; two FP32-bulk tiles fit), at most the patches.
+// occ2 (FP32 bulk only): the kernel of the two-workgroup register budget.
 template <class T, class I, bool GATHER, int K, class PS>
-hipError_t launch_listed(const StepArgs &a, unsigned long long *list, int counter, hipStream_t st)
+hipError_t launch_listed(const StepArgs &a, unsigned long long *list, int counter, hipStream_t st,
+                         bool occ2 = false)
 {
   const size_t bytes = sizeof(Tile<T>);
   const void *fn = (const void *)k_step_listed<T, I, GATHER, K, PS>;
+  if constexpr (sizeof(T) == 4) {
+    if (occ2) fn = (const void *)k_step_listed_occ2<T, I, GATHER, K, PS>;
+  } else {
+    occ2 = false;
+  }
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   int dev = 0, cus = 0, per_cu = 0;
   if (e == hipSuccess) e = hipGetDevice(&dev);
@@ -882,6 +995,12 @@ hipError_t launch_listed(const StepArgs &a, unsigned long long *list, int counte
   b.list_counter = counter;
   b.queue = nullptr;
   b.net_list = nullptr;
+  if constexpr (sizeof(T) == 4) {
+    if (occ2) {
+      hipLaunchKernelGGL((k_step_listed_occ2<T, I, GATHER, K, PS>), dim3((unsigned)groups), dim3(NT), bytes, st, b);
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL((k_step_listed<T, I, GATHER, K, PS>), dim3((unsigned)groups), dim3(threads_of<T>()), bytes, st, b);
   return hipGetLastError();
 }
@@ -896,18 +1015,29 @@ hipError_t launch_step_listed(const StepArgs &a, hipStream_t st)
   return launch_listed<double, double, GATHER, KD, float>(b, a.defer, 8, st);
 }
 
+// Zeroes, in one launch, what the step's kernels count from: the guard's and the split's list
+// words, and in the gather layout the output S_max and network bits.
+template <class T, bool GATHER>
+hipError_t launch_prologue(const StepArgs &a, hipStream_t st)
+{
+  const bool guard = sizeof(T) == 4 && a.defer != nullptr;
+  const int64_t nw = GATHER && a.net_out ? a.n_patch : 0;
+  const int64_t n = nw > 2 ? nw : 2;
+  hipLaunchKernelGGL(k_step_prologue, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                     guard ? a.defer : nullptr, a.net_list, GATHER ? a.smax_out : nullptr,
+                     GATHER ? a.net_out : nullptr, nw);
+  return hipGetLastError();
+}
+
+// The step kernel over every patch (one workgroup per patch, or the persistent grid).
 template <class T, class I, bool GATHER, int K>
-hipError_t launch_step_k(const StepArgs &a, hipStream_t st)
+hipError_t launch_main(const StepArgs &a, hipStream_t st)
 {
   const size_t bytes = sizeof(Tile<T>);
   const bool occ2 = a.occ2 && sizeof(T) == 4;
   hipError_t e = hipFuncSetAttribute(step_kernel<T, I, GATHER, K>(occ2),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
-  const bool guard = sizeof(T) == 4 && a.defer != nullptr;
-  if (guard) hipLaunchKernelGGL(k_zero_defer, dim3(1), dim3(64), 0, st, a.defer);
-  if (K == KV_ANALYTIC && a.net_list) hipLaunchKernelGGL(k_zero_defer, dim3(1), dim3(64), 0, st, a.net_list);
-  if (GATHER) hipLaunchKernelGGL(k_zero_bits, dim3(1), dim3(64), 0, st, a.smax_out);
   int64_t blocks;
   if (a.queue) {
     hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(64), 0, st, a.queue);
@@ -918,13 +1048,48 @@ hipError_t launch_step_k(const StepArgs &a, hipStream_t st)
   if constexpr (sizeof(T) == 4) {
     if (occ2) hipLaunchKernelGGL((k_step_occ2<T, I, GATHER, K>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
     else hipLaunchKernelGGL((k_step<T, I, GATHER, K>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
-    e = hipGetLastError();
-    if (e != hipSuccess || !guard) return e;
-    return launch_step_listed<GATHER, K>(a, st);
   } else {
     hipLaunchKernelGGL((k_step<T, I, GATHER, K>), dim3((unsigned)blocks), dim3(threads_of<T>()), bytes, st, a);
-    return hipGetLastError();
   }
+  return hipGetLastError();
+}
+
+template <class T, class I, bool GATHER, int K>
+hipError_t launch_step_k(const StepArgs &a, hipStream_t st)
+{
+  hipError_t e = launch_prologue<T, GATHER>(a, st);
+  if (e == hipSuccess) e = launch_main<T, I, GATHER, K>(a, st);
+  if (e != hipSuccess || !(sizeof(T) == 4 && a.defer)) return e;
+  return launch_step_listed<GATHER, K>(a, st);
+}
+
+// The learned-guess split with the input's network masks (gather layout): the list is formed
+// before the step, and the learned kernel steps the listed patches on the side stream while the
+// kernel without the network steps the others on `st`; the guard's FP64 pass, over the patches
+// either of them deferred, follows the join.
+template <class T, class I>
+hipError_t launch_split_concurrent(const StepArgs &a, hipStream_t st)
+{
+  hipError_t e = launch_prologue<T, true>(a, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_net_list, dim3((unsigned)((a.n_patch + 255) / 256)), dim3(256), 0, st,
+                     a.n_patch, a.neighbor, a.net_in, a.net_list);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  SideStream side;
+  if ((e = side_stream(side)) != hipSuccess) return e;
+  std::lock_guard<std::mutex> hold(*side.lock);
+  if ((e = hipEventRecord(side.fork, st)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(side.stream, side.fork, 0)) != hipSuccess) return e;
+  // the learned kernel applies the precision guard to its own patches (a.defer kept)
+  hipError_t el = launch_listed<T, I, true, KV_MLP, T>(a, a.net_list, 9, side.stream, true);
+  hipError_t ej = hipEventRecord(side.join, side.stream);
+  hipError_t em = el == hipSuccess ? launch_main<T, I, true, KV_ANALYTIC>(a, st) : hipSuccess;
+  if (ej == hipSuccess) ej = hipStreamWaitEvent(st, side.join, 0);
+  if (el != hipSuccess) return el;
+  if (ej != hipSuccess) return ej;
+  if (em != hipSuccess) return em;
+  if (sizeof(T) == 4 && a.defer) return launch_step_listed<true, KV_ANALYTIC>(a, st);
+  return hipSuccess;
 }
 
 // The original scheme exists where it can run: padded layout, bulk type = inversion type; the
@@ -949,6 +1114,9 @@ hipError_t launch_step_t(const StepArgs &a, hipStream_t st)
     return launch_step_k<T, I, GATHER, KV_ANALYTIC>(b, st);
   }
   if (!a.net_list) return launch_step_k<T, I, GATHER, KV_MLP>(a, st);
+  if constexpr (GATHER) {
+    if (a.net_in) return launch_split_concurrent<T, I>(a, st);
+  }
   // learned-guess split: the kernel without the network steps every patch and lists those whose
   // tile consults the network; then the learned kernel steps the listed ones
   hipError_t e = launch_step_k<T, I, GATHER, KV_ANALYTIC>(a, st);
@@ -981,13 +1149,15 @@ int occupancy_ti(bool gather, int kind, bool occ2)
 
 template <class T, class I>
 void launch_grid_prims_ti(int64_t n_patch, const double *cons, void *prims,
-                          unsigned long long *smax_bits, const MlpDev &m, bool mlp, int blocks,
-                          hipStream_t st)
+                          unsigned long long *smax_bits, unsigned int *net_mask,
+                          double net_gate, const MlpDev &m, bool mlp, int blocks, hipStream_t st)
 {
   if (mlp)
-    hipLaunchKernelGGL((k_grid_prims<T, I, true>), dim3(blocks), dim3(256), 0, st, n_patch, cons, (T *)prims, smax_bits, m);
+    hipLaunchKernelGGL((k_grid_prims<T, I, true>), dim3(blocks), dim3(256), 0, st, n_patch, cons,
+                       (T *)prims, smax_bits, net_mask, net_gate, m);
   else
-    hipLaunchKernelGGL((k_grid_prims<T, I, false>), dim3(blocks), dim3(256), 0, st, n_patch, cons, (T *)prims, smax_bits, m);
+    hipLaunchKernelGGL((k_grid_prims<T, I, false>), dim3(blocks), dim3(256), 0, st, n_patch, cons,
+                       (T *)prims, smax_bits, net_mask, net_gate, m);
 }
 
 // Entry points of one precision mode (bulk type T, inversion type I); each mode is compiled in
@@ -996,27 +1166,32 @@ template <class T, class I>
 hipError_t step_launch_ti(const StepArgs &a, bool gather, hipStream_t st)
 {
   if (gather) {
-    if (a.n_patch == 0) {
-      hipLaunchKernelGGL(k_zero_bits, dim3(1), dim3(64), 0, st, a.smax_out);
-      return hipGetLastError();
-    }
+    if (a.n_patch == 0) return launch_prologue<T, true>(a, st);
     return launch_step_t<T, I, true>(a, st);
   }
   if (a.n_patch == 0) return hipSuccess;
   return launch_step_t<T, I, false>(a, st);
 }
 
+// net_mask (may be NULL): the state's network masks, from the cells with L > gate of a learned
+// guess (all zero with the analytic guess).
 template <class T, class I>
 hipError_t grid_prims_ti(int64_t n_patch, const double *cons, void *prims,
-                         unsigned long long *smax_bits, const GuessArgs &g, hipStream_t st)
+                         unsigned long long *smax_bits, unsigned int *net_mask,
+                         const GuessArgs &g, hipStream_t st)
 {
-  hipLaunchKernelGGL(k_zero_bits, dim3(1), dim3(64), 0, st, smax_bits);
+  const int64_t nw = net_mask ? n_patch : 0;
+  const int64_t n = nw > 2 ? nw : 2;
+  hipLaunchKernelGGL(k_step_prologue, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                     (unsigned long long *)nullptr, (unsigned long long *)nullptr, smax_bits,
+                     net_mask, nw);
   if (n_patch > 0) {
     const int64_t total = n_patch * 512;
     int blocks = (int)((total + 511) / 512);
     if (blocks > 256 * 64) blocks = 256 * 64;
-    launch_grid_prims_ti<T, I>(n_patch, cons, prims, smax_bits, g.dev(), g.kind == SRHD_GUESS_MLP,
-                               blocks, st);
+    const bool mlp = g.kind == SRHD_GUESS_MLP;
+    launch_grid_prims_ti<T, I>(n_patch, cons, prims, smax_bits, net_mask,
+                               mlp ? g.gate : __builtin_huge_val(), g.dev(), mlp, blocks, st);
   }
   return hipGetLastError();
 }

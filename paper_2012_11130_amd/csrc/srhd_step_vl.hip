@@ -436,11 +436,15 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
 
   // ---------------------------------------------------------------- counters
   if (a.stats) {
-    atomicAdd(&s.cnt[0], unphys + bad_in);
-    atomicAdd(&s.cnt[2], my_nc);
-    atomicAdd(&s.cnt[3], my_iters);
-    atomicAdd(&s.cnt[4], my_inv);
-    atomicAdd(&s.cnt[7], my_pfb);
+    const unsigned int c0 = wave_sum(unphys + bad_in), c2 = wave_sum(my_nc),
+                       c3 = wave_sum(my_iters), c4 = wave_sum(my_inv), c7 = wave_sum(my_pfb);
+    if ((tid & 63) == 0) {
+      atomicAdd(&s.cnt[0], c0);
+      atomicAdd(&s.cnt[2], c2);
+      atomicAdd(&s.cnt[3], c3);
+      atomicAdd(&s.cnt[4], c4);
+      atomicAdd(&s.cnt[7], c7);
+    }
     __syncthreads();
     if (tid == 0) {
       unsigned long long *st = (unsigned long long *)a.stats;

@@ -50,7 +50,8 @@ class srhd_patches(ctypes.Structure):
 
 class srhd_grid(ctypes.Structure):
     _fields_ = [("n_patch", _i64), ("cons", _vp), ("prims", _vp), ("neighbor", _vp),
-                ("level", _vp), ("n_level", _int), ("dh", ctypes.c_double * MAX_LEVEL)]
+                ("level", _vp), ("n_level", _int), ("dh", ctypes.c_double * MAX_LEVEL),
+                ("net_mask", _vp)]
 
 
 class srhd_eos(ctypes.Structure):
@@ -112,13 +113,13 @@ _sig = {
                         ctypes.POINTER(srhd_step_params), _vp, _vp],
     "srhd_fluid_step_static": [ctypes.POINTER(srhd_patches), _vp, _vp,
                                ctypes.POINTER(srhd_step_params), _vp, _vp],
-    "srhd_grid_prims": [_int, _i64, _vp, _vp, _vp, ctypes.POINTER(srhd_guess), _vp],
+    "srhd_grid_prims": [_int, _i64, _vp, _vp, _vp, _vp, ctypes.POINTER(srhd_guess), _vp],
     "srhd_mlp_features": [_int, _int, _i64, _vp, _vp, _vp, _vp, _vp],
     "srhd_mlp_forward": [ctypes.POINTER(srhd_mlp), _i64, _vp, _vp, _vp],
     "srhd_mlp_grad": [ctypes.POINTER(srhd_mlp), _i64, _vp, _vp, _vp, _vp, _vp, _vp],
     "srhd_mlp_adam": [_vp, _vp, _vp, _vp, _int, ctypes.c_float, _vp, _vp, _vp],
     "srhd_fluid_step_grid": [ctypes.POINTER(srhd_grid), _vp, ctypes.c_double, _vp, _vp, _vp,
-                             _vp, _vp, ctypes.POINTER(srhd_step_params), _vp, _vp],
+                             _vp, _vp, _vp, ctypes.POINTER(srhd_step_params), _vp, _vp],
     "srhd_step_occupancy": [ctypes.POINTER(srhd_step_params), _int],
     "srhd_autotune_step": [ctypes.POINTER(srhd_patches), _vp, _vp,
                            ctypes.POINTER(srhd_step_params), _int,
@@ -129,7 +130,7 @@ _sig = {
     "srhd_flux_accumulate": [_i64, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp],
     "srhd_flux_correct": [_i64, _vp, _i64, _vp, _vp, _i64, _vp, ctypes.c_double, _vp, _vp],
     "srhd_autotune_step_grid": [ctypes.POINTER(srhd_grid), _vp, ctypes.c_double, _vp, _vp, _vp,
-                                _vp, ctypes.POINTER(srhd_step_params), _int,
+                                _vp, _vp, ctypes.POINTER(srhd_step_params), _int,
                                 ctypes.POINTER(srhd_tune_entry), _int, ctypes.POINTER(_int), _vp],
 }
 for _name, _args in _sig.items():
@@ -382,13 +383,14 @@ def srhd_autotune_step(padded, dt_lev, dh, level=None, out=None, theta=1.5, riem
     return sch, _table(table, n)
 
 
-def _grid(cons, prims, neighbor, dh, level):
+def _grid(cons, prims, neighbor, dh, level, net_mask=None):
     gr = srhd_grid()
     gr.n_patch = cons.shape[0]
     gr.cons = cons.data_ptr()
     gr.prims = prims.data_ptr()
     gr.neighbor = neighbor.data_ptr()
     gr.level = None if level is None else level.data_ptr()
+    gr.net_mask = None if net_mask is None else net_mask.data_ptr()
     dh = [float(x) for x in dh]
     gr.n_level = len(dh)
     for i, h in enumerate(dh):
@@ -399,23 +401,24 @@ def _grid(cons, prims, neighbor, dh, level):
 def srhd_autotune_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, dt_lev=None,
                             level=None, theta=1.5, riemann=HLLC, prec=PREC_FP64, max_retry=4,
                             guess=None, reps=2, kappa_max=KAPPA_MAX_DEFAULT, defer=None,
-                            learned_split=True):
+                            learned_split=True, net_in=None):
     """Times the candidate schedules of srhd_fluid_step_grid on this block; returns (Sched of
     the fastest, [(groups, chunk, occupancy, ms per step), ...])."""
-    _need_cuda(cons, prims, neighbor, smax_in, dt_lev, level)
+    _need_cuda(cons, prims, neighbor, smax_in, dt_lev, level, net_in)
     cons_out = torch.empty_like(cons)
     prims_out = torch.empty_like(prims)
     smax_out = torch.empty(1, dtype=torch.int64, device=cons.device)
+    net_out = None if net_in is None else torch.empty_like(net_in)
     sch = Sched(0, 1, cons.device)
-    gr = _grid(cons, prims, neighbor, dh, level)
+    gr = _grid(cons, prims, neighbor, dh, level, net_in)
     prm = _params(theta, riemann, prec, max_retry, guess, sch)
     ws = _guard(prm, kappa_max, defer, cons.shape[0], cons.device, learned_split)  # noqa: F841
     table = (srhd_tune_entry * 32)()
     n = _int(0)
     _check(_lib.srhd_autotune_step_grid(ctypes.byref(gr), _ptr(smax_in), float(c_cfl), _ptr(dt_lev),
                                         _ptr(cons_out), _ptr(prims_out), _ptr(smax_out),
-                                        ctypes.byref(prm), int(reps), table, 32, ctypes.byref(n),
-                                        _stream()))
+                                        _ptr(net_out), ctypes.byref(prm), int(reps), table, 32,
+                                        ctypes.byref(n), _stream()))
     sch.groups, sch.chunk, sch.occupancy = prm.sched.groups, prm.sched.chunk, prm.sched.occupancy
     return sch, _table(table, n)
 
@@ -479,9 +482,22 @@ def prims_dtype(prec):
     return torch.float64 if prec == PREC_FP64 else torch.float32
 
 
-def srhd_grid_prims(cons, prec=PREC_FP64, prims=None, smax_bits=None, guess=None):
-    """Interior cons [P][5][8][8][8] -> (prims in the step's bulk type, S_max bits int64 [1])."""
-    _need_cuda(cons)
+def new_net_mask(n_patch, device):
+    """Network masks of a gather-layout state (int32 [n_patch]): bit (rz + 1) 9 + (ry + 1) 3 +
+    (rx + 1) of patch p marks a cell with L above the learned guess's gate in region (rx, ry,
+    rz) of the patch (per axis 0: every cell, -1 / +1: the two lowest / highest layers)."""
+    return torch.zeros(max(int(n_patch), 1), dtype=torch.int32, device=device)
+
+
+def _need_mask(m, P):
+    if m is not None and (m.dtype != torch.int32 or m.numel() < P):
+        raise ValueError("a network mask array is int32 with at least %d entries" % P)
+
+
+def srhd_grid_prims(cons, prec=PREC_FP64, prims=None, smax_bits=None, guess=None, net_mask=None):
+    """Interior cons [P][5][8][8][8] -> (prims in the step's bulk type, S_max bits int64 [1]);
+    net_mask (int32 [P]) receives the state's network masks."""
+    _need_cuda(cons, net_mask)
     P = cons.shape[0]
     if prims is None:
         prims = torch.empty(cons.shape, dtype=prims_dtype(prec), device=cons.device)
@@ -489,8 +505,9 @@ def srhd_grid_prims(cons, prec=PREC_FP64, prims=None, smax_bits=None, guess=None
         smax_bits = torch.empty(1, dtype=torch.int64, device=cons.device)
     _need_cuda(prims, smax_bits)
     g = guess if guess is not None else srhd_guess(GUESS_ANALYTIC, None, 0)
+    _need_mask(net_mask, P)
     _check(_lib.srhd_grid_prims(int(prec), P, _ptr(cons), _ptr(prims), _ptr(smax_bits),
-                                ctypes.byref(g), _stream()))
+                                _ptr(net_mask), ctypes.byref(g), _stream()))
     return prims, smax_bits
 
 
@@ -503,10 +520,12 @@ def srhd_fluid_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, dt_
                          level=None, cons_out=None, prims_out=None, smax_out=None, dt_used=None,
                          theta=1.5, riemann=HLLC, prec=PREC_FP64, max_retry=4, stats=None,
                          guess=None, sched=None, gamma=None, kappa_max=KAPPA_MAX_DEFAULT,
-                         defer=None, learned_split=True):
+                         defer=None, learned_split=True, net_in=None, net_out=None):
     """One step of a block of same-level patches (ghosts gathered from neighbour interiors).
-    Returns (cons_out, prims_out, smax_out)."""
-    _need_cuda(cons, prims, neighbor, smax_in, dt_lev, level, stats)
+    net_in: the input state's network masks (with a learned guess and learned_split they fix the
+    split's list before the step, which then runs both kernels concurrently); net_out receives
+    the output's.  Returns (cons_out, prims_out, smax_out)."""
+    _need_cuda(cons, prims, neighbor, smax_in, dt_lev, level, stats, net_in, net_out)
     P = cons.shape[0]
     if cons_out is None:
         cons_out = torch.empty_like(cons)
@@ -517,12 +536,15 @@ def srhd_fluid_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, dt_
     _need_cuda(cons_out, prims_out, smax_out, dt_used)
     if prims.dtype != prims_dtype(prec) or prims_out.dtype != prims_dtype(prec):
         raise TypeError("primitives must be %s for this precision" % prims_dtype(prec))
-    gr = _grid(cons, prims, neighbor, dh, level)
+    _need_mask(net_in, P)
+    _need_mask(net_out, P)
+    gr = _grid(cons, prims, neighbor, dh, level, net_in)
     prm = _params(theta, riemann, prec, max_retry, guess, sched, gamma=gamma)
     ws = _guard(prm, kappa_max, defer, P, cons.device, learned_split)  # noqa: F841
     _check(_lib.srhd_fluid_step_grid(ctypes.byref(gr), _ptr(smax_in), float(c_cfl), _ptr(dt_lev),
                                      _ptr(cons_out), _ptr(prims_out), _ptr(smax_out),
-                                     _ptr(dt_used), ctypes.byref(prm), _ptr(stats), _stream()))
+                                     _ptr(net_out), _ptr(dt_used), ctypes.byref(prm), _ptr(stats),
+                                     _stream()))
     return cons_out, prims_out, smax_out
 
 

@@ -49,7 +49,7 @@ def test_argument_errors_are_reported_without_a_gpu(lib):
     assert b"overlap" in lib.srhd_last_error()
     assert lib.srhd_prim2cons(0, 1, a + 1, a + 400, None, None) == -1      # misaligned
     lib.srhd_abi_version.restype = ctypes.c_int
-    assert lib.srhd_abi_version() == 7
+    assert lib.srhd_abi_version() == 8
 
 
 def test_step_descriptor_checks(lib):
@@ -202,3 +202,35 @@ def test_schedule_checks(lib):
     assert S._lib.srhd_prim2cons(0, 10, None, None, ctypes.byref(bad), None) == -1
     assert S._lib.srhd_cfl_dt(0, 0, None, 1, (ctypes.c_double * 1)(0.1), 0.5, None, None,
                               ctypes.byref(bad), None) == -1
+
+
+def test_network_mask_checks(lib):
+    # host buffers stand in for device arrays: every call fails its checks before any launch
+    from paper_2012_11130_amd import srhd as S
+    P = 4
+    buf = lambda n: ctypes.create_string_buffer(n + 64)
+    al = lambda b: (ctypes.addressof(b) + 63) // 64 * 64
+    cons, prims, cout, pout = buf(P * 2560 * 8), buf(P * 2560 * 4), buf(P * 2560 * 8), buf(P * 2560 * 4)
+    nb, sm, masks = buf(P * 27 * 4), buf(16), buf(64)
+    g = S.srhd_guess(0, None, 0)
+    # srhd_grid_prims: misaligned or overlapping network masks
+    assert S._lib.srhd_grid_prims(1, P, al(cons), al(prims), al(sm), al(masks) + 2, ctypes.byref(g),
+                                  None) == -1
+    assert b"misaligned" in S._lib.srhd_last_error()
+    assert S._lib.srhd_grid_prims(1, P, al(cons), al(prims), al(sm), al(prims), ctypes.byref(g),
+                                  None) == -1
+    assert b"net_mask" in S._lib.srhd_last_error()
+    gr = S.srhd_grid()
+    gr.n_patch, gr.cons, gr.prims, gr.neighbor, gr.n_level = P, al(cons), al(prims), al(nb), 1
+    gr.dh[0] = 0.1
+    prm = S.srhd_step_params()
+    prm.theta, prm.max_retry, prm.prec = 1.5, 4, 1
+    call = lambda net_out: S._lib.srhd_fluid_step_grid(ctypes.byref(gr), al(sm), 0.5, None, al(cout),
+                                                       al(pout), al(sm) + 8, net_out, None,
+                                                       ctypes.byref(prm), None, None)
+    assert call(al(masks) + 2) == -1 and b"misaligned" in S._lib.srhd_last_error()
+    assert call(al(cout)) == -1 and b"net_out" in S._lib.srhd_last_error()
+    gr.net_mask = al(masks)
+    assert call(al(masks) + 8) == -1 and b"net_out" in S._lib.srhd_last_error()
+    gr.net_mask = al(masks) + 2
+    assert call(None) == -1 and b"misaligned" in S._lib.srhd_last_error()

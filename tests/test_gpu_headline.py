@@ -1,8 +1,9 @@
 """Full-size parity of the benchmark's headline configuration: the 256^3 blast (32,768 patches in
 Morton order) stepped by the gather-layout chain -- the next step's time step fused in, FP32
 primitives handed from step to step -- in mixed precision with the trained learned guess
-(paper_2012_11130_amd/mlp_guess.npz) and the precision guard, for four steps; and the same chain
-in FP64.
+(paper_2012_11130_amd/mlp_guess.npz), its network masks handed from step to step (the learned
+kernel on the library's second stream), and the precision guard, for four steps; and the same
+chain in FP64.
 
 Each step is compared with the oracle's step of the GPU's own input state (the step is
 patch-local given its ghosts, Sec. 3.1): the oracle fills the ghosts of the GPU's current
@@ -59,14 +60,18 @@ def test_headline_chain_full_size(S, blast, prec):
         guess = mlp.guess()
     c = torch.from_numpy(cons0).to(DEV)
     nb = torch.from_numpy(g.neighbor).to(DEV)
-    prims, smax = S.srhd_grid_prims(c, prec=prec, guess=guess)
+    mask = S.new_net_mask(g.n_patch, DEV) if guess is not None else None
+    prims, smax = S.srhd_grid_prims(c, prec=prec, guess=guess, net_mask=mask)
     rng = np.random.default_rng(7)
     dt_used = torch.empty(1, dtype=torch.float64, device=DEV)
     for step in range(N_STEPS):
         cin = c.cpu().numpy()
         st = S.new_stats(DEV)
+        mask_out = S.new_net_mask(g.n_patch, DEV) if guess is not None else None
         c, prims, smax = S.srhd_fluid_step_grid(c, prims, nb, g.dh_lev, smax_in=smax, c_cfl=0.5,
-                                                prec=prec, guess=guess, stats=st, dt_used=dt_used)
+                                                prec=prec, guess=guess, stats=st, dt_used=dt_used,
+                                                net_in=mask, net_out=mask_out)
+        mask = mask_out
         out = c.cpu().numpy()
         dt = dt_used.cpu().numpy()
         sd = S.stats_dict(st)
