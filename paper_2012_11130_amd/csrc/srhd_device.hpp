@@ -57,7 +57,9 @@ __device__ __forceinline__ double sq(double a) { return __builtin_sqrt(a); }
 __device__ __forceinline__ float sq(float a) { return __builtin_amdgcn_sqrtf(a); }
 // Division in the step's bulk: with FX (the FP64 step kernels) a times the refined reciprocal
 // (about 1 ulp) in FP64; otherwise dv.  (The refined square root is not used there: inlined
-// into the Riemann solver it pushes the 768-thread FP64 step into scratch spills.)
+// into the Riemann solver it pushes the 768-thread FP64 step into scratch spills.)  In
+// limited_slope with FX a zero dl + dr yields NaN for the harmonic mean, which the sign test then
+// discards, as it discards the infinity of the IEEE division.
 template <bool FX, class T> __device__ __forceinline__ T dvx(T a, T b)
 {
   if constexpr (FX && sizeof(T) == 8) return a * rcp_nr(b);
@@ -187,11 +189,11 @@ __device__ __forceinline__ double lhs_L_adaptive(double D, double Mx, double My,
 
 // ------------------------------------------------------------------------------ EoS
 // Eq. 22: reduced enthalpy from Theta, free of the subtraction h - 1.
-template <class T>
+template <bool FX = false, class T>
 __device__ __forceinline__ T htilde_of_theta(T th)
 {
   T a = T(2.25) * th * th;
-  return T(2.5) * th + dv(a, T(1) + sq(a + T(1)));
+  return T(2.5) * th + dvx<FX>(a, T(1) + sq(a + T(1)));
 }
 
 // Eq. 16: Theta from the reduced enthalpy, with 9 ht^2 + 18 ht + 25 = 9 h^2 + 16.
@@ -217,8 +219,8 @@ struct EosPoly {
   double k;      // (Gamma - 1) / Gamma
 };
 
-template <class T> __device__ __forceinline__ T htilde_of_theta(T th, EosTm) { return htilde_of_theta(th); }
-template <class T> __device__ __forceinline__ T htilde_of_theta(T th, const EosPoly &e) { return dv(th, T(e.k)); }
+template <bool FX = false, class T> __device__ __forceinline__ T htilde_of_theta(T th, EosTm) { return htilde_of_theta<FX>(th); }
+template <bool FX = false, class T> __device__ __forceinline__ T htilde_of_theta(T th, const EosPoly &e) { return dvx<FX>(th, T(e.k)); }
 template <class T> __device__ __forceinline__ T theta_of_htilde(T ht, EosTm) { return theta_of_htilde(ht); }
 template <class T> __device__ __forceinline__ T theta_of_htilde(T ht, const EosPoly &e) { return T(e.k) * ht; }
 template <bool FX = false, class T> __device__ __forceinline__ T sound_speed2(T th, EosTm) { return sound_speed2<FX>(th); }
@@ -512,26 +514,26 @@ template <class T>
 struct Cons { T D, m[3], E; };   // E is the reduced energy Et
 
 // Eqs. 8, 5a, 22, 5b, 15 (with Theta = p / rho known), 23.
-template <class T, class E = EosTm>
+template <bool FX = false, class T, class E = EosTm>
 __device__ __forceinline__ Cons<T> prim2cons(const Prim<T> &w, const E &eos = E())
 {
   T U2 = w.u[0] * w.u[0] + w.u[1] * w.u[1] + w.u[2] * w.u[2];
   T gam = sq(T(1) + U2);
   T D = w.rho * gam;
-  T th = dv(w.p, w.rho);
-  T ht = htilde_of_theta(th, eos);
+  T th = dvx<FX>(w.p, w.rho);
+  T ht = htilde_of_theta<FX>(th, eos);
   T h = T(1) + ht;
   T Dh = D * h;
   T h2 = h * h;
   T m2 = h2 * U2;
-  T f = ht * (ht + T(2)) - T(2) * th * h + dv(th * th * h2, h2 + m2);
+  T f = ht * (ht + T(2)) - T(2) * th * h + dvx<FX>(th * th * h2, h2 + m2);
   T a = m2 + f;
   Cons<T> u;
   u.D = D;
   u.m[0] = Dh * w.u[0];
   u.m[1] = Dh * w.u[1];
   u.m[2] = Dh * w.u[2];
-  u.E = dv(D * a, T(1) + sq(T(1) + a));
+  u.E = dvx<FX>(D * a, T(1) + sq(T(1) + a));
   return u;
 }
 
@@ -567,11 +569,11 @@ __device__ __forceinline__ Cons<T> prim2cons_total(const Prim<T> &w)
   return u;
 }
 
-template <bool TOT, class T, class E = EosTm>
+template <bool TOT, bool FX = false, class T, class E = EosTm>
 __device__ __forceinline__ Cons<T> prim2cons_s(const Prim<T> &w, const E &eos = E())
 {
   if constexpr (TOT) return prim2cons_total(w);
-  else return prim2cons(w, eos);
+  else return prim2cons<FX>(w, eos);
 }
 
 // The original scheme's physical check and left-hand side of Eq. 15: L = (E/D)^2 - (|M|/D)^2 - 1
@@ -809,7 +811,7 @@ __device__ __forceinline__ bool kappa_above(T rho, T ux, T uy, T uz, T p, T kmax
 // larger of |dl|, |dr| (equal to min(2 |dl dr| / |dl + dr|, theta |dl|, theta |dr|) for
 // differences of one sign): the ratio is bounded by 2, so nothing overflows, and it takes about
 // half the instructions.
-template <class T>
+template <bool FX = false, class T>
 __device__ __forceinline__ T limited_slope(T wl, T wc, T wr, T theta)
 {
   T dl = wc - wl, dr = wr - wc;
@@ -823,7 +825,7 @@ __device__ __forceinline__ T limited_slope(T wl, T wc, T wr, T theta)
   } else {
     constexpr T tiny = T(DBL_MIN);
     bool mono = (dl >= tiny && dr >= tiny) || (dl <= -tiny && dr <= -tiny);
-    T vl = absT(dv(T(2) * dl * dr, dl + dr));
+    T vl = absT(dvx<FX>(T(2) * dl * dr, dl + dr));
     T s = minT(vl, minT(theta * absT(dl), theta * absT(dr)));
     s = dl > T(0) ? s : -s;
     return mono ? s : T(0);

@@ -115,11 +115,13 @@ using GuessT = typename std::conditional<sizeof(T) == 4, float, I>::type;
 template <class T, bool GATHER> constexpr bool fast_of() { return sizeof(T) == 8 || GATHER; }
 // Downstream of the face inversions (the face states' gamma, 1 / gamma and c_s^2, the Riemann
 // solver) the FP64 bulk divides through the refined reciprocal (about 1 ulp).  Upstream of them
-// (slopes, prim -> cons, the half-step corrections) it keeps IEEE division: an inversion turns a
-// changed rounding of its input into a change of the face state of up to kappa times it (Eq. 20),
-// about 1e-9 where kappa ~ 1e6, which would exceed the step's 1e-10 parity against the oracle.
-// The FP32 bulk keeps its own arithmetic.
+// (slopes, prim -> cons, the half-step corrections) it does so only in patches whose tile holds
+// no cell with kappa = 1 + M^2 above KAPPA_FAST: an inversion turns a changed rounding of its
+// input into a change of the face state of up to kappa times it (Eq. 20), under 1e-12 there but
+// about 1e-9 where kappa ~ 1e6, beyond the step's 1e-10 parity against the oracle; those patches
+// keep IEEE division.  The FP32 bulk keeps its own arithmetic.
 template <class T> constexpr bool fx_of() { return sizeof(T) == 8; }
+constexpr double KAPPA_FAST = 1000.0;
 
 // Newton tolerance by (bulk type T, inversion type I): FP64 to ~2^-54; an FP64 inversion whose
 // result is consumed in FP32 to ~2^-28; an FP32 inversion to FP32 accuracy.
@@ -216,7 +218,7 @@ __device__ __forceinline__ bool invert_face(const Cons<T> &u, bool ok, double L,
 
 // Face state of cell (i, j, k) on side `side` (0: minus, 1: plus) of direction d: PLM along d,
 // prim -> cons, plus the cell's half-step correction, then the inversion.
-template <int d, int K, class I, bool FAST, class T>
+template <int d, int K, class I, bool FAST, bool FXU, class T>
 __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, int j, int k,
                                            T theta, const MlpDev &mlp, Prim<T> &w, Cons<T> &u,
                                            FaceAux<T> &x, int &iters, int &status, unsigned int &evals,
@@ -231,7 +233,7 @@ __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, in
 #pragma unroll
   for (int f = 0; f < 5; ++f) {
     T wc = s.W[f][b];
-    v[f] = wc + half * limited_slope(s.W[f][b - sd], wc, s.W[f][b + sd], theta);
+    v[f] = wc + half * limited_slope<FXU>(s.W[f][b - sd], wc, s.W[f][b + sd], theta);
   }
   wf.rho = v[0];
   wf.u[0] = v[1];
@@ -239,7 +241,7 @@ __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, in
   wf.u[2] = v[3];
   wf.p = v[4];
   constexpr bool MLP = K == KV_MLP;
-  u = prim2cons_s<K == KV_TOTAL>(wf, eos);
+  u = prim2cons_s<K == KV_TOTAL, FXU>(wf, eos);
   u.D += s.C[0][hb];
   u.m[0] += s.C[1][hb];
   u.m[1] += s.C[2][hb];
@@ -259,12 +261,12 @@ __device__ __forceinline__ bool face_state(const Tile<T> &s, int side, int i, in
 // Physical flux along d of a face state given by its primitives, with 1 / gamma = rho / D from
 // the conserved variables just formed (one reciprocal instead of a square root and a reciprocal).
 // The original scheme (TOT) keeps its own arithmetic: it is the comparison baseline.
-template <int d, bool TOT, class T, class E>
+template <int d, bool TOT, bool FXU, class T, class E>
 __device__ __forceinline__ Cons<T> state_flux(const Prim<T> &w, const E &eos)
 {
-  const Cons<T> u = prim2cons_s<TOT>(w, eos);
+  const Cons<T> u = prim2cons_s<TOT, FXU>(w, eos);
   if constexpr (TOT) return phys_flux<d, TOT>(w, u);
-  else return phys_flux<d, TOT>(w, u, w.rho * dv(T(1), u.D));
+  else return phys_flux<d, TOT>(w, u, w.rho * dvx<FXU>(T(1), u.D));
 }
 
 struct IfaceCount {
@@ -273,7 +275,7 @@ struct IfaceCount {
 
 // Flux through interface r of direction d (between cells c-1 and c along d, interfaces numbered
 // with x fastest, then y, then z), written to the ring slot of d.
-template <int d, int K, class I, bool FAST, class T>
+template <int d, int K, class I, bool FAST, bool FXU, class T>
 __device__ __forceinline__ bool interface_flux(Tile<T> &s, int r, T theta, int solver,
                                                const MlpDev &mlp, IfaceCount &cnt,
                                                const typename KEos<K>::type &eos)
@@ -290,8 +292,8 @@ __device__ __forceinline__ bool interface_flux(Tile<T> &s, int r, T theta, int s
   Cons<T> ul, ur;
   FaceAux<T> xl, xr;
   int itl, itr, stl, str;
-  bool okl = face_state<d, K, I, FAST>(s, 1, cl[0], cl[1], cl[2], theta, mlp, wl, ul, xl, itl, stl, cnt.mlp, eos);
-  bool okr = face_state<d, K, I, FAST>(s, 0, cr[0], cr[1], cr[2], theta, mlp, wr, ur, xr, itr, str, cnt.mlp, eos);
+  bool okl = face_state<d, K, I, FAST, FXU>(s, 1, cl[0], cl[1], cl[2], theta, mlp, wl, ul, xl, itl, stl, cnt.mlp, eos);
+  bool okr = face_state<d, K, I, FAST, FXU>(s, 0, cr[0], cr[1], cr[2], theta, mlp, wr, ur, xr, itr, str, cnt.mlp, eos);
   cnt.iters += itl + itr;
   cnt.inv += 2;
   cnt.fb += (stl == ST_FALLBACK) + (str == ST_FALLBACK);
@@ -425,7 +427,8 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
   }
 
   // ---------------------------------------------------------------- A: centre primitives
-  bool centre_bad = false, hot = false, net = false;
+  bool centre_bad = false, hot = false, net = false, steep = false;
+  const T kf1 = T(KAPPA_FAST - 1.0);
   unsigned int centre_unphys = 0;
   const T km1 = T(a.kappa_max - 1.0);
   // the learned-guess split's first launch (the kernel without the network) lists the patches
@@ -466,8 +469,11 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
       T v0 = okc ? (T)w[0] : nan, v1 = okc ? (T)w[512] : nan, v2 = okc ? (T)w[1024] : nan,
         v3 = okc ? (T)w[1536] : nan, v4 = okc ? (T)w[2048] : nan;
       bool bad = !(v0 > T(0)) || !(v4 > T(0)) || !finiteT(v1) || !finiteT(v2) || !finiteT(v3);
-      if constexpr (sizeof(T) == 4)
+      if constexpr (sizeof(T) == 4) {
         if (a.defer) hot |= kappa_above<T>(v0, v1, v2, v3, v4, km1, eos);
+      } else {
+        steep |= bad || kappa_above<T>(v0, v1, v2, v3, v4, kf1, eos);
+      }
       if (split) net |= !bad && (double)lhs_L_of_prim<T>(v0, v1, v2, v3, v4) > a.guess.gate;
       centre_bad |= bad;
       centre_unphys += bad;
@@ -516,12 +522,19 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
       s.W[2][b] = (T)o.uy;
       s.W[3][b] = (T)o.uz;
       s.W[4][b] = (T)o.p;
-      if constexpr (sizeof(T) == 4)
+      if constexpr (sizeof(T) == 4) {
         if (a.defer) hot |= kappa_above<T>((T)o.rho, (T)o.ux, (T)o.uy, (T)o.uz, (T)o.p, km1, eos);
+      } else {
+        steep |= o.status == ST_UNPHYSICAL ||
+                 kappa_above<T>((T)o.rho, (T)o.ux, (T)o.uy, (T)o.uz, (T)o.p, kf1, eos);
+      }
       if (split) net |= adm && L > a.guess.gate;
     }
   }
   centre_bad = __syncthreads_or(centre_bad);
+  // FP64 bulk: the refined division upstream of the face inversions in patches whose tile holds
+  // no cell with kappa > KAPPA_FAST (nor an unphysical one)
+  const bool fast64 = sizeof(T) == 8 && !__syncthreads_or(steep);
 
   // precision guard: a patch holding a cell beyond kappa_max goes to the FP64 kernel (its
   // unphysical centre cells are counted there)
@@ -550,6 +563,10 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
 
   T theta = (T)a.theta;
   unsigned int retries = 0, unphys = 0;
+  // the attempts, with the FP64 bulk's refined division upstream of the face inversions (FXU)
+  // where the tile allows it
+  auto attempts = [&](auto fx_tag) {
+  constexpr bool FXU = decltype(fx_tag)::value;
   for (int attempt = 0; !deferred; ++attempt) {
     // -------------------------------------------------------------- B: half-step corrections
     const T half = T(0.5 * dt / dh);
@@ -564,11 +581,11 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
         const int sd = d == 0 ? 1 : (d == 1 ? BX : BX * BX);
         Prim<T> wm = load_prim(s, b - sd), wp = load_prim(s, b + sd);
         T sl[5];
-        sl[0] = limited_slope(wm.rho, wc.rho, wp.rho, theta);
-        sl[1] = limited_slope(wm.u[0], wc.u[0], wp.u[0], theta);
-        sl[2] = limited_slope(wm.u[1], wc.u[1], wp.u[1], theta);
-        sl[3] = limited_slope(wm.u[2], wc.u[2], wp.u[2], theta);
-        sl[4] = limited_slope(wm.p, wc.p, wp.p, theta);
+        sl[0] = limited_slope<FXU>(wm.rho, wc.rho, wp.rho, theta);
+        sl[1] = limited_slope<FXU>(wm.u[0], wc.u[0], wp.u[0], theta);
+        sl[2] = limited_slope<FXU>(wm.u[1], wc.u[1], wp.u[1], theta);
+        sl[3] = limited_slope<FXU>(wm.u[2], wc.u[2], wp.u[2], theta);
+        sl[4] = limited_slope<FXU>(wm.p, wc.p, wp.p, theta);
         Prim<T> fm, fp;
         fm.rho = wc.rho - T(0.5) * sl[0];  fp.rho = wc.rho + T(0.5) * sl[0];
         fm.u[0] = wc.u[0] - T(0.5) * sl[1]; fp.u[0] = wc.u[0] + T(0.5) * sl[1];
@@ -576,9 +593,9 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
         fm.u[2] = wc.u[2] - T(0.5) * sl[3]; fp.u[2] = wc.u[2] + T(0.5) * sl[3];
         fm.p = wc.p - T(0.5) * sl[4];      fp.p = wc.p + T(0.5) * sl[4];
         Cons<T> Fm, Fp;
-        if (d == 0) { Fm = state_flux<0, TOT>(fm, eos); Fp = state_flux<0, TOT>(fp, eos); }
-        else if (d == 1) { Fm = state_flux<1, TOT>(fm, eos); Fp = state_flux<1, TOT>(fp, eos); }
-        else { Fm = state_flux<2, TOT>(fm, eos); Fp = state_flux<2, TOT>(fp, eos); }
+        if (d == 0) { Fm = state_flux<0, TOT, FXU>(fm, eos); Fp = state_flux<0, TOT, FXU>(fp, eos); }
+        else if (d == 1) { Fm = state_flux<1, TOT, FXU>(fm, eos); Fp = state_flux<1, TOT, FXU>(fp, eos); }
+        else { Fm = state_flux<2, TOT, FXU>(fm, eos); Fp = state_flux<2, TOT, FXU>(fp, eos); }
         acc[0] += Fp.D - Fm.D;
         acc[1] += Fp.m[0] - Fm.m[0];
         acc[2] += Fp.m[1] - Fm.m[1];
@@ -604,9 +621,9 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
         int r = qi - d * NIF;
         IfaceCount ic = {0, 0, 0, 0, 0, 0};
         bool ok;
-        if (d == 0) ok = interface_flux<0, K, I, fast_of<T, GATHER>()>(s, r, theta, a.riemann, mlp, ic, eos);
-        else if (d == 1) ok = interface_flux<1, K, I, fast_of<T, GATHER>()>(s, r, theta, a.riemann, mlp, ic, eos);
-        else ok = interface_flux<2, K, I, fast_of<T, GATHER>()>(s, r, theta, a.riemann, mlp, ic, eos);
+        if (d == 0) ok = interface_flux<0, K, I, fast_of<T, GATHER>(), FXU>(s, r, theta, a.riemann, mlp, ic, eos);
+        else if (d == 1) ok = interface_flux<1, K, I, fast_of<T, GATHER>(), FXU>(s, r, theta, a.riemann, mlp, ic, eos);
+        else ok = interface_flux<2, K, I, fast_of<T, GATHER>(), FXU>(s, r, theta, a.riemann, mlp, ic, eos);
         fail |= !ok;
         my_iters += ic.iters;
         my_mlp += ic.mlp;
@@ -731,6 +748,13 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
     ++retries;
     unphys = 0;
     theta = attempt < a.max_retry ? theta * T(0.75) : T(0);
+  }
+  };
+  if constexpr (sizeof(T) == 8) {
+    if (fast64) attempts(std::true_type{});
+    else attempts(std::false_type{});
+  } else {
+    attempts(std::false_type{});
   }
 
   // ---------------------------------------------------------------- counters
