@@ -65,6 +65,11 @@ template <bool FX, class T> __device__ __forceinline__ T dvx(T a, T b)
   if constexpr (FX && sizeof(T) == 8) return a * rcp_nr(b);
   else return dv(a, b);
 }
+template <bool FX, class T> __device__ __forceinline__ T sqx(T x)
+{
+  if constexpr (FX && sizeof(T) == 8) return sqrt_nr(x);
+  else return sq(x);
+}
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 template <class T> __device__ __forceinline__ T absT(T a) { return a < T(0) ? -a : a; }
@@ -193,7 +198,7 @@ template <bool FX = false, class T>
 __device__ __forceinline__ T htilde_of_theta(T th)
 {
   T a = T(2.25) * th * th;
-  return T(2.5) * th + dvx<FX>(a, T(1) + sq(a + T(1)));
+  return T(2.5) * th + dvx<FX>(a, T(1) + sqx<FX>(a + T(1)));
 }
 
 // Eq. 16: Theta from the reduced enthalpy, with 9 ht^2 + 18 ht + 25 = 9 h^2 + 16.
@@ -518,7 +523,7 @@ template <bool FX = false, class T, class E = EosTm>
 __device__ __forceinline__ Cons<T> prim2cons(const Prim<T> &w, const E &eos = E())
 {
   T U2 = w.u[0] * w.u[0] + w.u[1] * w.u[1] + w.u[2] * w.u[2];
-  T gam = sq(T(1) + U2);
+  T gam = sqx<FX>(T(1) + U2);
   T D = w.rho * gam;
   T th = dvx<FX>(w.p, w.rho);
   T ht = htilde_of_theta<FX>(th, eos);
@@ -533,7 +538,7 @@ __device__ __forceinline__ Cons<T> prim2cons(const Prim<T> &w, const E &eos = E(
   u.m[0] = Dh * w.u[0];
   u.m[1] = Dh * w.u[1];
   u.m[2] = Dh * w.u[2];
-  u.E = dvx<FX>(D * a, T(1) + sq(T(1) + a));
+  u.E = dvx<FX>(D * a, T(1) + sqx<FX>(T(1) + a));
   return u;
 }
 
