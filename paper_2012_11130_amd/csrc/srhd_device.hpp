@@ -56,15 +56,15 @@ __device__ __forceinline__ float sqrt_nr(float x) { return __builtin_amdgcn_sqrt
 __device__ __forceinline__ double sq(double a) { return __builtin_sqrt(a); }
 __device__ __forceinline__ float sq(float a) { return __builtin_amdgcn_sqrtf(a); }
 // Division in the step's bulk: with FX (the FP64 step kernels) a times the refined reciprocal
-// (about 1 ulp) in FP64; otherwise dv.  (The refined square root is not used there: inlined
-// into the Riemann solver it pushes the 768-thread FP64 step into scratch spills.)  In
-// limited_slope with FX a zero dl + dr yields NaN for the harmonic mean, which the sign test then
-// discards, as it discards the infinity of the IEEE division.
+// (about 1 ulp) in FP64; otherwise dv.  In limited_slope with FX a zero dl + dr yields NaN for
+// the harmonic mean, which the sign test then discards, as it discards the infinity of the IEEE
+// division.
 template <bool FX, class T> __device__ __forceinline__ T dvx(T a, T b)
 {
   if constexpr (FX && sizeof(T) == 8) return a * rcp_nr(b);
   else return dv(a, b);
 }
+// Square root likewise (FX: the refined square root, for positive x only).
 template <bool FX, class T> __device__ __forceinline__ T sqx(T x)
 {
   if constexpr (FX && sizeof(T) == 8) return sqrt_nr(x);
@@ -213,7 +213,7 @@ __device__ __forceinline__ T theta_of_htilde(T ht)
 template <bool FX = false, class T>
 __device__ __forceinline__ T sound_speed2(T th)
 {
-  T h = T(2.5) * th + sq(T(2.25) * th * th + T(1));
+  T h = T(2.5) * th + sqx<FX>(T(2.25) * th * th + T(1));
   return dvx<FX>(th * (T(5) * h - T(8) * th), T(3) * h * (h - th));
 }
 
@@ -611,7 +611,7 @@ template <bool FX = false, class T, class E = EosTm>
 __device__ __forceinline__ FaceAux<T> face_aux(const Prim<T> &w, const E &eos = E())
 {
   FaceAux<T> x;
-  x.gam = sq(T(1) + w.u[0] * w.u[0] + w.u[1] * w.u[1] + w.u[2] * w.u[2]);
+  x.gam = sqx<FX>(T(1) + w.u[0] * w.u[0] + w.u[1] * w.u[1] + w.u[2] * w.u[2]);
   x.igam = dvx<FX>(T(1), x.gam);
   x.cs2 = sound_speed2<FX>(dvx<FX>(w.p, w.rho), eos);
   return x;
@@ -652,7 +652,7 @@ __device__ __forceinline__ void signal_speeds(const Prim<T> &w, const FaceAux<T>
   T a = T(1) - cs2;
   T iden = dvx<FX>(T(1), T(1) + U2 * a);
   // cs sqrt(1 + Up^2 a) as one square root in FP32
-  T s = sizeof(T) == 4 ? sq(cs2 * (T(1) + Up2 * a)) : sq(cs2) * sq(T(1) + Up2 * a);
+  T s = sizeof(T) == 4 ? sq(cs2 * (T(1) + Up2 * a)) : sqx<FX>(cs2) * sqx<FX>(T(1) + Up2 * a);
   T c = gam * Ud * a;
   lm = (c - s) * iden;
   lp = (c + s) * iden;
@@ -732,6 +732,7 @@ __device__ __forceinline__ Cons<T> hllc(const Prim<T> &wl, const Prim<T> &wr, co
   T Fmh = (srl * (ur.m[d] - ul.m[d]) + sr * fl.m[d] - sl * fr.m[d]) * inv;
   T B = Eh + Fmh;
   T disc = maxT(B * B - T(4) * FEh * mh, T(0));
+  // (IEEE square root here: the refined one would push the 768-thread FP64 step into spills)
   T ls = dvx<FX>(T(2) * mh, B + sq(disc));
   T ps = Fmh - ls * FEh;
   bool left = ls >= T(0);
