@@ -30,9 +30,10 @@ __device__ __forceinline__ float dv(float a, float b) { return a * __builtin_amd
 // Reciprocal to about 1 ulp where no correctly rounded quotient is needed: the hardware estimate
 // refined by two Newton-Raphson steps (6 instructions in FP64 against 11 for a division).  For
 // normal, finite arguments of moderate exponent only (no scaling of extreme exponents).  The
-// inversion uses it with FAST: in the FP32-bulk gather-layout and VL step kernels, where it
-// measures faster (in the padded kernels the compiler's schedule around it costs registers and
-// occupancy; FP64 keeps the division so that both layouts give the same bits).
+// inversions use it with FAST: in every FP64 step kernel (both layouts alike, so that they give
+// the same bits) and in the FP32-bulk gather-layout and VL kernels, where it measures faster (in
+// the FP32-bulk padded kernels the compiler's schedule around it costs registers and occupancy).
+// The FP64 bulk uses it through dvx below.
 __device__ __forceinline__ double rcp_nr(double b)
 {
   double r = __builtin_amdgcn_rcp(b);
