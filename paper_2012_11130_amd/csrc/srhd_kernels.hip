@@ -50,7 +50,9 @@ __global__ void __launch_bounds__(kBlock) k_prim2cons(int64_t n, const T *__rest
 
 // With MLP, the learned guess is tried first and the analytic guess is the fallback.  The loop
 // runs the same number of times in every lane of a wavefront (the network's matrix instructions
-// need all lanes); lanes past the end work on a dummy state and store nothing.
+// need all lanes); lanes past the end work on a dummy state and store nothing.  Each iteration
+// loads the next state of the grid-stride loop before inverting the current one, so that the
+// loads' latency overlaps the Newton iteration.
 template <class T, bool MLP, class E>
 __global__ void __launch_bounds__(kBlock) k_cons2prim(int64_t n, const T *__restrict__ cons,
                                                       T *__restrict__ prim,
@@ -59,12 +61,21 @@ __global__ void __launch_bounds__(kBlock) k_cons2prim(int64_t n, const T *__rest
                                                       MlpDev mlp, E eos)
 {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+  int64_t base = (int64_t)blockIdx.x * blockDim.x;
+  T nD = T(0), nMx = T(0), nMy = T(0), nMz = T(0), nEt = T(0);
+  if (base < n) {
+    const int64_t i = base + threadIdx.x, j = i < n ? i : 0;
+    nD = cons[j]; nMx = cons[n + j]; nMy = cons[2 * n + j]; nMz = cons[3 * n + j]; nEt = cons[4 * n + j];
+  }
+  for (; base < n; base += stride) {
     const int64_t i = base + threadIdx.x;
     const bool in = i < n;
-    const int64_t j = in ? i : 0;
-    T D = cons[j], Mx = cons[n + j], My = cons[2 * n + j], Mz = cons[3 * n + j],
-      Et = cons[4 * n + j];
+    T D = nD, Mx = nMx, My = nMy, Mz = nMz, Et = nEt;
+    if (base + stride < n) {                         // uniform across the workgroup
+      const int64_t i2 = base + stride + threadIdx.x, j2 = i2 < n ? i2 : 0;
+      nD = cons[j2]; nMx = cons[n + j2]; nMy = cons[2 * n + j2]; nMz = cons[3 * n + j2];
+      nEt = cons[4 * n + j2];
+    }
     T L;
     const bool adm = admissible(D, Mx, My, Mz, Et, T(Tol<T>::eps), L);
     bool consulted = false;
@@ -73,8 +84,8 @@ __global__ void __launch_bounds__(kBlock) k_cons2prim(int64_t n, const T *__rest
     if (MLP) guess = (T)mlp_guess(mlp, D, Mx, My, Mz, Et, (in && adm) ? (double)L : 0.0, consulted, evals);
     if (!in) continue;
     InvOut<T> o;
-    // FP64: the Newton iteration and 1/D through the refined reciprocal and square root (about
-    // 1 ulp); L stays correctly rounded and the recovery keeps IEEE divisions
+    // FP64: the guess, the Newton iteration and the recovery through the refined reciprocal and
+    // square root (about 1 ulp); L stays correctly rounded
     if (adm)
       invert_with_L<T, T, T, sizeof(T) == 8>(D, Mx, My, Mz, L, guess, consulted, T(Tol<T>::v), max_iter, o, eos);
     else
