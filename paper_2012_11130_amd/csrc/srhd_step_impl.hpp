@@ -418,13 +418,11 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
   unsigned int my_iters = 0, my_inv = 0, my_fb = 0, my_nc = 0, my_mlp = 0;
   __syncthreads();
   // learned-guess split with the input's network masks: a patch whose tile holds a cell above
-  // the gate is on the list that the learned kernel steps (k_net_list applies the same rule)
-  if constexpr (GATHER && K == KV_ANALYTIC) {
-    if (a.net_list && a.net_in) {
-      const bool hit = tid < 27 && tile_hits_mask(tid, s.nb[tid], a.n_patch, a.net_in);
-      if (__syncthreads_or(hit)) return;
-    }
-  }
+  // the gate is on the list that the learned kernel steps (k_net_list applies the same rule).
+  // The masks are read here and tested after phase A, so that their latency overlaps it.
+  const bool prelisted = GATHER && K == KV_ANALYTIC && a.net_list && a.net_in;
+  bool hit = false;
+  if (prelisted && tid < 27) hit = tile_hits_mask(tid, s.nb[tid], a.n_patch, a.net_in);
 
   // ---------------------------------------------------------------- A: centre primitives
   bool centre_bad = false, hot = false, net = false, steep = false;
@@ -532,6 +530,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
     }
   }
   centre_bad = __syncthreads_or(centre_bad);
+  if (prelisted && __syncthreads_or(hit)) return;    // before the guard: the learned pass guards it
   // FP64 bulk: the refined division upstream of the face inversions in patches whose tile holds
   // no cell with kappa > KAPPA_FAST (nor an unphysical one)
   const bool fast64 = sizeof(T) == 8 && !__syncthreads_or(steep);
