@@ -182,3 +182,32 @@ def test_network_masks_concurrent_split(S, case, prec):
     torch.cuda.synchronize()
     w2 = _listed_by_masks(got, g.neighbor.reshape(P, 27))
     assert np.array_equal(b.cpu().numpy()[w2], a.cpu().numpy()[w2])
+
+
+def test_concurrent_split_on_a_caller_stream(S, case):
+    # the learned pass forks off the caller's stream and joins back into it: a chain of steps
+    # issued on a stream of the caller's, with no synchronisation between the steps, gives the
+    # bits of the same chain on the default stream
+    g, cons, dt, pad, ref, mlp, listed = case
+    P = g.n_patch
+    guess = mlp.guess()
+    nb = torch.from_numpy(g.neighbor).to(DEV)
+
+    def chain():
+        c = torch.from_numpy(cons).to(DEV)
+        m = S.new_net_mask(P, DEV)
+        prims, smax = S.srhd_grid_prims(c, prec=1, guess=guess, net_mask=m)
+        for _ in range(3):
+            m2 = S.new_net_mask(P, DEV)
+            c, prims, smax = S.srhd_fluid_step_grid(c, prims, nb, g.dh_lev, smax_in=smax, prec=1,
+                                                    guess=guess, net_in=m, net_out=m2)
+            m = m2
+        return c, m
+
+    ref_c, ref_m = chain()
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        got_c, got_m = chain()
+    s.synchronize()
+    assert torch.equal(got_c, ref_c) and torch.equal(got_m, ref_m)
