@@ -140,10 +140,34 @@ struct Tile {
   unsigned int cnt[8];   // workgroup counters
   int nb[32];            // neighbour table row (gather mode)
   unsigned long long claim;  // queue position claimed by the workgroup (persistent schedule)
+  unsigned int orf[2][4];    // workgroup OR (wg_or): one byte per wavefront, two buffers
 };
 
 // the updated state of the final inversion (5 doubles per thread) is parked in the primitive tile
 static_assert(sizeof(float) * 5 * NB >= sizeof(double) * 5 * NT, "parking space in the tile");
+
+// Workgroup-wide OR of a per-thread bit set (8 bits) with one barrier: lane 0 of each wavefront
+// stores its wavefront's OR (a ballot per bit) into its byte of buffer `par`, and every thread
+// reads the buffer after the barrier.  The two buffers alternate, so a buffer is written again
+// only after a further barrier -- after every thread has read it; bytes of absent wavefronts are
+// zeroed at the patch's start.  (The runtime's __syncthreads_or costs three barriers and a static
+// LDS block, which moves the dynamic tile to a link-time offset and the tile's addresses into
+// spilled scalar registers.)  Every thread of the workgroup must call it.
+template <class T>
+__device__ __forceinline__ unsigned int wg_or(Tile<T> &s, unsigned int v, int &par)
+{
+  unsigned int m = 0u;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) m |= (__ballot((v >> i) & 1u) != 0ull ? 1u : 0u) << i;
+  if ((threadIdx.x & 63) == 0) reinterpret_cast<unsigned char *>(s.orf[par])[threadIdx.x >> 6] = (unsigned char)m;
+  __syncthreads();
+  const uint4 q = *reinterpret_cast<const uint4 *>(s.orf[par]);
+  par ^= 1;
+  unsigned int r = q.x | q.y | q.z | q.w;
+  r |= r >> 16;
+  r |= r >> 8;
+  return r & 0xffu;
+}
 
 __device__ __forceinline__ int bidx(int i, int j, int k) { return ((k + 2) * BX + (j + 2)) * BX + (i + 2); }
 __device__ __forceinline__ int hidx(int i, int j, int k) { return ((k + 1) * HX + (j + 1)) * HX + (i + 1); }
@@ -414,6 +438,8 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
                              : a.c_cfl * a.dh[tid] / __longlong_as_double((long long)a.smax_in[0]);
 
   if (tid < 8) s.cnt[tid] = 0u;
+  if (tid < 8) s.orf[tid >> 2][tid & 3] = 0u;
+  int par = 0;
   if (GATHER && tid < 27) s.nb[tid] = a.neighbor[p * 27 + tid];
   unsigned int my_iters = 0, my_inv = 0, my_fb = 0, my_nc = 0, my_mlp = 0;
   __syncthreads();
@@ -529,18 +555,21 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
       if (split) net |= adm && L > a.guess.gate;
     }
   }
-  centre_bad = __syncthreads_or(centre_bad);
-  if (prelisted && __syncthreads_or(hit)) return;    // before the guard: the learned pass guards it
+  // the tile's flags, OR-ed over the workgroup in one pass
+  const unsigned int tf = wg_or(s, (centre_bad ? 1u : 0u) | (hit ? 2u : 0u) | (steep ? 4u : 0u) |
+                                       (hot ? 8u : 0u) | (net ? 16u : 0u), par);
+  centre_bad = tf & 1u;
+  if (prelisted && (tf & 2u)) return;    // before the guard: the learned pass guards the patch
   // FP64 bulk: the refined division upstream of the face inversions in patches whose tile holds
   // no cell with kappa > KAPPA_FAST (nor an unphysical one)
-  const bool fast64 = sizeof(T) == 8 && !__syncthreads_or(steep);
+  const bool fast64 = sizeof(T) == 8 && !(tf & 4u);
 
   // precision guard: a patch holding a cell beyond kappa_max goes to the FP64 kernel (its
   // unphysical centre cells are counted there)
   bool deferred = false;
   if constexpr (sizeof(T) == 4) {
     if (a.defer) {
-      deferred = __syncthreads_or(hot);
+      deferred = tf & 8u;
       if (deferred) {
         centre_unphys = 0;
         if (tid == 0) a.defer[2 + atomicAdd(&a.defer[0], 1ull)] = (unsigned long long)p;
@@ -548,7 +577,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
     }
   }
   if (split && !deferred) {
-    deferred = __syncthreads_or(net);
+    deferred = tf & 16u;
     if (deferred) {
       centre_unphys = 0;
       if (tid == 0) a.net_list[2 + atomicAdd(&a.net_list[0], 1ull)] = (unsigned long long)p;
@@ -669,7 +698,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
       else ok_out = admissible_adaptive<fast_of<T, GATHER>()>(un[0], un[1], un[2], un[3], un[4], DBL_EPSILON, Lo);
     }
     fail |= !ok_out;
-    fail = __syncthreads_or(fail);
+    fail = wg_or(s, fail ? 1u : 0u, par) != 0u;
     bool last = !fail || centre_bad || theta == T(0);
     if (last) {
       if (owner) {
