@@ -152,9 +152,10 @@ static_assert(sizeof(float) * 5 * NB >= sizeof(double) * 5 * NT, "parking space 
 // only after a further barrier -- after every thread has read it; bytes of absent wavefronts are
 // zeroed at the patch's start.  (The runtime's __syncthreads_or costs three barriers and a static
 // LDS block, which moves the dynamic tile to a link-time offset and the tile's addresses into
-// spilled scalar registers.)  Every thread of the workgroup must call it.
-template <class T>
-__device__ __forceinline__ unsigned int wg_or(Tile<T> &s, unsigned int v, int &par)
+// spilled scalar registers.)  Every thread of the workgroup must call it.  S: a tile with the
+// member orf[2][4].
+template <class S>
+__device__ __forceinline__ unsigned int wg_or(S &s, unsigned int v, int &par)
 {
   unsigned int m = 0u;
 #pragma unroll

@@ -151,6 +151,7 @@ struct VlTile {
   double red[NT / 64];
   unsigned int cnt[8];
   unsigned long long claim;
+  unsigned int orf[2][4];        // workgroup OR (wg_or)
 };
 static_assert(5 * NVF >= 2 * 5 * NIF, "the corrector's ring fits in the predictor buffer");
 
@@ -242,6 +243,8 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
   const double dt = a.dt_lev[lv];
 
   if (tid < 8) s.cnt[tid] = 0u;
+  if (tid < 8) s.orf[tid >> 2][tid & 3] = 0u;
+  int par = 0;
   unsigned int my_iters = 0, my_inv = 0, my_nc = 0, bad_in = 0, my_pfb = 0;
   __syncthreads();
 
@@ -349,7 +352,7 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
       }
     }
   }
-  const bool input_bad = __syncthreads_or(bad_in != 0);
+  const bool input_bad = wg_or(s, bad_in != 0 ? 1u : 0u, par) != 0u;
 
   // this thread's interior cell for D
   const int ci = tid & 7, cj = (tid >> 3) & 7, ck = tid >> 6;
@@ -422,7 +425,7 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
     for (int f = 0; f < 5; ++f) un[f] = q[f * N3 + lq] - full * (double)dU[f];
     double Lo;
     const bool ok_out = vl_admissible<T>(un[0], un[1], un[2], un[3], un[4], Lo);
-    const bool fail = __syncthreads_or(!ok_out);
+    const bool fail = wg_or(s, ok_out ? 0u : 1u, par) != 0u;
     if (!fail || input_bad || theta == T(0)) {
       double *o = a.out + p * 5 * 512 + lt;
 #pragma unroll
