@@ -799,11 +799,11 @@ __device__ __forceinline__ T signal_smax_t(T rho, T ux, T uy, T uz, T p, const E
 // Eq. 20's conversion condition number kappa = 1 + M^2 of a primitive state against a threshold:
 // M = U / U_s is the Mach number in four-velocities, U_s^2 = c_s^2 / (1 - c_s^2), so kappa > kmax
 // is U^2 (1 - c_s^2) > (kmax - 1) c_s^2 (no division by a vanishing sound speed).  A threshold
-// only: formed in the arithmetic of T; false for non-finite input.
-template <class T, class E = EosTm>
+// only: formed in the arithmetic of T (FX: with dvx / sqx); false for non-finite input.
+template <class T, class E = EosTm, bool FX = false>
 __device__ __forceinline__ bool kappa_above(T rho, T ux, T uy, T uz, T p, T kmax_m1, const E &eos = E())
 {
-  const T cs2 = sound_speed2(dv(p, rho), eos);
+  const T cs2 = sound_speed2<FX>(dvx<FX>(p, rho), eos);
   const T u2 = ux * ux + uy * uy + uz * uz;
   return u2 * (T(1) - cs2) > kmax_m1 * cs2;
 }

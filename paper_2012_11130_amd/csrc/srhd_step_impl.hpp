@@ -497,7 +497,7 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
       if constexpr (sizeof(T) == 4) {
         if (a.defer) hot |= kappa_above<T>(v0, v1, v2, v3, v4, km1, eos);
       } else {
-        steep |= bad || kappa_above<T>(v0, v1, v2, v3, v4, kf1, eos);
+        steep |= bad || kappa_above<T, typename KEos<K>::type, true>(v0, v1, v2, v3, v4, kf1, eos);
       }
       if (split) net |= !bad && (double)lhs_L_of_prim<T>(v0, v1, v2, v3, v4) > a.guess.gate;
       centre_bad |= bad;
@@ -551,7 +551,8 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
         if (a.defer) hot |= kappa_above<T>((T)o.rho, (T)o.ux, (T)o.uy, (T)o.uz, (T)o.p, km1, eos);
       } else {
         steep |= o.status == ST_UNPHYSICAL ||
-                 kappa_above<T>((T)o.rho, (T)o.ux, (T)o.uy, (T)o.uz, (T)o.p, kf1, eos);
+                 kappa_above<T, typename KEos<K>::type, true>((T)o.rho, (T)o.ux, (T)o.uy, (T)o.uz,
+                                                             (T)o.p, kf1, eos);
       }
       if (split) net |= adm && L > a.guess.gate;
     }
