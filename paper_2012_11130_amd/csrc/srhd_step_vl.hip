@@ -167,20 +167,24 @@ __device__ __forceinline__ Prim<T> vload(const VlTile<T> &s, int b)
   return w;
 }
 
-template <int d, class T>
+// FX: the refined division and square roots of the FP64 bulk (dvx, sqx) -- in the corrector only,
+// whose fluxes are not inverted again; the predictor's are (U* -> W*), and an inversion turns a
+// changed rounding of its input into up to kappa (Eq. 20) times that change.
+template <int d, bool FX, class T>
 __device__ __forceinline__ Cons<T> riemann(int solver, const Prim<T> &wl, const Prim<T> &wr)
 {
-  const Cons<T> ul = prim2cons(wl), ur = prim2cons(wr);
-  return solver == SRHD_HLLE ? hlle<d>(wl, wr, ul, ur) : hllc<d>(wl, wr, ul, ur);
+  const Cons<T> ul = prim2cons<FX>(wl), ur = prim2cons<FX>(wr);
+  const FaceAux<T> xl = face_aux<FX>(wl), xr = face_aux<FX>(wr);
+  return solver == SRHD_HLLE ? hlle<d, false, FX>(wl, wr, ul, ur, xl, xr)
+                             : hllc<d, false, FX>(wl, wr, ul, ur, xl, xr);
 }
 
-// Eq. 30 and L of an FP64 state.  With an FP32 bulk the primitives are consumed in FP32, so L may
-// come from the adaptive sum (every caller runs whole wavefronts); FP64 keeps the exact sum.
+// Eq. 30 and L of an FP64 state: the adaptive sum of the exact products (every caller runs whole
+// wavefronts), as in the MUSCL-Hancock step.
 template <class T>
 __device__ __forceinline__ bool vl_admissible(double D, double Mx, double My, double Mz, double Et, double &L)
 {
-  if constexpr (sizeof(T) == 4) return admissible_adaptive<true>(D, Mx, My, Mz, Et, DBL_EPSILON, L);
-  else return admissible(D, Mx, My, Mz, Et, DBL_EPSILON, L);
+  return admissible_adaptive<true>(D, Mx, My, Mz, Et, DBL_EPSILON, L);
 }
 
 // First-order flux of predictor face r along d into the buffer.
@@ -191,7 +195,7 @@ __device__ __forceinline__ void predictor_face(VlTile<T> &s, int r, int solver)
   unpack(kVl.face[d][r], i, j, k);
   const Prim<T> wr = vload(s, vslot(i, j, k));
   const Prim<T> wl = vload(s, vslot(i - (d == 0), j - (d == 1), k - (d == 2)));
-  const Cons<T> F = riemann<d>(solver, wl, wr);
+  const Cons<T> F = riemann<d, false>(solver, wl, wr);
   s.B[0 * NVF + r] = F.D;
   s.B[1 * NVF + r] = F.m[0];
   s.B[2 * NVF + r] = F.m[1];
@@ -214,13 +218,13 @@ __device__ __forceinline__ void corrector_face(VlTile<T> &s, int r, T theta, int
 #pragma unroll
   for (int f = 0; f < 5; ++f) {
     const T a0 = s.W[f][b - 2 * sd], a1 = s.W[f][b - sd], a2 = s.W[f][b], a3 = s.W[f][b + sd];
-    vl[f] = a1 + T(0.5) * limited_slope(a0, a1, a2, theta);
-    vr[f] = a2 - T(0.5) * limited_slope(a1, a2, a3, theta);
+    vl[f] = a1 + T(0.5) * limited_slope<sizeof(T) == 8>(a0, a1, a2, theta);
+    vr[f] = a2 - T(0.5) * limited_slope<sizeof(T) == 8>(a1, a2, a3, theta);
   }
   Prim<T> wl, wr;
   wl.rho = vl[0]; wl.u[0] = vl[1]; wl.u[1] = vl[2]; wl.u[2] = vl[3]; wl.p = vl[4];
   wr.rho = vr[0]; wr.u[0] = vr[1]; wr.u[1] = vr[2]; wr.u[2] = vr[3]; wr.p = vr[4];
-  const Cons<T> F = riemann<d>(solver, wl, wr);
+  const Cons<T> F = riemann<d, sizeof(T) == 8>(solver, wl, wr);
   constexpr int slot = d & 1;
   s.B[(slot * 5 + 0) * NIF + r] = F.D;
   s.B[(slot * 5 + 1) * NIF + r] = F.m[0];
@@ -258,7 +262,7 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
     double L;
     InvOut<I> o;
     if (vl_admissible<T>(D, Mx, My, Mz, Et, L))
-      invert_with_L<I, GuessT<T, I>, GuessT<T, I>, sizeof(T) == 4>((I)D, (I)Mx, (I)My, (I)Mz, (I)L, (I)-1.0, false,
+      invert_with_L<I, GuessT<T, I>, GuessT<T, I>, true>((I)D, (I)Mx, (I)My, (I)Mz, (I)L, (I)-1.0, false,
                                      (I)StepTol<T, I>::v, 30, o);
     else set_unphysical(o);
     bad_in += o.status == ST_UNPHYSICAL;
@@ -318,7 +322,7 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
         double L;
         InvOut<I> o;
         if (vl_admissible<T>(u[0], u[1], u[2], u[3], u[4], L))
-          invert_with_L<I, GuessT<T, I>, GuessT<T, I>, sizeof(T) == 4>((I)u[0], (I)u[1], (I)u[2], (I)u[3], (I)L, (I)-1.0, false,
+          invert_with_L<I, GuessT<T, I>, GuessT<T, I>, true>((I)u[0], (I)u[1], (I)u[2], (I)u[3], (I)L, (I)-1.0, false,
                                          (I)StepTol<T, I>::v, 30, o);
         else set_unphysical(o);
         my_iters += o.iters;
@@ -376,7 +380,7 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
           double L;
           InvOut<I> o;
           if (vl_admissible<T>(D, Mx, My, Mz, Et, L))
-            invert_with_L<I, GuessT<T, I>, GuessT<T, I>, sizeof(T) == 4>((I)D, (I)Mx, (I)My, (I)Mz, (I)L, (I)-1.0, false,
+            invert_with_L<I, GuessT<T, I>, GuessT<T, I>, true>((I)D, (I)Mx, (I)My, (I)Mz, (I)L, (I)-1.0, false,
                                            (I)StepTol<T, I>::v, 30, o);
           else set_unphysical(o);
           my_iters += o.iters;
