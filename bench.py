@@ -465,7 +465,7 @@ def main():
 
     pbufs = {}
 
-    def run_grid(prec, n_steps, time_kernel=False, guess=None, sched=None):
+    def run_grid(prec, n_steps, time_kernel=False, guess=None, sched=None, integrator=S.MHM):
         """n_steps from the initial state with the gather-mode step: each step is one kernel
         that reads ghosts from neighbour interiors and returns the next S_max; the entry
         inversion of the initial state is inside the timed region."""
@@ -497,7 +497,8 @@ def main():
             S.srhd_fluid_step_grid(bufs[cur], pb[cur], nb, dh, smax_in=sb[cur], c_cfl=0.5,
                                    cons_out=bufs[1 - cur], prims_out=pb[1 - cur],
                                    smax_out=sb[1 - cur], prec=prec, stats=stats, guess=guess,
-                                   sched=sched, net_in=nmask[cur], net_out=nmask[1 - cur])
+                                   sched=sched, net_in=nmask[cur], net_out=nmask[1 - cur],
+                                   integrator=integrator)
             if time_kernel:
                 b.record(stream)
                 evs.append((a, b))
@@ -643,30 +644,46 @@ def main():
                 "one_step": field_err(o32, o64),
                 "after_%d_steps" % args.steps: field_err(fin_32.cpu().numpy(), b)}
 
-    # the VL integrator (padded layout: CFL kernel + ghost fill + VL step per step), analytic guess
+    # the VL integrator, analytic guess: the gather layout (one kernel per step, the next step's
+    # S_max fused) and the padded layout (CFL kernel + ghost fill + VL step per step)
     if args.vl and not args.only_headline:
         res["vl"] = {}
         finals = {}
-        for prec, name in ((S.PREC_MIXED, "mixed"), (S.PREC_FP64, "fp64")):
-            S.srhd_cfl_dt(cons0, dh, 0.5, dt_lev=dt)
-            S.srhd_fill_ghosts(cons0, nb, 3, padded=pad)
-            sch, table = S.srhd_autotune_step(pad, dt, dh, prec=prec, reps=2, integrator=S.VL)
-            schedules["vl_" + name] = {"groups": sch.groups, "chunk": sch.chunk,
-                                       "occupancy": sch.occupancy,
-                                       "autotune_ms": [[t[0], t[1], t[2], round(t[3], 4)] for t in table]}
-            if args.warmup:
-                run_padded(prec, args.warmup, sched=sch, integrator=S.VL)
-            ms_v, kms_v, st_v, fin_v = run_padded(prec, args.steps, time_kernel=True, sched=sch,
+        for layout in ("grid", "padded"):
+            for prec, name in ((S.PREC_MIXED, "mixed"), (S.PREC_FP64, "fp64")):
+                if layout == "grid":
+                    prims, smax = S.srhd_grid_prims(cons0, prec=prec)
+                    sch, table = S.srhd_autotune_step_grid(cons0, prims, nb, dh, smax_in=smax,
+                                                           prec=prec, reps=2, integrator=S.VL)
+                    del prims
+                    runner = run_grid
+                else:
+                    S.srhd_cfl_dt(cons0, dh, 0.5, dt_lev=dt)
+                    S.srhd_fill_ghosts(cons0, nb, 3, padded=pad)
+                    sch, table = S.srhd_autotune_step(pad, dt, dh, prec=prec, reps=2,
+                                                      integrator=S.VL)
+                    runner = run_padded
+                key = name if layout == "grid" else "padded_" + name
+                schedules["vl_" + key] = {"groups": sch.groups, "chunk": sch.chunk,
+                                          "occupancy": sch.occupancy,
+                                          "autotune_ms": [[t[0], t[1], t[2], round(t[3], 4)] for t in table]}
+                if args.warmup:
+                    runner(prec, args.warmup, sched=sch, integrator=S.VL)
+                ms_v, kms_v, st_v, fin_v = runner(prec, args.steps, time_kernel=True, sched=sch,
                                                   integrator=S.VL)
-            finals[name] = fin_v.cpu().numpy()
-            print("# VL %s: %.2f ms for %d steps (step kernel %.3f ms avg); stats %s"
-                  % (name, ms_v, args.steps, float(np.mean(kms_v)), st_v), file=sys.stderr, flush=True)
-            res["vl"][name] = {"value": n_cells * args.steps / (ms_v * 1e-3),
-                               "ms_per_step": ms_v / args.steps,
-                               "step_kernel_ms": float(np.mean(kms_v)), "stats": st_v,
-                               "newton": newton_summary(st_v)}
+                finals[key] = fin_v.cpu().numpy()
+                print("# VL %s %s: %.2f ms for %d steps (step kernel %.3f ms avg); stats %s"
+                      % (layout, name, ms_v, args.steps, float(np.mean(kms_v)), st_v),
+                      file=sys.stderr, flush=True)
+                res["vl"][key] = {"value": n_cells * args.steps / (ms_v * 1e-3),
+                                  "ms_per_step": ms_v / args.steps,
+                                  "step_kernel_ms": float(np.mean(kms_v)), "stats": st_v,
+                                  "newton": newton_summary(st_v)}
         res["vl"]["mixed_vs_fp64_rel_err_after_%d_steps" % args.steps] = field_err(finals["mixed"],
                                                                                  finals["fp64"])
+        # the padded chain takes dt from the CFL kernel, the gather chain from the fused S_max: in
+        # FP64 the two are the same bits, so the two layouts end in the same state
+        res["vl"]["fp64_layouts_equal"] = bool(np.array_equal(finals["fp64"], finals["padded_fp64"]))
 
     # the widened rows on the same blast (padded layout, analytic guess): the original
     # total-energy scheme and the polytropic EoS, one-workgroup-per-patch launch

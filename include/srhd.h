@@ -76,8 +76,8 @@ typedef enum { SRHD_ENERGY_REDUCED = 0, SRHD_ENERGY_TOTAL = 1 } srhd_energy;
  * first-order half step U* = U^n - (dt/2dh) sum_d [F_d(W_c, W_{c+d}) - F_d(W_{c-d}, W_c)] with
  * the cell-centre primitives as face states, W* = cons -> prim of U*, then the full step with
  * the fluxes of PLM face states of W*.  Only an updated cell failing Eq. 30 triggers the limiter
- * retry.  VL runs in srhd_fluid_step with ghost >= 3, the analytic guess and the reduced
- * energy, in every precision mode (else SRHD_EUNSUPPORTED).  A predictor state that fails the
+ * retry.  VL runs in srhd_fluid_step with ghost >= 3 and in srhd_fluid_step_grid, with the
+ * analytic guess and the reduced energy, in every precision mode (else SRHD_EUNSUPPORTED).  A predictor state that fails the
  * inversion is replaced by the cell's state at t^n (W* = W^n: the half step is dropped for that
  * cell) and counted in n_pred_fallback. */
 typedef enum { SRHD_MHM = 0, SRHD_VL = 1 } srhd_integrator;
@@ -374,17 +374,19 @@ int srhd_grid_prims(int prec, int64_t n_patch, const double *cons, void *prims,
                     uint64_t *smax_bits, uint32_t *net_mask, const srhd_guess *guess,
                     void *stream);
 
-/* One MUSCL-Hancock step of a srhd_grid, identical in arithmetic to srhd_fluid_step on the
- * padded copies of the same patches.  The time step is dt_l = c_cfl * dh[l] / S_max with S_max
- * read from *smax_in (the bits written by srhd_grid_prims or by the previous step), unless
- * dt_lev (device double[n_level]) is given.  Outputs: cons_out [n_patch][5][8][8][8] FP64,
+/* One MUSCL-Hancock (or, prm->integrator = SRHD_VL, VL) step of a srhd_grid, the step of
+ * srhd_fluid_step on the padded copies of the same patches: for the same dt bit for bit in FP64,
+ * and with VL in every precision mode (MUSCL-Hancock with an FP32 bulk agrees to rounding: its
+ * gather kernel refines the hardware reciprocals and square roots of its inversions and L).
+ * The time step is dt_l = c_cfl * dh[l] / S_max with S_max read from *smax_in (the bits written
+ * by srhd_grid_prims or by the previous step), unless dt_lev (device double[n_level]) is given.  Outputs: cons_out [n_patch][5][8][8][8] FP64,
  * prims_out (bulk type) and *smax_out (zeroed, then the maximum over the updated cells);
  * net_out (device uint32 [n_patch], or NULL) the updated state's network masks;
  * dt_used (device double[n_level], may be NULL) receives the time step used.
  * Outputs must not overlap the inputs.  Patches are mapped to workgroups so that each XCD works
  * on a contiguous range of patch indices (order patches along a space-filling curve).  The
- * reduced energy and MUSCL-Hancock only (prm->energy = SRHD_ENERGY_TOTAL or prm->integrator =
- * SRHD_VL gives SRHD_EUNSUPPORTED). */
+ * reduced energy and the TM EoS only (prm->energy = SRHD_ENERGY_TOTAL or a polytropic EoS gives
+ * SRHD_EUNSUPPORTED); VL takes the analytic guess, and its network masks (net_out) are zero. */
 int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_cfl,
                          const double *dt_lev, double *cons_out, void *prims_out,
                          uint64_t *smax_out, uint32_t *net_out, double *dt_used,

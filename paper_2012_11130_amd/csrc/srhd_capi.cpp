@@ -96,8 +96,7 @@ int check_eos(const srhd_eos *eos, double &k, const char *who)
 
 // Energy variable and integrator of a step (include/srhd.h, srhd_energy, srhd_integrator): the
 // original scheme has kernels for the padded layout with equal bulk and inversion types and the
-// analytic guess; the VL integrator for the padded layout, the analytic guess and the reduced
-// energy.
+// analytic guess; the VL integrator for both layouts, the analytic guess and the reduced energy.
 int check_variant(int energy, int integrator, int prec, int guess_kind, int gather, const char *who)
 {
   if (integrator != SRHD_MHM && integrator != SRHD_VL)
@@ -105,7 +104,6 @@ int check_variant(int energy, int integrator, int prec, int guess_kind, int gath
   if (energy != SRHD_ENERGY_REDUCED && energy != SRHD_ENERGY_TOTAL)
     return fail(SRHD_EINVAL, "%s: unknown energy variable %d", who, energy);
   if (integrator == SRHD_VL) {
-    if (gather) return fail(SRHD_EUNSUPPORTED, "%s: the VL integrator runs on padded patches only", who);
     if (energy != SRHD_ENERGY_REDUCED)
       return fail(SRHD_EUNSUPPORTED, "%s: the VL integrator evolves the reduced energy only", who);
     if (guess_kind != SRHD_GUESS_ANALYTIC)
@@ -495,7 +493,7 @@ int srhd_step_occupancy(const srhd_step_params *prm, int gather)
   if (rc) return rc;
   const int kind = prm->energy == SRHD_ENERGY_TOTAL ? 2
                  : (eos_k > 0.0 ? 3 : (guess_kind == SRHD_GUESS_MLP ? 1 : 0));
-  int n = prm->integrator == SRHD_VL ? srhd::step_occupancy_vl(prec, occupancy == 2)
+  int n = prm->integrator == SRHD_VL ? srhd::step_occupancy_vl(prec, gather != 0, occupancy == 2)
                                      : srhd::step_occupancy(prec, gather != 0, kind, occupancy == 2);
   if (n <= 0) return fail(SRHD_EHIP, "srhd_step_occupancy: occupancy query failed");
   return n;
@@ -776,7 +774,7 @@ int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_
   s.dt_out = dt_used;
   s.xcd_remap = 1;
   s.energy = SRHD_ENERGY_REDUCED;
-  s.integrator = SRHD_MHM;
+  s.integrator = prm->integrator;
   s.eos_k = 0.0;
   s.flux_out = nullptr;
   if (prm->flux_out)
@@ -796,6 +794,8 @@ int srhd_fluid_step_grid(const srhd_grid *in, const uint64_t *smax_in, double c_
     s.net_gate = g.kind == SRHD_GUESS_MLP ? g.gate : __builtin_huge_val();
     if (s.net_list) s.net_in = in->net_mask;
   }
+  if (s.integrator == SRHD_VL)
+    return hip_status(srhd::launch_step_vl_grid(prm->prec, s, (hipStream_t)stream), "srhd_fluid_step_grid");
   return hip_status(srhd::launch_step_grid(prm->prec, s, (hipStream_t)stream),
                     "srhd_fluid_step_grid");
 }

@@ -109,9 +109,10 @@ __device__ __forceinline__ void write_boundary_fluxes(double *flux_out, int64_t 
 }
 
 hipError_t launch_step(int prec, const StepArgs &a, hipStream_t s);
-// the VL integrator (srhd_step_vl.hip): padded layout, analytic guess, reduced energy
+// the VL integrator (srhd_step_vl.hip): analytic guess, reduced energy; padded and gather layouts
 hipError_t launch_step_vl(int prec, const StepArgs &a, hipStream_t s);
-int step_occupancy_vl(int prec, bool occ2);
+hipError_t launch_step_vl_grid(int prec, const StepArgs &a, hipStream_t s);
+int step_occupancy_vl(int prec, bool gather, bool occ2);
 
 // per-precision launchers of the step (srhd_step_fp64.hip, srhd_step_mixed.hip, srhd_step_fp32.hip)
 #define SRHD_STEP_MODE(name)                                                                   \

@@ -1,9 +1,11 @@
 // srhd_step_vl.hip -- the VL predictor-corrector step (the paper's second integrator, Sec. 3.1;
-// Falle 1991, van Leer 2006) on padded 8^3 patches, one 512-thread workgroup per patch:
+// Falle 1991, van Leer 2006) on 8^3 patches, one 512-thread workgroup per patch:
 //
-//   A. cell-centre inversions of the 2,112 cells the predictor reads: the 12^3 box [-2, 10)^3
-//      (as far as it is needed) and the six 8x8 slabs one layer further out (coordinate -3 or
-//      10 along one axis)                                                     -> LDS W
+//   A. centre primitives of the 2,112 cells the predictor reads: the 12^3 box [-2, 10)^3 (as far
+//      as it is needed) and the six 8x8 slabs one layer further out (coordinate -3 or 10 along
+//      one axis) -- inverted from padded conserved patches, or, in the gather layout, read from
+//      the primitives of the patch and its 26 neighbours that the previous step (or
+//      srhd_grid_prims) stored                                                -> LDS W
 //   P. predictor, one direction at a time: first-order fluxes F_d(W_left, W_right) with the
 //      cell-centre primitives as face states on the 1,408 faces the half-step cells need
 //      -> LDS buffer; each of the 1,280 half-step cells (coordinate d in [-2, 10), the other
@@ -12,7 +14,9 @@
 //   C. corrector: for the 3 x 576 interfaces, PLM face states of W* (W* -/+ slope/2 on the two
 //      sides), their conserved variables and the HLLC / HLLE flux -> LDS ring, folded into
 //      each interior cell as in the MUSCL-Hancock kernel.
-//   D. U^{n+1} = U^n - (dt/dh) sum_d (F_{+1/2} - F_{-1/2}) with the Eq. 30 check.
+//   D. U^{n+1} = U^n - (dt/dh) sum_d (F_{+1/2} - F_{-1/2}) with the Eq. 30 check; in the gather
+//      layout each updated cell is then inverted, and its primitives and the workgroup's maximum
+//      signal speed (Eqs. 26-27) feed the next step.
 // The face states of C are primitives (no inversion); the limiter keeps rho and p between
 // neighbouring values, so only an output cell can fail: then C-D are redone with
 // theta *= 0.75 (max_retry times) and theta = 0 (Sec. 3.4).  A predictor state that fails the
@@ -152,6 +156,7 @@ struct VlTile {
   unsigned int cnt[8];
   unsigned long long claim;
   unsigned int orf[2][4];        // workgroup OR (wg_or)
+  int nb[28];                    // neighbour table row (gather layout)
 };
 static_assert(5 * NVF >= 2 * 5 * NIF, "the corrector's ring fits in the predictor buffer");
 
@@ -185,6 +190,48 @@ template <class T>
 __device__ __forceinline__ bool vl_admissible(double D, double Mx, double My, double Mz, double Et, double &L)
 {
   return admissible_adaptive<true>(D, Mx, My, Mz, Et, DBL_EPSILON, L);
+}
+
+// Gather layout: the patch and cell holding tile cell (i, j, k), coordinates in [-3, 11).  Along
+// an axis whose face neighbour is missing (< 0) the coordinate is clamped to the patch's own
+// boundary layer: the outflow (zero-gradient) copy of the padded ghost fill.  False when the
+// neighbour holding the cell is missing or out of range.
+__device__ __forceinline__ bool gather_cell(const int *nb, int64_t n_patch, int i, int j, int k,
+                                            int64_t &src, int &sc)
+{
+  int c[3] = {i, j, k};
+  const int fs[3] = {1, 3, 9};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int o = c[d] < 0 ? -1 : (c[d] >= 8 ? 1 : 0);
+    if (o != 0 && nb[13 + o * fs[d]] < 0) c[d] = o < 0 ? 0 : 7;
+  }
+  const int o0 = c[0] < 0 ? -1 : (c[0] >= 8 ? 1 : 0);
+  const int o1 = c[1] < 0 ? -1 : (c[1] >= 8 ? 1 : 0);
+  const int o2 = c[2] < 0 ? -1 : (c[2] >= 8 ? 1 : 0);
+  src = nb[(o2 + 1) * 9 + (o1 + 1) * 3 + (o0 + 1)];
+  sc = ((c[2] - 8 * o2) * 8 + (c[1] - 8 * o1)) * 8 + (c[0] - 8 * o0);
+  const bool ok = src >= 0 && src < n_patch;
+  if (!ok) src = 0;
+  return ok;
+}
+
+// Gather layout: the stored primitives of tile cell (i, j, k) into slot b of the tile (NaN where
+// the cell's patch is missing); true for a physical state.
+template <class T>
+__device__ __forceinline__ bool gather_prim(VlTile<T> &s, const StepArgs &a, int i, int j, int k, int b)
+{
+  int64_t src;
+  int sc;
+  const bool okc = gather_cell(s.nb, a.n_patch, i, j, k, src, sc);
+  const T *w = (const T *)a.prims + src * 5 * 512 + sc;
+  const T nan = T(__builtin_nan(""));
+  T v[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) v[f] = okc ? w[f * 512] : nan;
+#pragma unroll
+  for (int f = 0; f < 5; ++f) s.W[f][b] = v[f];
+  return v[0] > T(0) && v[4] > T(0) && finiteT(v[1]) && finiteT(v[2]) && finiteT(v[3]);
 }
 
 // First-order flux of predictor face r along d into the buffer.
@@ -233,21 +280,33 @@ __device__ __forceinline__ void corrector_face(VlTile<T> &s, int r, T theta, int
   s.B[(slot * 5 + 4) * NIF + r] = F.E;
 }
 
-template <class T, class I>
+// GATHER = false: padded conserved patches (ghost >= 3), centre inversions in phase A.
+// GATHER = true : the tile's primitives are gathered from the stored primitives of the patch and
+//                 its neighbours, U^n of the half-step cells from their conserved interiors; the
+//                 updated cells are inverted at the end.  The stored primitives come from the
+//                 same inversion as phase A's (srhd_grid_prims and this kernel's output), so for
+//                 equal dt both layouts give the same bits.
+template <class T, class I, bool GATHER>
 __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const int64_t p)
 {
   const int tid = threadIdx.x;
   const int g = a.ghost;
   const int N = 8 + 2 * g;
   const int N3 = N * N * N;
-  const double *__restrict__ q = a.padded + p * 5 * N3;
+  const double *__restrict__ q = GATHER ? nullptr : a.padded + p * 5 * N3;
   int lv = a.level ? (int)a.level[p] : 0;
   lv = lv < 0 ? 0 : (lv >= a.n_level ? a.n_level - 1 : lv);
   const double dh = a.dh[lv];
-  const double dt = a.dt_lev[lv];
+  double dt;
+  if (!GATHER || a.dt_lev) dt = a.dt_lev[lv];
+  else dt = a.c_cfl * dh / __longlong_as_double((long long)a.smax_in[0]);
+  if (GATHER && a.dt_out && p == 0 && tid < a.n_level)
+    a.dt_out[tid] = a.dt_lev ? a.dt_lev[tid]
+                             : a.c_cfl * a.dh[tid] / __longlong_as_double((long long)a.smax_in[0]);
 
   if (tid < 8) s.cnt[tid] = 0u;
   if (tid < 8) s.orf[tid >> 2][tid & 3] = 0u;
+  if (GATHER && tid < 27) s.nb[tid] = a.neighbor[p * 27 + tid];
   int par = 0;
   unsigned int my_iters = 0, my_inv = 0, my_nc = 0, bad_in = 0, my_pfb = 0;
   __syncthreads();
@@ -256,25 +315,29 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
   for (int r = tid; r < kVl.np; r += NT) {
     int i, j, k;
     unpack(kVl.pcell[r], i, j, k);
-    const int off = ((k + g) * N + (j + g)) * N + (i + g);
-    const double D = q[off], Mx = q[N3 + off], My = q[2 * N3 + off], Mz = q[3 * N3 + off],
-                 Et = q[4 * N3 + off];
-    double L;
-    InvOut<I> o;
-    if (vl_admissible<T>(D, Mx, My, Mz, Et, L))
-      invert_with_L<I, GuessT<T, I>, GuessT<T, I>, true>((I)D, (I)Mx, (I)My, (I)Mz, (I)L, (I)-1.0, false,
-                                     (I)StepTol<T, I>::v, 30, o);
-    else set_unphysical(o);
-    bad_in += o.status == ST_UNPHYSICAL;
-    my_iters += o.iters;
-    my_inv += 1;
-    my_nc += o.status == ST_NOCONV;
     const int b = vslot(i, j, k);
-    s.W[0][b] = (T)o.rho;
-    s.W[1][b] = (T)o.ux;
-    s.W[2][b] = (T)o.uy;
-    s.W[3][b] = (T)o.uz;
-    s.W[4][b] = (T)o.p;
+    if constexpr (GATHER) {
+      bad_in += !gather_prim(s, a, i, j, k, b);
+    } else {
+      const int off = ((k + g) * N + (j + g)) * N + (i + g);
+      const double D = q[off], Mx = q[N3 + off], My = q[2 * N3 + off], Mz = q[3 * N3 + off],
+                   Et = q[4 * N3 + off];
+      double L;
+      InvOut<I> o;
+      if (vl_admissible<T>(D, Mx, My, Mz, Et, L))
+        invert_with_L<I, GuessT<T, I>, GuessT<T, I>, true>((I)D, (I)Mx, (I)My, (I)Mz, (I)L, (I)-1.0, false,
+                                       (I)StepTol<T, I>::v, 30, o);
+      else set_unphysical(o);
+      bad_in += o.status == ST_UNPHYSICAL;
+      my_iters += o.iters;
+      my_inv += 1;
+      my_nc += o.status == ST_NOCONV;
+      s.W[0][b] = (T)o.rho;
+      s.W[1][b] = (T)o.ux;
+      s.W[2][b] = (T)o.uy;
+      s.W[3][b] = (T)o.uz;
+      s.W[4][b] = (T)o.p;
+    }
   }
   __syncthreads();
 
@@ -315,10 +378,19 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
       if (hc < NVH) {
         int i, j, k;
         unpack(kVl.hcell[hc], i, j, k);
-        const int off = ((k + g) * N + (j + g)) * N + (i + g);
         double u[5];
+        if constexpr (GATHER) {
+          int64_t src;
+          int sc;
+          const bool okc = gather_cell(s.nb, a.n_patch, i, j, k, src, sc);
+          const double *c = a.cons + src * 5 * 512 + sc;
 #pragma unroll
-        for (int f = 0; f < 5; ++f) u[f] = q[f * N3 + off] - half * (double)acc[h][f];
+          for (int f = 0; f < 5; ++f) u[f] = (okc ? c[f * 512] : __builtin_nan("")) - half * (double)acc[h][f];
+        } else {
+          const int off = ((k + g) * N + (j + g)) * N + (i + g);
+#pragma unroll
+          for (int f = 0; f < 5; ++f) u[f] = q[f * N3 + off] - half * (double)acc[h][f];
+        }
         double L;
         InvOut<I> o;
         if (vl_admissible<T>(u[0], u[1], u[2], u[3], u[4], L))
@@ -360,18 +432,23 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
 
   // this thread's interior cell for D
   const int ci = tid & 7, cj = (tid >> 3) & 7, ck = tid >> 6;
-  const int cq = ((ck + g) * N + (cj + g)) * N + (ci + g);
+  const int cq = GATHER ? tid : ((ck + g) * N + (cj + g)) * N + (ci + g);
   T theta = (T)a.theta;
   unsigned int retries = 0, unphys = 0;
   bool have_pred = predicted;
   for (int attempt = 0;; ++attempt) {
     if (theta == T(0) && have_pred) {
       // the last resort of the retry (theta = 0) is the Godunov step: put W^n back at the
-      // half-step cells, inverted again from the padded input
+      // half-step cells, inverted again from the padded input (gathered again from the stored
+      // primitives)
 #pragma unroll
       for (int h = 0; h < 3; ++h) {
         const int hc = tid + h * NT;
-        if (hc < NVH) {
+        if (GATHER && hc < NVH) {
+          int i, j, k;
+          unpack(kVl.hcell[hc], i, j, k);
+          gather_prim(s, a, i, j, k, bidx(i, j, k));
+        } else if (hc < NVH) {
           int i, j, k;
           unpack(kVl.hcell[hc], i, j, k);
           const int off = ((k + g) * N + (j + g)) * N + (i + g);
@@ -417,7 +494,9 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
         const int up = d == 0 ? 1 : (d == 1 ? 8 : 64);
 #pragma unroll
         for (int f = 0; f < 5; ++f) dU[f] += s.B[(slot * 5 + f) * NIF + r + up] - s.B[(slot * 5 + f) * NIF + r];
-        if (a.flux_out && tid < 128) write_boundary_fluxes(a.flux_out, p, d, &s.B[slot * 5 * NIF], NIF, tid);
+        if constexpr (!GATHER) {
+          if (a.flux_out && tid < 128) write_boundary_fluxes(a.flux_out, p, d, &s.B[slot * 5 * NIF], NIF, tid);
+        }
         __syncthreads();
       }
     }
@@ -426,7 +505,10 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
     asm volatile("" : "+v"(lt), "+v"(lq));
     double un[5];
 #pragma unroll
-    for (int f = 0; f < 5; ++f) un[f] = q[f * N3 + lq] - full * (double)dU[f];
+    for (int f = 0; f < 5; ++f) {
+      const double u0 = GATHER ? a.cons[(p * 5 + f) * 512 + lt] : q[f * N3 + lq];
+      un[f] = u0 - full * (double)dU[f];
+    }
     double Lo;
     const bool ok_out = vl_admissible<T>(un[0], un[1], un[2], un[3], un[4], Lo);
     const bool fail = wg_or(s, ok_out ? 0u : 1u, par) != 0u;
@@ -435,6 +517,38 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
 #pragma unroll
       for (int f = 0; f < 5; ++f) o[f * 512] = un[f];
       unphys += !ok_out;
+      if constexpr (GATHER) {
+        // the updated cell's primitives (the inversion of srhd_grid_prims) and signal speed
+        InvOut<I> w;
+        if (ok_out)
+          invert_with_L<I, GuessT<T, I>, GuessT<T, I>, true>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)Lo, (I)-1.0,
+                                                             false, (I)StepTol<T, I>::v, 30, w);
+        else set_unphysical(w);
+        my_iters += w.iters;
+        my_inv += 1;
+        my_nc += w.status == ST_NOCONV;
+        T *po = (T *)a.prims_out + p * 5 * 512 + lt;
+        po[0] = (T)w.rho;
+        po[512] = (T)w.ux;
+        po[1024] = (T)w.uy;
+        po[1536] = (T)w.uz;
+        po[2048] = (T)w.p;
+        double sm = 0.0;
+        if constexpr (sizeof(T) == 4) {
+          if (ok_out) sm = (double)signal_smax_t<float>((T)w.rho, (T)w.ux, (T)w.uy, (T)w.uz, (T)w.p);
+        } else {
+          if (ok_out) sm = signal_smax((double)w.rho, (double)w.ux, (double)w.uy, (double)w.uz, (double)w.p);
+        }
+        sm = wave_max(sm);
+        if ((tid & 63) == 0) s.red[tid >> 6] = sm;
+        __syncthreads();
+        if (tid == 0) {
+          double m = s.red[0];
+#pragma unroll
+          for (int w8 = 1; w8 < NT / 64; ++w8) m = fmax(m, s.red[w8]);
+          atomicMax(a.smax_out, (unsigned long long)__double_as_longlong(m));
+        }
+      }
       break;
     }
     ++retries;
@@ -468,14 +582,14 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
 // One patch per workgroup, or the persistent per-XCD queues, exactly as the MUSCL-Hancock
 // kernel's step_body distributes patches (the loop is repeated here rather than shared through a
 // callable: a call left out of line in the middle of these kernels costs them their registers).
-template <class T, class I>
+template <class T, class I, bool GATHER>
 __device__ __forceinline__ void vl_body(const StepArgs &a)
 {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   VlTile<T> &s = *reinterpret_cast<VlTile<T> *>(smem_raw);
   if (!a.queue) {
     const int64_t p = patch_of_block(a.n_patch, a.xcd_remap);
-    if (p < a.n_patch) vl_patch<T, I>(a, s, p);       // uniform per workgroup
+    if (p < a.n_patch) vl_patch<T, I, GATHER>(a, s, p);       // uniform per workgroup
     return;
   }
   const int64_t range = (a.n_patch + 7) / 8;
@@ -492,53 +606,59 @@ __device__ __forceinline__ void vl_body(const StepArgs &a)
       if (p0 >= hi) break;
       const int64_t p1 = p0 + a.chunk < hi ? p0 + a.chunk : hi;
       for (int64_t p = p0; p < p1; ++p) {
-        vl_patch<T, I>(a, s, p);
+        vl_patch<T, I, GATHER>(a, s, p);
         __syncthreads();
       }
     }
   }
 }
 
-template <class T, class I>
+template <class T, class I, bool GATHER>
 __global__ void __launch_bounds__(NT) k_vl(StepArgs a)
 {
-  vl_body<T, I>(a);
+  vl_body<T, I, GATHER>(a);
 }
 
 // Two workgroups per CU (FP32 bulk): at most 128 VGPRs.
-template <class T, class I>
+template <class T, class I, bool GATHER>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) k_vl_occ2(StepArgs a)
 {
-  vl_body<T, I>(a);
+  vl_body<T, I, GATHER>(a);
 }
 
-template <class T, class I>
+template <class T, class I, bool GATHER>
 const void *vl_kernel(bool occ2)
 {
   if constexpr (sizeof(T) == 4)
-    if (occ2) return (const void *)k_vl_occ2<T, I>;
-  return (const void *)k_vl<T, I>;
+    if (occ2) return (const void *)k_vl_occ2<T, I, GATHER>;
+  return (const void *)k_vl<T, I, GATHER>;
 }
 
-template <class T, class I>
+template <class T, class I, bool GATHER>
 int vl_occupancy_ti(bool occ2)
 {
   int n = 0;
   const size_t bytes = sizeof(VlTile<T>);
-  const void *fn = vl_kernel<T, I>(occ2);
+  const void *fn = vl_kernel<T, I, GATHER>(occ2);
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
     return 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, NT, bytes) != hipSuccess) return 0;
   return n;
 }
 
-template <class T, class I>
+// The gather layout's prologue zeroes the output's S_max (and network masks, which stay zero:
+// the VL step takes the analytic guess) before the kernel takes maxima into it.
+template <class T, class I, bool GATHER>
 hipError_t vl_launch_ti(const StepArgs &a, hipStream_t st)
 {
+  if (GATHER) {
+    hipError_t e = launch_prologue<T, true>(a, st);
+    if (e != hipSuccess) return e;
+  }
   if (a.n_patch == 0) return hipSuccess;
   const size_t bytes = sizeof(VlTile<T>);
   const bool occ2 = a.occ2 && sizeof(T) == 4;
-  hipError_t e = hipFuncSetAttribute(vl_kernel<T, I>(occ2), hipFuncAttributeMaxDynamicSharedMemorySize,
+  hipError_t e = hipFuncSetAttribute(vl_kernel<T, I, GATHER>(occ2), hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)bytes);
   if (e != hipSuccess) return e;
   int64_t blocks;
@@ -550,28 +670,45 @@ hipError_t vl_launch_ti(const StepArgs &a, hipStream_t st)
   }
   if constexpr (sizeof(T) == 4) {
     if (occ2) {
-      hipLaunchKernelGGL((k_vl_occ2<T, I>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
+      hipLaunchKernelGGL((k_vl_occ2<T, I, GATHER>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_vl<T, I>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
+  hipLaunchKernelGGL((k_vl<T, I, GATHER>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
   return hipGetLastError();
+}
+
+template <bool GATHER>
+hipError_t launch_vl(int prec, const StepArgs &a, hipStream_t st)
+{
+  if (prec == SRHD_PREC_MIXED) return vl_launch_ti<float, double, GATHER>(a, st);
+  if (prec == SRHD_PREC_FP32) return vl_launch_ti<float, float, GATHER>(a, st);
+  return vl_launch_ti<double, double, GATHER>(a, st);
+}
+
+template <bool GATHER>
+int occupancy_vl(int prec, bool occ2)
+{
+  if (prec == SRHD_PREC_MIXED) return vl_occupancy_ti<float, double, GATHER>(occ2);
+  if (prec == SRHD_PREC_FP32) return vl_occupancy_ti<float, float, GATHER>(occ2);
+  return vl_occupancy_ti<double, double, GATHER>(occ2);
 }
 
 }  // namespace
 
 hipError_t launch_step_vl(int prec, const StepArgs &a, hipStream_t st)
 {
-  if (prec == SRHD_PREC_MIXED) return vl_launch_ti<float, double>(a, st);
-  if (prec == SRHD_PREC_FP32) return vl_launch_ti<float, float>(a, st);
-  return vl_launch_ti<double, double>(a, st);
+  return launch_vl<false>(prec, a, st);
 }
 
-int step_occupancy_vl(int prec, bool occ2)
+hipError_t launch_step_vl_grid(int prec, const StepArgs &a, hipStream_t st)
 {
-  if (prec == SRHD_PREC_MIXED) return vl_occupancy_ti<float, double>(occ2);
-  if (prec == SRHD_PREC_FP32) return vl_occupancy_ti<float, float>(occ2);
-  return vl_occupancy_ti<double, double>(occ2);
+  return launch_vl<true>(prec, a, st);
+}
+
+int step_occupancy_vl(int prec, bool gather, bool occ2)
+{
+  return gather ? occupancy_vl<true>(prec, occ2) : occupancy_vl<false>(prec, occ2);
 }
 
 }  // namespace srhd

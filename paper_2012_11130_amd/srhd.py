@@ -401,7 +401,7 @@ def _grid(cons, prims, neighbor, dh, level, net_mask=None):
 def srhd_autotune_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, dt_lev=None,
                             level=None, theta=1.5, riemann=HLLC, prec=PREC_FP64, max_retry=4,
                             guess=None, reps=2, kappa_max=KAPPA_MAX_DEFAULT, defer=None,
-                            learned_split=True, net_in=None):
+                            learned_split=True, net_in=None, integrator=MHM):
     """Times the candidate schedules of srhd_fluid_step_grid on this block; returns (Sched of
     the fastest, [(groups, chunk, occupancy, ms per step), ...])."""
     _need_cuda(cons, prims, neighbor, smax_in, dt_lev, level, net_in)
@@ -411,7 +411,7 @@ def srhd_autotune_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, 
     net_out = None if net_in is None else torch.empty_like(net_in)
     sch = Sched(0, 1, cons.device)
     gr = _grid(cons, prims, neighbor, dh, level, net_in)
-    prm = _params(theta, riemann, prec, max_retry, guess, sch)
+    prm = _params(theta, riemann, prec, max_retry, guess, sch, integrator=integrator)
     ws = _guard(prm, kappa_max, defer, cons.shape[0], cons.device, learned_split)  # noqa: F841
     table = (srhd_tune_entry * 32)()
     n = _int(0)
@@ -520,9 +520,10 @@ def srhd_fluid_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, dt_
                          level=None, cons_out=None, prims_out=None, smax_out=None, dt_used=None,
                          theta=1.5, riemann=HLLC, prec=PREC_FP64, max_retry=4, stats=None,
                          guess=None, sched=None, gamma=None, kappa_max=KAPPA_MAX_DEFAULT,
-                         defer=None, learned_split=True, net_in=None, net_out=None):
-    """One step of a block of same-level patches (ghosts gathered from neighbour interiors).
-    net_in: the input state's network masks (with a learned guess and learned_split they fix the
+                         defer=None, learned_split=True, net_in=None, net_out=None,
+                         integrator=MHM):
+    """One MUSCL-Hancock (or, integrator=VL, VL) step of a block of same-level patches (ghosts
+    gathered from neighbour interiors).  net_in: the input state's network masks (with a learned guess and learned_split they fix the
     split's list before the step, which then runs both kernels concurrently); net_out receives
     the output's.  Returns (cons_out, prims_out, smax_out)."""
     _need_cuda(cons, prims, neighbor, smax_in, dt_lev, level, stats, net_in, net_out)
@@ -539,7 +540,8 @@ def srhd_fluid_step_grid(cons, prims, neighbor, dh, smax_in=None, c_cfl=0.5, dt_
     _need_mask(net_in, P)
     _need_mask(net_out, P)
     gr = _grid(cons, prims, neighbor, dh, level, net_in)
-    prm = _params(theta, riemann, prec, max_retry, guess, sched, gamma=gamma)
+    prm = _params(theta, riemann, prec, max_retry, guess, sched, integrator=integrator,
+                  gamma=gamma)
     ws = _guard(prm, kappa_max, defer, P, cons.device, learned_split)  # noqa: F841
     _check(_lib.srhd_fluid_step_grid(ctypes.byref(gr), _ptr(smax_in), float(c_cfl), _ptr(dt_lev),
                                      _ptr(cons_out), _ptr(prims_out), _ptr(smax_out),

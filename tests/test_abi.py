@@ -141,7 +141,7 @@ def test_schedule_checks(lib):
     assert occ(1, 0, 0, 0, energy=1) == -3
     assert occ(0, 1, 0, 0, energy=1) == -3
     assert occ(0, 0, 1, 0, energy=1) == -3 and b"padded" in S._lib.srhd_last_error()
-    # the VL integrator: padded layout, analytic guess, reduced energy, ghost >= 3
+    # the VL integrator: analytic guess, reduced energy; ghost >= 3 in the padded layout
     prm.integrator = 2
     assert call() == -1 and b"integrator" in S._lib.srhd_last_error()
     prm.integrator = 1
@@ -152,8 +152,9 @@ def test_schedule_checks(lib):
     assert call() == -1 and b"ghost" in S._lib.srhd_last_error()
     d.ghost = 3
     prm.integrator = 0
-    assert occ(0, 0, 1, 0, integrator=1) == -3
+    assert occ(0, 0, 1, 0, energy=1, integrator=1) == -3 and b"VL" in S._lib.srhd_last_error()
     assert occ(2, 1, 0, 0, integrator=1) == -3
+    assert occ(2, 1, 1, 0, integrator=1) == -3
     # the polytropic EoS: 1 < gamma <= 2; padded MUSCL-Hancock, reduced energy, analytic guess
     prm.eos = S.srhd_eos(1, 2.5)
     assert call() == -1 and b"gamma" in S._lib.srhd_last_error()

@@ -169,3 +169,111 @@ def test_zero_limiter_and_the_last_resort(S):
             bad += sd["n_unphysical"]
         print("VL prec %d 128^3, 12 steps: %d unphysical output cells; last stats %s" % (prec, bad, sd))
         assert bad == 0 and bool(torch.isfinite(c).all()), prec
+
+
+# ------------------------------------------------------------------------------ gather layout
+def _grid_vl(S, g, cons, prec, sched=None, dt=None, stats=None):
+    c = _gpu(cons)
+    nb = _gpu(g.neighbor)
+    prims, smax = S.srhd_grid_prims(c, prec=prec)
+    dt_used = torch.empty(len(g.dh_lev), dtype=torch.float64, device=DEV)
+    out, po, so = S.srhd_fluid_step_grid(c, prims, nb, g.dh_lev, smax_in=smax, dt_lev=dt,
+                                         prec=prec, integrator=S.VL, sched=sched,
+                                         dt_used=dt_used, stats=stats)
+    return out, po, so, dt_used
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_grid_vl_equals_padded_vl_bitwise(S, prec):
+    # The gather layout reads the primitives that srhd_grid_prims stored -- the inversion that
+    # the padded kernel's phase A runs -- and U^n from the neighbours' interiors: for the same dt
+    # the output is the padded step's, bit for bit, in every precision mode (outflow and periodic
+    # blocks, patches in Morton order), under every schedule, and the primitives and S_max handed
+    # to the next step equal a fresh srhd_grid_prims of the output.
+    for g in (W.shock_tube_32(), W.blast(64, seed=3, order="morton")):
+        cons = oracle_cons(g)
+        c = _gpu(cons)
+        nb = _gpu(g.neighbor)
+        dt = S.srhd_cfl_dt(c, g.dh_lev)
+        ref = S.srhd_fluid_step(S.srhd_fill_ghosts(c, nb, 3), dt, g.dh_lev, prec=prec,
+                                integrator=S.VL)
+        out, po, so, dt_used = _grid_vl(S, g, cons, prec, dt=dt)
+        torch.cuda.synchronize()
+        assert torch.equal(dt_used, dt), g.name
+        assert torch.equal(out, ref), (g.name, prec)
+        p2, s2 = S.srhd_grid_prims(out, prec=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(p2, po) and torch.equal(s2, so), g.name
+        scheds = [S.Sched(7, 3, DEV), S.Sched(1024, 1, DEV)]
+        if prec != 0:
+            scheds += [S.Sched(0, 1, DEV, occupancy=2), S.Sched(512, 2, DEV, occupancy=2)]
+        for sch in scheds:
+            o2, p3, s3, _ = _grid_vl(S, g, cons, prec, sched=sch, dt=dt)
+            torch.cuda.synchronize()
+            assert torch.equal(o2, out) and torch.equal(p3, po) and torch.equal(s3, so), (g.name, sch)
+        # the fused CFL: in FP64 the S_max of srhd_grid_prims gives the CFL kernel's dt bit for bit
+        if prec == 0:
+            o3, _, _, dt3 = _grid_vl(S, g, cons, prec)
+            torch.cuda.synchronize()
+            assert torch.equal(dt3, dt) and torch.equal(o3, out), g.name
+
+
+def test_grid_vl_chain_matches_oracle(S):
+    # 64^3 blast in Morton order, 5 FP64 steps chained through the output's primitives and S_max
+    # (one kernel per step): each state against the oracle's CFL + ghost fill + VL step from its
+    # own state, with the oracle's limiter retries counted alike.
+    g = W.blast(64, seed=3, order="morton")
+    co = oracle_cons(g)
+    c = _gpu(co)
+    nb = _gpu(g.neighbor)
+    prims, smax = S.srhd_grid_prims(c, prec=0)
+    st = S.new_stats(DEV)
+    retries = 0
+    for k in range(5):
+        c, prims, smax = S.srhd_fluid_step_grid(c, prims, nb, g.dh_lev, smax_in=smax, prec=0,
+                                                integrator=S.VL, stats=st)
+        dt_o, _, _ = O.cfl_dt(co, None, g.dh_lev, 0.5)
+        co, cnt = O.fluid_step(O.fill_ghosts(co, g.neighbor, 3), dt_o, g.dh_lev, integrator=1)
+        retries += cnt[3]
+        e = step_errors(c.cpu().numpy(), co)
+        assert max(e.values()) <= 1e-10 * (k + 1), (k, e)
+    sd = S.stats_dict(st)
+    print("VL grid chain 64^3: %d patch retries over 5 steps; stats %s" % (retries, sd))
+    assert sd["n_retry"] == retries and sd["n_unphysical"] == 0
+
+
+def test_grid_vl_full_size_blast(S):
+    # the 256^3 blast in the benchmark's launch configuration (gather layout, fused CFL, the
+    # persistent schedule and the one-workgroup-per-patch launch): FP64 against the oracle on
+    # sampled patches, and both layouts bit for bit in FP64 and with the FP32 bulk
+    g = W.blast(256, seed=1003, order="morton")
+    cons = oracle_cons(g)
+    c = _gpu(cons)
+    nb = _gpu(g.neighbor)
+    dt_g = S.srhd_cfl_dt(c, g.dh_lev)
+    pad = S.srhd_fill_ghosts(c, nb, 3)
+    for prec in (0, 1):
+        ref = S.srhd_fluid_step(pad, dt_g, g.dh_lev, prec=prec, integrator=S.VL)
+        for sch in (None, S.Sched(2 * 256, 1, DEV)):
+            out, _, _, dt_used = _grid_vl(S, g, cons, prec, sched=sch)
+            torch.cuda.synchronize()
+            if prec == 0:
+                assert torch.equal(dt_used, dt_g)
+            else:
+                assert abs(dt_used.item() / dt_g.item() - 1) < 1e-6
+            o = _grid_vl(S, g, cons, prec, sched=sch, dt=dt_g)[0]
+            torch.cuda.synchronize()
+            assert torch.equal(o, ref), (prec, sch)
+            del o
+        if prec == 0:
+            lab = g.extra["labels"].reshape(g.n_patch, -1).any(axis=1)
+            rng = np.random.default_rng(1)
+            sample = np.unique(np.concatenate([np.nonzero(lab)[0][:150],
+                                               rng.choice(g.n_patch, 150, replace=False)]))
+            r, _ = O.fluid_step(O.fill_ghosts(cons, g.neighbor[sample], 3), dt_g.cpu().numpy(),
+                                g.dh_lev, integrator=1)
+            e = step_errors(out.cpu().numpy()[sample], r)
+            print("VL grid 256^3 sampled (%d patches): %s" % (sample.size, e))
+            assert max(e.values()) <= 1e-10, e
+        del ref, out
+    del pad
