@@ -172,9 +172,11 @@ __device__ __forceinline__ Prim<T> vload(const VlTile<T> &s, int b)
   return w;
 }
 
-// FX: the refined division and square roots of the FP64 bulk (dvx, sqx) -- in the corrector only,
-// whose fluxes are not inverted again; the predictor's are (U* -> W*), and an inversion turns a
-// changed rounding of its input into up to kappa (Eq. 20) times that change.
+// FX: the refined division and square roots of the FP64 bulk (dvx, sqx).  The corrector's fluxes
+// are not inverted again and always take them; the predictor's are (U* -> W*), and an inversion
+// turns a changed rounding of its input into up to kappa (Eq. 20) times that change, so the
+// predictor takes them only in a patch whose tile has kappa <= KAPPA_FAST everywhere (as the
+// MUSCL-Hancock FP64 step gates its upstream arithmetic).
 template <int d, bool FX, class T>
 __device__ __forceinline__ Cons<T> riemann(int solver, const Prim<T> &wl, const Prim<T> &wr)
 {
@@ -216,17 +218,17 @@ __device__ __forceinline__ bool gather_cell(const int *nb, int64_t n_patch, int 
   return ok;
 }
 
-// Gather layout: the stored primitives of tile cell (i, j, k) into slot b of the tile (NaN where
-// the cell's patch is missing); true for a physical state.
+// Gather layout: the stored primitives of tile cell (i, j, k) into v and slot b of the tile (NaN
+// where the cell's patch is missing); true for a physical state.
 template <class T>
-__device__ __forceinline__ bool gather_prim(VlTile<T> &s, const StepArgs &a, int i, int j, int k, int b)
+__device__ __forceinline__ bool gather_prim(VlTile<T> &s, const StepArgs &a, int i, int j, int k, int b,
+                                            T (&v)[5])
 {
   int64_t src;
   int sc;
   const bool okc = gather_cell(s.nb, a.n_patch, i, j, k, src, sc);
   const T *w = (const T *)a.prims + src * 5 * 512 + sc;
   const T nan = T(__builtin_nan(""));
-  T v[5];
 #pragma unroll
   for (int f = 0; f < 5; ++f) v[f] = okc ? w[f * 512] : nan;
 #pragma unroll
@@ -234,15 +236,15 @@ __device__ __forceinline__ bool gather_prim(VlTile<T> &s, const StepArgs &a, int
   return v[0] > T(0) && v[4] > T(0) && finiteT(v[1]) && finiteT(v[2]) && finiteT(v[3]);
 }
 
-// First-order flux of predictor face r along d into the buffer.
-template <int d, class T>
+// First-order flux of predictor face r along d into the buffer (FX: see riemann).
+template <int d, bool FX, class T>
 __device__ __forceinline__ void predictor_face(VlTile<T> &s, int r, int solver)
 {
   int i, j, k;
   unpack(kVl.face[d][r], i, j, k);
   const Prim<T> wr = vload(s, vslot(i, j, k));
   const Prim<T> wl = vload(s, vslot(i - (d == 0), j - (d == 1), k - (d == 2)));
-  const Cons<T> F = riemann<d, false>(solver, wl, wr);
+  const Cons<T> F = riemann<d, FX>(solver, wl, wr);
   s.B[0 * NVF + r] = F.D;
   s.B[1 * NVF + r] = F.m[0];
   s.B[2 * NVF + r] = F.m[1];
@@ -312,12 +314,18 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
   __syncthreads();
 
   // ---------------------------------------------------------------- A: centre primitives
+  // steep: a tile cell with kappa > KAPPA_FAST or an unphysical one (FP64 bulk)
+  bool steep = false;
+  const T kf1 = T(KAPPA_FAST - 1.0);
   for (int r = tid; r < kVl.np; r += NT) {
     int i, j, k;
     unpack(kVl.pcell[r], i, j, k);
     const int b = vslot(i, j, k);
     if constexpr (GATHER) {
-      bad_in += !gather_prim(s, a, i, j, k, b);
+      T v[5];
+      const bool ok = gather_prim(s, a, i, j, k, b, v);
+      bad_in += !ok;
+      if constexpr (sizeof(T) == 8) steep |= !ok || kappa_above<T, EosTm, true>(v[0], v[1], v[2], v[3], v[4], kf1);
     } else {
       const int off = ((k + g) * N + (j + g)) * N + (i + g);
       const double D = q[off], Mx = q[N3 + off], My = q[2 * N3 + off], Mz = q[3 * N3 + off],
@@ -337,9 +345,14 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
       s.W[2][b] = (T)o.uy;
       s.W[3][b] = (T)o.uz;
       s.W[4][b] = (T)o.p;
+      if constexpr (sizeof(T) == 8)
+        steep |= o.status == ST_UNPHYSICAL || kappa_above<T, EosTm, true>((T)o.rho, (T)o.ux, (T)o.uy, (T)o.uz, (T)o.p, kf1);
     }
   }
-  __syncthreads();
+  // the predictor's arithmetic (the OR's barrier also ends phase A)
+  bool fast = false;
+  if constexpr (sizeof(T) == 8) fast = wg_or(s, steep ? 1u : 0u, par) == 0u;
+  else __syncthreads();
 
   // ---------------------------------------------------------------- P: predictor
   // this thread's half-step cells: tid, tid + 512, tid + 1024 (the last only for tid < 256)
@@ -355,9 +368,15 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       for (int r = tid; r < NVF; r += NT) {
-        if (d == 0) predictor_face<0>(s, r, a.riemann);
-        else if (d == 1) predictor_face<1>(s, r, a.riemann);
-        else predictor_face<2>(s, r, a.riemann);
+        if (fast) {                                  // uniform across the workgroup
+          if (d == 0) predictor_face<0, true>(s, r, a.riemann);
+          else if (d == 1) predictor_face<1, true>(s, r, a.riemann);
+          else predictor_face<2, true>(s, r, a.riemann);
+        } else {
+          if (d == 0) predictor_face<0, false>(s, r, a.riemann);
+          else if (d == 1) predictor_face<1, false>(s, r, a.riemann);
+          else predictor_face<2, false>(s, r, a.riemann);
+        }
       }
       __syncthreads();
 #pragma unroll
@@ -447,7 +466,8 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
         if (GATHER && hc < NVH) {
           int i, j, k;
           unpack(kVl.hcell[hc], i, j, k);
-          gather_prim(s, a, i, j, k, bidx(i, j, k));
+          T v[5];
+          gather_prim(s, a, i, j, k, bidx(i, j, k), v);
         } else if (hc < NVH) {
           int i, j, k;
           unpack(kVl.hcell[hc], i, j, k);
