@@ -339,27 +339,62 @@ __device__ __forceinline__ bool interface_flux(Tile<T> &s, int r, T theta, int s
   return okl && okr;
 }
 
-__device__ __forceinline__ double wave_max(double v)
+// Reductions over a wavefront into its last lane (lane 63; the other lanes keep partial
+// results), on the cross-lane DPP paths of the VALU rather than LDS permutes: an inclusive scan
+// within each row of 16 lanes (row_shr 1, 2, 4, 8), then the row totals carried into rows 1 and 3
+// (row_bcast:15) and from lane 31 into rows 2 and 3 (row_bcast:31).  A lane whose DPP source lies
+// outside its row, or whose row the row mask leaves out, receives `old`: the operation's neutral
+// value (0 for a sum or an OR, the lane's own value for a maximum).  Every lane must be active.
+// Counters are summed this way before one lane per wavefront adds them to the workgroup's (an
+// atomic add from all 64 lanes to one address is compiled to a loop over the lanes, which cost the
+// whole step ~15 %); the six dependent LDS permutes per value of a butterfly cost the patch's tail
+// ~3 % of the FP64 step.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned int dpp_u32(unsigned int old, unsigned int v)
 {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return (unsigned int)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWS, 0xf, false);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double old, double v)
+{
+  const unsigned long long o = (unsigned long long)__double_as_longlong(old),
+                           x = (unsigned long long)__double_as_longlong(v);
+  const unsigned int lo = dpp_u32<CTRL, ROWS>((unsigned int)o, (unsigned int)x);
+  const unsigned int hi = dpp_u32<CTRL, ROWS>((unsigned int)(o >> 32), (unsigned int)(x >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ unsigned int wave_sum_hi(unsigned int v)
+{
+  v += dpp_u32<0x111, 0xf>(0u, v);
+  v += dpp_u32<0x112, 0xf>(0u, v);
+  v += dpp_u32<0x114, 0xf>(0u, v);
+  v += dpp_u32<0x118, 0xf>(0u, v);
+  v += dpp_u32<0x142, 0xa>(0u, v);
+  v += dpp_u32<0x143, 0xc>(0u, v);
   return v;
 }
 
-// Sum over the wavefront (every lane active; every lane receives the total).  Counters are summed
-// this way before one lane per wavefront adds them to the workgroup's: an atomic add from all 64
-// lanes to one address is compiled to a loop over the lanes, which cost the whole step ~15 %.
-__device__ __forceinline__ unsigned int wave_sum(unsigned int v)
+__device__ __forceinline__ unsigned int wave_or_hi(unsigned int v)
 {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  v |= dpp_u32<0x111, 0xf>(0u, v);
+  v |= dpp_u32<0x112, 0xf>(0u, v);
+  v |= dpp_u32<0x114, 0xf>(0u, v);
+  v |= dpp_u32<0x118, 0xf>(0u, v);
+  v |= dpp_u32<0x142, 0xa>(0u, v);
+  v |= dpp_u32<0x143, 0xc>(0u, v);
   return v;
 }
 
-__device__ __forceinline__ unsigned int wave_or(unsigned int v)
+__device__ __forceinline__ double wave_max_hi(double v)
 {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+  v = fmax(v, dpp_f64<0x111, 0xf>(v, v));
+  v = fmax(v, dpp_f64<0x112, 0xf>(v, v));
+  v = fmax(v, dpp_f64<0x114, 0xf>(v, v));
+  v = fmax(v, dpp_f64<0x118, 0xf>(v, v));
+  v = fmax(v, dpp_f64<0x142, 0xa>(v, v));
+  v = fmax(v, dpp_f64<0x143, 0xc>(v, v));
   return v;
 }
 
@@ -758,13 +793,13 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
        }
         if (a.net_out) {
           // the updated state's network mask: L of the output check against the gate
-          const unsigned int m = wave_or(owner && ok_out && Lo > a.net_gate ? region_mask(ci, cj, ck) : 0u);
-          if ((tid & 63) == 0 && m) atomicOr(&s.cnt[7], m);
+          const unsigned int m = wave_or_hi(owner && ok_out && Lo > a.net_gate ? region_mask(ci, cj, ck) : 0u);
+          if ((tid & 63) == 63 && m) atomicOr(&s.cnt[7], m);
           __syncthreads();
           if (tid == 0) a.net_out[p] = s.cnt[7];
         }
-        sm = wave_max(sm);
-        if ((tid & 63) == 0) s.red[tid >> 6] = sm;
+        sm = wave_max_hi(sm);
+        if ((tid & 63) == 63) s.red[tid >> 6] = sm;
         __syncthreads();
         if (tid == 0) {
           double m = s.red[0];
@@ -789,10 +824,10 @@ __device__ __forceinline__ void step_patch(const StepArgs &a, Tile<T> &s, const 
 
   // ---------------------------------------------------------------- counters
   if (a.stats) {
-    const unsigned int c0 = wave_sum(unphys + centre_unphys), c1 = wave_sum(my_fb),
-                       c2 = wave_sum(my_nc), c3 = wave_sum(my_iters), c4 = wave_sum(my_inv),
-                       c5 = MLP ? wave_sum(my_mlp) : 0u;
-    if ((tid & 63) == 0) {
+    const unsigned int c0 = wave_sum_hi(unphys + centre_unphys), c1 = wave_sum_hi(my_fb),
+                       c2 = wave_sum_hi(my_nc), c3 = wave_sum_hi(my_iters), c4 = wave_sum_hi(my_inv),
+                       c5 = MLP ? wave_sum_hi(my_mlp) : 0u;
+    if ((tid & 63) == 63) {
       atomicAdd(&s.cnt[0], c0);
       atomicAdd(&s.cnt[1], c1);
       atomicAdd(&s.cnt[2], c2);
@@ -968,8 +1003,8 @@ __global__ void __launch_bounds__(256) k_grid_prims(int64_t n_patch, const doubl
     else set_unphysical(w);
     // the state's network mask (every wavefront's cells lie in one patch)
     if (net_mask) {
-      const unsigned int m = wave_or(ok && L > net_gate ? region_mask(c & 7, (c >> 3) & 7, c >> 6) : 0u);
-      if ((threadIdx.x & 63) == 0 && m) atomicOr(&net_mask[pp], m);
+      const unsigned int m = wave_or_hi(ok && L > net_gate ? region_mask(c & 7, (c >> 3) & 7, c >> 6) : 0u);
+      if ((threadIdx.x & 63) == 63 && m) atomicOr(&net_mask[pp], m);
     }
     T *po = prims + pp * 5 * 512 + c;
     po[0] = (T)w.rho;
@@ -984,8 +1019,8 @@ __global__ void __launch_bounds__(256) k_grid_prims(int64_t n_patch, const doubl
       if (ok) vmax = fmax(vmax, signal_smax((double)w.rho, (double)w.ux, (double)w.uy, (double)w.uz, (double)w.p));
     }
   }
-  vmax = wave_max(vmax);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = vmax;
+  vmax = wave_max_hi(vmax);
+  if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6] = vmax;
   __syncthreads();
   if (threadIdx.x == 0) {
     double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));

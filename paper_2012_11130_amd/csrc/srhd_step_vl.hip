@@ -559,8 +559,8 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
         } else {
           if (ok_out) sm = signal_smax((double)w.rho, (double)w.ux, (double)w.uy, (double)w.uz, (double)w.p);
         }
-        sm = wave_max(sm);
-        if ((tid & 63) == 0) s.red[tid >> 6] = sm;
+        sm = wave_max_hi(sm);
+        if ((tid & 63) == 63) s.red[tid >> 6] = sm;
         __syncthreads();
         if (tid == 0) {
           double m = s.red[0];
@@ -577,9 +577,9 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
 
   // ---------------------------------------------------------------- counters
   if (a.stats) {
-    const unsigned int c0 = wave_sum(unphys + bad_in), c2 = wave_sum(my_nc),
-                       c3 = wave_sum(my_iters), c4 = wave_sum(my_inv), c7 = wave_sum(my_pfb);
-    if ((tid & 63) == 0) {
+    const unsigned int c0 = wave_sum_hi(unphys + bad_in), c2 = wave_sum_hi(my_nc),
+                       c3 = wave_sum_hi(my_iters), c4 = wave_sum_hi(my_inv), c7 = wave_sum_hi(my_pfb);
+    if ((tid & 63) == 63) {
       atomicAdd(&s.cnt[0], c0);
       atomicAdd(&s.cnt[2], c2);
       atomicAdd(&s.cnt[3], c3);
