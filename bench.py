@@ -57,16 +57,16 @@ IO_BYTES_PER_PATCH = {                         # what one patch's step consumes 
 # FMA as 2), summarised in the profile named below; valid only for the kernel sources they were
 # taken on (hash of the files that make up the step kernels).  headline: one step of the
 # mixed-precision chain with the learned guess, gather layout, two-workgroup register variant --
-# the kernel without the network (2,377.4 us), the learned pass beside it on the second stream
-# (228.5 us, overlapped), the list (10.1 us), the counter prologue (4.6 us) and the guard's empty
-# FP64 pass (6.7 us); ms is their sum without the overlapped pass, valu_issue that of the first
+# the kernel without the network (2,307.8 us), the learned pass beside it on the second stream
+# (232.3 us, overlapped), the list (9.9 us), the counter prologue (4.2 us) and the guard's empty
+# FP64 pass (6.4 us); ms is their sum without the overlapped pass, valu_issue that of the first
 # kernel.  fp64: the FP64 step kernel (with its prologue).
-PROFILED = {"sources_sha256_16": "6c354187e031792e", "path": "grid",
+PROFILED = {"sources_sha256_16": "f0fd3add91e52df2", "path": "grid",
             "summary": "profiles/step_blast256_counters.md",
-            "headline": {"ms": 2.3988, "read": 1317.4e6, "write": 1022.6e6,
-                         "flops": 1.711e10 + 4.524e10 + 4.165e7 + 1.929e8, "valu_issue": 0.858},
-            "fp64": {"ms": 5.6342, "read": 1903.7e6, "write": 1345.4e6, "flops": 1.185e11,
-                     "valu_issue": 0.610}}
+            "headline": {"ms": 2.3283, "read": 1314.5e6, "write": 1020.5e6,
+                         "flops": 1.711e10 + 4.524e10 + 4.165e7 + 1.929e8, "valu_issue": 0.878},
+            "fp64": {"ms": 5.4791, "read": 1903.0e6, "write": 1345.4e6, "flops": 1.185e11,
+                     "valu_issue": 0.626}}
 STEP_SOURCES = ("srhd_step_impl.hpp", "srhd_step_mixed.hip", "srhd_step_fp64.hip", "srhd_step.hip",
                 "srhd_device.hpp", "srhd_mlp.hpp")
 
