@@ -68,7 +68,8 @@ def features(cons, kind=0):
             first = np.log(np.where(ok, L, 0.0))
     else:
         first = np.log(D)
-    return np.stack([first, np.log(np.maximum(m, 1e-300)), np.log(cons[4] / D)])
+    with np.errstate(divide="ignore", invalid="ignore"):     # unphysical inputs give NaN features
+        return np.stack([first, np.log(np.maximum(m, 1e-300)), np.log(cons[4] / D)])
 
 
 def forward(theta, x, bf16_round=True):
