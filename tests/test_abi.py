@@ -235,3 +235,20 @@ def test_network_mask_checks(lib):
     assert call(al(masks) + 8) == -1 and b"net_out" in S._lib.srhd_last_error()
     gr.net_mask = al(masks) + 2
     assert call(None) == -1 and b"misaligned" in S._lib.srhd_last_error()
+    # the VL integrator in the gather layout: the reduced energy and the analytic guess only, no
+    # boundary fluxes (rejected before any launch)
+    gr.net_mask = None
+    prm.integrator, prm.energy = 1, 1
+    assert call(None) == -3 and b"VL" in S._lib.srhd_last_error()
+    prm.energy = 0
+    prm.flux_out = al(cout)
+    assert call(None) == -3 and b"boundary fluxes" in S._lib.srhd_last_error()
+    prm.flux_out = None
+    prm.guess = S.srhd_guess(1, None, 0)
+    assert call(None) == -1                  # a learned guess without weights: rejected first
+    wb = buf(4352 * 2 + 129 * 4 + 8 * 4)
+    mlp = S.srhd_mlp(al(wb), al(wb) + 8704, al(wb) + 8704 + 516, 0, 0.1)
+    prm.guess = S.srhd_guess(1, ctypes.pointer(mlp), 0)
+    assert call(None) == -3 and b"VL" in S._lib.srhd_last_error()
+    prm.guess = S.srhd_guess(0, None, 0)
+    prm.integrator = 0
