@@ -55,8 +55,10 @@ def test_conversions(S, gamma):
 
 @pytest.mark.parametrize("gamma", GAMMAS)
 def test_cons2prim_fp32_error_is_stated(S, gamma):
-    # as for the TM EoS: FP32 inputs, the FP64 oracle on the upcast inputs, states whose Eq. 20
-    # amplification kappa ~ 1 + Mach^2 of the FP32 round-off stays below 1e3
+    # as for the TM EoS: FP32 inputs, the FP64 oracle on the upcast inputs; per state the error is
+    # bounded by the Eq. 20 amplification kappa ~ 1 + Mach^2 of the FP32 round-off of L (kappa from
+    # the state, L being the EoS-free left-hand side of Eq. 15), plus a few u32 of Newton tolerance
+    # and recovery: 16 u32 (kappa + 4), over the states FP32 can represent (kappa u32 < 1e-2)
     prim = W.conversion_batch(200_000, seed=23)
     with O.eos(gamma):
         cons32 = O.prim2cons(prim).astype(np.float32)
@@ -69,11 +71,18 @@ def test_cons2prim_fp32_error_is_stated(S, gamma):
     x = Et / D
     with np.errstate(over="ignore", divide="ignore"):
         kappa = (x * x + 2 * x + M2 / D ** 2) / np.maximum(O.L_batch(cons64), 1e-300)
-    good = ok & (kappa < 1e3)
-    e = prim_errors(w, ref, good)
-    print("Gamma %.4f fp32: %s over %d states" % (gamma, e, good.sum()))
-    assert good.sum() > 1000
-    assert e["rho"] < 1e-4 and e["U"] < 1e-4 and e["p"] < 1e-3, e
+    u32 = 2.0 ** -24
+    with np.errstate(invalid="ignore", divide="ignore"):
+        er = np.abs(w[0] / ref[0] - 1)
+        ep = np.abs(w[4] / ref[4] - 1)
+        eu = np.max(np.abs(w[1:4] - ref[1:4]), axis=0) / np.maximum(np.sqrt((ref[1:4] ** 2).sum(axis=0)), 1e-300)
+    emax = np.maximum(np.maximum(er, ep), eu)
+    rep = ok & (kappa * u32 < 1e-2)
+    ratio = emax[rep] / (u32 * (kappa[rep] + 4))
+    print("Gamma %.4f fp32: %d states with kappa u32 < 1e-2; error / (u32 (kappa + 4)): median %.3f, "
+          "max %.3f" % (gamma, rep.sum(), np.median(ratio), ratio.max()))
+    assert rep.sum() > 1000
+    assert np.all(emax[rep] <= 16 * u32 * (kappa[rep] + 4))
     assert not np.any((st == 0) & (st_ref == O.ST_UNPHYSICAL))
 
 
