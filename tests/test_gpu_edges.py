@@ -1,5 +1,6 @@
 """Edge cases of the step entry points on the GPU: empty patch lists, lists shorter than the
-eight XCD ranges of the persistent schedule, and a single patch."""
+eight XCD ranges of the persistent schedule, and a single patch; for the MUSCL-Hancock and the VL
+integrators."""
 import numpy as np
 import pytest
 import torch
@@ -61,3 +62,33 @@ def test_single_patch_matches_its_place_in_the_list(S, tube):
         one = S.srhd_fluid_step(pad[p:p + 1].clone(), dt, g.dh_lev)
         torch.cuda.synchronize()
         assert torch.equal(one[0], full[p]), p
+
+
+def test_vl_empty_and_short_lists(S, tube):
+    g, c, nb, dt, pad = tube
+    out = S.srhd_fluid_step(pad[:0], dt, g.dh_lev, integrator=S.VL)
+    assert out.shape[0] == 0
+    for prec in (0, 1, 2):
+        prims, smax = S.srhd_grid_prims(c[:0], prec=prec)
+        co, po, so = S.srhd_fluid_step_grid(c[:0], prims, nb[:0], g.dh_lev, smax_in=smax, prec=prec,
+                                            integrator=S.VL)
+        torch.cuda.synchronize()
+        assert co.shape[0] == 0 and int(so.item()) == 0
+    # the first n patches, each its own periodic neighbour in every slot, under the persistent
+    # schedule (fewer patches than XCD ranges): both layouts give the one-per-patch padded step
+    for n in (1, 3, 9):
+        nbn = torch.arange(n, dtype=torch.int32, device=DEV)[:, None].repeat(1, 27).contiguous()
+        cn = c[:n].contiguous()
+        padn = S.srhd_fill_ghosts(cn, nbn, 3)
+        dtn = S.srhd_cfl_dt(cn, g.dh_lev)
+        for prec in (0, 1):
+            ref = S.srhd_fluid_step(padn, dtn, g.dh_lev, prec=prec, integrator=S.VL)
+            prims, _ = S.srhd_grid_prims(cn, prec=prec)
+            for groups, chunk in ((64, 1), (7, 4), (1, 64)):
+                sch = S.Sched(groups, chunk, DEV)
+                o1 = S.srhd_fluid_step(padn, dtn, g.dh_lev, prec=prec, integrator=S.VL, sched=sch)
+                o2 = S.srhd_fluid_step_grid(cn, prims, nbn, g.dh_lev, dt_lev=dtn, prec=prec,
+                                            integrator=S.VL, sched=sch)[0]
+                torch.cuda.synchronize()
+                assert bool(torch.isfinite(ref).all()), (n, prec)
+                assert torch.equal(o1, ref) and torch.equal(o2, ref), (n, prec, groups, chunk)
