@@ -651,18 +651,20 @@ def main():
         finals = {}
         for layout in ("grid", "padded"):
             for prec, name in ((S.PREC_MIXED, "mixed"), (S.PREC_FP64, "fp64")):
-                if layout == "grid":
+                runner = run_grid if layout == "grid" else run_padded
+                if args.sched != "auto":
+                    gr, ch, oc = (int(v) for v in args.sched.split(","))
+                    sch, table = S.Sched(gr, ch, dev, occupancy=0 if prec == S.PREC_FP64 else oc), []
+                elif layout == "grid":
                     prims, smax = S.srhd_grid_prims(cons0, prec=prec)
                     sch, table = S.srhd_autotune_step_grid(cons0, prims, nb, dh, smax_in=smax,
                                                            prec=prec, reps=2, integrator=S.VL)
                     del prims
-                    runner = run_grid
                 else:
                     S.srhd_cfl_dt(cons0, dh, 0.5, dt_lev=dt)
                     S.srhd_fill_ghosts(cons0, nb, 3, padded=pad)
                     sch, table = S.srhd_autotune_step(pad, dt, dh, prec=prec, reps=2,
                                                       integrator=S.VL)
-                    runner = run_padded
                 key = name if layout == "grid" else "padded_" + name
                 schedules["vl_" + key] = {"groups": sch.groups, "chunk": sch.chunk,
                                           "occupancy": sch.occupancy,
