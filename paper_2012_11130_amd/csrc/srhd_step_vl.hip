@@ -35,6 +35,11 @@ constexpr int NVW = NB + NVS;            // LDS primitive slots: 12^3 box + slab
 
 constexpr bool in_range(int v, int lo, int hi) { return v >= lo && v < hi; }
 
+// Threads of a workgroup: 512 with an FP32 bulk (one per interior cell); 768 with the FP64 bulk,
+// whose 141 KB tile leaves one workgroup per CU -- three wavefronts per SIMD instead of two to
+// hide the FP64 latency (threads 512.. own no interior cell).
+template <class T> constexpr int vl_threads() { return sizeof(T) == 8 ? 768 : 512; }
+
 // Cells whose half-step primitives the corrector reads.
 constexpr bool vl_half(int i, int j, int k)
 {
@@ -152,7 +157,7 @@ template <class T>
 struct VlTile {
   T W[5][NVW];                   // centre primitives, then W* at the half-step cells
   T B[5 * NVF];                  // predictor fluxes of one direction / corrector flux ring
-  double red[NT / 64];
+  double red[16];                // per-wavefront maxima
   unsigned int cnt[8];
   unsigned long long claim;
   unsigned int orf[2][4];        // workgroup OR (wg_or)
@@ -291,7 +296,10 @@ __device__ __forceinline__ void corrector_face(VlTile<T> &s, int r, T theta, int
 template <class T, class I, bool GATHER>
 __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const int64_t p)
 {
+  constexpr int NTV = vl_threads<T>();
+  constexpr int HPT = (NVH + NTV - 1) / NTV;     // half-step cells per thread
   const int tid = threadIdx.x;
+  const bool owner = tid < NT;                   // owns interior cell tid in D
   const int g = a.ghost;
   const int N = 8 + 2 * g;
   const int N3 = N * N * N;
@@ -317,7 +325,7 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
   // steep: a tile cell with kappa > KAPPA_FAST or an unphysical one (FP64 bulk)
   bool steep = false;
   const T kf1 = T(KAPPA_FAST - 1.0);
-  for (int r = tid; r < kVl.np; r += NT) {
+  for (int r = tid; r < kVl.np; r += NTV) {
     int i, j, k;
     unpack(kVl.pcell[r], i, j, k);
     const int b = vslot(i, j, k);
@@ -355,19 +363,19 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
   else __syncthreads();
 
   // ---------------------------------------------------------------- P: predictor
-  // this thread's half-step cells: tid, tid + 512, tid + 1024 (the last only for tid < 256)
+  // this thread's half-step cells: tid + h NTV for h < HPT (below NVH)
   // With theta = 0 (piecewise-constant reconstruction) the half step is dropped everywhere: the
   // step is the first-order Godunov step, W* = W^n.
   const bool predicted = a.theta > 0.0;        // uniform across the workgroup
   if (predicted) {
-    T acc[3][5];
+    T acc[HPT][5];
 #pragma unroll
-    for (int h = 0; h < 3; ++h)
+    for (int h = 0; h < HPT; ++h)
 #pragma unroll
       for (int f = 0; f < 5; ++f) acc[h][f] = T(0);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      for (int r = tid; r < NVF; r += NT) {
+      for (int r = tid; r < NVF; r += NTV) {
         if (fast) {                                  // uniform across the workgroup
           if (d == 0) predictor_face<0, true>(s, r, a.riemann);
           else if (d == 1) predictor_face<1, true>(s, r, a.riemann);
@@ -380,8 +388,8 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
       }
       __syncthreads();
 #pragma unroll
-      for (int h = 0; h < 3; ++h) {
-        const int hc = tid + h * NT;
+      for (int h = 0; h < HPT; ++h) {
+        const int hc = tid + h * NTV;
         if (hc < NVH) {
           const int fm = kVl.hface[d][hc][0], fp = kVl.hface[d][hc][1];
 #pragma unroll
@@ -392,8 +400,8 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
     }
     const double half = 0.5 * dt / dh;
 #pragma unroll
-    for (int h = 0; h < 3; ++h) {
-      const int hc = tid + h * NT;
+    for (int h = 0; h < HPT; ++h) {
+      const int hc = tid + h * NTV;
       if (hc < NVH) {
         int i, j, k;
         unpack(kVl.hcell[hc], i, j, k);
@@ -436,8 +444,8 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
     }
     // every read of the centre primitives ended at the last barrier above: overwrite with W*
 #pragma unroll
-    for (int h = 0; h < 3; ++h) {
-      const int hc = tid + h * NT;
+    for (int h = 0; h < HPT; ++h) {
+      const int hc = tid + h * NTV;
       if (hc < NVH) {
         int i, j, k;
         unpack(kVl.hcell[hc], i, j, k);
@@ -450,7 +458,7 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
   const bool input_bad = wg_or(s, bad_in != 0 ? 1u : 0u, par) != 0u;
 
   // this thread's interior cell for D
-  const int ci = tid & 7, cj = (tid >> 3) & 7, ck = tid >> 6;
+  const int ci = tid & 7, cj = (tid >> 3) & 7, ck = (tid >> 6) & 7;
   const int cq = GATHER ? tid : ((ck + g) * N + (cj + g)) * N + (ci + g);
   T theta = (T)a.theta;
   unsigned int retries = 0, unphys = 0;
@@ -461,8 +469,8 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
       // half-step cells, inverted again from the padded input (gathered again from the stored
       // primitives)
 #pragma unroll
-      for (int h = 0; h < 3; ++h) {
-        const int hc = tid + h * NT;
+      for (int h = 0; h < HPT; ++h) {
+        const int hc = tid + h * NTV;
         if (GATHER && hc < NVH) {
           int i, j, k;
           unpack(kVl.hcell[hc], i, j, k);
@@ -496,9 +504,11 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
     }
     // -------------------------------------------------------------- C + D: corrector, update
     T dU[5] = {T(0), T(0), T(0), T(0), T(0)};
+    constexpr int NROUND = (3 * NIF + NTV - 1) / NTV;
+    int folded = 0;
 #pragma unroll 1
-    for (int round = 0; round < 4; ++round) {
-      const int qi = round * NT + tid;
+    for (int round = 0; round < NROUND; ++round) {
+      const int qi = round * NTV + tid;
       if (qi < 3 * NIF) {
         const int d = qi / NIF;                      // uniform across each wavefront
         const int r = qi - d * NIF;
@@ -507,13 +517,18 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
         else corrector_face<2>(s, r, theta, a.riemann);
       }
       __syncthreads();
-      if (round >= 1) {
-        const int d = round - 1;
+      // every direction this round completed: fold it into this thread's cell before the ring
+      // slot it shares with direction d + 2 is written again
+      const int done = (round + 1) * NTV / NIF < 3 ? (round + 1) * NTV / NIF : 3;
+      for (; folded < done; ++folded) {
+        const int d = folded;
         const int slot = d & 1;
-        const int r = d == 0 ? (ck * 8 + cj) * 9 + ci : (d == 1 ? (ck * 9 + cj) * 8 + ci : (ck * 8 + cj) * 8 + ci);
-        const int up = d == 0 ? 1 : (d == 1 ? 8 : 64);
+        if (owner) {
+          const int r = d == 0 ? (ck * 8 + cj) * 9 + ci : (d == 1 ? (ck * 9 + cj) * 8 + ci : (ck * 8 + cj) * 8 + ci);
+          const int up = d == 0 ? 1 : (d == 1 ? 8 : 64);
 #pragma unroll
-        for (int f = 0; f < 5; ++f) dU[f] += s.B[(slot * 5 + f) * NIF + r + up] - s.B[(slot * 5 + f) * NIF + r];
+          for (int f = 0; f < 5; ++f) dU[f] += s.B[(slot * 5 + f) * NIF + r + up] - s.B[(slot * 5 + f) * NIF + r];
+        }
         if constexpr (!GATHER) {
           if (a.flux_out && tid < 128) write_boundary_fluxes(a.flux_out, p, d, &s.B[slot * 5 * NIF], NIF, tid);
         }
@@ -523,41 +538,48 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
     const double full = dt / dh;
     int lt = tid, lq = cq;
     asm volatile("" : "+v"(lt), "+v"(lq));
-    double un[5];
+    double un[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double Lo = 0.0;
+    bool ok_out = true;
+    if (owner) {
 #pragma unroll
-    for (int f = 0; f < 5; ++f) {
-      const double u0 = GATHER ? a.cons[(p * 5 + f) * 512 + lt] : q[f * N3 + lq];
-      un[f] = u0 - full * (double)dU[f];
+      for (int f = 0; f < 5; ++f) {
+        const double u0 = GATHER ? a.cons[(p * 5 + f) * 512 + lt] : q[f * N3 + lq];
+        un[f] = u0 - full * (double)dU[f];
+      }
+      ok_out = vl_admissible<T>(un[0], un[1], un[2], un[3], un[4], Lo);
     }
-    double Lo;
-    const bool ok_out = vl_admissible<T>(un[0], un[1], un[2], un[3], un[4], Lo);
     const bool fail = wg_or(s, ok_out ? 0u : 1u, par) != 0u;
     if (!fail || input_bad || theta == T(0)) {
-      double *o = a.out + p * 5 * 512 + lt;
+      if (owner) {
+        double *o = a.out + p * 5 * 512 + lt;
 #pragma unroll
-      for (int f = 0; f < 5; ++f) o[f * 512] = un[f];
-      unphys += !ok_out;
+        for (int f = 0; f < 5; ++f) o[f * 512] = un[f];
+        unphys += !ok_out;
+      }
       if constexpr (GATHER) {
         // the updated cell's primitives (the inversion of srhd_grid_prims) and signal speed
-        InvOut<I> w;
-        if (ok_out)
-          invert_with_L<I, GuessT<T, I>, GuessT<T, I>, true>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)Lo, (I)-1.0,
-                                                             false, (I)StepTol<T, I>::v, 30, w);
-        else set_unphysical(w);
-        my_iters += w.iters;
-        my_inv += 1;
-        my_nc += w.status == ST_NOCONV;
-        T *po = (T *)a.prims_out + p * 5 * 512 + lt;
-        po[0] = (T)w.rho;
-        po[512] = (T)w.ux;
-        po[1024] = (T)w.uy;
-        po[1536] = (T)w.uz;
-        po[2048] = (T)w.p;
         double sm = 0.0;
-        if constexpr (sizeof(T) == 4) {
-          if (ok_out) sm = (double)signal_smax_t<float>((T)w.rho, (T)w.ux, (T)w.uy, (T)w.uz, (T)w.p);
-        } else {
-          if (ok_out) sm = signal_smax((double)w.rho, (double)w.ux, (double)w.uy, (double)w.uz, (double)w.p);
+        if (owner) {
+          InvOut<I> w;
+          if (ok_out)
+            invert_with_L<I, GuessT<T, I>, GuessT<T, I>, true>((I)un[0], (I)un[1], (I)un[2], (I)un[3], (I)Lo, (I)-1.0,
+                                                               false, (I)StepTol<T, I>::v, 30, w);
+          else set_unphysical(w);
+          my_iters += w.iters;
+          my_inv += 1;
+          my_nc += w.status == ST_NOCONV;
+          T *po = (T *)a.prims_out + p * 5 * 512 + lt;
+          po[0] = (T)w.rho;
+          po[512] = (T)w.ux;
+          po[1024] = (T)w.uy;
+          po[1536] = (T)w.uz;
+          po[2048] = (T)w.p;
+          if constexpr (sizeof(T) == 4) {
+            if (ok_out) sm = (double)signal_smax_t<float>((T)w.rho, (T)w.ux, (T)w.uy, (T)w.uz, (T)w.p);
+          } else {
+            if (ok_out) sm = signal_smax((double)w.rho, (double)w.ux, (double)w.uy, (double)w.uz, (double)w.p);
+          }
         }
         sm = wave_max_hi(sm);
         if ((tid & 63) == 63) s.red[tid >> 6] = sm;
@@ -565,7 +587,7 @@ __device__ __forceinline__ void vl_patch(const StepArgs &a, VlTile<T> &s, const 
         if (tid == 0) {
           double m = s.red[0];
 #pragma unroll
-          for (int w8 = 1; w8 < NT / 64; ++w8) m = fmax(m, s.red[w8]);
+          for (int w8 = 1; w8 < NTV / 64; ++w8) m = fmax(m, s.red[w8]);
           atomicMax(a.smax_out, (unsigned long long)__double_as_longlong(m));
         }
       }
@@ -634,7 +656,7 @@ __device__ __forceinline__ void vl_body(const StepArgs &a)
 }
 
 template <class T, class I, bool GATHER>
-__global__ void __launch_bounds__(NT) k_vl(StepArgs a)
+__global__ void __launch_bounds__(vl_threads<T>()) k_vl(StepArgs a)
 {
   vl_body<T, I, GATHER>(a);
 }
@@ -662,7 +684,7 @@ int vl_occupancy_ti(bool occ2)
   const void *fn = vl_kernel<T, I, GATHER>(occ2);
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, NT, bytes) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, vl_threads<T>(), bytes) != hipSuccess) return 0;
   return n;
 }
 
@@ -694,7 +716,7 @@ hipError_t vl_launch_ti(const StepArgs &a, hipStream_t st)
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_vl<T, I, GATHER>), dim3((unsigned)blocks), dim3(NT), bytes, st, a);
+  hipLaunchKernelGGL((k_vl<T, I, GATHER>), dim3((unsigned)blocks), dim3(vl_threads<T>()), bytes, st, a);
   return hipGetLastError();
 }
 
