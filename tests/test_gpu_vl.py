@@ -1,8 +1,10 @@
-"""GPU parity of the VL predictor-corrector step (srhd_fluid_step with integrator = VL) against
-the oracle's VL step, through the C ABI: one FP64 step within 1e-10 (HLLC and HLLE) on a shock
-tube and the 64^3 blast, multi-step runs with limiter retries on both sides, the persistent
-schedule bit for bit, the FP32-bulk modes within their stated errors, and sampled patches of the
-full-size 256^3 blast in the benchmark's launch configuration."""
+"""GPU parity of the VL predictor-corrector step (srhd_fluid_step and srhd_fluid_step_grid with
+integrator = VL) against the oracle's VL step, through the C ABI: one FP64 step within 1e-10
+(HLLC and HLLE) on a shock tube and the 64^3 blast, multi-step runs with limiter retries on both
+sides, the persistent schedule bit for bit, the FP32-bulk modes within their stated errors, and
+sampled patches of the full-size 256^3 blast; the gather layout bit for bit against the padded
+one in every precision mode and schedule, its fused S_max, a five-step FP64 chain against the
+oracle, and the 256^3 blast in the benchmark's launch configuration."""
 import numpy as np
 import pytest
 import torch
